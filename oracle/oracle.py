@@ -1,0 +1,155 @@
+"""Python access to the CPU oracle (test infrastructure only).
+
+The oracle is the plain fp64 definition of the layered-media electric dyadic
+Green's function sum that the GPU fast multipole path is checked against.  It
+is loaded only by the tests, by the package smoke check and by the CPU-baseline
+leg of the benchmark; the product path never imports it.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lm_oracle.c")
+_LIB = os.path.join(_HERE, "liblmoracle.so")
+_lib = None
+
+
+def build(force=True):
+    """Compile the oracle shared library with gcc (OpenMP, fp64, -O2)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+             "-D_DEFAULT_SOURCE", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER(ctypes.c_double)
+        lib.lm_oracle_pair.argtypes = [ctypes.c_int, P, P, P, P, ctypes.c_double, P]
+        lib.lm_oracle_reaction_pair.argtypes = [ctypes.c_int, P, P, P, P, ctypes.c_double, P]
+        lib.lm_oracle_free_check.argtypes = [ctypes.c_double, P, P, P, P]
+        lib.lm_oracle_spectral.argtypes = [ctypes.c_int, P, P, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, P]
+        lib.lm_oracle_bessel012.argtypes = [ctypes.c_double, ctypes.c_double, P]
+        lib.lm_oracle_bessel012.restype = None
+        lib.lm_oracle_direct.argtypes = [ctypes.c_int, P, P, ctypes.c_int64, P, ctypes.c_int, P,
+                                         ctypes.c_int64, P, P, ctypes.c_int]
+        lib.lm_oracle_direct_free.argtypes = [ctypes.c_int, P, P, ctypes.c_int64, P, P,
+                                              ctypes.c_int64, P, P, ctypes.c_int]
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _medium(d, k):
+    d = np.ascontiguousarray(np.asarray(d, dtype=np.float64).reshape(-1))
+    k = np.ascontiguousarray(np.asarray(k, dtype=np.float64).reshape(-1))
+    if d.size == 0:
+        d = np.zeros(1)
+    return d, k
+
+
+def pair(d, k, x, xp, quad_scale=1.0):
+    """Full 3x3 G(x, x') (free part for same-layer distinct points + reaction)."""
+    d, k = _medium(d, k)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    xp = np.ascontiguousarray(xp, dtype=np.float64)
+    out = np.zeros(18)
+    rc = _load().lm_oracle_pair(k.size, _p(d), _p(k), _p(x), _p(xp), quad_scale, _p(out))
+    if rc:
+        raise ValueError("oracle rejected the medium (rc=%d)" % rc)
+    return out.view(np.complex128).reshape(3, 3)
+
+
+def reaction_pair(d, k, x, xp, quad_scale=1.0):
+    """Reaction part G^r(x, x') only."""
+    d, k = _medium(d, k)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    xp = np.ascontiguousarray(xp, dtype=np.float64)
+    out = np.zeros(18)
+    rc = _load().lm_oracle_reaction_pair(k.size, _p(d), _p(k), _p(x), _p(xp), quad_scale,
+                                         _p(out))
+    if rc:
+        raise ValueError("oracle rejected the medium (rc=%d)" % rc)
+    return out.view(np.complex128).reshape(3, 3)
+
+
+def free_check(k, x, xp):
+    """(Sommerfeld-route free dyadic, closed-form free dyadic)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    xp = np.ascontiguousarray(xp, dtype=np.float64)
+    a = np.zeros(18)
+    b = np.zeros(18)
+    _load().lm_oracle_free_check(float(k), _p(x), _p(xp), _p(a), _p(b))
+    return a.view(np.complex128).reshape(3, 3), b.view(np.complex128).reshape(3, 3)
+
+
+def spectral(d, k, kr, z, zp):
+    """Reaction scalars [pol][R, dzR, dz'R, dzdz'R], pol 0 = TE, 1 = TM."""
+    d, k = _medium(d, k)
+    out = np.zeros(16)
+    kr = complex(kr)
+    rc = _load().lm_oracle_spectral(k.size, _p(d), _p(k), kr.real, kr.imag, float(z), float(zp),
+                                    _p(out))
+    if rc:
+        raise ValueError("oracle rejected the medium (rc=%d)" % rc)
+    return out.view(np.complex128).reshape(2, 4)
+
+
+def bessel012(z):
+    out = np.zeros(6)
+    z = complex(z)
+    _load().lm_oracle_bessel012(z.real, z.imag, _p(out))
+    return out.view(np.complex128)
+
+
+def direct(d, k, src, J, tgt, n_threads=None):
+    """A[r, i] = sum_j G(tgt_i, src_j) J[r, j]  (complex128 [n_rhs, n_tgt, 3]).
+
+    J may be [n_src, 3] (one right-hand side) or [n_rhs, n_src, 3]."""
+    d, k = _medium(d, k)
+    src = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, 3)
+    tgt = np.ascontiguousarray(tgt, dtype=np.float64).reshape(-1, 3)
+    J = np.asarray(J, dtype=np.complex128)
+    single = J.ndim == 2
+    J = np.ascontiguousarray(J.reshape(-1, src.shape[0], 3))
+    A = np.zeros((J.shape[0], tgt.shape[0], 3), dtype=np.complex128)
+    if n_threads is None:
+        n_threads = os.cpu_count() or 1
+    Jr = J.view(np.float64)
+    Ar = A.view(np.float64)
+    rc = _load().lm_oracle_direct(k.size, _p(d), _p(k), src.shape[0], _p(src), J.shape[0],
+                                  _p(Jr), tgt.shape[0], _p(tgt), _p(Ar), int(n_threads))
+    if rc:
+        raise ValueError("oracle failed (rc=%d)" % rc)
+    return A[0] if single else A
+
+
+def direct_free(d, k, src, J, tgt, n_threads=None):
+    """Free-space part only (closed form), one right-hand side."""
+    d, k = _medium(d, k)
+    src = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, 3)
+    tgt = np.ascontiguousarray(tgt, dtype=np.float64).reshape(-1, 3)
+    J = np.ascontiguousarray(np.asarray(J, dtype=np.complex128).reshape(-1, 3))
+    A = np.zeros((tgt.shape[0], 3), dtype=np.complex128)
+    if n_threads is None:
+        n_threads = os.cpu_count() or 1
+    rc = _load().lm_oracle_direct_free(k.size, _p(d), _p(k), src.shape[0], _p(src),
+                                       _p(J.view(np.float64)), tgt.shape[0], _p(tgt),
+                                       _p(A.view(np.float64)), int(n_threads))
+    if rc:
+        raise ValueError("oracle failed (rc=%d)" % rc)
+    return A

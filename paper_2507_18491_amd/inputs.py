@@ -1,0 +1,149 @@
+"""Seeded synthetic workloads (positions, currents) for tests and benchmarks.
+
+This module holds no arithmetic of the method: it only draws points and
+current vectors.  Both the GPU path's tests and the oracle's tests take their
+inputs from here.
+
+Workloads follow the paper's numerical-test setup (Sec. 4: uniformly
+distributed particles in each layer, real wavenumbers) at the sizes of the
+benchmark configurations:
+
+* ``tiny``     2 layers, interface z=0, k=(1.0, 1.5); 300 points uniform in
+               [-1,1]^2 x [0.1,2.1] and 300 in [-1,1]^2 x [-2.1,-0.1].
+* ``three``    3 layers, interfaces z=0, -1.2, k=(1.2, 2.0, 1.5); N points
+               uniform in [-4,4]^2 per layer slab, split 40/30/30 %, at least
+               0.05 from every interface.  The half-space slabs are 1.2 thick
+               beyond the 0.05 margin: [0.05,1.25] and [-2.45,-1.25]; the
+               middle slab is [-1.15,-0.05].
+* ``four``     4 layers, interfaces z=0, -1, -2.5, k=(1.0, 1.8, 2.4, 1.3);
+               half the points uniform (25 % per layer), half in 20 Gaussian
+               blobs (sigma 0.3, 5 per layer).
+* ``clustered`` the three-layer medium with Gaussian blobs (sigma 0.3).
+
+Currents are complex128 3-vectors with real and imaginary parts U[-1,1].
+"""
+import numpy as np
+
+MEDIA = {
+    "two": dict(d=[0.0], k=[1.0, 1.5]),
+    "three": dict(d=[0.0, -1.2], k=[1.2, 2.0, 1.5]),
+    "four": dict(d=[0.0, -1.0, -2.5], k=[1.0, 1.8, 2.4, 1.3]),
+}
+
+MARGIN = 0.05
+HALFSPACE_THICKNESS = 1.2
+
+
+def layer_slabs(d, margin=MARGIN, thick=HALFSPACE_THICKNESS):
+    """z-extent of the point slab in each layer (top to bottom)."""
+    d = list(d)
+    slabs = []
+    for l in range(len(d) + 1):
+        if l == 0:
+            slabs.append((d[0] + margin, d[0] + margin + thick))
+        elif l == len(d):
+            slabs.append((d[-1] - margin - thick, d[-1] - margin))
+        else:
+            slabs.append((d[l] + margin, d[l - 1] - margin))
+    return slabs
+
+
+def _uniform_layers(rng, counts, slabs, half_width):
+    pts = []
+    for n, (lo, hi) in zip(counts, slabs):
+        xy = rng.uniform(-half_width, half_width, (n, 2))
+        z = rng.uniform(lo, hi, (n, 1))
+        pts.append(np.hstack([xy, z]))
+    return np.vstack(pts)
+
+
+def currents(rng, n, n_rhs=1):
+    J = rng.uniform(-1, 1, (n_rhs, n, 3)) + 1j * rng.uniform(-1, 1, (n_rhs, n, 3))
+    return J[0] if n_rhs == 1 else J
+
+
+def tiny(seed=0):
+    """Two-layer 600-point workload; returns (d, k, xyz[600,3], J[600,3])."""
+    rng = np.random.default_rng(seed)
+    m = MEDIA["two"]
+    xyz = _uniform_layers(rng, [300, 300], [(0.1, 2.1), (-2.1, -0.1)], 1.0)
+    J = currents(rng, xyz.shape[0])
+    return np.array(m["d"]), np.array(m["k"]), xyz, J
+
+
+def three_layer(n, seed=0, n_rhs=1, split=(0.4, 0.3, 0.3), half_width=4.0):
+    """Three-layer uniform workload; returns (d, k, xyz[n,3], J)."""
+    rng = np.random.default_rng(seed)
+    m = MEDIA["three"]
+    counts = [int(round(n * s)) for s in split[:-1]]
+    counts.append(n - sum(counts))
+    xyz = _uniform_layers(rng, counts, layer_slabs(m["d"]), half_width)
+    J = currents(rng, n, n_rhs)
+    return np.array(m["d"]), np.array(m["k"]), xyz, J
+
+
+def _blobs(rng, n, slabs, n_blobs_per_layer, sigma, half_width, layer_probs):
+    """n points in Gaussian blobs; points outside their slab or the box are
+    redrawn from the same blob."""
+    L = len(slabs)
+    centers = []
+    for l, (lo, hi) in enumerate(slabs):
+        for _ in range(n_blobs_per_layer):
+            c = np.array([rng.uniform(-half_width, half_width), rng.uniform(-half_width, half_width),
+                          rng.uniform(lo, hi)])
+            centers.append((l, c))
+    probs = np.repeat(np.asarray(layer_probs, dtype=float) / n_blobs_per_layer, n_blobs_per_layer)
+    probs = probs / probs.sum()
+    which = rng.choice(len(centers), size=n, p=probs)
+    out = np.empty((n, 3))
+    for i, b in enumerate(which):
+        l, c = centers[b]
+        lo, hi = slabs[l]
+        while True:
+            p = c + sigma * rng.standard_normal(3)
+            if lo <= p[2] <= hi and abs(p[0]) <= half_width and abs(p[1]) <= half_width:
+                out[i] = p
+                break
+    return out
+
+
+def clustered_three_layer(n, seed=0, n_blobs=8, sigma=0.3, n_rhs=1):
+    """Three-layer medium, n points in n_blobs Gaussian blobs (40/30/30 %)."""
+    rng = np.random.default_rng(seed)
+    m = MEDIA["three"]
+    slabs = layer_slabs(m["d"])
+    per = max(1, n_blobs // 3)
+    xyz = _blobs(rng, n, slabs, per, sigma, 4.0, [0.4, 0.3, 0.3])
+    J = currents(rng, n, n_rhs)
+    return np.array(m["d"]), np.array(m["k"]), xyz, J
+
+
+def four_layer(n, seed=0, n_rhs=1):
+    """Four-layer workload: n/2 uniform (25 % per layer) + n/2 in 20 blobs."""
+    rng = np.random.default_rng(seed)
+    m = MEDIA["four"]
+    slabs = layer_slabs(m["d"])
+    nu = n // 2
+    counts = [nu // 4] * 3 + [nu - 3 * (nu // 4)]
+    a = _uniform_layers(rng, counts, slabs, 4.0)
+    b = _blobs(rng, n - nu, slabs, 5, 0.3, 4.0, [1, 1, 1, 1])
+    xyz = np.vstack([a, b])
+    J = currents(rng, n, n_rhs)
+    return np.array(m["d"]), np.array(m["k"]), xyz, J
+
+
+def sample_targets(n, count=256, seed=0):
+    """Indices of sampled targets for the oracle comparison."""
+    rng = np.random.default_rng(seed + 1000)
+    return np.sort(rng.choice(n, size=min(count, n), replace=False))
+
+
+def sparse_currents(J, count, seed=0):
+    """Copy of J with all but `count` randomly chosen sources zeroed (for
+    oracle checks at full problem size); returns (J_sparse, kept indices)."""
+    n = J.shape[-2]
+    rng = np.random.default_rng(seed + 2000)
+    keep = np.sort(rng.choice(n, size=min(count, n), replace=False))
+    Js = np.zeros_like(J)
+    Js[..., keep, :] = J[..., keep, :]
+    return Js, keep
