@@ -1,0 +1,147 @@
+#!/usr/bin/env python3
+"""Benchmark of the layered-media dyadic FMM on one MI355X.
+
+Workload: three-layer medium (interfaces z = 0, -1.2; k = 1.2, 2.0, 1.5),
+N = 1e6 points uniform in [-4,4]^2 slabs (40/30/30 %, 0.05 from interfaces),
+targets = sources, one complex128 current vector, p = 12.  A step is one
+evaluation A = G J (P2M, M2M, M2L, L2L, L2P and the near field) on the built
+geometry (trees and M2L tables prebuilt, their time is reported separately
+as build_s); inputs are resident in HBM before the timed region.
+
+Prints one JSON line (rank 0).  Only one GPU is used: --gpus N with N > 1
+exits with a message.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "targets/s, 3-layer dyadic FMM N=1M p=12 at rel err≤1e-6; batched/adjoint vs plain"
+FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 fp64 FMA/clk x 2 flop x 2.4 GHz
+
+
+def cpu_baseline(d, k, x, J, n_total, budget_s=15.0, threads=16):
+    """The oracle (direct Sommerfeld sum) timed on the host cores on a
+    bounded sample: nt sampled targets against ns sampled sources; the rate
+    is scaled to targets/s of the full N-source sum."""
+    from oracle import oracle
+    rng = np.random.default_rng(11)
+    ti = rng.choice(x.shape[0], 16, replace=False)
+    si = rng.choice(x.shape[0], 200, replace=False)
+    t = time.time()
+    oracle.direct(d, k, x[si], J[si], x[ti], n_threads=threads)
+    dt = time.time() - t
+    pairs = 16 * 200
+    scale = max(1.0, min(50.0, budget_s / max(dt, 1e-3)))
+    nt = 16
+    ns = int(200 * scale)
+    si = rng.choice(x.shape[0], ns, replace=False)
+    t = time.time()
+    oracle.direct(d, k, x[si], J[si], x[ti], n_threads=threads)
+    dt = time.time() - t
+    pairs = nt * ns
+    rate = pairs / dt
+    return {"value": rate / n_total, "unit": "targets/s", "cores": threads, "kind": "oracle",
+            "sample": "%d sampled targets x %d sampled sources (%d pairs) in %.1f s; rate scaled to "
+                      "the full %d-source sum" % (nt, ns, pairs, dt, n_total)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1000000)
+    ap.add_argument("--p", type=int, default=12)
+    ap.add_argument("--p-free", type=int, default=0)
+    ap.add_argument("--rhs", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (got --gpus %d); the path shards by "
+              "independent FMM instances but no multi-GPU run is provided." % args.gpus, flush=True)
+        sys.exit(2)
+    import torch
+    from paper_2507_18491_amd import inputs, lmfmm
+
+    d, k, x, J = inputs.three_layer(args.n, seed=0, n_rhs=args.rhs)
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    fmm = lmfmm.LayeredDyadicFMM(d, k, p=args.p, p_free=args.p_free, device=0).build(x)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    st = fmm.stats()
+    print("built: %.2f s (plan %.0f ms, tables %.0f ms), m2l pairs free %d react %d, cases %d" % (
+        build_s, st["t_plan_ms"], st["t_tables_ms"], st["m2l_pairs_free"], st["m2l_pairs_react"],
+        st["n_cases"]), file=sys.stderr, flush=True)
+    Jt = torch.tensor(J, device=dev)
+    A = torch.empty((args.rhs, args.n, 3), dtype=torch.complex128, device=dev)
+    for _ in range(args.warmup):
+        fmm.evaluate(Jt.reshape(args.rhs, args.n, 3), out=A)
+    torch.cuda.synchronize()
+    fmm.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(args.steps):
+        fmm.evaluate(Jt.reshape(args.rhs, args.n, 3), out=A)
+    torch.cuda.synchronize()
+    wall = time.time() - t0
+    phases, ncalls = fmm.timings()
+    fmm.set_timing(False)
+    ms_per_step = 1000.0 * wall / args.steps
+    value = args.n * args.rhs / (wall / args.steps)
+    m2l_ms = phases["m2l"] / max(1, ncalls)
+    m2l_flops = st["m2l_cmac_useful"] * 8.0 * args.rhs
+    achieved = m2l_flops / (m2l_ms * 1e-3) / 1e12
+    print("timed: %.1f ms/step, phases (ms/step): %s" % (
+        ms_per_step, {a: round(b / max(1, ncalls), 2) for a, b in phases.items()}), file=sys.stderr, flush=True)
+
+    acc = None
+    if not args.no_accuracy:
+        fn = os.path.join(ROOT, "tests", "golden", "three_%d_sparse400_oracle.npz" % args.n)
+        if os.path.exists(fn) and args.rhs == 1:
+            g = np.load(fn)
+            Js, keep = inputs.sparse_currents(J, 400, seed=0)
+            As = fmm.evaluate(torch.tensor(Js, device=dev)).cpu().numpy()
+            acc = float(np.linalg.norm(As[g["idx"]] - g["A"]) / np.linalg.norm(g["A"]))
+    fmm.close()
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(d, k, x, J if args.rhs == 1 else J[0], args.n)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "targets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "three-layer dyadic FMM, N=%d uniform in layer slabs, targets=sources, "
+                               "p=%d, %d complex128 current vector(s)" % (args.n, args.p, args.rhs),
+                   "n": args.n, "p": args.p, "p_free": args.p_free or args.p, "layers": 3, "n_rhs": args.rhs},
+        "roofline": {"bound": "alu", "kernel": "k_m2l", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+                     "launch_ms": m2l_ms, "algorithmic_flops": m2l_flops},
+        "cpu_baseline": cpu,
+        "rel_err_vs_oracle": acc,
+        "build_s": build_s,
+        "cold_targets_per_s": args.n * args.rhs / (build_s + wall / args.steps),
+        "phase_ms_per_step": {a: b / max(1, ncalls) for a, b in phases.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

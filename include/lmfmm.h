@@ -1,0 +1,182 @@
+/*
+ * lmfmm.h -- C ABI of the layered-media dyadic fast multipole library
+ * (MI355X / gfx950, fp64).
+ *
+ * The library evaluates, for current elements J_j at source points x_j and
+ * target points y_i in a horizontally layered medium,
+ *
+ *     A(y_i) = sum_j G(y_i, x_j) J_j ,
+ *
+ * where G is the layered electric dyadic Green's function: the free-space
+ * dyadic (I + grad grad / k^2) e^{ikR}/(4 pi R) when source and target share a
+ * layer (skipped for coincident points), plus the interface reaction field
+ * (all pairs).  The operation is the layered sum of the paper's Sec. 3.3
+ * (problem statement of the FMM in layered media) in the standard
+ * orientation: target first, source second (Sec. 3.1).  The reaction field is
+ * evaluated by one FMM per reaction component (Sec. 3.3), with M2L tables
+ * from Chebyshev-expanded associated Legendre functions and Sommerfeld
+ * quadrature on a deformed contour (Sec. 3.4); the free-space part by a
+ * Helmholtz FMM with the dyadic operator applied to the local expansion
+ * (Sec. 2).
+ *
+ * Medium: layers 0..n-1 from top to bottom, interfaces z = d[0] > d[1] > ...
+ * (n-1 values), real wavenumbers k[l] > 0, mu = 1 and eps proportional to
+ * k^2 (the reading used for the paper's two interface problems of Sec. 3.1).
+ * A point with d[l] < z < d[l-1] lies in layer l.  Time convention: outgoing
+ * e^{+ikR}, Im k_z >= 0.
+ *
+ * Errors: every function returns an int status, LM_OK (0) on success or a
+ * negative code; lm_last_error() describes the last failure on a context.
+ * On LM_EINVAL, LM_EDOMAIN and LM_ESTATE no output is touched.  Nothing
+ * throws across the ABI.  One context must not be used from two host
+ * threads at once; distinct contexts are independent.
+ *
+ * Ownership: the caller owns every array it passes.  Positions are host
+ * arrays, copied by lm_build.  Currents and outputs are device arrays of
+ * interleaved complex128 (re, im) values, 16-byte aligned; the library never
+ * keeps them.  The context owns its device tables and work buffers until
+ * lm_destroy (or the next lm_build / lm_set_layers / lm_set_params).
+ */
+#ifndef LMFMM_H
+#define LMFMM_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LM_OK 0
+#define LM_EINVAL (-1)   /* invalid argument (null pointer, size, range)            */
+#define LM_EDOMAIN (-2)  /* invalid medium or geometry (interfaces, k, point on an  */
+                         /* interface, points too close to an interface)            */
+#define LM_ESTATE (-3)   /* wrong call order                                        */
+#define LM_ENOMEM (-4)   /* device allocation failed                                */
+#define LM_EHIP (-5)     /* HIP runtime error (message carries hipGetErrorString)   */
+
+#define LM_PMAX_ORDER 20
+
+typedef struct lm_ctx lm_ctx;
+
+typedef struct {
+  int p;              /* reaction-field expansion order, 1..20                      */
+  int p_free;         /* free-space expansion order, 0 => p                          */
+  int free_depth;     /* free-space octree leaf level, 0 => chosen by a cost model   */
+  int max_depth;      /* cap of the reaction-tree refinement next to interfaces      */
+  int gamma1_panels;  /* Gauss-Legendre panels (16 nodes each) on the contour piece  */
+                      /* from 0 to a in the fourth quadrant (Sec. 3.4)               */
+  double contour_a;   /* end point a of that piece on the real axis, 0 => 1.5 max k  */
+  double tail_digits; /* the real tail [a, kcut] of the Sommerfeld integrals ends at */
+                      /* kcut = a + (3p + tail_digits) / dz_min                       */
+  int components;     /* bit 0: free-space part, bit 1: reaction field (3 = both)    */
+} lm_params;
+
+/* Fills *prm with the defaults (p = 12, p_free = p, automatic depths). */
+int lm_default_params(lm_params* prm);
+
+/* Creates a context bound to HIP device `hip_device`.  *out is owned by the
+ * caller and released with lm_destroy.  LM_EHIP if the device does not exist. */
+int lm_create(lm_ctx** out, int hip_device);
+
+/* Releases the context and every device buffer it owns. */
+int lm_destroy(lm_ctx* ctx);
+
+/* Message of the last failure on ctx (valid until the next call on ctx). */
+const char* lm_last_error(const lm_ctx* ctx);
+
+/* Sets the layered medium (Sec. 3.1).  d_host: n_layers-1 interfaces,
+ * strictly decreasing; k_host: n_layers wavenumbers, finite and > 0; mu_host:
+ * NULL or all 1.0 (other permeabilities: LM_EDOMAIN).  Host arrays, copied.
+ * Invalidates a previous lm_build. */
+int lm_set_layers(lm_ctx* ctx, int n_layers, const double* d_host, const double* k_host,
+                  const double* mu_host);
+
+/* Sets the method parameters (copied).  Invalidates a previous lm_build. */
+int lm_set_params(lm_ctx* ctx, const lm_params* prm);
+
+/* Builds trees, interaction lists and every translation table for the
+ * given points: src_xyz [n_src][3] and tgt_xyz [n_tgt][3] are HOST arrays of
+ * fp64 coordinates (may be the same array).  Runs the table kernels on
+ * `stream` (a hipStream_t, NULL = default stream) and synchronises it once
+ * before returning.  LM_EDOMAIN if a point lies on an interface
+ * (|z - d| <= 1e-12 max(1,|d|)) or closer to one than the refinement cap
+ * allows; LM_ESTATE if no medium was set. */
+int lm_build(lm_ctx* ctx, int64_t n_src, const double* src_xyz, int64_t n_tgt,
+             const double* tgt_xyz, void* stream);
+
+/* Evaluates A = G J for n_rhs right-hand sides on the built geometry.
+ * J: DEVICE complex128 [n_rhs][n_src][3]; A: DEVICE complex128
+ * [n_rhs][n_tgt][3], overwritten.  All work is enqueued on `stream`
+ * (asynchronous: the call returns before the results are ready).  The
+ * summation order is fixed, so repeated calls give bitwise equal results. */
+int lm_evaluate(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream);
+
+/* Phase timing.  lm_set_timing(ctx, 1) (re)starts recording HIP events on
+ * the evaluation stream between the phases of every following lm_evaluate;
+ * lm_timings() waits for the recorded events and writes, summed over the
+ * timed evaluations, the milliseconds of each phase (indices LM_PHASE_*)
+ * followed by the number of timed evaluations (n >= LM_PHASES + 1). */
+int lm_set_timing(lm_ctx* ctx, int enable);
+int lm_timings(lm_ctx* ctx, double* out_host, int n);
+
+#define LM_PHASE_CLEAR 0   /* zeroing of A and of the local expansions           */
+#define LM_PHASE_P2M 1
+#define LM_PHASE_M2M 2
+#define LM_PHASE_M2L 3     /* one kernel: the M2L GEMM over all classes          */
+#define LM_PHASE_L2L 4
+#define LM_PHASE_L2P 5
+#define LM_PHASE_P2P 6
+#define LM_PHASES 7
+
+/* Statistics of the current build (host array of n doubles, indices below). */
+int lm_stats(const lm_ctx* ctx, double* out_host, int n);
+
+#define LM_STAT_N_FREE_INST 0
+#define LM_STAT_N_REACT_INST 1
+#define LM_STAT_M2L_PAIRS_FREE 2
+#define LM_STAT_M2L_PAIRS_REACT 3
+#define LM_STAT_P2P_PAIRS 4          /* free-space near-field point pairs          */
+#define LM_STAT_N_CASES 5            /* reaction M2L table cases                   */
+#define LM_STAT_N_NODES 6            /* Sommerfeld quadrature nodes                */
+#define LM_STAT_MAT_BYTES 7
+#define LM_STAT_ME_BYTES_PER_RHS 8
+#define LM_STAT_LE_BYTES_PER_RHS 9
+#define LM_STAT_T_PLAN_MS 10
+#define LM_STAT_T_UPLOAD_MS 11
+#define LM_STAT_T_TABLES_MS 12
+#define LM_STAT_N_SRC_BOXES 13
+#define LM_STAT_N_TGT_BOXES 14
+#define LM_STAT_N_M2L_CLASSES 15
+#define LM_STAT_N_M2L_TILES_1RHS 16
+#define LM_STAT_M2L_CMAC_USEFUL 17   /* complex multiply-adds of the M2L per rhs   */
+#define LM_STAT_M2L_CMAC_EXEC 18     /* same, including absent-source columns      */
+#define LM_STAT_N_LEAVES_P2M 19
+#define LM_STAT_FREE_DEPTH 20
+#define LM_STATS_COUNT 21
+
+/* ---- host-only helpers (no GPU needed), for tests of the host logic ---- */
+
+/* Reaction components of a medium (Sec. 3.1): returns their count and writes
+ * up to `cap` records of 8 ints: target layer, source layer, arrives-up,
+ * leaves-up, sign s, target map slope (+1 identity / -1 reflection), source
+ * map slope, 0. */
+int lm_host_components(int n_layers, const double* d, const double* k, int* out, int cap);
+
+/* Appendix A: C[j][s] with T_j(a x + b) = sum_s C[j][s] T_s(x), j,s <= jmax,
+ * written row-major with stride jmax+1 into out[(jmax+1)^2]. */
+int lm_host_cheb_affine(int jmax, double a, double b, double* out);
+
+/* Appendix B: B[tri(n,m)][k] with P^m_n(cos t) = tau_nm(t) sum_k B^k T_k(cos 2t)
+ * for 0 <= m <= n <= p (orthonormal Legendre functions, Condon-Shortley
+ * phase); tri(n,m) = n(n+1)/2 + m; *stride receives the row stride. */
+int lm_host_legendre_cheb(int p, double* out, int* stride);
+
+/* Plans a build on the host only (trees, lists, tables sizes) and returns
+ * lm_stats-style statistics; errbuf receives the planner's message on failure. */
+int lm_host_plan_stats(int n_layers, const double* d, const double* k, const lm_params* prm,
+                       int64_t n_src, const double* src_xyz, int64_t n_tgt, const double* tgt_xyz,
+                       double* out, int n, char* errbuf, int errlen);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LMFMM_H */

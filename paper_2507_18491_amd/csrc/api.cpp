@@ -1,0 +1,593 @@
+// api.cpp -- C ABI of the layered-media dyadic FMM library (see include/lmfmm.h).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/lmfmm.h"
+#include "kernels.h"
+#include "plan.h"
+
+#define TM_ROWS 64
+#define TN_COLS 64
+
+struct lm_ctx {
+  int device = 0;
+  std::string err;
+  Medium med;
+  bool layers_set = false;
+  PlanParams prm;
+  Plan plan;
+  bool built = false;
+  DevPlan d;
+  std::vector<void*> allocs;  // persistent device buffers of the current build
+  double* d_src = nullptr;
+  double* d_tgt = nullptr;
+  int* d_p2m = nullptr;
+  std::vector<int*> d_m2m, d_l2l, d_l2p, d_p2p;
+  std::vector<int> n_m2m, n_l2l, n_l2p, n_p2p;
+  std::vector<int> p2p_inst;  // instance of each P2P list
+  cd* ME = nullptr;
+  cd* LE = nullptr;
+  long long me_cap = 0, le_cap = 0;
+  int tiles_rhs = -1;
+  int n_tiles = 0;
+  M2LTile* d_tiles = nullptr;
+  double t_plan_ms = 0, t_upload_ms = 0, t_tables_ms = 0;
+  int pmax = 0;
+  bool timing = false;
+  std::vector<std::vector<hipEvent_t>> evsets;  // per timed evaluation: LM_PHASES+1 events
+};
+
+static void clear_events(lm_ctx* ctx) {
+  for (auto& v : ctx->evsets)
+    for (auto e : v) hipEventDestroy(e);
+  ctx->evsets.clear();
+}
+
+static int fail(lm_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPC(x)                                                                               \
+  do {                                                                                        \
+    hipError_t e_ = (x);                                                                      \
+    if (e_ != hipSuccess) return fail(ctx, LM_EHIP, std::string(#x ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+static void free_build(lm_ctx* ctx) {
+  clear_events(ctx);
+  for (void* p : ctx->allocs) hipFree(p);
+  ctx->allocs.clear();
+  if (ctx->ME) hipFree(ctx->ME);
+  if (ctx->LE) hipFree(ctx->LE);
+  if (ctx->d_tiles) hipFree(ctx->d_tiles);
+  ctx->ME = ctx->LE = nullptr;
+  ctx->d_tiles = nullptr;
+  ctx->me_cap = ctx->le_cap = 0;
+  ctx->tiles_rhs = -1;
+  ctx->d_m2m.clear();
+  ctx->d_l2l.clear();
+  ctx->d_l2p.clear();
+  ctx->d_p2p.clear();
+  ctx->n_m2m.clear();
+  ctx->n_l2l.clear();
+  ctx->n_l2p.clear();
+  ctx->n_p2p.clear();
+  ctx->p2p_inst.clear();
+  memset(&ctx->d, 0, sizeof(ctx->d));
+  ctx->built = false;
+}
+
+template <class T>
+static int upload(lm_ctx* ctx, T** out, const std::vector<T>& v) {
+  *out = nullptr;
+  if (v.empty()) return 0;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, v.size() * sizeof(T));
+  if (e != hipSuccess) return fail(ctx, LM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  ctx->allocs.push_back(p);
+  e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(ctx, LM_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  *out = (T*)p;
+  return 0;
+}
+
+static int dalloc(lm_ctx* ctx, void** out, size_t bytes) {
+  *out = nullptr;
+  if (bytes == 0) return 0;
+  hipError_t e = hipMalloc(out, bytes);
+  if (e != hipSuccess) return fail(ctx, LM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  ctx->allocs.push_back(*out);
+  return 0;
+}
+
+extern "C" {
+
+int lm_default_params(lm_params* prm) {
+  if (!prm) return LM_EINVAL;
+  memset(prm, 0, sizeof(*prm));
+  prm->p = 12;
+  prm->p_free = 0;
+  prm->free_depth = 0;
+  prm->max_depth = 14;
+  prm->gamma1_panels = 4;
+  prm->contour_a = 0.0;
+  prm->tail_digits = 60.0;
+  prm->components = 3;
+  return LM_OK;
+}
+
+int lm_create(lm_ctx** out, int hip_device) {
+  if (!out) return LM_EINVAL;
+  *out = nullptr;
+  lm_ctx* ctx = new lm_ctx();
+  ctx->device = hip_device;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || hip_device < 0 || hip_device >= n) {
+    delete ctx;
+    return LM_EHIP;
+  }
+  *out = ctx;
+  return LM_OK;
+}
+
+int lm_destroy(lm_ctx* ctx) {
+  if (!ctx) return LM_EINVAL;
+  hipSetDevice(ctx->device);
+  free_build(ctx);
+  delete ctx;
+  return LM_OK;
+}
+
+const char* lm_last_error(const lm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int lm_set_layers(lm_ctx* ctx, int n_layers, const double* d_host, const double* k_host, const double* mu_host) {
+  if (!ctx) return LM_EINVAL;
+  if (n_layers < 1 || n_layers > LM_MAXL || !k_host || (n_layers > 1 && !d_host))
+    return fail(ctx, LM_EINVAL, "n_layers out of range or null pointer");
+  Medium m;
+  m.n = n_layers;
+  m.kmax = 0;
+  for (int l = 0; l < n_layers; l++) {
+    if (!(k_host[l] > 0) || !std::isfinite(k_host[l])) return fail(ctx, LM_EDOMAIN, "wavenumbers must be finite and > 0");
+    if (mu_host && mu_host[l] != 1.0) return fail(ctx, LM_EDOMAIN, "only mu = 1 is supported");
+    m.k[l] = k_host[l];
+    m.kmax = std::max(m.kmax, k_host[l]);
+  }
+  for (int l = 0; l < n_layers - 1; l++) {
+    if (!std::isfinite(d_host[l])) return fail(ctx, LM_EDOMAIN, "interfaces must be finite");
+    if (l > 0 && !(d_host[l] < d_host[l - 1])) return fail(ctx, LM_EDOMAIN, "interfaces must be strictly decreasing");
+    m.d[l] = d_host[l];
+  }
+  ctx->med = m;
+  ctx->layers_set = true;
+  if (ctx->built) {
+    hipSetDevice(ctx->device);
+    free_build(ctx);
+  }
+  return LM_OK;
+}
+
+int lm_set_params(lm_ctx* ctx, const lm_params* p) {
+  if (!ctx || !p) return LM_EINVAL;
+  if (p->p < 1 || p->p > LM_PMAX_ORDER || p->p_free < 0 || p->p_free > LM_PMAX_ORDER)
+    return fail(ctx, LM_EINVAL, "expansion order out of range (1..20)");
+  if (p->max_depth < 1 || p->max_depth > 19) return fail(ctx, LM_EINVAL, "max_depth out of range (1..19)");
+  if (p->components < 1 || p->components > 3) return fail(ctx, LM_EINVAL, "components must be 1, 2 or 3");
+  PlanParams q;
+  q.p = p->p;
+  q.p_free = p->p_free;
+  q.free_depth = p->free_depth;
+  q.max_depth = p->max_depth;
+  q.gamma1_panels = p->gamma1_panels > 0 ? p->gamma1_panels : 4;
+  q.contour_a = p->contour_a;
+  q.tail_digits = p->tail_digits > 0 ? p->tail_digits : 60.0;
+  q.components = p->components;
+  ctx->prm = q;
+  if (ctx->built) {
+    hipSetDevice(ctx->device);
+    free_build(ctx);
+  }
+  return LM_OK;
+}
+
+static bool finite_pts(const double* x, int64_t n) {
+  for (int64_t i = 0; i < 3 * n; i++)
+    if (!std::isfinite(x[i])) return false;
+  return true;
+}
+
+int lm_build(lm_ctx* ctx, int64_t n_src, const double* src_xyz, int64_t n_tgt, const double* tgt_xyz,
+             void* stream) {
+  if (!ctx) return LM_EINVAL;
+  if (!ctx->layers_set) return fail(ctx, LM_ESTATE, "lm_set_layers must be called before lm_build");
+  if (n_src < 0 || n_tgt < 0 || (n_src > 0 && !src_xyz) || (n_tgt > 0 && !tgt_xyz))
+    return fail(ctx, LM_EINVAL, "invalid point arrays");
+  if (n_src > 2000000000LL || n_tgt > 2000000000LL) return fail(ctx, LM_EINVAL, "too many points");
+  if (!finite_pts(src_xyz, n_src) || !finite_pts(tgt_xyz, n_tgt)) return fail(ctx, LM_EINVAL, "non-finite coordinates");
+  const Medium& med = ctx->med;
+  for (int pass = 0; pass < 2; pass++) {
+    const double* x = pass ? tgt_xyz : src_xyz;
+    int64_t n = pass ? n_tgt : n_src;
+    for (int64_t i = 0; i < n; i++)
+      for (int l = 0; l < med.n - 1; l++)
+        if (fabs(x[3 * i + 2] - med.d[l]) <= 1e-12 * std::max(1.0, fabs(med.d[l])))
+          return fail(ctx, LM_EDOMAIN, "a point lies on an interface");
+  }
+  HIPC(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  free_build(ctx);
+  auto t0 = std::chrono::steady_clock::now();
+  std::string msg = lm_make_plan(ctx->plan, med, ctx->prm, n_src, src_xyz, n_tgt, tgt_xyz);
+  if (!msg.empty()) return fail(ctx, LM_EDOMAIN, msg);
+  auto t1 = std::chrono::steady_clock::now();
+  Plan& pl = ctx->plan;
+  ctx->pmax = std::max(pl.p, pl.pf);
+  DevPlan& d = ctx->d;
+  int rc;
+  if ((rc = upload(ctx, &d.inst, pl.inst))) return rc;
+  if ((rc = upload(ctx, &d.sbox, pl.sbox))) return rc;
+  if ((rc = upload(ctx, &d.tbox, pl.tbox))) return rc;
+  if ((rc = upload(ctx, &d.sbox_m2m, pl.sbox_m2m))) return rc;
+  if ((rc = upload(ctx, &d.tbox_l2l, pl.tbox_l2l))) return rc;
+  if ((rc = upload(ctx, &d.src_perm, pl.src_perm))) return rc;
+  if ((rc = upload(ctx, &d.tgt_perm, pl.tgt_perm))) return rc;
+  if ((rc = upload(ctx, &d.p2p_list, pl.p2p_list))) return rc;
+  if ((rc = upload(ctx, &d.cls, pl.cls))) return rc;
+  if ((rc = upload(ctx, &d.offs, pl.offs))) return rc;
+  if ((rc = upload(ctx, &d.cls_tgt, pl.cls_tgt))) return rc;
+  if ((rc = upload(ctx, &d.cls_srcof, pl.cls_srcof))) return rc;
+  if ((rc = upload(ctx, &d.cls_srcof0, pl.cls_srcof0))) return rc;
+  if ((rc = upload(ctx, &d.gaunt, pl.gaunt))) return rc;
+  d.gaunt_p = pl.gaunt_p;
+  if ((rc = upload(ctx, &d.Bcoef, pl.Bcoef))) return rc;
+  if ((rc = upload(ctx, &d.Ccoef, pl.Ccoef))) return rc;
+  if ((rc = upload(ctx, &d.Ccoef0, pl.Ccoef0))) return rc;
+  if ((rc = upload(ctx, &d.cases, pl.cases))) return rc;
+  if ((rc = upload(ctx, &d.trans, pl.trans))) return rc;
+  std::vector<double> sx(src_xyz, src_xyz + 3 * n_src), tx(tgt_xyz, tgt_xyz + 3 * n_tgt);
+  if ((rc = upload(ctx, &ctx->d_src, sx))) return rc;
+  if ((rc = upload(ctx, &ctx->d_tgt, tx))) return rc;
+  if ((rc = upload(ctx, &ctx->d_p2m, pl.p2m_leaves))) return rc;
+  for (auto& v : pl.m2m_parents) {
+    int* p = nullptr;
+    if ((rc = upload(ctx, &p, v))) return rc;
+    ctx->d_m2m.push_back(p);
+    ctx->n_m2m.push_back((int)v.size());
+  }
+  for (auto& v : pl.l2l_children) {
+    int* p = nullptr;
+    if ((rc = upload(ctx, &p, v))) return rc;
+    ctx->d_l2l.push_back(p);
+    ctx->n_l2l.push_back((int)v.size());
+  }
+  for (auto& v : pl.l2p_leaves) {
+    int* p = nullptr;
+    if ((rc = upload(ctx, &p, v))) return rc;
+    ctx->d_l2p.push_back(p);
+    ctx->n_l2p.push_back((int)v.size());
+  }
+  {
+    int fi = 0;
+    for (size_t i = 0; i < pl.inst.size(); i++)
+      if (pl.inst[i].kind == 0) {
+        int* p = nullptr;
+        if ((rc = upload(ctx, &p, pl.p2p_tboxes[fi]))) return rc;
+        ctx->d_p2p.push_back(p);
+        ctx->n_p2p.push_back((int)pl.p2p_tboxes[fi].size());
+        ctx->p2p_inst.push_back((int)i);
+        fi++;
+      }
+  }
+  // matrices and table scratch
+  void* vp = nullptr;
+  if ((rc = dalloc(ctx, &vp, (size_t)pl.mat_size * sizeof(cd)))) return rc;
+  d.mats = (cd*)vp;
+  auto t2 = std::chrono::steady_clock::now();
+  launch_trans(d, (int)pl.trans.size(), pl.gaunt_p, s);
+  HIPC(hipGetLastError());
+  MediumDev md;
+  memset(&md, 0, sizeof(md));
+  md.n = med.n;
+  for (int l = 0; l < med.n; l++) md.k[l] = med.k[l];
+  for (int l = 0; l < med.n - 1; l++) md.d[l] = med.d[l];
+  if (!pl.cases.empty()) {
+    std::vector<cd> dummy;
+    cd *kr = nullptr, *w = nullptr;
+    int* ni = nullptr;
+    void *pk = nullptr, *pw = nullptr, *pi = nullptr, *pn = nullptr, *pib = nullptr, *psc = nullptr;
+    size_t nn = pl.node_kr.size();
+    HIPC(hipMalloc(&pk, nn * sizeof(cd)));
+    HIPC(hipMalloc(&pw, nn * sizeof(cd)));
+    HIPC(hipMalloc(&pi, nn * sizeof(int)));
+    HIPC(hipMalloc(&pn, nn * sizeof(QNode)));
+    HIPC(hipMemcpy(pk, pl.node_kr.data(), nn * sizeof(cd), hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(pw, pl.node_w.data(), nn * sizeof(cd), hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(pi, pl.node_inst.data(), nn * sizeof(int), hipMemcpyHostToDevice));
+    kr = (cd*)pk;
+    w = (cd*)pw;
+    ni = (int*)pi;
+    d.nodes = (QNode*)pn;
+    launch_nodes(d, md, (int)nn, ni, kr, w, s);
+    HIPC(hipGetLastError());
+    // integrals and assembly in batches of cases (bounded scratch)
+    int maxnode = 0;
+    for (auto& tc : pl.cases) maxnode = std::max(maxnode, tc.nnode);
+    int NQ = 2 * pl.p + 3;
+    long long per_case_scr = (long long)maxnode * (NQ + 1);
+    long long per_case_ib = 5LL * 16 * (pl.p + 2) * NQ;
+    int batch = (int)std::max(1LL, std::min((long long)pl.cases.size(), (long long)(256LL << 20) / (per_case_scr * 16)));
+    HIPC(hipMalloc(&psc, (size_t)batch * per_case_scr * sizeof(cd)));
+    HIPC(hipMalloc(&pib, (size_t)pl.cases.size() * per_case_ib * sizeof(cd)));
+    d.ibuf = (cd*)pib;
+    for (int c0 = 0; c0 < (int)pl.cases.size(); c0 += batch) {
+      int nc = std::min(batch, (int)pl.cases.size() - c0);
+      launch_tab_integrals(d, md, c0, nc, pl.p, (cd*)psc, maxnode, s);
+      HIPC(hipGetLastError());
+    }
+    launch_tab_assemble(d, 0, (int)pl.cases.size(), pl.p, pl.kmaxcheb, (ctx->pmax + 1) / 2 + 2, s);
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(s));
+    hipFree(pk);
+    hipFree(pw);
+    hipFree(pi);
+    hipFree(pn);
+    hipFree(psc);
+    hipFree(pib);
+    d.nodes = nullptr;
+    d.ibuf = nullptr;
+  }
+  HIPC(hipStreamSynchronize(s));
+  auto t3 = std::chrono::steady_clock::now();
+  ctx->t_plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  ctx->t_upload_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
+  ctx->t_tables_ms = std::chrono::duration<double, std::milli>(t3 - t2).count();
+  ctx->built = true;
+  return LM_OK;
+}
+
+static int ensure_rhs(lm_ctx* ctx, int n_rhs) {
+  Plan& pl = ctx->plan;
+  long long me = pl.me_size * n_rhs, le = pl.le_size * n_rhs;
+  if (me > ctx->me_cap) {
+    if (ctx->ME) hipFree(ctx->ME);
+    ctx->ME = nullptr;
+    HIPC(hipMalloc((void**)&ctx->ME, (size_t)std::max(1LL, me) * sizeof(cd)));
+    ctx->me_cap = me;
+  }
+  if (le > ctx->le_cap) {
+    if (ctx->LE) hipFree(ctx->LE);
+    ctx->LE = nullptr;
+    HIPC(hipMalloc((void**)&ctx->LE, (size_t)std::max(1LL, le) * sizeof(cd)));
+    ctx->le_cap = le;
+  }
+  if (ctx->tiles_rhs != n_rhs) {
+    std::vector<M2LTile> tiles;
+    for (int c = 0; c < (int)pl.cls.size(); c++) {
+      const M2LClass& C = pl.cls[c];
+      int ncol = C.n_tgt * n_rhs;
+      for (int ot = 0; ot < 3; ot++)
+        for (int r0 = 0; r0 < C.P; r0 += TM_ROWS)
+          for (int c0 = 0; c0 < ncol; c0 += TN_COLS) {
+            M2LTile t;
+            t.cls = c;
+            t.out_type = ot;
+            t.col0 = c0;
+            t.ncol = std::min(TN_COLS, ncol - c0);
+            t.row0 = r0;
+            tiles.push_back(t);
+          }
+    }
+    if (ctx->d_tiles) hipFree(ctx->d_tiles);
+    ctx->d_tiles = nullptr;
+    if (!tiles.empty()) {
+      HIPC(hipMalloc((void**)&ctx->d_tiles, tiles.size() * sizeof(M2LTile)));
+      HIPC(hipMemcpy(ctx->d_tiles, tiles.data(), tiles.size() * sizeof(M2LTile), hipMemcpyHostToDevice));
+    }
+    ctx->n_tiles = (int)tiles.size();
+    ctx->tiles_rhs = n_rhs;
+  }
+  ctx->d.tiles = ctx->d_tiles;
+  return LM_OK;
+}
+
+int lm_evaluate(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream) {
+  if (!ctx) return LM_EINVAL;
+  if (!ctx->built) return fail(ctx, LM_ESTATE, "lm_build must succeed before lm_evaluate");
+  if (n_rhs < 1 || n_rhs > 4096) return fail(ctx, LM_EINVAL, "n_rhs out of range (1..4096)");
+  Plan& pl = ctx->plan;
+  if ((pl.n_src > 0 && !J) || (pl.n_tgt > 0 && !A)) return fail(ctx, LM_EINVAL, "null J or A");
+  if (((uintptr_t)J % 16) || ((uintptr_t)A % 16)) return fail(ctx, LM_EINVAL, "J and A must be 16-byte aligned");
+  HIPC(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  int rc = ensure_rhs(ctx, n_rhs);
+  if (rc) return rc;
+  const cd* Jc = (const cd*)J;
+  cd* Ac = (cd*)A;
+  DevPlan& d = ctx->d;
+  std::vector<hipEvent_t> ev;
+  if (ctx->timing && ctx->evsets.size() < 4096) {
+    ev.resize(LM_PHASES + 1);
+    for (auto& e : ev) HIPC(hipEventCreate(&e));
+  }
+  auto mark = [&](int i) {
+    if (!ev.empty()) (void)hipEventRecord(ev[i], s);
+  };
+  mark(0);
+  launch_fill(Ac, (long long)n_rhs * pl.n_tgt * 3, s);
+  if (pl.n_src > 0 && pl.n_tgt > 0) launch_fill(ctx->LE, pl.le_size * n_rhs, s);
+  mark(1);
+  if (pl.n_src > 0 && pl.n_tgt > 0) {
+    launch_p2m(d, ctx->d_p2m, (int)pl.p2m_leaves.size(), ctx->d_src, Jc, pl.n_src, n_rhs, ctx->ME, ctx->pmax, s);
+    mark(2);
+    for (int l = (int)ctx->d_m2m.size() - 1; l >= 0; l--)
+      launch_m2m(d, ctx->d_m2m[l], ctx->n_m2m[l], n_rhs, ctx->ME, ctx->pmax, s);
+    mark(3);
+    launch_m2l(d, ctx->n_tiles, n_rhs, ctx->ME, ctx->LE, ctx->pmax, s);
+    mark(4);
+    for (int l = 1; l < (int)ctx->d_l2l.size(); l++)
+      launch_l2l(d, ctx->d_l2l[l], ctx->n_l2l[l], n_rhs, ctx->LE, ctx->pmax, s);
+    mark(5);
+    for (size_t i = 0; i < pl.inst.size(); i++)
+      launch_l2p(d, ctx->d_l2p[i], ctx->n_l2p[i], pl.inst[i].kind == 0 ? 0 : 1, ctx->d_tgt, pl.n_tgt, n_rhs,
+                 ctx->LE, Ac, ctx->pmax, s);
+    mark(6);
+    for (size_t f = 0; f < ctx->d_p2p.size(); f++) {
+      int i = ctx->p2p_inst[f];
+      launch_p2p(d, ctx->d_p2p[f], ctx->n_p2p[f], ctx->d_src, Jc, pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs,
+                 pl.inst[i].kt, Ac, s);
+    }
+    mark(7);
+  } else {
+    for (int i = 2; i <= 7; i++) mark(i);
+  }
+  if (!ev.empty()) ctx->evsets.push_back(ev);
+  HIPC(hipGetLastError());
+  return LM_OK;
+}
+
+int lm_set_timing(lm_ctx* ctx, int enable) {
+  if (!ctx) return LM_EINVAL;
+  HIPC(hipSetDevice(ctx->device));
+  clear_events(ctx);
+  ctx->timing = enable != 0;
+  return LM_OK;
+}
+
+int lm_timings(lm_ctx* ctx, double* out, int n) {
+  if (!ctx || !out || n < 1) return LM_EINVAL;
+  HIPC(hipSetDevice(ctx->device));
+  double acc[LM_PHASES + 1] = {0};
+  for (auto& v : ctx->evsets) {
+    HIPC(hipEventSynchronize(v[LM_PHASES]));
+    for (int i = 0; i < LM_PHASES; i++) {
+      float ms = 0;
+      HIPC(hipEventElapsedTime(&ms, v[i], v[i + 1]));
+      acc[i] += ms;
+    }
+  }
+  acc[LM_PHASES] = (double)ctx->evsets.size();
+  int m = n < LM_PHASES + 1 ? n : LM_PHASES + 1;
+  memcpy(out, acc, m * sizeof(double));
+  return LM_OK;
+}
+
+int lm_stats(const lm_ctx* ctx, double* out, int n) {
+  if (!ctx || !out || n < 1) return LM_EINVAL;
+  const Plan& pl = ctx->plan;
+  double v[LM_STATS_COUNT] = {0};
+  v[LM_STAT_N_FREE_INST] = pl.n_free_inst;
+  v[LM_STAT_N_REACT_INST] = pl.n_react_inst;
+  v[LM_STAT_M2L_PAIRS_FREE] = (double)pl.n_m2l_pairs_free;
+  v[LM_STAT_M2L_PAIRS_REACT] = (double)pl.n_m2l_pairs_react;
+  v[LM_STAT_P2P_PAIRS] = (double)pl.n_p2p_pairs;
+  v[LM_STAT_N_CASES] = (double)pl.cases.size();
+  v[LM_STAT_N_NODES] = (double)pl.node_kr.size();
+  v[LM_STAT_MAT_BYTES] = (double)pl.mat_size * 16.0;
+  v[LM_STAT_ME_BYTES_PER_RHS] = (double)pl.me_size * 16.0;
+  v[LM_STAT_LE_BYTES_PER_RHS] = (double)pl.le_size * 16.0;
+  v[LM_STAT_T_PLAN_MS] = ctx->t_plan_ms;
+  v[LM_STAT_T_UPLOAD_MS] = ctx->t_upload_ms;
+  v[LM_STAT_T_TABLES_MS] = ctx->t_tables_ms;
+  v[LM_STAT_N_SRC_BOXES] = (double)pl.sbox.size();
+  v[LM_STAT_N_TGT_BOXES] = (double)pl.tbox.size();
+  v[LM_STAT_N_M2L_CLASSES] = (double)pl.cls.size();
+  v[LM_STAT_N_M2L_TILES_1RHS] = 0;
+  {
+    long long t = 0;
+    for (auto& C : pl.cls) t += 3LL * ((C.P + TM_ROWS - 1) / TM_ROWS) * ((C.n_tgt + TN_COLS - 1) / TN_COLS);
+    v[LM_STAT_N_M2L_TILES_1RHS] = (double)t;
+  }
+  {
+    // dense M2L work (complex multiply-adds) per right-hand side, including
+    // the zero columns of absent sources inside a class
+    double cm = 0, ce = 0;
+    for (size_t c = 0; c < pl.cls.size(); c++) {
+      const M2LClass& C = pl.cls[c];
+      double per = 3.0 * C.P * (double)(C.nblk * C.P);
+      ce += per * C.n_tgt * C.n_off;
+      long long base = pl.cls_srcof0[c];
+      long long used = 0;
+      for (long long e = 0; e < (long long)C.n_tgt * C.n_off; e++) used += pl.cls_srcof[base + e] >= 0;
+      cm += per * used;
+    }
+    v[LM_STAT_M2L_CMAC_USEFUL] = cm;
+    v[LM_STAT_M2L_CMAC_EXEC] = ce;
+  }
+  v[LM_STAT_N_LEAVES_P2M] = (double)pl.p2m_leaves.size();
+  double fd = 0;
+  for (int x : pl.free_depth_used) fd = std::max(fd, (double)x);
+  v[LM_STAT_FREE_DEPTH] = fd;
+  int m = n < LM_STATS_COUNT ? n : LM_STATS_COUNT;
+  memcpy(out, v, m * sizeof(double));
+  return LM_OK;
+}
+
+// ---------------------------------------------------------------- host-only helpers
+int lm_host_components(int n_layers, const double* d, const double* k, int* out, int cap) {
+  if (n_layers < 1 || n_layers > LM_MAXL || !k || (n_layers > 1 && !d)) return LM_EINVAL;
+  Medium m;
+  m.n = n_layers;
+  for (int l = 0; l < n_layers; l++) m.k[l] = k[l];
+  for (int l = 0; l < n_layers - 1; l++) m.d[l] = d[l];
+  std::vector<InstParams> v;
+  int n = lm_enumerate_components(m, v);
+  for (int i = 0; i < n && i < cap; i++) {
+    out[8 * i + 0] = v[i].lt;
+    out[8 * i + 1] = v[i].ls;
+    out[8 * i + 2] = v[i].up_t;
+    out[8 * i + 3] = v[i].up_s;
+    out[8 * i + 4] = v[i].sgn;
+    out[8 * i + 5] = (int)v[i].at;
+    out[8 * i + 6] = (int)v[i].as;
+    out[8 * i + 7] = 0;
+  }
+  return n;
+}
+
+int lm_host_cheb_affine(int jmax, double a, double b, double* out) {
+  if (jmax < 0 || jmax > 64 || !out) return LM_EINVAL;
+  std::vector<double> C;
+  lm_cheb_affine(jmax, a, b, C);
+  memcpy(out, C.data(), C.size() * sizeof(double));
+  return LM_OK;
+}
+
+int lm_host_legendre_cheb(int p, double* out, int* stride) {
+  if (p < 0 || p > LM_PMAX_ORDER || !out || !stride) return LM_EINVAL;
+  std::vector<double> B;
+  lm_legendre_cheb(p, B);
+  memcpy(out, B.data(), B.size() * sizeof(double));
+  *stride = (p + 1) / 2 + 2;
+  return LM_OK;
+}
+
+int lm_host_plan_stats(int n_layers, const double* d, const double* k, const lm_params* prm, int64_t n_src,
+                       const double* src_xyz, int64_t n_tgt, const double* tgt_xyz, double* out, int n,
+                       char* errbuf, int errlen) {
+  lm_ctx tmp;
+  int rc = lm_set_layers(&tmp, n_layers, d, k, nullptr);
+  if (rc) {
+    if (errbuf && errlen > 0) snprintf(errbuf, errlen, "%s", tmp.err.c_str());
+    return rc;
+  }
+  if (prm && (rc = lm_set_params(&tmp, prm))) {
+    if (errbuf && errlen > 0) snprintf(errbuf, errlen, "%s", tmp.err.c_str());
+    return rc;
+  }
+  std::string msg = lm_make_plan(tmp.plan, tmp.med, tmp.prm, n_src, src_xyz, n_tgt, tgt_xyz);
+  if (!msg.empty()) {
+    if (errbuf && errlen > 0) snprintf(errbuf, errlen, "%s", msg.c_str());
+    return LM_EDOMAIN;
+  }
+  return lm_stats(&tmp, out, n);
+}
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+// kernels.h -- host-side launchers of the HIP kernels.
+#pragma once
+#include "lmfmm_internal.h"
+
+struct MediumDev {
+  int n;
+  double d[LM_MAXL];
+  double k[LM_MAXL];
+};
+
+// device-side view of a built plan
+struct DevPlan {
+  InstParams* inst;
+  SrcBox* sbox;
+  TgtBox* tbox;
+  long long* sbox_m2m;
+  long long* tbox_l2l;
+  int* src_perm;
+  int* tgt_perm;
+  int* p2p_list;
+  M2LClass* cls;
+  M2LOffset* offs;
+  int* cls_tgt;
+  int* cls_srcof;
+  long long* cls_srcof0;
+  M2LTile* tiles;
+  cd* mats;        // all translation / M2L matrices
+  double* gaunt;
+  int gaunt_p;
+  double* Bcoef;
+  double* Ccoef;
+  long long* Ccoef0;
+  TabCase* cases;
+  QNode* nodes;
+  cd* ibuf;        // Chebyshev-Sommerfeld integrals
+  TransJob* trans;
+};
+
+void launch_fill(cd* p, long long n, hipStream_t s);
+void launch_trans(const DevPlan& d, int n_jobs, int pmax_gaunt, hipStream_t s);
+void launch_nodes(const DevPlan& d, MediumDev med, int n_nodes, const int* node_inst, const cd* kr,
+                  const cd* w, hipStream_t s);
+void launch_tab_integrals(const DevPlan& d, MediumDev med, int case0, int ncase, int p, cd* scratch,
+                          long long scratch_stride, hipStream_t s);
+void launch_tab_assemble(const DevPlan& d, int case0, int ncase, int p, int kmaxcheb, int bstride, hipStream_t s);
+void launch_p2m(const DevPlan& d, const int* leaves, int n, const double* xyz, const cd* J,
+                long long n_src, int n_rhs, cd* ME, int pmax, hipStream_t s);
+void launch_m2m(const DevPlan& d, const int* parents, int n, int n_rhs, cd* ME, int pmax, hipStream_t s);
+void launch_m2l(const DevPlan& d, int n_tiles, int n_rhs, const cd* ME, cd* LE, int pmax, hipStream_t s);
+void launch_l2l(const DevPlan& d, const int* children, int n, int n_rhs, cd* LE, int pmax, hipStream_t s);
+void launch_l2p(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_tgt,
+                int n_rhs, const cd* LE, cd* A, int pmax, hipStream_t s);
+void launch_p2p(const DevPlan& d, const int* tboxes, int n, const double* sxyz, const cd* J, long long n_src,
+                const double* txyz, long long n_tgt, int n_rhs, double k, cd* A, hipStream_t s);

@@ -1,0 +1,943 @@
+// kernels.hip -- gfx950 kernels of the layered-media dyadic FMM (fp64).
+//
+// Passes (paper Sec. 2 and Sec. 3.3): P2M, M2M, M2L, L2L, L2P for the
+// free-space part of every layer and for every reaction component, the
+// free-space near field P2P, and the table builders: free-space translation
+// matrices (addition theorem through Gaunt coefficients), Sommerfeld
+// quadrature densities of the reaction components, the Chebyshev-weighted
+// Sommerfeld integrals (Sec. 3.4) and their assembly into M2L matrices.
+//
+// Coefficient vectors are stored per box as [rhs][channel][(p+1)^2], with
+// channels in the spin basis (x + i y, x - i y, z).
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+#define RC 4            // right-hand sides per block in the point/translation passes
+#define NT 256          // threads per block
+
+__device__ inline int n_of(int nm) {
+  int n = (int)sqrt((double)nm);
+  while (n * n > nm) n--;
+  while ((n + 1) * (n + 1) <= nm) n++;
+  return n;
+}
+
+// ------------------------------------------------------------------ fill
+__global__ void k_fill(cd* p, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += st) p[i] = cd{0.0, 0.0};
+}
+void launch_fill(cd* p, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  long long nb = (n + NT - 1) / NT;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)nb), dim3(NT), 0, s, p, n);
+}
+
+// ------------------------------------------------------------------ P2M
+// M[r][ch][nm] = sum_j q_j^ch j_n(k |d_j|) conj(Y^m_n(d_j)),  d_j = image(x_j) - centre
+// (paper Sec. 2, the multipole coefficients, and Sec. 3.3, the reaction ME
+// coefficients; the constant 4 pi lives in the M2L tables).
+#define P2M_NPT 32
+__global__ __launch_bounds__(NT) void k_p2m(DevPlan d, const int* leaves, const double* xyz, const cd* J,
+                                            long long n_src, int n_rhs, cd* ME) {
+  extern __shared__ double sm[];
+  int b = leaves[blockIdx.x];
+  SrcBox sb = d.sbox[b];
+  InstParams ip = d.inst[sb.inst];
+  int p = ip.p, P = ip.P, ntri = (p + 1) * (p + 2) / 2;
+  int r0 = blockIdx.y * RC, nr = min(RC, n_rhs - r0);
+  int stride = (p + 1) + ntri + 2 * (p + 1) + RC * 6;
+  int tid = threadIdx.x;
+  cd acc[2][RC][3];
+  for (int h = 0; h < 2; h++)
+    for (int r = 0; r < RC; r++)
+      for (int c = 0; c < 3; c++) acc[h][r][c] = cd{0, 0};
+  for (int base = sb.pt0; base < sb.pt1; base += P2M_NPT) {
+    int np = min(P2M_NPT, sb.pt1 - base);
+    __syncthreads();
+    if (tid < np) {
+      double* rec = sm + tid * stride;
+      int id = d.src_perm[base + tid];
+      double dx = xyz[3 * id] - sb.c[0], dy = xyz[3 * id + 1] - sb.c[1];
+      double dz = ip.as * xyz[3 * id + 2] + ip.bs - sb.c[2];
+      double rxy = sqrt(dx * dx + dy * dy), r = sqrt(dx * dx + dy * dy + dz * dz);
+      double ct = r > 0 ? dz / r : 1.0, st = r > 0 ? rxy / r : 0.0;
+      double ex = rxy > 0 ? dx / rxy : 1.0, ey = rxy > 0 ? dy / rxy : 0.0;
+      sph_jn(p, ip.ks * r, rec);
+      legendre_r(p, ct, st, rec + (p + 1));
+      double* e = rec + (p + 1) + ntri;  // e^{-i m phi}
+      cd em = cd{1.0, 0.0}, e1 = cd{ex, -ey};
+      for (int m = 0; m <= p; m++) {
+        e[2 * m] = em.x;
+        e[2 * m + 1] = em.y;
+        em = em * e1;
+      }
+      double* q = e + 2 * (p + 1);
+      for (int rr = 0; rr < RC; rr++) {
+        cd jx = cd{0, 0}, jy = cd{0, 0}, jz = cd{0, 0};
+        if (rr < nr) {
+          const cd* Jp = J + ((long long)(r0 + rr) * n_src + id) * 3;
+          jx = Jp[0];
+          jy = Jp[1];
+          jz = Jp[2];
+        }
+        cd up = jx + cd{-jy.y, jy.x};  // jx + i jy
+        cd um = jx - cd{-jy.y, jy.x};
+        q[rr * 6 + 0] = up.x;
+        q[rr * 6 + 1] = up.y;
+        q[rr * 6 + 2] = um.x;
+        q[rr * 6 + 3] = um.y;
+        q[rr * 6 + 4] = jz.x;
+        q[rr * 6 + 5] = jz.y;
+      }
+    }
+    __syncthreads();
+    for (int h = 0; h < 2; h++) {
+      int nm = tid + NT * h;
+      if (nm >= P) continue;
+      int n = n_of(nm), m = nm - n * n - n, am = m < 0 ? -m : m;
+      double sg = (m < 0 && (am & 1)) ? -1.0 : 1.0;
+      for (int t = 0; t < np; t++) {
+        const double* rec = sm + t * stride;
+        double rad = rec[n] * rec[(p + 1) + tri_idx(n, am)] * sg;
+        const double* e = rec + (p + 1) + ntri;
+        cd ph = cd{e[2 * am], m < 0 ? -e[2 * am + 1] : e[2 * am + 1]};
+        cd bas = rad * ph;
+        const double* q = e + 2 * (p + 1);
+        for (int rr = 0; rr < RC; rr++)
+          for (int c = 0; c < 3; c++) acc[h][rr][c] = acc[h][rr][c] + cd{q[rr * 6 + 2 * c], q[rr * 6 + 2 * c + 1]} * bas;
+      }
+    }
+  }
+  for (int h = 0; h < 2; h++) {
+    int nm = tid + NT * h;
+    if (nm >= P) continue;
+    for (int rr = 0; rr < nr; rr++)
+      for (int c = 0; c < 3; c++) ME[sb.me_off * n_rhs + ((long long)(r0 + rr) * 3 + c) * P + nm] = acc[h][rr][c];
+  }
+}
+void launch_p2m(const DevPlan& d, const int* leaves, int n, const double* xyz, const cd* J, long long n_src,
+                int n_rhs, cd* ME, int pmax, hipStream_t s) {
+  if (n <= 0) return;
+  int ntri = (pmax + 1) * (pmax + 2) / 2;
+  size_t shm = (size_t)P2M_NPT * ((pmax + 1) + ntri + 2 * (pmax + 1) + RC * 6) * sizeof(double);
+  hipFuncSetAttribute((const void*)k_p2m, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL(k_p2m, dim3(n, (n_rhs + RC - 1) / RC), dim3(NT), shm, s, d, leaves, xyz, J, n_src,
+                     n_rhs, ME);
+}
+
+// ------------------------------------------------------------------ M2M
+// ME_parent[nm] = sum_children sum_{nu mu} Mat_child[nu mu][nm] ME_child[nu mu]
+// (regular-to-regular shift, paper Sec. 2; identical for reaction components, Sec. 3.3)
+__global__ __launch_bounds__(NT) void k_m2m(DevPlan d, const int* parents, int n_rhs, cd* ME) {
+  extern __shared__ cd xs[];
+  int pb = parents[blockIdx.x];
+  SrcBox sp = d.sbox[pb];
+  int P = d.inst[sp.inst].P;
+  int r0 = blockIdx.y * RC, nr = min(RC, n_rhs - r0);
+  int tid = threadIdx.x;
+  cd acc[2][RC][3];
+  for (int h = 0; h < 2; h++)
+    for (int r = 0; r < RC; r++)
+      for (int c = 0; c < 3; c++) acc[h][r][c] = cd{0, 0};
+  for (int ci = 0; ci < sp.nchild; ci++) {
+    int cb = sp.child0 + ci;
+    long long base = d.sbox[cb].me_off * n_rhs + (long long)r0 * 3 * P;
+    const cd* M = d.mats + d.sbox_m2m[cb];
+    __syncthreads();
+    for (int e = tid; e < RC * 3 * P; e += NT) xs[e] = (e < nr * 3 * P) ? ME[base + e] : cd{0, 0};
+    __syncthreads();
+    for (int h = 0; h < 2; h++) {
+      int nm = tid + NT * h;
+      if (nm >= P) continue;
+      for (int k = 0; k < P; k++) {
+        cd a = M[(long long)k * P + nm];
+        for (int rr = 0; rr < RC; rr++)
+          for (int c = 0; c < 3; c++) acc[h][rr][c] = acc[h][rr][c] + a * xs[(rr * 3 + c) * P + k];
+      }
+    }
+  }
+  for (int h = 0; h < 2; h++) {
+    int nm = tid + NT * h;
+    if (nm >= P) continue;
+    for (int rr = 0; rr < nr; rr++)
+      for (int c = 0; c < 3; c++) ME[sp.me_off * n_rhs + ((long long)(r0 + rr) * 3 + c) * P + nm] = acc[h][rr][c];
+  }
+}
+void launch_m2m(const DevPlan& d, const int* parents, int n, int n_rhs, cd* ME, int pmax, hipStream_t s) {
+  if (n <= 0) return;
+  int P = (pmax + 1) * (pmax + 1);
+  hipFuncSetAttribute((const void*)k_m2m, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(RC * 3 * P * sizeof(cd)));
+  hipLaunchKernelGGL(k_m2m, dim3(n, (n_rhs + RC - 1) / RC), dim3(NT), (size_t)RC * 3 * P * sizeof(cd), s, d,
+                     parents, n_rhs, ME);
+}
+
+// ------------------------------------------------------------------ L2L
+// LE_child[nm] += sum_{nu mu} Mat[nu mu][nm] LE_parent[nu mu]
+__global__ __launch_bounds__(NT) void k_l2l(DevPlan d, const int* children, int n_rhs, cd* LE) {
+  extern __shared__ cd xs[];
+  int cb = children[blockIdx.x];
+  TgtBox tc = d.tbox[cb];
+  TgtBox tp = d.tbox[tc.parent];
+  int P = d.inst[tc.inst].P;
+  int r0 = blockIdx.y * RC, nr = min(RC, n_rhs - r0);
+  int tid = threadIdx.x;
+  const cd* M = d.mats + d.tbox_l2l[cb];
+  long long pbase = tp.le_off * n_rhs + (long long)r0 * 3 * P;
+  for (int e = tid; e < RC * 3 * P; e += NT) xs[e] = (e < nr * 3 * P) ? LE[pbase + e] : cd{0, 0};
+  __syncthreads();
+  for (int h = 0; h < 2; h++) {
+    int nm = tid + NT * h;
+    if (nm >= P) continue;
+    cd acc[RC][3];
+    for (int r = 0; r < RC; r++)
+      for (int c = 0; c < 3; c++) acc[r][c] = cd{0, 0};
+    for (int k = 0; k < P; k++) {
+      cd a = M[(long long)k * P + nm];
+      for (int rr = 0; rr < RC; rr++)
+        for (int c = 0; c < 3; c++) acc[rr][c] = acc[rr][c] + a * xs[(rr * 3 + c) * P + k];
+    }
+    for (int rr = 0; rr < nr; rr++)
+      for (int c = 0; c < 3; c++) {
+        long long idx = tc.le_off * n_rhs + ((long long)(r0 + rr) * 3 + c) * P + nm;
+        LE[idx] = LE[idx] + acc[rr][c];
+      }
+  }
+}
+void launch_l2l(const DevPlan& d, const int* children, int n, int n_rhs, cd* LE, int pmax, hipStream_t s) {
+  if (n <= 0) return;
+  int P = (pmax + 1) * (pmax + 1);
+  hipFuncSetAttribute((const void*)k_l2l, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(RC * 3 * P * sizeof(cd)));
+  hipLaunchKernelGGL(k_l2l, dim3(n, (n_rhs + RC - 1) / RC), dim3(NT), (size_t)RC * 3 * P * sizeof(cd), s, d,
+                     children, n_rhs, LE);
+}
+
+// ------------------------------------------------------------------ M2L
+// Tiled complex GEMM per class: for every target box t and offset o of the
+// class,  LE_t[out] += e^{-i m phi_o} A_o[out] X_{t,o},  where X_{t,o} stacks
+// the source box's channel vectors multiplied by e^{i (kappa + mu) phi_o}
+// (reaction: the three-block spin-basis form of the M2L tensor, Sec. 3.3;
+// free space: one block, phi = 0).
+#define TM 64
+#define TN 64
+#define KC 16
+__global__ __launch_bounds__(NT) void k_m2l(DevPlan d, int n_rhs, const cd* ME, cd* LE) {
+  __shared__ cd As[TM][KC + 1];
+  __shared__ cd Bs[KC][TN + 1];
+  __shared__ long long sbase[TN];
+  __shared__ cd eph[2 * LM_PMAX + 8];
+  __shared__ short mu_of[(LM_PMAX + 1) * (LM_PMAX + 1)];
+  __shared__ int anyv;
+  M2LTile tl = d.tiles[blockIdx.x];
+  M2LClass C = d.cls[tl.cls];
+  InstParams ip = d.inst[C.inst];
+  int P = C.P, p = ip.p, nblk = C.nblk, K = nblk * P;
+  int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
+  int ot = tl.out_type;
+  // per-block input recipe (source channel, kappa)
+  int rch[3], rkap[3];
+  if (nblk == 1) {
+    rch[0] = ot;
+    rkap[0] = 0;
+  } else if (ot == 0) {
+    rch[0] = 0; rkap[0] = 0; rch[1] = 1; rkap[1] = 2; rch[2] = 2; rkap[2] = 1;
+  } else if (ot == 1) {
+    rch[0] = 1; rkap[0] = 0; rch[1] = 0; rkap[1] = -2; rch[2] = 2; rkap[2] = -1;
+  } else {
+    rch[0] = 1; rkap[0] = 1; rch[1] = 0; rkap[1] = -1; rch[2] = 2; rkap[2] = 0;
+  }
+  for (int e = tid; e < P; e += NT) {
+    int n = n_of(e);
+    mu_of[e] = (short)(e - n * n - n);
+  }
+  bool phased = (nblk == 3);
+  cd acc[4][4];
+  for (int i = 0; i < 4; i++)
+    for (int j = 0; j < 4; j++) acc[i][j] = cd{0, 0};
+  long long srcof0 = d.cls_srcof0[tl.cls];
+  for (int o = 0; o < C.n_off; o++) {
+    M2LOffset off = d.offs[C.off0 + o];
+    __syncthreads();
+    if (tid == 0) anyv = 0;
+    __syncthreads();
+    if (tid < TN) {
+      long long v = -1;
+      if (tid < tl.ncol) {
+        int j = tl.col0 + tid;
+        int ts = j / n_rhs, r = j - ts * n_rhs;
+        int sbx = d.cls_srcof[srcof0 + (long long)ts * C.n_off + o];
+        if (sbx >= 0) {
+          v = d.sbox[sbx].me_off * n_rhs + (long long)r * 3 * P;
+          anyv = 1;
+        }
+      }
+      sbase[tid] = v;
+    }
+    if (tid < 2 * p + 5) {
+      double a = (tid - (p + 2)) * off.phi;
+      eph[tid] = cd{cos(a), sin(a)};
+    }
+    __syncthreads();
+    if (!anyv) continue;
+    cd tmp[4][4];
+    for (int i = 0; i < 4; i++)
+      for (int j = 0; j < 4; j++) tmp[i][j] = cd{0, 0};
+    const cd* A = d.mats + off.mat[ot];
+    for (int k0 = 0; k0 < K; k0 += KC) {
+      for (int e = tid; e < TM * KC; e += NT) {
+        int rr = e / KC, kk = e - rr * KC;
+        int row = tl.row0 + rr, k = k0 + kk;
+        As[rr][kk] = (row < P && k < K) ? A[(long long)row * K + k] : cd{0, 0};
+      }
+      for (int e = tid; e < KC * TN; e += NT) {
+        int cc = e / KC, kk = e - cc * KC;
+        int k = k0 + kk;
+        cd v = cd{0, 0};
+        long long sbb = sbase[cc];
+        if (sbb >= 0 && k < K) {
+          int bl = k / P, num = k - bl * P;
+          v = ME[sbb + (long long)rch[bl] * P + num];
+          if (phased) v = v * eph[rkap[bl] + mu_of[num] + p + 2];
+        }
+        Bs[kk][cc] = v;
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int kk = 0; kk < KC; kk++) {
+        cd a[4], bb[4];
+        for (int i = 0; i < 4; i++) a[i] = As[tr * 4 + i][kk];
+        for (int j = 0; j < 4; j++) bb[j] = Bs[kk][tc * 4 + j];
+        for (int i = 0; i < 4; i++)
+          for (int j = 0; j < 4; j++) tmp[i][j] = tmp[i][j] + a[i] * bb[j];
+      }
+      __syncthreads();
+    }
+    for (int i = 0; i < 4; i++) {
+      int row = tl.row0 + tr * 4 + i;
+      cd ph = cd{1, 0};
+      if (phased && row < P) ph = cconj(eph[mu_of[row] + p + 2]);
+      for (int j = 0; j < 4; j++) acc[i][j] = acc[i][j] + ph * tmp[i][j];
+    }
+  }
+  for (int j = 0; j < 4; j++) {
+    int col = tc * 4 + j;
+    if (col >= tl.ncol) continue;
+    int jj = tl.col0 + col;
+    int ts = jj / n_rhs, r = jj - ts * n_rhs;
+    TgtBox tb = d.tbox[d.cls_tgt[C.tgt0 + ts]];
+    for (int i = 0; i < 4; i++) {
+      int row = tl.row0 + tr * 4 + i;
+      if (row >= P) continue;
+      long long idx = tb.le_off * n_rhs + ((long long)r * 3 + ot) * P + row;
+      LE[idx] = LE[idx] + acc[i][j];
+    }
+  }
+}
+void launch_m2l(const DevPlan& d, int n_tiles, int n_rhs, const cd* ME, cd* LE, int pmax, hipStream_t s) {
+  if (n_tiles <= 0) return;
+  hipLaunchKernelGGL(k_m2l, dim3(n_tiles), dim3(NT), 0, s, d, n_rhs, ME, LE);
+}
+
+// ------------------------------------------------------------------ L2P
+// Reaction: Phi(r) = sum l_nm j_n(k|d|) Y^m_n(d), d = effective(r) - centre
+// (Sec. 3.3, the LE of a reaction component).  Free space: the LE of the
+// vector potential U is turned into the LE of U + grad div U / k^2 with the
+// exact ladder relations of the regular wave functions (paper Sec. 2: the
+// dyadic operator applied to the local expansion), then evaluated.
+__device__ inline double lad_a(int n, int m) {  // z ladder
+  if (n < 0 || (m < 0 ? -m : m) > n) return 0.0;
+  return sqrt((double)(n + 1 - m) * (n + 1 + m) / ((2.0 * n + 1) * (2.0 * n + 3)));
+}
+__device__ inline double lad_b1(int n, int m) { return sqrt((double)(n + m + 1) * (n + m + 2) / ((2.0 * n + 1) * (2.0 * n + 3))); }
+__device__ inline double lad_b2(int n, int m) {
+  double v = (double)(n - m) * (n - m - 1);
+  return (n <= 0 || v <= 0) ? 0.0 : sqrt(v / ((2.0 * n - 1) * (2.0 * n + 1)));
+}
+__device__ inline double lad_c1(int n, int m) { return sqrt((double)(n - m + 1) * (n - m + 2) / ((2.0 * n + 1) * (2.0 * n + 3))); }
+__device__ inline double lad_c2(int n, int m) {
+  double v = (double)(n + m) * (n + m - 1);
+  return (n <= 0 || v <= 0) ? 0.0 : sqrt(v / ((2.0 * n - 1) * (2.0 * n + 1)));
+}
+// coefficient of order `oi` (vector c, index nm) at (n, m); 0 outside
+__device__ inline cd cget(const cd* c, int oi, int n, int m) {
+  if (n < 0 || n > oi || m < -n || m > n) return cd{0, 0};
+  return c[nm_idx(n, m)];
+}
+// out (order oi+1) = D c, dir 0: d/dx + i d/dy, 1: d/dx - i d/dy, 2: d/dz (times 1/k)
+__device__ inline cd dapply(const cd* c, int oi, int dir, int n, int m) {
+  if (dir == 2) return lad_a(n, m) * cget(c, oi, n + 1, m) - lad_a(n - 1, m) * cget(c, oi, n - 1, m);
+  if (dir == 0) {
+    cd v = cd{0, 0};
+    if (n - 1 >= 0 && m - 1 >= -(n - 1) && m - 1 <= n - 1) v = v + lad_b1(n - 1, m - 1) * cget(c, oi, n - 1, m - 1);
+    v = v + lad_b2(n + 1, m - 1) * cget(c, oi, n + 1, m - 1);
+    return v;
+  }
+  cd v = cd{0, 0};
+  if (n - 1 >= 0 && m + 1 >= -(n - 1) && m + 1 <= n - 1) v = v + lad_c1(n - 1, m + 1) * cget(c, oi, n - 1, m + 1);
+  v = v + lad_c2(n + 1, m + 1) * cget(c, oi, n + 1, m + 1);
+  return -1.0 * v;
+}
+
+__global__ __launch_bounds__(NT) void k_l2p(DevPlan d, const int* leaves, int kind, const double* xyz,
+                                            long long n_tgt, int n_rhs, const cd* LE, cd* A) {
+  extern __shared__ cd Ls[];
+  int b = leaves[blockIdx.x];
+  TgtBox tb = d.tbox[b];
+  InstParams ip = d.inst[tb.inst];
+  int p = ip.p, P = ip.P;
+  int pe = (kind == 0) ? p + 2 : p, Pe = (pe + 1) * (pe + 1);
+  int r0 = blockIdx.y * RC, nr = min(RC, n_rhs - r0);
+  int tid = threadIdx.x;
+  double k = ip.kt;
+  cd* Lc = Ls;                       // [RC][3][Pe]
+  cd* Dv = Ls + RC * 3 * Pe;         // [RC][(p+2)^2] divergence
+  for (int e = tid; e < RC * 3 * Pe; e += NT) {
+    int rr = e / (3 * Pe), rem = e - rr * 3 * Pe, c = rem / Pe, nm = rem - c * Pe;
+    cd v = cd{0, 0};
+    if (rr < nr && nm < P) v = LE[tb.le_off * n_rhs + ((long long)(r0 + rr) * 3 + c) * P + nm];
+    Lc[e] = v;
+  }
+  __syncthreads();
+  if (kind == 0) {
+    int Pd = (p + 2) * (p + 2);
+    for (int e = tid; e < RC * Pd; e += NT) {
+      int rr = e / Pd, nm = e - rr * Pd;
+      int n = n_of(nm), m = nm - n * n - n;
+      const cd* Lp = Lc + (rr * 3 + 0) * Pe;
+      const cd* Lm = Lc + (rr * 3 + 1) * Pe;
+      const cd* Lz = Lc + (rr * 3 + 2) * Pe;
+      cd v = 0.5 * (dapply(Lm, p, 0, n, m) + dapply(Lp, p, 1, n, m)) + dapply(Lz, p, 2, n, m);
+      Dv[e] = k * v;
+    }
+    __syncthreads();
+    // A = U + grad div U / k^2 (order p+2); the gradient only reads Dv
+    for (int e = tid; e < RC * 3 * Pe; e += NT) {
+      int rr = e / (3 * Pe), rem = e - rr * 3 * Pe, c = rem / Pe, nm = rem - c * Pe;
+      int n = n_of(nm), m = nm - n * n - n;
+      Lc[e] = Lc[e] + (1.0 / k) * dapply(Dv + rr * Pd, p + 1, c, n, m);
+    }
+    __syncthreads();
+  }
+  for (int t0 = tb.pt0; t0 < tb.pt1; t0 += NT) {
+    int ti = t0 + tid;
+    if (ti >= tb.pt1) continue;
+    int id = d.tgt_perm[ti];
+    double dx = xyz[3 * id] - tb.c[0], dy = xyz[3 * id + 1] - tb.c[1];
+    double dz = ip.at * xyz[3 * id + 2] + ip.bt - tb.c[2];
+    double rxy = sqrt(dx * dx + dy * dy), r = sqrt(dx * dx + dy * dy + dz * dz);
+    double ct = r > 0 ? dz / r : 1.0, st = r > 0 ? rxy / r : 0.0;
+    cd e1 = rxy > 0 ? cd{dx / rxy, dy / rxy} : cd{1.0, 0.0};
+    double jn[LM_PMAX + 4];
+    sph_jn(pe, k * r, jn);
+    cd acc[RC][3];
+    for (int rr = 0; rr < RC; rr++)
+      for (int c = 0; c < 3; c++) acc[rr][c] = cd{0, 0};
+    // m-outer recurrence for the orthonormal Legendre functions
+    double pmm = LM_INV_SQRT_4PI;
+    cd em = cd{1.0, 0.0};
+    for (int m = 0; m <= pe; m++) {
+      if (m > 0) {
+        pmm = -sqrt((2.0 * m + 1.0) / (2.0 * m)) * st * pmm;
+        em = em * e1;
+      }
+      double p2 = 0.0, p1 = pmm;
+      for (int n = m; n <= pe; n++) {
+        double pn;
+        if (n == m)
+          pn = pmm;
+        else if (n == m + 1)
+          pn = sqrt(2.0 * m + 3.0) * ct * pmm;
+        else {
+          double a = sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));
+          double bb = sqrt(((n - 1.0) * (n - 1.0) - (double)m * m) / (4.0 * (n - 1.0) * (n - 1.0) - 1.0));
+          pn = a * (ct * p1 - bb * p2);
+        }
+        if (n > m) {
+          p2 = p1;
+          p1 = pn;
+        }
+        double rad = jn[n] * pn;
+        cd bp = rad * em;                       // j_n Y^m_n
+        int ip_ = nm_idx(n, m), im_ = nm_idx(n, -m);
+        for (int rr = 0; rr < RC; rr++)
+          for (int c = 0; c < 3; c++) {
+            const cd* L = Lc + (rr * 3 + c) * Pe;
+            acc[rr][c] = acc[rr][c] + L[ip_] * bp;
+            if (m > 0) {
+              cd bm = ((m & 1) ? -rad : rad) * cconj(em);  // j_n Y^{-m}_n
+              acc[rr][c] = acc[rr][c] + L[im_] * bm;
+            }
+          }
+      }
+    }
+    for (int rr = 0; rr < nr; rr++) {
+      cd vp = acc[rr][0], vm = acc[rr][1], vz = acc[rr][2];
+      cd ax = 0.5 * (vp + vm);
+      cd dd = 0.5 * (vp - vm);
+      cd ay = cd{dd.y, -dd.x};  // (vp - vm) / (2i)
+      cd* Ap = A + ((long long)(r0 + rr) * n_tgt + id) * 3;
+      Ap[0] = Ap[0] + ax;
+      Ap[1] = Ap[1] + ay;
+      Ap[2] = Ap[2] + vz;
+    }
+  }
+}
+void launch_l2p(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_tgt,
+                int n_rhs, const cd* LE, cd* A, int pmax, hipStream_t s) {
+  if (n <= 0) return;
+  int pe = pmax + 2;
+  int Pe = (pe + 1) * (pe + 1), Pd = (pmax + 2) * (pmax + 2);
+  size_t shm = (size_t)(RC * 3 * Pe + RC * Pd) * sizeof(cd);
+  hipFuncSetAttribute((const void*)k_l2p, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL(k_l2p, dim3(n, (n_rhs + RC - 1) / RC), dim3(NT), shm, s, d, leaves, kind, xyz, n_tgt, n_rhs,
+                     LE, A);
+}
+
+// ------------------------------------------------------------------ P2P
+// free-space near field: A_i += sum_j G^f(x_i - x_j) J_j over same-layer
+// sources in adjacent leaves, coincident points skipped (paper Sec. 2 and the
+// layered sums of Sec. 3.3)
+__global__ __launch_bounds__(NT) void k_p2p(DevPlan d, const int* tboxes, const double* sxyz, const cd* J,
+                                            long long n_src, const double* txyz, long long n_tgt, int n_rhs,
+                                            double k, cd* A) {
+  __shared__ double sp[NT][3];
+  __shared__ cd sj[NT][RC][3];
+  int b = tboxes[blockIdx.x];
+  TgtBox tb = d.tbox[b];
+  int r0 = blockIdx.y * RC, nr = min(RC, n_rhs - r0);
+  int tid = threadIdx.x;
+  const double inv4pi = 0.079577471545947667884;
+  for (int t0 = tb.pt0; t0 < tb.pt1; t0 += NT) {
+    int ti = t0 + tid;
+    bool act = ti < tb.pt1;
+    int id = act ? d.tgt_perm[ti] : 0;
+    double x0 = act ? txyz[3 * id] : 0, y0 = act ? txyz[3 * id + 1] : 0, z0 = act ? txyz[3 * id + 2] : 0;
+    cd acc[RC][3];
+    for (int rr = 0; rr < RC; rr++)
+      for (int c = 0; c < 3; c++) acc[rr][c] = cd{0, 0};
+    for (int li = tb.p2p0; li < tb.p2p1; li++) {
+      SrcBox sb = d.sbox[d.p2p_list[li]];
+      for (int s0 = sb.pt0; s0 < sb.pt1; s0 += NT) {
+        int ns = min(NT, sb.pt1 - s0);
+        __syncthreads();
+        if (tid < ns) {
+          int sid = d.src_perm[s0 + tid];
+          sp[tid][0] = sxyz[3 * sid];
+          sp[tid][1] = sxyz[3 * sid + 1];
+          sp[tid][2] = sxyz[3 * sid + 2];
+          for (int rr = 0; rr < RC; rr++)
+            for (int c = 0; c < 3; c++)
+              sj[tid][rr][c] = rr < nr ? J[((long long)(r0 + rr) * n_src + sid) * 3 + c] : cd{0, 0};
+        }
+        __syncthreads();
+        if (act) {
+          for (int j = 0; j < ns; j++) {
+            double rx = x0 - sp[j][0], ry = y0 - sp[j][1], rz = z0 - sp[j][2];
+            double r2 = rx * rx + ry * ry + rz * rz;
+            if (r2 == 0.0) continue;
+            double r = sqrt(r2), ir = 1.0 / r;
+            double kr = k * r, ikr = 1.0 / kr, ikr2 = ikr * ikr;
+            double sn, cs;
+            sincos(kr, &sn, &cs);
+            cd g = cd{cs * inv4pi * ir, sn * inv4pi * ir};
+            cd a = g * cd{1.0 - ikr2, ikr};
+            cd bq = g * cd{-1.0 + 3.0 * ikr2, -3.0 * ikr};
+            double ux = rx * ir, uy = ry * ir, uz = rz * ir;
+            for (int rr = 0; rr < RC; rr++) {
+              cd jx = sj[j][rr][0], jy = sj[j][rr][1], jz = sj[j][rr][2];
+              cd rj = ux * jx + uy * jy + uz * jz;
+              cd brj = bq * rj;
+              acc[rr][0] = acc[rr][0] + a * jx + ux * brj;
+              acc[rr][1] = acc[rr][1] + a * jy + uy * brj;
+              acc[rr][2] = acc[rr][2] + a * jz + uz * brj;
+            }
+          }
+        }
+      }
+    }
+    if (act)
+      for (int rr = 0; rr < nr; rr++) {
+        cd* Ap = A + ((long long)(r0 + rr) * n_tgt + id) * 3;
+        for (int c = 0; c < 3; c++) Ap[c] = Ap[c] + acc[rr][c];
+      }
+  }
+}
+void launch_p2p(const DevPlan& d, const int* tboxes, int n, const double* sxyz, const cd* J, long long n_src,
+                const double* txyz, long long n_tgt, int n_rhs, double k, cd* A, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_p2p, dim3(n, (n_rhs + RC - 1) / RC), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src, txyz,
+                     n_tgt, n_rhs, k, A);
+}
+
+// ------------------------------------------------------------------ translation tables
+// (R|R) and (S|R) by the addition theorem of wave functions written with
+// Gaunt coefficients G = int Y^mu_nu conj(Y^m_n) conj(Y^{mu-m}_q):
+//   f_nu^mu(x + b) = sum_nm [4 pi sum_q i^{n+q-nu} f_q(k|b|) Y^{mu-m}_q(b) G] j_n Y^m_n(x)
+// with f = j (regular) or h (outgoing, |x| < |b|).
+__device__ inline double gaunt_at(const double* G, int gp, int nu, int mu, int n, int m, int q) {
+  long long Pg = (long long)(gp + 1) * (gp + 1);
+  return G[(((long long)nm_idx(nu, mu) * Pg) + nm_idx(n, m)) * (2 * gp + 1) + q];
+}
+__global__ __launch_bounds__(NT) void k_trans(DevPlan d, int gp) {
+  __shared__ cd fq[2 * LM_PMAX + 2];
+  __shared__ cd Yq[(2 * LM_PMAX + 1) * (2 * LM_PMAX + 1)];
+  __shared__ double leg[(2 * LM_PMAX + 1) * (2 * LM_PMAX + 2) / 2];
+  __shared__ double jq[2 * LM_PMAX + 2], yq[2 * LM_PMAX + 2];
+  TransJob job = d.trans[blockIdx.x];
+  int p = job.p, P = (p + 1) * (p + 1), Q = 2 * p;
+  int tid = threadIdx.x;
+  double bx = job.b[0], by = job.b[1], bz = job.b[2];
+  double bn = sqrt(bx * bx + by * by + bz * bz), bxy = sqrt(bx * bx + by * by);
+  double ct = bn > 0 ? bz / bn : 1.0, st = bn > 0 ? bxy / bn : 0.0;
+  double phi = bxy > 0 ? atan2(by, bx) : 0.0;
+  if (tid == 0) {
+    legendre_r(Q, ct, st, leg);
+    sph_jn(Q, job.k * bn, jq);
+    if (job.kind == 0) sph_yn(Q, job.k * bn, yq);
+  }
+  __syncthreads();
+  for (int e = tid; e <= Q; e += NT) fq[e] = job.kind == 0 ? cd{jq[e], yq[e]} : cd{jq[e], 0.0};
+  for (int e = tid; e < (Q + 1) * (Q + 1); e += NT) {
+    int q = n_of(e), s = e - q * q - q, as = s < 0 ? -s : s;
+    double v = leg[tri_idx(q, as)];
+    if (s < 0 && (as & 1)) v = -v;
+    Yq[e] = cd{v * cos(s * phi), v * sin(s * phi)};
+  }
+  __syncthreads();
+  cd* M = d.mats + job.mat;
+  const double fourpi = 12.566370614359172954;
+  for (long long e = tid; e < (long long)P * P; e += NT) {
+    int a = (int)(e / P), bcol = (int)(e - (long long)a * P);
+    cd v = cd{0, 0};
+    if (job.kind == 0) {
+      // row-major [out nm = a][in nu mu = bcol]
+      int n = n_of(a), m = a - n * n - n, nu = n_of(bcol), mu = bcol - nu * nu - nu;
+      int s = mu - m;
+      for (int q = abs(n - nu); q <= n + nu; q += 2) {
+        if (abs(s) > q) continue;
+        v = v + (fourpi * gaunt_at(d.gaunt, gp, nu, mu, n, m, q)) * (ipow(n + q - nu) * fq[q] * Yq[nm_idx(q, s)]);
+      }
+      v = cd{0.0, job.k} * v;  // i k prefactor of the free-space multipole expansion
+    } else if (job.kind == 1) {
+      // [in nu mu = a][out nm = bcol]: conj of (R|R)_{nm -> nu mu}(b)
+      int nu = n_of(a), mu = a - nu * nu - nu, n = n_of(bcol), m = bcol - n * n - n;
+      int s = m - mu;
+      for (int q = abs(n - nu); q <= n + nu; q += 2) {
+        if (abs(s) > q) continue;
+        v = v + (fourpi * gaunt_at(d.gaunt, gp, n, m, nu, mu, q)) * (ipow(nu + q - n) * fq[q] * Yq[nm_idx(q, s)]);
+      }
+      v = cconj(v);
+    } else {
+      // [in nu mu = a][out nm = bcol]: (R|R)_{nu mu -> nm}(b)
+      int nu = n_of(a), mu = a - nu * nu - nu, n = n_of(bcol), m = bcol - n * n - n;
+      int s = mu - m;
+      for (int q = abs(n - nu); q <= n + nu; q += 2) {
+        if (abs(s) > q) continue;
+        v = v + (fourpi * gaunt_at(d.gaunt, gp, nu, mu, n, m, q)) * (ipow(n + q - nu) * fq[q] * Yq[nm_idx(q, s)]);
+      }
+    }
+    M[e] = v;
+  }
+}
+void launch_trans(const DevPlan& d, int n_jobs, int gp, hipStream_t s) {
+  if (n_jobs <= 0) return;
+  hipLaunchKernelGGL(k_trans, dim3(n_jobs), dim3(NT), 0, s, d, gp);
+}
+
+// ------------------------------------------------------------------ reaction densities
+// Generalized reflection coefficients (the classical O(L) recursion for the
+// layered 1-D interface problems of Sec. 3.1): amplitude, in the target
+// layer, of the up-going (up_t) or down-going wave excited by a unit source
+// wave leaving the source layer upward (up_s) or downward, with local
+// reference planes (every exponential factor has modulus <= 1).
+__device__ cd react_coef(const MediumDev& md, cd kr, int lt, int ls, int up_t, int up_s, int pol) {
+  int n = md.n, L = n - 1;
+  cd kz[LM_MAXL], E[LM_MAXL], Rd[LM_MAXL], Ru[LM_MAXL];
+  double beta[LM_MAXL];
+  for (int m = 0; m < n; m++) {
+    kz[m] = kz_of(md.k[m], kr);
+    beta[m] = pol ? md.k[m] * md.k[m] : 1.0;
+    E[m] = (m >= 1 && m <= L - 1) ? cexpd(cd{0, 1} * kz[m] * (md.d[m - 1] - md.d[m])) : cd{0, 0};
+    Rd[m] = Ru[m] = cd{0, 0};
+  }
+  auto fres = [&](int a, int b) {
+    cd x = (1.0 / beta[a]) * kz[a], y = (1.0 / beta[b]) * kz[b];
+    return (x - y) / (x + y);
+  };
+  for (int m = L - 1; m >= 0; m--) {
+    cd r = fres(m, m + 1);
+    if (m + 1 <= L - 1) {
+      cd e2 = E[m + 1] * E[m + 1];
+      Rd[m] = (r + Rd[m + 1] * e2) / (cd{1, 0} + r * Rd[m + 1] * e2);
+    } else
+      Rd[m] = r;
+  }
+  for (int m = 1; m <= L; m++) {
+    cd r = fres(m, m - 1);
+    if (m - 1 >= 1) {
+      cd e2 = E[m - 1] * E[m - 1];
+      Ru[m] = (r + Ru[m - 1] * e2) / (cd{1, 0} + r * Ru[m - 1] * e2);
+    } else
+      Ru[m] = r;
+  }
+  int s = ls;
+  cd c = cd{0, 1} / (2.0 * kz[s]);
+  cd Es = E[s];
+  cd den = cd{1, 0} - Ru[s] * Rd[s] * Es * Es;
+  cd Aa, Bb, ctop = cd{0, 0}, cbot = cd{0, 0};
+  if (up_s) {
+    Bb = Ru[s] * c / den;
+    Aa = Rd[s] * Es * Bb;
+    ctop = c;
+  } else {
+    Aa = Rd[s] * c / den;
+    Bb = Ru[s] * Es * Aa;
+    cbot = c;
+  }
+  cd a, b;
+  if (lt == s) {
+    a = Aa;
+    b = Bb;
+  } else if (lt > s) {
+    cd Dn = (cbot + Bb * Es) * (cd{1, 0} + Rd[s]) /
+            (cd{1, 0} + ((s + 1 <= L - 1) ? Rd[s + 1] * E[s + 1] * E[s + 1] : cd{0, 0}));
+    for (int m = s + 1; m < lt; m++)
+      Dn = Dn * E[m] * (cd{1, 0} + Rd[m]) / (cd{1, 0} + ((m + 1 <= L - 1) ? Rd[m + 1] * E[m + 1] * E[m + 1] : cd{0, 0}));
+    b = Dn;
+    a = (lt <= L - 1) ? Rd[lt] * Dn * E[lt] : cd{0, 0};
+  } else {
+    cd Up = (ctop + Aa * Es) * (cd{1, 0} + Ru[s]) /
+            (cd{1, 0} + ((s - 1 >= 1) ? Ru[s - 1] * E[s - 1] * E[s - 1] : cd{0, 0}));
+    for (int m = s - 1; m > lt; m--)
+      Up = Up * E[m] * (cd{1, 0} + Ru[m]) / (cd{1, 0} + ((m - 1 >= 1) ? Ru[m - 1] * E[m - 1] * E[m - 1] : cd{0, 0}));
+    a = Up;
+    b = (lt >= 1) ? Ru[lt] * Up * E[lt] : cd{0, 0};
+  }
+  return up_t ? a : b;
+}
+
+// Spectral densities of a reaction component at one quadrature node: the
+// coefficients of the eight-term angular decomposition of the spectral
+// dyadic (paper Sec. 3.1; sigma_3 with the sign that follows from Theta),
+// written as F = -(2i/k^2) S with
+//   S1 = k^2 c_TE - e h kz kz' c_TM,  S3 = k^2 c_TE + e h kz kz' c_TM,
+//   S2 = -e kz kr c_TM,  S4 = h kz' kr c_TM,  S5 = kr^2 c_TM,
+// e = +1 (-1) for a wave arriving up (down), h = -1 (+1) for leaving up (down).
+__global__ void k_nodes(DevPlan d, MediumDev md, int n_nodes, const int* node_inst, const cd* krs, const cd* ws) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_nodes) return;
+  InstParams ip = d.inst[node_inst[i]];
+  cd kr = krs[i];
+  QNode q;
+  q.kr = kr;
+  q.w = ws[i];
+  q.kzt = kz_of(ip.kt, kr);
+  q.kzs = kz_of(ip.ks, kr);
+  cd cte = react_coef(md, kr, ip.lt, ip.ls, ip.up_t, ip.up_s, 0);
+  cd ctm = react_coef(md, kr, ip.lt, ip.ls, ip.up_t, ip.up_s, 1);
+  double e = ip.up_t ? 1.0 : -1.0, h = ip.up_s ? -1.0 : 1.0;
+  double k2 = ip.kt * ip.kt;
+  cd kk = q.kzt * q.kzs;
+  cd S[5];
+  S[0] = k2 * cte - (e * h) * (kk * ctm);
+  S[1] = (-e) * (q.kzt * kr * ctm);
+  S[2] = k2 * cte + (e * h) * (kk * ctm);
+  S[3] = h * (q.kzs * kr * ctm);
+  S[4] = kr * kr * ctm;
+  cd pre = cd{0.0, -2.0 / k2};
+  for (int j = 0; j < 5; j++) q.F[j] = pre * S[j];
+  q.tau_t[0] = cd{1, 0};
+  q.tau_t[1] = cd{ip.kt, 0} / q.kzt;
+  q.tau_t[2] = (1.0 / ip.kt) * kr;
+  q.tau_t[3] = kr / q.kzt;
+  q.tau_s[0] = cd{1, 0};
+  q.tau_s[1] = cd{ip.ks, 0} / q.kzs;
+  q.tau_s[2] = (1.0 / ip.ks) * kr;
+  q.tau_s[3] = kr / q.kzs;
+  double kb = ip.kt <= ip.ks ? ip.kt : ip.ks;
+  q.x0 = cd{1, 0} - (2.0 / (kb * kb)) * (kr * kr);
+  d.nodes[i] = q;
+}
+void launch_nodes(const DevPlan& d, MediumDev med, int n_nodes, const int* node_inst, const cd* kr, const cd* w,
+                  hipStream_t s) {
+  if (n_nodes <= 0) return;
+  hipLaunchKernelGGL(k_nodes, dim3((n_nodes + 127) / 128), dim3(128), 0, s, d, med, n_nodes, node_inst, kr, w);
+}
+
+// per (case, node): g = w kr Z(centres) and J_q(kr rho), q <= 2p+2
+__global__ void k_tab_bessel(DevPlan d, MediumDev md, int case0, int ncase, int maxnode, int p, cd* scr) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  int NQ = 2 * p + 3;
+  if (i >= (long long)ncase * maxnode) return;
+  int ci = (int)(i / maxnode), nd = (int)(i - (long long)ci * maxnode);
+  TabCase tc = d.cases[case0 + ci];
+  cd* out = scr + i * (NQ + 1);
+  if (nd >= tc.nnode) return;
+  QNode q = d.nodes[tc.node0 + nd];
+  InstParams ip = d.inst[tc.inst];
+  double tz = ip.up_t ? tc.zt_orig - md.d[ip.lt] : md.d[ip.lt - 1] - tc.zt_orig;
+  double uz = ip.up_s ? md.d[ip.ls - 1] - tc.zs_orig : tc.zs_orig - md.d[ip.ls];
+  cd ex = cd{0, 1} * (tz * q.kzt + uz * q.kzs);
+  out[0] = q.w * q.kr * cexpd(ex);
+  bessel_jq(NQ - 1, tc.rho * q.kr, out + 1);
+}
+
+// Chebyshev-weighted Sommerfeld integrals of one case (Sec. 3.4):
+//   I[sig][tt][ts][l][q] = sum_nodes w kr Z F_sig tau_tt(b) tau_ts(b') T_l(cos 2 b0) J_q(kr rho)
+#define TAB_NC 8
+__global__ __launch_bounds__(NT) void k_tab_integrals(DevPlan d, int case0, int p, int maxnode, const cd* scr) {
+  extern __shared__ cd shm[];
+  int NQ = 2 * p + 3, NL = p + 2, NLQ = NL * NQ;
+  int E = 80 * NLQ;
+  cd* H = shm;                      // [TAB_NC][80]
+  cd* U = H + TAB_NC * 80;          // [TAB_NC][NLQ]
+  cd* Tl = U + TAB_NC * NLQ;        // [TAB_NC][NL]
+  int ci = blockIdx.x;
+  TabCase tc = d.cases[case0 + ci];
+  int tid = threadIdx.x;
+  int e0 = blockIdx.y * (NT * 4);
+  cd acc[4];
+  for (int j = 0; j < 4; j++) acc[j] = cd{0, 0};
+  const cd* sc = scr + (long long)ci * maxnode * (NQ + 1);
+  for (int n0 = 0; n0 < tc.nnode; n0 += TAB_NC) {
+    int nn = min(TAB_NC, tc.nnode - n0);
+    __syncthreads();
+    if (tid < nn) cheb_t(NL - 1, d.nodes[tc.node0 + n0 + tid].x0, Tl + tid * NL);
+    for (int e = tid; e < TAB_NC * 80; e += NT) {
+      int t = e / 80, a = e - t * 80;
+      cd v = cd{0, 0};
+      if (t < nn) {
+        const QNode& q = d.nodes[tc.node0 + n0 + t];
+        int sg = a / 16, tt = (a / 4) & 3, ts = a & 3;
+        v = sc[(long long)(n0 + t) * (NQ + 1)] * q.F[sg] * q.tau_t[tt] * q.tau_s[ts];
+      }
+      H[e] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < TAB_NC * NLQ; e += NT) {
+      int t = e / NLQ, b = e - t * NLQ, l = b / NQ, qq = b - l * NQ;
+      U[e] = (t < nn) ? Tl[t * NL + l] * sc[(long long)(n0 + t) * (NQ + 1) + 1 + qq] : cd{0, 0};
+    }
+    __syncthreads();
+    for (int j = 0; j < 4; j++) {
+      int e = e0 + j * NT + tid;
+      if (e >= E) break;
+      int a = e / NLQ, b = e - a * NLQ;
+      cd s = acc[j];
+      for (int t = 0; t < nn; t++) s = s + H[t * 80 + a] * U[t * NLQ + b];
+      acc[j] = s;
+    }
+  }
+  for (int j = 0; j < 4; j++) {
+    int e = e0 + j * NT + tid;
+    if (e < E) d.ibuf[tc.ibuf + e] = acc[j];
+  }
+}
+
+void launch_tab_integrals(const DevPlan& d, MediumDev med, int case0, int ncase, int p, cd* scr, long long maxnode,
+                          hipStream_t s) {
+  if (ncase <= 0) return;
+  long long nth = (long long)ncase * maxnode;
+  hipLaunchKernelGGL(k_tab_bessel, dim3((unsigned)((nth + 127) / 128)), dim3(128), 0, s, d, med, case0, ncase,
+                     (int)maxnode, p, scr);
+  int NQ = 2 * p + 3, NL = p + 2;
+  int E = 80 * NL * NQ;
+  size_t shm = (size_t)(TAB_NC * 80 + TAB_NC * NL * NQ + TAB_NC * NL) * sizeof(cd);
+  hipFuncSetAttribute((const void*)k_tab_integrals, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL(k_tab_integrals, dim3(ncase, (E + NT * 4 - 1) / (NT * 4)), dim3(NT), shm, s, d, case0, p,
+                     (int)maxnode, scr);
+}
+
+// Assembly of the reaction M2L matrices from the Chebyshev integrals
+// (Sec. 3.4): the product of the two associated Legendre functions is
+// expanded as s/2 tau tau sum_i sum_j B_i B_j sum_s C_js (T_{i+s} + T_{|i-s|})
+// in the variable of the smaller wavenumber, so every entry
+//   Ihat = s_{m mu}/2 sum_i sum_j B^i_{n|m|} B^j_{nu|mu|} A_ij,
+//   A_ij = sum_s C_js (I_{i+s} + I_{|i-s|})   (roles of i, j swapped if k > k')
+// and V = 4 pi i^{1+n+|q|} (-i)^nu s^{n+m+nu+mu} Ihat with q = kappa - m + mu.
+// The matrices for the three spin outputs are stored as P x 3P blocks.
+__global__ __launch_bounds__(NT) void k_tab_assemble(DevPlan d, int case0, int p, int KB, int BS) {
+  extern __shared__ cd Aij[];  // [(KB+1)^2][NQ]
+  int ci = blockIdx.x, sg = blockIdx.y;
+  TabCase tc = d.cases[case0 + ci];
+  InstParams ip = d.inst[tc.inst];
+  int P = ip.P, NQ = 2 * p + 3, NL = p + 2, NLQ = NL * NQ;
+  int W = KB + 2;  // stride of C
+  const double* C = d.Ccoef + d.Ccoef0[tc.inst];
+  bool tbase = ip.kt <= ip.ks;
+  int tid = threadIdx.x;
+  int K1 = KB + 1;
+  // kappa list and target slots for this density
+  int nk = 0, kap[2], slot_t[2][2], slot_b[2][2];
+  double coef[2][2];
+  int nslot[2] = {0, 0};
+  if (sg == 0) { nk = 1; kap[0] = 0; nslot[0] = 2; slot_t[0][0] = 0; slot_b[0][0] = 0; coef[0][0] = 0.5; slot_t[0][1] = 1; slot_b[0][1] = 0; coef[0][1] = 0.5; }
+  if (sg == 2) { nk = 2; kap[0] = 2; kap[1] = -2; nslot[0] = nslot[1] = 1; slot_t[0][0] = 0; slot_b[0][0] = 1; coef[0][0] = -0.5; slot_t[1][0] = 1; slot_b[1][0] = 1; coef[1][0] = -0.5; }
+  if (sg == 1) { nk = 2; kap[0] = 1; kap[1] = -1; nslot[0] = nslot[1] = 1; slot_t[0][0] = 0; slot_b[0][0] = 2; coef[0][0] = 1.0; slot_t[1][0] = 1; slot_b[1][0] = 2; coef[1][0] = 1.0; }
+  if (sg == 3) { nk = 2; kap[0] = 1; kap[1] = -1; nslot[0] = nslot[1] = 1; slot_t[0][0] = 2; slot_b[0][0] = 0; coef[0][0] = 0.5; slot_t[1][0] = 2; slot_b[1][0] = 1; coef[1][0] = 0.5; }
+  if (sg == 4) { nk = 1; kap[0] = 0; nslot[0] = 1; slot_t[0][0] = 2; slot_b[0][0] = 2; coef[0][0] = 1.0; }
+  const cd* Ib = d.ibuf + tc.ibuf;
+  cd* Mbase = d.mats + tc.mat;
+  const double fourpi = 12.566370614359172954;
+  for (int tt = 0; tt < 4; tt++)
+    for (int ts = 0; ts < 4; ts++) {
+      const cd* I = Ib + ((long long)(sg * 16 + tt * 4 + ts)) * NLQ;
+      __syncthreads();
+      for (int e = tid; e < K1 * K1 * NQ; e += NT) {
+        int ij = e / NQ, q = e - ij * NQ, i = ij / K1, j = ij - i * K1;
+        // ib: index on the base (smaller-k) side, io: index expanded by C
+        int ib = tbase ? i : j, io = tbase ? j : i;
+        cd v = cd{0, 0};
+        for (int s = 0; s <= io; s++) {
+          double c = C[io * W + s];
+          if (c == 0.0) continue;
+          int l1 = ib + s, l2 = ib > s ? ib - s : s - ib;
+          cd t1 = l1 < NL ? I[l1 * NQ + q] : cd{0, 0};
+          cd t2 = l2 < NL ? I[l2 * NQ + q] : cd{0, 0};
+          v = v + c * (t1 + t2);
+        }
+        Aij[e] = v;
+      }
+      __syncthreads();
+      for (long long e = tid; e < (long long)P * P; e += NT) {
+        int a = (int)(e / P), bb = (int)(e - (long long)a * P);
+        int n = n_of(a), m = a - n * n - n, nu = n_of(bb), mu = bb - nu * nu - nu;
+        int am = m < 0 ? -m : m, amu = mu < 0 ? -mu : mu;
+        // tau types (Appendix B)
+        int t1 = (n % 2 == 0) ? ((am % 2 == 0) ? 0 : 3) : ((am % 2 == 0) ? 1 : 2);
+        int t2 = (nu % 2 == 0) ? ((amu % 2 == 0) ? 0 : 3) : ((amu % 2 == 0) ? 1 : 2);
+        if (t1 != tt || t2 != ts) continue;
+        int Kn = (n % 2 == 0) ? n / 2 : ((am % 2 == 0) ? (n + 1) / 2 : (n - 1) / 2);
+        int Kv = (nu % 2 == 0) ? nu / 2 : ((amu % 2 == 0) ? (nu + 1) / 2 : (nu - 1) / 2);
+        double smu = ((m < 0 && (am & 1)) ? -1.0 : 1.0) * ((mu < 0 && (amu & 1)) ? -1.0 : 1.0);
+        const double* Bn = d.Bcoef + (long long)tri_idx(n, am) * BS;
+        const double* Bv = d.Bcoef + (long long)tri_idx(nu, amu) * BS;
+        double sgn_s = ((n + m + nu + mu) & 1) ? (double)ip.sgn : 1.0;
+        for (int kk = 0; kk < nk; kk++) {
+          int q = kap[kk] - m + mu, aq = q < 0 ? -q : q;
+          cd ih = cd{0, 0};
+          for (int i = 0; i <= Kn; i++) {
+            cd row = cd{0, 0};
+            for (int j = 0; j <= Kv; j++) row = row + Bv[j] * Aij[(i * K1 + j) * NQ + aq];
+            ih = ih + Bn[i] * row;
+          }
+          ih = (0.5 * smu) * ih;
+          cd V = (fourpi * sgn_s) * (ipow(1 + n + aq) * ipow(-nu) * ih);  // i^{1+n+|q|} (-i)^nu
+          for (int sl = 0; sl < nslot[kk]; sl++) {
+            int t = slot_t[kk][sl], blk = slot_b[kk][sl];
+            Mbase[(long long)t * 3 * P * P + (long long)a * 3 * P + (long long)blk * P + bb] = coef[kk][sl] * V;
+          }
+        }
+      }
+    }
+}
+void launch_tab_assemble(const DevPlan& d, int case0, int ncase, int p, int KB, int BS, hipStream_t s) {
+  if (ncase <= 0) return;
+  int NQ = 2 * p + 3;
+  size_t shm = (size_t)(KB + 1) * (KB + 1) * NQ * sizeof(cd);
+  hipFuncSetAttribute((const void*)k_tab_assemble, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL(k_tab_assemble, dim3(ncase, 5), dim3(NT), shm, s, d, case0, p, KB, BS);
+}

@@ -1,0 +1,110 @@
+// lmfmm_internal.h -- data structures shared by the host planner and the
+// HIP kernels of the layered-media dyadic FMM.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "special.h"
+
+#define LM_MAXL 16
+#define LM_PMAX 24
+
+// One FMM instance: the free-space part of one layer, or one reaction
+// component (target layer lt, source layer ls, arrival direction at the
+// target, departure direction at the source).
+struct InstParams {
+  int kind;          // 0 free space, 1 reaction component
+  int lt, ls;        // target layer, source layer
+  int up_t, up_s;    // reaction: 1 if the wave arrives at the target going up / leaves the source going up
+  int sgn;           // reaction sign s of the component
+  int p, P;          // expansion order, (p+1)^2
+  double kt, ks;     // target-side and source-side wavenumbers
+  double at, bt;     // target effective location  zhat = at*z + bt
+  double as, bs;     // source polarization image  zbrv = as*z + bs
+  double Dgap;       // distance between the two anchor planes (reaction)
+};
+
+// source-side box record (device)
+struct SrcBox {
+  double c[3];       // centre in image coordinates
+  int pt0, pt1;      // range in the concatenated source permutation
+  int inst;          // instance
+  int level;
+  int child0, nchild;  // children (source box ids) for M2M
+  int octant;        // octant of this box inside its parent (0..7), -1 for roots
+  int parent;
+  long long me_off;  // offset (in complex numbers) of this box's multipole vectors
+};
+
+// target-side box record (device)
+struct TgtBox {
+  double c[3];
+  int pt0, pt1;
+  int inst;
+  int level;
+  int parent;
+  int octant;
+  int leaf;
+  long long le_off;  // offset of this box's local vectors
+  int p2p0, p2p1;    // free space: range in the near-box list (P2P)
+};
+
+// M2L class: a set of target boxes sharing one list of potential source
+// offsets; each offset owns (per output type) a P x K matrix.
+struct M2LClass {
+  int inst;
+  int n_off;          // number of offsets
+  int off0;           // first offset record
+  int n_tgt;          // number of target boxes
+  int tgt0;           // first entry in the class target list
+  int nblk;           // 1 (free) or 3 (reaction)
+  int P;              // output/input vector length
+};
+
+struct M2LOffset {
+  long long mat[3];   // per output type: offset (in complex) of the P x (nblk*P) matrix
+  double phi;         // azimuth of the box-centre offset (reaction phases)
+};
+
+// one work tile of the M2L GEMM
+struct M2LTile {
+  int cls;
+  int out_type;       // 0: +, 1: -, 2: z
+  int col0, ncol;     // column range; a column is (target slot, rhs)
+  int row0;           // first output row
+};
+
+// node of a Sommerfeld quadrature set (one per instance and level)
+struct QNode {
+  cd kr, w;           // node and weight (includes d kr / dt)
+  cd kzt, kzs;        // vertical wavenumbers of target and source layer
+  cd F[5];            // densities F_sigma = -(2i/k^2) S_sigma (no centre exponential)
+  cd tau_t[4];        // 1, sec b, sin b, tan b for the target side
+  cd tau_s[4];        // same for the source side
+  cd x0;              // cos 2 b0 (base side = smaller wavenumber)
+};
+
+// one reaction M2L table case
+struct TabCase {
+  int inst;
+  int node0, nnode;   // quadrature node range
+  double rho;         // horizontal centre distance
+  double zt_orig;     // target centre mapped back to physical z
+  double zs_orig;     // source centre mapped back to physical z
+  long long mat;      // offset of the three P x 3P matrices (A+, A-, Az)
+  long long ibuf;     // offset of the Chebyshev integral buffer
+};
+
+// free-space / translation matrix job
+struct TransJob {
+  double b[3];        // translation vector
+  double k;
+  int p;
+  int kind;           // 0: S|R (M2L, times ik), 1: M2M conj(R|R) transposed, 2: L2L R|R
+  long long mat;      // output offset
+};
+
+std::string lm_fmt(const char* fmt, ...);

@@ -1,0 +1,966 @@
+// plan.cpp -- host planner of the layered-media dyadic FMM.
+//
+// Builds, from the medium and the point sets:
+//  * the reaction components (target layer, source layer, arrival and
+//    departure directions) with their polarization images and effective
+//    locations (paper Sec. 3.1, the images/effective-location definitions
+//    and the sign table of the Z functions);
+//  * one octree per free-space layer (uniform depth) and, per reaction
+//    component, a source tree over the images and a target tree over the
+//    effective locations.  The two reaction trees share the x-y lattice and
+//    are anchored on the two sides of the gap that always separates images
+//    from effective locations (Sec. 3.2), so every box centre of one tree
+//    lies strictly on its own side; boxes touching the gap are refined until
+//    no adjacent source/target boxes remain (Sec. 3.4, the S2T discussion),
+//    hence no direct reaction interactions are needed;
+//  * interaction lists, grouped into M2L classes (targets with the same
+//    lattice parity and distance to the gap share one list of offsets);
+//  * table cases for the reaction M2L (one per distinct (rho, z, z') box
+//    geometry and level, Sec. 3.4) and the Sommerfeld quadrature nodes;
+//  * Chebyshev coefficients of the associated Legendre functions
+//    (Appendix B) and of the affine Chebyshev change of variable
+//    (Appendix A), and the Gaunt table of the free-space translations.
+#include "plan.h"
+
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+
+std::string lm_fmt(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  return std::string(buf);
+}
+
+// ------------------------------------------------------------------ algebra
+
+// Chebyshev coefficients of T_j(a x + b) = sum_s C[j][s] T_s(x), j, s <= jmax
+// (Appendix A), from T_{j+1}(y) = 2 y T_j(y) - T_{j-1}(y) and the product rule
+// 2 x T_s(x) = T_{s+1}(x) + T_{|s-1|}(x).  Row stride jmax+1.
+void lm_cheb_affine(int jmax, double a, double b, std::vector<double>& C) {
+  int W = jmax + 1;
+  C.assign((size_t)W * W, 0.0);
+  C[0] = 1.0;
+  if (jmax >= 1) {
+    C[W + 0] = b;
+    C[W + 1] = a;
+  }
+  for (int j = 1; j < jmax; j++) {
+    double* cj = &C[(size_t)j * W];
+    double* cm = &C[(size_t)(j - 1) * W];
+    double* cn = &C[(size_t)(j + 1) * W];
+    for (int s = 0; s <= j; s++) {
+      double v = cj[s];
+      if (v == 0.0) continue;
+      cn[s] += 2.0 * b * v;
+      cn[s + 1] += a * v;
+      cn[s == 0 ? 1 : s - 1] += a * v;
+    }
+    for (int s = 0; s <= j - 1; s++) cn[s] -= cm[s];
+  }
+}
+
+// K_n of Appendix B: degree in cos(2 theta) of P^m_n / tau_nm
+int lm_cheb_K(int n, int m) {
+  m = m < 0 ? -m : m;
+  if (n % 2 == 0) return n / 2;
+  return (m % 2 == 0) ? (n + 1) / 2 : (n - 1) / 2;
+}
+
+// tau type: 0 -> 1, 1 -> sec, 2 -> sin, 3 -> tan  (Appendix B)
+int lm_tau_type(int n, int m) {
+  m = m < 0 ? -m : m;
+  bool ne = (n % 2 == 0), me = (m % 2 == 0);
+  if (ne && me) return 0;
+  if (!ne && me) return 1;
+  if (!ne && !me) return 2;
+  return 3;
+}
+
+// B[tri(n,m)][k]: P^m_n(cos t) = tau_nm(t) sum_k B^k T_k(cos 2t), m >= 0
+// (Appendix B).  The coefficients are obtained by exact Chebyshev
+// interpolation of the polynomial P^m_n / tau_nm in x = cos 2t at
+// Chebyshev-Gauss points (more points than the degree), which reproduces
+// the appendix's expansion without its recursion constants.
+// Row stride KS = (p+1)/2 + 2.
+void lm_legendre_cheb(int p, std::vector<double>& B) {
+  int KS = (p + 1) / 2 + 2;
+  int ntri = (p + 1) * (p + 2) / 2;
+  B.assign((size_t)ntri * KS, 0.0);
+  int NC = KS + 6;
+  std::vector<double> Pt((size_t)ntri);
+  for (int i = 0; i < NC; i++) {
+    double x = cos(M_PI * (i + 0.5) / NC);
+    double th = 0.5 * acos(x);
+    double c = cos(th), s = sin(th);
+    legendre_r(p, c, s, Pt.data());
+    for (int n = 0; n <= p; n++)
+      for (int m = 0; m <= n; m++) {
+        double tau;
+        switch (lm_tau_type(n, m)) {
+          case 0: tau = 1.0; break;
+          case 1: tau = 1.0 / c; break;
+          case 2: tau = s; break;
+          default: tau = s / c; break;
+        }
+        double f = Pt[tri_idx(n, m)] / tau;
+        int K = lm_cheb_K(n, m);
+        double tk0 = 1.0, tk1 = x;
+        for (int k = 0; k <= K; k++) {
+          double tk = (k == 0) ? 1.0 : (k == 1 ? x : 2.0 * x * tk1 - tk0);
+          if (k >= 2) {
+            tk0 = tk1;
+            tk1 = tk;
+          }
+          B[(size_t)tri_idx(n, m) * KS + k] += (k == 0 ? 1.0 : 2.0) / NC * f * tk;
+        }
+      }
+  }
+}
+
+// Gaunt coefficients G(nu,mu; n,m; q, mu-m) = int Y^mu_nu conj(Y^m_n) conj(Y^{mu-m}_q)
+// by Gauss-Legendre quadrature (exact: polynomial integrand).
+long long lm_gaunt_index(int p, int nu, int mu, int n, int m, int q) {
+  long long P = (long long)(p + 1) * (p + 1);
+  return (((long long)nm_idx(nu, mu) * P) + nm_idx(n, m)) * (2 * p + 1) + q;
+}
+
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < (n + 1) / 2; i++) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5)), pp = 0;
+    for (int it = 0; it < 100; it++) {
+      double p1 = 1, p2 = 0;
+      for (int j = 1; j <= n; j++) {
+        double p3 = p2;
+        p2 = p1;
+        p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+      }
+      pp = n * (z * p1 - p2) / (z * z - 1.0);
+      double z1 = z;
+      z = z1 - p1 / pp;
+      if (fabs(z - z1) < 1e-16) break;
+    }
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * pp * pp);
+  }
+}
+
+void lm_gaunt_table(int p, std::vector<double>& G) {
+  int Q = 2 * p;
+  long long P = (long long)(p + 1) * (p + 1);
+  G.assign((size_t)(P * P * (2 * p + 1)), 0.0);
+  int ng = 2 * p + 2;
+  std::vector<double> xg, wg;
+  gauss_legendre(ng, xg, wg);
+  int ntri = (Q + 1) * (Q + 2) / 2;
+  std::vector<double> Pl((size_t)ng * ntri);
+  for (int g = 0; g < ng; g++) legendre_r(Q, xg[g], sqrt(1.0 - xg[g] * xg[g]), &Pl[(size_t)g * ntri]);
+  auto Ph = [&](int g, int n, int m) {
+    double v = Pl[(size_t)g * ntri + tri_idx(n, m < 0 ? -m : m)];
+    return (m < 0 && (m % 2)) ? -v : v;
+  };
+  for (int nu = 0; nu <= p; nu++)
+    for (int mu = -nu; mu <= nu; mu++)
+      for (int n = 0; n <= p; n++)
+        for (int m = -n; m <= n; m++) {
+          int s = mu - m;
+          for (int q = std::abs(n - nu); q <= n + nu; q++) {
+            if (((n + nu + q) & 1) || std::abs(s) > q) continue;
+            double acc = 0;
+            for (int g = 0; g < ng; g++) acc += wg[g] * Ph(g, nu, mu) * Ph(g, n, m) * Ph(g, q, s);
+            G[lm_gaunt_index(p, nu, mu, n, m, q)] = 2.0 * M_PI * acc;
+          }
+        }
+}
+
+// ------------------------------------------------------------ components
+
+// Valid reaction components (Sec. 3.1): a wave arriving at the target going
+// down needs an interface above the target layer, going up one below; the
+// same for the departure at the source.  Fills lt, ls, up_t, up_s, sgn and the
+// image/effective-location maps; returns the count.
+int lm_enumerate_components(const Medium& med, std::vector<InstParams>& out) {
+  int L = med.n - 1;
+  out.clear();
+  for (int l = 0; l <= L; l++)
+    for (int lp = 0; lp <= L; lp++)
+      for (int ut = 1; ut >= 0; ut--)
+        for (int us = 1; us >= 0; us--) {
+          if (!ut && l < 1) continue;
+          if (ut && l > L - 1) continue;
+          if (us && lp < 1) continue;
+          if (!us && lp > L - 1) continue;
+          InstParams ip;
+          memset(&ip, 0, sizeof(ip));
+          ip.kind = 1;
+          ip.lt = l;
+          ip.ls = lp;
+          ip.up_t = ut;
+          ip.up_s = us;
+          ip.kt = med.k[l];
+          ip.ks = med.k[lp];
+          // sign of the Z exponent
+          if (!us)
+            ip.sgn = (l <= lp) ? 1 : -1;
+          else
+            ip.sgn = (l < lp) ? 1 : -1;
+          // polarization image of the source (z' -> as z' + bs)
+          if (!us) {
+            if (l <= lp) { ip.as = -1; ip.bs = 2 * med.d[lp]; }
+            else { ip.as = 1; ip.bs = 0; }
+          } else {
+            if (l < lp) { ip.as = 1; ip.bs = 0; }
+            else { ip.as = -1; ip.bs = 2 * med.d[lp - 1]; }
+          }
+          // effective location of the target (z -> at z + bt)
+          bool refl;
+          if (ut && us) refl = !(l < lp);
+          else if (ut && !us) refl = !(l <= lp);
+          else if (!ut && us) refl = (l < lp);
+          else refl = (l <= lp);
+          if (!refl) { ip.at = 1; ip.bt = 0; }
+          else if (ut) { ip.at = -1; ip.bt = 2 * med.d[l]; }
+          else { ip.at = -1; ip.bt = 2 * med.d[l - 1]; }
+          out.push_back(ip);
+        }
+  return (int)out.size();
+}
+
+// ------------------------------------------------------------------ trees
+
+static const int DK = 20;  // key depth
+
+static inline uint64_t spread3(uint64_t v) {
+  v &= 0xFFFFF;
+  v = (v | (v << 32)) & 0x1F00000000FFFFull;
+  v = (v | (v << 16)) & 0x1F0000FF0000FFull;
+  v = (v | (v << 8)) & 0x100F00F00F00F00Full;
+  v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+
+struct KeyRec {
+  uint64_t key;
+  int id;   // point id
+  int tag;  // 0 source, 1 target
+};
+
+static void radix_sort(std::vector<KeyRec>& a) {
+  std::vector<KeyRec> b(a.size());
+  for (int pass = 0; pass < 8; pass++) {
+    int sh = pass * 8;
+    size_t cnt[257] = {0};
+    for (auto& r : a) cnt[((r.key >> sh) & 255) + 1]++;
+    bool trivial = false;
+    for (int i = 0; i < 256; i++)
+      if (cnt[i + 1] == a.size()) trivial = true;
+    if (trivial) continue;
+    for (int i = 0; i < 256; i++) cnt[i + 1] += cnt[i];
+    for (auto& r : a) b[cnt[(r.key >> sh) & 255]++] = r;
+    a.swap(b);
+  }
+}
+
+struct HTree {
+  double x0, y0, z0, S0;
+  int zflip;  // j = iz (0) or j = 2^l - 1 - iz (1)
+  // per box
+  std::vector<int> lvl, ix, iy, iz, parent, child0, nchild, oct, u0, u1, a0, a1, b0, b1;
+  std::vector<int> lvl_start;
+  std::vector<KeyRec> recs;    // sorted union
+  std::vector<int> permA, permB;
+  int nbox() const { return (int)lvl.size(); }
+  int j(int b) const { return zflip ? ((1 << lvl[b]) - 1 - iz[b]) : iz[b]; }
+  double S(int l) const { return S0 / (double)(1 << l); }
+  void centre(int b, double* c) const {
+    double s = S(lvl[b]);
+    c[0] = x0 + (ix[b] + 0.5) * s;
+    c[1] = y0 + (iy[b] + 0.5) * s;
+    c[2] = z0 + (iz[b] + 0.5) * s;
+  }
+};
+
+// Build an octree over tagged points (positions pos[3*i]).  split(level, n,
+// j, S) decides whether a box is refined.
+template <class Split>
+static void build_tree(HTree& T, const std::vector<double>& pos, const std::vector<int>& ids,
+                       const std::vector<int>& tags, Split split) {
+  size_t n = ids.size();
+  T.recs.resize(n);
+  double inv = (double)(1 << DK) / T.S0;
+  for (size_t i = 0; i < n; i++) {
+    const double* x = &pos[3 * i];
+    long long ux = (long long)floor((x[0] - T.x0) * inv);
+    long long uy = (long long)floor((x[1] - T.y0) * inv);
+    long long uz = (long long)floor((x[2] - T.z0) * inv);
+    long long mx = (1 << DK) - 1;
+    ux = std::min(std::max(ux, 0LL), mx);
+    uy = std::min(std::max(uy, 0LL), mx);
+    uz = std::min(std::max(uz, 0LL), mx);
+    T.recs[i].key = spread3(ux) | (spread3(uy) << 1) | (spread3(uz) << 2);
+    T.recs[i].id = ids[i];
+    T.recs[i].tag = tags[i];
+  }
+  radix_sort(T.recs);
+  std::vector<int> cntA(n + 1, 0);
+  for (size_t i = 0; i < n; i++) cntA[i + 1] = cntA[i] + (T.recs[i].tag == 0);
+  T.permA.clear();
+  T.permB.clear();
+  for (size_t i = 0; i < n; i++) (T.recs[i].tag == 0 ? T.permA : T.permB).push_back(T.recs[i].id);
+  auto push_box = [&](int l, int px, int py, int pz, int par, int oc, int u0, int u1) {
+    T.lvl.push_back(l);
+    T.ix.push_back(px);
+    T.iy.push_back(py);
+    T.iz.push_back(pz);
+    T.parent.push_back(par);
+    T.child0.push_back(-1);
+    T.nchild.push_back(0);
+    T.oct.push_back(oc);
+    T.u0.push_back(u0);
+    T.u1.push_back(u1);
+    T.a0.push_back(cntA[u0]);
+    T.a1.push_back(cntA[u1]);
+    T.b0.push_back(u0 - cntA[u0]);
+    T.b1.push_back(u1 - cntA[u1]);
+  };
+  T.lvl_start.clear();
+  if (n == 0) {
+    T.lvl_start.push_back(0);
+    return;
+  }
+  push_box(0, 0, 0, 0, -1, -1, 0, (int)n);
+  T.lvl_start.push_back(0);
+  for (int l = 0; l < DK; l++) {
+    int b0 = T.lvl_start.back(), b1 = T.nbox();
+    if (b0 == b1) break;
+    T.lvl_start.push_back(b1);
+    bool any = false;
+    for (int b = b0; b < b1; b++) {
+      int cnt = T.u1[b] - T.u0[b];
+      if (!split(l, cnt, T.j(b), T.S(l))) continue;
+      any = true;
+      int sh = 3 * (DK - 1 - l);
+      int first = T.nbox();
+      int u = T.u0[b];
+      while (u < T.u1[b]) {
+        int dig = (int)((T.recs[u].key >> sh) & 7);
+        int v = u;
+        while (v < T.u1[b] && (int)((T.recs[v].key >> sh) & 7) == dig) v++;
+        push_box(l + 1, 2 * T.ix[b] + (dig & 1), 2 * T.iy[b] + ((dig >> 1) & 1),
+                 2 * T.iz[b] + ((dig >> 2) & 1), b, dig, u, v);
+        u = v;
+      }
+      T.child0[b] = first;
+      T.nchild[b] = T.nbox() - first;
+    }
+    if (!any) break;
+  }
+  if (T.lvl_start.back() != T.nbox()) T.lvl_start.push_back(T.nbox());
+}
+
+static inline uint64_t ckey(int x, int y, int z) {
+  return (uint64_t)(uint32_t)x | ((uint64_t)(uint32_t)y << 21) | ((uint64_t)(uint32_t)z << 42);
+}
+
+// ------------------------------------------------------------------ plan
+
+namespace {
+
+struct MatKey {
+  int kind;  // 0 free M2L, 1 M2M, 2 L2L
+  long long kq;  // quantised wavenumber
+  int p, level, a, b, c;
+  bool operator<(const MatKey& o) const {
+    return std::tie(kind, kq, p, level, a, b, c) < std::tie(o.kind, o.kq, o.p, o.level, o.a, o.b, o.c);
+  }
+};
+
+}  // namespace
+
+std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int64_t n_src,
+                         const double* src, int64_t n_tgt, const double* tgt) {
+  pl = Plan();
+  pl.med = med;
+  pl.prm = prm;
+  pl.p = prm.p;
+  pl.pf = prm.p_free > 0 ? prm.p_free : prm.p;
+  pl.n_src = n_src;
+  pl.n_tgt = n_tgt;
+  int L = med.n - 1;
+  int pmax = std::max(pl.p, pl.pf);
+
+  // layer membership
+  std::vector<std::vector<int>> src_in(med.n), tgt_in(med.n);
+  for (int64_t i = 0; i < n_src; i++) src_in[med.layer_of(src[3 * i + 2])].push_back((int)i);
+  for (int64_t i = 0; i < n_tgt; i++) tgt_in[med.layer_of(tgt[3 * i + 2])].push_back((int)i);
+
+  // global lattice: common x-y origin and root size for every tree
+  double xmin = 1e300, ymin = 1e300, xmax = -1e300, ymax = -1e300;
+  for (int64_t i = 0; i < n_src; i++) {
+    xmin = std::min(xmin, src[3 * i]);
+    xmax = std::max(xmax, src[3 * i]);
+    ymin = std::min(ymin, src[3 * i + 1]);
+    ymax = std::max(ymax, src[3 * i + 1]);
+  }
+  for (int64_t i = 0; i < n_tgt; i++) {
+    xmin = std::min(xmin, tgt[3 * i]);
+    xmax = std::max(xmax, tgt[3 * i]);
+    ymin = std::min(ymin, tgt[3 * i + 1]);
+    ymax = std::max(ymax, tgt[3 * i + 1]);
+  }
+  if (n_src == 0 && n_tgt == 0) return "";
+
+  // instances
+  std::vector<InstParams> comps;
+  lm_enumerate_components(med, comps);
+  struct IGeom {
+    InstParams ip;
+    std::vector<int> sid, tid;      // point ids
+    std::vector<double> spos, tpos; // positions in instance coordinates
+    double zs0, zs1, zt0, zt1;
+  };
+  std::vector<IGeom> geo;
+  double ext = std::max(xmax - xmin, ymax - ymin);
+  if (prm.components & 1) {
+    for (int l = 0; l <= L; l++) {
+      if (src_in[l].empty() || tgt_in[l].empty()) continue;
+      IGeom g;
+      memset(&g.ip, 0, sizeof(g.ip));
+      g.ip.kind = 0;
+      g.ip.lt = g.ip.ls = l;
+      g.ip.kt = g.ip.ks = med.k[l];
+      g.ip.at = g.ip.as = 1;
+      g.ip.sgn = 1;
+      g.sid = src_in[l];
+      g.tid = tgt_in[l];
+      g.zs0 = 1e300;
+      g.zs1 = -1e300;
+      for (int i : g.sid) {
+        g.spos.insert(g.spos.end(), {src[3 * i], src[3 * i + 1], src[3 * i + 2]});
+        g.zs0 = std::min(g.zs0, src[3 * i + 2]);
+        g.zs1 = std::max(g.zs1, src[3 * i + 2]);
+      }
+      for (int i : g.tid) {
+        g.tpos.insert(g.tpos.end(), {tgt[3 * i], tgt[3 * i + 1], tgt[3 * i + 2]});
+        g.zs0 = std::min(g.zs0, tgt[3 * i + 2]);
+        g.zs1 = std::max(g.zs1, tgt[3 * i + 2]);
+      }
+      g.zt0 = g.zs0;
+      g.zt1 = g.zs1;
+      ext = std::max(ext, g.zs1 - g.zs0);
+      geo.push_back(g);
+    }
+  }
+  if (prm.components & 2) {
+    for (auto& c : comps) {
+      if (src_in[c.ls].empty() || tgt_in[c.lt].empty()) continue;
+      IGeom g;
+      g.ip = c;
+      g.sid = src_in[c.ls];
+      g.tid = tgt_in[c.lt];
+      g.zs0 = g.zt0 = 1e300;
+      g.zs1 = g.zt1 = -1e300;
+      for (int i : g.sid) {
+        double z = c.as * src[3 * i + 2] + c.bs;
+        g.spos.insert(g.spos.end(), {src[3 * i], src[3 * i + 1], z});
+        g.zs0 = std::min(g.zs0, z);
+        g.zs1 = std::max(g.zs1, z);
+      }
+      for (int i : g.tid) {
+        double z = c.at * tgt[3 * i + 2] + c.bt;
+        g.tpos.insert(g.tpos.end(), {tgt[3 * i], tgt[3 * i + 1], z});
+        g.zt0 = std::min(g.zt0, z);
+        g.zt1 = std::max(g.zt1, z);
+      }
+      // images and effective locations must lie on the two sides of a gap
+      double gap = c.sgn > 0 ? g.zt0 - g.zs1 : g.zs0 - g.zt1;
+      if (!(gap > 0))
+        return lm_fmt("reaction component (%d,%d,%s,%s): images and effective locations are not "
+                      "separated (a point lies on an interface?)",
+                      c.lt, c.ls, c.up_t ? "up" : "down", c.up_s ? "up" : "down");
+      ext = std::max(ext, std::max(g.zs1 - g.zs0, g.zt1 - g.zt0));
+      geo.push_back(g);
+    }
+  }
+  double S0 = ext * (1.0 + 1e-9) + 1e-300;
+  if (!(S0 > 0)) S0 = 1.0;
+  double eps = 1e-9 * S0;
+  double X0 = xmin - eps, Y0 = ymin - eps;
+  S0 += 2 * eps;
+
+  auto kquant = [](double k) { return (long long)llround(k * 1e12); };
+  std::map<MatKey, long long> matmap;
+  auto alloc_mat = [&](const MatKey& key, long long size, const TransJob* job) -> long long {
+    auto it = matmap.find(key);
+    if (it != matmap.end()) return it->second;
+    long long off = pl.mat_size;
+    pl.mat_size += size;
+    matmap[key] = off;
+    if (job) {
+      TransJob j = *job;
+      j.mat = off;
+      pl.trans.push_back(j);
+    }
+    return off;
+  };
+
+  int KB = (pmax + 1) / 2;  // maximal Chebyshev index K_n
+  pl.kmaxcheb = KB;
+  std::map<std::tuple<int, int, long long, long long, long long>, int> casemap;
+  std::vector<double> case_dz;  // vertical centre separation of each case
+
+  for (auto& g : geo) {
+    InstParams ip = g.ip;
+    int inst = (int)pl.inst.size();
+    ip.p = ip.kind == 0 ? pl.pf : pl.p;
+    ip.P = (ip.p + 1) * (ip.p + 1);
+    int P = ip.P;
+    HTree S, T;
+    S.x0 = T.x0 = X0;
+    S.y0 = T.y0 = Y0;
+    S.S0 = T.S0 = S0;
+    std::vector<int> tagS, tagT;
+    bool free = ip.kind == 0;
+    double Dgap = 0;
+    int depth_used = 0;
+    if (free) {
+      S.z0 = g.zs0 - eps;
+      S.zflip = 0;
+      std::vector<double> pos = g.spos;
+      pos.insert(pos.end(), g.tpos.begin(), g.tpos.end());
+      std::vector<int> ids = g.sid;
+      ids.insert(ids.end(), g.tid.begin(), g.tid.end());
+      std::vector<int> tags(g.sid.size(), 0);
+      tags.resize(ids.size(), 1);
+      int D = prm.free_depth;
+      if (D <= 0) {
+        // cost model: near-field pairs vs. dense M2L work
+        double best = 1e300;
+        std::vector<uint64_t> keys(ids.size());
+        double inv = (double)(1 << DK) / S0;
+        for (size_t i = 0; i < ids.size(); i++) {
+          long long mx = (1 << DK) - 1;
+          long long ux = std::min(std::max((long long)floor((pos[3 * i] - S.x0) * inv), 0LL), mx);
+          long long uy = std::min(std::max((long long)floor((pos[3 * i + 1] - S.y0) * inv), 0LL), mx);
+          long long uz = std::min(std::max((long long)floor((pos[3 * i + 2] - S.z0) * inv), 0LL), mx);
+          keys[i] = spread3(ux) | (spread3(uy) << 1) | (spread3(uz) << 2);
+        }
+        std::sort(keys.begin(), keys.end());
+        for (int Dc = 2; Dc <= 12; Dc++) {
+          int sh = 3 * (DK - Dc);
+          long long leaves = 0;
+          for (size_t i = 0; i < keys.size(); i++)
+            if (i == 0 || (keys[i] >> sh) != (keys[i - 1] >> sh)) leaves++;
+          double ns = (double)g.sid.size(), nt = (double)g.tid.size();
+          double c_p2p = nt * 27.0 * ns / (double)leaves * 0.6 * 160.0;
+          double c_m2l = (double)leaves * 189.0 * 1.14 * 3.0 * P * (double)P * 8.0 / 0.6;
+          double c = c_p2p + c_m2l;
+          if (c < best) {
+            best = c;
+            D = Dc;
+          }
+        }
+      }
+      depth_used = D;
+      build_tree(S, pos, ids, tags, [&](int l, int n, int, double) { return n > 0 && l < D; });
+      pl.free_depth_used.push_back(D);
+    } else {
+      if (ip.sgn > 0) {
+        S.z0 = g.zs1 + eps - S0;
+        S.zflip = 1;
+        T.z0 = g.zt0 - eps;
+        T.zflip = 0;
+        Dgap = (g.zt0 - eps) - (g.zs1 + eps);
+      } else {
+        S.z0 = g.zs0 - eps;
+        S.zflip = 0;
+        T.z0 = g.zt1 + eps - S0;
+        T.zflip = 1;
+        Dgap = (g.zs0 - eps) - (g.zt1 + eps);
+      }
+      int Dmax = 0;
+      while (S0 / (double)(1 << Dmax) > Dgap) Dmax++;
+      if (Dmax > prm.max_depth)
+        return lm_fmt("reaction component (%d,%d): points are too close to an interface "
+                      "(gap %.3e needs %d tree levels, limit %d)",
+                      ip.lt, ip.ls, Dgap, Dmax, prm.max_depth);
+      depth_used = Dmax;
+      auto rule = [&](int l, int n, int j, double Sl) { return n > 0 && l < Dmax && j == 0 && Sl > Dgap; };
+      build_tree(S, g.spos, g.sid, std::vector<int>(g.sid.size(), 0), rule);
+      build_tree(T, g.tpos, g.tid, std::vector<int>(g.tid.size(), 1), rule);
+    }
+    ip.Dgap = Dgap;
+    (void)depth_used;
+    HTree& TT = free ? S : T;  // target tree
+
+    // ---- boxes -> global records
+    int sbase = (int)pl.sbox.size(), tbase = (int)pl.tbox.size();
+    int sp0 = (int)pl.src_perm.size(), tp0 = (int)pl.tgt_perm.size();
+    pl.src_perm.insert(pl.src_perm.end(), S.permA.begin(), S.permA.end());
+    pl.tgt_perm.insert(pl.tgt_perm.end(), TT.permB.begin(), TT.permB.end());
+    for (int b = 0; b < S.nbox(); b++) {
+      SrcBox sb;
+      memset(&sb, 0, sizeof(sb));
+      S.centre(b, sb.c);
+      sb.pt0 = sp0 + S.a0[b];
+      sb.pt1 = sp0 + S.a1[b];
+      sb.inst = inst;
+      sb.level = S.lvl[b];
+      sb.child0 = S.child0[b] >= 0 ? sbase + S.child0[b] : -1;
+      sb.nchild = S.nchild[b];
+      sb.octant = S.oct[b];
+      sb.parent = S.parent[b] >= 0 ? sbase + S.parent[b] : -1;
+      sb.me_off = pl.me_size;
+      pl.me_size += 3LL * P;
+      pl.sbox.push_back(sb);
+      long long mm = -1;
+      if (S.parent[b] >= 0) {
+        int o = S.oct[b];
+        double s = S.S(S.lvl[b]);
+        TransJob j;
+        j.b[0] = ((o & 1) - 0.5) * s;
+        j.b[1] = (((o >> 1) & 1) - 0.5) * s;
+        j.b[2] = (((o >> 2) & 1) - 0.5) * s;
+        j.k = ip.ks;
+        j.p = ip.p;
+        j.kind = 1;
+        mm = alloc_mat(MatKey{1, kquant(ip.ks), ip.p, S.lvl[b], o, 0, 0}, (long long)P * P, &j);
+      }
+      pl.sbox_m2m.push_back(mm);
+      if (S.nchild[b] == 0 && S.a1[b] > S.a0[b]) pl.p2m_leaves.push_back(sbase + b);
+    }
+    for (int b = 0; b < TT.nbox(); b++) {
+      TgtBox tb;
+      memset(&tb, 0, sizeof(tb));
+      TT.centre(b, tb.c);
+      tb.pt0 = tp0 + TT.b0[b];
+      tb.pt1 = tp0 + TT.b1[b];
+      tb.inst = inst;
+      tb.level = TT.lvl[b];
+      tb.parent = TT.parent[b] >= 0 ? tbase + TT.parent[b] : -1;
+      tb.octant = TT.oct[b];
+      tb.leaf = TT.nchild[b] == 0;
+      tb.le_off = pl.le_size;
+      tb.p2p0 = tb.p2p1 = 0;
+      pl.le_size += 3LL * P;
+      pl.tbox.push_back(tb);
+      long long mm = -1;
+      if (TT.parent[b] >= 0) {
+        int o = TT.oct[b];
+        double s = TT.S(TT.lvl[b]);
+        TransJob j;
+        j.b[0] = ((o & 1) - 0.5) * s;
+        j.b[1] = (((o >> 1) & 1) - 0.5) * s;
+        j.b[2] = (((o >> 2) & 1) - 0.5) * s;
+        j.k = ip.kt;
+        j.p = ip.p;
+        j.kind = 2;
+        mm = alloc_mat(MatKey{2, kquant(ip.kt), ip.p, TT.lvl[b], o, 0, 0}, (long long)P * P, &j);
+      }
+      pl.tbox_l2l.push_back(mm);
+    }
+    // M2M parents / L2L children per level
+    for (int b = 0; b < S.nbox(); b++)
+      if (S.nchild[b] > 0) {
+        int l = S.lvl[b];
+        if ((int)pl.m2m_parents.size() <= l) pl.m2m_parents.resize(l + 1);
+        pl.m2m_parents[l].push_back(sbase + b);
+      }
+    for (int b = 0; b < TT.nbox(); b++)
+      if (TT.parent[b] >= 0) {
+        int l = TT.lvl[b];
+        if ((int)pl.l2l_children.size() <= l) pl.l2l_children.resize(l + 1);
+        pl.l2l_children[l].push_back(tbase + b);
+      }
+    pl.l2p_leaves.push_back({});
+    for (int b = 0; b < TT.nbox(); b++)
+      if (TT.nchild[b] == 0 && TT.b1[b] > TT.b0[b]) pl.l2p_leaves.back().push_back(tbase + b);
+
+    // ---- interaction lists
+    struct Pair {
+      int s, t;  // local box ids
+    };
+    std::vector<Pair> m2l;
+    std::vector<std::unordered_map<uint64_t, int>> smap(DK + 2);
+    for (int b = 0; b < S.nbox(); b++) smap[S.lvl[b]][ckey(S.ix[b], S.iy[b], S.iz[b])] = b;
+    if (free) {
+      int D = S.lvl[S.nbox() - 1];
+      for (int t = 0; t < S.nbox(); t++) {
+        if (S.b1[t] <= S.b0[t]) continue;  // no targets
+        int l = S.lvl[t];
+        if (l < 1) continue;
+        int px = S.ix[t] >> 1, py = S.iy[t] >> 1, pz = S.iz[t] >> 1;
+        for (int dx = -1; dx <= 1; dx++)
+          for (int dy = -1; dy <= 1; dy++)
+            for (int dz = -1; dz <= 1; dz++) {
+              auto it = smap[l - 1].find(ckey(px + dx, py + dy, pz + dz));
+              if (it == smap[l - 1].end()) continue;
+              int q = it->second;
+              for (int c = S.child0[q]; c >= 0 && c < S.child0[q] + S.nchild[q]; c++) {
+                if (S.a1[c] <= S.a0[c]) continue;
+                int ddx = S.ix[c] - S.ix[t], ddy = S.iy[c] - S.iy[t], ddz = S.iz[c] - S.iz[t];
+                if (std::max(std::abs(ddx), std::max(std::abs(ddy), std::abs(ddz))) >= 2)
+                  m2l.push_back({c, t});
+              }
+            }
+        if (l == D) {
+          TgtBox& tb = pl.tbox[tbase + t];
+          tb.p2p0 = (int)pl.p2p_list.size();
+          for (int dx = -1; dx <= 1; dx++)
+            for (int dy = -1; dy <= 1; dy++)
+              for (int dz = -1; dz <= 1; dz++) {
+                auto it = smap[l].find(ckey(S.ix[t] + dx, S.iy[t] + dy, S.iz[t] + dz));
+                if (it == smap[l].end()) continue;
+                int q = it->second;
+                if (S.a1[q] <= S.a0[q]) continue;
+                pl.p2p_list.push_back(sbase + q);
+                pl.n_p2p_pairs += (long long)(S.a1[q] - S.a0[q]) * (S.b1[t] - S.b0[t]);
+              }
+          tb.p2p1 = (int)pl.p2p_list.size();
+        }
+      }
+      pl.p2p_tboxes.push_back({});
+      for (int t = 0; t < S.nbox(); t++)
+        if (S.lvl[t] == D && S.b1[t] > S.b0[t]) pl.p2p_tboxes.back().push_back(tbase + t);
+    } else {
+      std::vector<std::vector<int>> nearT(T.nbox());
+      auto ws = [&](int s, int t) {
+        double cs[3], ct[3];
+        S.centre(s, cs);
+        T.centre(t, ct);
+        double sl = S.S(S.lvl[s]) * (2.0 - 1e-9);
+        return fabs(cs[0] - ct[0]) >= sl || fabs(cs[1] - ct[1]) >= sl || fabs(cs[2] - ct[2]) >= sl;
+      };
+      if (S.nbox() > 0 && T.nbox() > 0) {
+        if (ws(0, 0))
+          m2l.push_back({0, 0});
+        else
+          nearT[0].push_back(0);
+      }
+      for (int t = 0; t < T.nbox(); t++) {
+        int P0 = T.parent[t];
+        if (P0 >= 0) {
+          for (int q : nearT[P0]) {
+            if (S.nchild[q] == 0)
+              return lm_fmt("reaction component (%d,%d): adjacent source leaf at level %d "
+                            "(points too close to an interface)",
+                            ip.lt, ip.ls, S.lvl[q]);
+            for (int c = S.child0[q]; c < S.child0[q] + S.nchild[q]; c++) {
+              if (ws(c, t))
+                m2l.push_back({c, t});
+              else
+                nearT[t].push_back(c);
+            }
+          }
+        }
+        if (T.nchild[t] == 0 && !nearT[t].empty())
+          return lm_fmt("reaction component (%d,%d): adjacent target leaf at level %d "
+                        "(points too close to an interface)",
+                        ip.lt, ip.ls, T.lvl[t]);
+      }
+    }
+    pl.n_m2l_pairs += (long long)m2l.size();
+    (free ? pl.n_m2l_pairs_free : pl.n_m2l_pairs_react) += (long long)m2l.size();
+    (free ? pl.n_free_inst : pl.n_react_inst)++;
+
+    // ---- M2L classes
+    // class key: level, parity of ix, iy, and iz parity (free) or gap index j (reaction)
+    std::map<std::tuple<int, int, int, int>, std::vector<Pair>> byclass;
+    for (auto& pr : m2l) {
+      int t = pr.t;
+      int l = TT.lvl[t];
+      int c3 = free ? (TT.iz[t] & 1) : TT.j(t);
+      byclass[std::make_tuple(l, TT.ix[t] & 1, TT.iy[t] & 1, c3)].push_back(pr);
+    }
+    for (auto& kv : byclass) {
+      int l = std::get<0>(kv.first);
+      double Sl = S0 / (double)(1 << l);
+      auto& prs = kv.second;
+      std::map<std::tuple<int, int, int>, int> offmap;
+      std::map<int, int> tslot;
+      std::vector<int> tlist;
+      for (auto& pr : prs) {
+        int dx = S.ix[pr.s] - TT.ix[pr.t], dy = S.iy[pr.s] - TT.iy[pr.t];
+        int dz = free ? S.iz[pr.s] - TT.iz[pr.t] : S.j(pr.s);
+        offmap.emplace(std::make_tuple(dx, dy, dz), 0);
+        if (!tslot.count(pr.t)) {
+          tslot[pr.t] = (int)tlist.size();
+          tlist.push_back(pr.t);
+        }
+      }
+      M2LClass C;
+      C.inst = inst;
+      C.n_off = (int)offmap.size();
+      C.off0 = (int)pl.offs.size();
+      C.n_tgt = (int)tlist.size();
+      C.tgt0 = (int)pl.cls_tgt.size();
+      C.nblk = free ? 1 : 3;
+      C.P = P;
+      int oi = 0;
+      int jt = std::get<3>(kv.first);
+      for (auto& ov : offmap) {
+        ov.second = oi++;
+        int dx = std::get<0>(ov.first), dy = std::get<1>(ov.first), dz = std::get<2>(ov.first);
+        M2LOffset mo;
+        if (free) {
+          TransJob j;
+          j.b[0] = -dx * Sl;
+          j.b[1] = -dy * Sl;
+          j.b[2] = -dz * Sl;
+          j.k = ip.kt;
+          j.p = ip.p;
+          j.kind = 0;
+          long long m = alloc_mat(MatKey{0, kquant(ip.kt), ip.p, l, dx, dy, dz}, (long long)P * P, &j);
+          mo.mat[0] = mo.mat[1] = mo.mat[2] = m;
+          mo.phi = 0;
+        } else {
+          int js = dz;
+          int r2 = dx * dx + dy * dy;
+          auto ck = std::make_tuple(inst, l, (long long)r2, (long long)jt, (long long)js);
+          int cid;
+          auto it = casemap.find(ck);
+          if (it == casemap.end()) {
+            cid = (int)pl.cases.size();
+            casemap[ck] = cid;
+            TabCase tc;
+            memset(&tc, 0, sizeof(tc));
+            tc.inst = inst;
+            tc.rho = sqrt((double)r2) * Sl;
+            // centres: target box with gap index jt, source box with gap index js
+            double zt_img, zs_img;
+            if (ip.sgn > 0) {
+              zt_img = T.z0 + (jt + 0.5) * Sl;
+              zs_img = S.z0 + S0 - (js + 0.5) * Sl;
+            } else {
+              zt_img = T.z0 + S0 - (jt + 0.5) * Sl;
+              zs_img = S.z0 + (js + 0.5) * Sl;
+            }
+            tc.zt_orig = ip.at * (zt_img - ip.bt);
+            tc.zs_orig = ip.as * (zs_img - ip.bs);
+            tc.node0 = l;  // temporarily the level
+            tc.nnode = 0;
+            case_dz.push_back(ip.sgn * (zt_img - zs_img));
+            tc.mat = pl.mat_size;
+            pl.mat_size += 9LL * P * P;
+            pl.cases.push_back(tc);
+          } else
+            cid = it->second;
+          long long base = pl.cases[cid].mat;
+          mo.mat[0] = base;
+          mo.mat[1] = base + 3LL * P * P;
+          mo.mat[2] = base + 6LL * P * P;
+          mo.phi = atan2(-(double)dy, -(double)dx);
+        }
+        pl.offs.push_back(mo);
+      }
+      pl.cls_srcof0.push_back((long long)pl.cls_srcof.size());
+      size_t base = pl.cls_srcof.size();
+      pl.cls_srcof.resize(base + (size_t)C.n_tgt * C.n_off, -1);
+      for (auto& pr : prs) {
+        int dx = S.ix[pr.s] - TT.ix[pr.t], dy = S.iy[pr.s] - TT.iy[pr.t];
+        int dz = free ? S.iz[pr.s] - TT.iz[pr.t] : S.j(pr.s);
+        int o = offmap[std::make_tuple(dx, dy, dz)];
+        pl.cls_srcof[base + (size_t)tslot[pr.t] * C.n_off + o] = sbase + pr.s;
+      }
+      for (int t : tlist) pl.cls_tgt.push_back(tbase + t);
+      pl.cls.push_back(C);
+    }
+    pl.inst.push_back(ip);
+  }
+
+  // ---- quadrature node sets: one per (reaction instance, level)
+  {
+    double a = prm.contour_a > 0 ? prm.contour_a : 1.5 * med.kmax;
+    double kg = med.kmax;
+    if (!(a > kg)) return "contour end point must exceed the largest wavenumber";
+    std::map<std::pair<int, int>, std::pair<double, double>> lvinfo;  // rho_max, dz_min
+    for (size_t ci = 0; ci < pl.cases.size(); ci++) {
+      auto& tc = pl.cases[ci];
+      auto key = std::make_pair(tc.inst, tc.node0);
+      double dz = case_dz[ci];
+      auto it = lvinfo.find(key);
+      if (it == lvinfo.end())
+        lvinfo[key] = std::make_pair(tc.rho, dz);
+      else {
+        it->second.first = std::max(it->second.first, tc.rho);
+        it->second.second = std::min(it->second.second, dz);
+      }
+    }
+    std::map<std::pair<int, int>, std::pair<int, int>> nodemap;
+    std::vector<double> gx, gw;
+    gauss_legendre(16, gx, gw);
+    double w_im = sqrt(a * a - kg * kg);
+    for (auto& kv : lvinfo) {
+      int inst = kv.first.first;
+      double rho_max = kv.second.first, dzmin = kv.second.second;
+      int n0 = (int)pl.node_kr.size();
+      // Gamma_1: k'_z runs on a straight line from kg to i*sqrt(a^2-kg^2)
+      int np1 = std::max(1, prm.gamma1_panels);
+      for (int pnl = 0; pnl < np1; pnl++) {
+        double t0 = (double)pnl / np1, t1 = (double)(pnl + 1) / np1;
+        for (int gi = 0; gi < 16; gi++) {
+          double t = 0.5 * (t0 + t1) + 0.5 * (t1 - t0) * gx[gi];
+          cd kzg = cd{kg * (1 - t), w_im * t};
+          cd kr = csqrtd(cd{kg * kg, 0} - kzg * kzg);
+          cd dkzg = cd{-kg, w_im};
+          cd dkr = (-1.0) * (kzg * dkzg) / kr;
+          pl.node_kr.push_back(kr);
+          pl.node_w.push_back(0.5 * (t1 - t0) * gw[gi] * dkr);
+          pl.node_inst.push_back(inst);
+        }
+      }
+      // real tail [a, kcut]
+      int pp = pl.inst[inst].p;
+      double kcut = a + (3.0 * pp + prm.tail_digits) / dzmin;
+      double len = std::min(4.0 / dzmin, rho_max > 0 ? 2.0 * M_PI / rho_max : 1e300);
+      int npan = (int)ceil((kcut - a) / len);
+      len = (kcut - a) / npan;
+      for (int pnl = 0; pnl < npan; pnl++) {
+        double k0 = a + pnl * len;
+        for (int gi = 0; gi < 16; gi++) {
+          pl.node_kr.push_back(cd{k0 + 0.5 * len * (gx[gi] + 1.0), 0.0});
+          pl.node_w.push_back(cd{0.5 * len * gw[gi], 0.0});
+          pl.node_inst.push_back(inst);
+        }
+      }
+      nodemap[kv.first] = std::make_pair(n0, (int)pl.node_kr.size() - n0);
+    }
+    int NQ = 2 * pl.p + 3, NL = pl.p + 2;
+    for (auto& tc : pl.cases) {
+      auto nm = nodemap[std::make_pair(tc.inst, tc.node0)];
+      tc.node0 = nm.first;
+      tc.nnode = nm.second;
+      tc.ibuf = pl.ibuf_size;
+      pl.ibuf_size += 5LL * 16 * NL * NQ;
+    }
+  }
+
+  // ---- coefficient tables
+  lm_legendre_cheb(pmax, pl.Bcoef);
+  for (auto& ip : pl.inst) {
+    pl.Ccoef0.push_back((long long)pl.Ccoef.size());
+    if (ip.kind != 1) continue;
+    double ksm = std::min(ip.kt, ip.ks), klg = std::max(ip.kt, ip.ks);
+    double aa = (ksm / klg) * (ksm / klg);
+    std::vector<double> C;
+    lm_cheb_affine(KB + 1, aa, 1.0 - aa, C);
+    pl.Ccoef.insert(pl.Ccoef.end(), C.begin(), C.end());
+  }
+  bool need_gaunt = !pl.trans.empty();
+  if (need_gaunt) {
+    lm_gaunt_table(pmax, pl.gaunt);
+    pl.gaunt_p = pmax;
+  }
+  return "";
+}

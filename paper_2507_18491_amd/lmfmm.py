@@ -1,0 +1,215 @@
+"""Python binding of the layered-media dyadic FMM library (liblmfmm.so).
+
+Argument marshalling only: every step of the evaluation runs in the HIP
+library.  PyTorch provides device memory and the current stream.  The
+binding raises if the library is missing; there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblmfmm.so")
+
+LM_OK = 0
+STAT_NAMES = ["n_free_inst", "n_react_inst", "m2l_pairs_free", "m2l_pairs_react", "p2p_pairs",
+              "n_cases", "n_nodes", "mat_bytes", "me_bytes_per_rhs", "le_bytes_per_rhs",
+              "t_plan_ms", "t_upload_ms", "t_tables_ms", "n_src_boxes", "n_tgt_boxes",
+              "n_m2l_classes", "n_m2l_tiles_1rhs", "m2l_cmac_useful", "m2l_cmac_exec",
+              "n_leaves_p2m", "free_depth"]
+
+
+PHASE_NAMES = ["clear", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p"]
+
+
+class lm_params(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int), ("p_free", ctypes.c_int), ("free_depth", ctypes.c_int),
+                ("max_depth", ctypes.c_int), ("gamma1_panels", ctypes.c_int),
+                ("contour_a", ctypes.c_double), ("tail_digits", ctypes.c_double),
+                ("components", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load_library():
+    """Loads liblmfmm.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("liblmfmm.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    D = P(ctypes.c_double)
+    vp = ctypes.c_void_p
+    lib.lm_default_params.argtypes = [P(lm_params)]
+    lib.lm_create.argtypes = [P(vp), ctypes.c_int]
+    lib.lm_destroy.argtypes = [vp]
+    lib.lm_last_error.argtypes = [vp]
+    lib.lm_last_error.restype = ctypes.c_char_p
+    lib.lm_set_layers.argtypes = [vp, ctypes.c_int, D, D, D]
+    lib.lm_set_params.argtypes = [vp, P(lm_params)]
+    lib.lm_build.argtypes = [vp, ctypes.c_int64, D, ctypes.c_int64, D, vp]
+    lib.lm_evaluate.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    lib.lm_stats.argtypes = [vp, D, ctypes.c_int]
+    lib.lm_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.lm_timings.argtypes = [vp, D, ctypes.c_int]
+    lib.lm_host_components.argtypes = [ctypes.c_int, D, D, P(ctypes.c_int), ctypes.c_int]
+    lib.lm_host_cheb_affine.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, D]
+    lib.lm_host_legendre_cheb.argtypes = [ctypes.c_int, D, P(ctypes.c_int)]
+    lib.lm_host_plan_stats.argtypes = [ctypes.c_int, D, D, P(lm_params), ctypes.c_int64, D, ctypes.c_int64,
+                                       D, D, ctypes.c_int, ctypes.c_char_p, ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _medium(d, k):
+    d = np.ascontiguousarray(np.asarray(d, dtype=np.float64).reshape(-1))
+    k = np.ascontiguousarray(np.asarray(k, dtype=np.float64).reshape(-1))
+    return (d if d.size else np.zeros(1)), k
+
+
+def make_params(**kw):
+    prm = lm_params()
+    load_library().lm_default_params(ctypes.byref(prm))
+    for key, v in kw.items():
+        if v is None:
+            continue
+        if not hasattr(prm, key):
+            raise TypeError("unknown parameter %s" % key)
+        setattr(prm, key, v)
+    return prm
+
+
+class LMError(RuntimeError):
+    pass
+
+
+class LayeredDyadicFMM:
+    """A = G J for the layered electric dyadic Green's function on one GPU.
+
+    d: interfaces (top to bottom), k: layer wavenumbers (top to bottom).
+    Keyword parameters are those of lm_params (p, p_free, free_depth, ...).
+    """
+
+    def __init__(self, d, k, device=0, **params):
+        self.lib = load_library()
+        self.ctx = ctypes.c_void_p()
+        rc = self.lib.lm_create(ctypes.byref(self.ctx), int(device))
+        if rc != LM_OK:
+            raise LMError("lm_create failed (%d)" % rc)
+        self.device = int(device)
+        self.d, self.k = _medium(d, k)
+        self._check(self.lib.lm_set_layers(self.ctx, self.k.size, _dp(self.d), _dp(self.k), None))
+        self.params = make_params(**params)
+        self._check(self.lib.lm_set_params(self.ctx, ctypes.byref(self.params)))
+        self.n_src = self.n_tgt = None
+
+    def _check(self, rc):
+        if rc != LM_OK:
+            msg = self.lib.lm_last_error(self.ctx)
+            raise LMError("lmfmm error %d: %s" % (rc, msg.decode() if msg else ""))
+
+    def build(self, src, tgt=None, stream=None):
+        import torch
+        src = np.ascontiguousarray(np.asarray(src, dtype=np.float64).reshape(-1, 3))
+        tgt = src if tgt is None else np.ascontiguousarray(np.asarray(tgt, dtype=np.float64).reshape(-1, 3))
+        if stream is None:
+            with torch.cuda.device(self.device):
+                stream = torch.cuda.current_stream().cuda_stream
+        self._check(self.lib.lm_build(self.ctx, src.shape[0], _dp(src), tgt.shape[0], _dp(tgt),
+                                      ctypes.c_void_p(stream)))
+        self.n_src, self.n_tgt = src.shape[0], tgt.shape[0]
+        return self
+
+    def evaluate(self, J, out=None, stream=None):
+        """J: complex128 CUDA tensor [n_src, 3] or [n_rhs, n_src, 3]; returns A (same rank)."""
+        import torch
+        if self.n_src is None:
+            raise LMError("build() must be called first")
+        if not (J.is_cuda and J.dtype == torch.complex128):
+            raise LMError("J must be a complex128 CUDA tensor")
+        single = J.dim() == 2
+        n_rhs = 1 if single else J.shape[0]
+        Jr = J.reshape(n_rhs, self.n_src, 3).contiguous()
+        if out is None:
+            out = torch.empty((n_rhs, self.n_tgt, 3), dtype=torch.complex128, device=J.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(J.device).cuda_stream
+        self._check(self.lib.lm_evaluate(self.ctx, n_rhs, ctypes.c_void_p(Jr.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)))
+        return out[0] if single else out
+
+    def stats(self):
+        buf = np.zeros(len(STAT_NAMES))
+        self._check(self.lib.lm_stats(self.ctx, _dp(buf), buf.size))
+        return dict(zip(STAT_NAMES, buf.tolist()))
+
+    def set_timing(self, enable=True):
+        self._check(self.lib.lm_set_timing(self.ctx, 1 if enable else 0))
+
+    def timings(self):
+        """Milliseconds per phase summed over the timed evaluations, and their count."""
+        buf = np.zeros(len(PHASE_NAMES) + 1)
+        self._check(self.lib.lm_timings(self.ctx, _dp(buf), buf.size))
+        return dict(zip(PHASE_NAMES, buf[:-1].tolist())), int(buf[-1])
+
+    def close(self):
+        if self.ctx:
+            self.lib.lm_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- host-only helpers
+def host_components(d, k):
+    lib = load_library()
+    d, k = _medium(d, k)
+    buf = (ctypes.c_int * (8 * 4096))()
+    n = lib.lm_host_components(k.size, _dp(d), _dp(k), buf, 4096)
+    if n < 0:
+        raise LMError("lm_host_components failed (%d)" % n)
+    return np.array(buf[:8 * n], dtype=np.int64).reshape(n, 8)
+
+
+def host_cheb_affine(jmax, a, b):
+    out = np.zeros((jmax + 1) * (jmax + 1))
+    rc = load_library().lm_host_cheb_affine(jmax, a, b, _dp(out))
+    if rc:
+        raise LMError("lm_host_cheb_affine failed")
+    return out.reshape(jmax + 1, jmax + 1)
+
+
+def host_legendre_cheb(p):
+    stride = ctypes.c_int()
+    out = np.zeros((p + 1) * (p + 2) // 2 * ((p + 1) // 2 + 2))
+    rc = load_library().lm_host_legendre_cheb(p, _dp(out), ctypes.byref(stride))
+    if rc:
+        raise LMError("lm_host_legendre_cheb failed")
+    return out.reshape(-1, stride.value)
+
+
+def host_plan_stats(d, k, src, tgt=None, **params):
+    lib = load_library()
+    d, k = _medium(d, k)
+    src = np.ascontiguousarray(np.asarray(src, dtype=np.float64).reshape(-1, 3))
+    tgt = src if tgt is None else np.ascontiguousarray(np.asarray(tgt, dtype=np.float64).reshape(-1, 3))
+    prm = make_params(**params)
+    out = np.zeros(len(STAT_NAMES))
+    err = ctypes.create_string_buffer(1024)
+    rc = lib.lm_host_plan_stats(k.size, _dp(d), _dp(k), ctypes.byref(prm), src.shape[0], _dp(src),
+                                tgt.shape[0], _dp(tgt), _dp(out), out.size, err, 1024)
+    if rc:
+        raise LMError("planning failed (%d): %s" % (rc, err.value.decode()))
+    return dict(zip(STAT_NAMES, out.tolist()))

@@ -1,0 +1,170 @@
+"""CPU tests of the library's host logic and of its C ABI (no GPU calls).
+
+Covers: the shared library loads and exports every function declared in
+include/lmfmm.h; the reaction-component enumeration (paper Sec. 3.1); the
+Chebyshev identities of Appendices A and B; the planner (trees, lists,
+refinement next to interfaces) and its error paths.
+"""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.special as sp
+
+from paper_2507_18491_amd import inputs, lmfmm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "lmfmm.h")).read()
+    names = set(re.findall(r"^(?:int|const char\*)\s+(lm_\w+)\s*\(", header, flags=re.M))
+    assert len(names) >= 12
+    lib = lmfmm.load_library()
+    for nm in sorted(names):
+        assert hasattr(lib, nm), nm
+
+
+@pytest.mark.parametrize("n_layers,count", [(1, 0), (2, 4), (3, 16), (4, 36), (5, 64)])
+def test_component_counts(n_layers, count):
+    d = -np.arange(n_layers - 1, dtype=float)
+    k = np.linspace(1.0, 2.0, n_layers)
+    c = lmfmm.host_components(d, k)
+    assert c.shape[0] == count
+    if n_layers >= 2:
+        # every valid (target layer, source layer) pair is present, and only
+        # directions with an interface on the corresponding side
+        L = n_layers - 1
+        for lt, ls, ut, us, sgn, at, as_, _ in c:
+            assert (ut and lt <= L - 1) or (not ut and lt >= 1)
+            assert (us and ls >= 1) or (not us and ls <= L - 1)
+            assert sgn in (1, -1) and at in (1, -1) and as_ in (1, -1)
+
+
+def test_three_layer_components_per_target_layer():
+    """Components per target layer (4, 8, 4): the middle layer carries twice
+    the reaction components of the outer ones, the 2:1 ratio of the
+    paper's three-layer timings (Sec. 4 table)."""
+    c = lmfmm.host_components([0.0, -1.5], [2.19, 1.79, 2.28])
+    per = [int((c[:, 0] == l).sum()) for l in range(3)]
+    assert per == [4, 8, 4]
+
+
+def test_component_signs_and_images_follow_the_paper():
+    """Same-layer reflection at the lower interface (target up, source down):
+    s = +1, image reflected, effective location identity (Sec. 3.1)."""
+    c = lmfmm.host_components([0.0], [1.0, 1.5])
+    row = [r for r in c if r[0] == 0 and r[1] == 0][0]
+    assert row[2] == 1 and row[3] == 0 and row[4] == 1 and row[5] == 1 and row[6] == -1
+    # transmission from layer 1 up to layer 0 (target above source): no
+    # reflection on either side and s = +1 (target layer index < source's)
+    row = [r for r in c if r[0] == 0 and r[1] == 1][0]
+    assert row[2] == 1 and row[3] == 1 and row[4] == 1 and row[5] == 1 and row[6] == 1
+    # the reverse transmission (target below source, both waves going down): s = -1
+    row = [r for r in c if r[0] == 1 and r[1] == 0][0]
+    assert row[2] == 0 and row[3] == 0 and row[4] == -1 and row[5] == 1 and row[6] == 1
+
+
+@pytest.mark.parametrize("a,b", [(0.49, 0.51), (0.36, 0.64), (1.0, 0.0), (0.8, 0.2)])
+def test_appendix_a_affine_chebyshev(a, b):
+    """T_j(a x + b) = sum_s C_js T_s(x) (Appendix A) against the closed form
+    T_j(y) = cos(j arccos y) on [-1, 1]."""
+    jmax = 18
+    C = lmfmm.host_cheb_affine(jmax, a, b)
+    x = np.linspace(-1, 1, 41)
+    Ts = np.array([np.cos(s * np.arccos(x)) for s in range(jmax + 1)])
+    y = np.clip(a * x + b, -1, 1)
+    for j in range(jmax + 1):
+        assert np.abs(C[j] @ Ts - np.cos(j * np.arccos(y))).max() < 5e-13
+    # the paper's low-order values: C_10 = b, C_21 = 4ab
+    assert abs(C[1, 0] - b) < 1e-15 and abs(C[2, 1] - 4 * a * b) < 1e-15
+
+
+def test_appendix_b_legendre_chebyshev():
+    """P^m_n(cos t) = tau_nm(t) sum_k B^k T_k(cos 2t) (Appendix B) against
+    scipy's orthonormal spherical harmonics, for all n, m <= 16."""
+    p = 16
+    B = lmfmm.host_legendre_cheb(p)
+    t = np.linspace(0.05, 1.5, 23)
+    for n in range(p + 1):
+        for m in range(n + 1):
+            ref = np.real(sp.sph_harm_y(n, m, t, 0.0))
+            if n % 2 == 0 and m % 2 == 0:
+                tau = np.ones_like(t)
+            elif n % 2 == 1 and m % 2 == 0:
+                tau = 1 / np.cos(t)
+            elif n % 2 == 1:
+                tau = np.sin(t)
+            else:
+                tau = np.tan(t)
+            K = n // 2 if n % 2 == 0 else ((n + 1) // 2 if m % 2 == 0 else (n - 1) // 2)
+            row = B[n * (n + 1) // 2 + m]
+            assert np.all(np.abs(row[K + 1:]) < 1e-14)
+            val = tau * sum(row[kk] * np.cos(2 * kk * t) for kk in range(K + 1))
+            assert np.abs(val - ref).max() < 5e-13 * max(1, np.abs(ref).max())
+
+
+def test_appendix_b_top_coefficient():
+    """Even n >= 2, even m: the leading coefficient B^{n/2}_{nm} equals the
+    closed form of Appendix B, (-1)^{m/2} Gamma(n+1/2)/pi sqrt((2n+1)/((n-m)!(n+m)!))
+    (the appendix's n = 0 value is twice the orthonormal one, so n = 0 is
+    excluded here)."""
+    p = 16
+    B = lmfmm.host_legendre_cheb(p)
+    for n in range(2, p + 1, 2):
+        for m in range(0, n + 1, 2):
+            ref = (-1) ** (m // 2) * math.gamma(n + 0.5) / math.pi * math.sqrt(
+                (2 * n + 1) / (math.factorial(n - m) * math.factorial(n + m)))
+            got = B[n * (n + 1) // 2 + m][n // 2]
+            assert abs(got - ref) < 1e-13 * max(1, abs(ref)), (n, m, got, ref)
+
+
+def test_plan_tiny_config():
+    d, k, x, _ = inputs.tiny()
+    s = lmfmm.host_plan_stats(d, k, x, p=8)
+    assert s["n_free_inst"] == 2 and s["n_react_inst"] == 4
+    assert s["free_depth"] == 2           # the tiny workload's octree depth
+    assert s["m2l_pairs_react"] > 0 and s["n_cases"] > 0 and s["p2p_pairs"] > 0
+    # near field covers at least every same-box pair
+    assert s["p2p_pairs"] >= 600
+
+
+def test_plan_three_layer_small():
+    d, k, x, _ = inputs.three_layer(20000)
+    s = lmfmm.host_plan_stats(d, k, x, p=12)
+    assert s["n_free_inst"] == 3 and s["n_react_inst"] == 16
+    # every reaction interaction is an M2L (boxes next to the interfaces are
+    # refined until no adjacent source/target boxes remain): planning succeeds
+    assert s["m2l_pairs_react"] > 0
+
+
+def test_plan_rejects_point_on_interface():
+    d, k, x, _ = inputs.tiny()
+    x = x.copy()
+    x[3, 2] = 0.0
+    with pytest.raises(lmfmm.LMError):
+        lmfmm.host_plan_stats(d, k, x, p=8)
+
+
+def test_plan_rejects_points_too_close_to_interface():
+    d, k, x, _ = inputs.tiny()
+    x = x.copy()
+    x[3, 2] = 1e-7
+    x[400, 2] = -1e-7
+    with pytest.raises(lmfmm.LMError, match="too close"):
+        lmfmm.host_plan_stats(d, k, x, p=8, max_depth=10)
+
+
+@pytest.mark.parametrize("d,k", [([0.0, 0.5], [1, 2, 3]), ([0.0], [1.0, -1.0]), ([0.0], [1.0, float("nan")])])
+def test_plan_rejects_bad_medium(d, k):
+    x = np.array([[0.0, 0.0, 0.5], [0.1, 0.0, -0.5]])
+    with pytest.raises(lmfmm.LMError):
+        lmfmm.host_plan_stats(d, k, x, p=4)
+
+
+def test_plan_rejects_bad_order():
+    x = np.array([[0.0, 0.0, 0.5], [0.1, 0.0, -0.5]])
+    with pytest.raises(lmfmm.LMError):
+        lmfmm.host_plan_stats([0.0], [1.0, 1.5], x, p=21)
