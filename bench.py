@@ -59,7 +59,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1000000)
     ap.add_argument("--p", type=int, default=12)
-    ap.add_argument("--p-free", type=int, default=0)
+    ap.add_argument("--p-free", type=int, default=20)
     ap.add_argument("--rhs", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
@@ -129,7 +129,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "three-layer dyadic FMM, N=%d uniform in layer slabs, targets=sources, "
-                               "p=%d, %d complex128 current vector(s)" % (args.n, args.p, args.rhs),
+                               "p=%d (free-space part p=%d), %d complex128 current vector(s)" % (args.n, args.p, args.p_free or args.p, args.rhs),
                    "n": args.n, "p": args.p, "p_free": args.p_free or args.p, "layers": 3, "n_rhs": args.rhs},
         "roofline": {"bound": "alu", "kernel": "k_m2l", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,

@@ -34,9 +34,19 @@ struct lm_ctx {
   cd* ME = nullptr;
   cd* LE = nullptr;
   long long me_cap = 0, le_cap = 0;
-  int tiles_rhs = -1;
-  int n_tiles = 0;
-  M2LTile* d_tiles = nullptr;
+  struct Chunk {
+    int tile0, ntile, bt0, nbt;
+  };
+  struct TileSet {            // M2L schedule for one right-hand-side count
+    M2LTile* d_tiles = nullptr;
+    long long* d_ybase = nullptr;
+    std::vector<Chunk> chunks;
+    int n_tiles = 0;
+    long long y_need = 0;     // scratch elements
+  };
+  std::map<int, TileSet> tilesets;
+  cd* Y = nullptr;           // M2L scratch
+  long long y_cap = 0;
   double t_plan_ms = 0, t_upload_ms = 0, t_tables_ms = 0;
   int pmax = 0;
   bool timing = false;
@@ -66,11 +76,16 @@ static void free_build(lm_ctx* ctx) {
   ctx->allocs.clear();
   if (ctx->ME) hipFree(ctx->ME);
   if (ctx->LE) hipFree(ctx->LE);
-  if (ctx->d_tiles) hipFree(ctx->d_tiles);
+  for (auto& kv : ctx->tilesets) {
+    if (kv.second.d_tiles) hipFree(kv.second.d_tiles);
+    if (kv.second.d_ybase) hipFree(kv.second.d_ybase);
+  }
+  ctx->tilesets.clear();
+  if (ctx->Y) hipFree(ctx->Y);
+  ctx->Y = nullptr;
+  ctx->y_cap = 0;
   ctx->ME = ctx->LE = nullptr;
-  ctx->d_tiles = nullptr;
   ctx->me_cap = ctx->le_cap = 0;
-  ctx->tiles_rhs = -1;
   ctx->d_m2m.clear();
   ctx->d_l2l.clear();
   ctx->d_l2p.clear();
@@ -245,6 +260,13 @@ int lm_build(lm_ctx* ctx, int64_t n_src, const double* src_xyz, int64_t n_tgt, c
   if ((rc = upload(ctx, &d.cls_tgt, pl.cls_tgt))) return rc;
   if ((rc = upload(ctx, &d.cls_srcof, pl.cls_srcof))) return rc;
   if ((rc = upload(ctx, &d.cls_srcof0, pl.cls_srcof0))) return rc;
+  if ((rc = upload(ctx, &d.blocks, pl.blocks))) return rc;
+  if ((rc = upload(ctx, &d.bt_tbox, pl.bt_tbox))) return rc;
+  if ((rc = upload(ctx, &d.bt_ptr, pl.bt_ptr))) return rc;
+  if ((rc = upload(ctx, &d.bt_pairs, pl.bt_pairs))) return rc;
+  if ((rc = upload(ctx, &d.pair_src, pl.pair_src))) return rc;
+  if ((rc = upload(ctx, &d.offr, pl.offr))) return rc;
+  if ((rc = upload(ctx, &d.bt_blk, pl.bt_blk))) return rc;
   if ((rc = upload(ctx, &d.gaunt, pl.gaunt))) return rc;
   d.gaunt_p = pl.gaunt_p;
   if ((rc = upload(ctx, &d.Bcoef, pl.Bcoef))) return rc;
@@ -353,9 +375,20 @@ int lm_build(lm_ctx* ctx, int64_t n_src, const double* src_xyz, int64_t n_tgt, c
   return LM_OK;
 }
 
-static int ensure_rhs(lm_ctx* ctx, int n_rhs) {
+// Work buffers and the M2L schedule for n_rhs right-hand sides.  Anything
+// that must be (re)allocated is done after the stream has drained, so no
+// buffer used by queued kernels is freed or overwritten.
+static int ensure_rhs(lm_ctx* ctx, int n_rhs, hipStream_t s) {
   Plan& pl = ctx->plan;
   long long me = pl.me_size * n_rhs, le = pl.le_size * n_rhs;
+  bool have = ctx->tilesets.count(n_rhs) > 0;
+  if (me <= ctx->me_cap && le <= ctx->le_cap && have && ctx->tilesets[n_rhs].y_need <= ctx->y_cap) {
+    lm_ctx::TileSet& ts = ctx->tilesets[n_rhs];
+    ctx->d.tiles = ts.d_tiles;
+    ctx->d.blk_ybase = ts.d_ybase;
+    return LM_OK;
+  }
+  HIPC(hipStreamSynchronize(s));
   if (me > ctx->me_cap) {
     if (ctx->ME) hipFree(ctx->ME);
     ctx->ME = nullptr;
@@ -368,35 +401,76 @@ static int ensure_rhs(lm_ctx* ctx, int n_rhs) {
     HIPC(hipMalloc((void**)&ctx->LE, (size_t)std::max(1LL, le) * sizeof(cd)));
     ctx->le_cap = le;
   }
-  if (ctx->tiles_rhs != n_rhs) {
+  if (!have) {
+    // chunks of whole blocks whose M2L outputs fit the scratch budget;
+    // each block gets its own scratch base (blocks differ in P)
+    const long long budget = 6LL << 30;  // bytes
+    lm_ctx::TileSet ts;
     std::vector<M2LTile> tiles;
-    for (int c = 0; c < (int)pl.cls.size(); c++) {
-      const M2LClass& C = pl.cls[c];
-      int ncol = C.n_tgt * n_rhs;
-      for (int ot = 0; ot < 3; ot++)
-        for (int r0 = 0; r0 < C.P; r0 += TM_ROWS)
-          for (int c0 = 0; c0 < ncol; c0 += TN_COLS) {
-            M2LTile t;
-            t.cls = c;
-            t.out_type = ot;
-            t.col0 = c0;
-            t.ncol = std::min(TN_COLS, ncol - c0);
-            t.row0 = r0;
-            tiles.push_back(t);
-          }
+    std::vector<long long> ybase(std::max<size_t>(1, pl.blocks.size()), 0);
+    long long need_max = 0;
+    size_t bi = 0;
+    while (bi < pl.blocks.size()) {
+      lm_ctx::Chunk ch;
+      ch.tile0 = (int)tiles.size();
+      ch.bt0 = pl.blocks[bi].bt0;
+      ch.nbt = 0;
+      long long bytes = 0;
+      while (bi < pl.blocks.size()) {
+        const M2LBlock& B = pl.blocks[bi];
+        const M2LClass& C = pl.cls[B.cls];
+        long long bb = (long long)B.nq * 3 * n_rhs * C.P * (long long)sizeof(cd);
+        if (ch.nbt > 0 && bytes + bb > budget) break;
+        ybase[bi] = bytes / (long long)sizeof(cd);
+        bytes += bb;
+        for (int o = 0; o < C.n_off; o++) {
+          int np = pl.offr[B.offr0 + o + 1] - pl.offr[B.offr0 + o];
+          int ncol = np * n_rhs;
+          for (int ot = 0; ot < 3; ot++)
+            for (int r0 = 0; r0 < C.P; r0 += TM_ROWS)
+              for (int c0 = 0; c0 < ncol; c0 += TN_COLS) {
+                M2LTile t;
+                t.blk = (int)bi;
+                t.off = o;
+                t.out_type = ot;
+                t.row0 = r0;
+                t.col0 = c0;
+                t.ncol = std::min(TN_COLS, ncol - c0);
+                tiles.push_back(t);
+              }
+        }
+        ch.nbt += B.nt;
+        bi++;
+      }
+      ch.ntile = (int)tiles.size() - ch.tile0;
+      need_max = std::max(need_max, bytes);
+      ts.chunks.push_back(ch);
     }
-    if (ctx->d_tiles) hipFree(ctx->d_tiles);
-    ctx->d_tiles = nullptr;
     if (!tiles.empty()) {
-      HIPC(hipMalloc((void**)&ctx->d_tiles, tiles.size() * sizeof(M2LTile)));
-      HIPC(hipMemcpy(ctx->d_tiles, tiles.data(), tiles.size() * sizeof(M2LTile), hipMemcpyHostToDevice));
+      HIPC(hipMalloc((void**)&ts.d_tiles, tiles.size() * sizeof(M2LTile)));
+      HIPC(hipMemcpy(ts.d_tiles, tiles.data(), tiles.size() * sizeof(M2LTile), hipMemcpyHostToDevice));
     }
-    ctx->n_tiles = (int)tiles.size();
-    ctx->tiles_rhs = n_rhs;
+    HIPC(hipMalloc((void**)&ts.d_ybase, ybase.size() * sizeof(long long)));
+    HIPC(hipMemcpy(ts.d_ybase, ybase.data(), ybase.size() * sizeof(long long), hipMemcpyHostToDevice));
+    ts.n_tiles = (int)tiles.size();
+    ts.y_need = need_max / (long long)sizeof(cd);
+    ctx->tilesets[n_rhs] = ts;
   }
-  ctx->d.tiles = ctx->d_tiles;
+  lm_ctx::TileSet& ts = ctx->tilesets[n_rhs];
+  if (ts.y_need > ctx->y_cap) {
+    if (ctx->Y) hipFree(ctx->Y);
+    ctx->Y = nullptr;
+    HIPC(hipMalloc((void**)&ctx->Y, (size_t)std::max(1LL, ts.y_need) * sizeof(cd)));
+    ctx->y_cap = ts.y_need;
+  }
+  ctx->d.tiles = ts.d_tiles;
+  ctx->d.blk_ybase = ts.d_ybase;
   return LM_OK;
 }
+
+static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream);
+
+#define LM_RHS_CHUNK 16
 
 int lm_evaluate(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream) {
   if (!ctx) return LM_EINVAL;
@@ -405,9 +479,26 @@ int lm_evaluate(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream) {
   Plan& pl = ctx->plan;
   if ((pl.n_src > 0 && !J) || (pl.n_tgt > 0 && !A)) return fail(ctx, LM_EINVAL, "null J or A");
   if (((uintptr_t)J % 16) || ((uintptr_t)A % 16)) return fail(ctx, LM_EINVAL, "J and A must be 16-byte aligned");
+  for (int r0 = 0; r0 < n_rhs; r0 += LM_RHS_CHUNK) {
+    int nr = std::min(LM_RHS_CHUNK, n_rhs - r0);
+    const cd* Jc = J ? (const cd*)J + (long long)r0 * pl.n_src * 3 : nullptr;
+    cd* Ac = A ? (cd*)A + (long long)r0 * pl.n_tgt * 3 : nullptr;
+    int rc = evaluate_chunk(ctx, nr, Jc, Ac, stream);
+    if (rc) return rc;
+  }
+  return LM_OK;
+}
+
+static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream) {
+  if (!ctx) return LM_EINVAL;
+  if (!ctx->built) return fail(ctx, LM_ESTATE, "lm_build must succeed before lm_evaluate");
+  if (n_rhs < 1 || n_rhs > 4096) return fail(ctx, LM_EINVAL, "n_rhs out of range (1..4096)");
+  Plan& pl = ctx->plan;
+  if ((pl.n_src > 0 && !J) || (pl.n_tgt > 0 && !A)) return fail(ctx, LM_EINVAL, "null J or A");
+  if (((uintptr_t)J % 16) || ((uintptr_t)A % 16)) return fail(ctx, LM_EINVAL, "J and A must be 16-byte aligned");
   HIPC(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
-  int rc = ensure_rhs(ctx, n_rhs);
+  int rc = ensure_rhs(ctx, n_rhs, s);
   if (rc) return rc;
   const cd* Jc = (const cd*)J;
   cd* Ac = (cd*)A;
@@ -430,7 +521,10 @@ int lm_evaluate(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream) {
     for (int l = (int)ctx->d_m2m.size() - 1; l >= 0; l--)
       launch_m2m(d, ctx->d_m2m[l], ctx->n_m2m[l], n_rhs, ctx->ME, ctx->pmax, s);
     mark(3);
-    launch_m2l(d, ctx->n_tiles, n_rhs, ctx->ME, ctx->LE, ctx->pmax, s);
+    for (auto& ch : ctx->tilesets[n_rhs].chunks) {
+      launch_m2l(d, d.tiles + ch.tile0, ch.ntile, n_rhs, ctx->ME, ctx->Y, ctx->pmax, s);
+      launch_m2l_reduce(d, ch.bt0, ch.nbt, n_rhs, ctx->Y, ctx->LE, ctx->pmax, s);
+    }
     mark(4);
     for (int l = 1; l < (int)ctx->d_l2l.size(); l++)
       launch_l2l(d, ctx->d_l2l[l], ctx->n_l2l[l], n_rhs, ctx->LE, ctx->pmax, s);
@@ -506,17 +600,19 @@ int lm_stats(const lm_ctx* ctx, double* out, int n) {
     v[LM_STAT_N_M2L_TILES_1RHS] = (double)t;
   }
   {
-    // dense M2L work (complex multiply-adds) per right-hand side, including
-    // the zero columns of absent sources inside a class
+    // M2L work (complex multiply-adds) per right-hand side: useful (one
+    // P x nblk*P product per pair and output type) and as executed by the
+    // 64 x 64 GEMM tiles (padding of partial tiles included)
     double cm = 0, ce = 0;
-    for (size_t c = 0; c < pl.cls.size(); c++) {
-      const M2LClass& C = pl.cls[c];
-      double per = 3.0 * C.P * (double)(C.nblk * C.P);
-      ce += per * C.n_tgt * C.n_off;
-      long long base = pl.cls_srcof0[c];
-      long long used = 0;
-      for (long long e = 0; e < (long long)C.n_tgt * C.n_off; e++) used += pl.cls_srcof[base + e] >= 0;
-      cm += per * used;
+    for (const M2LBlock& B : pl.blocks) {
+      const M2LClass& C = pl.cls[B.cls];
+      double K = (double)C.nblk * C.P;
+      double rows = (double)((C.P + TM_ROWS - 1) / TM_ROWS) * TM_ROWS;
+      for (int o = 0; o < C.n_off; o++) {
+        int np = pl.offr[B.offr0 + o + 1] - pl.offr[B.offr0 + o];
+        cm += 3.0 * C.P * K * np;
+        ce += 3.0 * rows * K * (double)((np + TN_COLS - 1) / TN_COLS) * TN_COLS;
+      }
     }
     v[LM_STAT_M2L_CMAC_USEFUL] = cm;
     v[LM_STAT_M2L_CMAC_EXEC] = ce;

@@ -24,6 +24,14 @@ struct DevPlan {
   int* cls_srcof;
   long long* cls_srcof0;
   M2LTile* tiles;
+  M2LBlock* blocks;
+  int* bt_tbox;
+  int* bt_ptr;
+  int* bt_pairs;
+  int* pair_src;
+  int* offr;
+  int* bt_blk;          // block of each block-target
+  long long* blk_ybase; // per block: first scratch element (depends on the rhs count)
   cd* mats;        // all translation / M2L matrices
   double* gaunt;
   int gaunt_p;
@@ -46,7 +54,10 @@ void launch_tab_assemble(const DevPlan& d, int case0, int ncase, int p, int kmax
 void launch_p2m(const DevPlan& d, const int* leaves, int n, const double* xyz, const cd* J,
                 long long n_src, int n_rhs, cd* ME, int pmax, hipStream_t s);
 void launch_m2m(const DevPlan& d, const int* parents, int n, int n_rhs, cd* ME, int pmax, hipStream_t s);
-void launch_m2l(const DevPlan& d, int n_tiles, int n_rhs, const cd* ME, cd* LE, int pmax, hipStream_t s);
+void launch_m2l(const DevPlan& d, const M2LTile* tiles, int n_tiles, int n_rhs, const cd* ME, cd* Y, int pmax,
+                hipStream_t s);
+void launch_m2l_reduce(const DevPlan& d, int bt0, int nbt, int n_rhs, const cd* Y, cd* LE, int pmax,
+                       hipStream_t s);
 void launch_l2l(const DevPlan& d, const int* children, int n, int n_rhs, cd* LE, int pmax, hipStream_t s);
 void launch_l2p(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_tgt,
                 int n_rhs, const cd* LE, cd* A, int pmax, hipStream_t s);

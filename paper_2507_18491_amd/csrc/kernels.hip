@@ -13,7 +13,7 @@
 
 #include "kernels.h"
 
-#define RC 4            // right-hand sides per block in the point/translation passes
+// RC (template parameter): right-hand sides per block in the point/translation passes (1 or 4)
 #define NT 256          // threads per block
 
 __device__ inline int n_of(int nm) {
@@ -41,6 +41,7 @@ void launch_fill(cd* p, long long n, hipStream_t s) {
 // (paper Sec. 2, the multipole coefficients, and Sec. 3.3, the reaction ME
 // coefficients; the constant 4 pi lives in the M2L tables).
 #define P2M_NPT 32
+template <int RC>
 __global__ __launch_bounds__(NT) void k_p2m(DevPlan d, const int* leaves, const double* xyz, const cd* J,
                                             long long n_src, int n_rhs, cd* ME) {
   extern __shared__ double sm[];
@@ -123,15 +124,21 @@ void launch_p2m(const DevPlan& d, const int* leaves, int n, const double* xyz, c
                 int n_rhs, cd* ME, int pmax, hipStream_t s) {
   if (n <= 0) return;
   int ntri = (pmax + 1) * (pmax + 2) / 2;
-  size_t shm = (size_t)P2M_NPT * ((pmax + 1) + ntri + 2 * (pmax + 1) + RC * 6) * sizeof(double);
-  hipFuncSetAttribute((const void*)k_p2m, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL(k_p2m, dim3(n, (n_rhs + RC - 1) / RC), dim3(NT), shm, s, d, leaves, xyz, J, n_src,
-                     n_rhs, ME);
+  int rc = n_rhs == 1 ? 1 : 4;
+  size_t shm = (size_t)P2M_NPT * ((pmax + 1) + ntri + 2 * (pmax + 1) + rc * 6) * sizeof(double);
+  if (rc == 1) {
+    hipFuncSetAttribute((const void*)k_p2m<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k_p2m<1>, dim3(n, n_rhs), dim3(NT), shm, s, d, leaves, xyz, J, n_src, n_rhs, ME);
+  } else {
+    hipFuncSetAttribute((const void*)k_p2m<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k_p2m<4>, dim3(n, (n_rhs + 3) / 4), dim3(NT), shm, s, d, leaves, xyz, J, n_src, n_rhs, ME);
+  }
 }
 
 // ------------------------------------------------------------------ M2M
 // ME_parent[nm] = sum_children sum_{nu mu} Mat_child[nu mu][nm] ME_child[nu mu]
 // (regular-to-regular shift, paper Sec. 2; identical for reaction components, Sec. 3.3)
+template <int RC>
 __global__ __launch_bounds__(NT) void k_m2m(DevPlan d, const int* parents, int n_rhs, cd* ME) {
   extern __shared__ cd xs[];
   int pb = parents[blockIdx.x];
@@ -170,13 +177,20 @@ __global__ __launch_bounds__(NT) void k_m2m(DevPlan d, const int* parents, int n
 void launch_m2m(const DevPlan& d, const int* parents, int n, int n_rhs, cd* ME, int pmax, hipStream_t s) {
   if (n <= 0) return;
   int P = (pmax + 1) * (pmax + 1);
-  hipFuncSetAttribute((const void*)k_m2m, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(RC * 3 * P * sizeof(cd)));
-  hipLaunchKernelGGL(k_m2m, dim3(n, (n_rhs + RC - 1) / RC), dim3(NT), (size_t)RC * 3 * P * sizeof(cd), s, d,
-                     parents, n_rhs, ME);
+  int rc = n_rhs == 1 ? 1 : 4;
+  size_t shm = (size_t)rc * 3 * P * sizeof(cd);
+  if (rc == 1) {
+    hipFuncSetAttribute((const void*)k_m2m<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k_m2m<1>, dim3(n, n_rhs), dim3(NT), shm, s, d, parents, n_rhs, ME);
+  } else {
+    hipFuncSetAttribute((const void*)k_m2m<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k_m2m<4>, dim3(n, (n_rhs + 3) / 4), dim3(NT), shm, s, d, parents, n_rhs, ME);
+  }
 }
 
 // ------------------------------------------------------------------ L2L
 // LE_child[nm] += sum_{nu mu} Mat[nu mu][nm] LE_parent[nu mu]
+template <int RC>
 __global__ __launch_bounds__(NT) void k_l2l(DevPlan d, const int* children, int n_rhs, cd* LE) {
   extern __shared__ cd xs[];
   int cb = children[blockIdx.x];
@@ -210,34 +224,41 @@ __global__ __launch_bounds__(NT) void k_l2l(DevPlan d, const int* children, int 
 void launch_l2l(const DevPlan& d, const int* children, int n, int n_rhs, cd* LE, int pmax, hipStream_t s) {
   if (n <= 0) return;
   int P = (pmax + 1) * (pmax + 1);
-  hipFuncSetAttribute((const void*)k_l2l, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(RC * 3 * P * sizeof(cd)));
-  hipLaunchKernelGGL(k_l2l, dim3(n, (n_rhs + RC - 1) / RC), dim3(NT), (size_t)RC * 3 * P * sizeof(cd), s, d,
-                     children, n_rhs, LE);
+  int rc = n_rhs == 1 ? 1 : 4;
+  size_t shm = (size_t)rc * 3 * P * sizeof(cd);
+  if (rc == 1) {
+    hipFuncSetAttribute((const void*)k_l2l<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k_l2l<1>, dim3(n, n_rhs), dim3(NT), shm, s, d, children, n_rhs, LE);
+  } else {
+    hipFuncSetAttribute((const void*)k_l2l<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k_l2l<4>, dim3(n, (n_rhs + 3) / 4), dim3(NT), shm, s, d, children, n_rhs, LE);
+  }
 }
 
 // ------------------------------------------------------------------ M2L
-// Tiled complex GEMM per class: for every target box t and offset o of the
-// class,  LE_t[out] += e^{-i m phi_o} A_o[out] X_{t,o},  where X_{t,o} stacks
-// the source box's channel vectors multiplied by e^{i (kappa + mu) phi_o}
-// (reaction: the three-block spin-basis form of the M2L tensor, Sec. 3.3;
-// free space: one block, phi = 0).
+// Tiled complex GEMM, one tile per (block, offset o, output type, row tile,
+// 64 (pair, rhs) columns):  Y_q[out] = e^{-i m phi_o} A_o[out] X_q,  where
+// X_q stacks the source box's channel vectors multiplied by
+// e^{i (kappa + mu) phi_o} (reaction: the three-block spin-basis form of the
+// M2L tensor, Sec. 3.3; free space: one block, phi = 0).  Only pairs whose
+// source box exists are columns.  Y is a scratch buffer; a second kernel
+// adds, per target, its pairs in a fixed order (no atomics).
 #define TM 64
 #define TN 64
 #define KC 16
-__global__ __launch_bounds__(NT) void k_m2l(DevPlan d, int n_rhs, const cd* ME, cd* LE) {
+__global__ __launch_bounds__(NT) void k_m2l(DevPlan d, const M2LTile* tiles, int n_rhs, const cd* ME, cd* Y) {
   __shared__ cd As[TM][KC + 1];
   __shared__ cd Bs[KC][TN + 1];
   __shared__ long long sbase[TN];
   __shared__ cd eph[2 * LM_PMAX + 8];
   __shared__ short mu_of[(LM_PMAX + 1) * (LM_PMAX + 1)];
-  __shared__ int anyv;
-  M2LTile tl = d.tiles[blockIdx.x];
-  M2LClass C = d.cls[tl.cls];
+  M2LTile tl = tiles[blockIdx.x];
+  M2LBlock B = d.blocks[tl.blk];
+  M2LClass C = d.cls[B.cls];
   InstParams ip = d.inst[C.inst];
   int P = C.P, p = ip.p, nblk = C.nblk, K = nblk * P;
   int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
   int ot = tl.out_type;
-  // per-block input recipe (source channel, kappa)
   int rch[3], rkap[3];
   if (nblk == 1) {
     rch[0] = ot;
@@ -249,96 +270,107 @@ __global__ __launch_bounds__(NT) void k_m2l(DevPlan d, int n_rhs, const cd* ME, 
   } else {
     rch[0] = 1; rkap[0] = 1; rch[1] = 0; rkap[1] = -1; rch[2] = 2; rkap[2] = 0;
   }
+  bool phased = (nblk == 3);
+  M2LOffset off = d.offs[C.off0 + tl.off];
+  int qo = d.offr[B.offr0 + tl.off];  // first pair of this offset
   for (int e = tid; e < P; e += NT) {
     int n = n_of(e);
     mu_of[e] = (short)(e - n * n - n);
   }
-  bool phased = (nblk == 3);
+  if (tid < TN) {
+    long long v = -1;
+    if (tid < tl.ncol) {
+      int j = tl.col0 + tid;
+      int q = qo + j / n_rhs, r = j % n_rhs;
+      v = d.sbox[d.pair_src[q]].me_off * n_rhs + (long long)r * 3 * P;
+    }
+    sbase[tid] = v;
+  }
+  if (tid < 2 * p + 5) {
+    double a = (tid - (p + 2)) * off.phi;
+    eph[tid] = cd{cos(a), sin(a)};
+  }
+  __syncthreads();
   cd acc[4][4];
   for (int i = 0; i < 4; i++)
     for (int j = 0; j < 4; j++) acc[i][j] = cd{0, 0};
-  long long srcof0 = d.cls_srcof0[tl.cls];
-  for (int o = 0; o < C.n_off; o++) {
-    M2LOffset off = d.offs[C.off0 + o];
-    __syncthreads();
-    if (tid == 0) anyv = 0;
-    __syncthreads();
-    if (tid < TN) {
-      long long v = -1;
-      if (tid < tl.ncol) {
-        int j = tl.col0 + tid;
-        int ts = j / n_rhs, r = j - ts * n_rhs;
-        int sbx = d.cls_srcof[srcof0 + (long long)ts * C.n_off + o];
-        if (sbx >= 0) {
-          v = d.sbox[sbx].me_off * n_rhs + (long long)r * 3 * P;
-          anyv = 1;
-        }
-      }
-      sbase[tid] = v;
+  const cd* A = d.mats + off.mat[ot];
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    for (int e = tid; e < TM * KC; e += NT) {
+      int rr = e / KC, kk = e - rr * KC;
+      int row = tl.row0 + rr, k = k0 + kk;
+      As[rr][kk] = (row < P && k < K) ? A[(long long)row * K + k] : cd{0, 0};
     }
-    if (tid < 2 * p + 5) {
-      double a = (tid - (p + 2)) * off.phi;
-      eph[tid] = cd{cos(a), sin(a)};
+    for (int e = tid; e < KC * TN; e += NT) {
+      int cc = e / KC, kk = e - cc * KC;
+      int k = k0 + kk;
+      cd v = cd{0, 0};
+      long long sbb = sbase[cc];
+      if (sbb >= 0 && k < K) {
+        int bl = k / P, num = k - bl * P;
+        v = ME[sbb + (long long)rch[bl] * P + num];
+        if (phased) v = v * eph[rkap[bl] + mu_of[num] + p + 2];
+      }
+      Bs[kk][cc] = v;
     }
     __syncthreads();
-    if (!anyv) continue;
-    cd tmp[4][4];
-    for (int i = 0; i < 4; i++)
-      for (int j = 0; j < 4; j++) tmp[i][j] = cd{0, 0};
-    const cd* A = d.mats + off.mat[ot];
-    for (int k0 = 0; k0 < K; k0 += KC) {
-      for (int e = tid; e < TM * KC; e += NT) {
-        int rr = e / KC, kk = e - rr * KC;
-        int row = tl.row0 + rr, k = k0 + kk;
-        As[rr][kk] = (row < P && k < K) ? A[(long long)row * K + k] : cd{0, 0};
-      }
-      for (int e = tid; e < KC * TN; e += NT) {
-        int cc = e / KC, kk = e - cc * KC;
-        int k = k0 + kk;
-        cd v = cd{0, 0};
-        long long sbb = sbase[cc];
-        if (sbb >= 0 && k < K) {
-          int bl = k / P, num = k - bl * P;
-          v = ME[sbb + (long long)rch[bl] * P + num];
-          if (phased) v = v * eph[rkap[bl] + mu_of[num] + p + 2];
-        }
-        Bs[kk][cc] = v;
-      }
-      __syncthreads();
 #pragma unroll 4
-      for (int kk = 0; kk < KC; kk++) {
-        cd a[4], bb[4];
-        for (int i = 0; i < 4; i++) a[i] = As[tr * 4 + i][kk];
-        for (int j = 0; j < 4; j++) bb[j] = Bs[kk][tc * 4 + j];
-        for (int i = 0; i < 4; i++)
-          for (int j = 0; j < 4; j++) tmp[i][j] = tmp[i][j] + a[i] * bb[j];
-      }
-      __syncthreads();
+    for (int kk = 0; kk < KC; kk++) {
+      cd a[4], bb[4];
+      for (int i = 0; i < 4; i++) a[i] = As[tr * 4 + i][kk];
+      for (int j = 0; j < 4; j++) bb[j] = Bs[kk][tc * 4 + j];
+      for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 4; j++) acc[i][j] = acc[i][j] + a[i] * bb[j];
     }
-    for (int i = 0; i < 4; i++) {
-      int row = tl.row0 + tr * 4 + i;
-      cd ph = cd{1, 0};
-      if (phased && row < P) ph = cconj(eph[mu_of[row] + p + 2]);
-      for (int j = 0; j < 4; j++) acc[i][j] = acc[i][j] + ph * tmp[i][j];
-    }
+    __syncthreads();
   }
   for (int j = 0; j < 4; j++) {
     int col = tc * 4 + j;
     if (col >= tl.ncol) continue;
     int jj = tl.col0 + col;
-    int ts = jj / n_rhs, r = jj - ts * n_rhs;
-    TgtBox tb = d.tbox[d.cls_tgt[C.tgt0 + ts]];
+    int q = qo + jj / n_rhs, r = jj % n_rhs;
+    // scratch slot: per-block base (blocks of one chunk may have different P)
+    cd* Yq = Y + d.blk_ybase[tl.blk] + ((long long)((q - B.q0) * 3 + ot) * n_rhs + r) * P;
     for (int i = 0; i < 4; i++) {
       int row = tl.row0 + tr * 4 + i;
       if (row >= P) continue;
-      long long idx = tb.le_off * n_rhs + ((long long)r * 3 + ot) * P + row;
-      LE[idx] = LE[idx] + acc[i][j];
+      cd ph = phased ? cconj(eph[mu_of[row] + p + 2]) : cd{1, 0};
+      Yq[row] = ph * acc[i][j];
     }
   }
 }
-void launch_m2l(const DevPlan& d, int n_tiles, int n_rhs, const cd* ME, cd* LE, int pmax, hipStream_t s) {
+void launch_m2l(const DevPlan& d, const M2LTile* tiles, int n_tiles, int n_rhs, const cd* ME, cd* Y, int pmax,
+                hipStream_t s) {
   if (n_tiles <= 0) return;
-  hipLaunchKernelGGL(k_m2l, dim3(n_tiles), dim3(NT), 0, s, d, n_rhs, ME, LE);
+  hipLaunchKernelGGL(k_m2l, dim3(n_tiles), dim3(NT), 0, s, d, tiles, n_rhs, ME, Y);
+}
+
+// LE_t[out][rhs] += sum over the target's pairs (fixed offset order) of Y
+__global__ __launch_bounds__(NT) void k_m2l_reduce(DevPlan d, int bt0, int n_rhs, const cd* Y, cd* LE) {
+  int bt = bt0 + blockIdx.x;
+  TgtBox tb = d.tbox[d.bt_tbox[bt]];
+  int P = d.inst[tb.inst].P;
+  int blk = d.bt_blk[bt];
+  long long ybase = d.blk_ybase[blk];
+  int qb = d.blocks[blk].q0;
+  int q0 = d.bt_ptr[bt], q1 = d.bt_ptr[bt + 1];
+  int nel = 3 * n_rhs * P;
+  for (int e = threadIdx.x; e < nel; e += NT) {
+    int tr_ = e / P, row = e - tr_ * P;   // tr_ = ot * n_rhs + r
+    int ot = tr_ / n_rhs, r = tr_ - ot * n_rhs;
+    cd s = cd{0, 0};
+    for (int qi = q0; qi < q1; qi++) {
+      int q = d.bt_pairs[qi];
+      s = s + Y[ybase + ((long long)(q - qb) * 3 * n_rhs + tr_) * P + row];
+    }
+    long long idx = tb.le_off * n_rhs + ((long long)r * 3 + ot) * P + row;
+    LE[idx] = LE[idx] + s;
+  }
+}
+void launch_m2l_reduce(const DevPlan& d, int bt0, int nbt, int n_rhs, const cd* Y, cd* LE, int pmax,
+                       hipStream_t s) {
+  if (nbt <= 0) return;
+  hipLaunchKernelGGL(k_m2l_reduce, dim3(nbt), dim3(NT), 0, s, d, bt0, n_rhs, Y, LE);
 }
 
 // ------------------------------------------------------------------ L2P
@@ -381,6 +413,7 @@ __device__ inline cd dapply(const cd* c, int oi, int dir, int n, int m) {
   return -1.0 * v;
 }
 
+template <int RC>
 __global__ __launch_bounds__(NT) void k_l2p(DevPlan d, const int* leaves, int kind, const double* xyz,
                                             long long n_tgt, int n_rhs, const cd* LE, cd* A) {
   extern __shared__ cd Ls[];
@@ -490,16 +523,22 @@ void launch_l2p(const DevPlan& d, const int* leaves, int n, int kind, const doub
   if (n <= 0) return;
   int pe = pmax + 2;
   int Pe = (pe + 1) * (pe + 1), Pd = (pmax + 2) * (pmax + 2);
-  size_t shm = (size_t)(RC * 3 * Pe + RC * Pd) * sizeof(cd);
-  hipFuncSetAttribute((const void*)k_l2p, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL(k_l2p, dim3(n, (n_rhs + RC - 1) / RC), dim3(NT), shm, s, d, leaves, kind, xyz, n_tgt, n_rhs,
-                     LE, A);
+  int rc = n_rhs == 1 ? 1 : 4;
+  size_t shm = (size_t)(rc * 3 * Pe + rc * Pd) * sizeof(cd);
+  if (rc == 1) {
+    hipFuncSetAttribute((const void*)k_l2p<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k_l2p<1>, dim3(n, n_rhs), dim3(NT), shm, s, d, leaves, kind, xyz, n_tgt, n_rhs, LE, A);
+  } else {
+    hipFuncSetAttribute((const void*)k_l2p<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k_l2p<4>, dim3(n, (n_rhs + 3) / 4), dim3(NT), shm, s, d, leaves, kind, xyz, n_tgt, n_rhs, LE, A);
+  }
 }
 
 // ------------------------------------------------------------------ P2P
 // free-space near field: A_i += sum_j G^f(x_i - x_j) J_j over same-layer
 // sources in adjacent leaves, coincident points skipped (paper Sec. 2 and the
 // layered sums of Sec. 3.3)
+template <int RC>
 __global__ __launch_bounds__(NT) void k_p2p(DevPlan d, const int* tboxes, const double* sxyz, const cd* J,
                                             long long n_src, const double* txyz, long long n_tgt, int n_rhs,
                                             double k, cd* A) {
@@ -568,8 +607,11 @@ __global__ __launch_bounds__(NT) void k_p2p(DevPlan d, const int* tboxes, const 
 void launch_p2p(const DevPlan& d, const int* tboxes, int n, const double* sxyz, const cd* J, long long n_src,
                 const double* txyz, long long n_tgt, int n_rhs, double k, cd* A, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_p2p, dim3(n, (n_rhs + RC - 1) / RC), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src, txyz,
-                     n_tgt, n_rhs, k, A);
+  if (n_rhs == 1)
+    hipLaunchKernelGGL(k_p2p<1>, dim3(n, n_rhs), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src, txyz, n_tgt, n_rhs, k, A);
+  else
+    hipLaunchKernelGGL(k_p2p<4>, dim3(n, (n_rhs + 3) / 4), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src, txyz, n_tgt,
+                       n_rhs, k, A);
 }
 
 // ------------------------------------------------------------------ translation tables

@@ -69,12 +69,23 @@ struct M2LOffset {
   double phi;         // azimuth of the box-centre offset (reaction phases)
 };
 
-// one work tile of the M2L GEMM
-struct M2LTile {
+// a block of M2L work: up to a fixed number of targets of one class, with
+// their (target, source) pairs sorted by offset
+struct M2LBlock {
   int cls;
+  int nt;             // targets in the block
+  int bt0;            // first block-target record
+  int q0, nq;         // pair range (global pair indices)
+  int offr0;          // start of the per-offset pair ranges (n_off + 1 entries)
+};
+
+// one work tile of the M2L GEMM: one offset, up to 64 (pair, rhs) columns
+struct M2LTile {
+  int blk;
+  int off;            // offset index within the class
   int out_type;       // 0: +, 1: -, 2: z
-  int col0, ncol;     // column range; a column is (target slot, rhs)
   int row0;           // first output row
+  int col0, ncol;     // column range within the offset's (pair, rhs) list
 };
 
 // node of a Sommerfeld quadrature set (one per instance and level)

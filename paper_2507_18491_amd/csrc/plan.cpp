@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <unordered_map>
 
 std::string lm_fmt(const char* fmt, ...) {
@@ -879,6 +880,49 @@ std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int
     pl.inst.push_back(ip);
   }
 
+  // ---- M2L work blocks: targets of a class in groups of at most 2048, pairs
+  // sorted by offset (GEMM columns) and per target (reduction)
+  {
+    const int TB = 512;
+    for (int c = 0; c < (int)pl.cls.size(); c++) {
+      const M2LClass& C = pl.cls[c];
+      long long base = pl.cls_srcof0[c];
+      for (int t0 = 0; t0 < C.n_tgt; t0 += TB) {
+        int t1 = std::min(C.n_tgt, t0 + TB);
+        M2LBlock B;
+        B.cls = c;
+        B.nt = t1 - t0;
+        B.bt0 = (int)pl.bt_tbox.size();
+        B.q0 = (int)pl.pair_src.size();
+        B.offr0 = (int)pl.offr.size();
+        // pair index of (target slot, offset) inside the block
+        std::vector<int> qidx((size_t)B.nt * C.n_off, -1);
+        for (int o = 0; o < C.n_off; o++) {
+          pl.offr.push_back((int)pl.pair_src.size());
+          for (int t = t0; t < t1; t++) {
+            int sb = pl.cls_srcof[base + (long long)t * C.n_off + o];
+            if (sb < 0) continue;
+            qidx[(size_t)(t - t0) * C.n_off + o] = (int)pl.pair_src.size();
+            pl.pair_src.push_back(sb);
+          }
+        }
+        pl.offr.push_back((int)pl.pair_src.size());
+        B.nq = (int)pl.pair_src.size() - B.q0;
+        for (int t = t0; t < t1; t++) {
+          pl.bt_tbox.push_back(pl.cls_tgt[C.tgt0 + t]);
+          pl.bt_blk.push_back((int)pl.blocks.size());
+          pl.bt_ptr.push_back((int)pl.bt_pairs.size());
+          for (int o = 0; o < C.n_off; o++) {
+            int q = qidx[(size_t)(t - t0) * C.n_off + o];
+            if (q >= 0) pl.bt_pairs.push_back(q);
+          }
+        }
+        pl.blocks.push_back(B);
+      }
+    }
+    pl.bt_ptr.push_back((int)pl.bt_pairs.size());
+  }
+
   // ---- quadrature node sets: one per (reaction instance, level)
   {
     double a = prm.contour_a > 0 ? prm.contour_a : 1.5 * med.kmax;
@@ -959,7 +1003,17 @@ std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int
   }
   bool need_gaunt = !pl.trans.empty();
   if (need_gaunt) {
-    lm_gaunt_table(pmax, pl.gaunt);
+    // the Gaunt table depends only on the order: computed once per process
+    static std::mutex mu;
+    static std::map<int, std::vector<double>> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(pmax);
+    if (it == cache.end()) {
+      std::vector<double> G;
+      lm_gaunt_table(pmax, G);
+      it = cache.emplace(pmax, std::move(G)).first;
+    }
+    pl.gaunt = it->second;
     pl.gaunt_p = pmax;
   }
   return "";

@@ -54,6 +54,13 @@ struct Plan {
   std::vector<int> cls_tgt;                   // target box ids
   std::vector<int> cls_srcof;                 // [tgt][off] source box id or -1
   std::vector<long long> cls_srcof0;          // per class start in cls_srcof
+  std::vector<M2LBlock> blocks;               // M2L work blocks
+  std::vector<int> bt_tbox;                   // per block-target: target box
+  std::vector<int> bt_ptr;                    // per block-target: first entry in bt_pairs (+ end)
+  std::vector<int> bt_pairs;                  // pair indices, per target sorted by offset
+  std::vector<int> pair_src;                  // per pair: source box
+  std::vector<int> offr;                      // per block: n_off+1 pair-range starts
+  std::vector<int> bt_blk;                    // per block-target: its block
   // tables
   std::vector<TransJob> trans;
   std::vector<TabCase> cases;
