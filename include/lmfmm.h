@@ -68,9 +68,15 @@ typedef struct {
   double tail_digits; /* the real tail [a, kcut] of the Sommerfeld integrals ends at */
                       /* kcut = a + (3p + tail_digits) / dz_min                       */
   int components;     /* bit 0: free-space part, bit 1: reaction field (3 = both)    */
+  int m2l_adapt;      /* 1: each M2L offset uses the least order whose truncation   */
+                      /* bound (separation ratio^(p+1)) does not exceed that of the */
+                      /* instance's worst admissible pair, lowered by m2l_margin   */
+                      /* decades; 0: order p everywhere                            */
+  double m2l_margin;  /* see m2l_adapt (default 3)                                  */
 } lm_params;
 
-/* Fills *prm with the defaults (p = 12, p_free = p, automatic depths). */
+/* Fills *prm with the defaults (p = 12, p_free = p, automatic depths, m2l_adapt = 1,
+ * m2l_margin = 3). */
 int lm_default_params(lm_params* prm);
 
 /* Creates a context bound to HIP device `hip_device`.  *out is owned by the

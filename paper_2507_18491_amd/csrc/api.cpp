@@ -135,6 +135,8 @@ int lm_default_params(lm_params* prm) {
   prm->contour_a = 0.0;
   prm->tail_digits = 60.0;
   prm->components = 3;
+  prm->m2l_adapt = 1;
+  prm->m2l_margin = 3.0;
   return LM_OK;
 }
 
@@ -196,6 +198,9 @@ int lm_set_params(lm_ctx* ctx, const lm_params* p) {
     return fail(ctx, LM_EINVAL, "expansion order out of range (1..20)");
   if (p->max_depth < 1 || p->max_depth > 19) return fail(ctx, LM_EINVAL, "max_depth out of range (1..19)");
   if (p->components < 1 || p->components > 3) return fail(ctx, LM_EINVAL, "components must be 1, 2 or 3");
+  if (p->m2l_adapt != 0 && p->m2l_adapt != 1) return fail(ctx, LM_EINVAL, "m2l_adapt must be 0 or 1");
+  if (p->m2l_adapt && !(p->m2l_margin >= 0 && p->m2l_margin <= 30))
+    return fail(ctx, LM_EINVAL, "m2l_margin out of range (0..30 decades)");
   PlanParams q;
   q.p = p->p;
   q.p_free = p->p_free;
@@ -205,6 +210,8 @@ int lm_set_params(lm_ctx* ctx, const lm_params* p) {
   q.contour_a = p->contour_a;
   q.tail_digits = p->tail_digits > 0 ? p->tail_digits : 60.0;
   q.components = p->components;
+  q.m2l_adapt = p->m2l_adapt;
+  q.m2l_margin = p->m2l_margin;
   ctx->prm = q;
   if (ctx->built) {
     hipSetDevice(ctx->device);
@@ -267,6 +274,7 @@ int lm_build(lm_ctx* ctx, int64_t n_src, const double* src_xyz, int64_t n_tgt, c
   if ((rc = upload(ctx, &d.pair_src, pl.pair_src))) return rc;
   if ((rc = upload(ctx, &d.offr, pl.offr))) return rc;
   if ((rc = upload(ctx, &d.bt_blk, pl.bt_blk))) return rc;
+  if ((rc = upload(ctx, &d.pair_P, pl.pair_P))) return rc;
   if ((rc = upload(ctx, &d.gaunt, pl.gaunt))) return rc;
   d.gaunt_p = pl.gaunt_p;
   if ((rc = upload(ctx, &d.Bcoef, pl.Bcoef))) return rc;
@@ -426,8 +434,9 @@ static int ensure_rhs(lm_ctx* ctx, int n_rhs, hipStream_t s) {
         for (int o = 0; o < C.n_off; o++) {
           int np = pl.offr[B.offr0 + o + 1] - pl.offr[B.offr0 + o];
           int ncol = np * n_rhs;
+          int po = pl.offs[C.off0 + o].pord, Po = (po + 1) * (po + 1);
           for (int ot = 0; ot < 3; ot++)
-            for (int r0 = 0; r0 < C.P; r0 += TM_ROWS)
+            for (int r0 = 0; r0 < Po; r0 += TM_ROWS)
               for (int c0 = 0; c0 < ncol; c0 += TN_COLS) {
                 M2LTile t;
                 t.blk = (int)bi;
@@ -606,11 +615,12 @@ int lm_stats(const lm_ctx* ctx, double* out, int n) {
     double cm = 0, ce = 0;
     for (const M2LBlock& B : pl.blocks) {
       const M2LClass& C = pl.cls[B.cls];
-      double K = (double)C.nblk * C.P;
-      double rows = (double)((C.P + TM_ROWS - 1) / TM_ROWS) * TM_ROWS;
       for (int o = 0; o < C.n_off; o++) {
         int np = pl.offr[B.offr0 + o + 1] - pl.offr[B.offr0 + o];
-        cm += 3.0 * C.P * K * np;
+        int po = pl.offs[C.off0 + o].pord, Po = (po + 1) * (po + 1);
+        double K = (double)C.nblk * Po;
+        double rows = (double)((Po + TM_ROWS - 1) / TM_ROWS) * TM_ROWS;
+        cm += 3.0 * Po * K * np;
         ce += 3.0 * rows * K * (double)((np + TN_COLS - 1) / TN_COLS) * TN_COLS;
       }
     }

@@ -31,6 +31,7 @@ struct DevPlan {
   int* pair_src;
   int* offr;
   int* bt_blk;          // block of each block-target
+  int* pair_P;          // per pair: number of rows/columns used ((pord+1)^2)
   long long* blk_ybase; // per block: first scratch element (depends on the rhs count)
   cd* mats;        // all translation / M2L matrices
   double* gaunt;

@@ -273,6 +273,11 @@ __global__ __launch_bounds__(NT) void k_m2l(DevPlan d, const M2LTile* tiles, int
   bool phased = (nblk == 3);
   M2LOffset off = d.offs[C.off0 + tl.off];
   int qo = d.offr[B.offr0 + tl.off];  // first pair of this offset
+  // order used for this offset: the leading Po rows and, in every block, the
+  // leading Po columns of the P x nblk*P matrix
+  int Po = (off.pord + 1) * (off.pord + 1);
+  int Kf = K;
+  K = nblk * Po;
   for (int e = tid; e < P; e += NT) {
     int n = n_of(e);
     mu_of[e] = (short)(e - n * n - n);
@@ -299,7 +304,12 @@ __global__ __launch_bounds__(NT) void k_m2l(DevPlan d, const M2LTile* tiles, int
     for (int e = tid; e < TM * KC; e += NT) {
       int rr = e / KC, kk = e - rr * KC;
       int row = tl.row0 + rr, k = k0 + kk;
-      As[rr][kk] = (row < P && k < K) ? A[(long long)row * K + k] : cd{0, 0};
+      cd v = cd{0, 0};
+      if (row < Po && k < K) {
+        int bl = k / Po;
+        v = A[(long long)row * Kf + (long long)bl * P + (k - bl * Po)];
+      }
+      As[rr][kk] = v;
     }
     for (int e = tid; e < KC * TN; e += NT) {
       int cc = e / KC, kk = e - cc * KC;
@@ -307,7 +317,7 @@ __global__ __launch_bounds__(NT) void k_m2l(DevPlan d, const M2LTile* tiles, int
       cd v = cd{0, 0};
       long long sbb = sbase[cc];
       if (sbb >= 0 && k < K) {
-        int bl = k / P, num = k - bl * P;
+        int bl = k / Po, num = k - bl * Po;
         v = ME[sbb + (long long)rch[bl] * P + num];
         if (phased) v = v * eph[rkap[bl] + mu_of[num] + p + 2];
       }
@@ -333,7 +343,7 @@ __global__ __launch_bounds__(NT) void k_m2l(DevPlan d, const M2LTile* tiles, int
     cd* Yq = Y + d.blk_ybase[tl.blk] + ((long long)((q - B.q0) * 3 + ot) * n_rhs + r) * P;
     for (int i = 0; i < 4; i++) {
       int row = tl.row0 + tr * 4 + i;
-      if (row >= P) continue;
+      if (row >= Po) continue;
       cd ph = phased ? cconj(eph[mu_of[row] + p + 2]) : cd{1, 0};
       Yq[row] = ph * acc[i][j];
     }
@@ -361,7 +371,7 @@ __global__ __launch_bounds__(NT) void k_m2l_reduce(DevPlan d, int bt0, int n_rhs
     cd s = cd{0, 0};
     for (int qi = q0; qi < q1; qi++) {
       int q = d.bt_pairs[qi];
-      s = s + Y[ybase + ((long long)(q - qb) * 3 * n_rhs + tr_) * P + row];
+      if (row < d.pair_P[q]) s = s + Y[ybase + ((long long)(q - qb) * 3 * n_rhs + tr_) * P + row];
     }
     long long idx = tb.le_off * n_rhs + ((long long)r * 3 + ot) * P + row;
     LE[idx] = LE[idx] + s;

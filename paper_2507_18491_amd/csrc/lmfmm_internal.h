@@ -67,6 +67,8 @@ struct M2LClass {
 struct M2LOffset {
   long long mat[3];   // per output type: offset (in complex) of the P x (nblk*P) matrix
   double phi;         // azimuth of the box-centre offset (reaction phases)
+  int pord;           // order used for this offset (<= p): leading (pord+1)^2 rows/columns
+  int pad_;
 };
 
 // a block of M2L work: up to a fixed number of targets of one class, with

@@ -520,6 +520,7 @@ std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int
   pl.kmaxcheb = KB;
   std::map<std::tuple<int, int, long long, long long, long long>, int> casemap;
   std::vector<double> case_dz;  // vertical centre separation of each case
+  std::vector<double> off_ratio;  // per M2L offset: (r_s + r_t) / |c_t - c_s|
 
   for (auto& g : geo) {
     InstParams ip = g.ip;
@@ -604,6 +605,7 @@ std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int
     ip.Dgap = Dgap;
     (void)depth_used;
     HTree& TT = free ? S : T;  // target tree
+    int inst_off0 = (int)pl.offs.size();
 
     // ---- boxes -> global records
     int sbase = (int)pl.sbox.size(), tbase = (int)pl.tbox.size();
@@ -825,6 +827,7 @@ std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int
           long long m = alloc_mat(MatKey{0, kquant(ip.kt), ip.p, l, dx, dy, dz}, (long long)P * P, &j);
           mo.mat[0] = mo.mat[1] = mo.mat[2] = m;
           mo.phi = 0;
+          off_ratio.push_back(sqrt(3.0) / sqrt((double)(dx * dx + dy * dy + dz * dz)));
         } else {
           int js = dz;
           int r2 = dx * dx + dy * dy;
@@ -858,11 +861,19 @@ std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int
           } else
             cid = it->second;
           long long base = pl.cases[cid].mat;
+          {
+            double zt_img = ip.sgn > 0 ? T.z0 + (jt + 0.5) * Sl : T.z0 + S0 - (jt + 0.5) * Sl;
+            double zs_img = ip.sgn > 0 ? S.z0 + S0 - (js + 0.5) * Sl : S.z0 + (js + 0.5) * Sl;
+            double R = sqrt((double)(dx * dx + dy * dy) * Sl * Sl + (zt_img - zs_img) * (zt_img - zs_img));
+            off_ratio.push_back(sqrt(3.0) * Sl / R);
+          }
           mo.mat[0] = base;
           mo.mat[1] = base + 3LL * P * P;
           mo.mat[2] = base + 6LL * P * P;
           mo.phi = atan2(-(double)dy, -(double)dx);
         }
+        mo.pord = ip.p;
+        mo.pad_ = 0;
         pl.offs.push_back(mo);
       }
       pl.cls_srcof0.push_back((long long)pl.cls_srcof.size());
@@ -876,6 +887,23 @@ std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int
       }
       for (int t : tlist) pl.cls_tgt.push_back(tbase + t);
       pl.cls.push_back(C);
+    }
+    // per-offset orders: the truncation error of an M2L pair behaves like
+    // rho^(p+1), rho = (r_s + r_t)/|c_t - c_s|.  Every offset gets the least
+    // order whose bound lies m2l_margin decades below the bound of the
+    // instance's worst admissible pair at order p (the margin accounts for
+    // the many better-separated pairs that would otherwise all contribute
+    // the worst pair's error).
+    if (prm.m2l_adapt && inst_off0 < (int)pl.offs.size()) {
+      double rref = 0;
+      for (int o = inst_off0; o < (int)pl.offs.size(); o++) rref = std::max(rref, off_ratio[o]);
+      double target = (ip.p + 1) * log(rref) - prm.m2l_margin * log(10.0);
+      for (int o = inst_off0; o < (int)pl.offs.size(); o++) {
+        double r = off_ratio[o];
+        int q = ip.p;
+        if (r < rref && rref < 1.0) q = (int)ceil(target / log(r)) - 1;
+        pl.offs[o].pord = std::min(ip.p, std::max(2, q));
+      }
     }
     pl.inst.push_back(ip);
   }
@@ -904,6 +932,8 @@ std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int
             if (sb < 0) continue;
             qidx[(size_t)(t - t0) * C.n_off + o] = (int)pl.pair_src.size();
             pl.pair_src.push_back(sb);
+            int po = pl.offs[C.off0 + o].pord;
+            pl.pair_P.push_back((po + 1) * (po + 1));
           }
         }
         pl.offr.push_back((int)pl.pair_src.size());

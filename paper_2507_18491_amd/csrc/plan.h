@@ -29,6 +29,8 @@ struct PlanParams {
   double contour_a = 0;  // 0: 1.5 * max k
   double tail_digits = 60;
   int components = 3;    // bit 0: free space, bit 1: reaction
+  int m2l_adapt = 1;     // per-offset M2L order from the separation ratio
+  double m2l_margin = 3.0;  // decades below the worst pair's truncation bound
 };
 
 struct Plan {
@@ -61,6 +63,7 @@ struct Plan {
   std::vector<int> pair_src;                  // per pair: source box
   std::vector<int> offr;                      // per block: n_off+1 pair-range starts
   std::vector<int> bt_blk;                    // per block-target: its block
+  std::vector<int> pair_P;                    // per pair: (pord+1)^2 of its offset
   // tables
   std::vector<TransJob> trans;
   std::vector<TabCase> cases;

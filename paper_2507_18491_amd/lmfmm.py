@@ -27,7 +27,8 @@ class lm_params(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int), ("p_free", ctypes.c_int), ("free_depth", ctypes.c_int),
                 ("max_depth", ctypes.c_int), ("gamma1_panels", ctypes.c_int),
                 ("contour_a", ctypes.c_double), ("tail_digits", ctypes.c_double),
-                ("components", ctypes.c_int)]
+                ("components", ctypes.c_int), ("m2l_adapt", ctypes.c_int),
+                ("m2l_margin", ctypes.c_double)]
 
 
 _lib = None

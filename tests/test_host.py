@@ -168,3 +168,24 @@ def test_plan_rejects_bad_order():
     x = np.array([[0.0, 0.0, 0.5], [0.1, 0.0, -0.5]])
     with pytest.raises(lmfmm.LMError):
         lmfmm.host_plan_stats([0.0], [1.0, 1.5], x, p=21)
+
+
+def test_plan_adaptive_orders_reduce_work():
+    """Per-offset orders never exceed p: the adaptive plan does no more M2L
+    work than the uniform one, and a larger margin never does less."""
+    d, k, x, _ = inputs.three_layer(20000)
+    s0 = lmfmm.host_plan_stats(d, k, x, p=12, m2l_adapt=0)
+    s2 = lmfmm.host_plan_stats(d, k, x, p=12, m2l_adapt=1, m2l_margin=2.0)
+    s3 = lmfmm.host_plan_stats(d, k, x, p=12, m2l_adapt=1, m2l_margin=3.0)
+    s30 = lmfmm.host_plan_stats(d, k, x, p=12, m2l_adapt=1, m2l_margin=30.0)
+    assert s2["m2l_cmac_useful"] <= s3["m2l_cmac_useful"] <= s0["m2l_cmac_useful"]
+    assert s3["m2l_cmac_useful"] < s0["m2l_cmac_useful"]
+    assert s30["m2l_cmac_useful"] == s0["m2l_cmac_useful"]
+    assert s3["m2l_pairs_free"] == s0["m2l_pairs_free"] and s3["m2l_pairs_react"] == s0["m2l_pairs_react"]
+
+
+@pytest.mark.parametrize("kw", [{"m2l_adapt": 2}, {"m2l_margin": -1.0}, {"m2l_margin": float("nan")}])
+def test_plan_rejects_bad_adaptive_params(kw):
+    d, k, x, _ = inputs.tiny()
+    with pytest.raises(lmfmm.LMError):
+        lmfmm.host_plan_stats(d, k, x, p=8, **kw)
