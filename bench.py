@@ -63,7 +63,19 @@ def main():
     ap.add_argument("--rhs", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 1 GiB device buffer three times (a reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read_per_copy": src.numel() * 8,
+                          "copy_calibration_bytes_written_per_copy": src.numel() * 8}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (got --gpus %d); the path shards by "
               "independent FMM instances but no multi-GPU run is provided." % args.gpus, flush=True)
@@ -94,12 +106,18 @@ def main():
     torch.cuda.synchronize()
     wall = time.time() - t0
     phases, ncalls = fmm.timings()
+    gemm_ms_total, gemm_launches = fmm.m2l_gemm_timing()
     fmm.set_timing(False)
     ms_per_step = 1000.0 * wall / args.steps
     value = args.n * args.rhs / (wall / args.steps)
-    m2l_ms = phases["m2l"] / max(1, ncalls)
+    # roofline of the M2L GEMM kernel: algorithmic flops (8 real flops per
+    # complex multiply-add actually needed, absent-source columns excluded)
+    # per launch over the kernel's average launch duration
+    launches_per_step = gemm_launches / max(1, ncalls)
+    launch_ms = gemm_ms_total / max(1, gemm_launches)
     m2l_flops = st["m2l_cmac_useful"] * 8.0 * args.rhs
-    achieved = m2l_flops / (m2l_ms * 1e-3) / 1e12
+    flops_per_launch = m2l_flops / max(1e-30, launches_per_step)
+    achieved = flops_per_launch / (launch_ms * 1e-3) / 1e12
     print("timed: %.1f ms/step, phases (ms/step): %s" % (
         ms_per_step, {a: round(b / max(1, ncalls), 2) for a, b in phases.items()}), file=sys.stderr, flush=True)
 
@@ -133,7 +151,8 @@ def main():
                    "n": args.n, "p": args.p, "p_free": args.p_free or args.p, "layers": 3, "n_rhs": args.rhs},
         "roofline": {"bound": "alu", "kernel": "k_m2l", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
-                     "launch_ms": m2l_ms, "algorithmic_flops": m2l_flops},
+                     "launch_ms": launch_ms, "launches_per_step": launches_per_step,
+                     "algorithmic_flops_per_launch": flops_per_launch},
         "cpu_baseline": cpu,
         "rel_err_vs_oracle": acc,
         "build_s": build_s,

@@ -117,21 +117,28 @@ int lm_build(lm_ctx* ctx, int64_t n_src, const double* src_xyz, int64_t n_tgt,
 int lm_evaluate(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream);
 
 /* Phase timing.  lm_set_timing(ctx, 1) (re)starts recording HIP events on
- * the evaluation stream between the phases of every following lm_evaluate;
- * lm_timings() waits for the recorded events and writes, summed over the
- * timed evaluations, the milliseconds of each phase (indices LM_PHASE_*)
- * followed by the number of timed evaluations (n >= LM_PHASES + 1). */
+ * the evaluation stream between the phases of every following lm_evaluate
+ * and around every launch of the M2L GEMM kernel; lm_timings() waits for the
+ * recorded events and writes up to n values, summed over the timed
+ * evaluations: the milliseconds of each phase (indices LM_PHASE_*), the
+ * number of timed evaluations (index LM_PHASES), the milliseconds spent in
+ * the M2L GEMM kernel alone (LM_TIMING_M2L_GEMM_MS, part of LM_PHASE_M2L,
+ * which also holds the per-target reduction) and the number of its launches
+ * (LM_TIMING_M2L_GEMM_LAUNCHES). */
 int lm_set_timing(lm_ctx* ctx, int enable);
 int lm_timings(lm_ctx* ctx, double* out_host, int n);
 
 #define LM_PHASE_CLEAR 0   /* zeroing of A and of the local expansions           */
 #define LM_PHASE_P2M 1
 #define LM_PHASE_M2M 2
-#define LM_PHASE_M2L 3     /* one kernel: the M2L GEMM over all classes          */
+#define LM_PHASE_M2L 3     /* M2L GEMM launches and the per-target reductions    */
 #define LM_PHASE_L2L 4
 #define LM_PHASE_L2P 5
 #define LM_PHASE_P2P 6
 #define LM_PHASES 7
+#define LM_TIMING_M2L_GEMM_MS (LM_PHASES + 1)
+#define LM_TIMING_M2L_GEMM_LAUNCHES (LM_PHASES + 2)
+#define LM_TIMINGS_COUNT (LM_PHASES + 3)
 
 /* Statistics of the current build (host array of n doubles, indices below). */
 int lm_stats(const lm_ctx* ctx, double* out_host, int n);

@@ -513,8 +513,10 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
   cd* Ac = (cd*)A;
   DevPlan& d = ctx->d;
   std::vector<hipEvent_t> ev;
+  const int nch = (int)ctx->tilesets[n_rhs].chunks.size();
   if (ctx->timing && ctx->evsets.size() < 4096) {
-    ev.resize(LM_PHASES + 1);
+    // phase boundaries, then a start/stop pair around every M2L GEMM launch
+    ev.resize(LM_PHASES + 1 + 2 * nch);
     for (auto& e : ev) HIPC(hipEventCreate(&e));
   }
   auto mark = [&](int i) {
@@ -530,8 +532,11 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
     for (int l = (int)ctx->d_m2m.size() - 1; l >= 0; l--)
       launch_m2m(d, ctx->d_m2m[l], ctx->n_m2m[l], n_rhs, ctx->ME, ctx->pmax, s);
     mark(3);
-    for (auto& ch : ctx->tilesets[n_rhs].chunks) {
+    for (int c = 0; c < nch; c++) {
+      const lm_ctx::Chunk& ch = ctx->tilesets[n_rhs].chunks[c];
+      mark(LM_PHASES + 1 + 2 * c);
       launch_m2l(d, d.tiles + ch.tile0, ch.ntile, n_rhs, ctx->ME, ctx->Y, ctx->pmax, s);
+      mark(LM_PHASES + 2 + 2 * c);
       launch_m2l_reduce(d, ch.bt0, ch.nbt, n_rhs, ctx->Y, ctx->LE, ctx->pmax, s);
     }
     mark(4);
@@ -550,6 +555,7 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
     mark(7);
   } else {
     for (int i = 2; i <= 7; i++) mark(i);
+    for (int c = 0; c < 2 * nch; c++) mark(LM_PHASES + 1 + c);
   }
   if (!ev.empty()) ctx->evsets.push_back(ev);
   HIPC(hipGetLastError());
@@ -567,7 +573,7 @@ int lm_set_timing(lm_ctx* ctx, int enable) {
 int lm_timings(lm_ctx* ctx, double* out, int n) {
   if (!ctx || !out || n < 1) return LM_EINVAL;
   HIPC(hipSetDevice(ctx->device));
-  double acc[LM_PHASES + 1] = {0};
+  double acc[LM_TIMINGS_COUNT] = {0};
   for (auto& v : ctx->evsets) {
     HIPC(hipEventSynchronize(v[LM_PHASES]));
     for (int i = 0; i < LM_PHASES; i++) {
@@ -575,9 +581,15 @@ int lm_timings(lm_ctx* ctx, double* out, int n) {
       HIPC(hipEventElapsedTime(&ms, v[i], v[i + 1]));
       acc[i] += ms;
     }
+    for (size_t j = LM_PHASES + 1; j + 1 < v.size(); j += 2) {
+      float ms = 0;
+      HIPC(hipEventElapsedTime(&ms, v[j], v[j + 1]));
+      acc[LM_TIMING_M2L_GEMM_MS] += ms;
+      acc[LM_TIMING_M2L_GEMM_LAUNCHES] += 1;
+    }
   }
   acc[LM_PHASES] = (double)ctx->evsets.size();
-  int m = n < LM_PHASES + 1 ? n : LM_PHASES + 1;
+  int m = n < LM_TIMINGS_COUNT ? n : LM_TIMINGS_COUNT;
   memcpy(out, acc, m * sizeof(double));
   return LM_OK;
 }

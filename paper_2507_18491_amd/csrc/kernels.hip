@@ -246,113 +246,283 @@ void launch_l2l(const DevPlan& d, const int* children, int n, int n_rhs, cd* LE,
 #define TM 64
 #define TN 64
 #define KC 16
-__global__ __launch_bounds__(NT) void k_m2l(DevPlan d, const M2LTile* tiles, int n_rhs, const cd* ME, cd* Y) {
-  __shared__ cd As[TM][KC + 1];
-  __shared__ cd Bs[KC][TN + 1];
-  __shared__ long long sbase[TN];
-  __shared__ cd eph[2 * LM_PMAX + 8];
-  __shared__ short mu_of[(LM_PMAX + 1) * (LM_PMAX + 1)];
-  M2LTile tl = tiles[blockIdx.x];
-  M2LBlock B = d.blocks[tl.blk];
-  M2LClass C = d.cls[B.cls];
-  InstParams ip = d.inst[C.inst];
-  int P = C.P, p = ip.p, nblk = C.nblk, K = nblk * P;
-  int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
-  int ot = tl.out_type;
-  int rch[3], rkap[3];
-  if (nblk == 1) {
-    rch[0] = ot;
-    rkap[0] = 0;
-  } else if (ot == 0) {
-    rch[0] = 0; rkap[0] = 0; rch[1] = 1; rkap[1] = 2; rch[2] = 2; rkap[2] = 1;
-  } else if (ot == 1) {
-    rch[0] = 1; rkap[0] = 0; rch[1] = 0; rkap[1] = -2; rch[2] = 2; rkap[2] = -1;
-  } else {
-    rch[0] = 1; rkap[0] = 1; rch[1] = 0; rkap[1] = -1; rch[2] = 2; rkap[2] = 0;
+#define LDS_LD (KC + 1)    // row pitch (doubles) of the LDS operand planes
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Shared state of one M2L tile (read by all waves of the block).
+struct M2LTileCtx {
+  const cd* A;        // the offset's P x Kf matrix of this output type
+  const cd* ME;
+  cd* Y;
+  long long ybase;    // scratch base of the tile's block
+  int P, Po, K, Kf, p, ot, row0, ncol, col0, qo, q0b, n_rhs;
+  bool phased;
+};
+
+// Operand planes are row-major, [row or column][k], pitch KC + 1 doubles:
+// the 16 threads that store one row's KC values write consecutive words,
+// and the MFMA operand reads (16 lanes on 16 rows, 4 groups of lanes on 4
+// consecutive k) fall on distinct banks.
+struct M2LLds {
+  double Ar[TM][LDS_LD], Ai[TM][LDS_LD], Br[TN][LDS_LD], Bi[TN][LDS_LD];
+  long long sbase[TN];
+  cd eph[2 * LM_PMAX + 8];
+  short mu_of[(LM_PMAX + 1) * (LM_PMAX + 1)];
+};
+
+// input channel and kappa of column block bl (reaction, spin basis):
+//   out +: (u+, 0), (u-, 2), (z, 1);  out -: (u-, 0), (u+, -2), (z, -1);
+//   out z: (u-, 1), (u+, -1), (z, 0).  Packed as 2 bits (channel) and
+//   3 bits (kappa + 2) per (ot, bl) entry.
+__device__ inline int m2l_rch(bool phased, int ot, int bl) {
+  const unsigned CH = 0u | 1u << 2 | 2u << 4 | 1u << 6 | 0u << 8 | 2u << 10 | 1u << 12 | 0u << 14 | 2u << 16;
+  return phased ? (int)((CH >> (2 * (3 * ot + bl))) & 3u) : ot;
+}
+__device__ inline int m2l_rkap(bool phased, int ot, int bl) {
+  const unsigned KP = 2u | 4u << 3 | 3u << 6 | 2u << 9 | 0u << 12 | 1u << 15 | 3u << 18 | 1u << 21 | 2u << 24;
+  return phased ? (int)((KP >> (3 * (3 * ot + bl))) & 7u) - 2 : 0;
+}
+
+// K loop and epilogue of one wave whose 32 x 32 wave tile has NI x NJ active
+// 16 x 16 MFMA tiles (NI, NJ in 0..2; rows beyond Po and columns beyond the
+// pair count are never computed).  Every wave of the block runs the same
+// number of barriers whatever its NI, NJ.
+// MFMA operand layout (v_mfma_f64_16x16x4f64, one fp64 per lane and
+// operand): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; the four
+// result registers of lane l hold C[4 r + l / 16][l % 16], r = 0..3.
+// Complex product with real MFMAs: C_re += A_re B_re + (-A_im) B_im,
+// C_im += A_re B_im + A_im B_re; the eight (or, for one active tile, four
+// split) accumulator chains are interleaved so that no MFMA waits on the
+// one issued just before it.
+template <int NI, int NJ>
+__device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds& L, int tid, int wr, int wc) {
+  constexpr bool SPLIT = (NI * NJ == 1);
+  constexpr int NIx = NI > 0 ? NI : 1, NJx = NJ > 0 ? NJ : 1;
+  v4d cr[NIx][NJx], ci[NIx][NJx], cr2[NIx][NJx], ci2[NIx][NJx];
+#pragma unroll
+  for (int i = 0; i < NIx; i++)
+#pragma unroll
+    for (int j = 0; j < NJx; j++) {
+      cr[i][j] = v4d{0, 0, 0, 0};
+      ci[i][j] = cr[i][j];
+      cr2[i][j] = cr[i][j];
+      ci2[i][j] = cr[i][j];
+    }
+  const int lane = tid & 63;
+  constexpr int NA = TM * KC / NT, NB = KC * TN / NT;
+  // fixed roles of this thread in the chunk loads: k offset kk, and rows
+  // (matrix) / columns (source vectors) r16 + 16 it; indices outside the
+  // tile are clamped to a valid entry and the value zeroed
+  const int kk = tid & (KC - 1), r16 = tid / KC;
+  long long aoff[NA], boff[NB];
+  bool aok[NA], bok[NB];
+#pragma unroll
+  for (int it = 0; it < NA; it++) {
+    int row = c.row0 + r16 + 16 * it;
+    aok[it] = row < c.Po;
+    aoff[it] = (long long)(aok[it] ? row : c.Po - 1) * c.Kf;
   }
-  bool phased = (nblk == 3);
-  M2LOffset off = d.offs[C.off0 + tl.off];
-  int qo = d.offr[B.offr0 + tl.off];  // first pair of this offset
-  // order used for this offset: the leading Po rows and, in every block, the
-  // leading Po columns of the P x nblk*P matrix
-  int Po = (off.pord + 1) * (off.pord + 1);
-  int Kf = K;
-  K = nblk * Po;
-  for (int e = tid; e < P; e += NT) {
+#pragma unroll
+  for (int it = 0; it < NB; it++) {
+    long long sb = L.sbase[r16 + 16 * it];
+    bok[it] = sb >= 0;
+    boff[it] = sb >= 0 ? sb : L.sbase[0];
+  }
+  cd ra[NA], rb[NB];
+  auto load = [&](int k0) {
+    const int k = k0 + kk;
+    const bool kok = k < c.K;
+    const int kc = kok ? k : c.K - 1;
+    const int bl = kc >= c.Po ? (kc >= 2 * c.Po ? 2 : 1) : 0;
+    const int num = kc - bl * c.Po;
+    const long long colA = (long long)bl * c.P + num;
+    const long long colB = (long long)m2l_rch(c.phased, c.ot, bl) * c.P + num;
+#pragma unroll
+    for (int it = 0; it < NA; it++) {
+      cd v = c.A[aoff[it] + colA];
+      ra[it] = (aok[it] && kok) ? v : cd{0, 0};
+    }
+#pragma unroll
+    for (int it = 0; it < NB; it++) {
+      cd v = c.ME[boff[it] + colB];
+      rb[it] = (bok[it] && kok) ? v : cd{0, 0};
+    }
+  };
+  // registers -> LDS planes; source values times the offset's phase
+  // e^{i (kappa + mu) phi}, which depends on k only
+  auto store = [&](int k0) {
+    cd ph = cd{1, 0};
+    if (c.phased) {
+      const int k = k0 + kk;
+      const int kc = k < c.K ? k : c.K - 1;
+      const int bl = kc >= c.Po ? (kc >= 2 * c.Po ? 2 : 1) : 0;
+      ph = L.eph[m2l_rkap(true, c.ot, bl) + L.mu_of[kc - bl * c.Po] + c.p + 2];
+    }
+#pragma unroll
+    for (int it = 0; it < NA; it++) {
+      L.Ar[r16 + 16 * it][kk] = ra[it].x;
+      L.Ai[r16 + 16 * it][kk] = ra[it].y;
+    }
+#pragma unroll
+    for (int it = 0; it < NB; it++) {
+      cd v = c.phased ? rb[it] * ph : rb[it];
+      L.Br[r16 + 16 * it][kk] = v.x;
+      L.Bi[r16 + 16 * it][kk] = v.y;
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < c.K; k0 += KC) {
+    store(k0);
+    __syncthreads();
+    if (k0 + KC < c.K) load(k0 + KC);
+    if (NI > 0 && NJ > 0) {
+#pragma unroll
+      for (int k4 = 0; k4 < KC; k4 += 4) {
+        const int kr = k4 + (lane >> 4), li = lane & 15;
+        double a_r[NIx], a_i[NIx], a_n[NIx], b_r[NJx], b_i[NJx];
+#pragma unroll
+        for (int i = 0; i < NIx; i++) {
+          a_r[i] = L.Ar[wr * 32 + i * 16 + li][kr];
+          a_i[i] = L.Ai[wr * 32 + i * 16 + li][kr];
+          a_n[i] = -a_i[i];
+        }
+#pragma unroll
+        for (int j = 0; j < NJx; j++) {
+          b_r[j] = L.Br[wc * 32 + j * 16 + li][kr];
+          b_i[j] = L.Bi[wc * 32 + j * 16 + li][kr];
+        }
+#pragma unroll
+        for (int i = 0; i < NIx; i++)
+#pragma unroll
+          for (int j = 0; j < NJx; j++) {
+            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[i], b_r[j], cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[i], b_i[j], ci[i][j], 0, 0, 0);
+          }
+#pragma unroll
+        for (int i = 0; i < NIx; i++)
+#pragma unroll
+          for (int j = 0; j < NJx; j++) {
+            if (SPLIT) {
+              cr2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_n[i], b_i[j], cr2[i][j], 0, 0, 0);
+              ci2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[i], b_r[j], ci2[i][j], 0, 0, 0);
+            } else {
+              cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_n[i], b_i[j], cr[i][j], 0, 0, 0);
+              ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[i], b_r[j], ci[i][j], 0, 0, 0);
+            }
+          }
+      }
+    }
+    __syncthreads();
+  }
+  if (NI == 0 || NJ == 0) return;
+  // epilogue: lane holds rows 4 r + lane / 16 of each 16 x 16 tile, column
+  // lane % 16; column j of the tile is (pair, rhs) = (qo + (col0 + j) / n_rhs,
+  // (col0 + j) % n_rhs) and goes to that pair's scratch vector
+  const int li = lane & 15, rq = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < NIx; i++)
+#pragma unroll
+    for (int j = 0; j < NJx; j++) {
+      const int col = wc * 32 + j * 16 + li;
+      if (col >= c.ncol) continue;
+      v4d vr = cr[i][j], vi = ci[i][j];
+      if (SPLIT) {
+        vr += cr2[i][j];
+        vi += ci2[i][j];
+      }
+      const int jj = c.col0 + col;
+      const int q = c.qo + jj / c.n_rhs, r = jj % c.n_rhs;
+      cd* Yq = c.Y + c.ybase + ((long long)((q - c.q0b) * 3 + c.ot) * c.n_rhs + r) * c.P;
+#pragma unroll
+      for (int rr = 0; rr < 4; rr++) {
+        const int row = c.row0 + wr * 32 + i * 16 + 4 * rr + rq;
+        if (row >= c.Po) continue;
+        cd v = cd{vr[rr], vi[rr]};
+        if (c.phased) v = cconj(L.eph[L.mu_of[row] + c.p + 2]) * v;
+        Yq[row] = v;
+      }
+    }
+}
+
+// One 64 x 64 output tile per block, complex fp64 on the matrix cores.  The
+// four waves form a 2 x 2 grid of 32 x 32 wave tiles; a wave computes only
+// those of its four 16 x 16 MFMA tiles that hold rows below the offset's
+// (pord+1)^2 and columns below the tile's pair count, so partial tiles cost
+// little; the choice is made once per tile from a wave-uniform value.
+// Operands are staged through LDS as separate real / imaginary planes,
+// k-major, KC values of k at a time, with the next chunk's global loads in
+// flight during the MFMAs.  Consecutive tiles are sent to one XCD (blocks
+// are dealt round-robin over the 8 XCDs), so the tiles sharing one offset's
+// matrix and source vectors run against one L2.
+__global__ __launch_bounds__(NT, 3) void k_m2l(DevPlan d, const M2LTile* tiles, int n_tiles, int n_rhs,
+                                           const cd* ME, cd* Y) {
+  __shared__ M2LLds L;
+  const int per_xcd = (n_tiles + 7) >> 3;
+  const int t_id = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  if (t_id >= n_tiles) return;
+  const M2LTile tl = tiles[t_id];
+  const M2LBlock B = d.blocks[tl.blk];
+  const M2LClass C = d.cls[B.cls];
+  const int tid = threadIdx.x;
+  const M2LOffset* offp = d.offs + C.off0 + tl.off;
+  M2LTileCtx c;
+  c.P = C.P;
+  c.p = d.inst[C.inst].p;
+  c.ot = tl.out_type;
+  c.phased = (C.nblk == 3);
+  // order used for this offset: the leading Po rows and, in every column
+  // block, the leading Po columns of the P x nblk*P matrix
+  c.Po = (offp->pord + 1) * (offp->pord + 1);
+  c.Kf = C.nblk * C.P;
+  c.K = C.nblk * c.Po;
+  c.row0 = tl.row0;
+  c.ncol = tl.ncol;
+  c.col0 = tl.col0;
+  c.qo = d.offr[B.offr0 + tl.off];  // first pair of this offset
+  c.q0b = B.q0;
+  c.n_rhs = n_rhs;
+  c.ybase = d.blk_ybase[tl.blk];    // per-block scratch base (blocks differ in P)
+  c.A = d.mats + offp->mat[c.ot];
+  c.ME = ME;
+  c.Y = Y;
+  const double phi = offp->phi;
+  for (int e = tid; e < c.P; e += NT) {
     int n = n_of(e);
-    mu_of[e] = (short)(e - n * n - n);
+    L.mu_of[e] = (short)(e - n * n - n);
   }
   if (tid < TN) {
     long long v = -1;
     if (tid < tl.ncol) {
       int j = tl.col0 + tid;
-      int q = qo + j / n_rhs, r = j % n_rhs;
-      v = d.sbox[d.pair_src[q]].me_off * n_rhs + (long long)r * 3 * P;
+      int q = c.qo + j / n_rhs, r = j % n_rhs;
+      v = d.sbox[d.pair_src[q]].me_off * n_rhs + (long long)r * 3 * c.P;
     }
-    sbase[tid] = v;
+    L.sbase[tid] = v;
   }
-  if (tid < 2 * p + 5) {
-    double a = (tid - (p + 2)) * off.phi;
-    eph[tid] = cd{cos(a), sin(a)};
+  if (tid < 2 * c.p + 5) {
+    double a = (tid - (c.p + 2)) * phi;
+    L.eph[tid] = cd{cos(a), sin(a)};
   }
   __syncthreads();
-  cd acc[4][4];
-  for (int i = 0; i < 4; i++)
-    for (int j = 0; j < 4; j++) acc[i][j] = cd{0, 0};
-  const cd* A = d.mats + off.mat[ot];
-  for (int k0 = 0; k0 < K; k0 += KC) {
-    for (int e = tid; e < TM * KC; e += NT) {
-      int rr = e / KC, kk = e - rr * KC;
-      int row = tl.row0 + rr, k = k0 + kk;
-      cd v = cd{0, 0};
-      if (row < Po && k < K) {
-        int bl = k / Po;
-        v = A[(long long)row * Kf + (long long)bl * P + (k - bl * Po)];
-      }
-      As[rr][kk] = v;
-    }
-    for (int e = tid; e < KC * TN; e += NT) {
-      int cc = e / KC, kk = e - cc * KC;
-      int k = k0 + kk;
-      cd v = cd{0, 0};
-      long long sbb = sbase[cc];
-      if (sbb >= 0 && k < K) {
-        int bl = k / Po, num = k - bl * Po;
-        v = ME[sbb + (long long)rch[bl] * P + num];
-        if (phased) v = v * eph[rkap[bl] + mu_of[num] + p + 2];
-      }
-      Bs[kk][cc] = v;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < KC; kk++) {
-      cd a[4], bb[4];
-      for (int i = 0; i < 4; i++) a[i] = As[tr * 4 + i][kk];
-      for (int j = 0; j < 4; j++) bb[j] = Bs[kk][tc * 4 + j];
-      for (int i = 0; i < 4; i++)
-        for (int j = 0; j < 4; j++) acc[i][j] = acc[i][j] + a[i] * bb[j];
-    }
-    __syncthreads();
-  }
-  for (int j = 0; j < 4; j++) {
-    int col = tc * 4 + j;
-    if (col >= tl.ncol) continue;
-    int jj = tl.col0 + col;
-    int q = qo + jj / n_rhs, r = jj % n_rhs;
-    // scratch slot: per-block base (blocks of one chunk may have different P)
-    cd* Yq = Y + d.blk_ybase[tl.blk] + ((long long)((q - B.q0) * 3 + ot) * n_rhs + r) * P;
-    for (int i = 0; i < 4; i++) {
-      int row = tl.row0 + tr * 4 + i;
-      if (row >= Po) continue;
-      cd ph = phased ? cconj(eph[mu_of[row] + p + 2]) : cd{1, 0};
-      Yq[row] = ph * acc[i][j];
-    }
+  // this wave's active MFMA tiles (uniform over the wave, kept in an SGPR)
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const int ni = (c.row0 + wr * 32 < c.Po) + (c.row0 + wr * 32 + 16 < c.Po);
+  const int nj = (wc * 32 < c.ncol) + (wc * 32 + 16 < c.ncol);
+  const int pat = __builtin_amdgcn_readfirstlane(ni * 3 + nj);
+  switch (pat) {
+    case 4: m2l_wave<1, 1>(c, L, tid, wr, wc); break;
+    case 5: m2l_wave<1, 2>(c, L, tid, wr, wc); break;
+    case 7: m2l_wave<2, 1>(c, L, tid, wr, wc); break;
+    case 8: m2l_wave<2, 2>(c, L, tid, wr, wc); break;
+    default: m2l_wave<0, 0>(c, L, tid, wr, wc); break;
   }
 }
 void launch_m2l(const DevPlan& d, const M2LTile* tiles, int n_tiles, int n_rhs, const cd* ME, cd* Y, int pmax,
                 hipStream_t s) {
   if (n_tiles <= 0) return;
-  hipLaunchKernelGGL(k_m2l, dim3(n_tiles), dim3(NT), 0, s, d, tiles, n_rhs, ME, Y);
+  int grid = ((n_tiles + 7) / 8) * 8;
+  hipLaunchKernelGGL(k_m2l, dim3(grid), dim3(NT), 0, s, d, tiles, n_tiles, n_rhs, ME, Y);
 }
 
 // LE_t[out][rhs] += sum over the target's pairs (fixed offset order) of Y

@@ -157,9 +157,19 @@ class LayeredDyadicFMM:
 
     def timings(self):
         """Milliseconds per phase summed over the timed evaluations, and their count."""
-        buf = np.zeros(len(PHASE_NAMES) + 1)
+        buf = np.zeros(len(PHASE_NAMES) + 3)
         self._check(self.lib.lm_timings(self.ctx, _dp(buf), buf.size))
-        return dict(zip(PHASE_NAMES, buf[:-1].tolist())), int(buf[-1])
+        n = len(PHASE_NAMES)
+        return dict(zip(PHASE_NAMES, buf[:n].tolist())), int(buf[n])
+
+    def m2l_gemm_timing(self):
+        """Milliseconds spent in the M2L GEMM kernel alone (HIP events around
+        each launch on the evaluation stream) over the timed evaluations, and
+        the number of its launches."""
+        buf = np.zeros(len(PHASE_NAMES) + 3)
+        self._check(self.lib.lm_timings(self.ctx, _dp(buf), buf.size))
+        n = len(PHASE_NAMES)
+        return float(buf[n + 1]), int(buf[n + 2])
 
     def close(self):
         if self.ctx:
