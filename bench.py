@@ -121,6 +121,28 @@ def main():
     print("timed: %.1f ms/step, phases (ms/step): %s" % (
         ms_per_step, {a: round(b / max(1, ncalls), 2) for a, b in phases.items()}), file=sys.stderr, flush=True)
 
+    # adjoint (gJ = G^H gA) and source-position gradient on the same build,
+    # timed like the forward step (same number of steps, after one warm-up)
+    gA = torch.tensor(inputs.cotangent(args.n, n_rhs=args.rhs, seed=0), device=dev).reshape(args.rhs, args.n, 3)
+    gJ = torch.empty_like(A)
+    fmm.evaluate_adjoint(gA, out=gJ)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(args.steps):
+        fmm.evaluate_adjoint(gA, out=gJ)
+    torch.cuda.synchronize()
+    adj_s = (time.time() - t0) / args.steps
+    gX = torch.empty((args.n, 3), dtype=torch.float64, device=dev)
+    fmm.grad_src_xyz(Jt.reshape(args.rhs, args.n, 3), gA, out=gX)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(args.steps):
+        fmm.grad_src_xyz(Jt.reshape(args.rhs, args.n, 3), gA, out=gX)
+    torch.cuda.synchronize()
+    grad_s = (time.time() - t0) / args.steps
+    print("adjoint: %.1f ms/step, source gradient: %.1f ms/step" % (1e3 * adj_s, 1e3 * grad_s),
+          file=sys.stderr, flush=True)
+
     acc = None
     if not args.no_accuracy:
         fn = os.path.join(ROOT, "tests", "golden", "three_%d_sparse400_oracle.npz" % args.n)
@@ -158,6 +180,10 @@ def main():
         "build_s": build_s,
         "cold_targets_per_s": args.n * args.rhs / (build_s + wall / args.steps),
         "phase_ms_per_step": {a: b / max(1, ncalls) for a, b in phases.items()},
+        "adjoint": {"targets_per_s": args.n * args.rhs / adj_s, "ms_per_step": 1e3 * adj_s,
+                    "vs_forward": (wall / args.steps) / adj_s},
+        "grad_src_xyz": {"targets_per_s": args.n * args.rhs / grad_s, "ms_per_step": 1e3 * grad_s,
+                         "vs_forward": (wall / args.steps) / grad_s},
     }
     print(json.dumps(out), flush=True)
 

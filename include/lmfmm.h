@@ -109,12 +109,55 @@ int lm_set_params(lm_ctx* ctx, const lm_params* prm);
 int lm_build(lm_ctx* ctx, int64_t n_src, const double* src_xyz, int64_t n_tgt,
              const double* tgt_xyz, void* stream);
 
+/* Builds several independent geometries into one plan, so that every later
+ * lm_evaluate / lm_evaluate_adjoint / lm_grad_src_xyz processes all of them
+ * with one launch per pass (many small problems at the occupancy of one
+ * large one).  Geometry g owns the sources src_off[g] .. src_off[g+1]-1 and
+ * the targets tgt_off[g] .. tgt_off[g+1]-1 of the concatenated HOST arrays
+ * src_xyz / tgt_xyz; only sources and targets of the same geometry interact
+ * (each geometry is the sum of Sec. 3.3 on its own points, with its own
+ * trees).  src_off, tgt_off: HOST int64 [n_geom+1], starting at 0,
+ * non-decreasing; J and A of the evaluations are the concatenations in the
+ * same order.  Otherwise as lm_build.  LM_EINVAL for bad offsets. */
+int lm_build_batch(lm_ctx* ctx, int n_geom, const int64_t* src_off, const double* src_xyz,
+                   const int64_t* tgt_off, const double* tgt_xyz, void* stream);
+
 /* Evaluates A = G J for n_rhs right-hand sides on the built geometry.
  * J: DEVICE complex128 [n_rhs][n_src][3]; A: DEVICE complex128
  * [n_rhs][n_tgt][3], overwritten.  All work is enqueued on `stream`
  * (asynchronous: the call returns before the results are ready).  The
  * summation order is fixed, so repeated calls give bitwise equal results. */
 int lm_evaluate(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream);
+
+/* Adjoint evaluation (the conjugate transpose of lm_evaluate's operator):
+ *     gJ_j = sum_i G(x_i, x_j)^H gA_i      (x_i targets, x_j sources),
+ * for n_rhs vectors.  gA: DEVICE complex128 [n_rhs][n_tgt][3]; gJ: DEVICE
+ * complex128 [n_rhs][n_src][3], overwritten.  Computed through the
+ * reciprocity of the layered Green's function, G(x, y) = G(y, x)^T (Sec. 3.3,
+ * mu = 1): gJ = conj(G~ conj(gA)) with G~ the forward sum with sources and
+ * targets exchanged.  When the source and target arrays given to lm_build
+ * are the same point set this is the built FMM itself; otherwise a second
+ * FMM with the roles exchanged is built on the first call (which then
+ * synchronises `stream` once and allocates; later calls reuse it).  The
+ * result equals G^H gA to the FMM's accuracy (it is the adjoint of the exact
+ * operator, not the exact transpose of the discrete FMM).  Asynchronous on
+ * `stream` otherwise; errors as lm_evaluate. */
+int lm_evaluate_adjoint(lm_ctx* ctx, int n_rhs, const void* gA, void* gJ, void* stream);
+
+/* Gradient with respect to the source positions (targets fixed) of a real
+ * loss L whose gradient with respect to A is gA (gA = dL/dRe A + i dL/dIm A,
+ * the convention of complex autograd):
+ *     gX_j = sum_r Re sum_i gA_{r,i}^H (d/dx_j G(x_i, x_j)) J_{r,j},
+ * summed over the n_rhs right-hand sides.  J: DEVICE complex128
+ * [n_rhs][n_src][3] (the currents of the forward evaluation); gA: DEVICE
+ * complex128 [n_rhs][n_tgt][3]; gX: DEVICE fp64 [n_src][3], overwritten.
+ * Uses the same reciprocity as lm_evaluate_adjoint: the field of the
+ * currents conj(gA) placed at the targets is differentiated at the source
+ * points (ladder relations of the regular wave functions on the local
+ * expansions, closed-form derivative of the free-space dyadic in the near
+ * field) and contracted with J.  Build, stream and error behaviour as
+ * lm_evaluate_adjoint. */
+int lm_grad_src_xyz(lm_ctx* ctx, int n_rhs, const void* J, const void* gA, double* gX, void* stream);
 
 /* Phase timing.  lm_set_timing(ctx, 1) (re)starts recording HIP events on
  * the evaluation stream between the phases of every following lm_evaluate

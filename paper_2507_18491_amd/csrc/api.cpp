@@ -51,7 +51,16 @@ struct lm_ctx {
   int pmax = 0;
   bool timing = false;
   std::vector<std::vector<hipEvent_t>> evsets;  // per timed evaluation: LM_PHASES+1 events
+  // adjoint and gradients
+  bool same_sets = false;                 // sources and targets are the same point array
+  std::vector<double> host_src, host_tgt;  // kept when they differ (for the swapped build)
+  std::vector<int64_t> host_soff, host_toff;
+  lm_ctx* adj = nullptr;                   // swapped-role context (built on first use)
+  cd* Jc = nullptr;                        // conjugated-input scratch
+  long long jc_cap = 0;
 };
+
+extern "C" int lm_destroy(lm_ctx* ctx);
 
 static void clear_events(lm_ctx* ctx) {
   for (auto& v : ctx->evsets)
@@ -97,6 +106,16 @@ static void free_build(lm_ctx* ctx) {
   ctx->p2p_inst.clear();
   memset(&ctx->d, 0, sizeof(ctx->d));
   ctx->built = false;
+  if (ctx->adj) lm_destroy(ctx->adj);
+  ctx->adj = nullptr;
+  if (ctx->Jc) hipFree(ctx->Jc);
+  ctx->Jc = nullptr;
+  ctx->jc_cap = 0;
+  ctx->same_sets = false;
+  ctx->host_src.clear();
+  ctx->host_tgt.clear();
+  ctx->host_soff.clear();
+  ctx->host_toff.clear();
 }
 
 template <class T>
@@ -226,12 +245,36 @@ static bool finite_pts(const double* x, int64_t n) {
   return true;
 }
 
+static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const double* src_xyz, const int64_t* toff,
+                        const double* tgt_xyz, void* stream);
+
 int lm_build(lm_ctx* ctx, int64_t n_src, const double* src_xyz, int64_t n_tgt, const double* tgt_xyz,
              void* stream) {
   if (!ctx) return LM_EINVAL;
   if (!ctx->layers_set) return fail(ctx, LM_ESTATE, "lm_set_layers must be called before lm_build");
   if (n_src < 0 || n_tgt < 0 || (n_src > 0 && !src_xyz) || (n_tgt > 0 && !tgt_xyz))
     return fail(ctx, LM_EINVAL, "invalid point arrays");
+  int64_t so[2] = {0, n_src}, to[2] = {0, n_tgt};
+  return build_common(ctx, 1, so, src_xyz, to, tgt_xyz, stream);
+}
+
+int lm_build_batch(lm_ctx* ctx, int n_geom, const int64_t* src_off, const double* src_xyz, const int64_t* tgt_off,
+                   const double* tgt_xyz, void* stream) {
+  if (!ctx) return LM_EINVAL;
+  if (!ctx->layers_set) return fail(ctx, LM_ESTATE, "lm_set_layers must be called before lm_build_batch");
+  if (n_geom < 1 || n_geom > 65536 || !src_off || !tgt_off) return fail(ctx, LM_EINVAL, "invalid geometry count or offsets");
+  if (src_off[0] != 0 || tgt_off[0] != 0) return fail(ctx, LM_EINVAL, "offsets must start at 0");
+  for (int g = 0; g < n_geom; g++)
+    if (src_off[g + 1] < src_off[g] || tgt_off[g + 1] < tgt_off[g])
+      return fail(ctx, LM_EINVAL, "offsets must be non-decreasing");
+  if ((src_off[n_geom] > 0 && !src_xyz) || (tgt_off[n_geom] > 0 && !tgt_xyz))
+    return fail(ctx, LM_EINVAL, "invalid point arrays");
+  return build_common(ctx, n_geom, src_off, src_xyz, tgt_off, tgt_xyz, stream);
+}
+
+static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const double* src_xyz, const int64_t* toff,
+                        const double* tgt_xyz, void* stream) {
+  const int64_t n_src = soff[n_geom], n_tgt = toff[n_geom];
   if (n_src > 2000000000LL || n_tgt > 2000000000LL) return fail(ctx, LM_EINVAL, "too many points");
   if (!finite_pts(src_xyz, n_src) || !finite_pts(tgt_xyz, n_tgt)) return fail(ctx, LM_EINVAL, "non-finite coordinates");
   const Medium& med = ctx->med;
@@ -247,7 +290,7 @@ int lm_build(lm_ctx* ctx, int64_t n_src, const double* src_xyz, int64_t n_tgt, c
   hipStream_t s = (hipStream_t)stream;
   free_build(ctx);
   auto t0 = std::chrono::steady_clock::now();
-  std::string msg = lm_make_plan(ctx->plan, med, ctx->prm, n_src, src_xyz, n_tgt, tgt_xyz);
+  std::string msg = lm_make_plan_multi(ctx->plan, med, ctx->prm, n_geom, soff, src_xyz, toff, tgt_xyz);
   if (!msg.empty()) return fail(ctx, LM_EDOMAIN, msg);
   auto t1 = std::chrono::steady_clock::now();
   Plan& pl = ctx->plan;
@@ -379,6 +422,15 @@ int lm_build(lm_ctx* ctx, int64_t n_src, const double* src_xyz, int64_t n_tgt, c
   ctx->t_plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   ctx->t_upload_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
   ctx->t_tables_ms = std::chrono::duration<double, std::milli>(t3 - t2).count();
+  ctx->same_sets = n_src == n_tgt && memcmp(soff, toff, (size_t)(n_geom + 1) * sizeof(int64_t)) == 0 &&
+                   (src_xyz == tgt_xyz || n_src == 0 ||
+                    memcmp(src_xyz, tgt_xyz, (size_t)n_src * 3 * sizeof(double)) == 0);
+  if (!ctx->same_sets) {
+    ctx->host_src.assign(src_xyz, src_xyz + 3 * n_src);
+    ctx->host_tgt.assign(tgt_xyz, tgt_xyz + 3 * n_tgt);
+    ctx->host_soff.assign(soff, soff + n_geom + 1);
+    ctx->host_toff.assign(toff, toff + n_geom + 1);
+  }
   ctx->built = true;
   return LM_OK;
 }
@@ -477,7 +529,8 @@ static int ensure_rhs(lm_ctx* ctx, int n_rhs, hipStream_t s) {
   return LM_OK;
 }
 
-static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream);
+static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream, const cd* W = nullptr,
+                          double* gX = nullptr);
 
 #define LM_RHS_CHUNK 16
 
@@ -498,12 +551,119 @@ int lm_evaluate(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream) {
   return LM_OK;
 }
 
-static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream) {
+// One group of right-hand sides.  Normal mode (gX == nullptr): A = G J.
+// Gradient mode: the upward pass and M2L run on J as usual, then instead of
+// writing A the leaf passes add, at every target point, Re sum_b W^b grad B_b
+// (B the field of J) into gX [n_tgt][3]; A is not touched.
+// The context that evaluates the transposed operator: by reciprocity
+// (G(x, y) = G(y, x)^T), sum_i G(x_i, x_j)^T v_i is the forward sum with the
+// roles of sources and targets exchanged.  That is this context when the two
+// point sets are the same array, otherwise a second context built (once, on
+// the first call) with the sets swapped.
+static int swapped_ctx(lm_ctx* ctx, hipStream_t s, lm_ctx** out) {
+  *out = nullptr;
+  if (ctx->same_sets) {
+    *out = ctx;
+    return LM_OK;
+  }
+  if (!ctx->adj) {
+    lm_ctx* a = nullptr;
+    int rc = lm_create(&a, ctx->device);
+    if (rc) return fail(ctx, rc, "cannot create the swapped-role context");
+    a->med = ctx->med;
+    a->layers_set = true;
+    a->prm = ctx->prm;
+    int ng = (int)ctx->host_soff.size() - 1;
+    rc = build_common(a, ng, ctx->host_toff.data(), ctx->host_tgt.data(), ctx->host_soff.data(),
+                      ctx->host_src.data(), s);
+    if (rc) {
+      std::string m = a->err;
+      lm_destroy(a);
+      return fail(ctx, rc, "swapped-role build: " + m);
+    }
+    ctx->adj = a;
+  }
+  *out = ctx->adj;
+  return LM_OK;
+}
+
+static int ensure_jc(lm_ctx* ctx, long long n, hipStream_t s) {
+  if (n <= ctx->jc_cap) return LM_OK;
+  HIPC(hipStreamSynchronize(s));
+  if (ctx->Jc) hipFree(ctx->Jc);
+  ctx->Jc = nullptr;
+  ctx->jc_cap = 0;
+  HIPC(hipMalloc((void**)&ctx->Jc, (size_t)std::max(1LL, n) * sizeof(cd)));
+  ctx->jc_cap = n;
+  return LM_OK;
+}
+
+int lm_evaluate_adjoint(lm_ctx* ctx, int n_rhs, const void* gA, void* gJ, void* stream) {
+  if (!ctx) return LM_EINVAL;
+  if (!ctx->built) return fail(ctx, LM_ESTATE, "lm_build must succeed before lm_evaluate_adjoint");
+  if (n_rhs < 1 || n_rhs > 4096) return fail(ctx, LM_EINVAL, "n_rhs out of range (1..4096)");
+  Plan& pl = ctx->plan;
+  if ((pl.n_tgt > 0 && !gA) || (pl.n_src > 0 && !gJ)) return fail(ctx, LM_EINVAL, "null gA or gJ");
+  if (((uintptr_t)gA % 16) || ((uintptr_t)gJ % 16)) return fail(ctx, LM_EINVAL, "gA and gJ must be 16-byte aligned");
+  HIPC(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  lm_ctx* T = nullptr;
+  int rc = swapped_ctx(ctx, s, &T);
+  if (rc) return rc;
+  int nr0 = std::min(LM_RHS_CHUNK, n_rhs);
+  if ((rc = ensure_jc(ctx, (long long)nr0 * pl.n_tgt * 3, s))) return rc;
+  for (int r0 = 0; r0 < n_rhs; r0 += LM_RHS_CHUNK) {
+    int nr = std::min(LM_RHS_CHUNK, n_rhs - r0);
+    const cd* g = (const cd*)gA + (long long)r0 * pl.n_tgt * 3;
+    cd* o = (cd*)gJ + (long long)r0 * pl.n_src * 3;
+    launch_conj(ctx->Jc, g, (long long)nr * pl.n_tgt * 3, s);
+    rc = evaluate_chunk(T, nr, ctx->Jc, o, stream);
+    if (rc) return T == ctx ? rc : fail(ctx, rc, "swapped-role evaluation: " + T->err);
+    launch_conj(o, o, (long long)nr * pl.n_src * 3, s);
+  }
+  HIPC(hipGetLastError());
+  return LM_OK;
+}
+
+int lm_grad_src_xyz(lm_ctx* ctx, int n_rhs, const void* J, const void* gA, double* gX, void* stream) {
+  if (!ctx) return LM_EINVAL;
+  if (!ctx->built) return fail(ctx, LM_ESTATE, "lm_build must succeed before lm_grad_src_xyz");
+  if (n_rhs < 1 || n_rhs > 4096) return fail(ctx, LM_EINVAL, "n_rhs out of range (1..4096)");
+  Plan& pl = ctx->plan;
+  if ((pl.n_src > 0 && (!J || !gX)) || (pl.n_tgt > 0 && !gA)) return fail(ctx, LM_EINVAL, "null J, gA or gX");
+  if (((uintptr_t)J % 16) || ((uintptr_t)gA % 16) || ((uintptr_t)gX % 8))
+    return fail(ctx, LM_EINVAL, "J and gA must be 16-byte aligned, gX 8-byte aligned");
+  HIPC(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  lm_ctx* T = nullptr;
+  int rc = swapped_ctx(ctx, s, &T);
+  if (rc) return rc;
+  launch_fill_d(gX, 3 * pl.n_src, s);
+  if (pl.n_src == 0 || pl.n_tgt == 0) {
+    HIPC(hipGetLastError());
+    return LM_OK;
+  }
+  int nr0 = std::min(LM_RHS_CHUNK, n_rhs);
+  if ((rc = ensure_jc(ctx, (long long)nr0 * pl.n_tgt * 3, s))) return rc;
+  for (int r0 = 0; r0 < n_rhs; r0 += LM_RHS_CHUNK) {
+    int nr = std::min(LM_RHS_CHUNK, n_rhs - r0);
+    const cd* g = (const cd*)gA + (long long)r0 * pl.n_tgt * 3;
+    const cd* w = (const cd*)J + (long long)r0 * pl.n_src * 3;
+    launch_conj(ctx->Jc, g, (long long)nr * pl.n_tgt * 3, s);
+    rc = evaluate_chunk(T, nr, ctx->Jc, nullptr, stream, w, gX);
+    if (rc) return T == ctx ? rc : fail(ctx, rc, "swapped-role evaluation: " + T->err);
+  }
+  HIPC(hipGetLastError());
+  return LM_OK;
+}
+
+static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream, const cd* W, double* gX) {
   if (!ctx) return LM_EINVAL;
   if (!ctx->built) return fail(ctx, LM_ESTATE, "lm_build must succeed before lm_evaluate");
   if (n_rhs < 1 || n_rhs > 4096) return fail(ctx, LM_EINVAL, "n_rhs out of range (1..4096)");
   Plan& pl = ctx->plan;
-  if ((pl.n_src > 0 && !J) || (pl.n_tgt > 0 && !A)) return fail(ctx, LM_EINVAL, "null J or A");
+  const bool grad = gX != nullptr;
+  if ((pl.n_src > 0 && !J) || (pl.n_tgt > 0 && !grad && !A)) return fail(ctx, LM_EINVAL, "null J or A");
   if (((uintptr_t)J % 16) || ((uintptr_t)A % 16)) return fail(ctx, LM_EINVAL, "J and A must be 16-byte aligned");
   HIPC(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
@@ -523,7 +683,7 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
     if (!ev.empty()) (void)hipEventRecord(ev[i], s);
   };
   mark(0);
-  launch_fill(Ac, (long long)n_rhs * pl.n_tgt * 3, s);
+  if (!grad) launch_fill(Ac, (long long)n_rhs * pl.n_tgt * 3, s);
   if (pl.n_src > 0 && pl.n_tgt > 0) launch_fill(ctx->LE, pl.le_size * n_rhs, s);
   mark(1);
   if (pl.n_src > 0 && pl.n_tgt > 0) {
@@ -543,14 +703,23 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
     for (int l = 1; l < (int)ctx->d_l2l.size(); l++)
       launch_l2l(d, ctx->d_l2l[l], ctx->n_l2l[l], n_rhs, ctx->LE, ctx->pmax, s);
     mark(5);
-    for (size_t i = 0; i < pl.inst.size(); i++)
-      launch_l2p(d, ctx->d_l2p[i], ctx->n_l2p[i], pl.inst[i].kind == 0 ? 0 : 1, ctx->d_tgt, pl.n_tgt, n_rhs,
-                 ctx->LE, Ac, ctx->pmax, s);
+    for (size_t i = 0; i < pl.inst.size(); i++) {
+      int kind = pl.inst[i].kind == 0 ? 0 : 1;
+      if (grad)
+        launch_l2p_grad(d, ctx->d_l2p[i], ctx->n_l2p[i], kind, ctx->d_tgt, pl.n_tgt, n_rhs, ctx->LE, W, gX,
+                        ctx->pmax, s);
+      else
+        launch_l2p(d, ctx->d_l2p[i], ctx->n_l2p[i], kind, ctx->d_tgt, pl.n_tgt, n_rhs, ctx->LE, Ac, ctx->pmax, s);
+    }
     mark(6);
     for (size_t f = 0; f < ctx->d_p2p.size(); f++) {
       int i = ctx->p2p_inst[f];
-      launch_p2p(d, ctx->d_p2p[f], ctx->n_p2p[f], ctx->d_src, Jc, pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs,
-                 pl.inst[i].kt, Ac, s);
+      if (grad)
+        launch_p2p_grad(d, ctx->d_p2p[f], ctx->n_p2p[f], ctx->d_src, Jc, pl.n_src, ctx->d_tgt, W, pl.n_tgt, n_rhs,
+                        pl.inst[i].kt, gX, s);
+      else
+        launch_p2p(d, ctx->d_p2p[f], ctx->n_p2p[f], ctx->d_src, Jc, pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs,
+                   pl.inst[i].kt, Ac, s);
     }
     mark(7);
   } else {

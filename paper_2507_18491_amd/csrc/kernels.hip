@@ -794,6 +794,262 @@ void launch_p2p(const DevPlan& d, const int* tboxes, int n, const double* sxyz, 
                        n_rhs, k, A);
 }
 
+// ------------------------------------------------------------------ gradients
+// Source-position gradients use reciprocity, G(x, y) = G(y, x)^T (the
+// reciprocity of the layered Green's function, Sec. 3.3): with the currents
+// conj(gA) placed at the targets, the field B(y) = sum_i G(y, x_i) conj(gA_i)
+// is evaluated with its gradient at the source points and contracted with
+// the source currents,  gX_j = Re sum_b J_j^b grad B_b(x_j).  The kernels
+// below evaluate that contraction for the far field (from the local
+// expansions) and for the free-space near field.  Each point is owned by one
+// thread of one block per launch, and right-hand sides are taken in order,
+// so the accumulation into gX is deterministic.
+
+// out = conj(in)
+__global__ void k_conj(cd* out, const cd* in, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += st) out[i] = cconj(in[i]);
+}
+__global__ void k_fill_d(double* p, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += st) p[i] = 0.0;
+}
+void launch_fill_d(double* p, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  long long nb = std::min<long long>((n + NT - 1) / NT, 65536);
+  hipLaunchKernelGGL(k_fill_d, dim3((unsigned)nb), dim3(NT), 0, s, p, n);
+}
+void launch_conj(cd* out, const cd* in, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  long long nb = std::min<long long>((n + NT - 1) / NT, 65536);
+  hipLaunchKernelGGL(k_conj, dim3((unsigned)nb), dim3(NT), 0, s, out, in, n);
+}
+
+// Far field: the local expansion (3 spin channels) is turned into the
+// expansion of the field (free space: U + grad div U / k^2, order p + 2;
+// reaction: the LE itself, order p), then the three derivatives
+// (d/dx + i d/dy, d/dx - i d/dy, d/dz, exact ladder relations of the regular
+// wave functions) give 9 expansions of one order more, evaluated at every
+// point of the leaf.  For a reaction component the evaluation point is the
+// effective location zhat = at z + bt, so d/dz = at d/dzhat.
+__global__ __launch_bounds__(NT) void k_l2p_grad(DevPlan d, const int* leaves, int kind, const double* xyz,
+                                                 long long n_pts, int n_rhs, const cd* LE, const cd* W,
+                                                 double* gX) {
+  extern __shared__ cd Ls[];
+  int b = leaves[blockIdx.x];
+  TgtBox tb = d.tbox[b];
+  InstParams ip = d.inst[tb.inst];
+  int p = ip.p, P = ip.P;
+  int pa = (kind == 0) ? p + 2 : p;  // order of the field expansion
+  int pg = pa + 1, Pg = (pg + 1) * (pg + 1);
+  int Pd = (p + 2) * (p + 2);
+  int tid = threadIdx.x;
+  double k = ip.kt;
+  cd* Lc = Ls;            // [3][Pg]   field expansion (order pa)
+  cd* Dv = Ls + 3 * Pg;   // [Pd]      k x divergence (free space)
+  cd* Gc = Dv + Pd;       // [9][Pg]   (channel, direction) derivative expansions
+  for (int r = 0; r < n_rhs; r++) {
+    __syncthreads();
+    for (int e = tid; e < 3 * Pg; e += NT) {
+      int c = e / Pg, nm = e - c * Pg;
+      Lc[e] = nm < P ? LE[tb.le_off * n_rhs + ((long long)r * 3 + c) * P + nm] : cd{0, 0};
+    }
+    __syncthreads();
+    if (kind == 0) {
+      for (int nm = tid; nm < Pd; nm += NT) {
+        int n = n_of(nm), m = nm - n * n - n;
+        cd v = 0.5 * (dapply(Lc + Pg, p, 0, n, m) + dapply(Lc, p, 1, n, m)) + dapply(Lc + 2 * Pg, p, 2, n, m);
+        Dv[nm] = k * v;
+      }
+      __syncthreads();
+      int Pa = (pa + 1) * (pa + 1);
+      for (int e = tid; e < 3 * Pa; e += NT) {
+        int c = e / Pa, nm = e - c * Pa;
+        int n = n_of(nm), m = nm - n * n - n;
+        Lc[c * Pg + nm] = Lc[c * Pg + nm] + (1.0 / k) * dapply(Dv, p + 1, c, n, m);
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < 9 * Pg; e += NT) {
+      int cd_ = e / Pg, nm = e - cd_ * Pg;
+      int c = cd_ / 3, dir = cd_ - 3 * c;
+      int n = n_of(nm), m = nm - n * n - n;
+      Gc[e] = dapply(Lc + c * Pg, pa, dir, n, m);
+    }
+    __syncthreads();
+    for (int t0 = tb.pt0; t0 < tb.pt1; t0 += NT) {
+      int ti = t0 + tid;
+      if (ti >= tb.pt1) continue;
+      int id = d.tgt_perm[ti];
+      double dx = xyz[3 * id] - tb.c[0], dy = xyz[3 * id + 1] - tb.c[1];
+      double dz = ip.at * xyz[3 * id + 2] + ip.bt - tb.c[2];
+      double rxy = sqrt(dx * dx + dy * dy), rr_ = sqrt(dx * dx + dy * dy + dz * dz);
+      double ct = rr_ > 0 ? dz / rr_ : 1.0, st = rr_ > 0 ? rxy / rr_ : 0.0;
+      cd e1 = rxy > 0 ? cd{dx / rxy, dy / rxy} : cd{1.0, 0.0};
+      double jn[LM_PMAX + 5];
+      sph_jn(pg, k * rr_, jn);
+      cd acc[9];
+      for (int q = 0; q < 9; q++) acc[q] = cd{0, 0};
+      double pmm = LM_INV_SQRT_4PI;
+      cd em = cd{1.0, 0.0};
+      for (int m = 0; m <= pg; m++) {
+        if (m > 0) {
+          pmm = -sqrt((2.0 * m + 1.0) / (2.0 * m)) * st * pmm;
+          em = em * e1;
+        }
+        double p2 = 0.0, p1 = pmm;
+        for (int n = m; n <= pg; n++) {
+          double pn;
+          if (n == m)
+            pn = pmm;
+          else if (n == m + 1)
+            pn = sqrt(2.0 * m + 3.0) * ct * pmm;
+          else {
+            double a = sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));
+            double bb = sqrt(((n - 1.0) * (n - 1.0) - (double)m * m) / (4.0 * (n - 1.0) * (n - 1.0) - 1.0));
+            pn = a * (ct * p1 - bb * p2);
+          }
+          if (n > m) {
+            p2 = p1;
+            p1 = pn;
+          }
+          double rad = jn[n] * pn;
+          cd bp = rad * em;
+          cd bm = ((m & 1) ? -rad : rad) * cconj(em);
+          int ip_ = nm_idx(n, m), im_ = nm_idx(n, -m);
+          for (int q = 0; q < 9; q++) {
+            acc[q] = acc[q] + Gc[q * Pg + ip_] * bp;
+            if (m > 0) acc[q] = acc[q] + Gc[q * Pg + im_] * bm;
+          }
+        }
+      }
+      // derivatives of the spin channels: D+ = d/dx + i d/dy, D- = d/dx - i d/dy
+      // (both times 1/k in acc), d/dz (times 1/k, in zhat)
+      cd dB[3][3];  // [cartesian direction][spin channel]
+      for (int c = 0; c < 3; c++) {
+        cd dp = k * acc[c * 3 + 0], dm = k * acc[c * 3 + 1], dzv = (k * ip.at) * acc[c * 3 + 2];
+        dB[0][c] = 0.5 * (dp + dm);
+        cd h = 0.5 * (dp - dm);
+        dB[1][c] = cd{h.y, -h.x};  // (dp - dm) / (2i)
+        dB[2][c] = dzv;
+      }
+      const cd* w = W + ((long long)r * n_pts + id) * 3;
+      cd wx = w[0], wy = w[1], wz = w[2];
+      for (int a = 0; a < 3; a++) {
+        // cartesian field components from the spin channels
+        cd bx = 0.5 * (dB[a][0] + dB[a][1]);
+        cd h = 0.5 * (dB[a][0] - dB[a][1]);
+        cd by = cd{h.y, -h.x};
+        cd bz = dB[a][2];
+        cd v = wx * bx + wy * by + wz * bz;
+        gX[3 * id + a] += v.x;
+      }
+    }
+  }
+}
+void launch_l2p_grad(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_pts,
+                     int n_rhs, const cd* LE, const cd* W, double* gX, int pmax, hipStream_t s) {
+  if (n <= 0) return;
+  int pg = pmax + 3;
+  int Pg = (pg + 1) * (pg + 1), Pd = (pmax + 2) * (pmax + 2);
+  size_t shm = (size_t)(12 * Pg + Pd) * sizeof(cd);
+  hipFuncSetAttribute((const void*)k_l2p_grad, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL(k_l2p_grad, dim3(n), dim3(NT), shm, s, d, leaves, kind, xyz, n_pts, n_rhs, LE, W, gX);
+}
+
+// Free-space near field: for the target point x_i (here a source point of
+// the original problem, weights w = its currents) and near sources x_j with
+// currents s_j:  G_bc(R) = a(r) delta_bc + b(r) u_b u_c, R = x_i - x_j,
+// u = R / r, and
+//   sum_bc w_b d_alpha G_bc s_c = u_alpha [a' (w.s) + (b' - 2 b / r)(w.u)(u.s)]
+//                                  + (b / r) [w_alpha (u.s) + s_alpha (w.u)].
+__global__ __launch_bounds__(NT) void k_p2p_grad(DevPlan d, const int* tboxes, const double* sxyz, const cd* Jsrc,
+                                                 long long n_src, const double* txyz, const cd* W,
+                                                 long long n_tgt, int n_rhs, double k, double* gX) {
+  __shared__ double sp[NT][3];
+  __shared__ cd sj[NT][3];
+  int b = tboxes[blockIdx.x];
+  TgtBox tb = d.tbox[b];
+  int tid = threadIdx.x;
+  const double inv4pi = 0.079577471545947667884;
+  for (int r = 0; r < n_rhs; r++) {
+    for (int t0 = tb.pt0; t0 < tb.pt1; t0 += NT) {
+      int ti = t0 + tid;
+      bool act = ti < tb.pt1;
+      int id = act ? d.tgt_perm[ti] : 0;
+      double x0 = act ? txyz[3 * id] : 0, y0 = act ? txyz[3 * id + 1] : 0, z0 = act ? txyz[3 * id + 2] : 0;
+      cd wx = cd{0, 0}, wy = cd{0, 0}, wz = cd{0, 0};
+      if (act) {
+        const cd* w = W + ((long long)r * n_tgt + id) * 3;
+        wx = w[0];
+        wy = w[1];
+        wz = w[2];
+      }
+      double g0 = 0, g1 = 0, g2 = 0;
+      for (int li = tb.p2p0; li < tb.p2p1; li++) {
+        SrcBox sb = d.sbox[d.p2p_list[li]];
+        for (int s0 = sb.pt0; s0 < sb.pt1; s0 += NT) {
+          int ns = min(NT, sb.pt1 - s0);
+          __syncthreads();
+          if (tid < ns) {
+            int sid = d.src_perm[s0 + tid];
+            sp[tid][0] = sxyz[3 * sid];
+            sp[tid][1] = sxyz[3 * sid + 1];
+            sp[tid][2] = sxyz[3 * sid + 2];
+            for (int c = 0; c < 3; c++) sj[tid][c] = Jsrc[((long long)r * n_src + sid) * 3 + c];
+          }
+          __syncthreads();
+          if (act) {
+            for (int j = 0; j < ns; j++) {
+              double rx = x0 - sp[j][0], ry = y0 - sp[j][1], rz = z0 - sp[j][2];
+              double r2 = rx * rx + ry * ry + rz * rz;
+              if (r2 == 0.0) continue;
+              double rd = sqrt(r2), ir = 1.0 / rd;
+              double kr = k * rd, ikr = 1.0 / kr, ikr2 = ikr * ikr, ikr3 = ikr2 * ikr;
+              double sn, cs;
+              sincos(kr, &sn, &cs);
+              cd g = cd{cs * inv4pi * ir, sn * inv4pi * ir};
+              cd gp = g * cd{-ir, k};                          // g' = g (ik - 1/r)
+              cd fa = cd{1.0 - ikr2, ikr}, fb = cd{-1.0 + 3.0 * ikr2, -3.0 * ikr};
+              cd dfa = k * cd{2.0 * ikr3, -ikr2};              // d fa / dr
+              cd dfb = k * cd{-6.0 * ikr3, 3.0 * ikr2};        // d fb / dr
+              cd a = g * fa, bq = g * fb;
+              cd ap = gp * fa + g * dfa, bp = gp * fb + g * dfb;
+              double ux = rx * ir, uy = ry * ir, uz = rz * ir;
+              cd sx = sj[j][0], sy = sj[j][1], sz = sj[j][2];
+              cd ws = wx * sx + wy * sy + wz * sz;
+              cd wu = ux * wx + uy * wy + uz * wz;
+              cd us = ux * sx + uy * sy + uz * sz;
+              cd radial = ap * ws + (bp - (2.0 * ir) * bq) * (wu * us);
+              cd br = ir * bq;
+              cd v0 = ux * radial + br * (wx * us + sx * wu);
+              cd v1 = uy * radial + br * (wy * us + sy * wu);
+              cd v2 = uz * radial + br * (wz * us + sz * wu);
+              g0 += v0.x;
+              g1 += v1.x;
+              g2 += v2.x;
+            }
+          }
+        }
+      }
+      if (act) {
+        gX[3 * id] += g0;
+        gX[3 * id + 1] += g1;
+        gX[3 * id + 2] += g2;
+      }
+    }
+  }
+}
+void launch_p2p_grad(const DevPlan& d, const int* tboxes, int n, const double* sxyz, const cd* Jsrc,
+                     long long n_src, const double* txyz, const cd* W, long long n_tgt, int n_rhs, double k,
+                     double* gX, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_p2p_grad, dim3(n), dim3(NT), 0, s, d, tboxes, sxyz, Jsrc, n_src, txyz, W, n_tgt, n_rhs, k,
+                     gX);
+}
+
 // ------------------------------------------------------------------ translation tables
 // (R|R) and (S|R) by the addition theorem of wave functions written with
 // Gaunt coefficients G = int Y^mu_nu conj(Y^m_n) conj(Y^{mu-m}_q):

@@ -381,9 +381,11 @@ namespace {
 struct MatKey {
   int kind;  // 0 free M2L, 1 M2M, 2 L2L
   long long kq;  // quantised wavenumber
-  int p, level, a, b, c;
+  int p;
+  long long sq;  // quantised box size of the level
+  int a, b, c;
   bool operator<(const MatKey& o) const {
-    return std::tie(kind, kq, p, level, a, b, c) < std::tie(o.kind, o.kq, o.p, o.level, o.a, o.b, o.c);
+    return std::tie(kind, kq, p, sq, a, b, c) < std::tie(o.kind, o.kq, o.p, o.sq, o.a, o.b, o.c);
   }
 };
 
@@ -391,36 +393,22 @@ struct MatKey {
 
 std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int64_t n_src,
                          const double* src, int64_t n_tgt, const double* tgt) {
+  int64_t so[2] = {0, n_src}, to[2] = {0, n_tgt};
+  return lm_make_plan_multi(pl, med, prm, 1, so, src, to, tgt);
+}
+
+std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& prm, int n_geom,
+                               const int64_t* src_off, const double* src, const int64_t* tgt_off,
+                               const double* tgt) {
   pl = Plan();
   pl.med = med;
   pl.prm = prm;
   pl.p = prm.p;
   pl.pf = prm.p_free > 0 ? prm.p_free : prm.p;
-  pl.n_src = n_src;
-  pl.n_tgt = n_tgt;
+  pl.n_src = src_off[n_geom];
+  pl.n_tgt = tgt_off[n_geom];
   int L = med.n - 1;
   int pmax = std::max(pl.p, pl.pf);
-
-  // layer membership
-  std::vector<std::vector<int>> src_in(med.n), tgt_in(med.n);
-  for (int64_t i = 0; i < n_src; i++) src_in[med.layer_of(src[3 * i + 2])].push_back((int)i);
-  for (int64_t i = 0; i < n_tgt; i++) tgt_in[med.layer_of(tgt[3 * i + 2])].push_back((int)i);
-
-  // global lattice: common x-y origin and root size for every tree
-  double xmin = 1e300, ymin = 1e300, xmax = -1e300, ymax = -1e300;
-  for (int64_t i = 0; i < n_src; i++) {
-    xmin = std::min(xmin, src[3 * i]);
-    xmax = std::max(xmax, src[3 * i]);
-    ymin = std::min(ymin, src[3 * i + 1]);
-    ymax = std::max(ymax, src[3 * i + 1]);
-  }
-  for (int64_t i = 0; i < n_tgt; i++) {
-    xmin = std::min(xmin, tgt[3 * i]);
-    xmax = std::max(xmax, tgt[3 * i]);
-    ymin = std::min(ymin, tgt[3 * i + 1]);
-    ymax = std::max(ymax, tgt[3 * i + 1]);
-  }
-  if (n_src == 0 && n_tgt == 0) return "";
 
   // instances
   std::vector<InstParams> comps;
@@ -430,8 +418,33 @@ std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int
     std::vector<int> sid, tid;      // point ids
     std::vector<double> spos, tpos; // positions in instance coordinates
     double zs0, zs1, zt0, zt1;
+    double S0, eps, X0, Y0;         // lattice of the geometry: x-y origin and root size
   };
   std::vector<IGeom> geo;
+  for (int gi = 0; gi < n_geom; gi++) {
+  const int64_t s_lo = src_off[gi], s_hi = src_off[gi + 1], t_lo = tgt_off[gi], t_hi = tgt_off[gi + 1];
+  if (s_hi == s_lo && t_hi == t_lo) continue;
+  size_t geo0 = geo.size();
+
+  // layer membership
+  std::vector<std::vector<int>> src_in(med.n), tgt_in(med.n);
+  for (int64_t i = s_lo; i < s_hi; i++) src_in[med.layer_of(src[3 * i + 2])].push_back((int)i);
+  for (int64_t i = t_lo; i < t_hi; i++) tgt_in[med.layer_of(tgt[3 * i + 2])].push_back((int)i);
+
+  // lattice of this geometry: common x-y origin and root size for every tree
+  double xmin = 1e300, ymin = 1e300, xmax = -1e300, ymax = -1e300;
+  for (int64_t i = s_lo; i < s_hi; i++) {
+    xmin = std::min(xmin, src[3 * i]);
+    xmax = std::max(xmax, src[3 * i]);
+    ymin = std::min(ymin, src[3 * i + 1]);
+    ymax = std::max(ymax, src[3 * i + 1]);
+  }
+  for (int64_t i = t_lo; i < t_hi; i++) {
+    xmin = std::min(xmin, tgt[3 * i]);
+    xmax = std::max(xmax, tgt[3 * i]);
+    ymin = std::min(ymin, tgt[3 * i + 1]);
+    ymax = std::max(ymax, tgt[3 * i + 1]);
+  }
   double ext = std::max(xmax - xmin, ymax - ymin);
   if (prm.components & 1) {
     for (int l = 0; l <= L; l++) {
@@ -499,6 +512,14 @@ std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int
   double eps = 1e-9 * S0;
   double X0 = xmin - eps, Y0 = ymin - eps;
   S0 += 2 * eps;
+  for (size_t q = geo0; q < geo.size(); q++) {
+    geo[q].S0 = S0;
+    geo[q].eps = eps;
+    geo[q].X0 = X0;
+    geo[q].Y0 = Y0;
+  }
+  }  // geometries
+  if (geo.empty()) return "";
 
   auto kquant = [](double k) { return (long long)llround(k * 1e12); };
   std::map<MatKey, long long> matmap;
@@ -523,6 +544,7 @@ std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int
   std::vector<double> off_ratio;  // per M2L offset: (r_s + r_t) / |c_t - c_s|
 
   for (auto& g : geo) {
+    const double S0 = g.S0, eps = g.eps, X0 = g.X0, Y0 = g.Y0;
     InstParams ip = g.ip;
     int inst = (int)pl.inst.size();
     ip.p = ip.kind == 0 ? pl.pf : pl.p;
@@ -638,7 +660,7 @@ std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int
         j.k = ip.ks;
         j.p = ip.p;
         j.kind = 1;
-        mm = alloc_mat(MatKey{1, kquant(ip.ks), ip.p, S.lvl[b], o, 0, 0}, (long long)P * P, &j);
+        mm = alloc_mat(MatKey{1, kquant(ip.ks), ip.p, kquant(S.S(S.lvl[b])), o, 0, 0}, (long long)P * P, &j);
       }
       pl.sbox_m2m.push_back(mm);
       if (S.nchild[b] == 0 && S.a1[b] > S.a0[b]) pl.p2m_leaves.push_back(sbase + b);
@@ -669,7 +691,7 @@ std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int
         j.k = ip.kt;
         j.p = ip.p;
         j.kind = 2;
-        mm = alloc_mat(MatKey{2, kquant(ip.kt), ip.p, TT.lvl[b], o, 0, 0}, (long long)P * P, &j);
+        mm = alloc_mat(MatKey{2, kquant(ip.kt), ip.p, kquant(TT.S(TT.lvl[b])), o, 0, 0}, (long long)P * P, &j);
       }
       pl.tbox_l2l.push_back(mm);
     }
@@ -824,7 +846,8 @@ std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int
           j.k = ip.kt;
           j.p = ip.p;
           j.kind = 0;
-          long long m = alloc_mat(MatKey{0, kquant(ip.kt), ip.p, l, dx, dy, dz}, (long long)P * P, &j);
+          long long m = alloc_mat(MatKey{0, kquant(ip.kt), ip.p, kquant(S0 / (double)(1 << l)), dx, dy, dz},
+                                  (long long)P * P, &j);
           mo.mat[0] = mo.mat[1] = mo.mat[2] = m;
           mo.phi = 0;
           off_ratio.push_back(sqrt(3.0) / sqrt((double)(dx * dx + dy * dy + dz * dz)));

@@ -86,6 +86,14 @@ struct Plan {
 std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int64_t n_src,
                          const double* src, int64_t n_tgt, const double* tgt);
 
+// several independent geometries in one plan: geometry g owns sources
+// src_off[g] .. src_off[g+1]-1 and targets tgt_off[g] .. tgt_off[g+1]-1 (global
+// indices into src / tgt); each gets its own lattice and FMM instances, and
+// only same-geometry pairs interact
+std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& prm, int n_geom,
+                               const int64_t* src_off, const double* src, const int64_t* tgt_off,
+                               const double* tgt);
+
 // small helpers exported for host-only tests
 void lm_cheb_affine(int jmax, double a, double b, std::vector<double>& C);
 void lm_legendre_cheb(int p, std::vector<double>& B);

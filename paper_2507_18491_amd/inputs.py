@@ -147,3 +147,40 @@ def sparse_currents(J, count, seed=0):
     Js = np.zeros_like(J)
     Js[..., keep, :] = J[..., keep, :]
     return Js, keep
+
+
+def tiny_targets(count=200, seed=0):
+    """Target points distinct from the tiny workload's sources, drawn in the
+    same two slabs (half above, half below the interface)."""
+    rng = np.random.default_rng(seed + 4000)
+    a = count // 2
+    return _uniform_layers(rng, [a, count - a], [(0.1, 2.1), (-2.1, -0.1)], 1.0)
+
+
+def cotangent(n, n_rhs=1, seed=0):
+    """Seeded complex128 vectors [n, 3] (or [n_rhs, n, 3]) used as output
+    gradients gA in the adjoint and gradient checks."""
+    rng = np.random.default_rng(seed + 3000)
+    return currents(rng, n, n_rhs)
+
+
+def sample_sources(n, count, seed=0):
+    """Sorted distinct source indices for sampled gradient checks."""
+    rng = np.random.default_rng(seed + 5000)
+    return np.sort(rng.choice(n, count, replace=False))
+
+
+def uneven_geometries(n_geom=32, seed=0, n_min=5000, n_max=200000):
+    """Many independent three-layer geometries of uneven size: N_g =
+    round(exp(U(ln n_min, ln n_max))), each clustered (8 Gaussian blobs,
+    sigma 0.3, 40/30/30 layer choice) with seed g.  Returns (d, k, [xyz_g],
+    [J_g])."""
+    rng = np.random.default_rng(seed + 6000)
+    sizes = np.round(np.exp(rng.uniform(np.log(n_min), np.log(n_max), n_geom))).astype(int)
+    xs, Js = [], []
+    d = k = None
+    for g, n in enumerate(sizes):
+        d, k, x, J = clustered_three_layer(int(n), seed=seed * 1000 + g)
+        xs.append(x)
+        Js.append(J)
+    return d, k, xs, Js

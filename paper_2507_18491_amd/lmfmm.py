@@ -54,6 +54,9 @@ def load_library():
     lib.lm_set_params.argtypes = [vp, P(lm_params)]
     lib.lm_build.argtypes = [vp, ctypes.c_int64, D, ctypes.c_int64, D, vp]
     lib.lm_evaluate.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    lib.lm_build_batch.argtypes = [vp, ctypes.c_int, P(ctypes.c_int64), D, P(ctypes.c_int64), D, vp]
+    lib.lm_evaluate_adjoint.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    lib.lm_grad_src_xyz.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     lib.lm_stats.argtypes = [vp, D, ctypes.c_int]
     lib.lm_set_timing.argtypes = [vp, ctypes.c_int]
     lib.lm_timings.argtypes = [vp, D, ctypes.c_int]
@@ -129,6 +132,32 @@ class LayeredDyadicFMM:
         self.n_src, self.n_tgt = src.shape[0], tgt.shape[0]
         return self
 
+    def build_batch(self, srcs, tgts=None, stream=None):
+        """Several independent geometries in one plan (one launch per pass for
+        all of them).  srcs: list of [n_g, 3] arrays; tgts: list or None (targets
+        = sources).  Currents and outputs are the concatenations in order;
+        self.src_off / self.tgt_off give the geometry boundaries."""
+        import torch
+        srcs = [np.asarray(a, dtype=np.float64).reshape(-1, 3) for a in srcs]
+        tgts = srcs if tgts is None else [np.asarray(a, dtype=np.float64).reshape(-1, 3) for a in tgts]
+        if len(tgts) != len(srcs):
+            raise LMError("srcs and tgts must have the same number of geometries")
+        so = np.zeros(len(srcs) + 1, dtype=np.int64)
+        to = np.zeros(len(srcs) + 1, dtype=np.int64)
+        so[1:] = np.cumsum([a.shape[0] for a in srcs])
+        to[1:] = np.cumsum([a.shape[0] for a in tgts])
+        src = np.ascontiguousarray(np.concatenate(srcs)) if srcs else np.zeros((0, 3))
+        tgt = src if tgts is srcs else (np.ascontiguousarray(np.concatenate(tgts)) if tgts else np.zeros((0, 3)))
+        if stream is None:
+            with torch.cuda.device(self.device):
+                stream = torch.cuda.current_stream().cuda_stream
+        i64 = ctypes.POINTER(ctypes.c_int64)
+        self._check(self.lib.lm_build_batch(self.ctx, len(srcs), so.ctypes.data_as(i64), _dp(src),
+                                            to.ctypes.data_as(i64), _dp(tgt), ctypes.c_void_p(stream)))
+        self.n_src, self.n_tgt = int(so[-1]), int(to[-1])
+        self.src_off, self.tgt_off = so, to
+        return self
+
     def evaluate(self, J, out=None, stream=None):
         """J: complex128 CUDA tensor [n_src, 3] or [n_rhs, n_src, 3]; returns A (same rank)."""
         import torch
@@ -146,6 +175,47 @@ class LayeredDyadicFMM:
         self._check(self.lib.lm_evaluate(self.ctx, n_rhs, ctypes.c_void_p(Jr.data_ptr()),
                                          ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)))
         return out[0] if single else out
+
+    def _rhs_view(self, X, n, name):
+        import torch
+        if not (X.is_cuda and X.dtype == torch.complex128):
+            raise LMError("%s must be a complex128 CUDA tensor" % name)
+        single = X.dim() == 2
+        n_rhs = 1 if single else X.shape[0]
+        return single, n_rhs, X.reshape(n_rhs, n, 3).contiguous()
+
+    def evaluate_adjoint(self, gA, out=None, stream=None):
+        """gJ = G^H gA.  gA: complex128 CUDA tensor [n_tgt, 3] or [n_rhs, n_tgt, 3]."""
+        import torch
+        if self.n_src is None:
+            raise LMError("build() must be called first")
+        single, n_rhs, g = self._rhs_view(gA, self.n_tgt, "gA")
+        if out is None:
+            out = torch.empty((n_rhs, self.n_src, 3), dtype=torch.complex128, device=gA.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(gA.device).cuda_stream
+        self._check(self.lib.lm_evaluate_adjoint(self.ctx, n_rhs, ctypes.c_void_p(g.data_ptr()),
+                                                 ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)))
+        return out[0] if single else out
+
+    def grad_src_xyz(self, J, gA, out=None, stream=None):
+        """Gradient [n_src, 3] (fp64) of a real loss with dL/dA = gA with respect to
+        the source positions (targets fixed), summed over right-hand sides."""
+        import torch
+        if self.n_src is None:
+            raise LMError("build() must be called first")
+        _, n_rhs, Jr = self._rhs_view(J, self.n_src, "J")
+        _, n_rhs2, g = self._rhs_view(gA, self.n_tgt, "gA")
+        if n_rhs2 != n_rhs:
+            raise LMError("J and gA have different numbers of right-hand sides")
+        if out is None:
+            out = torch.empty((self.n_src, 3), dtype=torch.float64, device=J.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(J.device).cuda_stream
+        self._check(self.lib.lm_grad_src_xyz(self.ctx, n_rhs, ctypes.c_void_p(Jr.data_ptr()),
+                                             ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                             ctypes.c_void_p(stream)))
+        return out
 
     def stats(self):
         buf = np.zeros(len(STAT_NAMES))

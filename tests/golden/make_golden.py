@@ -39,12 +39,86 @@ def scale_sparse(n=100000, n_active=400, n_tgt=128):
                         keep=keep, seed=0)
 
 
+def tiny_adjoint():
+    """Adjoint references on the tiny workload, from the reciprocity of the
+    oracle's Green's function (G(x, y) = G(y, x)^T, itself a pinned property
+    of the oracle): gJ = conj(sum_i G(x_j, x_i) conj(gA_i)).
+    (a) targets = sources; (b) distinct targets y (forward A as well)."""
+    d, k, x, J = inputs.tiny(seed=0)
+    gA = inputs.cotangent(x.shape[0], seed=0)
+    gJ = np.conj(oracle.direct(d, k, x, np.conj(gA), x))
+    y = inputs.tiny_targets(200, seed=0)
+    A2 = oracle.direct(d, k, x, J, y)
+    gA2 = inputs.cotangent(y.shape[0], seed=1)
+    gJ2 = np.conj(oracle.direct(d, k, y, np.conj(gA2), x))
+    np.savez_compressed(os.path.join(OUT, "tiny_adjoint_oracle.npz"), gA=gA, gJ=gJ, y=y, A2=A2, gA2=gA2,
+                        gJ2=gJ2, seed=0)
+
+
+def _grad_entry(d, k, tgt, gA, s0, Js, self_index, h=1e-4):
+    """d/ds of Re sum_i gA_i^H G(tgt_i, s) Js at s = s0 (targets fixed), by a
+    fourth-order central difference of the oracle; the free-space term of a
+    target that coincides with the source (self_index) is excluded, its
+    reaction term kept."""
+    out = np.zeros(3)
+    for a in range(3):
+        vals = []
+        for m in (2, 1, -1, -2):
+            s = s0.copy()
+            s[a] += m * h
+            col = oracle.direct(d, k, s[None, :], Js[None, :], tgt)  # [n_tgt, 3]
+            if self_index is not None:
+                col[self_index] = oracle.reaction_pair(d, k, tgt[self_index], s) @ Js
+            vals.append(np.sum(np.conj(gA) * col))
+        f2, f1, fm1, fm2 = vals
+        out[a] = ((-f2 + 8 * f1 - 8 * fm1 + fm2) / (12 * h)).real
+    return out
+
+
+def tiny_grad(count=24):
+    """Source-position gradients of Re <gA, G J> at sampled sources of the tiny
+    workload (a) with targets = sources and (b) with the distinct targets y."""
+    d, k, x, J = inputs.tiny(seed=0)
+    gA = inputs.cotangent(x.shape[0], seed=0)
+    js = inputs.sample_sources(x.shape[0], count, seed=0)
+    gX = np.array([_grad_entry(d, k, x, gA, x[j], J[j], j) for j in js])
+    y = inputs.tiny_targets(200, seed=0)
+    gA2 = inputs.cotangent(y.shape[0], seed=1)
+    gX2 = np.array([_grad_entry(d, k, y, gA2, x[j], J[j], None) for j in js])
+    np.savez_compressed(os.path.join(OUT, "tiny_grad_oracle.npz"), js=js, gX=gX, gX2=gX2, h=1e-4, seed=0)
+
+
+def adjoint_sparse(n=1000000, n_active=400, n_src=128, n_grad=24):
+    """Three-layer workload at n points (targets = sources): output gradients
+    gA non-zero on n_active targets only; the adjoint gJ = G^H gA at n_src
+    sampled sources (through the oracle's reciprocity), and the source-position
+    gradients of Re <gA, G J> at n_grad sampled sources (fourth-order
+    differences of the oracle, targets fixed)."""
+    d, k, x, J = inputs.three_layer(n, seed=0)
+    gA = inputs.cotangent(n, seed=0)
+    gAs, keep = inputs.sparse_currents(gA, n_active, seed=1)
+    idx = inputs.sample_sources(n, n_src, seed=0)
+    gJ = np.conj(oracle.direct(d, k, x[keep], np.conj(gA[keep]), x[idx]))
+    js = idx[:n_grad]
+    pos = {int(t): i for i, t in enumerate(keep)}
+    gX = np.array([_grad_entry(d, k, x[keep], gA[keep], x[j], J[j], pos.get(int(j))) for j in js])
+    np.savez_compressed(os.path.join(OUT, "three_%d_adjoint_sparse%d_oracle.npz" % (n, n_active)), gJ=gJ,
+                        idx=idx, keep=keep, js=js, gX=gX, seed=0)
+
+
 if __name__ == "__main__":
     names = sys.argv[1:] or ["tiny"]
     for nm in names:
         t = time.time()
         if nm == "tiny":
             tiny()
+        elif nm == "tiny_adjoint":
+            tiny_adjoint()
+        elif nm == "tiny_grad":
+            tiny_grad()
+        elif nm.startswith("adjoint_sparse"):
+            parts = nm.split(":")
+            adjoint_sparse(n=int(parts[1]) if len(parts) > 1 else 1000000)
         elif nm.startswith("scale"):
             parts = nm.split(":")
             n = int(parts[1]) if len(parts) > 1 else 100000

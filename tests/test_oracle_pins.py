@@ -268,3 +268,37 @@ def test_sparse_currents_are_skipped_exactly(oracle):
     A1 = oracle.direct(d, k, x, Js, x[:3], n_threads=4)
     A2 = oracle.direct(d, k, x[keep], J[keep], x[:3], n_threads=4)
     assert rel(A1, A2) < 1e-15
+
+
+def test_adjoint_reference_matches_pair_definition(oracle):
+    """The stored adjoint reference (computed through reciprocity) equals the
+    definition sum_i G(x_i, x_j)^H gA_i evaluated pair by pair."""
+    import os
+    from paper_2507_18491_amd import inputs
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "tiny_adjoint_oracle.npz"))
+    d, k, x, J = inputs.tiny(seed=0)
+    for j in (3, 450):
+        v = sum(oracle.pair(d, k, x[i], x[j]).conj().T @ g["gA"][i] for i in range(x.shape[0]))
+        assert np.linalg.norm(v - g["gJ"][j]) < 1e-10 * np.linalg.norm(v)
+    y = g["y"]
+    j = 123
+    v = sum(oracle.pair(d, k, y[i], x[j]).conj().T @ g["gA2"][i] for i in range(y.shape[0]))
+    assert np.linalg.norm(v - g["gJ2"][j]) < 1e-10 * np.linalg.norm(v)
+
+
+def test_gradient_reference_is_converged(oracle):
+    """The stored source-position gradients (fourth-order differences of the
+    oracle, h = 1e-4) agree with a recomputation at twice the step."""
+    import importlib.util
+    import os
+    from paper_2507_18491_amd import inputs
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_golden", os.path.join(here, "make_golden.py"))
+    mg = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mg)
+    gg = np.load(os.path.join(here, "tiny_grad_oracle.npz"))
+    d, k, x, J = inputs.tiny(seed=0)
+    gA = inputs.cotangent(x.shape[0], seed=0)
+    j = int(gg["js"][0])
+    v = mg._grad_entry(d, k, x, gA, x[j], J[j], j, h=2e-4)
+    assert np.linalg.norm(v - gg["gX"][0]) < 1e-7 * np.linalg.norm(v)
