@@ -52,6 +52,40 @@ def cpu_baseline(d, k, x, J, n_total, budget_s=15.0, threads=16):
                       "the full %d-source sum" % (nt, ns, pairs, dt, n_total)}
 
 
+def uneven_geometries(args, torch, inputs, lmfmm):
+    """32 clustered geometries of 5e3 .. 2e5 points built into one plan; one
+    evaluation of all of them captured in a HIP graph and replayed."""
+    d, k, xs, Js = inputs.uneven_geometries(32, seed=0)
+    n = sum(x.shape[0] for x in xs)
+    t0 = time.time()
+    f = lmfmm.LayeredDyadicFMM(d, k, p=args.p, p_free=args.p_free).build_batch(xs)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    J = torch.tensor(np.concatenate(Js), device="cuda:0").reshape(1, n, 3)
+    A = torch.empty((1, n, 3), dtype=torch.complex128, device="cuda:0")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        f.evaluate(J, out=A)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        f.evaluate(J, out=A)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    dt = (time.time() - t0) / args.steps
+    f.close()
+    print("uneven geometries: %d points in 32 geometries, %.1f ms per graph replay, build %.2f s" % (
+        n, 1e3 * dt, build_s), file=sys.stderr, flush=True)
+    return {"targets_per_s": n / dt, "n_points": n, "n_geometries": 32, "ms_per_step": 1e3 * dt,
+            "build_s": build_s, "launch": "hip graph replay of one evaluation"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +97,7 @@ def main():
     ap.add_argument("--rhs", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the 32 uneven geometries")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB device buffer three times (a reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -152,6 +187,7 @@ def main():
             As = fmm.evaluate(torch.tensor(Js, device=dev)).cpu().numpy()
             acc = float(np.linalg.norm(As[g["idx"]] - g["A"]) / np.linalg.norm(g["A"]))
     fmm.close()
+    uneven = None if args.no_uneven else uneven_geometries(args, torch, inputs, lmfmm)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(d, k, x, J if args.rhs == 1 else J[0], args.n)
@@ -184,6 +220,7 @@ def main():
                     "vs_forward": (wall / args.steps) / adj_s},
         "grad_src_xyz": {"targets_per_s": args.n * args.rhs / grad_s, "ms_per_step": 1e3 * grad_s,
                          "vs_forward": (wall / args.steps) / grad_s},
+        "uneven_geometries": uneven,
     }
     print(json.dumps(out), flush=True)
 

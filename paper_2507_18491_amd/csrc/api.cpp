@@ -354,7 +354,7 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
         int* p = nullptr;
         if ((rc = upload(ctx, &p, pl.p2p_tboxes[fi]))) return rc;
         ctx->d_p2p.push_back(p);
-        ctx->n_p2p.push_back((int)pl.p2p_tboxes[fi].size());
+        ctx->n_p2p.push_back((int)pl.p2p_tboxes[fi].size() / 2);
         ctx->p2p_inst.push_back((int)i);
         fi++;
       }

@@ -15,6 +15,7 @@
 
 // RC (template parameter): right-hand sides per block in the point/translation passes (1 or 4)
 #define NT 256          // threads per block
+static_assert(NT == LM_P2P_CHUNK, "near-field work items hold one block's worth of targets");
 
 __device__ inline int n_of(int nm) {
   int n = (int)sqrt((double)nm);
@@ -724,12 +725,14 @@ __global__ __launch_bounds__(NT) void k_p2p(DevPlan d, const int* tboxes, const 
                                             double k, cd* A) {
   __shared__ double sp[NT][3];
   __shared__ cd sj[NT][RC][3];
-  int b = tboxes[blockIdx.x];
+  // work item: (target leaf, chunk of NT targets)
+  int b = tboxes[2 * blockIdx.x];
   TgtBox tb = d.tbox[b];
   int r0 = blockIdx.y * RC, nr = min(RC, n_rhs - r0);
   int tid = threadIdx.x;
   const double inv4pi = 0.079577471545947667884;
-  for (int t0 = tb.pt0; t0 < tb.pt1; t0 += NT) {
+  {
+    int t0 = tb.pt0 + tboxes[2 * blockIdx.x + 1] * NT;
     int ti = t0 + tid;
     bool act = ti < tb.pt1;
     int id = act ? d.tgt_perm[ti] : 0;
@@ -970,12 +973,14 @@ __global__ __launch_bounds__(NT) void k_p2p_grad(DevPlan d, const int* tboxes, c
                                                  long long n_tgt, int n_rhs, double k, double* gX) {
   __shared__ double sp[NT][3];
   __shared__ cd sj[NT][3];
-  int b = tboxes[blockIdx.x];
+  // work item: (target leaf, chunk of NT targets)
+  int b = tboxes[2 * blockIdx.x];
   TgtBox tb = d.tbox[b];
   int tid = threadIdx.x;
   const double inv4pi = 0.079577471545947667884;
   for (int r = 0; r < n_rhs; r++) {
-    for (int t0 = tb.pt0; t0 < tb.pt1; t0 += NT) {
+    {
+      int t0 = tb.pt0 + tboxes[2 * blockIdx.x + 1] * NT;
       int ti = t0 + tid;
       bool act = ti < tb.pt1;
       int id = act ? d.tgt_perm[ti] : 0;

@@ -11,6 +11,7 @@
 
 #define LM_MAXL 16
 #define LM_PMAX 24
+#define LM_P2P_CHUNK 256   // targets per near-field work item (= threads per block)
 
 // One FMM instance: the free-space part of one layer, or one reaction
 // component (target layer lt, source layer ls, arrival direction at the

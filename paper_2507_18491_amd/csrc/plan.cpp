@@ -569,27 +569,53 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       tags.resize(ids.size(), 1);
       int D = prm.free_depth;
       if (D <= 0) {
-        // cost model: near-field pairs vs. dense M2L work
-        double best = 1e300;
-        std::vector<uint64_t> keys(ids.size());
-        double inv = (double)(1 << DK) / S0;
+        // cost model: exact near-field pair count vs M2L work per depth, with
+        // the measured rates of the two kernels (about 1e-11 s per near pair
+        // and 1.9e-13 s per complex multiply-add of the M2L GEMM; adaptive
+        // orders keep about 2/3 of the dense 3 P^2 work per pair).  Cell
+        // occupancies come from a dense grid per level (depth <= 7), so
+        // clustered points get deeper trees than uniform ones.
+        const double t_pair = 1.0e-11, t_m2l_pair = 3.0 * P * (double)P * 0.67 * 1.9e-13;
+        const int DMAXC = 7;
+        std::vector<uint32_t> ucell(3 * ids.size());
+        double inv = (double)(1 << DMAXC) / S0;
         for (size_t i = 0; i < ids.size(); i++) {
-          long long mx = (1 << DK) - 1;
-          long long ux = std::min(std::max((long long)floor((pos[3 * i] - S.x0) * inv), 0LL), mx);
-          long long uy = std::min(std::max((long long)floor((pos[3 * i + 1] - S.y0) * inv), 0LL), mx);
-          long long uz = std::min(std::max((long long)floor((pos[3 * i + 2] - S.z0) * inv), 0LL), mx);
-          keys[i] = spread3(ux) | (spread3(uy) << 1) | (spread3(uz) << 2);
+          long long mx = (1 << DMAXC) - 1;
+          ucell[3 * i] = (uint32_t)std::min(std::max((long long)floor((pos[3 * i] - S.x0) * inv), 0LL), mx);
+          ucell[3 * i + 1] = (uint32_t)std::min(std::max((long long)floor((pos[3 * i + 1] - S.y0) * inv), 0LL), mx);
+          ucell[3 * i + 2] = (uint32_t)std::min(std::max((long long)floor((pos[3 * i + 2] - S.z0) * inv), 0LL), mx);
         }
-        std::sort(keys.begin(), keys.end());
-        for (int Dc = 2; Dc <= 12; Dc++) {
-          int sh = 3 * (DK - Dc);
-          long long leaves = 0;
-          for (size_t i = 0; i < keys.size(); i++)
-            if (i == 0 || (keys[i] >> sh) != (keys[i - 1] >> sh)) leaves++;
-          double ns = (double)g.sid.size(), nt = (double)g.tid.size();
-          double c_p2p = nt * 27.0 * ns / (double)leaves * 0.6 * 160.0;
-          double c_m2l = (double)leaves * 189.0 * 1.14 * 3.0 * P * (double)P * 8.0 / 0.6;
-          double c = c_p2p + c_m2l;
+        double best = 1e300, m2l_acc = 0;
+        for (int Dc = 2; Dc <= DMAXC; Dc++) {
+          int n1 = 1 << Dc, sh = DMAXC - Dc;
+          std::vector<int> cs((size_t)n1 * n1 * n1, 0), ct((size_t)n1 * n1 * n1, 0);
+          for (size_t i = 0; i < ids.size(); i++) {
+            size_t c = ((size_t)(ucell[3 * i + 2] >> sh) * n1 + (ucell[3 * i + 1] >> sh)) * n1 + (ucell[3 * i] >> sh);
+            if (tags[i] == 0) cs[c]++; else ct[c]++;
+          }
+          double pairs = 0, occ_t = 0, nb_occ = 0;
+          for (int z = 0; z < n1; z++)
+            for (int y = 0; y < n1; y++)
+              for (int x = 0; x < n1; x++) {
+                size_t c = ((size_t)z * n1 + y) * n1 + x;
+                if (!ct[c]) continue;
+                occ_t += 1;
+                double ns = 0;
+                for (int dz = -1; dz <= 1; dz++)
+                  for (int dy = -1; dy <= 1; dy++)
+                    for (int dx = -1; dx <= 1; dx++) {
+                      int xx = x + dx, yy = y + dy, zz = z + dz;
+                      if (xx < 0 || yy < 0 || zz < 0 || xx >= n1 || yy >= n1 || zz >= n1) continue;
+                      int v = cs[((size_t)zz * n1 + yy) * n1 + xx];
+                      ns += v;
+                      nb_occ += v > 0;
+                    }
+                pairs += ct[c] * ns;
+              }
+          // M2L pairs at this level: occupied target boxes x 189 interaction
+          // slots x the occupied fraction of their neighbourhoods
+          m2l_acc += occ_t > 0 ? occ_t * 189.0 * (nb_occ / (27.0 * occ_t)) : 0.0;
+          double c = pairs * t_pair + m2l_acc * t_m2l_pair;
           if (c < best) {
             best = c;
             D = Dc;
@@ -755,9 +781,15 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
           tb.p2p1 = (int)pl.p2p_list.size();
         }
       }
+      // near-field work items: (target leaf, chunk of LM_P2P_CHUNK targets),
+      // so that leaves holding many points spread over many workgroups
       pl.p2p_tboxes.push_back({});
       for (int t = 0; t < S.nbox(); t++)
-        if (S.lvl[t] == D && S.b1[t] > S.b0[t]) pl.p2p_tboxes.back().push_back(tbase + t);
+        if (S.lvl[t] == D && S.b1[t] > S.b0[t])
+          for (int c = 0; c * LM_P2P_CHUNK < S.b1[t] - S.b0[t]; c++) {
+            pl.p2p_tboxes.back().push_back(tbase + t);
+            pl.p2p_tboxes.back().push_back(c);
+          }
     } else {
       std::vector<std::vector<int>> nearT(T.nbox());
       auto ws = [&](int s, int t) {

@@ -48,7 +48,7 @@ struct Plan {
   std::vector<std::vector<int>> l2l_children; // per level (child level), child box ids
   std::vector<int> p2m_leaves;                // source boxes doing P2M
   std::vector<std::vector<int>> l2p_leaves;   // per instance, target leaf boxes
-  std::vector<std::vector<int>> p2p_tboxes;   // per free instance, target leaf boxes with near lists
+  std::vector<std::vector<int>> p2p_tboxes;   // per free instance, near-field work items (target leaf, chunk) pairs
   std::vector<int> p2p_list;                  // near source boxes
   // M2L
   std::vector<M2LClass> cls;
