@@ -23,7 +23,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "targets/s, 3-layer dyadic FMM N=1M p=12 at rel err≤1e-6; batched/adjoint vs plain"
-FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 fp64 FMA/clk x 2 flop x 2.4 GHz
+FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 fp64 FMA/clk x 2 flop x 2.4 GHz (fp64 MFMA: same)
+
+# HBM traffic of one k_m2l launch at the default workload (N=1e6, p=12,
+# p_free=20), from rocprofv3 FETCH_SIZE / WRITE_SIZE per dispatch scaled by a
+# plain 1 GiB device copy (FETCH_SIZE reads 0.5 KiB per KiB read: factor 2.0;
+# WRITE_SIZE 1:1); see profiles/k_m2l_three_layer_1M_p12_pf20.md.  Valid only
+# for the kernel source it was measured on (digest of the M2L section of
+# kernels.hip); otherwise reported as null.
+K_M2L_TRAFFIC = {"digest": "06ddfc2f6f6a08a2", "fetch_bytes": 1.5234e7 * 1024 * 2.0,
+                 "write_bytes": 5.0596e6 * 1024 * 1.0}
+
+
+def m2l_source_digest():
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2507_18491_amd", "csrc", "kernels.hip")).read()
+    a = src.index("// ------------------------------------------------------------------ M2L")
+    b = src.index("// LE_t[out][rhs] += sum")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
 def cpu_baseline(d, k, x, J, n_total, budget_s=15.0, threads=16):
@@ -178,6 +195,10 @@ def main():
     print("adjoint: %.1f ms/step, source gradient: %.1f ms/step" % (1e3 * adj_s, 1e3 * grad_s),
           file=sys.stderr, flush=True)
 
+    default_cfg = (args.n, args.p, args.p_free, args.rhs) == (1000000, 12, 20, 1)
+    traffic = (K_M2L_TRAFFIC["fetch_bytes"] + K_M2L_TRAFFIC["write_bytes"]
+               if default_cfg and m2l_source_digest() == K_M2L_TRAFFIC["digest"] else None)
+
     acc = None
     if not args.no_accuracy:
         fn = os.path.join(ROOT, "tests", "golden", "three_%d_sparse400_oracle.npz" % args.n)
@@ -207,8 +228,8 @@ def main():
         "config": {"workload": "three-layer dyadic FMM, N=%d uniform in layer slabs, targets=sources, "
                                "p=%d (free-space part p=%d), %d complex128 current vector(s)" % (args.n, args.p, args.p_free or args.p, args.rhs),
                    "n": args.n, "p": args.p, "p_free": args.p_free or args.p, "layers": 3, "n_rhs": args.rhs},
-        "roofline": {"bound": "alu", "kernel": "k_m2l", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None,
+        "roofline": {"bound": "mfma", "kernel": "k_m2l", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": traffic,
                      "launch_ms": launch_ms, "launches_per_step": launches_per_step,
                      "algorithmic_flops_per_launch": flops_per_launch},
         "cpu_baseline": cpu,
