@@ -209,6 +209,13 @@ int lm_stats(const lm_ctx* ctx, double* out_host, int n);
 #define LM_STAT_FREE_DEPTH 20
 #define LM_STATS_COUNT 21
 
+/* Self-test of the device arithmetic used by the near field (no context):
+ * for each x_dev[i] writes out_dev[4i..4i+3] = sin x, cos x (the reduced-range
+ * routine of the near field), 1/sqrt(x^2 + 1e-300) (refined estimate) and the
+ * same by the library's sqrt and division.  DEVICE arrays x [n], out [4n];
+ * enqueued on `stream`.  For tests. */
+int lm_selftest_math(int64_t n, const double* x_dev, double* out_dev, void* stream);
+
 /* ---- host-only helpers (no GPU needed), for tests of the host logic ---- */
 
 /* Reaction components of a medium (Sec. 3.1): returns their count and writes

@@ -52,6 +52,7 @@ struct lm_ctx {
   bool timing = false;
   std::vector<std::vector<hipEvent_t>> evsets;  // per timed evaluation: LM_PHASES+1 events
   // adjoint and gradients
+  bool p2p_red = false;                   // near-field arguments k r bounded: reduced-range sincos
   bool same_sets = false;                 // sources and targets are the same point array
   std::vector<double> host_src, host_tgt;  // kept when they differ (for the swapped build)
   std::vector<int64_t> host_soff, host_toff;
@@ -422,6 +423,23 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
   ctx->t_plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   ctx->t_upload_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
   ctx->t_tables_ms = std::chrono::duration<double, std::milli>(t3 - t2).count();
+  {
+    // every near-field argument k r is below k_max times the diameter of
+    // the point set (pairs only form within one geometry)
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int pass = 0; pass < 2; pass++) {
+      const double* x = pass ? tgt_xyz : src_xyz;
+      int64_t n = pass ? n_tgt : n_src;
+      for (int64_t i = 0; i < n; i++)
+        for (int c = 0; c < 3; c++) {
+          lo[c] = std::min(lo[c], x[3 * i + c]);
+          hi[c] = std::max(hi[c], x[3 * i + c]);
+        }
+    }
+    double diam = 0;
+    for (int c = 0; c < 3; c++) diam += hi[c] > lo[c] ? (hi[c] - lo[c]) * (hi[c] - lo[c]) : 0.0;
+    ctx->p2p_red = med.kmax * sqrt(diam) < 0.5 * LM_SINCOS_RED_MAX;
+  }
   ctx->same_sets = n_src == n_tgt && memcmp(soff, toff, (size_t)(n_geom + 1) * sizeof(int64_t)) == 0 &&
                    (src_xyz == tgt_xyz || n_src == 0 ||
                     memcmp(src_xyz, tgt_xyz, (size_t)n_src * 3 * sizeof(double)) == 0);
@@ -716,10 +734,10 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
       int i = ctx->p2p_inst[f];
       if (grad)
         launch_p2p_grad(d, ctx->d_p2p[f], ctx->n_p2p[f], ctx->d_src, Jc, pl.n_src, ctx->d_tgt, W, pl.n_tgt, n_rhs,
-                        pl.inst[i].kt, gX, s);
+                        pl.inst[i].kt, gX, ctx->p2p_red, s);
       else
         launch_p2p(d, ctx->d_p2p[f], ctx->n_p2p[f], ctx->d_src, Jc, pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs,
-                   pl.inst[i].kt, Ac, s);
+                   pl.inst[i].kt, Ac, ctx->p2p_red, s);
     }
     mark(7);
   } else {
@@ -815,6 +833,12 @@ int lm_stats(const lm_ctx* ctx, double* out, int n) {
   int m = n < LM_STATS_COUNT ? n : LM_STATS_COUNT;
   memcpy(out, v, m * sizeof(double));
   return LM_OK;
+}
+
+int lm_selftest_math(int64_t n, const double* x_dev, double* out_dev, void* stream) {
+  if (n < 0 || (n > 0 && (!x_dev || !out_dev))) return LM_EINVAL;
+  launch_selftest_math(x_dev, n, out_dev, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? LM_OK : LM_EHIP;
 }
 
 // ---------------------------------------------------------------- host-only helpers

@@ -719,7 +719,7 @@ void launch_l2p(const DevPlan& d, const int* leaves, int n, int kind, const doub
 // free-space near field: A_i += sum_j G^f(x_i - x_j) J_j over same-layer
 // sources in adjacent leaves, coincident points skipped (paper Sec. 2 and the
 // layered sums of Sec. 3.3)
-template <int RC>
+template <int RC, bool RED>
 __global__ __launch_bounds__(NT) void k_p2p(DevPlan d, const int* tboxes, const double* sxyz, const cd* J,
                                             long long n_src, const double* txyz, long long n_tgt, int n_rhs,
                                             double k, cd* A) {
@@ -731,6 +731,7 @@ __global__ __launch_bounds__(NT) void k_p2p(DevPlan d, const int* tboxes, const 
   int r0 = blockIdx.y * RC, nr = min(RC, n_rhs - r0);
   int tid = threadIdx.x;
   const double inv4pi = 0.079577471545947667884;
+  const double invk = 1.0 / k;
   {
     int t0 = tb.pt0 + tboxes[2 * blockIdx.x + 1] * NT;
     int ti = t0 + tid;
@@ -760,10 +761,10 @@ __global__ __launch_bounds__(NT) void k_p2p(DevPlan d, const int* tboxes, const 
             double rx = x0 - sp[j][0], ry = y0 - sp[j][1], rz = z0 - sp[j][2];
             double r2 = rx * rx + ry * ry + rz * rz;
             if (r2 == 0.0) continue;
-            double r = sqrt(r2), ir = 1.0 / r;
-            double kr = k * r, ikr = 1.0 / kr, ikr2 = ikr * ikr;
+            double ir = lm_rsqrt(r2), r = r2 * ir;
+            double kr = k * r, ikr = invk * ir, ikr2 = ikr * ikr;
             double sn, cs;
-            sincos(kr, &sn, &cs);
+            lm_sincos_nf<RED>(kr, &sn, &cs);
             cd g = cd{cs * inv4pi * ir, sn * inv4pi * ir};
             cd a = g * cd{1.0 - ikr2, ikr};
             cd bq = g * cd{-1.0 + 3.0 * ikr2, -3.0 * ikr};
@@ -788,13 +789,46 @@ __global__ __launch_bounds__(NT) void k_p2p(DevPlan d, const int* tboxes, const 
   }
 }
 void launch_p2p(const DevPlan& d, const int* tboxes, int n, const double* sxyz, const cd* J, long long n_src,
-                const double* txyz, long long n_tgt, int n_rhs, double k, cd* A, hipStream_t s) {
+                const double* txyz, long long n_tgt, int n_rhs, double k, cd* A, bool red, hipStream_t s) {
   if (n <= 0) return;
-  if (n_rhs == 1)
-    hipLaunchKernelGGL(k_p2p<1>, dim3(n, n_rhs), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src, txyz, n_tgt, n_rhs, k, A);
+  if (n_rhs == 1) {
+    if (red)
+      hipLaunchKernelGGL((k_p2p<1, true>), dim3(n, n_rhs), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src, txyz, n_tgt,
+                         n_rhs, k, A);
+    else
+      hipLaunchKernelGGL((k_p2p<1, false>), dim3(n, n_rhs), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src, txyz, n_tgt,
+                         n_rhs, k, A);
+  } else {
+    if (red)
+      hipLaunchKernelGGL((k_p2p<4, true>), dim3(n, (n_rhs + 3) / 4), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src, txyz,
+                         n_tgt, n_rhs, k, A);
+    else
+      hipLaunchKernelGGL((k_p2p<4, false>), dim3(n, (n_rhs + 3) / 4), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src,
+                         txyz, n_tgt, n_rhs, k, A);
+  }
+}
+
+// ------------------------------------------------------------------ self-test
+// out[4 i .. 4 i + 3] = (sin, cos) by the near-field routine (library beyond
+// its range), then
+// 1/sqrt(x_i^2 + 1e-300) by the refined estimate, then by the library.
+__global__ void k_selftest_math(const double* x, long long n, double* out) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double sn, cs;
+  if (fabs(x[i]) < LM_SINCOS_RED_MAX)
+    lm_sincos_red(x[i], &sn, &cs);
   else
-    hipLaunchKernelGGL(k_p2p<4>, dim3(n, (n_rhs + 3) / 4), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src, txyz, n_tgt,
-                       n_rhs, k, A);
+    sincos(x[i], &sn, &cs);
+  double a = x[i] * x[i] + 1e-300;
+  out[4 * i] = sn;
+  out[4 * i + 1] = cs;
+  out[4 * i + 2] = lm_rsqrt(a);
+  out[4 * i + 3] = 1.0 / sqrt(a);
+}
+void launch_selftest_math(const double* x, long long n, double* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_selftest_math, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, x, n, out);
 }
 
 // ------------------------------------------------------------------ gradients
@@ -968,6 +1002,7 @@ void launch_l2p_grad(const DevPlan& d, const int* leaves, int n, int kind, const
 // u = R / r, and
 //   sum_bc w_b d_alpha G_bc s_c = u_alpha [a' (w.s) + (b' - 2 b / r)(w.u)(u.s)]
 //                                  + (b / r) [w_alpha (u.s) + s_alpha (w.u)].
+template <bool RED>
 __global__ __launch_bounds__(NT) void k_p2p_grad(DevPlan d, const int* tboxes, const double* sxyz, const cd* Jsrc,
                                                  long long n_src, const double* txyz, const cd* W,
                                                  long long n_tgt, int n_rhs, double k, double* gX) {
@@ -978,6 +1013,7 @@ __global__ __launch_bounds__(NT) void k_p2p_grad(DevPlan d, const int* tboxes, c
   TgtBox tb = d.tbox[b];
   int tid = threadIdx.x;
   const double inv4pi = 0.079577471545947667884;
+  const double invk = 1.0 / k;
   for (int r = 0; r < n_rhs; r++) {
     {
       int t0 = tb.pt0 + tboxes[2 * blockIdx.x + 1] * NT;
@@ -1011,10 +1047,10 @@ __global__ __launch_bounds__(NT) void k_p2p_grad(DevPlan d, const int* tboxes, c
               double rx = x0 - sp[j][0], ry = y0 - sp[j][1], rz = z0 - sp[j][2];
               double r2 = rx * rx + ry * ry + rz * rz;
               if (r2 == 0.0) continue;
-              double rd = sqrt(r2), ir = 1.0 / rd;
-              double kr = k * rd, ikr = 1.0 / kr, ikr2 = ikr * ikr, ikr3 = ikr2 * ikr;
+              double ir = lm_rsqrt(r2), rd = r2 * ir;
+              double kr = k * rd, ikr = invk * ir, ikr2 = ikr * ikr, ikr3 = ikr2 * ikr;
               double sn, cs;
-              sincos(kr, &sn, &cs);
+              lm_sincos_nf<RED>(kr, &sn, &cs);
               cd g = cd{cs * inv4pi * ir, sn * inv4pi * ir};
               cd gp = g * cd{-ir, k};                          // g' = g (ik - 1/r)
               cd fa = cd{1.0 - ikr2, ikr}, fb = cd{-1.0 + 3.0 * ikr2, -3.0 * ikr};
@@ -1049,10 +1085,14 @@ __global__ __launch_bounds__(NT) void k_p2p_grad(DevPlan d, const int* tboxes, c
 }
 void launch_p2p_grad(const DevPlan& d, const int* tboxes, int n, const double* sxyz, const cd* Jsrc,
                      long long n_src, const double* txyz, const cd* W, long long n_tgt, int n_rhs, double k,
-                     double* gX, hipStream_t s) {
+                     double* gX, bool red, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_p2p_grad, dim3(n), dim3(NT), 0, s, d, tboxes, sxyz, Jsrc, n_src, txyz, W, n_tgt, n_rhs, k,
-                     gX);
+  if (red)
+    hipLaunchKernelGGL(k_p2p_grad<true>, dim3(n), dim3(NT), 0, s, d, tboxes, sxyz, Jsrc, n_src, txyz, W, n_tgt, n_rhs,
+                       k, gX);
+  else
+    hipLaunchKernelGGL(k_p2p_grad<false>, dim3(n), dim3(NT), 0, s, d, tboxes, sxyz, Jsrc, n_src, txyz, W, n_tgt,
+                       n_rhs, k, gX);
 }
 
 // ------------------------------------------------------------------ translation tables

@@ -78,6 +78,66 @@ LM_HD int nm_idx(int n, int m) { return n * n + n + m; }
 // index of (n, m>=0) in a triangular table
 LM_HD int tri_idx(int n, int m) { return n * (n + 1) / 2 + m; }
 
+// sin and cos of x for |x| < 2^19 (pi/2), as needed by the near field where
+// x = k r is a few units: Cody-Waite additive range reduction x = n pi/2 + t
+// (W. J. Cody and W. Waite, Software Manual for the Elementary Functions,
+// 1980), with pi/2 split into three parts of which the first two carry 33
+// significant bits (so n times each is exact for n < 2^20; the split was
+// computed from a 100-digit value of pi), followed by the Taylor series of
+// sin and cos on |t| <= pi/4 up to t^17 and t^16 (truncation below 1e-17).
+// Callers guarantee |x| < LM_SINCOS_RED_MAX (the host selects the library
+// routine otherwise).
+#define LM_SINCOS_RED_MAX 823549.0   // 2^19 pi/2
+__device__ inline void lm_sincos_red(double x, double* sn, double* cs) {
+  const double PIO2_1 = 1.5707963267341256, PIO2_2 = 6.077100506303966e-11, PIO2_3 = 2.0222662487959506e-21;
+  const double TWO_OVER_PI = 0.6366197723675814;
+  double n = rint(x * TWO_OVER_PI);
+  double t = fma(-n, PIO2_1, x);
+  t = fma(-n, PIO2_2, t);
+  t = fma(-n, PIO2_3, t);
+  double u = t * t;
+  double ps = fma(u, 2.8114572543455206e-15, -7.647163731819816e-13);
+  ps = fma(u, ps, 1.6059043836821613e-10);
+  ps = fma(u, ps, -2.505210838544172e-08);
+  ps = fma(u, ps, 2.7557319223985893e-06);
+  ps = fma(u, ps, -0.0001984126984126984);
+  ps = fma(u, ps, 0.008333333333333333);
+  ps = fma(u, ps, -0.16666666666666666);
+  double s = fma(t * u, ps, t);
+  double pc = fma(u, 4.779477332387385e-14, -1.1470745597729725e-11);
+  pc = fma(u, pc, 2.08767569878681e-09);
+  pc = fma(u, pc, -2.755731922398589e-07);
+  pc = fma(u, pc, 2.48015873015873e-05);
+  pc = fma(u, pc, -0.001388888888888889);
+  pc = fma(u, pc, 0.041666666666666664);
+  pc = fma(u, pc, -0.5);
+  double c = fma(u, pc, 1.0);
+  int q = ((int)n) & 3;
+  double so = (q & 1) ? c : s, co = (q & 1) ? s : c;
+  *sn = (q & 2) ? -so : so;
+  *cs = ((q + 1) & 2) ? -co : co;
+}
+
+template <bool RED>
+__device__ inline void lm_sincos_nf(double x, double* sn, double* cs) {
+  if (RED)
+    lm_sincos_red(x, sn, cs);
+  else
+    sincos(x, sn, cs);
+}
+
+// 1/sqrt(a) for a > 0 (normal range): hardware estimate refined by two
+// Newton steps y <- y + y (1/2 - (a y / 2) y)
+__device__ inline double lm_rsqrt(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  double h = 0.5 * a * y;
+  double e = fma(-h, y, 0.5);
+  y = fma(y, e, y);
+  h = 0.5 * a * y;
+  e = fma(-h, y, 0.5);
+  return fma(y, e, y);
+}
+
 #define LM_INV_SQRT_4PI 0.28209479177387814347
 
 // Orthonormal associated Legendre functions P^m_n(cos b), 0 <= m <= n <= nmax,

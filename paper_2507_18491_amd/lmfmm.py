@@ -54,6 +54,7 @@ def load_library():
     lib.lm_set_params.argtypes = [vp, P(lm_params)]
     lib.lm_build.argtypes = [vp, ctypes.c_int64, D, ctypes.c_int64, D, vp]
     lib.lm_evaluate.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    lib.lm_selftest_math.argtypes = [ctypes.c_int64, vp, vp, vp]
     lib.lm_build_batch.argtypes = [vp, ctypes.c_int, P(ctypes.c_int64), D, P(ctypes.c_int64), D, vp]
     lib.lm_evaluate_adjoint.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     lib.lm_grad_src_xyz.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
@@ -294,3 +295,17 @@ def host_plan_stats(d, k, src, tgt=None, **params):
     if rc:
         raise LMError("planning failed (%d): %s" % (rc, err.value.decode()))
     return dict(zip(STAT_NAMES, out.tolist()))
+
+
+def selftest_math(x):
+    """(sin, cos, refined 1/sqrt(x^2), library 1/sqrt(x^2)) of a float64 CUDA
+    tensor x by the near-field device routines; returns a [n, 4] tensor."""
+    import torch
+    lib = load_library()
+    x = x.contiguous()
+    out = torch.empty((x.numel(), 4), dtype=torch.float64, device=x.device)
+    rc = lib.lm_selftest_math(x.numel(), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                              ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream))
+    if rc:
+        raise LMError("lm_selftest_math failed (%d)" % rc)
+    return out
