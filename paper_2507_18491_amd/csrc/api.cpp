@@ -27,7 +27,9 @@ struct lm_ctx {
   std::vector<void*> allocs;  // persistent device buffers of the current build
   double* d_src = nullptr;
   double* d_tgt = nullptr;
-  int* d_p2m = nullptr;
+  int* d_p2m = nullptr;       // P2M leaves of instances with p <= 12
+  int* d_p2m_hi = nullptr;    // P2M leaves of higher-order instances
+  int n_p2m_lo = 0, n_p2m_hi = 0, p2m_plo = 0, p2m_phi = 0;
   std::vector<int*> d_m2m, d_l2l, d_l2p, d_p2p;
   std::vector<int> n_m2m, n_l2l, n_l2p, n_p2p;
   std::vector<int> p2p_inst;  // instance of each P2P list
@@ -290,6 +292,7 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
   HIPC(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   free_build(ctx);
+  if (lm_upload_leg_tables()) return fail(ctx, LM_EHIP, "cannot upload the Legendre coefficient tables");
   auto t0 = std::chrono::steady_clock::now();
   std::string msg = lm_make_plan_multi(ctx->plan, med, ctx->prm, n_geom, soff, src_xyz, toff, tgt_xyz);
   if (!msg.empty()) return fail(ctx, LM_EDOMAIN, msg);
@@ -329,7 +332,29 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
   std::vector<double> sx(src_xyz, src_xyz + 3 * n_src), tx(tgt_xyz, tgt_xyz + 3 * n_tgt);
   if ((rc = upload(ctx, &ctx->d_src, sx))) return rc;
   if ((rc = upload(ctx, &ctx->d_tgt, tx))) return rc;
-  if ((rc = upload(ctx, &ctx->d_p2m, pl.p2m_leaves))) return rc;
+  {
+    // leaves of low-order instances (reaction components, typically few points
+    // each) and of high-order ones are launched separately, each with LDS
+    // sized for its own order
+    std::vector<int> lo, hi;
+    int plo = 0, phi = 0;
+    for (int b : pl.p2m_leaves) {
+      int ip = pl.inst[pl.sbox[b].inst].p;
+      if (ip <= 12) {
+        lo.push_back(b);
+        plo = std::max(plo, ip);
+      } else {
+        hi.push_back(b);
+        phi = std::max(phi, ip);
+      }
+    }
+    if ((rc = upload(ctx, &ctx->d_p2m, lo))) return rc;
+    if ((rc = upload(ctx, &ctx->d_p2m_hi, hi))) return rc;
+    ctx->n_p2m_lo = (int)lo.size();
+    ctx->n_p2m_hi = (int)hi.size();
+    ctx->p2m_plo = plo;
+    ctx->p2m_phi = phi;
+  }
   for (auto& v : pl.m2m_parents) {
     int* p = nullptr;
     if ((rc = upload(ctx, &p, v))) return rc;
@@ -342,11 +367,20 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
     ctx->d_l2l.push_back(p);
     ctx->n_l2l.push_back((int)v.size());
   }
-  for (auto& v : pl.l2p_leaves) {
+  for (size_t i = 0; i < pl.l2p_leaves.size(); i++) {
+    // L2P work items: (leaf, chunk of LM_L2P_CHUNK points), so that leaves
+    // holding many points spread over many workgroups
+    int ch = LM_L2P_CHUNK(pl.inst[i].kind == 0 ? 0 : 1);
+    std::vector<int> items;
+    for (int b : pl.l2p_leaves[i])
+      for (int c = 0; c * ch < pl.tbox[b].pt1 - pl.tbox[b].pt0; c++) {
+        items.push_back(b);
+        items.push_back(c);
+      }
     int* p = nullptr;
-    if ((rc = upload(ctx, &p, v))) return rc;
+    if ((rc = upload(ctx, &p, items))) return rc;
     ctx->d_l2p.push_back(p);
-    ctx->n_l2p.push_back((int)v.size());
+    ctx->n_l2p.push_back((int)items.size() / 2);
   }
   {
     int fi = 0;
@@ -705,7 +739,8 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
   if (pl.n_src > 0 && pl.n_tgt > 0) launch_fill(ctx->LE, pl.le_size * n_rhs, s);
   mark(1);
   if (pl.n_src > 0 && pl.n_tgt > 0) {
-    launch_p2m(d, ctx->d_p2m, (int)pl.p2m_leaves.size(), ctx->d_src, Jc, pl.n_src, n_rhs, ctx->ME, ctx->pmax, s);
+    launch_p2m(d, ctx->d_p2m, ctx->n_p2m_lo, ctx->d_src, Jc, pl.n_src, n_rhs, ctx->ME, ctx->p2m_plo, s);
+    launch_p2m(d, ctx->d_p2m_hi, ctx->n_p2m_hi, ctx->d_src, Jc, pl.n_src, n_rhs, ctx->ME, ctx->p2m_phi, s);
     mark(2);
     for (int l = (int)ctx->d_m2m.size() - 1; l >= 0; l--)
       launch_m2m(d, ctx->d_m2m[l], ctx->n_m2m[l], n_rhs, ctx->ME, ctx->pmax, s);
@@ -727,7 +762,7 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
         launch_l2p_grad(d, ctx->d_l2p[i], ctx->n_l2p[i], kind, ctx->d_tgt, pl.n_tgt, n_rhs, ctx->LE, W, gX,
                         ctx->pmax, s);
       else
-        launch_l2p(d, ctx->d_l2p[i], ctx->n_l2p[i], kind, ctx->d_tgt, pl.n_tgt, n_rhs, ctx->LE, Ac, ctx->pmax, s);
+        launch_l2p(d, ctx->d_l2p[i], ctx->n_l2p[i], kind, ctx->d_tgt, pl.n_tgt, n_rhs, ctx->LE, Ac, pl.inst[i].p, s);
     }
     mark(6);
     for (size_t f = 0; f < ctx->d_p2p.size(); f++) {

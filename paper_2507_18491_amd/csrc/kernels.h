@@ -46,6 +46,8 @@ struct DevPlan {
 };
 
 void launch_fill(cd* p, long long n, hipStream_t s);
+// uploads the Legendre recurrence coefficients to the current device (once)
+int lm_upload_leg_tables();
 void launch_trans(const DevPlan& d, int n_jobs, int pmax_gaunt, hipStream_t s);
 void launch_nodes(const DevPlan& d, MediumDev med, int n_nodes, const int* node_inst, const cd* kr,
                   const cd* w, hipStream_t s);
@@ -53,7 +55,7 @@ void launch_tab_integrals(const DevPlan& d, MediumDev med, int case0, int ncase,
                           long long scratch_stride, hipStream_t s);
 void launch_tab_assemble(const DevPlan& d, int case0, int ncase, int p, int kmaxcheb, int bstride, hipStream_t s);
 void launch_p2m(const DevPlan& d, const int* leaves, int n, const double* xyz, const cd* J,
-                long long n_src, int n_rhs, cd* ME, int pmax, hipStream_t s);
+                long long n_src, int n_rhs, cd* ME, int pl, hipStream_t s);
 void launch_m2m(const DevPlan& d, const int* parents, int n, int n_rhs, cd* ME, int pmax, hipStream_t s);
 void launch_m2l(const DevPlan& d, const M2LTile* tiles, int n_tiles, int n_rhs, const cd* ME, cd* Y, int pmax,
                 hipStream_t s);
@@ -61,7 +63,7 @@ void launch_m2l_reduce(const DevPlan& d, int bt0, int nbt, int n_rhs, const cd* 
                        hipStream_t s);
 void launch_l2l(const DevPlan& d, const int* children, int n, int n_rhs, cd* LE, int pmax, hipStream_t s);
 void launch_l2p(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_tgt,
-                int n_rhs, const cd* LE, cd* A, int pmax, hipStream_t s);
+                int n_rhs, const cd* LE, cd* A, int pi, hipStream_t s);
 void launch_p2p(const DevPlan& d, const int* tboxes, int n, const double* sxyz, const cd* J, long long n_src,
                 const double* txyz, long long n_tgt, int n_rhs, double k, cd* A, bool red, hipStream_t s);
 void launch_conj(cd* out, const cd* in, long long n, hipStream_t s);

@@ -11,11 +11,55 @@
 // channels in the spin basis (x + i y, x - i y, z).
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+#include <vector>
+
 #include "kernels.h"
 
 // RC (template parameter): right-hand sides per block in the point/translation passes (1 or 4)
 #define NT 256          // threads per block
 static_assert(NT == LM_P2P_CHUNK, "near-field work items hold one block's worth of targets");
+
+// Coefficients of the orthonormal associated Legendre recurrences (uploaded
+// once per device): P^m_m = LEG_MM[m] sin P^{m-1}_{m-1}, P^m_{m+1} =
+// LEG_M1[m] cos P^m_m, P^m_n = LEG_A[n][m] (cos P^m_{n-1} - LEG_B[n][m] P^m_{n-2}).
+#define LEGN (LM_PMAX + 5)
+__constant__ double c_leg_a[LEGN * LEGN], c_leg_b[LEGN * LEGN], c_leg_mm[LEGN], c_leg_m1[LEGN];
+
+int lm_upload_leg_tables() {
+  static bool done[64] = {false};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -1;
+  if (done[dev]) return 0;
+  std::vector<double> a(LEGN * LEGN, 0.0), b(LEGN * LEGN, 0.0), mm(LEGN, 0.0), m1(LEGN, 0.0);
+  for (int m = 0; m < LEGN; m++) {
+    mm[m] = m > 0 ? -std::sqrt((2.0 * m + 1.0) / (2.0 * m)) : 0.0;
+    m1[m] = std::sqrt(2.0 * m + 3.0);
+    for (int n = m + 2; n < LEGN; n++) {
+      a[n * LEGN + m] = std::sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));
+      b[n * LEGN + m] = std::sqrt(((n - 1.0) * (n - 1.0) - (double)m * m) / (4.0 * (n - 1.0) * (n - 1.0) - 1.0));
+    }
+  }
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_leg_a), a.data(), a.size() * sizeof(double)) != hipSuccess ||
+      hipMemcpyToSymbol(HIP_SYMBOL(c_leg_b), b.data(), b.size() * sizeof(double)) != hipSuccess ||
+      hipMemcpyToSymbol(HIP_SYMBOL(c_leg_mm), mm.data(), mm.size() * sizeof(double)) != hipSuccess ||
+      hipMemcpyToSymbol(HIP_SYMBOL(c_leg_m1), m1.data(), m1.size() * sizeof(double)) != hipSuccess)
+    return -1;
+  done[dev] = true;
+  return 0;
+}
+
+// orthonormal P^m_n(cos t), 0 <= m <= n <= nmax, triangular layout tri_idx(n, m)
+__device__ inline void legendre_rt(int nmax, double c, double s, double* out) {
+  out[0] = LM_INV_SQRT_4PI;
+  for (int m = 1; m <= nmax; m++) out[tri_idx(m, m)] = c_leg_mm[m] * s * out[tri_idx(m - 1, m - 1)];
+  for (int m = 0; m <= nmax; m++) {
+    if (m + 1 <= nmax) out[tri_idx(m + 1, m)] = c_leg_m1[m] * c * out[tri_idx(m, m)];
+    for (int n = m + 2; n <= nmax; n++)
+      out[tri_idx(n, m)] =
+          c_leg_a[n * LEGN + m] * (c * out[tri_idx(n - 1, m)] - c_leg_b[n * LEGN + m] * out[tri_idx(n - 2, m)]);
+  }
+}
 
 __device__ inline int n_of(int nm) {
   int n = (int)sqrt((double)nm);
@@ -41,10 +85,13 @@ void launch_fill(cd* p, long long n, hipStream_t s) {
 // M[r][ch][nm] = sum_j q_j^ch j_n(k |d_j|) conj(Y^m_n(d_j)),  d_j = image(x_j) - centre
 // (paper Sec. 2, the multipole coefficients, and Sec. 3.3, the reaction ME
 // coefficients; the constant 4 pi lives in the M2L tables).
-#define P2M_NPT 32
-template <int RC>
-__global__ __launch_bounds__(NT) void k_p2m(DevPlan d, const int* leaves, const double* xyz, const cd* J,
-                                            long long n_src, int n_rhs, cd* ME) {
+// NTB threads per leaf, each owning H coefficients (P <= NTB H); point
+// records (basis values, charges) staged in LDS NPT points at a time.  Reaction
+// leaves hold few points (often one or two near the interfaces), so they are
+// run with one-wave blocks and LDS sized for their own order.
+template <int RC, int NTB, int H, int NPT>
+__global__ __launch_bounds__(NTB) void k_p2m(DevPlan d, const int* leaves, const double* xyz, const cd* J,
+                                             long long n_src, int n_rhs, cd* ME) {
   extern __shared__ double sm[];
   int b = leaves[blockIdx.x];
   SrcBox sb = d.sbox[b];
@@ -53,12 +100,12 @@ __global__ __launch_bounds__(NT) void k_p2m(DevPlan d, const int* leaves, const 
   int r0 = blockIdx.y * RC, nr = min(RC, n_rhs - r0);
   int stride = (p + 1) + ntri + 2 * (p + 1) + RC * 6;
   int tid = threadIdx.x;
-  cd acc[2][RC][3];
-  for (int h = 0; h < 2; h++)
+  cd acc[H][RC][3];
+  for (int h = 0; h < H; h++)
     for (int r = 0; r < RC; r++)
       for (int c = 0; c < 3; c++) acc[h][r][c] = cd{0, 0};
-  for (int base = sb.pt0; base < sb.pt1; base += P2M_NPT) {
-    int np = min(P2M_NPT, sb.pt1 - base);
+  for (int base = sb.pt0; base < sb.pt1; base += NPT) {
+    int np = min(NPT, sb.pt1 - base);
     __syncthreads();
     if (tid < np) {
       double* rec = sm + tid * stride;
@@ -69,7 +116,7 @@ __global__ __launch_bounds__(NT) void k_p2m(DevPlan d, const int* leaves, const 
       double ct = r > 0 ? dz / r : 1.0, st = r > 0 ? rxy / r : 0.0;
       double ex = rxy > 0 ? dx / rxy : 1.0, ey = rxy > 0 ? dy / rxy : 0.0;
       sph_jn(p, ip.ks * r, rec);
-      legendre_r(p, ct, st, rec + (p + 1));
+      legendre_rt(p, ct, st, rec + (p + 1));
       double* e = rec + (p + 1) + ntri;  // e^{-i m phi}
       cd em = cd{1.0, 0.0}, e1 = cd{ex, -ey};
       for (int m = 0; m <= p; m++) {
@@ -97,8 +144,8 @@ __global__ __launch_bounds__(NT) void k_p2m(DevPlan d, const int* leaves, const 
       }
     }
     __syncthreads();
-    for (int h = 0; h < 2; h++) {
-      int nm = tid + NT * h;
+    for (int h = 0; h < H; h++) {
+      int nm = tid + NTB * h;
       if (nm >= P) continue;
       int n = n_of(nm), m = nm - n * n - n, am = m < 0 ? -m : m;
       double sg = (m < 0 && (am & 1)) ? -1.0 : 1.0;
@@ -114,26 +161,36 @@ __global__ __launch_bounds__(NT) void k_p2m(DevPlan d, const int* leaves, const 
       }
     }
   }
-  for (int h = 0; h < 2; h++) {
-    int nm = tid + NT * h;
+  for (int h = 0; h < H; h++) {
+    int nm = tid + NTB * h;
     if (nm >= P) continue;
     for (int rr = 0; rr < nr; rr++)
       for (int c = 0; c < 3; c++) ME[sb.me_off * n_rhs + ((long long)(r0 + rr) * 3 + c) * P + nm] = acc[h][rr][c];
   }
 }
+template <int RC, int NTB, int H, int NPT>
+static void p2m_go(const DevPlan& d, const int* leaves, int n, const double* xyz, const cd* J, long long n_src,
+                   int n_rhs, cd* ME, int pl, hipStream_t s) {
+  int ntri = (pl + 1) * (pl + 2) / 2;
+  size_t shm = (size_t)NPT * ((pl + 1) + ntri + 2 * (pl + 1) + RC * 6) * sizeof(double);
+  hipFuncSetAttribute((const void*)k_p2m<RC, NTB, H, NPT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL((k_p2m<RC, NTB, H, NPT>), dim3(n, (n_rhs + RC - 1) / RC), dim3(NTB), shm, s, d, leaves, xyz, J,
+                     n_src, n_rhs, ME);
+}
+// pl: the largest order among the listed leaves' instances
 void launch_p2m(const DevPlan& d, const int* leaves, int n, const double* xyz, const cd* J, long long n_src,
-                int n_rhs, cd* ME, int pmax, hipStream_t s) {
+                int n_rhs, cd* ME, int pl, hipStream_t s) {
   if (n <= 0) return;
-  int ntri = (pmax + 1) * (pmax + 2) / 2;
-  int rc = n_rhs == 1 ? 1 : 4;
-  size_t shm = (size_t)P2M_NPT * ((pmax + 1) + ntri + 2 * (pmax + 1) + rc * 6) * sizeof(double);
-  if (rc == 1) {
-    hipFuncSetAttribute((const void*)k_p2m<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(k_p2m<1>, dim3(n, n_rhs), dim3(NT), shm, s, d, leaves, xyz, J, n_src, n_rhs, ME);
-  } else {
-    hipFuncSetAttribute((const void*)k_p2m<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(k_p2m<4>, dim3(n, (n_rhs + 3) / 4), dim3(NT), shm, s, d, leaves, xyz, J, n_src, n_rhs, ME);
-  }
+  bool rc1 = n_rhs == 1;
+  int P = (pl + 1) * (pl + 1);
+  if (P <= 64 * 3 && rc1)
+    p2m_go<1, 64, 3, 16>(d, leaves, n, xyz, J, n_src, n_rhs, ME, pl, s);
+  else if (P <= 128 * 2 && !rc1)
+    p2m_go<4, 128, 2, 16>(d, leaves, n, xyz, J, n_src, n_rhs, ME, pl, s);
+  else if (rc1)
+    p2m_go<1, NT, 2, 32>(d, leaves, n, xyz, J, n_src, n_rhs, ME, pl, s);
+  else
+    p2m_go<4, NT, 2, 32>(d, leaves, n, xyz, J, n_src, n_rhs, ME, pl, s);
 }
 
 // ------------------------------------------------------------------ M2M
@@ -594,11 +651,15 @@ __device__ inline cd dapply(const cd* c, int oi, int dir, int n, int m) {
   return -1.0 * v;
 }
 
-template <int RC>
-__global__ __launch_bounds__(NT) void k_l2p(DevPlan d, const int* leaves, int kind, const double* xyz,
-                                            long long n_tgt, int n_rhs, const cd* LE, cd* A) {
+// NTB threads per leaf (one point each at a time); the spherical Bessel
+// values of each thread's point sit in its own LDS slot.
+template <int RC, int NTB>
+__global__ __launch_bounds__(NTB) void k_l2p(DevPlan d, const int* leaves, int ch, int kind, const double* xyz,
+                                             long long n_tgt, int n_rhs, const cd* LE, cd* A) {
   extern __shared__ cd Ls[];
-  int b = leaves[blockIdx.x];
+  // work item: (leaf, chunk of ch points)
+  int b = leaves[2 * blockIdx.x];
+  const int q0 = d.tbox[b].pt0 + leaves[2 * blockIdx.x + 1] * ch;
   TgtBox tb = d.tbox[b];
   InstParams ip = d.inst[tb.inst];
   int p = ip.p, P = ip.P;
@@ -608,7 +669,7 @@ __global__ __launch_bounds__(NT) void k_l2p(DevPlan d, const int* leaves, int ki
   double k = ip.kt;
   cd* Lc = Ls;                       // [RC][3][Pe]
   cd* Dv = Ls + RC * 3 * Pe;         // [RC][(p+2)^2] divergence
-  for (int e = tid; e < RC * 3 * Pe; e += NT) {
+  for (int e = tid; e < RC * 3 * Pe; e += NTB) {
     int rr = e / (3 * Pe), rem = e - rr * 3 * Pe, c = rem / Pe, nm = rem - c * Pe;
     cd v = cd{0, 0};
     if (rr < nr && nm < P) v = LE[tb.le_off * n_rhs + ((long long)(r0 + rr) * 3 + c) * P + nm];
@@ -617,7 +678,7 @@ __global__ __launch_bounds__(NT) void k_l2p(DevPlan d, const int* leaves, int ki
   __syncthreads();
   if (kind == 0) {
     int Pd = (p + 2) * (p + 2);
-    for (int e = tid; e < RC * Pd; e += NT) {
+    for (int e = tid; e < RC * Pd; e += NTB) {
       int rr = e / Pd, nm = e - rr * Pd;
       int n = n_of(nm), m = nm - n * n - n;
       const cd* Lp = Lc + (rr * 3 + 0) * Pe;
@@ -628,23 +689,24 @@ __global__ __launch_bounds__(NT) void k_l2p(DevPlan d, const int* leaves, int ki
     }
     __syncthreads();
     // A = U + grad div U / k^2 (order p+2); the gradient only reads Dv
-    for (int e = tid; e < RC * 3 * Pe; e += NT) {
+    for (int e = tid; e < RC * 3 * Pe; e += NTB) {
       int rr = e / (3 * Pe), rem = e - rr * 3 * Pe, c = rem / Pe, nm = rem - c * Pe;
       int n = n_of(nm), m = nm - n * n - n;
       Lc[e] = Lc[e] + (1.0 / k) * dapply(Dv + rr * Pd, p + 1, c, n, m);
     }
     __syncthreads();
   }
-  for (int t0 = tb.pt0; t0 < tb.pt1; t0 += NT) {
+  const int q1 = min(tb.pt1, q0 + ch);
+  for (int t0 = q0; t0 < q1; t0 += NTB) {
     int ti = t0 + tid;
-    if (ti >= tb.pt1) continue;
+    if (ti >= q1) continue;
     int id = d.tgt_perm[ti];
     double dx = xyz[3 * id] - tb.c[0], dy = xyz[3 * id + 1] - tb.c[1];
     double dz = ip.at * xyz[3 * id + 2] + ip.bt - tb.c[2];
     double rxy = sqrt(dx * dx + dy * dy), r = sqrt(dx * dx + dy * dy + dz * dz);
     double ct = r > 0 ? dz / r : 1.0, st = r > 0 ? rxy / r : 0.0;
     cd e1 = rxy > 0 ? cd{dx / rxy, dy / rxy} : cd{1.0, 0.0};
-    double jn[LM_PMAX + 4];
+    double* jn = (double*)(Dv + RC * (p + 2) * (p + 2)) + tid * (pe + 1);
     sph_jn(pe, k * r, jn);
     cd acc[RC][3];
     for (int rr = 0; rr < RC; rr++)
@@ -654,7 +716,7 @@ __global__ __launch_bounds__(NT) void k_l2p(DevPlan d, const int* leaves, int ki
     cd em = cd{1.0, 0.0};
     for (int m = 0; m <= pe; m++) {
       if (m > 0) {
-        pmm = -sqrt((2.0 * m + 1.0) / (2.0 * m)) * st * pmm;
+        pmm = c_leg_mm[m] * st * pmm;
         em = em * e1;
       }
       double p2 = 0.0, p1 = pmm;
@@ -663,12 +725,9 @@ __global__ __launch_bounds__(NT) void k_l2p(DevPlan d, const int* leaves, int ki
         if (n == m)
           pn = pmm;
         else if (n == m + 1)
-          pn = sqrt(2.0 * m + 3.0) * ct * pmm;
-        else {
-          double a = sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));
-          double bb = sqrt(((n - 1.0) * (n - 1.0) - (double)m * m) / (4.0 * (n - 1.0) * (n - 1.0) - 1.0));
-          pn = a * (ct * p1 - bb * p2);
-        }
+          pn = c_leg_m1[m] * ct * pmm;
+        else
+          pn = c_leg_a[n * LEGN + m] * (ct * p1 - c_leg_b[n * LEGN + m] * p2);
         if (n > m) {
           p2 = p1;
           p1 = pn;
@@ -699,19 +758,34 @@ __global__ __launch_bounds__(NT) void k_l2p(DevPlan d, const int* leaves, int ki
     }
   }
 }
+template <int RC, int NTB>
+static void l2p_go(const DevPlan& d, const int* leaves, int n, int ch, int kind, const double* xyz, long long n_tgt,
+                   int n_rhs, const cd* LE, cd* A, int pi, hipStream_t s) {
+  int pe = kind == 0 ? pi + 2 : pi;
+  int Pe = (pe + 1) * (pe + 1), Pd = (pi + 2) * (pi + 2);
+  size_t shm = (size_t)(RC * 3 * Pe + RC * Pd) * sizeof(cd) + (size_t)NTB * (pe + 1) * sizeof(double);
+  hipFuncSetAttribute((const void*)k_l2p<RC, NTB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL((k_l2p<RC, NTB>), dim3(n, (n_rhs + RC - 1) / RC), dim3(NTB), shm, s, d, leaves, ch, kind, xyz,
+                     n_tgt, n_rhs, LE, A);
+}
+// leaves: n work items (leaf, chunk of LM_L2P_CHUNK(kind) points); pi: the
+// instance's expansion order.  Reaction items (kind 1) run with one-wave
+// blocks, free-space ones with 256 threads.
 void launch_l2p(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_tgt,
-                int n_rhs, const cd* LE, cd* A, int pmax, hipStream_t s) {
+                int n_rhs, const cd* LE, cd* A, int pi, hipStream_t s) {
   if (n <= 0) return;
-  int pe = pmax + 2;
-  int Pe = (pe + 1) * (pe + 1), Pd = (pmax + 2) * (pmax + 2);
-  int rc = n_rhs == 1 ? 1 : 4;
-  size_t shm = (size_t)(rc * 3 * Pe + rc * Pd) * sizeof(cd);
-  if (rc == 1) {
-    hipFuncSetAttribute((const void*)k_l2p<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(k_l2p<1>, dim3(n, n_rhs), dim3(NT), shm, s, d, leaves, kind, xyz, n_tgt, n_rhs, LE, A);
+  bool rc1 = n_rhs == 1;
+  int ch = LM_L2P_CHUNK(kind);
+  if (kind == 1) {
+    if (rc1)
+      l2p_go<1, 64>(d, leaves, n, ch, kind, xyz, n_tgt, n_rhs, LE, A, pi, s);
+    else
+      l2p_go<4, 64>(d, leaves, n, ch, kind, xyz, n_tgt, n_rhs, LE, A, pi, s);
   } else {
-    hipFuncSetAttribute((const void*)k_l2p<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(k_l2p<4>, dim3(n, (n_rhs + 3) / 4), dim3(NT), shm, s, d, leaves, kind, xyz, n_tgt, n_rhs, LE, A);
+    if (rc1)
+      l2p_go<1, NT>(d, leaves, n, ch, kind, xyz, n_tgt, n_rhs, LE, A, pi, s);
+    else  // 4 right-hand sides at p = 20: 128 threads keep LDS under 160 KB
+      l2p_go<4, 128>(d, leaves, n, ch, kind, xyz, n_tgt, n_rhs, LE, A, pi, s);
   }
 }
 
@@ -871,11 +945,13 @@ void launch_conj(cd* out, const cd* in, long long n, hipStream_t s) {
 // wave functions) give 9 expansions of one order more, evaluated at every
 // point of the leaf.  For a reaction component the evaluation point is the
 // effective location zhat = at z + bt, so d/dz = at d/dzhat.
-__global__ __launch_bounds__(NT) void k_l2p_grad(DevPlan d, const int* leaves, int kind, const double* xyz,
+__global__ __launch_bounds__(NT) void k_l2p_grad(DevPlan d, const int* leaves, int ch, int kind, const double* xyz,
                                                  long long n_pts, int n_rhs, const cd* LE, const cd* W,
                                                  double* gX) {
   extern __shared__ cd Ls[];
-  int b = leaves[blockIdx.x];
+  // work item: (leaf, chunk of ch points)
+  int b = leaves[2 * blockIdx.x];
+  const int q0 = d.tbox[b].pt0 + leaves[2 * blockIdx.x + 1] * ch;
   TgtBox tb = d.tbox[b];
   InstParams ip = d.inst[tb.inst];
   int p = ip.p, P = ip.P;
@@ -916,9 +992,10 @@ __global__ __launch_bounds__(NT) void k_l2p_grad(DevPlan d, const int* leaves, i
       Gc[e] = dapply(Lc + c * Pg, pa, dir, n, m);
     }
     __syncthreads();
-    for (int t0 = tb.pt0; t0 < tb.pt1; t0 += NT) {
+    const int q1 = min(tb.pt1, q0 + ch);
+    for (int t0 = q0; t0 < q1; t0 += NT) {
       int ti = t0 + tid;
-      if (ti >= tb.pt1) continue;
+      if (ti >= q1) continue;
       int id = d.tgt_perm[ti];
       double dx = xyz[3 * id] - tb.c[0], dy = xyz[3 * id + 1] - tb.c[1];
       double dz = ip.at * xyz[3 * id + 2] + ip.bt - tb.c[2];
@@ -933,7 +1010,7 @@ __global__ __launch_bounds__(NT) void k_l2p_grad(DevPlan d, const int* leaves, i
       cd em = cd{1.0, 0.0};
       for (int m = 0; m <= pg; m++) {
         if (m > 0) {
-          pmm = -sqrt((2.0 * m + 1.0) / (2.0 * m)) * st * pmm;
+          pmm = c_leg_mm[m] * st * pmm;
           em = em * e1;
         }
         double p2 = 0.0, p1 = pmm;
@@ -942,12 +1019,9 @@ __global__ __launch_bounds__(NT) void k_l2p_grad(DevPlan d, const int* leaves, i
           if (n == m)
             pn = pmm;
           else if (n == m + 1)
-            pn = sqrt(2.0 * m + 3.0) * ct * pmm;
-          else {
-            double a = sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));
-            double bb = sqrt(((n - 1.0) * (n - 1.0) - (double)m * m) / (4.0 * (n - 1.0) * (n - 1.0) - 1.0));
-            pn = a * (ct * p1 - bb * p2);
-          }
+            pn = c_leg_m1[m] * ct * pmm;
+          else
+            pn = c_leg_a[n * LEGN + m] * (ct * p1 - c_leg_b[n * LEGN + m] * p2);
           if (n > m) {
             p2 = p1;
             p1 = pn;
@@ -993,7 +1067,8 @@ void launch_l2p_grad(const DevPlan& d, const int* leaves, int n, int kind, const
   int Pg = (pg + 1) * (pg + 1), Pd = (pmax + 2) * (pmax + 2);
   size_t shm = (size_t)(12 * Pg + Pd) * sizeof(cd);
   hipFuncSetAttribute((const void*)k_l2p_grad, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL(k_l2p_grad, dim3(n), dim3(NT), shm, s, d, leaves, kind, xyz, n_pts, n_rhs, LE, W, gX);
+  hipLaunchKernelGGL(k_l2p_grad, dim3(n), dim3(NT), shm, s, d, leaves, LM_L2P_CHUNK(kind), kind, xyz, n_pts, n_rhs,
+                     LE, W, gX);
 }
 
 // Free-space near field: for the target point x_i (here a source point of

@@ -12,6 +12,7 @@
 #define LM_MAXL 16
 #define LM_PMAX 24
 #define LM_P2P_CHUNK 256   // targets per near-field work item (= threads per block)
+#define LM_L2P_CHUNK(kind) ((kind) == 0 ? 256 : 64)   // points per L2P work item (free / reaction)
 
 // One FMM instance: the free-space part of one layer, or one reaction
 // component (target layer lt, source layer ls, arrival direction at the

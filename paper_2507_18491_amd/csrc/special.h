@@ -187,14 +187,16 @@ LM_HD void sph_jn(int nmax, double x, double* out) {
   if (x > (double)nmax) {
     out[0] = j0;
     if (nmax >= 1) out[1] = j1;
-    for (int n = 1; n < nmax; n++) out[n + 1] = (2.0 * n + 1.0) / x * out[n] - out[n - 1];
+    const double ix = 1.0 / x;
+    for (int n = 1; n < nmax; n++) out[n + 1] = (2.0 * n + 1.0) * ix * out[n] - out[n - 1];
     return;
   }
   int N = nmax + 16 + (int)(x);
   double fp1 = 0.0, f = 1e-280, scale = 1.0;
   // run down from N to 0, storing n <= nmax
+  const double ix = 1.0 / x;
   for (int n = N; n >= 1; n--) {
-    double fm1 = (2.0 * n + 1.0) / x * f - fp1;
+    double fm1 = (2.0 * n + 1.0) * ix * f - fp1;
     fp1 = f;
     f = fm1;
     if (n - 1 <= nmax) out[n - 1] = f;
