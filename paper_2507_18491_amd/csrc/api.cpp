@@ -760,7 +760,7 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
       int kind = pl.inst[i].kind == 0 ? 0 : 1;
       if (grad)
         launch_l2p_grad(d, ctx->d_l2p[i], ctx->n_l2p[i], kind, ctx->d_tgt, pl.n_tgt, n_rhs, ctx->LE, W, gX,
-                        ctx->pmax, s);
+                        pl.inst[i].p, s);
       else
         launch_l2p(d, ctx->d_l2p[i], ctx->n_l2p[i], kind, ctx->d_tgt, pl.n_tgt, n_rhs, ctx->LE, Ac, pl.inst[i].p, s);
     }

@@ -70,7 +70,7 @@ void launch_conj(cd* out, const cd* in, long long n, hipStream_t s);
 void launch_fill_d(double* p, long long n, hipStream_t s);
 void launch_selftest_math(const double* x, long long n, double* out, hipStream_t s);
 void launch_l2p_grad(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_pts,
-                     int n_rhs, const cd* LE, const cd* W, double* gX, int pmax, hipStream_t s);
+                     int n_rhs, const cd* LE, const cd* W, double* gX, int pi, hipStream_t s);
 void launch_p2p_grad(const DevPlan& d, const int* tboxes, int n, const double* sxyz, const cd* Jsrc,
                      long long n_src, const double* txyz, const cd* W, long long n_tgt, int n_rhs, double k,
                      double* gX, bool red, hipStream_t s);

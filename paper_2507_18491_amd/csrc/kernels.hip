@@ -945,9 +945,10 @@ void launch_conj(cd* out, const cd* in, long long n, hipStream_t s) {
 // wave functions) give 9 expansions of one order more, evaluated at every
 // point of the leaf.  For a reaction component the evaluation point is the
 // effective location zhat = at z + bt, so d/dz = at d/dzhat.
-__global__ __launch_bounds__(NT) void k_l2p_grad(DevPlan d, const int* leaves, int ch, int kind, const double* xyz,
-                                                 long long n_pts, int n_rhs, const cd* LE, const cd* W,
-                                                 double* gX) {
+template <int NTB>
+__global__ __launch_bounds__(NTB) void k_l2p_grad(DevPlan d, const int* leaves, int ch, int kind, const double* xyz,
+                                                  long long n_pts, int n_rhs, const cd* LE, const cd* W,
+                                                  double* gX) {
   extern __shared__ cd Ls[];
   // work item: (leaf, chunk of ch points)
   int b = leaves[2 * blockIdx.x];
@@ -965,27 +966,27 @@ __global__ __launch_bounds__(NT) void k_l2p_grad(DevPlan d, const int* leaves, i
   cd* Gc = Dv + Pd;       // [9][Pg]   (channel, direction) derivative expansions
   for (int r = 0; r < n_rhs; r++) {
     __syncthreads();
-    for (int e = tid; e < 3 * Pg; e += NT) {
+    for (int e = tid; e < 3 * Pg; e += NTB) {
       int c = e / Pg, nm = e - c * Pg;
       Lc[e] = nm < P ? LE[tb.le_off * n_rhs + ((long long)r * 3 + c) * P + nm] : cd{0, 0};
     }
     __syncthreads();
     if (kind == 0) {
-      for (int nm = tid; nm < Pd; nm += NT) {
+      for (int nm = tid; nm < Pd; nm += NTB) {
         int n = n_of(nm), m = nm - n * n - n;
         cd v = 0.5 * (dapply(Lc + Pg, p, 0, n, m) + dapply(Lc, p, 1, n, m)) + dapply(Lc + 2 * Pg, p, 2, n, m);
         Dv[nm] = k * v;
       }
       __syncthreads();
       int Pa = (pa + 1) * (pa + 1);
-      for (int e = tid; e < 3 * Pa; e += NT) {
+      for (int e = tid; e < 3 * Pa; e += NTB) {
         int c = e / Pa, nm = e - c * Pa;
         int n = n_of(nm), m = nm - n * n - n;
         Lc[c * Pg + nm] = Lc[c * Pg + nm] + (1.0 / k) * dapply(Dv, p + 1, c, n, m);
       }
       __syncthreads();
     }
-    for (int e = tid; e < 9 * Pg; e += NT) {
+    for (int e = tid; e < 9 * Pg; e += NTB) {
       int cd_ = e / Pg, nm = e - cd_ * Pg;
       int c = cd_ / 3, dir = cd_ - 3 * c;
       int n = n_of(nm), m = nm - n * n - n;
@@ -993,7 +994,7 @@ __global__ __launch_bounds__(NT) void k_l2p_grad(DevPlan d, const int* leaves, i
     }
     __syncthreads();
     const int q1 = min(tb.pt1, q0 + ch);
-    for (int t0 = q0; t0 < q1; t0 += NT) {
+    for (int t0 = q0; t0 < q1; t0 += NTB) {
       int ti = t0 + tid;
       if (ti >= q1) continue;
       int id = d.tgt_perm[ti];
@@ -1002,7 +1003,7 @@ __global__ __launch_bounds__(NT) void k_l2p_grad(DevPlan d, const int* leaves, i
       double rxy = sqrt(dx * dx + dy * dy), rr_ = sqrt(dx * dx + dy * dy + dz * dz);
       double ct = rr_ > 0 ? dz / rr_ : 1.0, st = rr_ > 0 ? rxy / rr_ : 0.0;
       cd e1 = rxy > 0 ? cd{dx / rxy, dy / rxy} : cd{1.0, 0.0};
-      double jn[LM_PMAX + 5];
+      double* jn = (double*)(Gc + 9 * Pg) + tid * (pg + 1);
       sph_jn(pg, k * rr_, jn);
       cd acc[9];
       for (int q = 0; q < 9; q++) acc[q] = cd{0, 0};
@@ -1060,15 +1061,25 @@ __global__ __launch_bounds__(NT) void k_l2p_grad(DevPlan d, const int* leaves, i
     }
   }
 }
+template <int NTB>
+static void l2p_grad_go(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_pts,
+                        int n_rhs, const cd* LE, const cd* W, double* gX, int pi, hipStream_t s) {
+  int pg = (kind == 0 ? pi + 2 : pi) + 1;
+  int Pg = (pg + 1) * (pg + 1), Pd = (pi + 2) * (pi + 2);
+  size_t shm = (size_t)(12 * Pg + Pd) * sizeof(cd) + (size_t)NTB * (pg + 1) * sizeof(double);
+  hipFuncSetAttribute((const void*)k_l2p_grad<NTB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL(k_l2p_grad<NTB>, dim3(n), dim3(NTB), shm, s, d, leaves, LM_L2P_CHUNK(kind), kind, xyz, n_pts,
+                     n_rhs, LE, W, gX);
+}
+// pi: the instance's expansion order; reaction items with one-wave blocks,
+// free-space items with 128 threads (LDS of order p + 3 expansions)
 void launch_l2p_grad(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_pts,
-                     int n_rhs, const cd* LE, const cd* W, double* gX, int pmax, hipStream_t s) {
+                     int n_rhs, const cd* LE, const cd* W, double* gX, int pi, hipStream_t s) {
   if (n <= 0) return;
-  int pg = pmax + 3;
-  int Pg = (pg + 1) * (pg + 1), Pd = (pmax + 2) * (pmax + 2);
-  size_t shm = (size_t)(12 * Pg + Pd) * sizeof(cd);
-  hipFuncSetAttribute((const void*)k_l2p_grad, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL(k_l2p_grad, dim3(n), dim3(NT), shm, s, d, leaves, LM_L2P_CHUNK(kind), kind, xyz, n_pts, n_rhs,
-                     LE, W, gX);
+  if (kind == 1)
+    l2p_grad_go<64>(d, leaves, n, kind, xyz, n_pts, n_rhs, LE, W, gX, pi, s);
+  else
+    l2p_grad_go<128>(d, leaves, n, kind, xyz, n_pts, n_rhs, LE, W, gX, pi, s);
 }
 
 // Free-space near field: for the target point x_i (here a source point of
