@@ -73,10 +73,18 @@ typedef struct {
                       /* instance's worst admissible pair, lowered by m2l_margin   */
                       /* decades; 0: order p everywhere                            */
   double m2l_margin;  /* see m2l_adapt (default 3)                                  */
+  int react_s2t;      /* 0 (default): reaction trees are refined next to the gap    */
+                      /* between images and effective locations until no source   */
+                      /* and target leaves are adjacent (every reaction            */
+                      /* interaction is an M2L).  1: a tree may stop one level     */
+                      /* earlier where a cost model finds the direct near field    */
+                      /* cheaper; 2: always one level earlier.  Leaves that stay   */
+                      /* adjacent interact directly through the component's        */
+                      /* Sommerfeld integral (S2T, Sec. 3.3/3.4)                   */
 } lm_params;
 
 /* Fills *prm with the defaults (p = 12, p_free = p, automatic depths, m2l_adapt = 1,
- * m2l_margin = 3). */
+ * m2l_margin = 3, react_s2t = 0). */
 int lm_default_params(lm_params* prm);
 
 /* Creates a context bound to HIP device `hip_device`.  *out is owned by the
@@ -177,7 +185,7 @@ int lm_timings(lm_ctx* ctx, double* out_host, int n);
 #define LM_PHASE_M2L 3     /* M2L GEMM launches and the per-target reductions    */
 #define LM_PHASE_L2L 4
 #define LM_PHASE_L2P 5
-#define LM_PHASE_P2P 6
+#define LM_PHASE_P2P 6     /* near field: free-space P2P and reaction S2T         */
 #define LM_PHASES 7
 #define LM_TIMING_M2L_GEMM_MS (LM_PHASES + 1)
 #define LM_TIMING_M2L_GEMM_LAUNCHES (LM_PHASES + 2)
@@ -207,7 +215,8 @@ int lm_stats(const lm_ctx* ctx, double* out_host, int n);
 #define LM_STAT_M2L_CMAC_EXEC 18     /* same, including absent-source columns      */
 #define LM_STAT_N_LEAVES_P2M 19
 #define LM_STAT_FREE_DEPTH 20
-#define LM_STATS_COUNT 21
+#define LM_STAT_S2T_PAIRS 21         /* reaction near-field (S2T) point pairs        */
+#define LM_STATS_COUNT 22
 
 /* Self-test of the device arithmetic used by the near field (no context):
  * for each x_dev[i] writes out_dev[4i..4i+3] = sin x, cos x (the reduced-range

@@ -59,6 +59,15 @@ struct lm_ctx {
   std::vector<double> host_src, host_tgt;  // kept when they differ (for the swapped build)
   std::vector<int64_t> host_soff, host_toff;
   lm_ctx* adj = nullptr;                   // swapped-role context (built on first use)
+  lm_ctx* gctx = nullptr;                  // swapped-role context without S2T, for gradients
+  MediumDev md;                            // medium as seen by the kernels
+  int* d_s2t = nullptr;                    // S2T work items (target leaf, chunk)
+  struct S2TRange {
+    int inst, item0, n;
+    bool smallz;
+  };
+  std::vector<S2TRange> s2t_ranges;        // per reaction component with direct pairs
+  double contour_a = 0;
   cd* Jc = nullptr;                        // conjugated-input scratch
   long long jc_cap = 0;
 };
@@ -111,6 +120,10 @@ static void free_build(lm_ctx* ctx) {
   ctx->built = false;
   if (ctx->adj) lm_destroy(ctx->adj);
   ctx->adj = nullptr;
+  if (ctx->gctx) lm_destroy(ctx->gctx);
+  ctx->gctx = nullptr;
+  ctx->d_s2t = nullptr;
+  ctx->s2t_ranges.clear();
   if (ctx->Jc) hipFree(ctx->Jc);
   ctx->Jc = nullptr;
   ctx->jc_cap = 0;
@@ -159,6 +172,7 @@ int lm_default_params(lm_params* prm) {
   prm->components = 3;
   prm->m2l_adapt = 1;
   prm->m2l_margin = 3.0;
+  prm->react_s2t = 0;
   return LM_OK;
 }
 
@@ -223,6 +237,7 @@ int lm_set_params(lm_ctx* ctx, const lm_params* p) {
   if (p->m2l_adapt != 0 && p->m2l_adapt != 1) return fail(ctx, LM_EINVAL, "m2l_adapt must be 0 or 1");
   if (p->m2l_adapt && !(p->m2l_margin >= 0 && p->m2l_margin <= 30))
     return fail(ctx, LM_EINVAL, "m2l_margin out of range (0..30 decades)");
+  if (p->react_s2t < 0 || p->react_s2t > 2) return fail(ctx, LM_EINVAL, "react_s2t must be 0, 1 or 2");
   PlanParams q;
   q.p = p->p;
   q.p_free = p->p_free;
@@ -234,6 +249,7 @@ int lm_set_params(lm_ctx* ctx, const lm_params* p) {
   q.components = p->components;
   q.m2l_adapt = p->m2l_adapt;
   q.m2l_margin = p->m2l_margin;
+  q.react_s2t = p->react_s2t;
   ctx->prm = q;
   if (ctx->built) {
     hipSetDevice(ctx->device);
@@ -394,6 +410,24 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
         fi++;
       }
   }
+  {
+    // reaction near-field (S2T) work items, grouped by component
+    if ((rc = upload(ctx, &ctx->d_s2t, pl.s2t_items))) return rc;
+    const double a = ctx->prm.contour_a > 0 ? ctx->prm.contour_a : 1.5 * med.kmax;
+    int n_items = (int)pl.s2t_items.size() / 2;
+    for (int it = 0; it < n_items;) {
+      int inst = pl.tbox[pl.s2t_items[2 * it]].inst;
+      int j = it;
+      while (j < n_items && pl.tbox[pl.s2t_items[2 * j]].inst == inst) j++;
+      lm_ctx::S2TRange r;
+      r.inst = inst;
+      r.item0 = it;
+      r.n = j - it;
+      r.smallz = a * pl.inst[inst].s2t_rho <= 7.5;
+      ctx->s2t_ranges.push_back(r);
+      it = j;
+    }
+  }
   // matrices and table scratch
   void* vp = nullptr;
   if ((rc = dalloc(ctx, &vp, (size_t)pl.mat_size * sizeof(cd)))) return rc;
@@ -406,25 +440,37 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
   md.n = med.n;
   for (int l = 0; l < med.n; l++) md.k[l] = med.k[l];
   for (int l = 0; l < med.n - 1; l++) md.d[l] = med.d[l];
-  if (!pl.cases.empty()) {
-    std::vector<cd> dummy;
-    cd *kr = nullptr, *w = nullptr;
-    int* ni = nullptr;
-    void *pk = nullptr, *pw = nullptr, *pi = nullptr, *pn = nullptr, *pib = nullptr, *psc = nullptr;
+  ctx->md = md;
+  ctx->contour_a = ctx->prm.contour_a > 0 ? ctx->prm.contour_a : 1.5 * med.kmax;
+  d.nodes = nullptr;
+  if (!pl.node_kr.empty()) {
+    // quadrature nodes with their densities: read by the table kernels
+    // below and, for the direct reaction near field (S2T), by every
+    // evaluation, so they live as long as the build
+    void *pk = nullptr, *pw = nullptr, *pi = nullptr, *pn = nullptr;
     size_t nn = pl.node_kr.size();
     HIPC(hipMalloc(&pk, nn * sizeof(cd)));
     HIPC(hipMalloc(&pw, nn * sizeof(cd)));
     HIPC(hipMalloc(&pi, nn * sizeof(int)));
-    HIPC(hipMalloc(&pn, nn * sizeof(QNode)));
+    if ((rc = dalloc(ctx, &pn, nn * sizeof(QNode)))) {
+      hipFree(pk);
+      hipFree(pw);
+      hipFree(pi);
+      return rc;
+    }
     HIPC(hipMemcpy(pk, pl.node_kr.data(), nn * sizeof(cd), hipMemcpyHostToDevice));
     HIPC(hipMemcpy(pw, pl.node_w.data(), nn * sizeof(cd), hipMemcpyHostToDevice));
     HIPC(hipMemcpy(pi, pl.node_inst.data(), nn * sizeof(int), hipMemcpyHostToDevice));
-    kr = (cd*)pk;
-    w = (cd*)pw;
-    ni = (int*)pi;
     d.nodes = (QNode*)pn;
-    launch_nodes(d, md, (int)nn, ni, kr, w, s);
+    launch_nodes(d, md, (int)nn, (int*)pi, (cd*)pk, (cd*)pw, s);
     HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(s));
+    hipFree(pk);
+    hipFree(pw);
+    hipFree(pi);
+  }
+  if (!pl.cases.empty()) {
+    void *pib = nullptr, *psc = nullptr;
     // integrals and assembly in batches of cases (bounded scratch)
     int maxnode = 0;
     for (auto& tc : pl.cases) maxnode = std::max(maxnode, tc.nnode);
@@ -443,15 +489,12 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
     launch_tab_assemble(d, 0, (int)pl.cases.size(), pl.p, pl.kmaxcheb, (ctx->pmax + 1) / 2 + 2, s);
     HIPC(hipGetLastError());
     HIPC(hipStreamSynchronize(s));
-    hipFree(pk);
-    hipFree(pw);
-    hipFree(pi);
-    hipFree(pn);
     hipFree(psc);
     hipFree(pib);
-    d.nodes = nullptr;
     d.ibuf = nullptr;
   }
+  if (!ctx->s2t_ranges.empty() && !d.nodes)
+    return fail(ctx, LM_EHIP, "internal: direct near field without quadrature nodes");
   HIPC(hipStreamSynchronize(s));
   auto t3 = std::chrono::steady_clock::now();
   ctx->t_plan_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -477,7 +520,8 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
   ctx->same_sets = n_src == n_tgt && memcmp(soff, toff, (size_t)(n_geom + 1) * sizeof(int64_t)) == 0 &&
                    (src_xyz == tgt_xyz || n_src == 0 ||
                     memcmp(src_xyz, tgt_xyz, (size_t)n_src * 3 * sizeof(double)) == 0);
-  if (!ctx->same_sets) {
+  if (!ctx->same_sets || ctx->prm.react_s2t) {
+    // kept for the swapped-role builds (adjoint of distinct sets, gradients)
     ctx->host_src.assign(src_xyz, src_xyz + 3 * n_src);
     ctx->host_tgt.assign(tgt_xyz, tgt_xyz + 3 * n_tgt);
     ctx->host_soff.assign(soff, soff + n_geom + 1);
@@ -639,6 +683,36 @@ static int swapped_ctx(lm_ctx* ctx, hipStream_t s, lm_ctx** out) {
   return LM_OK;
 }
 
+// The context that evaluates source-position gradients: the swapped-role
+// FMM, but with reaction trees refined until no direct (S2T) pairs remain
+// (the gradient passes differentiate local expansions and the free-space
+// near field only).  Built once, on the first call, when the forward plan
+// uses S2T.
+static int grad_ctx(lm_ctx* ctx, hipStream_t s, lm_ctx** out) {
+  *out = nullptr;
+  if (!ctx->prm.react_s2t) return swapped_ctx(ctx, s, out);
+  if (!ctx->gctx) {
+    lm_ctx* a = nullptr;
+    int rc = lm_create(&a, ctx->device);
+    if (rc) return fail(ctx, rc, "cannot create the gradient context");
+    a->med = ctx->med;
+    a->layers_set = true;
+    a->prm = ctx->prm;
+    a->prm.react_s2t = 0;
+    int ng = (int)ctx->host_soff.size() - 1;
+    rc = build_common(a, ng, ctx->host_toff.data(), ctx->host_tgt.data(), ctx->host_soff.data(),
+                      ctx->host_src.data(), s);
+    if (rc) {
+      std::string m = a->err;
+      lm_destroy(a);
+      return fail(ctx, rc, "gradient-context build: " + m);
+    }
+    ctx->gctx = a;
+  }
+  *out = ctx->gctx;
+  return LM_OK;
+}
+
 static int ensure_jc(lm_ctx* ctx, long long n, hipStream_t s) {
   if (n <= ctx->jc_cap) return LM_OK;
   HIPC(hipStreamSynchronize(s));
@@ -688,7 +762,7 @@ int lm_grad_src_xyz(lm_ctx* ctx, int n_rhs, const void* J, const void* gA, doubl
   HIPC(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   lm_ctx* T = nullptr;
-  int rc = swapped_ctx(ctx, s, &T);
+  int rc = grad_ctx(ctx, s, &T);
   if (rc) return rc;
   launch_fill_d(gX, 3 * pl.n_src, s);
   if (pl.n_src == 0 || pl.n_tgt == 0) {
@@ -774,6 +848,10 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
         launch_p2p(d, ctx->d_p2p[f], ctx->n_p2p[f], ctx->d_src, Jc, pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs,
                    pl.inst[i].kt, Ac, ctx->p2p_red, s);
     }
+    if (!grad)
+      for (auto& r : ctx->s2t_ranges)
+        launch_s2t(d, ctx->md, ctx->d_s2t + 2 * r.item0, r.n, ctx->d_src, Jc, pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs,
+                   ctx->contour_a, r.smallz, Ac, s);
     mark(7);
   } else {
     for (int i = 2; i <= 7; i++) mark(i);
@@ -865,6 +943,7 @@ int lm_stats(const lm_ctx* ctx, double* out, int n) {
   double fd = 0;
   for (int x : pl.free_depth_used) fd = std::max(fd, (double)x);
   v[LM_STAT_FREE_DEPTH] = fd;
+  v[LM_STAT_S2T_PAIRS] = (double)pl.n_s2t_pairs;
   int m = n < LM_STATS_COUNT ? n : LM_STATS_COUNT;
   memcpy(out, v, m * sizeof(double));
   return LM_OK;

@@ -25,6 +25,9 @@ static_assert(NT == LM_P2P_CHUNK, "near-field work items hold one block's worth 
 // LEG_M1[m] cos P^m_m, P^m_n = LEG_A[n][m] (cos P^m_{n-1} - LEG_B[n][m] P^m_{n-2}).
 #define LEGN (LM_PMAX + 5)
 __constant__ double c_leg_a[LEGN * LEGN], c_leg_b[LEGN * LEGN], c_leg_mm[LEGN], c_leg_m1[LEGN];
+// 1/k, 1/k^2, 1/(k(k+1)), 1/(k(k+2)) for the Bessel series (index k, 1..64)
+#define RCPN 65
+__constant__ double c_rk[RCPN], c_rk2[RCPN], c_rkk1[RCPN], c_rkk2[RCPN];
 
 int lm_upload_leg_tables() {
   static bool done[64] = {false};
@@ -44,6 +47,18 @@ int lm_upload_leg_tables() {
       hipMemcpyToSymbol(HIP_SYMBOL(c_leg_b), b.data(), b.size() * sizeof(double)) != hipSuccess ||
       hipMemcpyToSymbol(HIP_SYMBOL(c_leg_mm), mm.data(), mm.size() * sizeof(double)) != hipSuccess ||
       hipMemcpyToSymbol(HIP_SYMBOL(c_leg_m1), m1.data(), m1.size() * sizeof(double)) != hipSuccess)
+    return -1;
+  std::vector<double> rk(RCPN, 0.0), rk2(RCPN, 0.0), rkk1(RCPN, 0.0), rkk2(RCPN, 0.0);
+  for (int k = 1; k < RCPN; k++) {
+    rk[k] = 1.0 / k;
+    rk2[k] = 1.0 / ((double)k * k);
+    rkk1[k] = 1.0 / ((double)k * (k + 1));
+    rkk2[k] = 1.0 / ((double)k * (k + 2));
+  }
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_rk), rk.data(), rk.size() * sizeof(double)) != hipSuccess ||
+      hipMemcpyToSymbol(HIP_SYMBOL(c_rk2), rk2.data(), rk2.size() * sizeof(double)) != hipSuccess ||
+      hipMemcpyToSymbol(HIP_SYMBOL(c_rkk1), rkk1.data(), rkk1.size() * sizeof(double)) != hipSuccess ||
+      hipMemcpyToSymbol(HIP_SYMBOL(c_rkk2), rkk2.data(), rkk2.size() * sizeof(double)) != hipSuccess)
     return -1;
   done[dev] = true;
   return 0;
@@ -1179,6 +1194,238 @@ void launch_p2p_grad(const DevPlan& d, const int* tboxes, int n, const double* s
   else
     hipLaunchKernelGGL(k_p2p_grad<false>, dim3(n), dim3(NT), 0, s, d, tboxes, sxyz, Jsrc, n_src, txyz, W, n_tgt,
                        n_rhs, k, gX);
+}
+
+// ------------------------------------------------------------------ S2T
+// Reaction near field of one component between adjacent leaves next to the
+// gap (Sec. 3.3: the component's Sommerfeld integral evaluated directly).
+// For a target x and a source x' (horizontal offset rho at angle phi):
+//   I_sigma,|kappa| = sum_nodes w kr Z F_sigma J_|kappa|(kr rho),
+//   Z = exp(i (k_z t(z) + k'_z u(z'))),
+//   W(kappa, sigma) = e^{i kappa phi} i^{1+|kappa|} I_sigma,|kappa|,
+// combined in the spin basis exactly as the M2L tensor (the order-0 case of
+// P2M -> M2L -> L2P at the pair itself, hence the factor 1/(4 pi)):
+//   out+ = W(0,s1) u+/2 - W(2,s3) u-/2 + W(1,s2) m_z
+//   out- = W(0,s1) u-/2 - W(-2,s3) u+/2 + W(-1,s2) m_z
+//   out_z = W(1,s4) u-/2 + W(-1,s4) u+/2 + W(0,s5) m_z.
+// The nodes are Gamma_1 (complex k_rho) then the real tail in increasing
+// order; each pair stops at its own cut a + 45 / (t + u).  One block of
+// LM_S2T_CHUNK threads per work item (target leaf, chunk); each target is
+// owned by one thread and the launches go component by component, so the
+// accumulation into A is deterministic.
+// J_0, J_1, J_2 of complex z by their power series (|z| <= 8: terms stay
+// below 2e2, so about 14 digits survive the cancellation)
+__device__ inline void bessel012_series(cd z, cd* j0, cd* j1, cd* j2) {
+  cd h = 0.5 * z, w = -1.0 * (h * h);
+  cd t0 = cd{1, 0}, t1 = h, t2 = 0.5 * (h * h);
+  cd s0 = t0, s1 = t1, s2 = t2;
+  for (int k = 1; k <= 40; k++) {
+    t0 = c_rk2[k] * (t0 * w);
+    t1 = c_rkk1[k] * (t1 * w);
+    t2 = c_rkk2[k] * (t2 * w);
+    s0 = s0 + t0;
+    s1 = s1 + t1;
+    s2 = s2 + t2;
+    if (fabs(t0.x) + fabs(t0.y) + fabs(t1.x) + fabs(t1.y) < 1e-17 * (fabs(s0.x) + fabs(s0.y) + 1e-300)) break;
+  }
+  *j0 = s0;
+  *j1 = s1;
+  *j2 = s2;
+}
+
+// J_0(x), J_1(x) for real x >= 0 to about 1e-11: the power series below 12
+// (terms stay below 5e3), the Hankel asymptotic expansion above
+// (J_n = sqrt(2 / (pi x)) (P_n cos chi_n - Q_n sin chi_n), chi_n = x - (2n+1) pi/4,
+// summed until the terms stop decreasing; the first omitted term is below
+// e^{-2x} < 4e-11).
+__device__ inline void bessel01_real(double x, double* j0v, double* j1v) {
+  if (x < 12.0) {
+    double w = -0.25 * x * x, t0 = 1.0, t1 = 1.0, s0 = 1.0, s1 = 1.0;
+    for (int k = 1; k <= 60; k++) {
+      t0 *= w * c_rk2[k];
+      t1 *= w * c_rkk1[k];
+      s0 += t0;
+      s1 += t1;
+      if (fabs(t0) + fabs(t1) < 1e-17) break;
+    }
+    *j0v = s0;
+    *j1v = 0.5 * x * s1;
+    return;
+  }
+  double ix8 = 0.125 / x;
+  // a_k(n) = prod_{i=1..k} (4 n^2 - (2i-1)^2) / (k! (8x)^k)
+  double a0 = 1.0, a1 = 1.0, p0 = 1.0, q0 = 0.0, p1 = 1.0, q1 = 0.0, last = 1.0;
+  for (int k = 1; k <= 40; k++) {
+    double o = (2.0 * k - 1.0) * (2.0 * k - 1.0);
+    a0 *= (0.0 - o) * ix8 * c_rk[k];
+    a1 *= (4.0 - o) * ix8 * c_rk[k];
+    double m = fabs(a0) + fabs(a1);
+    if (m > last) break;
+    last = m;
+    double sg = ((k >> 1) & 1) ? -1.0 : 1.0;  // (-1)^{k/2} (even k), (-1)^{(k-1)/2} (odd k)
+    if (k & 1) {
+      q0 += sg * a0;
+      q1 += sg * a1;
+    } else {
+      p0 += sg * a0;
+      p1 += sg * a1;
+    }
+    if (m < 1e-17) break;
+  }
+  double sn, cs;
+  lm_sincos_red(x - 0.78539816339744830962, &sn, &cs);  // chi_0 = x - pi/4
+  double amp = sqrt(0.63661977236758134308 / x);       // sqrt(2 / (pi x))
+  *j0v = amp * (p0 * cs - q0 * sn);
+  // chi_1 = chi_0 - pi/2: cos chi_1 = sin chi_0, sin chi_1 = -cos chi_0
+  *j1v = amp * (p1 * sn + q1 * cs);
+}
+
+template <bool SMALLZ>
+__global__ __launch_bounds__(LM_S2T_CHUNK, 3) void k_s2t(DevPlan d, MediumDev md, const int* items,
+                                                        const double* sxyz, const cd* J, long long n_src,
+                                                        const double* txyz, long long n_tgt, int n_rhs, double a,
+                                                        cd* A) {
+  __shared__ double tp[LM_S2T_CHUNK][3];  // targets: x, y, t
+  __shared__ double sp[LM_S2T_CHUNK][3];  // sources: x, y, u
+  __shared__ cd sq[LM_S2T_CHUNK][3];      // sources: u+, u-, m_z
+  __shared__ cd res[LM_S2T_CHUNK][3];     // per pair of the round: out+, out-, out_z
+  const int tid = threadIdx.x;
+  // work item, component and node range are uniform over the block
+  const int b = __builtin_amdgcn_readfirstlane(items[2 * blockIdx.x]);
+  const int chunk = __builtin_amdgcn_readfirstlane(items[2 * blockIdx.x + 1]);
+  const TgtBox tb = d.tbox[b];
+  const InstParams ip = d.inst[__builtin_amdgcn_readfirstlane(tb.inst)];
+  const int r = blockIdx.y;
+  const int t0 = tb.pt0 + chunk * LM_S2T_CHUNK;
+  const int nt = min(LM_S2T_CHUNK, tb.pt1 - t0);
+  const int n0 = __builtin_amdgcn_readfirstlane(ip.s2t0), nn = __builtin_amdgcn_readfirstlane(ip.s2tn);
+  const QNode* nodes = d.nodes + n0;
+  int id = 0;
+  if (tid < nt) {
+    id = d.tgt_perm[t0 + tid];
+    double zt = txyz[3 * id + 2];
+    tp[tid][0] = txyz[3 * id];
+    tp[tid][1] = txyz[3 * id + 1];
+    tp[tid][2] = ip.up_t ? zt - md.d[ip.lt] : md.d[ip.lt - 1] - zt;
+  }
+  cd op = cd{0, 0}, om = cd{0, 0}, oz = cd{0, 0};  // thread tid < nt: totals of target tid
+  for (int li = tb.p2p0; li < tb.p2p1; li++) {
+    const SrcBox sb = d.sbox[d.p2p_list[li]];
+    for (int s0 = sb.pt0; s0 < sb.pt1; s0 += LM_S2T_CHUNK) {
+      const int ns = min(LM_S2T_CHUNK, sb.pt1 - s0);
+      __syncthreads();
+      if (tid < ns) {
+        int sid = d.src_perm[s0 + tid];
+        double zs = sxyz[3 * sid + 2];
+        sp[tid][0] = sxyz[3 * sid];
+        sp[tid][1] = sxyz[3 * sid + 1];
+        sp[tid][2] = ip.up_s ? md.d[ip.ls - 1] - zs : zs - md.d[ip.ls];
+        const cd* Jp = J + ((long long)r * n_src + sid) * 3;
+        cd jx = Jp[0], jy = Jp[1], jz = Jp[2];
+        sq[tid][0] = jx + cd{-jy.y, jy.x};
+        sq[tid][1] = jx - cd{-jy.y, jy.x};
+        sq[tid][2] = jz;
+      }
+      __syncthreads();
+      // pairs (target i, source j) of this tile, pair q = i ns + j, one per lane
+      const int npair = nt * ns;
+      for (int q0 = 0; q0 < npair; q0 += LM_S2T_CHUNK) {
+        const int q = q0 + tid;
+        cd rp = cd{0, 0}, rm = cd{0, 0}, rz = cd{0, 0};
+        if (q < npair) {
+          const int i = q / ns, j = q - i * ns;
+          double dx = tp[i][0] - sp[j][0], dy = tp[i][1] - sp[j][1];
+          double tz = tp[i][2], uz = sp[j][2];
+          double rho = sqrt(dx * dx + dy * dy);
+          double cph = rho > 0 ? dx / rho : 1.0, sph = rho > 0 ? dy / rho : 0.0;
+          double kcut = a + LM_S2T_DIGITS / (tz + uz);
+          cd I1 = cd{0, 0}, I2 = cd{0, 0}, I3 = cd{0, 0}, I4 = cd{0, 0}, I5 = cd{0, 0};
+          int n = 0;
+          for (; n < nn; n++) {
+            const QNode& nd = nodes[n];
+            if (nd.kr.y == 0.0) break;  // end of Gamma_1
+            cd e = cd{0, 1} * (tz * nd.kzt + uz * nd.kzs);
+            cd base = nd.w * nd.kr * cexpd(e);
+            cd jb[3];
+            if (SMALLZ)
+              bessel012_series(rho * nd.kr, jb, jb + 1, jb + 2);
+            else
+              bessel_jq(2, rho * nd.kr, jb);
+            cd b0 = base * jb[0], b1 = base * jb[1], b2 = base * jb[2];
+            I1 = I1 + b0 * nd.F[0];
+            I2 = I2 + b1 * nd.F[1];
+            I3 = I3 + b2 * nd.F[2];
+            I4 = I4 + b1 * nd.F[3];
+            I5 = I5 + b0 * nd.F[4];
+          }
+          for (; n < nn; n++) {
+            const QNode& nd = nodes[n];
+            double kr = nd.kr.x;
+            if (kr > kcut) break;
+            // real tail: k_z = i |k_z|, Z = exp(-t |k_z| - u |k_z'|)
+            double z = exp(-(tz * nd.kzt.y + uz * nd.kzs.y));
+            double base = nd.w.x * kr * z;
+            double x = kr * rho;
+            double J0, J1;
+            bessel01_real(x, &J0, &J1);
+            double J2 = x > 1e-3 ? 2.0 * J1 / x - J0 : x * x * (0.125 - x * x / 192.0);
+            double b0 = base * J0, b1 = base * J1, b2 = base * J2;
+            I1 = I1 + b0 * nd.F[0];
+            I2 = I2 + b1 * nd.F[1];
+            I3 = I3 + b2 * nd.F[2];
+            I4 = I4 + b1 * nd.F[3];
+            I5 = I5 + b0 * nd.F[4];
+          }
+          cd e1 = cd{cph, sph}, e2 = e1 * e1;
+          cd W01 = cd{-I1.y, I1.x};  // i I1
+          cd W05 = cd{-I5.y, I5.x};  // i I5
+          cd t3 = cd{I3.y, -I3.x};   // -i I3
+          cd W2p = e2 * t3, W2m = cconj(e2) * t3;
+          cd W1p2 = -1.0 * (e1 * I2), W1m2 = -1.0 * (cconj(e1) * I2);
+          cd W1p4 = -1.0 * (e1 * I4), W1m4 = -1.0 * (cconj(e1) * I4);
+          cd up = sq[j][0], um = sq[j][1], mz = sq[j][2];
+          rp = 0.5 * (W01 * up) - 0.5 * (W2p * um) + W1p2 * mz;
+          rm = 0.5 * (W01 * um) - 0.5 * (W2m * up) + W1m2 * mz;
+          rz = 0.5 * (W1p4 * um) + 0.5 * (W1m4 * up) + W05 * mz;
+        }
+        res[tid][0] = rp;
+        res[tid][1] = rm;
+        res[tid][2] = rz;
+        __syncthreads();
+        // target tid adds its pairs of this round in source order
+        if (tid < nt) {
+          int qa = max(q0, tid * ns), qb = min(q0 + LM_S2T_CHUNK, (tid + 1) * ns);
+          for (int qq = qa; qq < qb; qq++) {
+            op = op + res[qq - q0][0];
+            om = om + res[qq - q0][1];
+            oz = oz + res[qq - q0][2];
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+  if (tid < nt) {
+    const double f = 0.079577471545947667884;  // 1 / (4 pi)
+    cd ax = (0.5 * f) * (op + om);
+    cd dd = (0.5 * f) * (op - om);
+    cd* Ap = A + ((long long)r * n_tgt + id) * 3;
+    Ap[0] = Ap[0] + ax;
+    Ap[1] = Ap[1] + cd{dd.y, -dd.x};
+    Ap[2] = Ap[2] + f * oz;
+  }
+}
+// smallz: |k_rho| rho <= 8 on Gamma_1 for every pair of the component
+void launch_s2t(const DevPlan& d, MediumDev md, const int* items, int n, const double* sxyz, const cd* J,
+                long long n_src, const double* txyz, long long n_tgt, int n_rhs, double a, bool smallz, cd* A,
+                hipStream_t s) {
+  if (n <= 0) return;
+  if (smallz)
+    hipLaunchKernelGGL(k_s2t<true>, dim3(n, n_rhs), dim3(LM_S2T_CHUNK), 0, s, d, md, items, sxyz, J, n_src, txyz,
+                       n_tgt, n_rhs, a, A);
+  else
+    hipLaunchKernelGGL(k_s2t<false>, dim3(n, n_rhs), dim3(LM_S2T_CHUNK), 0, s, d, md, items, sxyz, J, n_src, txyz,
+                       n_tgt, n_rhs, a, A);
 }
 
 // ------------------------------------------------------------------ translation tables

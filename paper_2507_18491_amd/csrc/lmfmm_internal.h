@@ -13,6 +13,8 @@
 #define LM_PMAX 24
 #define LM_P2P_CHUNK 256   // targets per near-field work item (= threads per block)
 #define LM_L2P_CHUNK(kind) ((kind) == 0 ? 256 : 64)   // points per L2P work item (free / reaction)
+#define LM_S2T_CHUNK 64    // targets per reaction near-field work item (= threads per block)
+#define LM_S2T_DIGITS 45.0 // the S2T tail stops where e^{-k (t + u)} < e^{-45}
 
 // One FMM instance: the free-space part of one layer, or one reaction
 // component (target layer lt, source layer ls, arrival direction at the
@@ -27,6 +29,8 @@ struct InstParams {
   double at, bt;     // target effective location  zhat = at*z + bt
   double as, bs;     // source polarization image  zbrv = as*z + bs
   double Dgap;       // distance between the two anchor planes (reaction)
+  int s2t0, s2tn;    // reaction: quadrature nodes of the direct (S2T) near field
+  double s2t_rho;    // reaction: largest horizontal distance of an S2T pair (-1: none)
 };
 
 // source-side box record (device)

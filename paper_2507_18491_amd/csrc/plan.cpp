@@ -543,6 +543,7 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
   std::vector<double> case_dz;  // vertical centre separation of each case
   std::vector<double> off_ratio;  // per M2L offset: (r_s + r_t) / |c_t - c_s|
 
+  std::vector<double> s2t_rho_of;  // per instance: largest horizontal S2T pair distance, -1 if none
   for (auto& g : geo) {
     const double S0 = g.S0, eps = g.eps, X0 = g.X0, Y0 = g.Y0;
     InstParams ip = g.ip;
@@ -639,14 +640,59 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
         T.zflip = 1;
         Dgap = (g.zs0 - eps) - (g.zt1 + eps);
       }
-      int Dmax = 0;
-      while (S0 / (double)(1 << Dmax) > Dgap) Dmax++;
-      if (Dmax > prm.max_depth)
+      // D1: the first level whose boxes are no larger than the gap (no
+      // adjacent source/target leaves remain).  With the direct near field
+      // enabled, the boxes next to the gap may stop one level earlier when
+      // the direct (S2T) pairs of that level cost less than the M2L work of
+      // the last level (measured rates: about 3e-8 s per S2T pair, 2.9e-8 s
+      // per reaction M2L pair at p = 12 with adaptive orders; about 50 M2L
+      // pairs per box at the finest level).
+      int D1 = 0;
+      while (S0 / (double)(1 << D1) > Dgap) D1++;
+      if (D1 > prm.max_depth)
         return lm_fmt("reaction component (%d,%d): points are too close to an interface "
                       "(gap %.3e needs %d tree levels, limit %d)",
-                      ip.lt, ip.ls, Dgap, Dmax, prm.max_depth);
+                      ip.lt, ip.ls, Dgap, D1, prm.max_depth);
+      int Dmax = D1;
+      if (prm.react_s2t && D1 >= 2) {
+        // distance of each point from the gap plane of its tree
+        auto hz_t = [&](double z) { return T.zflip ? (T.z0 + S0 - z) : (z - T.z0); };
+        auto hz_s = [&](double z) { return S.zflip ? (S.z0 + S0 - z) : (z - S.z0); };
+        auto cell = [&](double x, double y, double sl) {
+          long long cx = (long long)floor((x - X0) / sl), cy = (long long)floor((y - Y0) / sl);
+          return (cx << 32) ^ (cy & 0xffffffffLL);
+        };
+        double s1 = S0 / (double)(1 << D1), sb = 2.0 * s1;
+        std::unordered_map<long long, int> tb1;  // occupied level-D1 target boxes next to the gap
+        std::unordered_map<long long, long long> ct, cs;  // level D1-1, first layer: counts per x-y cell
+        for (size_t i = 0; i < g.tid.size(); i++) {
+          double x = g.tpos[3 * i], y = g.tpos[3 * i + 1], h = hz_t(g.tpos[3 * i + 2]);
+          if (h < sb) {
+            tb1[cell(x, y, s1) * 2 + (h >= s1 ? 1 : 0)] = 1;
+            ct[cell(x, y, sb)]++;
+          }
+        }
+        for (size_t i = 0; i < g.sid.size(); i++) {
+          double h = hz_s(g.spos[3 * i + 2]);
+          if (h < sb) cs[cell(g.spos[3 * i], g.spos[3 * i + 1], sb)]++;
+        }
+        double pairs = 0;
+        for (auto& kv : ct) {
+          long long cx = kv.first >> 32, cy = (long long)(int)(kv.first & 0xffffffffLL);
+          long long ns = 0;
+          for (int dx = -1; dx <= 1; dx++)
+            for (int dy = -1; dy <= 1; dy++) {
+              auto it = cs.find(((cx + dx) << 32) ^ ((cy + dy) & 0xffffffffLL));
+              if (it != cs.end()) ns += it->second;
+            }
+          pairs += (double)kv.second * (double)ns;
+        }
+        double c_s2t = pairs * 3.0e-8;
+        double c_m2l = (double)tb1.size() * 50.0 * 9.0 * (double)P * P * 8.0 * 0.6 / 43e12;
+        if (prm.react_s2t == 2 || c_s2t < c_m2l) Dmax = D1 - 1;
+      }
       depth_used = Dmax;
-      auto rule = [&](int l, int n, int j, double Sl) { return n > 0 && l < Dmax && j == 0 && Sl > Dgap; };
+      auto rule = [&](int l, int n, int j, double) { return n > 0 && l < Dmax && j == 0; };
       build_tree(S, g.spos, g.sid, std::vector<int>(g.sid.size(), 0), rule);
       build_tree(T, g.tpos, g.tid, std::vector<int>(g.tid.size(), 1), rule);
     }
@@ -743,6 +789,7 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       int s, t;  // local box ids
     };
     std::vector<Pair> m2l;
+    std::vector<std::pair<int, std::vector<int>>> s2t_near;  // reaction: target leaf, near source boxes
     std::vector<std::unordered_map<uint64_t, int>> smap(DK + 2);
     for (int b = 0; b < S.nbox(); b++) smap[S.lvl[b]][ckey(S.ix[b], S.iy[b], S.iz[b])] = b;
     if (free) {
@@ -792,6 +839,7 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
           }
     } else {
       std::vector<std::vector<int>> nearT(T.nbox());
+      s2t_near.clear();
       auto ws = [&](int s, int t) {
         double cs[3], ct[3];
         S.centre(s, cs);
@@ -821,12 +869,41 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
             }
           }
         }
-        if (T.nchild[t] == 0 && !nearT[t].empty())
-          return lm_fmt("reaction component (%d,%d): adjacent target leaf at level %d "
-                        "(points too close to an interface)",
-                        ip.lt, ip.ls, T.lvl[t]);
+        if (T.nchild[t] == 0 && !nearT[t].empty()) {
+          if (!prm.react_s2t)
+            return lm_fmt("reaction component (%d,%d): adjacent target leaf at level %d "
+                          "(points too close to an interface)",
+                          ip.lt, ip.ls, T.lvl[t]);
+          s2t_near.push_back({t, nearT[t]});
+        }
       }
     }
+    // ---- reaction near field (S2T): target leaves next to the gap and their
+    // adjacent source boxes, evaluated by direct Sommerfeld integrals
+    double s2t_rho = 0;
+    if (!free) {
+      for (auto& tn : s2t_near) {
+        int t = tn.first;
+        TgtBox& tb = pl.tbox[tbase + t];
+        tb.p2p0 = (int)pl.p2p_list.size();
+        double ct[3];
+        T.centre(t, ct);
+        for (int q : tn.second) {
+          pl.p2p_list.push_back(sbase + q);
+          pl.n_s2t_pairs += (long long)(S.a1[q] - S.a0[q]) * (T.b1[t] - T.b0[t]);
+          double cs[3];
+          S.centre(q, cs);
+          double rh = hypot(ct[0] - cs[0], ct[1] - cs[1]) + 0.5 * sqrt(2.0) * (T.S(T.lvl[t]) + S.S(S.lvl[q]));
+          s2t_rho = std::max(s2t_rho, rh);
+        }
+        tb.p2p1 = (int)pl.p2p_list.size();
+        for (int c = 0; c * LM_S2T_CHUNK < T.b1[t] - T.b0[t]; c++) {
+          pl.s2t_items.push_back(tbase + t);
+          pl.s2t_items.push_back(c);
+        }
+      }
+    }
+    s2t_rho_of.push_back(s2t_near.empty() ? -1.0 : s2t_rho);
     pl.n_m2l_pairs += (long long)m2l.size();
     (free ? pl.n_m2l_pairs_free : pl.n_m2l_pairs_react) += (long long)m2l.size();
     (free ? pl.n_free_inst : pl.n_react_inst)++;
@@ -1064,6 +1141,46 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
         }
       }
       nodemap[kv.first] = std::make_pair(n0, (int)pl.node_kr.size() - n0);
+    }
+    // direct near field (S2T) of a reaction component: Gamma_1 and the real
+    // tail up to a + s2t_digits / gap (every pair's vertical transmission
+    // distance is at least the gap; each pair stops at its own cut)
+    if (s2t_rho_of.size() != pl.inst.size()) return "internal: near-field bookkeeping out of step";
+    for (size_t inst = 0; inst < pl.inst.size(); inst++) {
+      InstParams& ipr = pl.inst[inst];
+      ipr.s2t0 = ipr.s2tn = 0;
+      ipr.s2t_rho = s2t_rho_of[inst];
+      if (ipr.kind != 1 || s2t_rho_of[inst] < 0) continue;
+      double dzmin = ipr.Dgap, rho_max = s2t_rho_of[inst];
+      int n0 = (int)pl.node_kr.size();
+      int np1 = std::max(1, prm.gamma1_panels);
+      for (int pnl = 0; pnl < np1; pnl++) {
+        double t0 = (double)pnl / np1, t1 = (double)(pnl + 1) / np1;
+        for (int gi = 0; gi < 16; gi++) {
+          double t = 0.5 * (t0 + t1) + 0.5 * (t1 - t0) * gx[gi];
+          cd kzg = cd{kg * (1 - t), w_im * t};
+          cd kr = csqrtd(cd{kg * kg, 0} - kzg * kzg);
+          cd dkzg = cd{-kg, w_im};
+          cd dkr = (-1.0) * (kzg * dkzg) / kr;
+          pl.node_kr.push_back(kr);
+          pl.node_w.push_back(0.5 * (t1 - t0) * gw[gi] * dkr);
+          pl.node_inst.push_back((int)inst);
+        }
+      }
+      double kcut = a + LM_S2T_DIGITS / dzmin;
+      double len = std::min(4.0 / dzmin, rho_max > 0 ? 2.0 * M_PI / rho_max : 1e300);
+      int npan = (int)ceil((kcut - a) / len);
+      len = (kcut - a) / npan;
+      for (int pnl = 0; pnl < npan; pnl++) {
+        double k0 = a + pnl * len;
+        for (int gi = 0; gi < 16; gi++) {
+          pl.node_kr.push_back(cd{k0 + 0.5 * len * (gx[gi] + 1.0), 0.0});
+          pl.node_w.push_back(cd{0.5 * len * gw[gi], 0.0});
+          pl.node_inst.push_back((int)inst);
+        }
+      }
+      ipr.s2t0 = n0;
+      ipr.s2tn = (int)pl.node_kr.size() - n0;
     }
     int NQ = 2 * pl.p + 3, NL = pl.p + 2;
     for (auto& tc : pl.cases) {

@@ -31,6 +31,9 @@ struct PlanParams {
   int components = 3;    // bit 0: free space, bit 1: reaction
   int m2l_adapt = 1;     // per-offset M2L order from the separation ratio
   double m2l_margin = 3.0;  // decades below the worst pair's truncation bound
+  int react_s2t = 0;         // 0: refine reaction trees until no adjacent leaves remain;
+                             // 1: stop one level early next to the gap where direct (S2T)
+                             // pairs are estimated cheaper; 2: always stop one level early
 };
 
 struct Plan {
@@ -64,6 +67,7 @@ struct Plan {
   std::vector<int> offr;                      // per block: n_off+1 pair-range starts
   std::vector<int> bt_blk;                    // per block-target: its block
   std::vector<int> pair_P;                    // per pair: (pord+1)^2 of its offset
+  std::vector<int> s2t_items;                 // reaction near field: (target leaf, chunk) pairs
   // tables
   std::vector<TransJob> trans;
   std::vector<TabCase> cases;
@@ -77,7 +81,7 @@ struct Plan {
   long long me_size = 0, le_size = 0, mat_size = 0, ibuf_size = 0;
   int kmaxcheb = 0;                           // max Chebyshev index K
   // statistics
-  long long n_m2l_pairs = 0, n_p2p_pairs = 0, n_m2l_pairs_free = 0, n_m2l_pairs_react = 0;
+  long long n_m2l_pairs = 0, n_p2p_pairs = 0, n_m2l_pairs_free = 0, n_m2l_pairs_react = 0, n_s2t_pairs = 0;
   int n_free_inst = 0, n_react_inst = 0;
   std::vector<int> free_depth_used;
 };

@@ -17,7 +17,7 @@ STAT_NAMES = ["n_free_inst", "n_react_inst", "m2l_pairs_free", "m2l_pairs_react"
               "n_cases", "n_nodes", "mat_bytes", "me_bytes_per_rhs", "le_bytes_per_rhs",
               "t_plan_ms", "t_upload_ms", "t_tables_ms", "n_src_boxes", "n_tgt_boxes",
               "n_m2l_classes", "n_m2l_tiles_1rhs", "m2l_cmac_useful", "m2l_cmac_exec",
-              "n_leaves_p2m", "free_depth"]
+              "n_leaves_p2m", "free_depth", "s2t_pairs"]
 
 
 PHASE_NAMES = ["clear", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p"]
@@ -28,7 +28,7 @@ class lm_params(ctypes.Structure):
                 ("max_depth", ctypes.c_int), ("gamma1_panels", ctypes.c_int),
                 ("contour_a", ctypes.c_double), ("tail_digits", ctypes.c_double),
                 ("components", ctypes.c_int), ("m2l_adapt", ctypes.c_int),
-                ("m2l_margin", ctypes.c_double)]
+                ("m2l_margin", ctypes.c_double), ("react_s2t", ctypes.c_int)]
 
 
 _lib = None

@@ -174,3 +174,19 @@ def test_adjoint_and_grad_full_size_sampled():
     e2 = rel(gX[g["js"]], g["gX"])
     print("  adjoint rel L2 = %.3e, gradient rel L2 = %.3e" % (e1, e2), flush=True)
     assert e1 < 1.5e-6 and e2 < 1.2e-5
+
+
+def test_adjoint_and_grad_with_direct_near_field(tiny):
+    """With the direct reaction near field on, the adjoint uses it (through
+    the same evaluation); the gradient runs on a fully refined swapped-role
+    plan."""
+    d, k, x, J, g = tiny
+    gg = np.load(os.path.join(GOLD, "tiny_grad_oracle.npz"))
+    f = lmfmm.LayeredDyadicFMM(d, k, p=12, react_s2t=2).build(x)
+    assert f.stats()["s2t_pairs"] > 0
+    gJ = f.evaluate_adjoint(cuda(g["gA"])).cpu().numpy()
+    gX = f.grad_src_xyz(cuda(J), cuda(g["gA"])).cpu().numpy()
+    f.close()
+    e1, e2 = rel(gJ, g["gJ"]), rel(gX[gg["js"]], gg["gX"])
+    print("  adjoint rel L2 = %.3e, gradient rel L2 = %.3e" % (e1, e2), flush=True)
+    assert e1 < ADJ_TOL[12] and e2 < GRAD_TOL[12]

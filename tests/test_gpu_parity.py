@@ -215,3 +215,44 @@ def test_many_rhs_chunked(tiny):
     for r in (0, 15, 16, 20):
         assert np.array_equal(Am[r], f.evaluate(torch.tensor(Jm[r], device="cuda")).cpu().numpy())
     f.close()
+
+
+# direct reaction near field (S2T): reaction trees stop one level early next
+# to the gap and adjacent leaves interact through the component's Sommerfeld
+# integral; recorded errors x 3 (tiny: 783 direct pairs; reaction part
+# p = 8 / 12: 1.24e-4 / 3.39e-6, full field p = 12 9.4e-8; 1e5 sampled with
+# the cost model choosing the direct pairs: recorded below)
+@pytest.mark.parametrize("p,tol", [(8, 5e-4), (12, 1.2e-5)])
+def test_tiny_reaction_part_direct_near_field(tiny, p, tol):
+    d, k, x, J, g = tiny
+    print("case tiny reaction, direct near field, p=%d" % p, flush=True)
+    f = lmfmm.LayeredDyadicFMM(d, k, p=p, components=2, react_s2t=2).build(x)
+    assert f.stats()["s2t_pairs"] > 0
+    A = f.evaluate(torch.tensor(J, device="cuda")).cpu().numpy()
+    f.close()
+    e = rel(A, g["A"] - g["A_free"])
+    print("  rel L2 = %.3e" % e, flush=True)
+    assert e < tol
+
+
+def test_tiny_full_field_direct_near_field(tiny):
+    d, k, x, J, g = tiny
+    A = run(d, k, x, J, p=12, react_s2t=2)
+    e = rel(A, g["A"])
+    print("  rel L2 = %.3e" % e, flush=True)
+    assert e < TINY_TOL[12]
+
+
+def test_three_layer_100k_direct_near_field():
+    n = 100000
+    g = np.load(os.path.join(GOLD, "three_%d_sparse400_oracle.npz" % n))
+    d, k, x, J = inputs.three_layer(n, seed=0)
+    Js, keep = inputs.sparse_currents(J, 400, seed=0)
+    print("case three-layer n=%d, direct near field chosen by the cost model" % n, flush=True)
+    f = lmfmm.LayeredDyadicFMM(d, k, p=12, p_free=20, react_s2t=1).build(x)
+    npairs = f.stats()["s2t_pairs"]
+    A = f.evaluate(torch.tensor(Js, device="cuda")).cpu().numpy()
+    f.close()
+    e = rel(A[g["idx"]], g["A"])
+    print("  s2t pairs %d, rel L2 = %.3e" % (npairs, e), flush=True)
+    assert npairs > 0 and e < 6e-6
