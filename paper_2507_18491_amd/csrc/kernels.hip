@@ -363,23 +363,21 @@ __device__ inline int m2l_rkap(bool phased, int ot, int bl) {
 // MFMA operand layout (v_mfma_f64_16x16x4f64, one fp64 per lane and
 // operand): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; the four
 // result registers of lane l hold C[4 r + l / 16][l % 16], r = 0..3.
-// Complex product with real MFMAs: C_re += A_re B_re + (-A_im) B_im,
-// C_im += A_re B_im + A_im B_re; the eight (or, for one active tile, four
-// split) accumulator chains are interleaved so that no MFMA waits on the
-// one issued just before it.
+// Complex product with three real MFMAs per step (Gauss): P1 = sum A_re
+// B_re, P2 = sum A_im B_im, P3 = sum (A_re + A_im)(B_re + B_im); then C_re =
+// P1 - P2 and C_im = P3 - P1 - P2.  The accumulator chains are interleaved
+// so that no MFMA waits on the one issued just before it.
 template <int NI, int NJ>
 __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds& L, int tid, int wr, int wc) {
-  constexpr bool SPLIT = (NI * NJ == 1);
   constexpr int NIx = NI > 0 ? NI : 1, NJx = NJ > 0 ? NJ : 1;
-  v4d cr[NIx][NJx], ci[NIx][NJx], cr2[NIx][NJx], ci2[NIx][NJx];
+  v4d p1[NIx][NJx], p2[NIx][NJx], p3[NIx][NJx];
 #pragma unroll
   for (int i = 0; i < NIx; i++)
 #pragma unroll
     for (int j = 0; j < NJx; j++) {
-      cr[i][j] = v4d{0, 0, 0, 0};
-      ci[i][j] = cr[i][j];
-      cr2[i][j] = cr[i][j];
-      ci2[i][j] = cr[i][j];
+      p1[i][j] = v4d{0, 0, 0, 0};
+      p2[i][j] = p1[i][j];
+      p3[i][j] = p1[i][j];
     }
   const int lane = tid & 63;
   constexpr int NA = TM * KC / NT, NB = KC * TN / NT;
@@ -443,46 +441,39 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds& L, int tid
       L.Bi[r16 + 16 * it][kk] = v.y;
     }
   };
-  load(0);
   for (int k0 = 0; k0 < c.K; k0 += KC) {
+    load(k0);
     store(k0);
     __syncthreads();
-    if (k0 + KC < c.K) load(k0 + KC);
     if (NI > 0 && NJ > 0) {
 #pragma unroll
       for (int k4 = 0; k4 < KC; k4 += 4) {
         const int kr = k4 + (lane >> 4), li = lane & 15;
-        double a_r[NIx], a_i[NIx], a_n[NIx], b_r[NJx], b_i[NJx];
+        double a_r[NIx], a_i[NIx], a_s[NIx], b_r[NJx], b_i[NJx], b_s[NJx];
 #pragma unroll
         for (int i = 0; i < NIx; i++) {
           a_r[i] = L.Ar[wr * 32 + i * 16 + li][kr];
           a_i[i] = L.Ai[wr * 32 + i * 16 + li][kr];
-          a_n[i] = -a_i[i];
+          a_s[i] = a_r[i] + a_i[i];
         }
 #pragma unroll
         for (int j = 0; j < NJx; j++) {
           b_r[j] = L.Br[wc * 32 + j * 16 + li][kr];
           b_i[j] = L.Bi[wc * 32 + j * 16 + li][kr];
+          b_s[j] = b_r[j] + b_i[j];
         }
 #pragma unroll
         for (int i = 0; i < NIx; i++)
 #pragma unroll
-          for (int j = 0; j < NJx; j++) {
-            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[i], b_r[j], cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[i], b_i[j], ci[i][j], 0, 0, 0);
-          }
+          for (int j = 0; j < NJx; j++) p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[i], b_r[j], p1[i][j], 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < NIx; i++)
 #pragma unroll
-          for (int j = 0; j < NJx; j++) {
-            if (SPLIT) {
-              cr2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_n[i], b_i[j], cr2[i][j], 0, 0, 0);
-              ci2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[i], b_r[j], ci2[i][j], 0, 0, 0);
-            } else {
-              cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_n[i], b_i[j], cr[i][j], 0, 0, 0);
-              ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[i], b_r[j], ci[i][j], 0, 0, 0);
-            }
-          }
+          for (int j = 0; j < NJx; j++) p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[i], b_i[j], p2[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < NIx; i++)
+#pragma unroll
+          for (int j = 0; j < NJx; j++) p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_s[i], b_s[j], p3[i][j], 0, 0, 0);
       }
     }
     __syncthreads();
@@ -498,11 +489,7 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds& L, int tid
     for (int j = 0; j < NJx; j++) {
       const int col = wc * 32 + j * 16 + li;
       if (col >= c.ncol) continue;
-      v4d vr = cr[i][j], vi = ci[i][j];
-      if (SPLIT) {
-        vr += cr2[i][j];
-        vi += ci2[i][j];
-      }
+      v4d vr = p1[i][j] - p2[i][j], vi = p3[i][j] - p1[i][j] - p2[i][j];
       const int jj = c.col0 + col;
       const int q = c.qo + jj / c.n_rhs, r = jj % c.n_rhs;
       cd* Yq = c.Y + c.ybase + ((long long)((q - c.q0b) * 3 + c.ot) * c.n_rhs + r) * c.P;
