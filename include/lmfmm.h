@@ -73,18 +73,19 @@ typedef struct {
                       /* instance's worst admissible pair, lowered by m2l_margin   */
                       /* decades; 0: order p everywhere                            */
   double m2l_margin;  /* see m2l_adapt (default 3)                                  */
-  int react_s2t;      /* 0 (default): reaction trees are refined next to the gap    */
-                      /* between images and effective locations until no source   */
-                      /* and target leaves are adjacent (every reaction            */
-                      /* interaction is an M2L).  1: a tree may stop one level     */
-                      /* earlier where a cost model finds the direct near field    */
-                      /* cheaper; 2: always one level earlier.  Leaves that stay   */
-                      /* adjacent interact directly through the component's        */
-                      /* Sommerfeld integral (S2T, Sec. 3.3/3.4)                   */
+  int react_s2t;      /* 0: reaction trees are refined next to the gap between      */
+                      /* images and effective locations until no source and        */
+                      /* target leaves are adjacent (every reaction interaction   */
+                      /* is an M2L).  1 (default): a tree stops one level earlier */
+                      /* where a cost model finds the direct near field cheaper   */
+                      /* than that level's M2L work; 2: always one level earlier. */
+                      /* Leaves that stay adjacent interact directly through the  */
+                      /* component's Sommerfeld integral (S2T, Sec. 3.3/3.4).     */
+                      /* Source-position gradients use a second plan with 0.      */
 } lm_params;
 
 /* Fills *prm with the defaults (p = 12, p_free = p, automatic depths, m2l_adapt = 1,
- * m2l_margin = 3, react_s2t = 0). */
+ * m2l_margin = 3, react_s2t = 1). */
 int lm_default_params(lm_params* prm);
 
 /* Creates a context bound to HIP device `hip_device`.  *out is owned by the
@@ -219,10 +220,11 @@ int lm_stats(const lm_ctx* ctx, double* out_host, int n);
 #define LM_STATS_COUNT 22
 
 /* Self-test of the device arithmetic used by the near field (no context):
- * for each x_dev[i] writes out_dev[4i..4i+3] = sin x, cos x (the reduced-range
- * routine of the near field), 1/sqrt(x^2 + 1e-300) (refined estimate) and the
- * same by the library's sqrt and division.  DEVICE arrays x [n], out [4n];
- * enqueued on `stream`.  For tests. */
+ * for each x_dev[i] writes out_dev[6i..6i+5] = sin x, cos x (the reduced-range
+ * routine of the near field), 1/sqrt(x^2 + 1e-300) (refined estimate), the
+ * same by the library's sqrt and division, and J0(|x|), J1(|x|) (the
+ * polynomial forms used on the real tail of the direct reaction near field).
+ * DEVICE arrays x [n], out [6n]; enqueued on `stream`.  For tests. */
 int lm_selftest_math(int64_t n, const double* x_dev, double* out_dev, void* stream);
 
 /* ---- host-only helpers (no GPU needed), for tests of the host logic ---- */

@@ -172,7 +172,7 @@ int lm_default_params(lm_params* prm) {
   prm->components = 3;
   prm->m2l_adapt = 1;
   prm->m2l_margin = 3.0;
-  prm->react_s2t = 0;
+  prm->react_s2t = 1;
   return LM_OK;
 }
 

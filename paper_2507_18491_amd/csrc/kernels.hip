@@ -14,6 +14,7 @@
 #include <cmath>
 #include <vector>
 
+#include "bessel_pq.h"
 #include "kernels.h"
 
 // RC (template parameter): right-hand sides per block in the point/translation passes (1 or 4)
@@ -509,9 +510,9 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds& L, int tid
 // those of its four 16 x 16 MFMA tiles that hold rows below the offset's
 // (pord+1)^2 and columns below the tile's pair count, so partial tiles cost
 // little; the choice is made once per tile from a wave-uniform value.
-// Operands are staged through LDS as separate real / imaginary planes,
-// k-major, KC values of k at a time, with the next chunk's global loads in
-// flight during the MFMAs.  Consecutive tiles are sent to one XCD (blocks
+// Operands are staged through LDS as separate real / imaginary planes, KC
+// values of k at a time; three resident blocks per CU overlap one block's
+// global loads with the others' MFMAs.  Consecutive tiles are sent to one XCD (blocks
 // are dealt round-robin over the 8 XCDs), so the tiles sharing one offset's
 // matrix and source vectors run against one L2.
 __global__ __launch_bounds__(NT, 3) void k_m2l(DevPlan d, const M2LTile* tiles, int n_tiles, int n_rhs,
@@ -888,6 +889,62 @@ void launch_p2p(const DevPlan& d, const int* tboxes, int n, const double* sxyz, 
 // out[4 i .. 4 i + 3] = (sin, cos) by the near-field routine (library beyond
 // its range), then
 // 1/sqrt(x_i^2 + 1e-300) by the refined estimate, then by the library.
+// J0 and J1 of a real argument x >= 0, ix = 1 / x (read only from
+// LM_BPQ_X0 up): fixed-degree polynomials, so every lane of a wave runs the
+// same steps.  Below LM_BPQ_X0 the power series S(w) in w = x^2 / 4 and
+// J1 = -(x/2) S'(w); above, the Hankel modulus/phase form with P and Q / t as
+// polynomials in u = t^2, t = X0 / x, and J1 = -J0' from their derivatives
+// (coefficients and their accuracy: gen_bessel_pq.py).  The coefficients are
+// read through an offset the compiler cannot fold, so that they are loaded
+// per call instead of being held in registers across the caller's loop.
+__constant__ double c_bpq[LM_BPQ_N] = {LM_BPQ_COEFFS};
+// a b + c with c a wave-uniform value read from scalar registers (the
+// three-operand form; the compiler otherwise copies c to vector registers
+// for the two-address form, two moves per coefficient)
+__device__ __forceinline__ double fma_s(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+}
+__device__ inline void bessel01_real(double x, double ix, double* j0v, double* j1v) {
+  int z = 0;
+  asm volatile("" : "+s"(z));
+  const double* c = c_bpq + z;
+  if (x < LM_BPQ_X0) {
+    const double w = 0.25 * x * x;
+    double b = c[LM_BPQ_NSER - 1], d = 0.0;
+#pragma unroll
+    for (int k = LM_BPQ_NSER - 2; k >= 0; k--) {
+      d = fma(d, w, b);
+      b = fma_s(b, w, c[k]);
+    }
+    *j0v = b;
+    *j1v = -0.5 * x * d;
+    return;
+  }
+  const double* cp = c + LM_BPQ_NSER;
+  const double* cq = cp + LM_BPQ_DEG + 1;
+  const double t = LM_BPQ_X0 * ix, u = t * t;
+  double P = cp[LM_BPQ_DEG], dP = 0.0, Qt = cq[LM_BPQ_DEG], dQt = 0.0;
+#pragma unroll
+  for (int k = LM_BPQ_DEG - 1; k >= 0; k--) {
+    dP = fma(dP, u, P);
+    P = fma_s(P, u, cp[k]);
+    dQt = fma(dQt, u, Qt);
+    Qt = fma_s(Qt, u, cq[k]);
+  }
+  const double Q = t * Qt;
+  const double dPx = -2.0 * u * ix * dP;                // dP / dx
+  const double dQx = -(t * ix) * fma(2.0 * u, dQt, Qt);  // dQ / dx
+  double sn, cs;
+  lm_sincos_red(x - 0.78539816339744830962, &sn, &cs);  // chi = x - pi/4
+  const double A = sqrt(0.63661977236758134308 * ix);   // sqrt(2 / (pi x))
+  const double j0 = A * (P * cs - Q * sn);
+  *j0v = j0;
+  // J1 = -J0' = J0 / (2x) + A ((Q - P') cos chi + (P + Q') sin chi)
+  *j1v = 0.5 * ix * j0 + A * ((Q - dPx) * cs + (P + dQx) * sn);
+}
+
 __global__ void k_selftest_math(const double* x, long long n, double* out) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -897,10 +954,14 @@ __global__ void k_selftest_math(const double* x, long long n, double* out) {
   else
     sincos(x[i], &sn, &cs);
   double a = x[i] * x[i] + 1e-300;
-  out[4 * i] = sn;
-  out[4 * i + 1] = cs;
-  out[4 * i + 2] = lm_rsqrt(a);
-  out[4 * i + 3] = 1.0 / sqrt(a);
+  double ax = fabs(x[i]), j0, j1;
+  bessel01_real(ax, ax > 0 ? 1.0 / ax : 0.0, &j0, &j1);
+  out[6 * i] = sn;
+  out[6 * i + 1] = cs;
+  out[6 * i + 2] = lm_rsqrt(a);
+  out[6 * i + 3] = 1.0 / sqrt(a);
+  out[6 * i + 4] = j0;
+  out[6 * i + 5] = j1;
 }
 void launch_selftest_math(const double* x, long long n, double* out, hipStream_t s) {
   if (n <= 0) return;
@@ -1220,62 +1281,23 @@ __device__ inline void bessel012_series(cd z, cd* j0, cd* j1, cd* j2) {
   *j2 = s2;
 }
 
-// J_0(x), J_1(x) for real x >= 0 to about 1e-11: the power series below 12
-// (terms stay below 5e3), the Hankel asymptotic expansion above
-// (J_n = sqrt(2 / (pi x)) (P_n cos chi_n - Q_n sin chi_n), chi_n = x - (2n+1) pi/4,
-// summed until the terms stop decreasing; the first omitted term is below
-// e^{-2x} < 4e-11).
-__device__ inline void bessel01_real(double x, double* j0v, double* j1v) {
-  if (x < 12.0) {
-    double w = -0.25 * x * x, t0 = 1.0, t1 = 1.0, s0 = 1.0, s1 = 1.0;
-    for (int k = 1; k <= 60; k++) {
-      t0 *= w * c_rk2[k];
-      t1 *= w * c_rkk1[k];
-      s0 += t0;
-      s1 += t1;
-      if (fabs(t0) + fabs(t1) < 1e-17) break;
-    }
-    *j0v = s0;
-    *j1v = 0.5 * x * s1;
-    return;
-  }
-  double ix8 = 0.125 / x;
-  // a_k(n) = prod_{i=1..k} (4 n^2 - (2i-1)^2) / (k! (8x)^k)
-  double a0 = 1.0, a1 = 1.0, p0 = 1.0, q0 = 0.0, p1 = 1.0, q1 = 0.0, last = 1.0;
-  for (int k = 1; k <= 40; k++) {
-    double o = (2.0 * k - 1.0) * (2.0 * k - 1.0);
-    a0 *= (0.0 - o) * ix8 * c_rk[k];
-    a1 *= (4.0 - o) * ix8 * c_rk[k];
-    double m = fabs(a0) + fabs(a1);
-    if (m > last) break;
-    last = m;
-    double sg = ((k >> 1) & 1) ? -1.0 : 1.0;  // (-1)^{k/2} (even k), (-1)^{(k-1)/2} (odd k)
-    if (k & 1) {
-      q0 += sg * a0;
-      q1 += sg * a1;
-    } else {
-      p0 += sg * a0;
-      p1 += sg * a1;
-    }
-    if (m < 1e-17) break;
-  }
-  double sn, cs;
-  lm_sincos_red(x - 0.78539816339744830962, &sn, &cs);  // chi_0 = x - pi/4
-  double amp = sqrt(0.63661977236758134308 / x);       // sqrt(2 / (pi x))
-  *j0v = amp * (p0 * cs - q0 * sn);
-  // chi_1 = chi_0 - pi/2: cos chi_1 = sin chi_0, sin chi_1 = -cos chi_0
-  *j1v = amp * (p1 * sn + q1 * cs);
-}
-
+// One work item: a chunk of up to 64 targets of a reaction leaf against the
+// sources of all its near boxes, taken as one concatenated list (segments of
+// up to LM_S2T_SEG boxes).  Pair q = i ns + j (target i, source j of the
+// segment) is one lane per round of 64 pairs; each lane loads its own source
+// and runs the node loop of the component's Sommerfeld integrals (Gamma_1,
+// then the real tail up to its own cut).  Nodes are staged through LDS 64 at
+// a time and read in a wave-uniform loop.  A target adds its pairs in q order
+// (no atomics).
 template <bool SMALLZ>
-__global__ __launch_bounds__(LM_S2T_CHUNK, 3) void k_s2t(DevPlan d, MediumDev md, const int* items,
-                                                        const double* sxyz, const cd* J, long long n_src,
-                                                        const double* txyz, long long n_tgt, int n_rhs, double a,
-                                                        cd* A) {
+__global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md, const int* items,
+                                                                     const double* sxyz, const cd* J,
+                                                                     long long n_src, const double* txyz,
+                                                                     long long n_tgt, int n_rhs, double a, cd* A) {
   __shared__ double tp[LM_S2T_CHUNK][3];  // targets: x, y, t
-  __shared__ double sp[LM_S2T_CHUNK][3];  // sources: x, y, u
-  __shared__ cd sq[LM_S2T_CHUNK][3];      // sources: u+, u-, m_z
+  __shared__ int seg_pt0[LM_S2T_SEG], seg_cum[LM_S2T_SEG + 1];
   __shared__ cd res[LM_S2T_CHUNK][3];     // per pair of the round: out+, out-, out_z
+  __shared__ cd nk[LM_S2T_CHUNK][10];     // node chunk: kr, w, kz_t, kz_s, F_1..F_5, 1 / kr (tail)
   const int tid = threadIdx.x;
   // work item, component and node range are uniform over the block
   const int b = __builtin_amdgcn_readfirstlane(items[2 * blockIdx.x]);
@@ -1287,6 +1309,7 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 3) void k_s2t(DevPlan d, MediumDev md
   const int nt = min(LM_S2T_CHUNK, tb.pt1 - t0);
   const int n0 = __builtin_amdgcn_readfirstlane(ip.s2t0), nn = __builtin_amdgcn_readfirstlane(ip.s2tn);
   const QNode* nodes = d.nodes + n0;
+  const double dls = ip.up_s ? md.d[ip.ls - 1] : md.d[ip.ls];
   int id = 0;
   if (tid < nt) {
     id = d.tgt_perm[t0 + tid];
@@ -1296,100 +1319,124 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 3) void k_s2t(DevPlan d, MediumDev md
     tp[tid][2] = ip.up_t ? zt - md.d[ip.lt] : md.d[ip.lt - 1] - zt;
   }
   cd op = cd{0, 0}, om = cd{0, 0}, oz = cd{0, 0};  // thread tid < nt: totals of target tid
-  for (int li = tb.p2p0; li < tb.p2p1; li++) {
-    const SrcBox sb = d.sbox[d.p2p_list[li]];
-    for (int s0 = sb.pt0; s0 < sb.pt1; s0 += LM_S2T_CHUNK) {
-      const int ns = min(LM_S2T_CHUNK, sb.pt1 - s0);
-      __syncthreads();
-      if (tid < ns) {
-        int sid = d.src_perm[s0 + tid];
-        double zs = sxyz[3 * sid + 2];
-        sp[tid][0] = sxyz[3 * sid];
-        sp[tid][1] = sxyz[3 * sid + 1];
-        sp[tid][2] = ip.up_s ? md.d[ip.ls - 1] - zs : zs - md.d[ip.ls];
-        const cd* Jp = J + ((long long)r * n_src + sid) * 3;
-        cd jx = Jp[0], jy = Jp[1], jz = Jp[2];
-        sq[tid][0] = jx + cd{-jy.y, jy.x};
-        sq[tid][1] = jx - cd{-jy.y, jy.x};
-        sq[tid][2] = jz;
+  for (int l0 = tb.p2p0; l0 < tb.p2p1; l0 += LM_S2T_SEG) {
+    const int nb = min(LM_S2T_SEG, tb.p2p1 - l0);
+    __syncthreads();
+    if (tid == 0) {
+      int cum = 0;
+      for (int e = 0; e < nb; e++) {
+        const SrcBox sb = d.sbox[d.p2p_list[l0 + e]];
+        seg_pt0[e] = sb.pt0;
+        seg_cum[e] = cum;
+        cum += sb.pt1 - sb.pt0;
       }
-      __syncthreads();
-      // pairs (target i, source j) of this tile, pair q = i ns + j, one per lane
-      const int npair = nt * ns;
-      for (int q0 = 0; q0 < npair; q0 += LM_S2T_CHUNK) {
-        const int q = q0 + tid;
-        cd rp = cd{0, 0}, rm = cd{0, 0}, rz = cd{0, 0};
-        if (q < npair) {
-          const int i = q / ns, j = q - i * ns;
-          double dx = tp[i][0] - sp[j][0], dy = tp[i][1] - sp[j][1];
-          double tz = tp[i][2], uz = sp[j][2];
-          double rho = sqrt(dx * dx + dy * dy);
-          double cph = rho > 0 ? dx / rho : 1.0, sph = rho > 0 ? dy / rho : 0.0;
-          double kcut = a + LM_S2T_DIGITS / (tz + uz);
-          cd I1 = cd{0, 0}, I2 = cd{0, 0}, I3 = cd{0, 0}, I4 = cd{0, 0}, I5 = cd{0, 0};
-          int n = 0;
-          for (; n < nn; n++) {
-            const QNode& nd = nodes[n];
-            if (nd.kr.y == 0.0) break;  // end of Gamma_1
-            cd e = cd{0, 1} * (tz * nd.kzt + uz * nd.kzs);
-            cd base = nd.w * nd.kr * cexpd(e);
+      seg_cum[nb] = cum;
+    }
+    __syncthreads();
+    const int ns = seg_cum[nb];
+    const int npair = nt * ns;
+    for (int q0 = 0; q0 < npair; q0 += LM_S2T_CHUNK) {
+      const int q = q0 + tid;
+      cd rp = cd{0, 0}, rm = cd{0, 0}, rz = cd{0, 0};
+      const bool pa = q < npair;
+      const int i = pa ? q / ns : 0, j = pa ? q - (q / ns) * ns : 0;
+      // this lane's source: box of the segment holding source j
+      int e = 0;
+      while (e + 1 < nb && seg_cum[e + 1] <= j) e++;
+      const int sid = d.src_perm[seg_pt0[e] + (j - seg_cum[e])];
+      const double* sx = sxyz + 3 * (long long)sid;
+      const cd* Jp = J + ((long long)r * n_src + sid) * 3;
+      const cd jx = Jp[0], jy = Jp[1], jz = Jp[2];
+      double dx = tp[i][0] - sx[0], dy = tp[i][1] - sx[1];
+      double tz = tp[i][2], uz = ip.up_s ? dls - sx[2] : sx[2] - dls;
+      double rho = sqrt(dx * dx + dy * dy);
+      const double irho = rho > 0 ? 1.0 / rho : 0.0;
+      double cph = rho > 0 ? dx * irho : 1.0, sph = rho > 0 ? dy * irho : 0.0;
+      // each pair's cut on the real tail; inactive lanes need no node
+      double kcut = pa ? a + LM_S2T_DIGITS / (tz + uz) : -1.0;
+      cd I1 = cd{0, 0}, I2 = cd{0, 0}, I3 = cd{0, 0}, I4 = cd{0, 0}, I5 = cd{0, 0};
+      for (int c0 = 0; c0 < nn; c0 += LM_S2T_CHUNK) {
+        const int nc = min(LM_S2T_CHUNK, nn - c0);
+        __syncthreads();
+        if (tid < nc) {
+          const QNode& nd = nodes[c0 + tid];
+          nk[tid][0] = nd.kr;
+          nk[tid][1] = nd.w;
+          nk[tid][2] = nd.kzt;
+          nk[tid][3] = nd.kzs;
+          for (int f = 0; f < 5; f++) nk[tid][4 + f] = nd.F[f];
+          nk[tid][9] = cd{nd.kr.y == 0.0 ? 1.0 / nd.kr.x : 0.0, 0.0};
+        }
+        __syncthreads();
+        for (int m = 0; m < nc; m++) {
+          const cd kr = nk[m][0];
+          if (kr.y != 0.0) {  // Gamma_1 (complex k_rho): every active pair
+            if (!pa) continue;
+            cd ez = cd{0, 1} * (tz * nk[m][2] + uz * nk[m][3]);
+            cd base = nk[m][1] * kr * cexpd(ez);
             cd jb[3];
             if (SMALLZ)
-              bessel012_series(rho * nd.kr, jb, jb + 1, jb + 2);
+              bessel012_series(rho * kr, jb, jb + 1, jb + 2);
             else
-              bessel_jq(2, rho * nd.kr, jb);
+              bessel_jq(2, rho * kr, jb);
             cd b0 = base * jb[0], b1 = base * jb[1], b2 = base * jb[2];
-            I1 = I1 + b0 * nd.F[0];
-            I2 = I2 + b1 * nd.F[1];
-            I3 = I3 + b2 * nd.F[2];
-            I4 = I4 + b1 * nd.F[3];
-            I5 = I5 + b0 * nd.F[4];
-          }
-          for (; n < nn; n++) {
-            const QNode& nd = nodes[n];
-            double kr = nd.kr.x;
-            if (kr > kcut) break;
+            I1 = I1 + b0 * nk[m][4];
+            I2 = I2 + b1 * nk[m][5];
+            I3 = I3 + b2 * nk[m][6];
+            I4 = I4 + b1 * nk[m][7];
+            I5 = I5 + b0 * nk[m][8];
+          } else if (kr.x <= kcut) {
             // real tail: k_z = i |k_z|, Z = exp(-t |k_z| - u |k_z'|)
-            double z = exp(-(tz * nd.kzt.y + uz * nd.kzs.y));
-            double base = nd.w.x * kr * z;
-            double x = kr * rho;
+            double z = exp(-(tz * nk[m][2].y + uz * nk[m][3].y));
+            double base = nk[m][1].x * kr.x * z;
+            const double x = kr.x * rho, ix = nk[m][9].x * irho;
             double J0, J1;
-            bessel01_real(x, &J0, &J1);
-            double J2 = x > 1e-3 ? 2.0 * J1 / x - J0 : x * x * (0.125 - x * x / 192.0);
+            bessel01_real(x, ix, &J0, &J1);
+            // J2 = 2 J1 / x - J0; its series x^2/8 - x^4/96 near 0
+            double J2 = x > 1e-3 ? 2.0 * J1 * ix - J0 : x * x * (0.125 - x * x * (1.0 / 96.0));
             double b0 = base * J0, b1 = base * J1, b2 = base * J2;
-            I1 = I1 + b0 * nd.F[0];
-            I2 = I2 + b1 * nd.F[1];
-            I3 = I3 + b2 * nd.F[2];
-            I4 = I4 + b1 * nd.F[3];
-            I5 = I5 + b0 * nd.F[4];
-          }
-          cd e1 = cd{cph, sph}, e2 = e1 * e1;
-          cd W01 = cd{-I1.y, I1.x};  // i I1
-          cd W05 = cd{-I5.y, I5.x};  // i I5
-          cd t3 = cd{I3.y, -I3.x};   // -i I3
-          cd W2p = e2 * t3, W2m = cconj(e2) * t3;
-          cd W1p2 = -1.0 * (e1 * I2), W1m2 = -1.0 * (cconj(e1) * I2);
-          cd W1p4 = -1.0 * (e1 * I4), W1m4 = -1.0 * (cconj(e1) * I4);
-          cd up = sq[j][0], um = sq[j][1], mz = sq[j][2];
-          rp = 0.5 * (W01 * up) - 0.5 * (W2p * um) + W1p2 * mz;
-          rm = 0.5 * (W01 * um) - 0.5 * (W2m * up) + W1m2 * mz;
-          rz = 0.5 * (W1p4 * um) + 0.5 * (W1m4 * up) + W05 * mz;
-        }
-        res[tid][0] = rp;
-        res[tid][1] = rm;
-        res[tid][2] = rz;
-        __syncthreads();
-        // target tid adds its pairs of this round in source order
-        if (tid < nt) {
-          int qa = max(q0, tid * ns), qb = min(q0 + LM_S2T_CHUNK, (tid + 1) * ns);
-          for (int qq = qa; qq < qb; qq++) {
-            op = op + res[qq - q0][0];
-            om = om + res[qq - q0][1];
-            oz = oz + res[qq - q0][2];
+            I1 = I1 + b0 * nk[m][4];
+            I2 = I2 + b1 * nk[m][5];
+            I3 = I3 + b2 * nk[m][6];
+            I4 = I4 + b1 * nk[m][7];
+            I5 = I5 + b0 * nk[m][8];
           }
         }
-        __syncthreads();
+        // stop once the next chunk starts on the tail beyond every pair's cut
+        bool more = false;
+        if (c0 + nc < nn) {
+          const cd kn = nodes[c0 + nc].kr;
+          more = kn.y != 0.0 || kn.x <= kcut;
+        }
+        if (!__syncthreads_or(more)) break;
       }
+      if (pa) {
+        cd e1 = cd{cph, sph}, e2 = e1 * e1;
+        cd W01 = cd{-I1.y, I1.x};  // i I1
+        cd W05 = cd{-I5.y, I5.x};  // i I5
+        cd t3 = cd{I3.y, -I3.x};   // -i I3
+        cd W2p = e2 * t3, W2m = cconj(e2) * t3;
+        cd W1p2 = -1.0 * (e1 * I2), W1m2 = -1.0 * (cconj(e1) * I2);
+        cd W1p4 = -1.0 * (e1 * I4), W1m4 = -1.0 * (cconj(e1) * I4);
+        cd up = jx + cd{-jy.y, jy.x}, um = jx - cd{-jy.y, jy.x}, mz = jz;
+        rp = 0.5 * (W01 * up) - 0.5 * (W2p * um) + W1p2 * mz;
+        rm = 0.5 * (W01 * um) - 0.5 * (W2m * up) + W1m2 * mz;
+        rz = 0.5 * (W1p4 * um) + 0.5 * (W1m4 * up) + W05 * mz;
+      }
+      res[tid][0] = rp;
+      res[tid][1] = rm;
+      res[tid][2] = rz;
+      __syncthreads();
+      // target tid adds its pairs of this round in source order
+      if (tid < nt) {
+        int qa = max(q0, tid * ns), qb = min(q0 + LM_S2T_CHUNK, (tid + 1) * ns);
+        for (int qq = qa; qq < qb; qq++) {
+          op = op + res[qq - q0][0];
+          om = om + res[qq - q0][1];
+          oz = oz + res[qq - q0][2];
+        }
+      }
+      __syncthreads();
     }
   }
   if (tid < nt) {

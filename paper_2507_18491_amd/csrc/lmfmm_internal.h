@@ -14,7 +14,8 @@
 #define LM_P2P_CHUNK 256   // targets per near-field work item (= threads per block)
 #define LM_L2P_CHUNK(kind) ((kind) == 0 ? 256 : 64)   // points per L2P work item (free / reaction)
 #define LM_S2T_CHUNK 64    // targets per reaction near-field work item (= threads per block)
-#define LM_S2T_DIGITS 45.0 // the S2T tail stops where e^{-k (t + u)} < e^{-45}
+#define LM_S2T_DIGITS 36.0 // the S2T tail stops where e^{-k (t + u)} < e^{-36}
+#define LM_S2T_SEG 32      // near boxes per source segment of one S2T work item
 
 // One FMM instance: the free-space part of one layer, or one reaction
 // component (target layer lt, source layer ls, arrival direction at the

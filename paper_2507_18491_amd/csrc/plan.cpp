@@ -644,7 +644,7 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       // adjacent source/target leaves remain).  With the direct near field
       // enabled, the boxes next to the gap may stop one level earlier when
       // the direct (S2T) pairs of that level cost less than the M2L work of
-      // the last level (measured rates: about 3e-8 s per S2T pair, 2.9e-8 s
+      // the last level (measured rates: about 4e-9 s per S2T pair, 2.9e-8 s
       // per reaction M2L pair at p = 12 with adaptive orders; about 50 M2L
       // pairs per box at the finest level).
       int D1 = 0;
@@ -676,7 +676,11 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
           double h = hz_s(g.spos[3 * i + 2]);
           if (h < sb) cs[cell(g.spos[3 * i], g.spos[3 * i + 1], sb)]++;
         }
-        double pairs = 0;
+        // direct work in lane rounds: a work item takes up to LM_S2T_CHUNK
+        // targets of a leaf against all its near sources, LM_S2T_CHUNK pairs
+        // per round, and a round costs about the same however many of its
+        // lanes hold a pair
+        double rounds = 0;
         for (auto& kv : ct) {
           long long cx = kv.first >> 32, cy = (long long)(int)(kv.first & 0xffffffffLL);
           long long ns = 0;
@@ -685,9 +689,10 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
               auto it = cs.find(((cx + dx) << 32) ^ ((cy + dy) & 0xffffffffLL));
               if (it != cs.end()) ns += it->second;
             }
-          pairs += (double)kv.second * (double)ns;
+          const long long nt = kv.second, CH = LM_S2T_CHUNK;
+          rounds += (double)((nt / CH) * ns + ((nt % CH) * ns + CH - 1) / CH);
         }
-        double c_s2t = pairs * 3.0e-8;
+        double c_s2t = rounds * (double)LM_S2T_CHUNK * 4.0e-9;
         double c_m2l = (double)tb1.size() * 50.0 * 9.0 * (double)P * P * 8.0 * 0.6 / 43e12;
         if (prm.react_s2t == 2 || c_s2t < c_m2l) Dmax = D1 - 1;
       }
@@ -1129,7 +1134,10 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       // real tail [a, kcut]
       int pp = pl.inst[inst].p;
       double kcut = a + (3.0 * pp + prm.tail_digits) / dzmin;
-      double len = std::min(4.0 / dzmin, rho_max > 0 ? 2.0 * M_PI / rho_max : 1e300);
+      // 16-point Gauss-Legendre panels spanning two periods of J(k rho_max)
+      // (error below 3e-16 of the panel's largest integrand value while the
+      // decay over half a panel, len h / 2, stays below about 7)
+      double len = std::min(4.0 / dzmin, rho_max > 0 ? 4.0 * M_PI / rho_max : 1e300);
       int npan = (int)ceil((kcut - a) / len);
       len = (kcut - a) / npan;
       for (int pnl = 0; pnl < npan; pnl++) {
@@ -1168,7 +1176,10 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
         }
       }
       double kcut = a + LM_S2T_DIGITS / dzmin;
-      double len = std::min(4.0 / dzmin, rho_max > 0 ? 2.0 * M_PI / rho_max : 1e300);
+      // 16-point Gauss-Legendre panels spanning two periods of J(k rho_max)
+      // (error below 3e-16 of the panel's largest integrand value while the
+      // decay over half a panel, len h / 2, stays below about 7)
+      double len = std::min(4.0 / dzmin, rho_max > 0 ? 4.0 * M_PI / rho_max : 1e300);
       int npan = (int)ceil((kcut - a) / len);
       len = (kcut - a) / npan;
       for (int pnl = 0; pnl < npan; pnl++) {

@@ -31,7 +31,7 @@ struct PlanParams {
   int components = 3;    // bit 0: free space, bit 1: reaction
   int m2l_adapt = 1;     // per-offset M2L order from the separation ratio
   double m2l_margin = 3.0;  // decades below the worst pair's truncation bound
-  int react_s2t = 0;         // 0: refine reaction trees until no adjacent leaves remain;
+  int react_s2t = 1;         // 0: refine reaction trees until no adjacent leaves remain;
                              // 1: stop one level early next to the gap where direct (S2T)
                              // pairs are estimated cheaper; 2: always stop one level early
 };

@@ -298,12 +298,13 @@ def host_plan_stats(d, k, src, tgt=None, **params):
 
 
 def selftest_math(x):
-    """(sin, cos, refined 1/sqrt(x^2), library 1/sqrt(x^2)) of a float64 CUDA
-    tensor x by the near-field device routines; returns a [n, 4] tensor."""
+    """(sin, cos, refined 1/sqrt(x^2), library 1/sqrt(x^2), J0(|x|), J1(|x|))
+    of a float64 CUDA tensor x by the near-field device routines; returns a
+    [n, 6] tensor."""
     import torch
     lib = load_library()
     x = x.contiguous()
-    out = torch.empty((x.numel(), 4), dtype=torch.float64, device=x.device)
+    out = torch.empty((x.numel(), 6), dtype=torch.float64, device=x.device)
     rc = lib.lm_selftest_math(x.numel(), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                               ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream))
     if rc:

@@ -1,6 +1,7 @@
 """GPU unit test of the near-field arithmetic (through the C ABI): the
-reduced-range sin/cos (Cody-Waite reduction by pi/2, Taylor polynomials) and
-the refined reciprocal square root, against numpy's fp64 routines."""
+reduced-range sin/cos (Cody-Waite reduction by pi/2, Taylor polynomials), the
+refined reciprocal square root, against numpy's fp64 routines, and the
+polynomial J0, J1 of the direct reaction near field against scipy's."""
 import numpy as np
 import pytest
 
@@ -29,3 +30,20 @@ def test_near_field_sincos_and_rsqrt():
     er = np.abs(out[:, 2] - ref) / ref
     print("max rsqrt rel err %.3e" % er.max(), flush=True)
     assert er.max() < 5e-16
+
+
+def test_real_bessel_j0_j1():
+    from scipy import special
+    x = np.concatenate([
+        np.linspace(0.0, 12.0, 120001),          # both sides of the switch at x = 6
+        np.linspace(12.0, 400.0, 100001),
+        np.geomspace(400.0, 2000.0, 2000),   # (beyond, rounding of x - pi/4 grows with x)
+        [1e-300, 1e-12, 1e-3, 6.0 - 1e-12, 6.0, 6.0 + 1e-12],
+    ])
+    out = lmfmm.selftest_math(torch.tensor(x, device="cuda")).cpu().numpy()
+    e0 = np.abs(out[:, 4] - special.j0(x))
+    e1 = np.abs(out[:, 5] - special.j1(x))
+    print("max |J0 err| %.3e, max |J1 err| %.3e" % (e0.max(), e1.max()), flush=True)
+    # absolute bound from the generator's fit and the series' cancellation
+    # near the switch (about 3e-15), plus scipy's own rounding
+    assert e0.max() < 1e-14 and e1.max() < 1e-14

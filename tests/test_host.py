@@ -189,3 +189,28 @@ def test_plan_rejects_bad_adaptive_params(kw):
     d, k, x, _ = inputs.tiny()
     with pytest.raises(lmfmm.LMError):
         lmfmm.host_plan_stats(d, k, x, p=8, **kw)
+
+
+def test_real_bessel_coefficient_table():
+    """The committed J0/J1 coefficient header (polynomial forms used on the
+    real tail of the direct reaction near field), evaluated on the host with
+    the kernel's steps, against scipy's J0 and J1."""
+    import re
+    import sys
+    from scipy import special
+    csrc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2507_18491_amd", "csrc")
+    sys.path.insert(0, csrc)
+    try:
+        import gen_bessel_pq as g
+    finally:
+        sys.path.pop(0)
+    h = open(os.path.join(csrc, "bessel_pq.h")).read()
+    assert int(re.search(r"#define LM_BPQ_NSER (\d+)", h).group(1)) == g.NSER
+    assert int(re.search(r"#define LM_BPQ_DEG (\d+)", h).group(1)) == g.DEG
+    c = [float(v) for v in re.findall(r"^\s+([-0-9.e+]+),", h, re.M)]
+    assert len(c) == g.NSER + 2 * (g.DEG + 1)
+    cs, cp, cq = c[:g.NSER], c[g.NSER:g.NSER + g.DEG + 1], c[g.NSER + g.DEG + 1:]
+    x = np.concatenate([np.linspace(0.0, 12.0, 2401), np.linspace(12.0, 400.0, 2001), [1e-12, 6.0 - 1e-12, 6.0]])
+    j = np.array([g.j01(cs, cp, cq, float(v)) for v in x])
+    assert np.abs(j[:, 0] - special.j0(x)).max() < 1e-14
+    assert np.abs(j[:, 1] - special.j1(x)).max() < 1e-14
