@@ -30,9 +30,10 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 fp64 FMA/clk x 2 flop x 2.4 GHz (fp
 # plain 1 GiB device copy (FETCH_SIZE reads 0.5 KiB per KiB read: factor 2.0;
 # WRITE_SIZE 1:1); see profiles/k_m2l_three_layer_1M_p12_pf20.md.  Valid only
 # for the kernel source it was measured on (digest of the M2L section of
-# kernels.hip); otherwise reported as null.
-K_M2L_TRAFFIC = {"digest": "06ddfc2f6f6a08a2", "fetch_bytes": 1.5234e7 * 1024 * 2.0,
-                 "write_bytes": 5.0596e6 * 1024 * 1.0}
+# kernels.hip) and the same launches per step (the plan's split of the M2L
+# work); otherwise reported as null.
+K_M2L_TRAFFIC = {"digest": "ab3c394a52a316dc", "launches_per_step": 8,
+                 "fetch_bytes": 1.7698e7 * 1024 * 2.0, "write_bytes": 5.4396e6 * 1024 * 1.0}
 
 
 def m2l_source_digest():
@@ -115,6 +116,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-uneven", action="store_true", help="skip the 32 uneven geometries")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint and source-gradient timings (profiling runs of the forward step)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB device buffer three times (a reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -175,29 +178,32 @@ def main():
 
     # adjoint (gJ = G^H gA) and source-position gradient on the same build,
     # timed like the forward step (same number of steps, after one warm-up)
-    gA = torch.tensor(inputs.cotangent(args.n, n_rhs=args.rhs, seed=0), device=dev).reshape(args.rhs, args.n, 3)
-    gJ = torch.empty_like(A)
-    fmm.evaluate_adjoint(gA, out=gJ)
-    torch.cuda.synchronize()
-    t0 = time.time()
-    for _ in range(args.steps):
+    adj_s = grad_s = None
+    if not args.no_adjoint:
+        gA = torch.tensor(inputs.cotangent(args.n, n_rhs=args.rhs, seed=0), device=dev).reshape(args.rhs, args.n, 3)
+        gJ = torch.empty_like(A)
         fmm.evaluate_adjoint(gA, out=gJ)
-    torch.cuda.synchronize()
-    adj_s = (time.time() - t0) / args.steps
-    gX = torch.empty((args.n, 3), dtype=torch.float64, device=dev)
-    fmm.grad_src_xyz(Jt.reshape(args.rhs, args.n, 3), gA, out=gX)
-    torch.cuda.synchronize()
-    t0 = time.time()
-    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for _ in range(args.steps):
+            fmm.evaluate_adjoint(gA, out=gJ)
+        torch.cuda.synchronize()
+        adj_s = (time.time() - t0) / args.steps
+        gX = torch.empty((args.n, 3), dtype=torch.float64, device=dev)
         fmm.grad_src_xyz(Jt.reshape(args.rhs, args.n, 3), gA, out=gX)
-    torch.cuda.synchronize()
-    grad_s = (time.time() - t0) / args.steps
-    print("adjoint: %.1f ms/step, source gradient: %.1f ms/step" % (1e3 * adj_s, 1e3 * grad_s),
-          file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for _ in range(args.steps):
+            fmm.grad_src_xyz(Jt.reshape(args.rhs, args.n, 3), gA, out=gX)
+        torch.cuda.synchronize()
+        grad_s = (time.time() - t0) / args.steps
+        print("adjoint: %.1f ms/step, source gradient: %.1f ms/step" % (1e3 * adj_s, 1e3 * grad_s),
+              file=sys.stderr, flush=True)
 
     default_cfg = (args.n, args.p, args.p_free, args.rhs) == (1000000, 12, 20, 1)
     traffic = (K_M2L_TRAFFIC["fetch_bytes"] + K_M2L_TRAFFIC["write_bytes"]
-               if default_cfg and m2l_source_digest() == K_M2L_TRAFFIC["digest"] else None)
+               if default_cfg and m2l_source_digest() == K_M2L_TRAFFIC["digest"]
+               and abs(launches_per_step - K_M2L_TRAFFIC["launches_per_step"]) < 0.5 else None)
 
     acc = None
     if not args.no_accuracy:
@@ -237,10 +243,12 @@ def main():
         "build_s": build_s,
         "cold_targets_per_s": args.n * args.rhs / (build_s + wall / args.steps),
         "phase_ms_per_step": {a: b / max(1, ncalls) for a, b in phases.items()},
-        "adjoint": {"targets_per_s": args.n * args.rhs / adj_s, "ms_per_step": 1e3 * adj_s,
-                    "vs_forward": (wall / args.steps) / adj_s},
-        "grad_src_xyz": {"targets_per_s": args.n * args.rhs / grad_s, "ms_per_step": 1e3 * grad_s,
-                         "vs_forward": (wall / args.steps) / grad_s},
+        "adjoint": None if adj_s is None else {
+            "targets_per_s": args.n * args.rhs / adj_s, "ms_per_step": 1e3 * adj_s,
+            "vs_forward": (wall / args.steps) / adj_s},
+        "grad_src_xyz": None if grad_s is None else {
+            "targets_per_s": args.n * args.rhs / grad_s, "ms_per_step": 1e3 * grad_s,
+            "vs_forward": (wall / args.steps) / grad_s},
         "uneven_geometries": uneven,
     }
     print(json.dumps(out), flush=True)

@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "bessel_pq.h"
 #include "../../include/lmfmm.h"
 #include "kernels.h"
 #include "plan.h"
@@ -64,7 +65,8 @@ struct lm_ctx {
   int* d_s2t = nullptr;                    // S2T work items (target leaf, chunk)
   struct S2TRange {
     int inst, item0, n;
-    bool smallz;
+    bool smallz;  // |k_rho| rho <= 7.5 on Gamma_1: J0..J2 by their power series
+    int nser;     // terms of that series
   };
   std::vector<S2TRange> s2t_ranges;        // per reaction component with direct pairs
   double contour_a = 0;
@@ -424,6 +426,17 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
       r.item0 = it;
       r.n = j - it;
       r.smallz = a * pl.inst[inst].s2t_rho <= 7.5;
+      // series terms: the first omitted term (|z|/2)^{2n} / (n!)^2 below
+      // 1e-19 at the largest |z| = a rho_max (at most LM_BPQ_NSERC terms,
+      // enough for |z| = 7.5)
+      const double zh = 0.5 * a * pl.inst[inst].s2t_rho;
+      double term = 1.0;
+      r.nser = 1;
+      while (r.nser < LM_BPQ_NSERC) {
+        term *= zh * zh / ((double)r.nser * r.nser);
+        if (term < 1e-19) break;
+        r.nser++;
+      }
       ctx->s2t_ranges.push_back(r);
       it = j;
     }
@@ -851,7 +864,7 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
     if (!grad)
       for (auto& r : ctx->s2t_ranges)
         launch_s2t(d, ctx->md, ctx->d_s2t + 2 * r.item0, r.n, ctx->d_src, Jc, pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs,
-                   ctx->contour_a, r.smallz, Ac, s);
+                   ctx->contour_a, r.smallz, r.nser, Ac, s);
     mark(7);
   } else {
     for (int i = 2; i <= 7; i++) mark(i);

@@ -922,7 +922,7 @@ __device__ inline void bessel01_real(double x, double ix, double* j0v, double* j
     *j1v = -0.5 * x * d;
     return;
   }
-  const double* cp = c + LM_BPQ_NSER;
+  const double* cp = c + LM_BPQ_NSERC;
   const double* cq = cp + LM_BPQ_DEG + 1;
   const double t = LM_BPQ_X0 * ix, u = t * t;
   double P = cp[LM_BPQ_DEG], dP = 0.0, Qt = cq[LM_BPQ_DEG], dQt = 0.0;
@@ -943,6 +943,27 @@ __device__ inline void bessel01_real(double x, double ix, double* j0v, double* j
   *j0v = j0;
   // J1 = -J0' = J0 / (2x) + A ((Q - P') cos chi + (P + Q') sin chi)
   *j1v = 0.5 * ix * j0 + A * ((Q - dPx) * cs + (P + dQx) * sn);
+}
+
+// J0, J1, J2 of a complex argument by the power series S(w) = sum_k
+// (-w)^k / (k!)^2, w = z^2 / 4, with n terms: J0 = S, J1 = -J0' =
+// -(z/2) S'(w) and J2 = J0'' - J0'/z = w S''(w) (Bessel's equation), from one
+// pass of Horner's rule carrying both derivatives: no division, exact at
+// z = 0.  Coefficients as in bessel01_real (n <= LM_BPQ_NSERC).
+__device__ inline void bessel012_horner(cd z, int n, cd* j0, cd* j1, cd* j2) {
+  const cd w = 0.25 * (z * z);
+  int zo = 0;
+  asm volatile("" : "+s"(zo));
+  const double* c = c_bpq + zo;
+  cd v = cd{c[n - 1], 0.0}, d1 = cd{0, 0}, d2 = cd{0, 0};
+  for (int k = n - 2; k >= 0; k--) {
+    d2 = d2 * w + d1;
+    d1 = d1 * w + v;
+    v = cd{fma(v.x, w.x, fma_s(-v.y, w.y, c[k])), fma(v.x, w.y, v.y * w.x)};
+  }
+  *j0 = v;
+  *j1 = -0.5 * (z * d1);
+  *j2 = 2.0 * (w * d2);
 }
 
 __global__ void k_selftest_math(const double* x, long long n, double* out) {
@@ -1257,30 +1278,9 @@ void launch_p2p_grad(const DevPlan& d, const int* tboxes, int n, const double* s
 //   out- = W(0,s1) u-/2 - W(-2,s3) u+/2 + W(-1,s2) m_z
 //   out_z = W(1,s4) u-/2 + W(-1,s4) u+/2 + W(0,s5) m_z.
 // The nodes are Gamma_1 (complex k_rho) then the real tail in increasing
-// order; each pair stops at its own cut a + 45 / (t + u).  One block of
-// LM_S2T_CHUNK threads per work item (target leaf, chunk); each target is
-// owned by one thread and the launches go component by component, so the
-// accumulation into A is deterministic.
-// J_0, J_1, J_2 of complex z by their power series (|z| <= 8: terms stay
-// below 2e2, so about 14 digits survive the cancellation)
-__device__ inline void bessel012_series(cd z, cd* j0, cd* j1, cd* j2) {
-  cd h = 0.5 * z, w = -1.0 * (h * h);
-  cd t0 = cd{1, 0}, t1 = h, t2 = 0.5 * (h * h);
-  cd s0 = t0, s1 = t1, s2 = t2;
-  for (int k = 1; k <= 40; k++) {
-    t0 = c_rk2[k] * (t0 * w);
-    t1 = c_rkk1[k] * (t1 * w);
-    t2 = c_rkk2[k] * (t2 * w);
-    s0 = s0 + t0;
-    s1 = s1 + t1;
-    s2 = s2 + t2;
-    if (fabs(t0.x) + fabs(t0.y) + fabs(t1.x) + fabs(t1.y) < 1e-17 * (fabs(s0.x) + fabs(s0.y) + 1e-300)) break;
-  }
-  *j0 = s0;
-  *j1 = s1;
-  *j2 = s2;
-}
-
+// order; each pair stops at its own cut a + LM_S2T_DIGITS / (t + u).  Each
+// target is owned by one thread of one work item and the launches go
+// component by component, so the accumulation into A is deterministic.
 // One work item: a chunk of up to 64 targets of a reaction leaf against the
 // sources of all its near boxes, taken as one concatenated list (segments of
 // up to LM_S2T_SEG boxes).  Pair q = i ns + j (target i, source j of the
@@ -1293,7 +1293,8 @@ template <bool SMALLZ>
 __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md, const int* items,
                                                                      const double* sxyz, const cd* J,
                                                                      long long n_src, const double* txyz,
-                                                                     long long n_tgt, int n_rhs, double a, cd* A) {
+                                                                     long long n_tgt, int n_rhs, double a, int nser,
+                                                                     cd* A) {
   __shared__ double tp[LM_S2T_CHUNK][3];  // targets: x, y, t
   __shared__ int seg_pt0[LM_S2T_SEG], seg_cum[LM_S2T_SEG + 1];
   __shared__ cd res[LM_S2T_CHUNK][3];     // per pair of the round: out+, out-, out_z
@@ -1361,7 +1362,7 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
         if (tid < nc) {
           const QNode& nd = nodes[c0 + tid];
           nk[tid][0] = nd.kr;
-          nk[tid][1] = nd.w;
+          nk[tid][1] = nd.w * nd.kr;
           nk[tid][2] = nd.kzt;
           nk[tid][3] = nd.kzs;
           for (int f = 0; f < 5; f++) nk[tid][4 + f] = nd.F[f];
@@ -1372,11 +1373,15 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
           const cd kr = nk[m][0];
           if (kr.y != 0.0) {  // Gamma_1 (complex k_rho): every active pair
             if (!pa) continue;
-            cd ez = cd{0, 1} * (tz * nk[m][2] + uz * nk[m][3]);
-            cd base = nk[m][1] * kr * cexpd(ez);
+            // w k_rho exp(i (t k_z + u k_z')); the phase is small (|k_z| (t + u))
+            const cd ez = cd{0, 1} * (tz * nk[m][2] + uz * nk[m][3]);
+            double esn, ecs;
+            lm_sincos_red(ez.y, &esn, &ecs);
+            const double ea = exp(ez.x);
+            const cd base = nk[m][1] * cd{ea * ecs, ea * esn};
             cd jb[3];
             if (SMALLZ)
-              bessel012_series(rho * kr, jb, jb + 1, jb + 2);
+              bessel012_horner(rho * kr, nser, jb, jb + 1, jb + 2);
             else
               bessel_jq(2, rho * kr, jb);
             cd b0 = base * jb[0], b1 = base * jb[1], b2 = base * jb[2];
@@ -1388,7 +1393,7 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
           } else if (kr.x <= kcut) {
             // real tail: k_z = i |k_z|, Z = exp(-t |k_z| - u |k_z'|)
             double z = exp(-(tz * nk[m][2].y + uz * nk[m][3].y));
-            double base = nk[m][1].x * kr.x * z;
+            double base = nk[m][1].x * z;
             const double x = kr.x * rho, ix = nk[m][9].x * irho;
             double J0, J1;
             bessel01_real(x, ix, &J0, &J1);
@@ -1449,17 +1454,18 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
     Ap[2] = Ap[2] + f * oz;
   }
 }
-// smallz: |k_rho| rho <= 8 on Gamma_1 for every pair of the component
+// smallz: |k_rho| rho <= 7.5 on Gamma_1 for every pair of the component;
+// nser: terms of the complex series there (1..LM_BPQ_NSERC)
 void launch_s2t(const DevPlan& d, MediumDev md, const int* items, int n, const double* sxyz, const cd* J,
-                long long n_src, const double* txyz, long long n_tgt, int n_rhs, double a, bool smallz, cd* A,
-                hipStream_t s) {
+                long long n_src, const double* txyz, long long n_tgt, int n_rhs, double a, bool smallz, int nser,
+                cd* A, hipStream_t s) {
   if (n <= 0) return;
   if (smallz)
     hipLaunchKernelGGL(k_s2t<true>, dim3(n, n_rhs), dim3(LM_S2T_CHUNK), 0, s, d, md, items, sxyz, J, n_src, txyz,
-                       n_tgt, n_rhs, a, A);
+                       n_tgt, n_rhs, a, nser, A);
   else
     hipLaunchKernelGGL(k_s2t<false>, dim3(n, n_rhs), dim3(LM_S2T_CHUNK), 0, s, d, md, items, sxyz, J, n_src, txyz,
-                       n_tgt, n_rhs, a, A);
+                       n_tgt, n_rhs, a, nser, A);
 }
 
 // ------------------------------------------------------------------ translation tables

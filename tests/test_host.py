@@ -207,10 +207,34 @@ def test_real_bessel_coefficient_table():
     h = open(os.path.join(csrc, "bessel_pq.h")).read()
     assert int(re.search(r"#define LM_BPQ_NSER (\d+)", h).group(1)) == g.NSER
     assert int(re.search(r"#define LM_BPQ_DEG (\d+)", h).group(1)) == g.DEG
+    assert int(re.search(r"#define LM_BPQ_NSERC (\d+)", h).group(1)) == g.NSERC
     c = [float(v) for v in re.findall(r"^\s+([-0-9.e+]+),", h, re.M)]
-    assert len(c) == g.NSER + 2 * (g.DEG + 1)
-    cs, cp, cq = c[:g.NSER], c[g.NSER:g.NSER + g.DEG + 1], c[g.NSER + g.DEG + 1:]
+    assert len(c) == g.NSERC + 2 * (g.DEG + 1)
+    cs, cp, cq = c[:g.NSER], c[g.NSERC:g.NSERC + g.DEG + 1], c[g.NSERC + g.DEG + 1:]
     x = np.concatenate([np.linspace(0.0, 12.0, 2401), np.linspace(12.0, 400.0, 2001), [1e-12, 6.0 - 1e-12, 6.0]])
     j = np.array([g.j01(cs, cp, cq, float(v)) for v in x])
     assert np.abs(j[:, 0] - special.j0(x)).max() < 1e-14
     assert np.abs(j[:, 1] - special.j1(x)).max() < 1e-14
+
+    # the complex series of the Gamma_1 nodes: J0 = S(w), J1 = -(z/2) S'(w),
+    # J2 = w S''(w), w = z^2/4, with the term count the library picks for
+    # the largest |z| of a component
+    rng = np.random.default_rng(3)
+    for zmax in (0.3, 1.5, 4.0, 7.5):
+        n, term, zh = 1, 1.0, 0.5 * zmax
+        while n < g.NSERC:
+            term *= zh * zh / (n * n)
+            if term < 1e-19:
+                break
+            n += 1
+        z = zmax * np.sqrt(rng.uniform(0, 1, 200)) * np.exp(1j * rng.uniform(0, 2 * np.pi, 200))
+        z = np.concatenate([z, [0.0, zmax, 1j * zmax]])
+        w = 0.25 * z * z
+        v = np.full_like(z, c[n - 1]); d1 = np.zeros_like(z); d2 = np.zeros_like(z)
+        for kk in range(n - 2, -1, -1):
+            d2 = d2 * w + d1
+            d1 = d1 * w + v
+            v = v * w + c[kk]
+        scale = np.exp(np.abs(z.imag))
+        for val, order in ((v, 0), (-0.5 * z * d1, 1), (2.0 * w * d2, 2)):
+            assert (np.abs(val - sp.jv(order, z)) / scale).max() < 2e-14, (zmax, order)
