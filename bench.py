@@ -162,6 +162,7 @@ def main():
     wall = time.time() - t0
     phases, ncalls = fmm.timings()
     gemm_ms_total, gemm_launches = fmm.m2l_gemm_timing()
+    m2l_var, m2l_ms = fmm.m2l_variants(args.rhs)
     fmm.set_timing(False)
     ms_per_step = 1000.0 * wall / args.steps
     value = args.n * args.rhs / (wall / args.steps)
@@ -250,6 +251,9 @@ def main():
             "targets_per_s": args.n * args.rhs / grad_s, "ms_per_step": 1e3 * grad_s,
             "vs_forward": (wall / args.steps) / grad_s},
         "uneven_geometries": uneven,
+        "m2l_autotune": {"chosen_variant_per_launch": m2l_var,
+                         "tuning_ms_per_step_by_variant": [round(float(v), 3) for v in m2l_ms.sum(axis=0)],
+                         "tuning_ms_per_step_chosen": round(float(sum(m2l_ms[i, v] for i, v in enumerate(m2l_var))), 3)},
     }
     print(json.dumps(out), flush=True)
 

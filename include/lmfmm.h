@@ -82,10 +82,18 @@ typedef struct {
                       /* Leaves that stay adjacent interact directly through the  */
                       /* component's Sommerfeld integral (S2T, Sec. 3.3/3.4).     */
                       /* Source-position gradients use a second plan with 0.      */
+  int m2l_variant;    /* tile shape of the M2L GEMM kernel: -1 (default) tunes each */
+                      /* launch of the schedule on its first eager evaluation and  */
+                      /* keeps the fastest; 0..LM_M2L_VARIANTS-1 fixes one (0: 16  */
+                      /* values of k per LDS chunk, 3 blocks per CU; 1: 32 values,  */
+                      /* 2 blocks; 2: 16 values double-buffered, 2 blocks).  All   */
+                      /* variants give bitwise equal results.                      */
 } lm_params;
 
+#define LM_M2L_VARIANTS 3
+
 /* Fills *prm with the defaults (p = 12, p_free = p, automatic depths, m2l_adapt = 1,
- * m2l_margin = 3, react_s2t = 1). */
+ * m2l_margin = 3, react_s2t = 1, m2l_variant = -1). */
 int lm_default_params(lm_params* prm);
 
 /* Creates a context bound to HIP device `hip_device`.  *out is owned by the
@@ -191,6 +199,14 @@ int lm_timings(lm_ctx* ctx, double* out_host, int n);
 #define LM_TIMING_M2L_GEMM_MS (LM_PHASES + 1)
 #define LM_TIMING_M2L_GEMM_LAUNCHES (LM_PHASES + 2)
 #define LM_TIMINGS_COUNT (LM_PHASES + 3)
+
+/* The M2L GEMM variant of each launch of the evaluation schedule for n_rhs
+ * right-hand sides (one launch per chunk, in evaluation order).  HOST arrays:
+ * variant_host [cap] receives the chosen variant (-1: not tuned yet),
+ * ms_host [cap * LM_M2L_VARIANTS] the autotuner's time of each variant in
+ * milliseconds (negative: not measured).  Returns the number of launches
+ * (0 when no evaluation with n_rhs has run yet) or a negative error. */
+int lm_m2l_variants(const lm_ctx* ctx, int n_rhs, int* variant_host, double* ms_host, int cap);
 
 /* Statistics of the current build (host array of n doubles, indices below). */
 int lm_stats(const lm_ctx* ctx, double* out_host, int n);

@@ -22,6 +22,7 @@ struct lm_ctx {
   Medium med;
   bool layers_set = false;
   PlanParams prm;
+  int m2l_variant = -1;       // M2L GEMM variant: -1 autotune per launch, else fixed
   Plan plan;
   bool built = false;
   DevPlan d;
@@ -39,6 +40,8 @@ struct lm_ctx {
   long long me_cap = 0, le_cap = 0;
   struct Chunk {
     int tile0, ntile, bt0, nbt;
+    int variant = -1;                  // M2L GEMM variant chosen by the autotuner
+    double ms[LM_M2L_VARIANTS] = {-1, -1, -1};  // its measurements (ms; < 0: none)
   };
   struct TileSet {            // M2L schedule for one right-hand-side count
     M2LTile* d_tiles = nullptr;
@@ -175,6 +178,7 @@ int lm_default_params(lm_params* prm) {
   prm->m2l_adapt = 1;
   prm->m2l_margin = 3.0;
   prm->react_s2t = 1;
+  prm->m2l_variant = -1;
   return LM_OK;
 }
 
@@ -240,6 +244,8 @@ int lm_set_params(lm_ctx* ctx, const lm_params* p) {
   if (p->m2l_adapt && !(p->m2l_margin >= 0 && p->m2l_margin <= 30))
     return fail(ctx, LM_EINVAL, "m2l_margin out of range (0..30 decades)");
   if (p->react_s2t < 0 || p->react_s2t > 2) return fail(ctx, LM_EINVAL, "react_s2t must be 0, 1 or 2");
+  if (p->m2l_variant < -1 || p->m2l_variant >= LM_M2L_VARIANTS)
+    return fail(ctx, LM_EINVAL, "m2l_variant must be -1 (autotune) or 0.." + std::to_string(LM_M2L_VARIANTS - 1));
   PlanParams q;
   q.p = p->p;
   q.p_free = p->p_free;
@@ -253,6 +259,7 @@ int lm_set_params(lm_ctx* ctx, const lm_params* p) {
   q.m2l_margin = p->m2l_margin;
   q.react_s2t = p->react_s2t;
   ctx->prm = q;
+  ctx->m2l_variant = p->m2l_variant;
   if (ctx->built) {
     hipSetDevice(ctx->device);
     free_build(ctx);
@@ -682,6 +689,7 @@ static int swapped_ctx(lm_ctx* ctx, hipStream_t s, lm_ctx** out) {
     a->med = ctx->med;
     a->layers_set = true;
     a->prm = ctx->prm;
+    a->m2l_variant = ctx->m2l_variant;
     int ng = (int)ctx->host_soff.size() - 1;
     rc = build_common(a, ng, ctx->host_toff.data(), ctx->host_tgt.data(), ctx->host_soff.data(),
                       ctx->host_src.data(), s);
@@ -711,6 +719,7 @@ static int grad_ctx(lm_ctx* ctx, hipStream_t s, lm_ctx** out) {
     a->med = ctx->med;
     a->layers_set = true;
     a->prm = ctx->prm;
+    a->m2l_variant = ctx->m2l_variant;
     a->prm.react_s2t = 0;
     int ng = (int)ctx->host_soff.size() - 1;
     rc = build_common(a, ng, ctx->host_toff.data(), ctx->host_tgt.data(), ctx->host_soff.data(),
@@ -723,6 +732,44 @@ static int grad_ctx(lm_ctx* ctx, hipStream_t s, lm_ctx** out) {
     ctx->gctx = a;
   }
   *out = ctx->gctx;
+  return LM_OK;
+}
+
+// Autotuner of the M2L GEMM (tile-shape variants of k_m2l, bitwise equal
+// results): the first time a launch of the schedule runs outside graph
+// capture, each variant is run twice on the real operands and timed with
+// events on the evaluation stream (the second run counts, the first absorbs
+// code loading); the fastest is kept for that launch.  Every run writes the
+// same scratch vectors, so the evaluation continues with valid data.  Under
+// capture nothing is timed and variant 0 is used until a later eager call.
+static int tune_m2l(lm_ctx* ctx, lm_ctx::Chunk& ch, int n_rhs, hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIPC(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone) return LM_OK;
+  hipEvent_t e0, e1;
+  HIPC(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(ctx, LM_EHIP, "hipEventCreate failed");
+  }
+  int rc = LM_OK;
+  int best = 0;
+  for (int v = 0; v < LM_M2L_VARIANTS && rc == LM_OK; v++) {
+    float ms = 0;
+    for (int rep = 0; rep < 2 && rc == LM_OK; rep++) {
+      if (hipEventRecord(e0, s) != hipSuccess) rc = LM_EHIP;
+      launch_m2l(ctx->d, ctx->d.tiles + ch.tile0, ch.ntile, n_rhs, ctx->ME, ctx->Y, ctx->pmax, v, s);
+      if (rc == LM_OK && (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
+                          hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = LM_EHIP;
+    }
+    ch.ms[v] = ms;
+    if (rc == LM_OK && ch.ms[v] < ch.ms[best]) best = v;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return fail(ctx, rc, "M2L autotuning: a HIP call failed");
+  ch.variant = best;
   return LM_OK;
 }
 
@@ -833,9 +880,14 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
       launch_m2m(d, ctx->d_m2m[l], ctx->n_m2m[l], n_rhs, ctx->ME, ctx->pmax, s);
     mark(3);
     for (int c = 0; c < nch; c++) {
-      const lm_ctx::Chunk& ch = ctx->tilesets[n_rhs].chunks[c];
+      lm_ctx::Chunk& ch = ctx->tilesets[n_rhs].chunks[c];
+      int v = ctx->m2l_variant >= 0 ? ctx->m2l_variant : ch.variant;
+      if (v < 0) {
+        if ((rc = tune_m2l(ctx, ch, n_rhs, s))) return rc;
+        v = ch.variant >= 0 ? ch.variant : 0;
+      }
       mark(LM_PHASES + 1 + 2 * c);
-      launch_m2l(d, d.tiles + ch.tile0, ch.ntile, n_rhs, ctx->ME, ctx->Y, ctx->pmax, s);
+      launch_m2l(d, d.tiles + ch.tile0, ch.ntile, n_rhs, ctx->ME, ctx->Y, ctx->pmax, v, s);
       mark(LM_PHASES + 2 + 2 * c);
       launch_m2l_reduce(d, ch.bt0, ch.nbt, n_rhs, ctx->Y, ctx->LE, ctx->pmax, s);
     }
@@ -905,6 +957,18 @@ int lm_timings(lm_ctx* ctx, double* out, int n) {
   int m = n < LM_TIMINGS_COUNT ? n : LM_TIMINGS_COUNT;
   memcpy(out, acc, m * sizeof(double));
   return LM_OK;
+}
+
+int lm_m2l_variants(const lm_ctx* ctx, int n_rhs, int* variant_host, double* ms_host, int cap) {
+  if (!ctx || cap < 0 || (cap > 0 && (!variant_host || !ms_host))) return LM_EINVAL;
+  auto it = ctx->tilesets.find(n_rhs);
+  if (it == ctx->tilesets.end()) return 0;
+  const std::vector<lm_ctx::Chunk>& ch = it->second.chunks;
+  for (int c = 0; c < (int)ch.size() && c < cap; c++) {
+    variant_host[c] = ch[c].variant;
+    for (int v = 0; v < LM_M2L_VARIANTS; v++) ms_host[(size_t)c * LM_M2L_VARIANTS + v] = ch[c].ms[v];
+  }
+  return (int)ch.size();
 }
 
 int lm_stats(const lm_ctx* ctx, double* out, int n) {

@@ -1,5 +1,6 @@
 // kernels.h -- host-side launchers of the HIP kernels.
 #pragma once
+#include "../../include/lmfmm.h"
 #include "lmfmm_internal.h"
 
 struct MediumDev {
@@ -57,8 +58,9 @@ void launch_tab_assemble(const DevPlan& d, int case0, int ncase, int p, int kmax
 void launch_p2m(const DevPlan& d, const int* leaves, int n, const double* xyz, const cd* J,
                 long long n_src, int n_rhs, cd* ME, int pl, hipStream_t s);
 void launch_m2m(const DevPlan& d, const int* parents, int n, int n_rhs, cd* ME, int pmax, hipStream_t s);
+// tile-shape variants of the M2L GEMM kernel (LM_M2L_VARIANTS of the C ABI)
 void launch_m2l(const DevPlan& d, const M2LTile* tiles, int n_tiles, int n_rhs, const cd* ME, cd* Y, int pmax,
-                hipStream_t s);
+                int variant, hipStream_t s);
 void launch_m2l_reduce(const DevPlan& d, int bt0, int nbt, int n_rhs, const cd* Y, cd* LE, int pmax,
                        hipStream_t s);
 void launch_l2l(const DevPlan& d, const int* children, int n, int n_rhs, cd* LE, int pmax, hipStream_t s);

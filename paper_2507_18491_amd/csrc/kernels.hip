@@ -319,8 +319,6 @@ void launch_l2l(const DevPlan& d, const int* children, int n, int n_rhs, cd* LE,
 // adds, per target, its pairs in a fixed order (no atomics).
 #define TM 64
 #define TN 64
-#define KC 16
-#define LDS_LD (KC + 1)    // row pitch (doubles) of the LDS operand planes
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // Shared state of one M2L tile (read by all waves of the block).
@@ -333,12 +331,14 @@ struct M2LTileCtx {
   bool phased;
 };
 
-// Operand planes are row-major, [row or column][k], pitch KC + 1 doubles:
-// the 16 threads that store one row's KC values write consecutive words,
-// and the MFMA operand reads (16 lanes on 16 rows, 4 groups of lanes on 4
-// consecutive k) fall on distinct banks.
+// Operand planes are row-major, [row or column][k], pitch KCV + 1 doubles
+// (KCV values of k per chunk, NB chunk buffers): the threads that store one
+// row's KCV values write consecutive words, and the MFMA operand reads (16
+// lanes on 16 rows, 4 groups of lanes on 4 consecutive k) fall on distinct
+// banks (the pitch is odd in doubles).
+template <int KCV, int NB>
 struct M2LLds {
-  double Ar[TM][LDS_LD], Ai[TM][LDS_LD], Br[TN][LDS_LD], Bi[TN][LDS_LD];
+  double Ar[NB][TM][KCV + 1], Ai[NB][TM][KCV + 1], Br[NB][TN][KCV + 1], Bi[NB][TN][KCV + 1];
   long long sbase[TN];
   cd eph[2 * LM_PMAX + 8];
   short mu_of[(LM_PMAX + 1) * (LM_PMAX + 1)];
@@ -368,8 +368,13 @@ __device__ inline int m2l_rkap(bool phased, int ot, int bl) {
 // B_re, P2 = sum A_im B_im, P3 = sum (A_re + A_im)(B_re + B_im); then C_re =
 // P1 - P2 and C_im = P3 - P1 - P2.  The accumulator chains are interleaved
 // so that no MFMA waits on the one issued just before it.
-template <int NI, int NJ>
-__device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds& L, int tid, int wr, int wc) {
+// Tile-shape variants (the same sums in the same order, so bitwise equal
+// results): KCV values of k per LDS chunk; NB = 1 stages a chunk, waits,
+// multiplies and waits again; NB = 2 loads the next chunk into registers
+// while the current one is multiplied and stores it into the other buffer
+// (one barrier per chunk).
+template <int KCV, int NB, int NI, int NJ>
+__device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds<KCV, NB>& L, int tid, int wr, int wc) {
   constexpr int NIx = NI > 0 ? NI : 1, NJx = NJ > 0 ? NJ : 1;
   v4d p1[NIx][NJx], p2[NIx][NJx], p3[NIx][NJx];
 #pragma unroll
@@ -381,26 +386,28 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds& L, int tid
       p3[i][j] = p1[i][j];
     }
   const int lane = tid & 63;
-  constexpr int NA = TM * KC / NT, NB = KC * TN / NT;
-  // fixed roles of this thread in the chunk loads: k offset kk, and rows
-  // (matrix) / columns (source vectors) r16 + 16 it; indices outside the
-  // tile are clamped to a valid entry and the value zeroed
-  const int kk = tid & (KC - 1), r16 = tid / KC;
-  long long aoff[NA], boff[NB];
-  bool aok[NA], bok[NB];
+  // rows (matrix) / columns (source vectors) staged per pass of the block
+  constexpr int RPI = NT / KCV;
+  constexpr int NA = TM / RPI, NB_ = TN / RPI;
+  // fixed roles of this thread in the chunk loads: k offset kk, and rows /
+  // columns r16 + RPI it; indices outside the tile are clamped to a valid
+  // entry and the value zeroed
+  const int kk = tid & (KCV - 1), r16 = tid / KCV;
+  long long aoff[NA], boff[NB_];
+  bool aok[NA], bok[NB_];
 #pragma unroll
   for (int it = 0; it < NA; it++) {
-    int row = c.row0 + r16 + 16 * it;
+    int row = c.row0 + r16 + RPI * it;
     aok[it] = row < c.Po;
     aoff[it] = (long long)(aok[it] ? row : c.Po - 1) * c.Kf;
   }
 #pragma unroll
-  for (int it = 0; it < NB; it++) {
-    long long sb = L.sbase[r16 + 16 * it];
+  for (int it = 0; it < NB_; it++) {
+    long long sb = L.sbase[r16 + RPI * it];
     bok[it] = sb >= 0;
     boff[it] = sb >= 0 ? sb : L.sbase[0];
   }
-  cd ra[NA], rb[NB];
+  cd ra[NA], rb[NB_];
   auto load = [&](int k0) {
     const int k = k0 + kk;
     const bool kok = k < c.K;
@@ -415,14 +422,14 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds& L, int tid
       ra[it] = (aok[it] && kok) ? v : cd{0, 0};
     }
 #pragma unroll
-    for (int it = 0; it < NB; it++) {
+    for (int it = 0; it < NB_; it++) {
       cd v = c.ME[boff[it] + colB];
       rb[it] = (bok[it] && kok) ? v : cd{0, 0};
     }
   };
-  // registers -> LDS planes; source values times the offset's phase
-  // e^{i (kappa + mu) phi}, which depends on k only
-  auto store = [&](int k0) {
+  // registers -> LDS planes of buffer bf; source values times the offset's
+  // phase e^{i (kappa + mu) phi}, which depends on k only
+  auto store = [&](int k0, int bf) {
     cd ph = cd{1, 0};
     if (c.phased) {
       const int k = k0 + kk;
@@ -432,35 +439,32 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds& L, int tid
     }
 #pragma unroll
     for (int it = 0; it < NA; it++) {
-      L.Ar[r16 + 16 * it][kk] = ra[it].x;
-      L.Ai[r16 + 16 * it][kk] = ra[it].y;
+      L.Ar[bf][r16 + RPI * it][kk] = ra[it].x;
+      L.Ai[bf][r16 + RPI * it][kk] = ra[it].y;
     }
 #pragma unroll
-    for (int it = 0; it < NB; it++) {
+    for (int it = 0; it < NB_; it++) {
       cd v = c.phased ? rb[it] * ph : rb[it];
-      L.Br[r16 + 16 * it][kk] = v.x;
-      L.Bi[r16 + 16 * it][kk] = v.y;
+      L.Br[bf][r16 + RPI * it][kk] = v.x;
+      L.Bi[bf][r16 + RPI * it][kk] = v.y;
     }
   };
-  for (int k0 = 0; k0 < c.K; k0 += KC) {
-    load(k0);
-    store(k0);
-    __syncthreads();
+  auto mma = [&](int bf) {
     if (NI > 0 && NJ > 0) {
 #pragma unroll
-      for (int k4 = 0; k4 < KC; k4 += 4) {
+      for (int k4 = 0; k4 < KCV; k4 += 4) {
         const int kr = k4 + (lane >> 4), li = lane & 15;
         double a_r[NIx], a_i[NIx], a_s[NIx], b_r[NJx], b_i[NJx], b_s[NJx];
 #pragma unroll
         for (int i = 0; i < NIx; i++) {
-          a_r[i] = L.Ar[wr * 32 + i * 16 + li][kr];
-          a_i[i] = L.Ai[wr * 32 + i * 16 + li][kr];
+          a_r[i] = L.Ar[bf][wr * 32 + i * 16 + li][kr];
+          a_i[i] = L.Ai[bf][wr * 32 + i * 16 + li][kr];
           a_s[i] = a_r[i] + a_i[i];
         }
 #pragma unroll
         for (int j = 0; j < NJx; j++) {
-          b_r[j] = L.Br[wc * 32 + j * 16 + li][kr];
-          b_i[j] = L.Bi[wc * 32 + j * 16 + li][kr];
+          b_r[j] = L.Br[bf][wc * 32 + j * 16 + li][kr];
+          b_i[j] = L.Bi[bf][wc * 32 + j * 16 + li][kr];
           b_s[j] = b_r[j] + b_i[j];
         }
 #pragma unroll
@@ -477,7 +481,30 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds& L, int tid
           for (int j = 0; j < NJx; j++) p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_s[i], b_s[j], p3[i][j], 0, 0, 0);
       }
     }
+  };
+  if (NB == 1) {
+    for (int k0 = 0; k0 < c.K; k0 += KCV) {
+      load(k0);
+      store(k0, 0);
+      __syncthreads();
+      mma(0);
+      __syncthreads();
+    }
+  } else {
+    // chunk k0 is in buffer (k0 / KCV) & 1; the loads of the next chunk are
+    // in flight during this chunk's MFMAs, and its stores go to the buffer
+    // that every wave finished reading before the previous barrier
+    load(0);
+    store(0, 0);
     __syncthreads();
+    for (int k0 = 0; k0 < c.K; k0 += KCV) {
+      const int bf = (k0 / KCV) & 1;
+      const bool more = k0 + KCV < c.K;
+      if (more) load(k0 + KCV);
+      mma(bf);
+      if (more) store(k0 + KCV, bf ^ 1);
+      __syncthreads();
+    }
   }
   if (NI == 0 || NJ == 0) return;
   // epilogue: lane holds rows 4 r + lane / 16 of each 16 x 16 tile, column
@@ -510,14 +537,15 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds& L, int tid
 // those of its four 16 x 16 MFMA tiles that hold rows below the offset's
 // (pord+1)^2 and columns below the tile's pair count, so partial tiles cost
 // little; the choice is made once per tile from a wave-uniform value.
-// Operands are staged through LDS as separate real / imaginary planes, KC
-// values of k at a time; three resident blocks per CU overlap one block's
-// global loads with the others' MFMAs.  Consecutive tiles are sent to one XCD (blocks
-// are dealt round-robin over the 8 XCDs), so the tiles sharing one offset's
-// matrix and source vectors run against one L2.
-__global__ __launch_bounds__(NT, 3) void k_m2l(DevPlan d, const M2LTile* tiles, int n_tiles, int n_rhs,
-                                           const cd* ME, cd* Y) {
-  __shared__ M2LLds L;
+// Operands are staged through LDS as separate real / imaginary planes, KCV
+// values of k at a time (variants above); resident blocks overlap one
+// block's global loads with the others' MFMAs.  Consecutive tiles are sent
+// to one XCD (blocks are dealt round-robin over the 8 XCDs), so the tiles
+// sharing one offset's matrix and source vectors run against one L2.
+template <int KCV, int NB, int OCC>
+__global__ __launch_bounds__(NT, OCC) void k_m2l(DevPlan d, const M2LTile* tiles, int n_tiles, int n_rhs,
+                                                 const cd* ME, cd* Y) {
+  __shared__ M2LLds<KCV, NB> L;
   const int per_xcd = (n_tiles + 7) >> 3;
   const int t_id = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
   if (t_id >= n_tiles) return;
@@ -572,18 +600,25 @@ __global__ __launch_bounds__(NT, 3) void k_m2l(DevPlan d, const M2LTile* tiles, 
   const int nj = (wc * 32 < c.ncol) + (wc * 32 + 16 < c.ncol);
   const int pat = __builtin_amdgcn_readfirstlane(ni * 3 + nj);
   switch (pat) {
-    case 4: m2l_wave<1, 1>(c, L, tid, wr, wc); break;
-    case 5: m2l_wave<1, 2>(c, L, tid, wr, wc); break;
-    case 7: m2l_wave<2, 1>(c, L, tid, wr, wc); break;
-    case 8: m2l_wave<2, 2>(c, L, tid, wr, wc); break;
-    default: m2l_wave<0, 0>(c, L, tid, wr, wc); break;
+    case 4: m2l_wave<KCV, NB, 1, 1>(c, L, tid, wr, wc); break;
+    case 5: m2l_wave<KCV, NB, 1, 2>(c, L, tid, wr, wc); break;
+    case 7: m2l_wave<KCV, NB, 2, 1>(c, L, tid, wr, wc); break;
+    case 8: m2l_wave<KCV, NB, 2, 2>(c, L, tid, wr, wc); break;
+    default: m2l_wave<KCV, NB, 0, 0>(c, L, tid, wr, wc); break;
   }
 }
+// variant: 0 = 16 values of k per chunk, one buffer, three blocks per CU;
+// 1 = 32 values, one buffer, two blocks; 2 = 16 values, two buffers, two
+// blocks (LM_M2L_VARIANTS variants, bitwise equal results)
 void launch_m2l(const DevPlan& d, const M2LTile* tiles, int n_tiles, int n_rhs, const cd* ME, cd* Y, int pmax,
-                hipStream_t s) {
+                int variant, hipStream_t s) {
   if (n_tiles <= 0) return;
   int grid = ((n_tiles + 7) / 8) * 8;
-  hipLaunchKernelGGL(k_m2l, dim3(grid), dim3(NT), 0, s, d, tiles, n_tiles, n_rhs, ME, Y);
+  switch (variant) {
+    case 1: hipLaunchKernelGGL((k_m2l<32, 1, 2>), dim3(grid), dim3(NT), 0, s, d, tiles, n_tiles, n_rhs, ME, Y); break;
+    case 2: hipLaunchKernelGGL((k_m2l<16, 2, 2>), dim3(grid), dim3(NT), 0, s, d, tiles, n_tiles, n_rhs, ME, Y); break;
+    default: hipLaunchKernelGGL((k_m2l<16, 1, 3>), dim3(grid), dim3(NT), 0, s, d, tiles, n_tiles, n_rhs, ME, Y); break;
+  }
 }
 
 // LE_t[out][rhs] += sum over the target's pairs (fixed offset order) of Y

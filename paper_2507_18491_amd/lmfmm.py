@@ -28,7 +28,10 @@ class lm_params(ctypes.Structure):
                 ("max_depth", ctypes.c_int), ("gamma1_panels", ctypes.c_int),
                 ("contour_a", ctypes.c_double), ("tail_digits", ctypes.c_double),
                 ("components", ctypes.c_int), ("m2l_adapt", ctypes.c_int),
-                ("m2l_margin", ctypes.c_double), ("react_s2t", ctypes.c_int)]
+                ("m2l_margin", ctypes.c_double), ("react_s2t", ctypes.c_int),
+                ("m2l_variant", ctypes.c_int)]
+
+M2L_VARIANTS = 3
 
 
 _lib = None
@@ -59,6 +62,7 @@ def load_library():
     lib.lm_evaluate_adjoint.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     lib.lm_grad_src_xyz.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     lib.lm_stats.argtypes = [vp, D, ctypes.c_int]
+    lib.lm_m2l_variants.argtypes = [vp, ctypes.c_int, P(ctypes.c_int), D, ctypes.c_int]
     lib.lm_set_timing.argtypes = [vp, ctypes.c_int]
     lib.lm_timings.argtypes = [vp, D, ctypes.c_int]
     lib.lm_host_components.argtypes = [ctypes.c_int, D, D, P(ctypes.c_int), ctypes.c_int]
@@ -222,6 +226,19 @@ class LayeredDyadicFMM:
         buf = np.zeros(len(STAT_NAMES))
         self._check(self.lib.lm_stats(self.ctx, _dp(buf), buf.size))
         return dict(zip(STAT_NAMES, buf.tolist()))
+
+    def m2l_variants(self, n_rhs=1):
+        """(variant, ms) for each M2L GEMM launch of the n_rhs schedule: the
+        variant the autotuner chose (-1: not tuned yet) and its timings of the
+        M2L_VARIANTS variants in ms (negative: not measured)."""
+        cap = 4096
+        var = (ctypes.c_int * cap)()
+        ms = np.zeros(cap * M2L_VARIANTS)
+        n = self.lib.lm_m2l_variants(self.ctx, n_rhs, var, _dp(ms), cap)
+        if n < 0:
+            self._check(n)
+        n = min(n, cap)
+        return [int(var[i]) for i in range(n)], ms[:n * M2L_VARIANTS].reshape(n, M2L_VARIANTS)
 
     def set_timing(self, enable=True):
         self._check(self.lib.lm_set_timing(self.ctx, 1 if enable else 0))
