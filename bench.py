@@ -32,8 +32,8 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 fp64 FMA/clk x 2 flop x 2.4 GHz (fp
 # for the kernel source it was measured on (digest of the M2L section of
 # kernels.hip) and the same launches per step (the plan's split of the M2L
 # work); otherwise reported as null.
-K_M2L_TRAFFIC = {"digest": "ab3c394a52a316dc", "launches_per_step": 8,
-                 "fetch_bytes": 1.7698e7 * 1024 * 2.0, "write_bytes": 5.4396e6 * 1024 * 1.0}
+K_M2L_TRAFFIC = {"digest": "d399e554001bfd19", "launches_per_step": 8,
+                 "fetch_bytes": 1.7669e7 * 1024 * 2.0, "write_bytes": 5.4397e6 * 1024 * 1.0}
 
 
 def m2l_source_digest():
