@@ -135,6 +135,7 @@ class LayeredDyadicFMM:
         self._check(self.lib.lm_build(self.ctx, src.shape[0], _dp(src), tgt.shape[0], _dp(tgt),
                                       ctypes.c_void_p(stream)))
         self.n_src, self.n_tgt = src.shape[0], tgt.shape[0]
+        self._src_host, self._src_dev = src, None
         return self
 
     def build_batch(self, srcs, tgts=None, stream=None):
@@ -161,6 +162,7 @@ class LayeredDyadicFMM:
                                             to.ctypes.data_as(i64), _dp(tgt), ctypes.c_void_p(stream)))
         self.n_src, self.n_tgt = int(so[-1]), int(to[-1])
         self.src_off, self.tgt_off = so, to
+        self._src_host, self._src_dev = src, None
         return self
 
     def evaluate(self, J, out=None, stream=None):
@@ -227,6 +229,41 @@ class LayeredDyadicFMM:
         self._check(self.lib.lm_stats(self.ctx, _dp(buf), buf.size))
         return dict(zip(STAT_NAMES, buf.tolist()))
 
+    def source_positions(self, requires_grad=False):
+        """The source positions of the build as a new float64 CUDA tensor
+        [n_src, 3] (a leaf; with requires_grad=True, pass it to apply() to get
+        the gradient of a loss with respect to the source positions)."""
+        import torch
+        if self.n_src is None:
+            raise LMError("build() must be called first")
+        X = torch.tensor(self._src_host, dtype=torch.float64, device="cuda:%d" % self.device)
+        return X.requires_grad_(requires_grad)
+
+    def apply(self, J, X=None):
+        """A = G J as a differentiable torch operation (torch.autograd.Function):
+        the backward pass gives dL/dJ = G^H dL/dA (lm_evaluate_adjoint, the
+        transposed FMM by reciprocity, its upward pass recomputed) and, when X
+        is given, dL/dX for the source positions (lm_grad_src_xyz).  The
+        positions are fixed by the build: X must hold exactly the built source
+        positions (e.g. source_positions(requires_grad=True)) and only carries
+        their gradient.  J: complex128 CUDA tensor [n_src, 3] or
+        [n_rhs, n_src, 3]."""
+        import torch
+        if self.n_src is None:
+            raise LMError("build() must be called first")
+        if X is not None:
+            if X.dtype != torch.float64 or tuple(X.shape) != (self.n_src, 3):
+                raise LMError("X must be a float64 tensor [n_src, 3]")
+            if X.is_cuda:
+                if self._src_dev is None or self._src_dev.device != X.device:
+                    self._src_dev = torch.tensor(self._src_host, dtype=torch.float64, device=X.device)
+                same = torch.equal(X.detach(), self._src_dev)
+            else:
+                same = np.array_equal(X.detach().numpy(), self._src_host)
+            if not same:
+                raise LMError("X differs from the source positions of the build (rebuild for new positions)")
+        return _fmm_function().apply(self, J, X)
+
     def m2l_variants(self, n_rhs=1):
         """(variant, ms) for each M2L GEMM launch of the n_rhs schedule: the
         variant the autotuner chose (-1: not tuned yet) and its timings of the
@@ -269,6 +306,40 @@ class LayeredDyadicFMM:
             self.close()
         except Exception:
             pass
+
+
+_FMM_FUNCTION = None
+
+
+def _fmm_function():
+    """The torch.autograd.Function behind LayeredDyadicFMM.apply (created on
+    first use, so that importing this module does not import torch)."""
+    global _FMM_FUNCTION
+    if _FMM_FUNCTION is None:
+        import torch
+
+        class FMMApply(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, fmm, J, X):
+                ctx.fmm = fmm
+                ctx.x_on_cpu = X is not None and not X.is_cuda
+                ctx.save_for_backward(J)
+                return fmm.evaluate(J)
+
+            @staticmethod
+            def backward(ctx, gA):
+                (J,) = ctx.saved_tensors
+                gA = gA.contiguous()
+                gJ = ctx.fmm.evaluate_adjoint(gA) if ctx.needs_input_grad[1] else None
+                gX = None
+                if ctx.needs_input_grad[2]:
+                    gX = ctx.fmm.grad_src_xyz(J.detach(), gA)
+                    if ctx.x_on_cpu:
+                        gX = gX.cpu()
+                return None, gJ, gX
+
+        _FMM_FUNCTION = FMMApply
+    return _FMM_FUNCTION
 
 
 # ---------------------------------------------------------------- host-only helpers

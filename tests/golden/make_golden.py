@@ -106,6 +106,24 @@ def adjoint_sparse(n=1000000, n_active=400, n_src=128, n_grad=24):
                         idx=idx, keep=keep, js=js, gX=gX, seed=0)
 
 
+def largest_sparse(n=2000000, n_rhs=16, n_active=400, n_tgt=128):
+    """Four-layer workload at n points (half uniform, half in 20 Gaussian
+    clusters) with n_rhs current vectors sharing n_active nonzero sources:
+    the oracle at n_tgt sampled targets; and n_rhs output gradients non-zero
+    on n_active targets, with their adjoint gJ = G^H gA at n_tgt sampled
+    sources (through the oracle's reciprocity, as adjoint_sparse)."""
+    d, k, x, J = inputs.four_layer(n, seed=0, n_rhs=n_rhs)
+    Js, keep = inputs.sparse_currents(J, n_active, seed=0)
+    idx = inputs.sample_targets(n, n_tgt, seed=0)
+    A = oracle.direct(d, k, x[keep], J[:, keep], x[idx])
+    gA = inputs.cotangent(n, n_rhs=n_rhs, seed=0)
+    gAs, keep_a = inputs.sparse_currents(gA, n_active, seed=1)
+    idx_s = inputs.sample_sources(n, n_tgt, seed=0)
+    gJ = np.conj(oracle.direct(d, k, x[keep_a], np.conj(gA[:, keep_a]), x[idx_s]))
+    np.savez_compressed(os.path.join(OUT, "four_%d_rhs%d_sparse%d_oracle.npz" % (n, n_rhs, n_active)), A=A,
+                        idx=idx, keep=keep, gJ=gJ, idx_s=idx_s, keep_a=keep_a, seed=0)
+
+
 if __name__ == "__main__":
     names = sys.argv[1:] or ["tiny"]
     for nm in names:
@@ -119,6 +137,8 @@ if __name__ == "__main__":
         elif nm.startswith("adjoint_sparse"):
             parts = nm.split(":")
             adjoint_sparse(n=int(parts[1]) if len(parts) > 1 else 1000000)
+        elif nm == "largest":
+            largest_sparse()
         elif nm.startswith("scale"):
             parts = nm.split(":")
             n = int(parts[1]) if len(parts) > 1 else 100000

@@ -1,0 +1,125 @@
+"""GPU tests of the differentiable evaluation (torch.autograd.Function
+behind LayeredDyadicFMM.apply, through the C ABI): for the loss
+L = sum_i |A(x_i) - A*_i|^2 with A* from a random J*, the backward pass gives
+dL/dJ by the transposed FMM (lm_evaluate_adjoint) and dL/d(source positions)
+(lm_grad_src_xyz), checked bitwise against those calls and against central
+finite differences of the same loss (quadratic in J, so exact up to
+rounding there; h^2-accurate in the positions, each probe a rebuild, both
+evaluated from the probe's own field).  The
+targets are a point set of their own, so that moving a source never brings
+it onto a target."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+from paper_2507_18491_amd import inputs, lmfmm  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def cuda(a):
+    return torch.tensor(a, device="cuda")
+
+
+def check(d, k, x, y, J, Jstar, n_j, n_x, h_x, seed, **kw):
+    """Autograd gradients against central finite differences of the FMM loss.
+
+    For fixed positions the FMM is linear in J, so the central difference in
+    one current entry, [L(J + h e) - L(J - h e)] / 2h, is exactly
+    2 Re <A - A*, F(e)> with F(e) the field of the probe current e alone (no
+    truncation in h); evaluating it so avoids subtracting two large losses
+    (targets that lie close to a source carry |A| up to 1e8 at N = 5e5).
+    Moving source j changes only its own column of F (same plan, targets
+    fixed), so with u the field of J_j alone at x_j + h, x_j - h and x_j:
+        L(+) - L(-) = sum 2 Re(conj(R - u0) (u+ - u-)) + |u+|^2 - |u-|^2,
+    R = A - A*, again without the large common part."""
+    f = lmfmm.LayeredDyadicFMM(d, k, **kw).build(x, y)
+    Astar = f.evaluate(cuda(Jstar))
+    Jt = cuda(J).requires_grad_(True)
+    X = f.source_positions(requires_grad=True)
+    A = f.apply(Jt, X)
+    seen = []
+    A.register_hook(lambda g: seen.append(g.detach().clone()))
+    L = ((A - Astar).abs() ** 2).sum()
+    L.backward()
+    gJ, gX = Jt.grad.cpu().numpy(), X.grad.cpu().numpy()
+    # the gradient reaching A is 2 (A - A*); the backward pass is exactly the
+    # adjoint and gradient calls on it
+    r = seen[0].contiguous()
+    R = A.detach() - Astar
+    assert torch.allclose(r, 2.0 * R, rtol=1e-13, atol=0)
+    assert np.array_equal(gJ, f.evaluate_adjoint(r).cpu().numpy())
+    assert np.array_equal(gX, f.grad_src_xyz(cuda(J), r).cpu().numpy())
+    rng = np.random.default_rng(seed)
+    n = x.shape[0]
+    # currents: d/dRe and d/dIm of random entries
+    fd, an = [], []
+    for t in range(n_j):
+        j, c, part = rng.integers(n), rng.integers(3), rng.integers(2)
+        e = np.zeros_like(J)
+        e[j, c] = 1.0 if part == 0 else 1j
+        Fe = f.evaluate(cuda(e))
+        fd.append(float(2.0 * (R.conj() * Fe).real.sum()))
+        an.append(gJ[j, c].real if part == 0 else gJ[j, c].imag)
+    fd, an = np.array(fd), np.array(an)
+    ej = np.linalg.norm(fd - an) / np.linalg.norm(an)
+    print("  dL/dJ vs finite differences (%d entries): rel %.3e" % (n_j, ej), flush=True)
+    # positions: each probe moves one coordinate of one source and rebuilds
+    probes = [(rng.integers(n), rng.integers(3)) for _ in range(n_x)]
+    u0 = []
+    for j, c in probes:
+        Jj = np.zeros_like(J)
+        Jj[j] = J[j]
+        u0.append(f.evaluate(cuda(Jj)))
+    f.close()
+    fdx, anx = [], []
+    for (j, c), u in zip(probes, u0):
+        Jj = np.zeros_like(J)
+        Jj[j] = J[j]
+        us = []
+        for sgn in (1.0, -1.0):
+            xp = x.copy()
+            xp[j, c] += sgn * h_x
+            g = lmfmm.LayeredDyadicFMM(d, k, **kw).build(xp, y)   # targets fixed
+            us.append(g.evaluate(cuda(Jj)))
+            g.close()
+        dL = (2.0 * ((R - u).conj() * (us[0] - us[1])).real + us[0].abs() ** 2 - us[1].abs() ** 2).sum()
+        fdx.append(float(dL) / (2 * h_x))
+        anx.append(gX[j, c])
+    fdx, anx = np.array(fdx), np.array(anx)
+    ex = np.linalg.norm(fdx - anx) / np.linalg.norm(anx)
+    print("  dL/dX vs finite differences (%d entries): rel %.3e" % (n_x, ex), flush=True)
+    return ej, ex
+
+
+# The adjoint and the gradient are those of the exact operator to the FMM's
+# accuracy, not the exact transpose of the discrete FMM, and a finite
+# difference in one entry probes the field of a single source, which carries
+# the worst-case truncation of its boxes rather than the L2 average: at p = 12
+# on the tiny workload the finite differences of the FMM loss differ from the
+# exact derivative (oracle) by 6.8e-5 on 16 entries, the autograd gradient by
+# 7.5e-6.  The tiny case therefore runs at p = 16, where that truncation is
+# negligible, and checks the wiring tightly; the p = 12 configuration uses a
+# bound of a few times that single-source truncation.  A finite difference in
+# a source position also differentiates the truncation error, which grows by
+# about the order over the box size: measured 1.0e-4 at p = 12 and 2.0e-5 at
+# p = 16 on the tiny sample.
+def test_autograd_tiny():
+    d, k, x, J = inputs.tiny()
+    y = inputs.tiny(seed=9)[2]
+    Jstar = inputs.currents(np.random.default_rng(77), x.shape[0], 1)
+    print("case tiny p=16 (distinct targets)", flush=True)
+    ej, ex = check(d, k, x, y, J, Jstar, n_j=16, n_x=8, h_x=1e-6, seed=1, p=16)
+    assert ej < 1e-5 and ex < 1e-4
+
+
+def test_autograd_differentiation_config_500k():
+    """Three-layer medium, N = 5e5, p = 12 (free part p = 20): 64 random
+    current entries and 16 random position entries."""
+    n = 500000
+    d, k, x, J = inputs.three_layer(n, seed=5)
+    y = inputs.three_layer(n, seed=6)[2]
+    Jstar = inputs.currents(np.random.default_rng(78), n, 1)
+    print("case three-layer N=%d p=12 (distinct targets)" % n, flush=True)
+    ej, ex = check(d, k, x, y, J, Jstar, n_j=64, n_x=16, h_x=1e-6, seed=2, p=12, p_free=20)
+    assert ej < 3e-4 and ex < 5e-4

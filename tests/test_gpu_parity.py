@@ -256,3 +256,40 @@ def test_three_layer_100k_direct_near_field():
     e = rel(A[g["idx"]], g["A"])
     print("  s2t pairs %d, rel L2 = %.3e" % (npairs, e), flush=True)
     assert npairs > 0 and e < 6e-6
+
+
+def cuda(a):
+    return torch.tensor(a, device="cuda")
+
+
+def test_four_layer_largest_sampled():
+    """Four-layer medium (interfaces 0, -1, -2.5; k = 1.0, 1.8, 2.4, 1.3),
+    N = 2e6 points (half uniform, half in 20 Gaussian clusters), p = 16 (free
+    part p = 20), 16 current vectors in one evaluation and their adjoint, at
+    full size: sampled targets and sources against the oracle (stored; 400
+    nonzero sources, resp. output gradients, shared by the 16 vectors).  The
+    bound is the accuracy asked at p = 16 (relative L2 <= 1e-6).  One column
+    evaluated alone equals its column of the batch bitwise."""
+    n, nr = 2000000, 16
+    g = np.load(os.path.join(GOLD, "four_%d_rhs%d_sparse400_oracle.npz" % (n, nr)))
+    d, k, x, J = inputs.four_layer(n, seed=0, n_rhs=nr)
+    Js, keep = inputs.sparse_currents(J, 400, seed=0)
+    assert np.array_equal(keep, g["keep"])
+    print("case four-layer N=%d p=16 free p=20, %d right-hand sides" % (n, nr), flush=True)
+    f = lmfmm.LayeredDyadicFMM(d, k, p=16, p_free=20).build(x)
+    print("  built: %s" % {a: f.stats()[a] for a in ("m2l_pairs_react", "m2l_pairs_free", "s2t_pairs")},
+          flush=True)
+    A = f.evaluate(cuda(Js))
+    e = rel(A[:, g["idx"]].cpu().numpy(), g["A"])
+    A3 = f.evaluate(cuda(Js[3])).cpu().numpy()
+    same = np.array_equal(A3, A[3].cpu().numpy())
+    del A
+    print("  forward rel L2 = %.3e, column 3 alone bitwise equal: %s" % (e, same), flush=True)
+    gA = inputs.cotangent(n, n_rhs=nr, seed=0)
+    gAs, keep_a = inputs.sparse_currents(gA, 400, seed=1)
+    assert np.array_equal(keep_a, g["keep_a"])
+    gJ = f.evaluate_adjoint(cuda(gAs))
+    ea = rel(gJ[:, g["idx_s"]].cpu().numpy(), g["gJ"])
+    f.close()
+    print("  adjoint rel L2 = %.3e" % ea, flush=True)
+    assert e < 1e-6 and ea < 1e-6 and same
