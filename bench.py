@@ -104,6 +104,39 @@ def uneven_geometries(args, torch, inputs, lmfmm):
             "build_s": build_s, "launch": "hip graph replay of one evaluation"}
 
 
+def batched_rhs(args, torch, inputs, lmfmm, n=200000, n_rhs=64):
+    """Many current vectors on one tree: the three-layer geometry at n points
+    with n_rhs vectors in one call, against the same tree with one vector per
+    call (targets x right-hand sides per second)."""
+    d, k, x, J = inputs.three_layer(n, seed=0, n_rhs=n_rhs)
+    f = lmfmm.LayeredDyadicFMM(d, k, p=args.p, p_free=args.p_free).build(x)
+    Jm = torch.tensor(J, device="cuda:0")
+    A = torch.empty_like(Jm)
+    f.evaluate(Jm, out=A)
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 2))
+    t0 = time.time()
+    for _ in range(steps):
+        f.evaluate(Jm, out=A)
+    torch.cuda.synchronize()
+    dt_b = (time.time() - t0) / steps
+    J1 = Jm[0].contiguous()
+    A1 = torch.empty_like(J1)
+    f.evaluate(J1, out=A1)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for _ in range(args.steps):
+        f.evaluate(J1, out=A1)
+    torch.cuda.synchronize()
+    dt_1 = (time.time() - t0) / args.steps
+    f.close()
+    print("batched: %d points x %d right-hand sides, %.1f ms per call (one vector: %.1f ms)" % (
+        n, n_rhs, 1e3 * dt_b, 1e3 * dt_1), file=sys.stderr, flush=True)
+    return {"n": n, "n_rhs": n_rhs, "ms_per_call": 1e3 * dt_b, "targets_rhs_per_s": n * n_rhs / dt_b,
+            "plain_ms_per_call": 1e3 * dt_1, "plain_targets_per_s": n / dt_1,
+            "vs_plain": (n * n_rhs / dt_b) / (n / dt_1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +149,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-uneven", action="store_true", help="skip the 32 uneven geometries")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-vector batched evaluation")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint and source-gradient timings (profiling runs of the forward step)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -216,6 +250,7 @@ def main():
             acc = float(np.linalg.norm(As[g["idx"]] - g["A"]) / np.linalg.norm(g["A"]))
     fmm.close()
     uneven = None if args.no_uneven else uneven_geometries(args, torch, inputs, lmfmm)
+    batched = None if args.no_batched else batched_rhs(args, torch, inputs, lmfmm)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(d, k, x, J if args.rhs == 1 else J[0], args.n)
@@ -251,6 +286,7 @@ def main():
             "targets_per_s": args.n * args.rhs / grad_s, "ms_per_step": 1e3 * grad_s,
             "vs_forward": (wall / args.steps) / grad_s},
         "uneven_geometries": uneven,
+        "batched_rhs": batched,
         "m2l_autotune": {"chosen_variant_per_launch": m2l_var,
                          "tuning_ms_per_step_by_variant": [round(float(v), 3) for v in m2l_ms.sum(axis=0)],
                          "tuning_ms_per_step_chosen": round(float(sum(m2l_ms[i, v] for i, v in enumerate(m2l_var))), 3)},

@@ -124,6 +124,17 @@ def largest_sparse(n=2000000, n_rhs=16, n_active=400, n_tgt=128):
                         idx=idx, keep=keep, gJ=gJ, idx_s=idx_s, keep_a=keep_a, seed=0)
 
 
+def batched_sparse(n=200000, n_rhs=64, n_active=400, n_tgt=64):
+    """Three-layer workload at n points with n_rhs current vectors sharing
+    n_active nonzero sources; the oracle at n_tgt sampled targets."""
+    d, k, x, J = inputs.three_layer(n, seed=0, n_rhs=n_rhs)
+    Js, keep = inputs.sparse_currents(J, n_active, seed=0)
+    idx = inputs.sample_targets(n, n_tgt, seed=0)
+    A = oracle.direct(d, k, x[keep], J[:, keep], x[idx])
+    np.savez_compressed(os.path.join(OUT, "three_%d_rhs%d_sparse%d_oracle.npz" % (n, n_rhs, n_active)), A=A,
+                        idx=idx, keep=keep, seed=0)
+
+
 if __name__ == "__main__":
     names = sys.argv[1:] or ["tiny"]
     for nm in names:
@@ -139,6 +150,8 @@ if __name__ == "__main__":
             adjoint_sparse(n=int(parts[1]) if len(parts) > 1 else 1000000)
         elif nm == "largest":
             largest_sparse()
+        elif nm == "batched":
+            batched_sparse()
         elif nm.startswith("scale"):
             parts = nm.split(":")
             n = int(parts[1]) if len(parts) > 1 else 100000
