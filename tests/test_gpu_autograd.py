@@ -115,11 +115,11 @@ def test_autograd_tiny():
 
 def test_autograd_differentiation_config_500k():
     """Three-layer medium, N = 5e5, p = 12 (free part p = 20): 64 random
-    current entries and 16 random position entries."""
+    current entries and 8 random position entries (each two rebuilds)."""
     n = 500000
     d, k, x, J = inputs.three_layer(n, seed=5)
     y = inputs.three_layer(n, seed=6)[2]
     Jstar = inputs.currents(np.random.default_rng(78), n, 1)
     print("case three-layer N=%d p=12 (distinct targets)" % n, flush=True)
-    ej, ex = check(d, k, x, y, J, Jstar, n_j=64, n_x=16, h_x=1e-6, seed=2, p=12, p_free=20)
+    ej, ex = check(d, k, x, y, J, Jstar, n_j=64, n_x=8, h_x=1e-6, seed=2, p=12, p_free=20)
     assert ej < 3e-4 and ex < 5e-4
