@@ -1323,8 +1323,9 @@ void launch_p2p_grad(const DevPlan& d, const int* tboxes, int n, const double* s
 // and runs the node loop of the component's Sommerfeld integrals (Gamma_1,
 // then the real tail up to its own cut).  Nodes are staged through LDS 64 at
 // a time and read in a wave-uniform loop.  A target adds its pairs in q order
-// (no atomics).
-template <bool SMALLZ>
+// (no atomics).  The integrals depend on the pair only: a block applies them
+// to RS right-hand sides (blockIdx.y: the group of RS).
+template <bool SMALLZ, int RS>
 __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md, const int* items,
                                                                      const double* sxyz, const cd* J,
                                                                      long long n_src, const double* txyz,
@@ -1332,7 +1333,7 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
                                                                      cd* A) {
   __shared__ double tp[LM_S2T_CHUNK][3];  // targets: x, y, t
   __shared__ int seg_pt0[LM_S2T_SEG], seg_cum[LM_S2T_SEG + 1];
-  __shared__ cd res[LM_S2T_CHUNK][3];     // per pair of the round: out+, out-, out_z
+  __shared__ cd res[LM_S2T_CHUNK][RS][3];  // per pair of the round and rhs: out+, out-, out_z
   __shared__ cd nk[LM_S2T_CHUNK][10];     // node chunk: kr, w, kz_t, kz_s, F_1..F_5, 1 / kr (tail)
   const int tid = threadIdx.x;
   // work item, component and node range are uniform over the block
@@ -1340,7 +1341,7 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
   const int chunk = __builtin_amdgcn_readfirstlane(items[2 * blockIdx.x + 1]);
   const TgtBox tb = d.tbox[b];
   const InstParams ip = d.inst[__builtin_amdgcn_readfirstlane(tb.inst)];
-  const int r = blockIdx.y;
+  const int r0 = blockIdx.y * RS, nr = min(RS, n_rhs - r0);
   const int t0 = tb.pt0 + chunk * LM_S2T_CHUNK;
   const int nt = min(LM_S2T_CHUNK, tb.pt1 - t0);
   const int n0 = __builtin_amdgcn_readfirstlane(ip.s2t0), nn = __builtin_amdgcn_readfirstlane(ip.s2tn);
@@ -1354,7 +1355,8 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
     tp[tid][1] = txyz[3 * id + 1];
     tp[tid][2] = ip.up_t ? zt - md.d[ip.lt] : md.d[ip.lt - 1] - zt;
   }
-  cd op = cd{0, 0}, om = cd{0, 0}, oz = cd{0, 0};  // thread tid < nt: totals of target tid
+  cd op[RS], om[RS], oz[RS];  // thread tid < nt: totals of target tid
+  for (int rr = 0; rr < RS; rr++) op[rr] = om[rr] = oz[rr] = cd{0, 0};
   for (int l0 = tb.p2p0; l0 < tb.p2p1; l0 += LM_S2T_SEG) {
     const int nb = min(LM_S2T_SEG, tb.p2p1 - l0);
     __syncthreads();
@@ -1373,7 +1375,6 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
     const int npair = nt * ns;
     for (int q0 = 0; q0 < npair; q0 += LM_S2T_CHUNK) {
       const int q = q0 + tid;
-      cd rp = cd{0, 0}, rm = cd{0, 0}, rz = cd{0, 0};
       const bool pa = q < npair;
       const int i = pa ? q / ns : 0, j = pa ? q - (q / ns) * ns : 0;
       // this lane's source: box of the segment holding source j
@@ -1381,8 +1382,6 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
       while (e + 1 < nb && seg_cum[e + 1] <= j) e++;
       const int sid = d.src_perm[seg_pt0[e] + (j - seg_cum[e])];
       const double* sx = sxyz + 3 * (long long)sid;
-      const cd* Jp = J + ((long long)r * n_src + sid) * 3;
-      const cd jx = Jp[0], jy = Jp[1], jz = Jp[2];
       double dx = tp[i][0] - sx[0], dy = tp[i][1] - sx[1];
       double tz = tp[i][2], uz = ip.up_s ? dls - sx[2] : sx[2] - dls;
       double rho = sqrt(dx * dx + dy * dy);
@@ -1451,42 +1450,68 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
         if (!__syncthreads_or(more)) break;
       }
       if (pa) {
-        cd e1 = cd{cph, sph}, e2 = e1 * e1;
-        cd W01 = cd{-I1.y, I1.x};  // i I1
-        cd W05 = cd{-I5.y, I5.x};  // i I5
-        cd t3 = cd{I3.y, -I3.x};   // -i I3
-        cd W2p = e2 * t3, W2m = cconj(e2) * t3;
-        cd W1p2 = -1.0 * (e1 * I2), W1m2 = -1.0 * (cconj(e1) * I2);
-        cd W1p4 = -1.0 * (e1 * I4), W1m4 = -1.0 * (cconj(e1) * I4);
-        cd up = jx + cd{-jy.y, jy.x}, um = jx - cd{-jy.y, jy.x}, mz = jz;
-        rp = 0.5 * (W01 * up) - 0.5 * (W2p * um) + W1p2 * mz;
-        rm = 0.5 * (W01 * um) - 0.5 * (W2m * up) + W1m2 * mz;
-        rz = 0.5 * (W1p4 * um) + 0.5 * (W1m4 * up) + W05 * mz;
+        // written out with explicit fma and contraction off: the same
+        // rounding whatever the number of right-hand sides a block serves (a
+        // column of a batch equals its single-vector evaluation bitwise)
+#pragma clang fp contract(off)
+        auto cm = [](cd u, cd v) { return cd{fma(u.x, v.x, -(u.y * v.y)), fma(u.x, v.y, u.y * v.x)}; };
+        const cd e1 = cd{cph, sph}, e1c = cd{cph, -sph};
+        const cd e2 = cm(e1, e1), e2c = cd{e2.x, -e2.y};
+        const cd W01 = cd{-I1.y, I1.x};  // i I1
+        const cd W05 = cd{-I5.y, I5.x};  // i I5
+        const cd t3 = cd{I3.y, -I3.x};   // -i I3
+        const cd W2p = cm(e2, t3), W2m = cm(e2c, t3);
+        const cd P2 = cm(e1, I2), M2 = cm(e1c, I2), P4 = cm(e1, I4), M4 = cm(e1c, I4);
+        const cd W1p2 = cd{-P2.x, -P2.y}, W1m2 = cd{-M2.x, -M2.y};
+        const cd W1p4 = cd{-P4.x, -P4.y}, W1m4 = cd{-M4.x, -M4.y};
+        for (int rr = 0; rr < RS; rr++) {
+          cd rp = cd{0, 0}, rm = cd{0, 0}, rz = cd{0, 0};
+          if (rr < nr) {
+            const cd* Jp = J + ((long long)(r0 + rr) * n_src + sid) * 3;
+            const cd jx = Jp[0], jy = Jp[1], jz = Jp[2];
+            const cd up = cd{jx.x - jy.y, jx.y + jy.x}, um = cd{jx.x + jy.y, jx.y - jy.x};
+            const cd a1 = cm(W01, up), a2 = cm(W2p, um), a3 = cm(W1p2, jz);
+            const cd b1 = cm(W01, um), b2 = cm(W2m, up), b3 = cm(W1m2, jz);
+            const cd c1 = cm(W1p4, um), c2 = cm(W1m4, up), c3 = cm(W05, jz);
+            rp = cd{(0.5 * a1.x - 0.5 * a2.x) + a3.x, (0.5 * a1.y - 0.5 * a2.y) + a3.y};
+            rm = cd{(0.5 * b1.x - 0.5 * b2.x) + b3.x, (0.5 * b1.y - 0.5 * b2.y) + b3.y};
+            rz = cd{(0.5 * c1.x + 0.5 * c2.x) + c3.x, (0.5 * c1.y + 0.5 * c2.y) + c3.y};
+          }
+          res[tid][rr][0] = rp;
+          res[tid][rr][1] = rm;
+          res[tid][rr][2] = rz;
+        }
+      } else {
+        for (int rr = 0; rr < RS; rr++) res[tid][rr][0] = res[tid][rr][1] = res[tid][rr][2] = cd{0, 0};
       }
-      res[tid][0] = rp;
-      res[tid][1] = rm;
-      res[tid][2] = rz;
       __syncthreads();
       // target tid adds its pairs of this round in source order
       if (tid < nt) {
         int qa = max(q0, tid * ns), qb = min(q0 + LM_S2T_CHUNK, (tid + 1) * ns);
-        for (int qq = qa; qq < qb; qq++) {
-          op = op + res[qq - q0][0];
-          om = om + res[qq - q0][1];
-          oz = oz + res[qq - q0][2];
-        }
+        for (int qq = qa; qq < qb; qq++)
+          for (int rr = 0; rr < RS; rr++) {
+            op[rr] = op[rr] + res[qq - q0][rr][0];
+            om[rr] = om[rr] + res[qq - q0][rr][1];
+            oz[rr] = oz[rr] + res[qq - q0][rr][2];
+          }
       }
       __syncthreads();
     }
   }
   if (tid < nt) {
+#pragma clang fp contract(off)
     const double f = 0.079577471545947667884;  // 1 / (4 pi)
-    cd ax = (0.5 * f) * (op + om);
-    cd dd = (0.5 * f) * (op - om);
-    cd* Ap = A + ((long long)r * n_tgt + id) * 3;
-    Ap[0] = Ap[0] + ax;
-    Ap[1] = Ap[1] + cd{dd.y, -dd.x};
-    Ap[2] = Ap[2] + f * oz;
+#pragma unroll
+    for (int rr = 0; rr < RS; rr++) {
+      if (rr >= nr) break;
+      const double hx = 0.5 * f * (op[rr].x + om[rr].x), hy = 0.5 * f * (op[rr].y + om[rr].y);
+      const double dx = 0.5 * f * (op[rr].x - om[rr].x), dy = 0.5 * f * (op[rr].y - om[rr].y);
+      cd* Ap = A + ((long long)(r0 + rr) * n_tgt + id) * 3;
+      const cd a0 = Ap[0], a1 = Ap[1], a2 = Ap[2];
+      Ap[0] = cd{a0.x + hx, a0.y + hy};
+      Ap[1] = cd{a1.x + dy, a1.y - dx};
+      Ap[2] = cd{a2.x + f * oz[rr].x, a2.y + f * oz[rr].y};
+    }
   }
 }
 // smallz: |k_rho| rho <= 7.5 on Gamma_1 for every pair of the component;
@@ -1495,12 +1520,21 @@ void launch_s2t(const DevPlan& d, MediumDev md, const int* items, int n, const d
                 long long n_src, const double* txyz, long long n_tgt, int n_rhs, double a, bool smallz, int nser,
                 cd* A, hipStream_t s) {
   if (n <= 0) return;
-  if (smallz)
-    hipLaunchKernelGGL(k_s2t<true>, dim3(n, n_rhs), dim3(LM_S2T_CHUNK), 0, s, d, md, items, sxyz, J, n_src, txyz,
-                       n_tgt, n_rhs, a, nser, A);
-  else
-    hipLaunchKernelGGL(k_s2t<false>, dim3(n, n_rhs), dim3(LM_S2T_CHUNK), 0, s, d, md, items, sxyz, J, n_src, txyz,
-                       n_tgt, n_rhs, a, nser, A);
+#define LM_S2T_GO(SZ, RS)                                                                                   \
+  hipLaunchKernelGGL((k_s2t<SZ, RS>), dim3(n, (n_rhs + RS - 1) / RS), dim3(LM_S2T_CHUNK), 0, s, d, md, items, \
+                     sxyz, J, n_src, txyz, n_tgt, n_rhs, a, nser, A)
+  if (n_rhs == 1) {
+    if (smallz)
+      LM_S2T_GO(true, 1);
+    else
+      LM_S2T_GO(false, 1);
+  } else {
+    if (smallz)
+      LM_S2T_GO(true, 4);
+    else
+      LM_S2T_GO(false, 4);
+  }
+#undef LM_S2T_GO
 }
 
 // ------------------------------------------------------------------ translation tables

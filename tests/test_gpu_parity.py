@@ -314,3 +314,18 @@ def test_batched_rhs_200k_sampled():
     f.close()
     print("  rel L2 = %.3e, single columns bitwise equal: %s" % (e, same), flush=True)
     assert e < 3e-6 and same
+
+
+def test_direct_near_field_many_rhs(tiny):
+    """The direct reaction near field evaluates its integrals once per pair
+    for up to 4 right-hand sides: with 6 current vectors (groups of 4 and 2)
+    every column equals its single-vector evaluation bitwise."""
+    d, k, x, J, g = tiny
+    rng = np.random.default_rng(12)
+    Jm = rng.uniform(-1, 1, (6, 600, 3)) + 1j * rng.uniform(-1, 1, (6, 600, 3))
+    f = lmfmm.LayeredDyadicFMM(d, k, p=8, react_s2t=2).build(x)
+    assert f.stats()["s2t_pairs"] > 0
+    Am = f.evaluate(cuda(Jm)).cpu().numpy()
+    for r in range(6):
+        assert np.array_equal(Am[r], f.evaluate(cuda(Jm[r])).cpu().numpy()), r
+    f.close()
