@@ -17,6 +17,14 @@
 #include "bessel_pq.h"
 #include "kernels.h"
 
+// Raises a kernel's dynamic LDS limit before its launch.  A failure leaves
+// the default limit in place; the launch that follows then fails, and the
+// caller's hipGetLastError check reports it (as it reports this call's
+// error, which HIP keeps as the last error).
+static inline void set_dyn_lds(const void* f, size_t bytes) {
+  (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 // RC (template parameter): right-hand sides per block in the point/translation passes (1 or 4)
 #define NT 256          // threads per block
 static_assert(NT == LM_P2P_CHUNK, "near-field work items hold one block's worth of targets");
@@ -189,7 +197,7 @@ static void p2m_go(const DevPlan& d, const int* leaves, int n, const double* xyz
                    int n_rhs, cd* ME, int pl, hipStream_t s) {
   int ntri = (pl + 1) * (pl + 2) / 2;
   size_t shm = (size_t)NPT * ((pl + 1) + ntri + 2 * (pl + 1) + RC * 6) * sizeof(double);
-  hipFuncSetAttribute((const void*)k_p2m<RC, NTB, H, NPT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  set_dyn_lds((const void*)k_p2m<RC, NTB, H, NPT>, shm);
   hipLaunchKernelGGL((k_p2m<RC, NTB, H, NPT>), dim3(n, (n_rhs + RC - 1) / RC), dim3(NTB), shm, s, d, leaves, xyz, J,
                      n_src, n_rhs, ME);
 }
@@ -254,10 +262,10 @@ void launch_m2m(const DevPlan& d, const int* parents, int n, int n_rhs, cd* ME, 
   int rc = n_rhs == 1 ? 1 : 4;
   size_t shm = (size_t)rc * 3 * P * sizeof(cd);
   if (rc == 1) {
-    hipFuncSetAttribute((const void*)k_m2m<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    set_dyn_lds((const void*)k_m2m<1>, shm);
     hipLaunchKernelGGL(k_m2m<1>, dim3(n, n_rhs), dim3(NT), shm, s, d, parents, n_rhs, ME);
   } else {
-    hipFuncSetAttribute((const void*)k_m2m<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    set_dyn_lds((const void*)k_m2m<4>, shm);
     hipLaunchKernelGGL(k_m2m<4>, dim3(n, (n_rhs + 3) / 4), dim3(NT), shm, s, d, parents, n_rhs, ME);
   }
 }
@@ -301,10 +309,10 @@ void launch_l2l(const DevPlan& d, const int* children, int n, int n_rhs, cd* LE,
   int rc = n_rhs == 1 ? 1 : 4;
   size_t shm = (size_t)rc * 3 * P * sizeof(cd);
   if (rc == 1) {
-    hipFuncSetAttribute((const void*)k_l2l<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    set_dyn_lds((const void*)k_l2l<1>, shm);
     hipLaunchKernelGGL(k_l2l<1>, dim3(n, n_rhs), dim3(NT), shm, s, d, children, n_rhs, LE);
   } else {
-    hipFuncSetAttribute((const void*)k_l2l<4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    set_dyn_lds((const void*)k_l2l<4>, shm);
     hipLaunchKernelGGL(k_l2l<4>, dim3(n, (n_rhs + 3) / 4), dim3(NT), shm, s, d, children, n_rhs, LE);
   }
 }
@@ -802,7 +810,7 @@ static void l2p_go(const DevPlan& d, const int* leaves, int n, int ch, int kind,
   int pe = kind == 0 ? pi + 2 : pi;
   int Pe = (pe + 1) * (pe + 1), Pd = (pi + 2) * (pi + 2);
   size_t shm = (size_t)(RC * 3 * Pe + RC * Pd) * sizeof(cd) + (size_t)NTB * (pe + 1) * sizeof(double);
-  hipFuncSetAttribute((const void*)k_l2p<RC, NTB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  set_dyn_lds((const void*)k_l2p<RC, NTB>, shm);
   hipLaunchKernelGGL((k_l2p<RC, NTB>), dim3(n, (n_rhs + RC - 1) / RC), dim3(NTB), shm, s, d, leaves, ch, kind, xyz,
                      n_tgt, n_rhs, LE, A);
 }
@@ -1186,7 +1194,7 @@ static void l2p_grad_go(const DevPlan& d, const int* leaves, int n, int kind, co
   int pg = (kind == 0 ? pi + 2 : pi) + 1;
   int Pg = (pg + 1) * (pg + 1), Pd = (pi + 2) * (pi + 2);
   size_t shm = (size_t)(12 * Pg + Pd) * sizeof(cd) + (size_t)NTB * (pg + 1) * sizeof(double);
-  hipFuncSetAttribute((const void*)k_l2p_grad<NTB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  set_dyn_lds((const void*)k_l2p_grad<NTB>, shm);
   hipLaunchKernelGGL(k_l2p_grad<NTB>, dim3(n), dim3(NTB), shm, s, d, leaves, LM_L2P_CHUNK(kind), kind, xyz, n_pts,
                      n_rhs, LE, W, gX);
 }
@@ -1811,7 +1819,7 @@ void launch_tab_integrals(const DevPlan& d, MediumDev med, int case0, int ncase,
   int NQ = 2 * p + 3, NL = p + 2;
   int E = 80 * NL * NQ;
   size_t shm = (size_t)(TAB_NC * 80 + TAB_NC * NL * NQ + TAB_NC * NL) * sizeof(cd);
-  hipFuncSetAttribute((const void*)k_tab_integrals, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  set_dyn_lds((const void*)k_tab_integrals, shm);
   hipLaunchKernelGGL(k_tab_integrals, dim3(ncase, (E + NT * 4 - 1) / (NT * 4)), dim3(NT), shm, s, d, case0, p,
                      (int)maxnode, scr);
 }
@@ -1903,6 +1911,6 @@ void launch_tab_assemble(const DevPlan& d, int case0, int ncase, int p, int KB, 
   if (ncase <= 0) return;
   int NQ = 2 * p + 3;
   size_t shm = (size_t)(KB + 1) * (KB + 1) * NQ * sizeof(cd);
-  hipFuncSetAttribute((const void*)k_tab_assemble, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  set_dyn_lds((const void*)k_tab_assemble, shm);
   hipLaunchKernelGGL(k_tab_assemble, dim3(ncase, 5), dim3(NT), shm, s, d, case0, p, KB, BS);
 }
