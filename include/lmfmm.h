@@ -128,8 +128,10 @@ int lm_build(lm_ctx* ctx, int64_t n_src, const double* src_xyz, int64_t n_tgt,
 
 /* Builds several independent geometries into one plan, so that every later
  * lm_evaluate / lm_evaluate_adjoint / lm_grad_src_xyz processes all of them
- * with one launch per pass (many small problems at the occupancy of one
- * large one).  Geometry g owns the sources src_off[g] .. src_off[g+1]-1 and
+ * together: each pass launches once for all geometries (the leaf passes once
+ * per group of instances that share no target point: free space, and each
+ * reaction component type), so many small problems run at the occupancy of
+ * one large one.  Geometry g owns the sources src_off[g] .. src_off[g+1]-1 and
  * the targets tgt_off[g] .. tgt_off[g+1]-1 of the concatenated HOST arrays
  * src_xyz / tgt_xyz; only sources and targets of the same geometry interact
  * (each geometry is the sum of Sec. 3.3 on its own points, with its own

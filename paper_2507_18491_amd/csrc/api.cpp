@@ -34,7 +34,7 @@ struct lm_ctx {
   int n_p2m_lo = 0, n_p2m_hi = 0, p2m_plo = 0, p2m_phi = 0;
   std::vector<int*> d_m2m, d_l2l, d_l2p, d_p2p;
   std::vector<int> n_m2m, n_l2l, n_l2p, n_p2p;
-  std::vector<int> p2p_inst;  // instance of each P2P list
+  std::vector<int> l2p_inst;  // an instance of each L2P launch group (its kind and order)
   cd* ME = nullptr;
   cd* LE = nullptr;
   long long me_cap = 0, le_cap = 0;
@@ -67,9 +67,8 @@ struct lm_ctx {
   MediumDev md;                            // medium as seen by the kernels
   int* d_s2t = nullptr;                    // S2T work items (target leaf, chunk)
   struct S2TRange {
-    int inst, item0, n;
-    bool smallz;  // |k_rho| rho <= 7.5 on Gamma_1: J0..J2 by their power series
-    int nser;     // terms of that series
+    int item0, n;  // work items of one launch (one component type)
+    bool smallz;   // |k_rho| rho <= 7.5 on Gamma_1: J0..J2 by their power series
   };
   std::vector<S2TRange> s2t_ranges;        // per reaction component with direct pairs
   double contour_a = 0;
@@ -120,7 +119,7 @@ static void free_build(lm_ctx* ctx) {
   ctx->n_l2l.clear();
   ctx->n_l2p.clear();
   ctx->n_p2p.clear();
-  ctx->p2p_inst.clear();
+  ctx->l2p_inst.clear();
   memset(&ctx->d, 0, sizeof(ctx->d));
   ctx->built = false;
   if (ctx->adj) lm_destroy(ctx->adj);
@@ -326,6 +325,27 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
   ctx->pmax = std::max(pl.p, pl.pf);
   DevPlan& d = ctx->d;
   int rc;
+  {
+    // direct reaction near field: J0..J2 on Gamma_1 by their power series
+    // where |k_rho| rho <= 7.5 for every pair of the component; the series
+    // stops where the first omitted term (|z|/2)^{2n} / (n!)^2 falls below
+    // 1e-19 at the largest |z| = a rho_max (at most LM_BPQ_NSERC terms,
+    // enough for |z| = 7.5)
+    const double a = ctx->prm.contour_a > 0 ? ctx->prm.contour_a : 1.5 * med.kmax;
+    for (auto& ip : pl.inst) {
+      ip.s2t_nser = 1;
+      ip.s2t_smallz = 1;
+      if (ip.kind != 1 || ip.s2t_rho < 0) continue;
+      ip.s2t_smallz = a * ip.s2t_rho <= 7.5 ? 1 : 0;
+      const double zh = 0.5 * a * ip.s2t_rho;
+      double term = 1.0;
+      while (ip.s2t_nser < LM_BPQ_NSERC) {
+        term *= zh * zh / ((double)ip.s2t_nser * ip.s2t_nser);
+        if (term < 1e-19) break;
+        ip.s2t_nser++;
+      }
+    }
+  }
   if ((rc = upload(ctx, &d.inst, pl.inst))) return rc;
   if ((rc = upload(ctx, &d.sbox, pl.sbox))) return rc;
   if ((rc = upload(ctx, &d.tbox, pl.tbox))) return rc;
@@ -392,61 +412,73 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
     ctx->d_l2l.push_back(p);
     ctx->n_l2l.push_back((int)v.size());
   }
-  for (size_t i = 0; i < pl.l2p_leaves.size(); i++) {
+  // Launch groups: instances that never share a target point run in one
+  // launch: all free-space instances (a point lies in one layer), and the
+  // instances of one reaction component type (lt, ls, up_t, up_s) across
+  // geometries.  Groups launch in key order (free space first), so a point
+  // receives its contributions in the same order in a batch of geometries
+  // as in a build of its own geometry.
+  auto group_of = [](const InstParams& ip) -> long long {
+    if (ip.kind == 0) return -1;
+    return (((long long)ip.lt * LM_MAXL + ip.ls) * 2 + ip.up_t) * 2 + ip.up_s;
+  };
+  {
     // L2P work items: (leaf, chunk of LM_L2P_CHUNK points), so that leaves
     // holding many points spread over many workgroups
-    int ch = LM_L2P_CHUNK(pl.inst[i].kind == 0 ? 0 : 1);
-    std::vector<int> items;
-    for (int b : pl.l2p_leaves[i])
-      for (int c = 0; c * ch < pl.tbox[b].pt1 - pl.tbox[b].pt0; c++) {
-        items.push_back(b);
-        items.push_back(c);
-      }
-    int* p = nullptr;
-    if ((rc = upload(ctx, &p, items))) return rc;
-    ctx->d_l2p.push_back(p);
-    ctx->n_l2p.push_back((int)items.size() / 2);
-  }
-  {
-    int fi = 0;
-    for (size_t i = 0; i < pl.inst.size(); i++)
-      if (pl.inst[i].kind == 0) {
-        int* p = nullptr;
-        if ((rc = upload(ctx, &p, pl.p2p_tboxes[fi]))) return rc;
-        ctx->d_p2p.push_back(p);
-        ctx->n_p2p.push_back((int)pl.p2p_tboxes[fi].size() / 2);
-        ctx->p2p_inst.push_back((int)i);
-        fi++;
-      }
-  }
-  {
-    // reaction near-field (S2T) work items, grouped by component
-    if ((rc = upload(ctx, &ctx->d_s2t, pl.s2t_items))) return rc;
-    const double a = ctx->prm.contour_a > 0 ? ctx->prm.contour_a : 1.5 * med.kmax;
-    int n_items = (int)pl.s2t_items.size() / 2;
-    for (int it = 0; it < n_items;) {
-      int inst = pl.tbox[pl.s2t_items[2 * it]].inst;
-      int j = it;
-      while (j < n_items && pl.tbox[pl.s2t_items[2 * j]].inst == inst) j++;
-      lm_ctx::S2TRange r;
-      r.inst = inst;
-      r.item0 = it;
-      r.n = j - it;
-      r.smallz = a * pl.inst[inst].s2t_rho <= 7.5;
-      // series terms: the first omitted term (|z|/2)^{2n} / (n!)^2 below
-      // 1e-19 at the largest |z| = a rho_max (at most LM_BPQ_NSERC terms,
-      // enough for |z| = 7.5)
-      const double zh = 0.5 * a * pl.inst[inst].s2t_rho;
-      double term = 1.0;
-      r.nser = 1;
-      while (r.nser < LM_BPQ_NSERC) {
-        term *= zh * zh / ((double)r.nser * r.nser);
-        if (term < 1e-19) break;
-        r.nser++;
-      }
-      ctx->s2t_ranges.push_back(r);
-      it = j;
+    std::map<long long, std::vector<int>> items;
+    std::map<long long, int> rep;
+    for (size_t i = 0; i < pl.l2p_leaves.size(); i++) {
+      const long long g = group_of(pl.inst[i]);
+      int ch = LM_L2P_CHUNK(pl.inst[i].kind == 0 ? 0 : 1);
+      std::vector<int>& v = items[g];
+      rep.emplace(g, (int)i);
+      for (int b : pl.l2p_leaves[i])
+        for (int c = 0; c * ch < pl.tbox[b].pt1 - pl.tbox[b].pt0; c++) {
+          v.push_back(b);
+          v.push_back(c);
+        }
     }
+    for (auto& kv : items) {
+      int* p = nullptr;
+      if ((rc = upload(ctx, &p, kv.second))) return rc;
+      ctx->d_l2p.push_back(p);
+      ctx->n_l2p.push_back((int)kv.second.size() / 2);
+      ctx->l2p_inst.push_back(rep[kv.first]);
+    }
+  }
+  {
+    // free-space near field: every free instance in one launch (each block
+    // reads its wavenumber from its target box's instance)
+    std::vector<int> v;
+    for (auto& t : pl.p2p_tboxes) v.insert(v.end(), t.begin(), t.end());
+    if (!v.empty()) {
+      int* p = nullptr;
+      if ((rc = upload(ctx, &p, v))) return rc;
+      ctx->d_p2p.push_back(p);
+      ctx->n_p2p.push_back((int)v.size() / 2);
+    }
+  }
+  {
+    // reaction near-field (S2T) work items: one launch per component type
+    // and kernel variant (small or general complex arguments on Gamma_1)
+    std::map<std::pair<long long, int>, std::vector<int>> items;
+    const int n_items = (int)pl.s2t_items.size() / 2;
+    for (int it = 0; it < n_items; it++) {
+      const InstParams& ip = pl.inst[pl.tbox[pl.s2t_items[2 * it]].inst];
+      std::vector<int>& v = items[std::make_pair(group_of(ip), ip.s2t_smallz)];
+      v.push_back(pl.s2t_items[2 * it]);
+      v.push_back(pl.s2t_items[2 * it + 1]);
+    }
+    std::vector<int> all;
+    for (auto& kv : items) {
+      lm_ctx::S2TRange r;
+      r.item0 = (int)all.size() / 2;
+      r.n = (int)kv.second.size() / 2;
+      r.smallz = kv.first.second != 0;
+      all.insert(all.end(), kv.second.begin(), kv.second.end());
+      ctx->s2t_ranges.push_back(r);
+    }
+    if ((rc = upload(ctx, &ctx->d_s2t, all))) return rc;
   }
   // matrices and table scratch
   void* vp = nullptr;
@@ -895,28 +927,28 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
     for (int l = 1; l < (int)ctx->d_l2l.size(); l++)
       launch_l2l(d, ctx->d_l2l[l], ctx->n_l2l[l], n_rhs, ctx->LE, ctx->pmax, s);
     mark(5);
-    for (size_t i = 0; i < pl.inst.size(); i++) {
+    for (size_t g = 0; g < ctx->d_l2p.size(); g++) {
+      const int i = ctx->l2p_inst[g];
       int kind = pl.inst[i].kind == 0 ? 0 : 1;
       if (grad)
-        launch_l2p_grad(d, ctx->d_l2p[i], ctx->n_l2p[i], kind, ctx->d_tgt, pl.n_tgt, n_rhs, ctx->LE, W, gX,
+        launch_l2p_grad(d, ctx->d_l2p[g], ctx->n_l2p[g], kind, ctx->d_tgt, pl.n_tgt, n_rhs, ctx->LE, W, gX,
                         pl.inst[i].p, s);
       else
-        launch_l2p(d, ctx->d_l2p[i], ctx->n_l2p[i], kind, ctx->d_tgt, pl.n_tgt, n_rhs, ctx->LE, Ac, pl.inst[i].p, s);
+        launch_l2p(d, ctx->d_l2p[g], ctx->n_l2p[g], kind, ctx->d_tgt, pl.n_tgt, n_rhs, ctx->LE, Ac, pl.inst[i].p, s);
     }
     mark(6);
     for (size_t f = 0; f < ctx->d_p2p.size(); f++) {
-      int i = ctx->p2p_inst[f];
       if (grad)
         launch_p2p_grad(d, ctx->d_p2p[f], ctx->n_p2p[f], ctx->d_src, Jc, pl.n_src, ctx->d_tgt, W, pl.n_tgt, n_rhs,
-                        pl.inst[i].kt, gX, ctx->p2p_red, s);
+                        gX, ctx->p2p_red, s);
       else
-        launch_p2p(d, ctx->d_p2p[f], ctx->n_p2p[f], ctx->d_src, Jc, pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs,
-                   pl.inst[i].kt, Ac, ctx->p2p_red, s);
+        launch_p2p(d, ctx->d_p2p[f], ctx->n_p2p[f], ctx->d_src, Jc, pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs, Ac,
+                   ctx->p2p_red, s);
     }
     if (!grad)
       for (auto& r : ctx->s2t_ranges)
         launch_s2t(d, ctx->md, ctx->d_s2t + 2 * r.item0, r.n, ctx->d_src, Jc, pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs,
-                   ctx->contour_a, r.smallz, r.nser, Ac, s);
+                   ctx->contour_a, r.smallz, Ac, s);
     mark(7);
   } else {
     for (int i = 2; i <= 7; i++) mark(i);

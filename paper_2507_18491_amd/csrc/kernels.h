@@ -67,15 +67,15 @@ void launch_l2l(const DevPlan& d, const int* children, int n, int n_rhs, cd* LE,
 void launch_l2p(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_tgt,
                 int n_rhs, const cd* LE, cd* A, int pi, hipStream_t s);
 void launch_p2p(const DevPlan& d, const int* tboxes, int n, const double* sxyz, const cd* J, long long n_src,
-                const double* txyz, long long n_tgt, int n_rhs, double k, cd* A, bool red, hipStream_t s);
+                const double* txyz, long long n_tgt, int n_rhs, cd* A, bool red, hipStream_t s);
 void launch_conj(cd* out, const cd* in, long long n, hipStream_t s);
 void launch_s2t(const DevPlan& d, MediumDev md, const int* items, int n, const double* sxyz, const cd* J,
-                long long n_src, const double* txyz, long long n_tgt, int n_rhs, double a, bool smallz, int nser,
-                cd* A, hipStream_t s);
+                long long n_src, const double* txyz, long long n_tgt, int n_rhs, double a, bool smallz, cd* A,
+                hipStream_t s);
 void launch_fill_d(double* p, long long n, hipStream_t s);
 void launch_selftest_math(const double* x, long long n, double* out, hipStream_t s);
 void launch_l2p_grad(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_pts,
                      int n_rhs, const cd* LE, const cd* W, double* gX, int pi, hipStream_t s);
 void launch_p2p_grad(const DevPlan& d, const int* tboxes, int n, const double* sxyz, const cd* Jsrc,
-                     long long n_src, const double* txyz, const cd* W, long long n_tgt, int n_rhs, double k,
-                     double* gX, bool red, hipStream_t s);
+                     long long n_src, const double* txyz, const cd* W, long long n_tgt, int n_rhs, double* gX,
+                     bool red, hipStream_t s);

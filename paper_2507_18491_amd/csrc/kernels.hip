@@ -842,12 +842,14 @@ void launch_l2p(const DevPlan& d, const int* leaves, int n, int kind, const doub
 template <int RC, bool RED>
 __global__ __launch_bounds__(NT) void k_p2p(DevPlan d, const int* tboxes, const double* sxyz, const cd* J,
                                             long long n_src, const double* txyz, long long n_tgt, int n_rhs,
-                                            double k, cd* A) {
+                                            cd* A) {
   __shared__ double sp[NT][3];
   __shared__ cd sj[NT][RC][3];
-  // work item: (target leaf, chunk of NT targets)
+  // work item: (target leaf, chunk of NT targets); the wavenumber is that of
+  // the leaf's instance (its layer)
   int b = tboxes[2 * blockIdx.x];
   TgtBox tb = d.tbox[b];
+  const double k = d.inst[__builtin_amdgcn_readfirstlane(tb.inst)].kt;
   int r0 = blockIdx.y * RC, nr = min(RC, n_rhs - r0);
   int tid = threadIdx.x;
   const double inv4pi = 0.079577471545947667884;
@@ -909,22 +911,22 @@ __global__ __launch_bounds__(NT) void k_p2p(DevPlan d, const int* tboxes, const 
   }
 }
 void launch_p2p(const DevPlan& d, const int* tboxes, int n, const double* sxyz, const cd* J, long long n_src,
-                const double* txyz, long long n_tgt, int n_rhs, double k, cd* A, bool red, hipStream_t s) {
+                const double* txyz, long long n_tgt, int n_rhs, cd* A, bool red, hipStream_t s) {
   if (n <= 0) return;
   if (n_rhs == 1) {
     if (red)
       hipLaunchKernelGGL((k_p2p<1, true>), dim3(n, n_rhs), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src, txyz, n_tgt,
-                         n_rhs, k, A);
+                         n_rhs, A);
     else
       hipLaunchKernelGGL((k_p2p<1, false>), dim3(n, n_rhs), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src, txyz, n_tgt,
-                         n_rhs, k, A);
+                         n_rhs, A);
   } else {
     if (red)
       hipLaunchKernelGGL((k_p2p<4, true>), dim3(n, (n_rhs + 3) / 4), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src, txyz,
-                         n_tgt, n_rhs, k, A);
+                         n_tgt, n_rhs, A);
     else
       hipLaunchKernelGGL((k_p2p<4, false>), dim3(n, (n_rhs + 3) / 4), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src,
-                         txyz, n_tgt, n_rhs, k, A);
+                         txyz, n_tgt, n_rhs, A);
   }
 }
 
@@ -1218,12 +1220,13 @@ void launch_l2p_grad(const DevPlan& d, const int* leaves, int n, int kind, const
 template <bool RED>
 __global__ __launch_bounds__(NT) void k_p2p_grad(DevPlan d, const int* tboxes, const double* sxyz, const cd* Jsrc,
                                                  long long n_src, const double* txyz, const cd* W,
-                                                 long long n_tgt, int n_rhs, double k, double* gX) {
+                                                 long long n_tgt, int n_rhs, double* gX) {
   __shared__ double sp[NT][3];
   __shared__ cd sj[NT][3];
-  // work item: (target leaf, chunk of NT targets)
+  // work item: (target leaf, chunk of NT targets); wavenumber of its instance
   int b = tboxes[2 * blockIdx.x];
   TgtBox tb = d.tbox[b];
+  const double k = d.inst[__builtin_amdgcn_readfirstlane(tb.inst)].kt;
   int tid = threadIdx.x;
   const double inv4pi = 0.079577471545947667884;
   const double invk = 1.0 / k;
@@ -1297,15 +1300,15 @@ __global__ __launch_bounds__(NT) void k_p2p_grad(DevPlan d, const int* tboxes, c
   }
 }
 void launch_p2p_grad(const DevPlan& d, const int* tboxes, int n, const double* sxyz, const cd* Jsrc,
-                     long long n_src, const double* txyz, const cd* W, long long n_tgt, int n_rhs, double k,
-                     double* gX, bool red, hipStream_t s) {
+                     long long n_src, const double* txyz, const cd* W, long long n_tgt, int n_rhs, double* gX,
+                     bool red, hipStream_t s) {
   if (n <= 0) return;
   if (red)
     hipLaunchKernelGGL(k_p2p_grad<true>, dim3(n), dim3(NT), 0, s, d, tboxes, sxyz, Jsrc, n_src, txyz, W, n_tgt, n_rhs,
-                       k, gX);
+                       gX);
   else
     hipLaunchKernelGGL(k_p2p_grad<false>, dim3(n), dim3(NT), 0, s, d, tboxes, sxyz, Jsrc, n_src, txyz, W, n_tgt,
-                       n_rhs, k, gX);
+                       n_rhs, gX);
 }
 
 // ------------------------------------------------------------------ S2T
@@ -1337,7 +1340,7 @@ template <bool SMALLZ, int RS>
 __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md, const int* items,
                                                                      const double* sxyz, const cd* J,
                                                                      long long n_src, const double* txyz,
-                                                                     long long n_tgt, int n_rhs, double a, int nser,
+                                                                     long long n_tgt, int n_rhs, double a,
                                                                      cd* A) {
   __shared__ double tp[LM_S2T_CHUNK][3];  // targets: x, y, t
   __shared__ int seg_pt0[LM_S2T_SEG], seg_cum[LM_S2T_SEG + 1];
@@ -1353,6 +1356,7 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
   const int t0 = tb.pt0 + chunk * LM_S2T_CHUNK;
   const int nt = min(LM_S2T_CHUNK, tb.pt1 - t0);
   const int n0 = __builtin_amdgcn_readfirstlane(ip.s2t0), nn = __builtin_amdgcn_readfirstlane(ip.s2tn);
+  const int nser = __builtin_amdgcn_readfirstlane(ip.s2t_nser);
   const QNode* nodes = d.nodes + n0;
   const double dls = ip.up_s ? md.d[ip.ls - 1] : md.d[ip.ls];
   int id = 0;
@@ -1522,15 +1526,16 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
     }
   }
 }
-// smallz: |k_rho| rho <= 7.5 on Gamma_1 for every pair of the component;
-// nser: terms of the complex series there (1..LM_BPQ_NSERC)
+// items: work items of instances of one component type (never sharing a
+// target); smallz: |k_rho| rho <= 7.5 on Gamma_1 for all of their pairs (the
+// series length comes from each block's instance)
 void launch_s2t(const DevPlan& d, MediumDev md, const int* items, int n, const double* sxyz, const cd* J,
-                long long n_src, const double* txyz, long long n_tgt, int n_rhs, double a, bool smallz, int nser,
-                cd* A, hipStream_t s) {
+                long long n_src, const double* txyz, long long n_tgt, int n_rhs, double a, bool smallz, cd* A,
+                hipStream_t s) {
   if (n <= 0) return;
 #define LM_S2T_GO(SZ, RS)                                                                                   \
   hipLaunchKernelGGL((k_s2t<SZ, RS>), dim3(n, (n_rhs + RS - 1) / RS), dim3(LM_S2T_CHUNK), 0, s, d, md, items, \
-                     sxyz, J, n_src, txyz, n_tgt, n_rhs, a, nser, A)
+                     sxyz, J, n_src, txyz, n_tgt, n_rhs, a, A)
   if (n_rhs == 1) {
     if (smallz)
       LM_S2T_GO(true, 1);

@@ -32,6 +32,8 @@ struct InstParams {
   double Dgap;       // distance between the two anchor planes (reaction)
   int s2t0, s2tn;    // reaction: quadrature nodes of the direct (S2T) near field
   double s2t_rho;    // reaction: largest horizontal distance of an S2T pair (-1: none)
+  int s2t_nser;      // reaction: terms of the S2T complex Bessel series (Gamma_1)
+  int s2t_smallz;    // reaction: 1 if |k_rho| rho <= 7.5 on Gamma_1 for every S2T pair
 };
 
 // source-side box record (device)

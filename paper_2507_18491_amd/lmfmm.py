@@ -139,8 +139,8 @@ class LayeredDyadicFMM:
         return self
 
     def build_batch(self, srcs, tgts=None, stream=None):
-        """Several independent geometries in one plan (one launch per pass for
-        all of them).  srcs: list of [n_g, 3] arrays; tgts: list or None (targets
+        """Several independent geometries in one plan (each pass launched for
+        all of them together, see lm_build_batch).  srcs: list of [n_g, 3] arrays; tgts: list or None (targets
         = sources).  Currents and outputs are the concatenations in order;
         self.src_off / self.tgt_off give the geometry boundaries."""
         import torch
