@@ -389,6 +389,25 @@ struct MatKey {
   }
 };
 
+// one M2L pair (global box ids) with its class key and offset
+struct M2LRec {
+  int gid, l, px, py, c3, dx, dy, dz, s, t;
+};
+// lattice of an instance: instances with equal keys share M2L classes
+struct LatKey {
+  int free, lt, ls, up_t, up_s, p;
+  long long kq, s0q, tzq, szq, rq;
+  bool operator<(const LatKey& o) const {
+    return std::tie(free, lt, ls, up_t, up_s, p, kq, s0q, tzq, szq, rq) <
+           std::tie(o.free, o.lt, o.ls, o.up_t, o.up_s, o.p, o.kq, o.s0q, o.tzq, o.szq, o.rq);
+  }
+};
+struct LatGroup {
+  int inst;  // first instance of the group (its parameters serve the group)
+  bool free;
+  double S0, Tz0, Sz0, rref;
+};
+
 }  // namespace
 
 std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int64_t n_src,
@@ -507,11 +526,16 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       geo.push_back(g);
     }
   }
-  double S0 = ext * (1.0 + 1e-9) + 1e-300;
-  if (!(S0 > 0)) S0 = 1.0;
+  // root size: the power of two at or above the extent (with room for the
+  // anchor snapping of the reaction trees below), a function of this
+  // geometry alone, so that geometries of like size share box sizes level by
+  // level (and translation tables) whether built together or apart
+  const double need = ext * (1.0 + 1.0 / 256) + 1e-300;
+  double S0 = 1.0;
+  while (S0 < need) S0 *= 2.0;
+  while (S0 * 0.5 >= need) S0 *= 0.5;
   double eps = 1e-9 * S0;
   double X0 = xmin - eps, Y0 = ymin - eps;
-  S0 += 2 * eps;
   for (size_t q = geo0; q < geo.size(); q++) {
     geo[q].S0 = S0;
     geo[q].eps = eps;
@@ -540,8 +564,11 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
   int KB = (pmax + 1) / 2;  // maximal Chebyshev index K_n
   pl.kmaxcheb = KB;
   std::map<std::tuple<int, int, long long, long long, long long>, int> casemap;
-  std::vector<double> case_dz;  // vertical centre separation of each case
   std::vector<double> off_ratio;  // per M2L offset: (r_s + r_t) / |c_t - c_s|
+  std::vector<M2LRec> recs;       // M2L pairs of every instance
+  std::map<LatKey, int> latmap;
+  std::vector<LatGroup> lat;
+  std::vector<double> inst_S0;    // root size of each instance's lattice
 
   std::vector<double> s2t_rho_of;  // per instance: largest horizontal S2T pair distance, -1 if none
   for (auto& g : geo) {
@@ -627,18 +654,27 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       build_tree(S, pos, ids, tags, [&](int l, int n, int, double) { return n > 0 && l < D; });
       pl.free_depth_used.push_back(D);
     } else {
+      // anchors on the two sides of the gap, moved outward to multiples of a
+      // power-of-two fraction delta of S0 (at most S0 / 1024 and an eighth of
+      // the gap), so that geometries whose points come equally close to the
+      // interface share anchors, hence M2L tables and GEMMs
+      const double raw = ip.sgn > 0 ? (g.zt0 - eps) - (g.zs1 + eps) : (g.zs0 - eps) - (g.zt1 + eps);
+      double delta = S0 / 1024.0;
+      while (delta > raw / 8.0) delta *= 0.5;
       if (ip.sgn > 0) {
-        S.z0 = g.zs1 + eps - S0;
+        const double tb = floor((g.zt0 - eps) / delta) * delta, st = ceil((g.zs1 + eps) / delta) * delta;
+        S.z0 = st - S0;
         S.zflip = 1;
-        T.z0 = g.zt0 - eps;
+        T.z0 = tb;
         T.zflip = 0;
-        Dgap = (g.zt0 - eps) - (g.zs1 + eps);
+        Dgap = tb - st;
       } else {
-        S.z0 = g.zs0 - eps;
+        const double sb = floor((g.zs0 - eps) / delta) * delta, tt = ceil((g.zt1 + eps) / delta) * delta;
+        S.z0 = sb;
         S.zflip = 0;
-        T.z0 = g.zt1 + eps - S0;
+        T.z0 = tt - S0;
         T.zflip = 1;
-        Dgap = (g.zs0 - eps) - (g.zt1 + eps);
+        Dgap = sb - tt;
       }
       // D1: the first level whose boxes are no larger than the gap (no
       // adjacent source/target leaves remain).  With the direct near field
@@ -714,7 +750,6 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
     ip.Dgap = Dgap;
     (void)depth_used;
     HTree& TT = free ? S : T;  // target tree
-    int inst_off0 = (int)pl.offs.size();
 
     // ---- boxes -> global records
     int sbase = (int)pl.sbox.size(), tbase = (int)pl.tbox.size();
@@ -923,29 +958,102 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
     (free ? pl.n_m2l_pairs_free : pl.n_m2l_pairs_react) += (long long)m2l.size();
     (free ? pl.n_free_inst : pl.n_react_inst)++;
 
-    // ---- M2L classes
-    // class key: level, parity of ix, iy, and iz parity (free) or gap index j (reaction)
-    std::map<std::tuple<int, int, int, int>, std::vector<Pair>> byclass;
+    // ---- M2L pairs of this instance, for the classes formed below across
+    // instances.  The worst separation ratio rho = (r_s + r_t) / |c_t - c_s|
+    // of the instance's pairs sets its adaptive orders; instances share
+    // classes (and tables) when their lattices agree: same kind and
+    // component, order, root size, anchors and worst ratio.
+    double rref = 0;
     for (auto& pr : m2l) {
       int t = pr.t;
       int l = TT.lvl[t];
-      int c3 = free ? (TT.iz[t] & 1) : TT.j(t);
-      byclass[std::make_tuple(l, TT.ix[t] & 1, TT.iy[t] & 1, c3)].push_back(pr);
+      double Sl = S0 / (double)(1 << l);
+      M2LRec rec;
+      rec.l = l;
+      rec.px = TT.ix[t] & 1;
+      rec.py = TT.iy[t] & 1;
+      rec.c3 = free ? (TT.iz[t] & 1) : TT.j(t);
+      rec.dx = S.ix[pr.s] - TT.ix[t];
+      rec.dy = S.iy[pr.s] - TT.iy[t];
+      rec.dz = free ? S.iz[pr.s] - TT.iz[t] : S.j(pr.s);
+      rec.s = sbase + pr.s;
+      rec.t = tbase + t;
+      double r;
+      if (free) {
+        r = sqrt(3.0) / sqrt((double)(rec.dx * rec.dx + rec.dy * rec.dy + rec.dz * rec.dz));
+      } else {
+        const int jt = rec.c3, js = rec.dz;
+        double zt_img = ip.sgn > 0 ? T.z0 + (jt + 0.5) * Sl : T.z0 + S0 - (jt + 0.5) * Sl;
+        double zs_img = ip.sgn > 0 ? S.z0 + S0 - (js + 0.5) * Sl : S.z0 + (js + 0.5) * Sl;
+        double R = sqrt((double)(rec.dx * rec.dx + rec.dy * rec.dy) * Sl * Sl + (zt_img - zs_img) * (zt_img - zs_img));
+        r = sqrt(3.0) * Sl / R;
+      }
+      rref = std::max(rref, r);
+      recs.push_back(rec);
     }
+    {
+      LatKey key;
+      key.free = free ? 1 : 0;
+      key.lt = ip.lt;
+      key.ls = ip.ls;
+      key.up_t = ip.up_t;
+      key.up_s = ip.up_s;
+      key.p = ip.p;
+      key.kq = kquant(ip.kt);
+      key.s0q = kquant(S0);
+      key.tzq = free ? 0 : kquant(T.z0);
+      key.szq = free ? 0 : kquant(S.z0);
+      key.rq = kquant(rref);
+      auto it = latmap.find(key);
+      int gid;
+      if (it == latmap.end()) {
+        gid = (int)lat.size();
+        latmap[key] = gid;
+        LatGroup lg;
+        lg.inst = inst;
+        lg.free = free;
+        lg.S0 = S0;
+        lg.Tz0 = T.z0;
+        lg.Sz0 = S.z0;
+        lg.rref = rref;
+        lat.push_back(lg);
+      } else {
+        gid = it->second;
+      }
+      for (size_t q = recs.size() - m2l.size(); q < recs.size(); q++) recs[q].gid = gid;
+    }
+    inst_S0.push_back(S0);
+    pl.inst.push_back(ip);
+  }
+
+  // ---- M2L classes, across instances of one lattice group: key (group,
+  // level, parity of ix, iy, and iz parity (free) or gap index j (reaction)).
+  // A target's pairs, offsets, matrices and orders are those of its own
+  // instance alone, so a geometry in a batch computes exactly what its own
+  // build computes; the batch only puts more pairs into each GEMM.
+  {
+    std::map<std::tuple<int, int, int, int, int>, std::vector<const M2LRec*>> byclass;
+    for (const M2LRec& r : recs) byclass[std::make_tuple(r.gid, r.l, r.px, r.py, r.c3)].push_back(&r);
+    std::vector<std::vector<int>> group_offs(lat.size());
     for (auto& kv : byclass) {
-      int l = std::get<0>(kv.first);
+      const int gid = std::get<0>(kv.first);
+      const LatGroup& lg = lat[gid];
+      const InstParams& ip = pl.inst[lg.inst];
+      const bool free = lg.free;
+      const int inst = lg.inst;
+      const int P = ip.P;
+      const double S0 = lg.S0;
+      int l = std::get<1>(kv.first);
       double Sl = S0 / (double)(1 << l);
       auto& prs = kv.second;
       std::map<std::tuple<int, int, int>, int> offmap;
       std::map<int, int> tslot;
       std::vector<int> tlist;
-      for (auto& pr : prs) {
-        int dx = S.ix[pr.s] - TT.ix[pr.t], dy = S.iy[pr.s] - TT.iy[pr.t];
-        int dz = free ? S.iz[pr.s] - TT.iz[pr.t] : S.j(pr.s);
-        offmap.emplace(std::make_tuple(dx, dy, dz), 0);
-        if (!tslot.count(pr.t)) {
-          tslot[pr.t] = (int)tlist.size();
-          tlist.push_back(pr.t);
+      for (const M2LRec* pr : prs) {
+        offmap.emplace(std::make_tuple(pr->dx, pr->dy, pr->dz), 0);
+        if (!tslot.count(pr->t)) {
+          tslot[pr->t] = (int)tlist.size();
+          tlist.push_back(pr->t);
         }
       }
       M2LClass C;
@@ -957,11 +1065,12 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       C.nblk = free ? 1 : 3;
       C.P = P;
       int oi = 0;
-      int jt = std::get<3>(kv.first);
+      int jt = std::get<4>(kv.first);
       for (auto& ov : offmap) {
         ov.second = oi++;
         int dx = std::get<0>(ov.first), dy = std::get<1>(ov.first), dz = std::get<2>(ov.first);
         M2LOffset mo;
+        group_offs[gid].push_back((int)pl.offs.size());
         if (free) {
           TransJob j;
           j.b[0] = -dx * Sl;
@@ -970,15 +1079,16 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
           j.k = ip.kt;
           j.p = ip.p;
           j.kind = 0;
-          long long m = alloc_mat(MatKey{0, kquant(ip.kt), ip.p, kquant(S0 / (double)(1 << l)), dx, dy, dz},
-                                  (long long)P * P, &j);
+          long long m = alloc_mat(MatKey{0, kquant(ip.kt), ip.p, kquant(Sl), dx, dy, dz}, (long long)P * P, &j);
           mo.mat[0] = mo.mat[1] = mo.mat[2] = m;
           mo.phi = 0;
           off_ratio.push_back(sqrt(3.0) / sqrt((double)(dx * dx + dy * dy + dz * dz)));
         } else {
           int js = dz;
           int r2 = dx * dx + dy * dy;
-          auto ck = std::make_tuple(inst, l, (long long)r2, (long long)jt, (long long)js);
+          double zt_img = ip.sgn > 0 ? lg.Tz0 + (jt + 0.5) * Sl : lg.Tz0 + S0 - (jt + 0.5) * Sl;
+          double zs_img = ip.sgn > 0 ? lg.Sz0 + S0 - (js + 0.5) * Sl : lg.Sz0 + (js + 0.5) * Sl;
+          auto ck = std::make_tuple(gid, l, (long long)r2, (long long)jt, (long long)js);
           int cid;
           auto it = casemap.find(ck);
           if (it == casemap.end()) {
@@ -989,31 +1099,18 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
             tc.inst = inst;
             tc.rho = sqrt((double)r2) * Sl;
             // centres: target box with gap index jt, source box with gap index js
-            double zt_img, zs_img;
-            if (ip.sgn > 0) {
-              zt_img = T.z0 + (jt + 0.5) * Sl;
-              zs_img = S.z0 + S0 - (js + 0.5) * Sl;
-            } else {
-              zt_img = T.z0 + S0 - (jt + 0.5) * Sl;
-              zs_img = S.z0 + (js + 0.5) * Sl;
-            }
             tc.zt_orig = ip.at * (zt_img - ip.bt);
             tc.zs_orig = ip.as * (zs_img - ip.bs);
             tc.node0 = l;  // temporarily the level
             tc.nnode = 0;
-            case_dz.push_back(ip.sgn * (zt_img - zs_img));
             tc.mat = pl.mat_size;
             pl.mat_size += 9LL * P * P;
             pl.cases.push_back(tc);
           } else
             cid = it->second;
           long long base = pl.cases[cid].mat;
-          {
-            double zt_img = ip.sgn > 0 ? T.z0 + (jt + 0.5) * Sl : T.z0 + S0 - (jt + 0.5) * Sl;
-            double zs_img = ip.sgn > 0 ? S.z0 + S0 - (js + 0.5) * Sl : S.z0 + (js + 0.5) * Sl;
-            double R = sqrt((double)(dx * dx + dy * dy) * Sl * Sl + (zt_img - zs_img) * (zt_img - zs_img));
-            off_ratio.push_back(sqrt(3.0) * Sl / R);
-          }
+          double R = sqrt((double)(dx * dx + dy * dy) * Sl * Sl + (zt_img - zs_img) * (zt_img - zs_img));
+          off_ratio.push_back(sqrt(3.0) * Sl / R);
           mo.mat[0] = base;
           mo.mat[1] = base + 3LL * P * P;
           mo.mat[2] = base + 6LL * P * P;
@@ -1026,33 +1123,30 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       pl.cls_srcof0.push_back((long long)pl.cls_srcof.size());
       size_t base = pl.cls_srcof.size();
       pl.cls_srcof.resize(base + (size_t)C.n_tgt * C.n_off, -1);
-      for (auto& pr : prs) {
-        int dx = S.ix[pr.s] - TT.ix[pr.t], dy = S.iy[pr.s] - TT.iy[pr.t];
-        int dz = free ? S.iz[pr.s] - TT.iz[pr.t] : S.j(pr.s);
-        int o = offmap[std::make_tuple(dx, dy, dz)];
-        pl.cls_srcof[base + (size_t)tslot[pr.t] * C.n_off + o] = sbase + pr.s;
+      for (const M2LRec* pr : prs) {
+        int o = offmap[std::make_tuple(pr->dx, pr->dy, pr->dz)];
+        pl.cls_srcof[base + (size_t)tslot[pr->t] * C.n_off + o] = pr->s;
       }
-      for (int t : tlist) pl.cls_tgt.push_back(tbase + t);
+      for (int t : tlist) pl.cls_tgt.push_back(t);
       pl.cls.push_back(C);
     }
     // per-offset orders: the truncation error of an M2L pair behaves like
-    // rho^(p+1), rho = (r_s + r_t)/|c_t - c_s|.  Every offset gets the least
-    // order whose bound lies m2l_margin decades below the bound of the
-    // instance's worst admissible pair at order p (the margin accounts for
-    // the many better-separated pairs that would otherwise all contribute
-    // the worst pair's error).
-    if (prm.m2l_adapt && inst_off0 < (int)pl.offs.size()) {
-      double rref = 0;
-      for (int o = inst_off0; o < (int)pl.offs.size(); o++) rref = std::max(rref, off_ratio[o]);
-      double target = (ip.p + 1) * log(rref) - prm.m2l_margin * log(10.0);
-      for (int o = inst_off0; o < (int)pl.offs.size(); o++) {
-        double r = off_ratio[o];
-        int q = ip.p;
-        if (r < rref && rref < 1.0) q = (int)ceil(target / log(r)) - 1;
-        pl.offs[o].pord = std::min(ip.p, std::max(2, q));
+    // rho^(p+1).  Every offset gets the least order whose bound lies
+    // m2l_margin decades below the bound of the group's worst admissible
+    // pair at order p (the margin accounts for the many better-separated
+    // pairs that would otherwise all contribute the worst pair's error).
+    if (prm.m2l_adapt)
+      for (size_t gid = 0; gid < lat.size(); gid++) {
+        const double rr = lat[gid].rref;
+        const int p = pl.inst[lat[gid].inst].p;
+        double target = (p + 1) * log(rr) - prm.m2l_margin * log(10.0);
+        for (int o : group_offs[gid]) {
+          double r = off_ratio[o];
+          int q = p;
+          if (r < rr && rr < 1.0) q = (int)ceil(target / log(r)) - 1;
+          pl.offs[o].pord = std::min(p, std::max(2, q));
+        }
       }
-    }
-    pl.inst.push_back(ip);
   }
 
   // ---- M2L work blocks: targets of a class in groups of at most 2048, pairs
@@ -1105,18 +1199,15 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
     double a = prm.contour_a > 0 ? prm.contour_a : 1.5 * med.kmax;
     double kg = med.kmax;
     if (!(a > kg)) return "contour end point must exceed the largest wavenumber";
+    // per (lattice group, level): the largest horizontal distance and the
+    // smallest vertical centre separation an interaction-list pair of the
+    // level can have (offsets up to 3 boxes in x and y; both boxes next to
+    // the gap), so that the node set depends on the lattice alone
     std::map<std::pair<int, int>, std::pair<double, double>> lvinfo;  // rho_max, dz_min
     for (size_t ci = 0; ci < pl.cases.size(); ci++) {
       auto& tc = pl.cases[ci];
-      auto key = std::make_pair(tc.inst, tc.node0);
-      double dz = case_dz[ci];
-      auto it = lvinfo.find(key);
-      if (it == lvinfo.end())
-        lvinfo[key] = std::make_pair(tc.rho, dz);
-      else {
-        it->second.first = std::max(it->second.first, tc.rho);
-        it->second.second = std::min(it->second.second, dz);
-      }
+      const double Sl = inst_S0[tc.inst] / (double)(1 << tc.node0);
+      lvinfo[std::make_pair(tc.inst, tc.node0)] = std::make_pair(3.0 * sqrt(2.0) * Sl, pl.inst[tc.inst].Dgap + Sl);
     }
     std::map<std::pair<int, int>, std::pair<int, int>> nodemap;
     std::vector<double> gx, gw;
