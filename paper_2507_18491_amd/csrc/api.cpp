@@ -29,9 +29,15 @@ struct lm_ctx {
   std::vector<void*> allocs;  // persistent device buffers of the current build
   double* d_src = nullptr;
   double* d_tgt = nullptr;
-  int* d_p2m = nullptr;       // P2M leaves of instances with p <= 12
-  int* d_p2m_hi = nullptr;    // P2M leaves of higher-order instances
-  int n_p2m_lo = 0, n_p2m_hi = 0, p2m_plo = 0, p2m_phi = 0;
+  // P2M work items (leaf, chunk, slot) of instances with p <= 12 ([0]) and
+  // of higher orders ([1]), the sums of the leaves of several chunks (leaf,
+  // first slot, chunks), and the scratch slots of those partials
+  int* d_p2m[2] = {nullptr, nullptr};
+  int* d_p2m_sum[2] = {nullptr, nullptr};
+  int n_p2m[2] = {0, 0}, n_p2m_sum[2] = {0, 0}, p2m_p[2] = {0, 0};
+  long long p2m_slots[2] = {0, 0};
+  cd* p2m_part = nullptr;     // partial expansions [slot][rhs][3][(p+1)^2] of both groups
+  long long p2m_part_cap = 0;
   std::vector<int*> d_m2m, d_l2l, d_l2p, d_p2p;
   std::vector<int> n_m2m, n_l2l, n_l2p, n_p2p;
   std::vector<int> l2p_inst;  // an instance of each L2P launch group (its kind and order)
@@ -111,6 +117,14 @@ static void free_build(lm_ctx* ctx) {
   ctx->y_cap = 0;
   ctx->ME = ctx->LE = nullptr;
   ctx->me_cap = ctx->le_cap = 0;
+  if (ctx->p2m_part) hipFree(ctx->p2m_part);
+  ctx->p2m_part = nullptr;
+  ctx->p2m_part_cap = 0;
+  for (int g = 0; g < 2; g++) {
+    ctx->d_p2m[g] = ctx->d_p2m_sum[g] = nullptr;
+    ctx->n_p2m[g] = ctx->n_p2m_sum[g] = ctx->p2m_p[g] = 0;
+    ctx->p2m_slots[g] = 0;
+  }
   ctx->d_m2m.clear();
   ctx->d_l2l.clear();
   ctx->d_l2p.clear();
@@ -381,24 +395,32 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
     // leaves of low-order instances (reaction components, typically few points
     // each) and of high-order ones are launched separately, each with LDS
     // sized for its own order
-    std::vector<int> lo, hi;
-    int plo = 0, phi = 0;
+    // P2M work items: leaves of up to LM_P2M_CHUNK points write their
+    // expansion; larger leaves are cut into chunks whose partials land in
+    // scratch slots and are summed in chunk order (dense leaves spread over
+    // many workgroups)
+    std::vector<int> items[2], sums[2];
     for (int b : pl.p2m_leaves) {
-      int ip = pl.inst[pl.sbox[b].inst].p;
-      if (ip <= 12) {
-        lo.push_back(b);
-        plo = std::max(plo, ip);
-      } else {
-        hi.push_back(b);
-        phi = std::max(phi, ip);
+      const int ip = pl.inst[pl.sbox[b].inst].p;
+      const int g = ip <= 12 ? 0 : 1;
+      ctx->p2m_p[g] = std::max(ctx->p2m_p[g], ip);
+      const int n = pl.sbox[b].pt1 - pl.sbox[b].pt0;
+      const int nch = (n + LM_P2M_CHUNK - 1) / LM_P2M_CHUNK;
+      if (nch <= 1) {
+        items[g].insert(items[g].end(), {b, 0, -1});
+        continue;
       }
+      const int slot0 = (int)ctx->p2m_slots[g];
+      for (int c = 0; c < nch; c++) items[g].insert(items[g].end(), {b, c, slot0 + c});
+      sums[g].insert(sums[g].end(), {b, slot0, nch});
+      ctx->p2m_slots[g] += nch;
     }
-    if ((rc = upload(ctx, &ctx->d_p2m, lo))) return rc;
-    if ((rc = upload(ctx, &ctx->d_p2m_hi, hi))) return rc;
-    ctx->n_p2m_lo = (int)lo.size();
-    ctx->n_p2m_hi = (int)hi.size();
-    ctx->p2m_plo = plo;
-    ctx->p2m_phi = phi;
+    for (int g = 0; g < 2; g++) {
+      if ((rc = upload(ctx, &ctx->d_p2m[g], items[g]))) return rc;
+      if ((rc = upload(ctx, &ctx->d_p2m_sum[g], sums[g]))) return rc;
+      ctx->n_p2m[g] = (int)items[g].size() / 3;
+      ctx->n_p2m_sum[g] = (int)sums[g].size() / 3;
+    }
   }
   for (auto& v : pl.m2m_parents) {
     int* p = nullptr;
@@ -589,8 +611,11 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
 static int ensure_rhs(lm_ctx* ctx, int n_rhs, hipStream_t s) {
   Plan& pl = ctx->plan;
   long long me = pl.me_size * n_rhs, le = pl.le_size * n_rhs;
+  long long part = 0;  // P2M partials of both groups
+  for (int g = 0; g < 2; g++) part += ctx->p2m_slots[g] * n_rhs * 3LL * (ctx->p2m_p[g] + 1) * (ctx->p2m_p[g] + 1);
   bool have = ctx->tilesets.count(n_rhs) > 0;
-  if (me <= ctx->me_cap && le <= ctx->le_cap && have && ctx->tilesets[n_rhs].y_need <= ctx->y_cap) {
+  if (me <= ctx->me_cap && le <= ctx->le_cap && part <= ctx->p2m_part_cap && have &&
+      ctx->tilesets[n_rhs].y_need <= ctx->y_cap) {
     lm_ctx::TileSet& ts = ctx->tilesets[n_rhs];
     ctx->d.tiles = ts.d_tiles;
     ctx->d.blk_ybase = ts.d_ybase;
@@ -608,6 +633,12 @@ static int ensure_rhs(lm_ctx* ctx, int n_rhs, hipStream_t s) {
     ctx->LE = nullptr;
     HIPC(hipMalloc((void**)&ctx->LE, (size_t)std::max(1LL, le) * sizeof(cd)));
     ctx->le_cap = le;
+  }
+  if (part > ctx->p2m_part_cap) {
+    if (ctx->p2m_part) hipFree(ctx->p2m_part);
+    ctx->p2m_part = nullptr;
+    HIPC(hipMalloc((void**)&ctx->p2m_part, (size_t)part * sizeof(cd)));
+    ctx->p2m_part_cap = part;
   }
   if (!have) {
     // chunks of whole blocks whose M2L outputs fit the scratch budget;
@@ -905,8 +936,13 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
   if (pl.n_src > 0 && pl.n_tgt > 0) launch_fill(ctx->LE, pl.le_size * n_rhs, s);
   mark(1);
   if (pl.n_src > 0 && pl.n_tgt > 0) {
-    launch_p2m(d, ctx->d_p2m, ctx->n_p2m_lo, ctx->d_src, Jc, pl.n_src, n_rhs, ctx->ME, ctx->p2m_plo, s);
-    launch_p2m(d, ctx->d_p2m_hi, ctx->n_p2m_hi, ctx->d_src, Jc, pl.n_src, n_rhs, ctx->ME, ctx->p2m_phi, s);
+    cd* part = ctx->p2m_part;
+    for (int g = 0; g < 2; g++) {
+      const int pg = ctx->p2m_p[g], Pg = (pg + 1) * (pg + 1);
+      launch_p2m(d, ctx->d_p2m[g], ctx->n_p2m[g], ctx->d_src, Jc, pl.n_src, n_rhs, ctx->ME, part, pg, s);
+      launch_p2m_sum(d, ctx->d_p2m_sum[g], ctx->n_p2m_sum[g], n_rhs, part, Pg, ctx->ME, s);
+      part += ctx->p2m_slots[g] * n_rhs * 3 * Pg;
+    }
     mark(2);
     for (int l = (int)ctx->d_m2m.size() - 1; l >= 0; l--)
       launch_m2m(d, ctx->d_m2m[l], ctx->n_m2m[l], n_rhs, ctx->ME, ctx->pmax, s);

@@ -55,8 +55,10 @@ void launch_nodes(const DevPlan& d, MediumDev med, int n_nodes, const int* node_
 void launch_tab_integrals(const DevPlan& d, MediumDev med, int case0, int ncase, int p, cd* scratch,
                           long long scratch_stride, hipStream_t s);
 void launch_tab_assemble(const DevPlan& d, int case0, int ncase, int p, int kmaxcheb, int bstride, hipStream_t s);
-void launch_p2m(const DevPlan& d, const int* leaves, int n, const double* xyz, const cd* J,
-                long long n_src, int n_rhs, cd* ME, int pl, hipStream_t s);
+void launch_p2m(const DevPlan& d, const int* items, int n, const double* xyz, const cd* J, long long n_src,
+                int n_rhs, cd* ME, cd* part, int pl, hipStream_t s);
+void launch_p2m_sum(const DevPlan& d, const int* items, int n, int n_rhs, const cd* part, int Pg, cd* ME,
+                    hipStream_t s);
 void launch_m2m(const DevPlan& d, const int* parents, int n, int n_rhs, cd* ME, int pmax, hipStream_t s);
 // tile-shape variants of the M2L GEMM kernel (LM_M2L_VARIANTS of the C ABI)
 void launch_m2l(const DevPlan& d, const M2LTile* tiles, int n_tiles, int n_rhs, const cd* ME, cd* Y, int pmax,

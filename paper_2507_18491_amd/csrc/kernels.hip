@@ -109,16 +109,22 @@ void launch_fill(cd* p, long long n, hipStream_t s) {
 // M[r][ch][nm] = sum_j q_j^ch j_n(k |d_j|) conj(Y^m_n(d_j)),  d_j = image(x_j) - centre
 // (paper Sec. 2, the multipole coefficients, and Sec. 3.3, the reaction ME
 // coefficients; the constant 4 pi lives in the M2L tables).
-// NTB threads per leaf, each owning H coefficients (P <= NTB H); point
-// records (basis values, charges) staged in LDS NPT points at a time.  Reaction
-// leaves hold few points (often one or two near the interfaces), so they are
-// run with one-wave blocks and LDS sized for their own order.
+// Work item (leaf, chunk of LM_P2M_CHUNK points, slot): NTB threads, each
+// owning H coefficients (P <= NTB H); point records (basis values, charges)
+// staged in LDS NPT points at a time.  A leaf of one chunk (slot < 0) writes
+// its expansion; each chunk of a larger leaf writes a partial expansion to
+// slot `slot` of `part` ([slot][rhs][3][Pg]), summed in chunk order by
+// k_p2m_sum.  Reaction leaves hold few points (often one or two near the
+// interfaces), so they are run with one-wave blocks and LDS sized for their
+// own order.
 template <int RC, int NTB, int H, int NPT>
-__global__ __launch_bounds__(NTB) void k_p2m(DevPlan d, const int* leaves, const double* xyz, const cd* J,
-                                             long long n_src, int n_rhs, cd* ME) {
+__global__ __launch_bounds__(NTB) void k_p2m(DevPlan d, const int* items, const double* xyz, const cd* J,
+                                             long long n_src, int n_rhs, cd* ME, cd* part, int Pg) {
   extern __shared__ double sm[];
-  int b = leaves[blockIdx.x];
+  const int b = items[3 * blockIdx.x], chunk = items[3 * blockIdx.x + 1], slot = items[3 * blockIdx.x + 2];
   SrcBox sb = d.sbox[b];
+  sb.pt0 += chunk * LM_P2M_CHUNK;
+  sb.pt1 = min(sb.pt1, sb.pt0 + LM_P2M_CHUNK);
   InstParams ip = d.inst[sb.inst];
   int p = ip.p, P = ip.P, ntri = (p + 1) * (p + 2) / 2;
   int r0 = blockIdx.y * RC, nr = min(RC, n_rhs - r0);
@@ -189,32 +195,58 @@ __global__ __launch_bounds__(NTB) void k_p2m(DevPlan d, const int* leaves, const
     int nm = tid + NTB * h;
     if (nm >= P) continue;
     for (int rr = 0; rr < nr; rr++)
-      for (int c = 0; c < 3; c++) ME[sb.me_off * n_rhs + ((long long)(r0 + rr) * 3 + c) * P + nm] = acc[h][rr][c];
+      for (int c = 0; c < 3; c++) {
+        if (slot < 0)
+          ME[sb.me_off * n_rhs + ((long long)(r0 + rr) * 3 + c) * P + nm] = acc[h][rr][c];
+        else
+          part[(((long long)slot * n_rhs + r0 + rr) * 3 + c) * Pg + nm] = acc[h][rr][c];
+      }
   }
 }
+// ME of a leaf of several chunks: its partials (slots slot0 .. slot0+nch-1)
+// added in chunk order.  Work item (leaf, slot0, nch).
+__global__ __launch_bounds__(NT) void k_p2m_sum(DevPlan d, const int* items, int n_rhs, const cd* part, int Pg,
+                                                cd* ME) {
+  const int b = items[3 * blockIdx.x], slot0 = items[3 * blockIdx.x + 1], nch = items[3 * blockIdx.x + 2];
+  const SrcBox sb = d.sbox[b];
+  const int P = d.inst[sb.inst].P;
+  const int nel = n_rhs * 3 * P;
+  for (int e = threadIdx.x; e < nel; e += NT) {
+    const int rc = e / P, nm = e - rc * P;  // rc = rhs * 3 + channel
+    cd acc = cd{0, 0};
+    for (int c = 0; c < nch; c++) acc = acc + part[((long long)(slot0 + c) * n_rhs * 3 + rc) * Pg + nm];
+    ME[sb.me_off * n_rhs + (long long)rc * P + nm] = acc;
+  }
+}
+void launch_p2m_sum(const DevPlan& d, const int* items, int n, int n_rhs, const cd* part, int Pg, cd* ME,
+                    hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_p2m_sum, dim3(n), dim3(NT), 0, s, d, items, n_rhs, part, Pg, ME);
+}
 template <int RC, int NTB, int H, int NPT>
-static void p2m_go(const DevPlan& d, const int* leaves, int n, const double* xyz, const cd* J, long long n_src,
-                   int n_rhs, cd* ME, int pl, hipStream_t s) {
+static void p2m_go(const DevPlan& d, const int* items, int n, const double* xyz, const cd* J, long long n_src,
+                   int n_rhs, cd* ME, cd* part, int pl, hipStream_t s) {
   int ntri = (pl + 1) * (pl + 2) / 2;
   size_t shm = (size_t)NPT * ((pl + 1) + ntri + 2 * (pl + 1) + RC * 6) * sizeof(double);
   set_dyn_lds((const void*)k_p2m<RC, NTB, H, NPT>, shm);
-  hipLaunchKernelGGL((k_p2m<RC, NTB, H, NPT>), dim3(n, (n_rhs + RC - 1) / RC), dim3(NTB), shm, s, d, leaves, xyz, J,
-                     n_src, n_rhs, ME);
+  hipLaunchKernelGGL((k_p2m<RC, NTB, H, NPT>), dim3(n, (n_rhs + RC - 1) / RC), dim3(NTB), shm, s, d, items, xyz, J,
+                     n_src, n_rhs, ME, part, (pl + 1) * (pl + 1));
 }
-// pl: the largest order among the listed leaves' instances
-void launch_p2m(const DevPlan& d, const int* leaves, int n, const double* xyz, const cd* J, long long n_src,
-                int n_rhs, cd* ME, int pl, hipStream_t s) {
+// items: n work items (leaf, chunk, slot); pl: the largest order among their
+// instances (the slot stride of `part` is (pl+1)^2)
+void launch_p2m(const DevPlan& d, const int* items, int n, const double* xyz, const cd* J, long long n_src,
+                int n_rhs, cd* ME, cd* part, int pl, hipStream_t s) {
   if (n <= 0) return;
   bool rc1 = n_rhs == 1;
   int P = (pl + 1) * (pl + 1);
   if (P <= 64 * 3 && rc1)
-    p2m_go<1, 64, 3, 16>(d, leaves, n, xyz, J, n_src, n_rhs, ME, pl, s);
+    p2m_go<1, 64, 3, 16>(d, items, n, xyz, J, n_src, n_rhs, ME, part, pl, s);
   else if (P <= 128 * 2 && !rc1)
-    p2m_go<4, 128, 2, 16>(d, leaves, n, xyz, J, n_src, n_rhs, ME, pl, s);
+    p2m_go<4, 128, 2, 16>(d, items, n, xyz, J, n_src, n_rhs, ME, part, pl, s);
   else if (rc1)
-    p2m_go<1, NT, 2, 32>(d, leaves, n, xyz, J, n_src, n_rhs, ME, pl, s);
+    p2m_go<1, NT, 2, 32>(d, items, n, xyz, J, n_src, n_rhs, ME, part, pl, s);
   else
-    p2m_go<4, NT, 2, 32>(d, leaves, n, xyz, J, n_src, n_rhs, ME, pl, s);
+    p2m_go<4, NT, 2, 32>(d, items, n, xyz, J, n_src, n_rhs, ME, part, pl, s);
 }
 
 // ------------------------------------------------------------------ M2M

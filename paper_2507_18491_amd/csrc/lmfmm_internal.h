@@ -12,6 +12,7 @@
 #define LM_MAXL 16
 #define LM_PMAX 24
 #define LM_P2P_CHUNK 256   // targets per near-field work item (= threads per block)
+#define LM_P2M_CHUNK 512   // source points per P2M work item (larger leaves: partials, summed)
 #define LM_L2P_CHUNK(kind) ((kind) == 0 ? 256 : 64)   // points per L2P work item (free / reaction)
 #define LM_S2T_CHUNK 64    // targets per reaction near-field work item (= threads per block)
 #define LM_S2T_DIGITS 36.0 // the S2T tail stops where e^{-k (t + u)} < e^{-36}
