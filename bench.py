@@ -33,7 +33,7 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 fp64 FMA/clk x 2 flop x 2.4 GHz (fp
 # kernels.hip) and the same launches per step (the plan's split of the M2L
 # work); otherwise reported as null.
 K_M2L_TRAFFIC = {"digest": "d399e554001bfd19", "launches_per_step": 8,
-                 "fetch_bytes": 1.7669e7 * 1024 * 2.0, "write_bytes": 5.4397e6 * 1024 * 1.0}
+                 "fetch_bytes": 1.7712e7 * 1024 * 2.0, "write_bytes": 5.4600e6 * 1024 * 1.0}
 
 
 def m2l_source_digest():
