@@ -153,3 +153,36 @@ def direct_free(d, k, src, J, tgt, n_threads=None):
     if rc:
         raise ValueError("oracle failed (rc=%d)" % rc)
     return A
+
+
+def dense_operator(d, k, pts, n_threads=None):
+    """The matrix M [3n, 3n] of the layered sum on one point set (sources =
+    targets): (M J)[3i + a] = sum_j sum_b G_ab(x_i, x_j) J[3j + b], built
+    column by column from the direct sum applied to unit currents."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+    n = pts.shape[0]
+    M = np.zeros((3 * n, 3 * n), dtype=np.complex128)
+    for c0 in range(0, 3 * n, 64):
+        cols = np.arange(c0, min(3 * n, c0 + 64))
+        E = np.zeros((cols.size, n, 3), dtype=np.complex128)
+        E[np.arange(cols.size), cols // 3, cols % 3] = 1.0
+        A = direct(d, k, pts, E, pts, n_threads)
+        M[:, cols] = A.reshape(cols.size, 3 * n).T
+    return M
+
+
+def solve(d, k, pts, diag, B, n_threads=None):
+    """Solution X of the coupled-dipole system (diag - G) X = B on one point
+    set: diag [n] complex (one value per point, on its three components),
+    B [n, 3] or [n_rhs, n, 3] complex.  Dense LU of the assembled matrix
+    (the system whose matrix-vector product is the layered sum of the paper's
+    Sec. 3.3, the integral-equation use the paper's introduction names)."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+    n = pts.shape[0]
+    B = np.asarray(B, dtype=np.complex128)
+    single = B.ndim == 2
+    Bm = B.reshape(-1, 3 * n).T
+    K = np.diag(np.repeat(np.asarray(diag, dtype=np.complex128).reshape(n), 3)) - dense_operator(d, k, pts,
+                                                                                             n_threads)
+    X = np.linalg.solve(K, Bm).T.reshape(-1, n, 3)
+    return X[0] if single else X

@@ -1,7 +1,8 @@
 """Seeded synthetic workloads (positions, currents) for tests and benchmarks.
 
 This module holds no arithmetic of the method: it only draws points and
-current vectors.  Both the GPU path's tests and the oracle's tests take their
+current vectors (and, for the coupled-dipole solve, the diagonal of the
+system, a material input).  Both the GPU path's tests and the oracle's tests take their
 inputs from here.
 
 Workloads follow the paper's numerical-test setup (Sec. 4: uniformly
@@ -19,6 +20,9 @@ benchmark configurations:
                half the points uniform (25 % per layer), half in 20 Gaussian
                blobs (sigma 0.3, 5 per layer).
 * ``clustered`` the three-layer medium with Gaussian blobs (sigma 0.3).
+* ``dipole_lattice`` the three-layer medium filled with a jittered cubic
+               lattice of small dielectric spheres: the coupled-dipole system
+               (diag - G) X = B of the iterative solve.
 
 Currents are complex128 3-vectors with real and imaginary parts U[-1,1].
 """
@@ -184,3 +188,46 @@ def uneven_geometries(n_geom=32, seed=0, n_min=5000, n_max=200000):
         xs.append(x)
         Js.append(J)
     return d, k, xs, Js
+
+
+def dipole_lattice(n, seed=0, n_rhs=1, eps_r=2.25, jitter=0.1, split=(0.4, 0.3, 0.3), half_width=4.0):
+    """Coupled-dipole workload for the iterative solve: about n points on a
+    jittered cubic lattice filling the three-layer slabs (40/30/30 %), the
+    diagonal of the system and seeded excitations.
+
+    Each layer's slab [-w, w]^2 x [lo, hi] gets a lattice of spacing h_l
+    chosen so that the slab holds its share of points; every point is moved
+    by U(-jitter, jitter) h_l per coordinate (nearest neighbours stay at least
+    (1 - 2 jitter) h_l apart).  A point of layer l is a small sphere of
+    relative permittivity eps_r in its layer: Clausius-Mossotti polarisability
+    alpha = 3 h_l^3 chi / (4 pi), chi = (eps_r - 1) / (eps_r + 2), with the
+    radiation-reaction term, so the diagonal is
+        diag = 1 / (alpha k_l^2) - i k_l / (6 pi)
+    in the units where the field of the dipoles is G applied to them.
+    Returns (d, k, xyz [n', 3], diag [n'] complex128, B) with B complex128
+    [n', 3] (n_rhs = 1) or [n_rhs, n', 3]; n' is close to n."""
+    rng = np.random.default_rng(seed + 7000)
+    m = MEDIA["three"]
+    d, k = np.array(m["d"]), np.array(m["k"])
+    slabs = layer_slabs(m["d"])
+    chi = (eps_r - 1.0) / (eps_r + 2.0)
+    pts, diag = [], []
+    for l, ((lo, hi), s) in enumerate(zip(slabs, split)):
+        vol = (2 * half_width) ** 2 * (hi - lo)
+        h = (vol / (n * s)) ** (1.0 / 3.0)
+        nx = max(1, int(round(2 * half_width / h)))
+        nz = max(1, int(round((hi - lo) / h)))
+        hx, hz = 2 * half_width / nx, (hi - lo) / nz
+        gx = -half_width + (np.arange(nx) + 0.5) * hx
+        gz = lo + (np.arange(nz) + 0.5) * hz
+        X, Y, Z = np.meshgrid(gx, gx, gz, indexing="ij")
+        p = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+        p[:, :2] += rng.uniform(-jitter, jitter, (p.shape[0], 2)) * hx
+        p[:, 2] += rng.uniform(-jitter, jitter, p.shape[0]) * hz
+        hv = (hx * hx * hz) ** (1.0 / 3.0)
+        alpha = 3.0 * hv ** 3 * chi / (4.0 * np.pi)
+        pts.append(p)
+        diag.append(np.full(p.shape[0], 1.0 / (alpha * k[l] ** 2) - 1j * k[l] / (6.0 * np.pi)))
+    xyz = np.vstack(pts)
+    B = currents(rng, xyz.shape[0], n_rhs)
+    return d, k, xyz, np.concatenate(diag), B

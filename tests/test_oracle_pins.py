@@ -302,3 +302,48 @@ def test_gradient_reference_is_converged(oracle):
     j = int(gg["js"][0])
     v = mg._grad_entry(d, k, x, gA, x[j], J[j], j, h=2e-4)
     assert np.linalg.norm(v - gg["gX"][0]) < 1e-7 * np.linalg.norm(v)
+
+
+def test_solve_satisfies_the_unassembled_system(oracle):
+    """The dense solve of (diag - G) X = B is pinned to the direct sum it is
+    built from, without the assembled matrix: diag X - direct(X) = B."""
+    d, k, x, dg, B = inputs.dipole_lattice(40, seed=3, n_rhs=2, half_width=1.0)
+    X = oracle.solve(d, k, x, dg, B)
+    res = dg[None, :, None] * X - oracle.direct(d, k, x, X, x) - B
+    assert np.linalg.norm(res) <= 1e-12 * np.linalg.norm(B)
+    # and the matrix is the symmetric one reciprocity gives (G(x,y) = G(y,x)^T)
+    M = oracle.dense_operator(d, k, x)
+    assert np.abs(M - M.T).max() <= 1e-13 * np.abs(M).max()
+
+
+def test_solve_two_dipoles_closed_form(oracle):
+    """Two points in a homogeneous stack: G between them is the free dyadic
+    a I + b u u^T (u the unit separation, textbook closed form), so the 6 x 6
+    system splits into 2 x 2 systems along u and across it, solved by hand."""
+    kk = 1.3
+    d, k = [0.0], [kk, kk]
+    x = np.array([[0.2, -0.1, 0.35], [-0.3, 0.25, -0.4]])
+    Rv = x[0] - x[1]
+    R = np.linalg.norm(Rv)
+    u = Rv / R
+    g = np.exp(1j * kk * R) / (4 * np.pi * R)
+    t = 1j / (kk * R) - 1 / (kk * R) ** 2
+    a = g * (1 + t)
+    b = g * (-1 - 3 * t)
+    dg = np.array([2.5 - 0.1j, 3.1 + 0.05j])
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((2, 3)) + 1j * rng.standard_normal((2, 3))
+    X = oracle.solve(d, k, x, dg, B)
+    # basis u, e1, e2 (orthonormal); along each direction the coupling is lam
+    e1 = np.cross(u, [0.0, 0.0, 1.0])
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(u, e1)
+    ref = np.zeros((2, 3), dtype=complex)
+    for v, lam in [(u, a + b), (e1, a), (e2, a)]:
+        b1, b2 = B[0] @ v, B[1] @ v
+        det = dg[0] * dg[1] - lam * lam
+        x1 = (dg[1] * b1 + lam * b2) / det
+        x2 = (dg[0] * b2 + lam * b1) / det
+        ref[0] += x1 * v
+        ref[1] += x2 * v
+    assert np.abs(X - ref).max() <= 1e-12 * np.abs(ref).max()
