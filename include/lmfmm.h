@@ -237,6 +237,50 @@ int lm_stats(const lm_ctx* ctx, double* out_host, int n);
 #define LM_STAT_S2T_PAIRS 21         /* reaction near-field (S2T) point pairs        */
 #define LM_STATS_COUNT 22
 
+/* ---- iterative solve over the evaluation ---- */
+
+/* Restarted GMRES for the coupled-dipole system on the built point set
+ *     (D - G) X = B,      D = diag(d_j) on the three components of point j,
+ * with G the layered sum that lm_evaluate applies: the matrix-vector product
+ * of an integral-equation solver, the use the paper's introduction gives for
+ * the layered sum (Sec. 3.3 writes the sum over the first argument with
+ * method-of-moments solvers in view; by the reciprocity stated there it is
+ * the same operator).  Each right-hand side is solved to its own stopping test,
+ * in lockstep with the others, so that every operator application is one
+ * batched lm_evaluate of all n_rhs vectors.
+ *
+ * The build must have the same point array as sources and targets (LM_ESTATE
+ * otherwise).  diag: DEVICE complex128 [n] or NULL (D = 0); B: DEVICE
+ * complex128 [n_rhs][n][3]; X: DEVICE complex128 [n_rhs][n][3], the initial
+ * guess on entry (zero it for the usual start), the last iterate on return.
+ * Stopping test per column: ||B - (D - G) X|| <= tol ||B|| (2-norm), checked
+ * on the true residual at the end of each restart cycle; a column with B = 0
+ * returns X = 0.  restart: Krylov dimension per cycle, 1..LM_SOLVE_MAX_RESTART;
+ * max_iter: total Arnoldi steps (operator applications not counting residual
+ * checks), >= 1.  relres_host: NULL or host double [n_rhs], the final true
+ * relative residuals; info: NULL or host struct, filled.  Orthogonalisation is
+ * classical Gram-Schmidt applied twice, by deterministic reductions, so the
+ * result is bitwise repeatable.  The call synchronises `stream` several times
+ * per iteration (host decisions) and allocates the Krylov basis, (restart + 1)
+ * n_rhs n 48 bytes, on first use or growth (kept until the next build).
+ * Returns LM_OK also when max_iter ends the iteration before the stopping
+ * test holds (info->converged = 0); errors as lm_evaluate. */
+#define LM_SOLVE_MAX_RESTART 64
+
+typedef struct {
+  int iters;          /* Arnoldi steps taken                                     */
+  int matvecs;        /* operator applications, residual checks included          */
+  int cycles;         /* restart cycles                                          */
+  int converged;      /* 1 if every column met the stopping test                   */
+  double ms_total;    /* time of the call on `stream` (HIP events)                 */
+  double ms_matvec;   /* time of the operator applications within it               */
+  double ms_krylov;   /* time of the vector kernels (products, updates, norms)     */
+  double krylov_bytes;/* bytes those kernels must move (each vector read or written once per pass) */
+} lm_solve_info;
+
+int lm_solve(lm_ctx* ctx, int n_rhs, const void* diag, const void* B, void* X, double tol, int restart,
+             int max_iter, double* relres_host, lm_solve_info* info, void* stream);
+
 /* Self-test of the device arithmetic used by the near field (no context):
  * for each x_dev[i] writes out_dev[6i..6i+5] = sin x, cos x (the reduced-range
  * routine of the near field), 1/sqrt(x^2 + 1e-300) (refined estimate), the
@@ -261,6 +305,16 @@ int lm_host_cheb_affine(int jmax, double a, double b, double* out);
  * for 0 <= m <= n <= p (orthonormal Legendre functions, Condon-Shortley
  * phase); tri(n,m) = n(n+1)/2 + m; *stride receives the row stride. */
 int lm_host_legendre_cheb(int p, double* out, int* stride);
+
+/* The host logic of lm_solve (Arnoldi with Gram-Schmidt applied twice, Givens
+ * least squares, restarts and stopping tests) on a dense complex system
+ * A x = b of order n held in host memory: A row-major complex128 [n][n],
+ * b and x complex128 [n] (x: initial guess in, solution out).  Same
+ * arguments and results as lm_solve for one column; *iters receives the
+ * Arnoldi steps and *relres the final true relative residual (LM_OK also
+ * when max_iter ends the iteration first: compare *relres with tol). */
+int lm_host_gmres_dense(int n, const double* A, const double* b, double* x, double tol, int restart,
+                        int max_iter, int* iters, double* relres);
 
 /* Plans a build on the host only (trees, lists, tables sizes) and returns
  * lm_stats-style statistics; errbuf receives the planner's message on failure. */

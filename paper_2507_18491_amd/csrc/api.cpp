@@ -10,6 +10,7 @@
 
 #include "bessel_pq.h"
 #include "../../include/lmfmm.h"
+#include "gmres.h"
 #include "kernels.h"
 #include "plan.h"
 
@@ -80,6 +81,16 @@ struct lm_ctx {
   double contour_a = 0;
   cd* Jc = nullptr;                        // conjugated-input scratch
   long long jc_cap = 0;
+  // iterative solve: Krylov basis and work vector, inner-product partials,
+  // a small device block (vector table, sums, coefficients) and its pinned
+  // host staging
+  cd* kv_buf = nullptr;
+  long long kv_cap = 0;
+  cd* kv_part = nullptr;
+  long long kv_part_cap = 0;
+  void* kv_small = nullptr;
+  void* kv_host = nullptr;
+  size_t kv_small_cap = 0;
 };
 
 extern "C" int lm_destroy(lm_ctx* ctx);
@@ -145,6 +156,14 @@ static void free_build(lm_ctx* ctx) {
   if (ctx->Jc) hipFree(ctx->Jc);
   ctx->Jc = nullptr;
   ctx->jc_cap = 0;
+  if (ctx->kv_buf) hipFree(ctx->kv_buf);
+  if (ctx->kv_part) hipFree(ctx->kv_part);
+  if (ctx->kv_small) hipFree(ctx->kv_small);
+  if (ctx->kv_host) hipHostFree(ctx->kv_host);
+  ctx->kv_buf = ctx->kv_part = nullptr;
+  ctx->kv_small = ctx->kv_host = nullptr;
+  ctx->kv_cap = ctx->kv_part_cap = 0;
+  ctx->kv_small_cap = 0;
   ctx->same_sets = false;
   ctx->host_src.clear();
   ctx->host_tgt.clear();
@@ -1158,6 +1177,308 @@ int lm_host_plan_stats(int n_layers, const double* d, const double* k, const lm_
     return LM_EDOMAIN;
   }
   return lm_stats(&tmp, out, n);
+}
+
+
+// ---------------------------------------------------------------- iterative solve
+// Device vectors of the GMRES iteration on a built context: the basis and the
+// work vector live in ctx->kv_buf, the iterate X and the right-hand side B are
+// the caller's arrays.  Inner products come back to the host through pinned
+// memory (one stream synchronisation each); coefficient vectors go down the
+// same way, each before the next synchronisation, so one staging block serves.
+struct DevKrylov : KrylovSpace {
+  lm_ctx* ctx = nullptr;
+  hipStream_t s = nullptr;
+  long long n3 = 0;
+  const cd* diag = nullptr;
+  cd* const* vt = nullptr;   // device vector table
+  cd* dsum = nullptr;              // device inner products [(m+1) R]
+  cd* dcoef = nullptr;             // device coefficients [(m+1) R]
+  cd* hsum = nullptr;              // pinned host copies
+  cd* hcoef = nullptr;
+  double bytes = 0, ms_matvec = 0, ms_krylov = 0;
+  struct Ev {
+    hipEvent_t a, b;
+    int kind;  // 0 matvec, 1 vector kernels
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Ev> pending;
+  int err = 0;
+
+  ~DevKrylov() override {
+    for (auto& e : pending) {
+      pool.push_back(e.a);
+      pool.push_back(e.b);
+    }
+    for (auto e : pool) hipEventDestroy(e);
+  }
+  hipEvent_t ev() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) err = 1;
+    return e;
+  }
+  int tic(Ev& e, int kind) {
+    e.a = ev();
+    e.b = ev();
+    e.kind = kind;
+    if (err) return fail(ctx, LM_EHIP, "hipEventCreate failed");
+    return hipEventRecord(e.a, s) == hipSuccess ? 0 : fail(ctx, LM_EHIP, "hipEventRecord failed");
+  }
+  int toc(Ev& e) {
+    if (hipEventRecord(e.b, s) != hipSuccess) return fail(ctx, LM_EHIP, "hipEventRecord failed");
+    pending.push_back(e);
+    return 0;
+  }
+  // waits for the stream and books the elapsed times of the recorded spans
+  int sync() {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(ctx, LM_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+    for (auto& p : pending) {
+      float ms = 0;
+      hipEventElapsedTime(&ms, p.a, p.b);
+      (p.kind ? ms_krylov : ms_matvec) += ms;
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+    return 0;
+  }
+  int launched() {
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : fail(ctx, LM_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  }
+  int put_coef(const cd* c, int count) {
+    memcpy(hcoef, c, (size_t)count * n_rhs * sizeof(cd));
+    hipError_t e = hipMemcpyAsync(dcoef, hcoef, (size_t)count * n_rhs * sizeof(cd), hipMemcpyHostToDevice, s);
+    return e == hipSuccess ? 0 : fail(ctx, LM_EHIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+  }
+  double vec_bytes() const { return (double)n_rhs * n3 * sizeof(cd); }
+
+  int apply(int src, int dst) override {
+    Ev e;
+    int rc = tic(e, 0);
+    if (rc) return rc;
+    rc = lm_evaluate(ctx, n_rhs, host_ptr[src], host_ptr[dst], s);
+    if (rc) return rc;
+    if ((rc = toc(e))) return rc;
+    if ((rc = tic(e, 1))) return rc;
+    launch_kv_diag(vt, src, diag, dst, n3, n_rhs, s);
+    if ((rc = launched())) return rc;
+    bytes += 3 * vec_bytes() + (diag ? (double)n3 / 3 * sizeof(cd) : 0.0);
+    return toc(e);
+  }
+  int dots(int first, int count, int w, cd* h) override {
+    Ev e;
+    int rc = tic(e, 1);
+    if (rc) return rc;
+    launch_kv_dots(vt, first, count, w, n3, n_rhs, kv_dots_nb(n3, n_rhs, count), ctx->kv_part, dsum, s);
+    if ((rc = launched()) || (rc = toc(e))) return rc;
+    bytes += (count + 1) * vec_bytes();
+    hipError_t x = hipMemcpyAsync(hsum, dsum, (size_t)count * n_rhs * sizeof(cd), hipMemcpyDeviceToHost, s);
+    if (x != hipSuccess) return fail(ctx, LM_EHIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(x));
+    if ((rc = sync())) return rc;
+    memcpy(h, hsum, (size_t)count * n_rhs * sizeof(cd));
+    return 0;
+  }
+  int combine(int first, int count, const cd* c, int dst) override {
+    int rc = put_coef(c, count);
+    if (rc) return rc;
+    Ev e;
+    if ((rc = tic(e, 1))) return rc;
+    launch_kv_combine(vt, first, count, dcoef, dst, n3, n_rhs, s);
+    bytes += (count + 2) * vec_bytes();
+    if ((rc = launched())) return rc;
+    return toc(e);
+  }
+  int scale(int src, const cd* c, int dst) override {
+    int rc = put_coef(c, 1);
+    if (rc) return rc;
+    Ev e;
+    if ((rc = tic(e, 1))) return rc;
+    launch_kv_scale(vt, src, dcoef, dst, n3, n_rhs, s);
+    bytes += 2 * vec_bytes();
+    if ((rc = launched())) return rc;
+    return toc(e);
+  }
+  int rsub(int b, int w) override {
+    Ev e;
+    int rc = tic(e, 1);
+    if (rc) return rc;
+    launch_kv_rsub(vt, b, w, n3, n_rhs, s);
+    bytes += 3 * vec_bytes();
+    if ((rc = launched())) return rc;
+    return toc(e);
+  }
+  std::vector<cd*> host_ptr;  // the same table on the host
+};
+
+int lm_solve(lm_ctx* ctx, int n_rhs, const void* diag, const void* B, void* X, double tol, int restart,
+             int max_iter, double* relres_host, lm_solve_info* info, void* stream) {
+  if (!ctx) return LM_EINVAL;
+  if (!ctx->built) return fail(ctx, LM_ESTATE, "lm_build must succeed before lm_solve");
+  if (!ctx->same_sets) return fail(ctx, LM_ESTATE, "lm_solve needs a build with the same source and target points");
+  if (n_rhs < 1 || n_rhs > 4096) return fail(ctx, LM_EINVAL, "n_rhs out of range (1..4096)");
+  if (restart < 1 || restart > LM_SOLVE_MAX_RESTART) return fail(ctx, LM_EINVAL, "restart out of range");
+  if (max_iter < 1) return fail(ctx, LM_EINVAL, "max_iter must be >= 1");
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(ctx, LM_EINVAL, "tol must be finite and > 0");
+  const long long n = ctx->plan.n_src;
+  if (n > 0 && (!B || !X)) return fail(ctx, LM_EINVAL, "null B or X");
+  if (((uintptr_t)B % 16) || ((uintptr_t)X % 16) || ((uintptr_t)diag % 16))
+    return fail(ctx, LM_EINVAL, "B, X and diag must be 16-byte aligned");
+  HIPC(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (n == 0) {
+    for (int r = 0; r < n_rhs && relres_host; r++) relres_host[r] = 0.0;
+    if (info) *info = lm_solve_info{0, 0, 0, 1, 0.0, 0.0, 0.0, 0.0};
+    return LM_OK;
+  }
+  const int m = restart;
+  const long long n3 = 3 * n;
+  // buffers: basis 0..m and W; partials; small block = vector table + sums + coefficients
+  const long long need = (long long)(m + 2) * n_rhs * n3;
+  if (need > ctx->kv_cap) {
+    if (ctx->kv_buf) hipFree(ctx->kv_buf);
+    ctx->kv_buf = nullptr;
+    ctx->kv_cap = 0;
+    if (hipMalloc((void**)&ctx->kv_buf, (size_t)need * sizeof(cd)) != hipSuccess)
+      return fail(ctx, LM_ENOMEM, "cannot allocate the Krylov basis");
+    ctx->kv_cap = need;
+  }
+  long long pneed = 1;
+  for (int c = 1; c <= m + 1; c++)
+    pneed = std::max(pneed, (long long)c * n_rhs * kv_dots_nb(n3, n_rhs, c));
+  if (pneed > ctx->kv_part_cap) {
+    if (ctx->kv_part) hipFree(ctx->kv_part);
+    ctx->kv_part = nullptr;
+    ctx->kv_part_cap = 0;
+    if (hipMalloc((void**)&ctx->kv_part, (size_t)pneed * sizeof(cd)) != hipSuccess)
+      return fail(ctx, LM_ENOMEM, "cannot allocate the inner-product partials");
+    ctx->kv_part_cap = pneed;
+  }
+  const size_t tab_bytes = 1024, vec_small = (size_t)(m + 1) * n_rhs * sizeof(cd);
+  const size_t sneed = tab_bytes + 2 * vec_small;
+  if (sneed > ctx->kv_small_cap) {
+    if (ctx->kv_small) hipFree(ctx->kv_small);
+    if (ctx->kv_host) hipHostFree(ctx->kv_host);
+    ctx->kv_small = ctx->kv_host = nullptr;
+    ctx->kv_small_cap = 0;
+    if (hipMalloc(&ctx->kv_small, sneed) != hipSuccess || hipHostMalloc(&ctx->kv_host, sneed) != hipSuccess)
+      return fail(ctx, LM_ENOMEM, "cannot allocate the solve's small buffers");
+    ctx->kv_small_cap = sneed;
+  }
+  DevKrylov S;
+  S.ctx = ctx;
+  S.s = s;
+  S.m = m;
+  S.n_rhs = n_rhs;
+  S.n3 = n3;
+  S.diag = (const cd*)diag;
+  S.host_ptr.resize(m + 4);
+  for (int v = 0; v <= m + 1; v++) S.host_ptr[v] = ctx->kv_buf + (long long)v * n_rhs * n3;
+  S.host_ptr[S.vX()] = (cd*)X;
+  S.host_ptr[S.vB()] = (cd*)B;
+  char* sm = (char*)ctx->kv_small;
+  char* hm = (char*)ctx->kv_host;
+  S.vt = (cd* const*)sm;
+  S.dsum = (cd*)(sm + tab_bytes);
+  S.dcoef = (cd*)(sm + tab_bytes + vec_small);
+  S.hsum = (cd*)(hm + tab_bytes);
+  S.hcoef = (cd*)(hm + tab_bytes + vec_small);
+  memcpy(hm, S.host_ptr.data(), (m + 4) * sizeof(cd*));
+  HIPC(hipMemcpyAsync(sm, hm, (m + 4) * sizeof(cd*), hipMemcpyHostToDevice, s));
+  hipEvent_t e0 = S.ev(), e1 = S.ev();
+  if (S.err) return fail(ctx, LM_EHIP, "hipEventCreate failed");
+  HIPC(hipEventRecord(e0, s));
+  std::vector<double> rr(n_rhs, 0.0);
+  GmresResult gr;
+  int rc = gmres_drive(S, tol, max_iter, rr.data(), &gr);
+  if (rc) {
+    hipStreamSynchronize(s);
+    S.pool.push_back(e0);
+    S.pool.push_back(e1);
+    return rc;
+  }
+  HIPC(hipEventRecord(e1, s));
+  if ((rc = S.sync())) return rc;
+  float total = 0;
+  hipEventElapsedTime(&total, e0, e1);
+  S.pool.push_back(e0);
+  S.pool.push_back(e1);
+  if (relres_host) memcpy(relres_host, rr.data(), n_rhs * sizeof(double));
+  if (info) {
+    info->iters = gr.iters;
+    info->matvecs = gr.matvecs;
+    info->cycles = gr.cycles;
+    info->converged = gr.converged;
+    info->ms_total = total;
+    info->ms_matvec = S.ms_matvec;
+    info->ms_krylov = S.ms_krylov;
+    info->krylov_bytes = S.bytes;
+  }
+  return LM_OK;
+}
+
+// The same driver on a dense host matrix (tests of the host logic).
+struct HostKrylov : KrylovSpace {
+  int n = 0;
+  const double* A = nullptr;          // complex128 [n][n]
+  std::vector<std::vector<cd>> v;     // vectors 0..m+3
+  int apply(int src, int dst) override {
+    const cd* a = (const cd*)A;
+    for (int i = 0; i < n; i++) {
+      cd acc{0, 0};
+      for (int j = 0; j < n; j++) acc = acc + a[(size_t)i * n + j] * v[src][j];
+      v[dst][i] = acc;
+    }
+    return 0;
+  }
+  int dots(int first, int count, int w, cd* h) override {
+    for (int k = 0; k < count; k++) {
+      cd acc{0, 0};
+      for (int i = 0; i < n; i++) acc = acc + cconj(v[first + k][i]) * v[w][i];
+      h[k] = acc;
+    }
+    return 0;
+  }
+  int combine(int first, int count, const cd* c, int dst) override {
+    for (int i = 0; i < n; i++)
+      for (int k = 0; k < count; k++) v[dst][i] = v[dst][i] + v[first + k][i] * c[k];
+    return 0;
+  }
+  int scale(int src, const cd* c, int dst) override {
+    for (int i = 0; i < n; i++) v[dst][i] = v[src][i] * c[0];
+    return 0;
+  }
+  int rsub(int b, int w) override {
+    for (int i = 0; i < n; i++) v[w][i] = v[b][i] - v[w][i];
+    return 0;
+  }
+};
+
+int lm_host_gmres_dense(int n, const double* A, const double* b, double* x, double tol, int restart, int max_iter,
+                        int* iters, double* relres) {
+  if (n < 1 || !A || !b || !x || restart < 1 || restart > LM_SOLVE_MAX_RESTART || max_iter < 1 || !(tol > 0))
+    return LM_EINVAL;
+  HostKrylov S;
+  S.n = n;
+  S.m = restart;
+  S.n_rhs = 1;
+  S.A = A;
+  S.v.assign(restart + 4, std::vector<cd>(n, cd{0, 0}));
+  memcpy(S.v[S.vX()].data(), x, (size_t)n * sizeof(cd));
+  memcpy(S.v[S.vB()].data(), b, (size_t)n * sizeof(cd));
+  double rr = 0;
+  GmresResult gr;
+  gmres_drive(S, tol, max_iter, &rr, &gr);
+  memcpy(x, S.v[S.vX()].data(), (size_t)n * sizeof(cd));
+  if (iters) *iters = gr.iters;
+  if (relres) *relres = rr;
+  return LM_OK;
 }
 
 }  // extern "C"

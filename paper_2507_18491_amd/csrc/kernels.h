@@ -81,3 +81,13 @@ void launch_l2p_grad(const DevPlan& d, const int* leaves, int n, int kind, const
 void launch_p2p_grad(const DevPlan& d, const int* tboxes, int n, const double* sxyz, const cd* Jsrc,
                      long long n_src, const double* txyz, const cd* W, long long n_tgt, int n_rhs, double* gX,
                      bool red, hipStream_t s);
+
+// vector kernels of the GMRES solve (krylov.hip); vt: device table of vector base pointers
+int kv_dots_nb(long long n3, int n_rhs, int count);
+void launch_kv_dots(cd* const* vt, int first, int count, int w, long long n3, int n_rhs, int nb, cd* part,
+                    cd* out, hipStream_t s);
+void launch_kv_combine(cd* const* vt, int first, int count, const cd* c, int dst, long long n3, int n_rhs,
+                       hipStream_t s);
+void launch_kv_scale(cd* const* vt, int src, const cd* c, int dst, long long n3, int n_rhs, hipStream_t s);
+void launch_kv_rsub(cd* const* vt, int b, int w, long long n3, int n_rhs, hipStream_t s);
+void launch_kv_diag(cd* const* vt, int src, const cd* diag, int dst, long long n3, int n_rhs, hipStream_t s);

@@ -32,6 +32,13 @@ class lm_params(ctypes.Structure):
                 ("m2l_variant", ctypes.c_int)]
 
 M2L_VARIANTS = 3
+SOLVE_MAX_RESTART = 64
+
+
+class lm_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("matvecs", ctypes.c_int), ("cycles", ctypes.c_int),
+                ("converged", ctypes.c_int), ("ms_total", ctypes.c_double), ("ms_matvec", ctypes.c_double),
+                ("ms_krylov", ctypes.c_double), ("krylov_bytes", ctypes.c_double)]
 
 
 _lib = None
@@ -68,6 +75,10 @@ def load_library():
     lib.lm_host_components.argtypes = [ctypes.c_int, D, D, P(ctypes.c_int), ctypes.c_int]
     lib.lm_host_cheb_affine.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, D]
     lib.lm_host_legendre_cheb.argtypes = [ctypes.c_int, D, P(ctypes.c_int)]
+    lib.lm_solve.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, D,
+                             P(lm_solve_info), vp]
+    lib.lm_host_gmres_dense.argtypes = [ctypes.c_int, D, D, D, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                        P(ctypes.c_int), D]
     lib.lm_host_plan_stats.argtypes = [ctypes.c_int, D, D, P(lm_params), ctypes.c_int64, D, ctypes.c_int64,
                                        D, D, ctypes.c_int, ctypes.c_char_p, ctypes.c_int]
     _lib = lib
@@ -223,6 +234,42 @@ class LayeredDyadicFMM:
                                              ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                              ctypes.c_void_p(stream)))
         return out
+
+    def solve(self, diag, B, X=None, tol=1e-6, restart=30, max_iter=1000, stream=None):
+        """Solves (diag - G) X = B by restarted GMRES on the built point set
+        (sources = targets).  diag: complex128 CUDA tensor [n] or None (zero);
+        B: complex128 CUDA tensor [n, 3] or [n_rhs, n, 3]; X: initial guess
+        of the same shape (zeros if None), overwritten with the solution.
+        Returns (X, info) with info a dict: iters, matvecs, cycles,
+        converged, relres (per right-hand side), ms_total, ms_matvec,
+        ms_krylov, krylov_bytes."""
+        import torch
+        if self.n_src is None:
+            raise LMError("build() must be called first")
+        single, n_rhs, Bv = self._rhs_view(B, self.n_src, "B")
+        if X is None:
+            X = torch.zeros_like(Bv)
+        else:
+            if not (X.is_cuda and X.dtype == torch.complex128 and X.is_contiguous()
+                    and X.numel() == Bv.numel()):
+                raise LMError("X must be a contiguous complex128 CUDA tensor shaped like B")
+        if diag is not None:
+            if not (diag.is_cuda and diag.dtype == torch.complex128 and diag.numel() == self.n_src):
+                raise LMError("diag must be a complex128 CUDA tensor [n]")
+            diag = diag.contiguous()
+        if stream is None:
+            stream = torch.cuda.current_stream(Bv.device).cuda_stream
+        rel = np.zeros(n_rhs)
+        info = lm_solve_info()
+        self._check(self.lib.lm_solve(self.ctx, n_rhs, ctypes.c_void_p(diag.data_ptr() if diag is not None else 0),
+                                      ctypes.c_void_p(Bv.data_ptr()), ctypes.c_void_p(X.data_ptr()), float(tol),
+                                      int(restart), int(max_iter), _dp(rel), ctypes.byref(info),
+                                      ctypes.c_void_p(stream)))
+        out = {f: getattr(info, f) for f, _ in lm_solve_info._fields_}
+        out["converged"] = bool(out["converged"])
+        out["relres"] = rel
+        Xv = X.reshape(n_rhs, self.n_src, 3)
+        return (Xv[0] if single else Xv), out
 
     def stats(self):
         buf = np.zeros(len(STAT_NAMES))
@@ -383,6 +430,23 @@ def host_plan_stats(d, k, src, tgt=None, **params):
     if rc:
         raise LMError("planning failed (%d): %s" % (rc, err.value.decode()))
     return dict(zip(STAT_NAMES, out.tolist()))
+
+
+def host_gmres_dense(A, b, x0=None, tol=1e-10, restart=30, max_iter=1000):
+    """The solve's host logic on a dense complex system A x = b (host
+    arrays); returns (x, iters, relres)."""
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128))
+    n = A.shape[0]
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.complex128).reshape(n))
+    x = np.zeros(n, dtype=np.complex128) if x0 is None else np.array(x0, dtype=np.complex128).reshape(n)
+    it = ctypes.c_int()
+    rr = ctypes.c_double()
+    rc = load_library().lm_host_gmres_dense(n, _dp(A.view(np.float64)), _dp(b.view(np.float64)),
+                                            _dp(x.view(np.float64)), float(tol), int(restart), int(max_iter),
+                                            ctypes.byref(it), ctypes.byref(rr))
+    if rc:
+        raise LMError("lm_host_gmres_dense failed (%d)" % rc)
+    return x, it.value, rr.value
 
 
 def selftest_math(x):

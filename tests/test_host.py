@@ -238,3 +238,70 @@ def test_real_bessel_coefficient_table():
         scale = np.exp(np.abs(z.imag))
         for val, order in ((v, 0), (-0.5 * z * d1, 1), (2.0 * w * d2, 2)):
             assert (np.abs(val - sp.jv(order, z)) / scale).max() < 2e-14, (zmax, order)
+
+
+# ---------------------------------------------------------------- GMRES host logic
+def _rand_system(n, seed, shift=4.0):
+    rng = np.random.default_rng(seed)
+    A = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    A += shift * np.eye(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    return A, b
+
+
+def test_gmres_host_logic_solves_with_restarts():
+    A, b = _rand_system(60, 1)
+    x, it, rr = lmfmm.host_gmres_dense(A, b, tol=1e-12, restart=8, max_iter=500)
+    ref = np.linalg.solve(A, b)
+    assert rr <= 1e-12
+    assert it > 8  # several restart cycles
+    assert np.abs(x - ref).max() <= 1e-10 * np.abs(ref).max()
+    assert np.linalg.norm(b - A @ x) <= 1.01e-12 * np.linalg.norm(b)
+
+
+def test_gmres_minimal_residual_over_the_krylov_space():
+    """One cycle of m steps from x0 = 0 returns the minimiser of |b - A x|
+    over the Krylov space span{b, Ab, ..., A^{m-1} b} (the defining property
+    of GMRES), here computed by a least-squares solve on an explicit basis."""
+    A, b = _rand_system(40, 2, shift=1.5)
+    for m in (1, 3, 7, 12):
+        x, it, rr = lmfmm.host_gmres_dense(A, b, tol=1e-15, restart=m, max_iter=m)
+        assert it == m
+        K = np.empty((40, m), dtype=complex)
+        v = b.copy()
+        for j in range(m):
+            K[:, j] = v
+            v = A @ v
+        Q, _ = np.linalg.qr(K)
+        y = np.linalg.lstsq(A @ Q, b, rcond=None)[0]
+        rmin = np.linalg.norm(b - A @ (Q @ y)) / np.linalg.norm(b)
+        assert abs(rr - rmin) <= 1e-9 * max(rmin, 1e-12) + 1e-13, (m, rr, rmin)
+        assert np.abs(x - Q @ y).max() <= 1e-9 * np.abs(Q @ y).max()
+
+
+def test_gmres_finite_termination_and_breakdown():
+    # a full cycle solves an order-n system in at most n steps (up to rounding)
+    A, b = _rand_system(12, 3, shift=0.3)
+    x, it, rr = lmfmm.host_gmres_dense(A, b, tol=1e-11, restart=12, max_iter=40)
+    assert rr <= 1e-11 and it <= 14
+    # invariant Krylov space at the first step: A = c I
+    c = 2.0 - 0.5j
+    x, it, rr = lmfmm.host_gmres_dense(c * np.eye(9), b[:9], tol=1e-13, restart=5)
+    assert it == 1 and rr <= 1e-13
+    assert np.abs(x - b[:9] / c).max() <= 1e-14 * np.abs(b).max()
+
+
+def test_gmres_zero_rhs_and_iteration_cap():
+    A, b = _rand_system(20, 4, shift=0.2)
+    x, it, rr = lmfmm.host_gmres_dense(A, np.zeros(20), x0=np.ones(20), tol=1e-8)
+    assert it == 0 and rr == 0.0 and not np.any(x)
+    x, it, rr = lmfmm.host_gmres_dense(A, b, tol=1e-14, restart=3, max_iter=5)
+    assert it == 5 and rr > 1e-14
+    assert rr == pytest.approx(np.linalg.norm(b - A @ x) / np.linalg.norm(b), rel=1e-9)
+
+
+def test_gmres_rejects_bad_arguments():
+    A, b = _rand_system(5, 5)
+    for kw in (dict(restart=0), dict(restart=65), dict(max_iter=0), dict(tol=0.0)):
+        with pytest.raises(lmfmm.LMError):
+            lmfmm.host_gmres_dense(A, b, **kw)
