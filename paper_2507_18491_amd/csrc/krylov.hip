@@ -77,6 +77,7 @@ __global__ __launch_bounds__(KV_NT) void k_kv_combine(cd* const* vt, int first, 
   cd* dp = vt[dst] + off;
   for (long long i = (long long)blockIdx.x * KV_NT + threadIdx.x; i < n3; i += (long long)gridDim.x * KV_NT) {
     cd a = dp[i];
+#pragma unroll 4
     for (int k = 0; k < count; k++) a = a + vps[k][i] * cs[k];
     dp[i] = a;
   }
