@@ -16,7 +16,8 @@
  *     Fourier transform of the spectral dyadic of Sec. 3.1 (the J1..J5 form)
  *     with the free-space term removed.  The scalar coefficients phi, psi
  *     come from the two 1-D interface problems of Sec. 3.1 (TE jump
- *     [[u]] = [[u']] = 0, TM jump [[u]] = [[u'/eps]] = 0, eps ~ k^2, mu = 1).
+ *     [[u]] = [[u'/mu]] = 0, TM jump [[u]] = [[u'/eps]] = 0, with relative
+ *     permeabilities mu (default 1) and eps proportional to k^2 / mu).
  *     The paper's four-component decomposition, images, effective locations,
  *     Z-functions and sigma densities are deliberately NOT used here: the
  *     reaction field is computed in one piece.
@@ -25,9 +26,11 @@
  * G = (I + grad grad/k^2) e^{ikR}/(4 pi R) in a homogeneous medium.  With the
  * normalised 1-D field u (u'' + k_z^2 u = -delta(z - z'), free part
  * u^f = i e^{i k_z |z-z'|} / (2 k_z)) the spectral dyadic is
- *   Ghat = (1/k^2) [ k^2 u_TE J1 + kr^2 u_TM J2 + d_z u_TM J3 - d_z' u_TM J4
- *                    + (k^2 u_TE - d_z d_z' u_TM) J5 / kr^2 ],
- * k the target-layer wavenumber.  The angular integral over the spectral
+ *   Ghat = (1/k^2) [ k^2 u_TE J1 + g kr^2 u_TM J2 + g d_z u_TM J3 - g d_z' u_TM J4
+ *                    + (k^2 u_TE - g d_z d_z' u_TM) J5 / kr^2 ],
+ * k the target-layer wavenumber, g = mu_t / mu_s (target over source layer:
+ * the paper's TM coefficient carries mu of the target layer and its 1-D
+ * source 1/mu of the source layer; g = 1 for mu = 1).  The angular integral over the spectral
  * polar angle is done analytically (integer-order Bessel identity, Sec. 3.4),
  * leaving Sommerfeld integrals in kr with J0, J1, J2.
  *
@@ -52,11 +55,13 @@ typedef double complex cplx;
 #define OR_MAXL 16 /* maximum number of layers */
 
 /* ------------------------------------------------------------------ */
-/* Medium: n layers, interfaces d[0] > d[1] > ... > d[n-2], wavenumbers k */
+/* Medium: n layers, interfaces d[0] > d[1] > ... > d[n-2], wavenumbers k,
+ * relative permeabilities mu (eps proportional to k^2 / mu)               */
 typedef struct {
   int n;
   double d[OR_MAXL];
   double k[OR_MAXL];
+  double mu[OR_MAXL];
   double kmax;
 } or_medium;
 
@@ -150,7 +155,8 @@ static void or_solve_1d(const or_medium *md, cplx kr, int s, int pol,
   cplx kz[OR_MAXL], E[OR_MAXL], beta[OR_MAXL];
   for (int m = 0; m < n; m++) {
     kz[m] = or_kz(md->k[m], kr);
-    beta[m] = pol ? md->k[m] * md->k[m] : 1.0;
+    /* the jump conditions of Sec. 3.1: [[u' / mu]] = 0 (TE), [[u' / eps]] = 0 (TM) */
+    beta[m] = pol ? md->k[m] * md->k[m] / md->mu[m] : md->mu[m];
     E[m] = (m >= 1 && m <= L - 1) ? cexp(I * kz[m] * (md->d[m - 1] - md->d[m])) : 0.0;
   }
   for (int src = 0; src < 2; src++)
@@ -305,6 +311,10 @@ static void or_sommerfeld_pair(const or_medium *md, const or_contour *ct, const 
   double c1 = cos(phi), s1 = sin(phi), c2 = cos(2 * phi), s2 = sin(2 * phi);
   int t = free_only ? 0 : or_layer_of(md, z), s = free_only ? 0 : or_layer_of(md, zp);
   double k = free_only ? kfree : md->k[t];
+  /* the TM terms of the spectral dyadic carry mu_t / mu_s (Sec. 3.1: the TM
+   * coefficient is scaled by the target layer's mu and its 1-D source by
+   * 1 / mu of the source layer); the TE terms carry no mu                  */
+  double tm_scale = free_only ? 1.0 : md->mu[t] / md->mu[s];
   cplx ampf[2][OR_MAXL][2], ampp[2][OR_MAXL][2];
   cplx Sf[4], Sp[4], Jb[3];
   /* ellipse: kr(th) = a/2 (1 - cos th) - i depth sin th, th in [0, pi] */
@@ -324,6 +334,7 @@ static void or_sommerfeld_pair(const or_medium *md, const or_contour *ct, const 
         or_solve_1d(md, kr, s, 1, ampp);
         or_reaction_scalars(md, kr, t, s, 0, ampf, z, zp, Sf);
         or_reaction_scalars(md, kr, t, s, 1, ampp, z, zp, Sp);
+        for (int q = 0; q < 4; q++) Sp[q] *= tm_scale;
       }
       or_bessel012_c(kr * rho, Jb);
       or_accumulate(G, wgt, kr, k, Sf, Sp, Jb, c1, s1, c2, s2);
@@ -350,6 +361,7 @@ static void or_sommerfeld_pair(const or_medium *md, const or_contour *ct, const 
         or_solve_1d(md, kr, s, 1, ampp);
         or_reaction_scalars(md, kr, t, s, 0, ampf, z, zp, Sf);
         or_reaction_scalars(md, kr, t, s, 1, ampp, z, zp, Sp);
+        for (int q = 0; q < 4; q++) Sp[q] *= tm_scale;
       }
       or_bessel012_r(krr * rho, Jb);
       or_accumulate(G, wgt, kr, k, Sf, Sp, Jb, c1, s1, c2, s2);
@@ -370,13 +382,14 @@ static void or_free_dyadic(double k, const double *R, cplx G[3][3]) {
     for (int j = 0; j < 3; j++) G[i][j] = (i == j ? a : 0.0) + b * (R[i] / r) * (R[j] / r);
 }
 
-static int or_setup(or_medium *md, int n_layers, const double *d, const double *k) {
+static int or_setup(or_medium *md, int n_layers, const double *d, const double *k, const double *mu) {
   if (n_layers < 1 || n_layers > OR_MAXL) return -1;
   md->n = n_layers;
   md->kmax = 0.0;
   for (int l = 0; l < n_layers; l++) {
     md->k[l] = k[l];
-    if (!(k[l] > 0.0)) return -2;
+    md->mu[l] = mu ? mu[l] : 1.0;
+    if (!(k[l] > 0.0) || !(md->mu[l] > 0.0) || !isfinite(md->mu[l])) return -2;
     if (k[l] > md->kmax) md->kmax = k[l];
   }
   for (int l = 0; l < n_layers - 1; l++) {
@@ -399,10 +412,10 @@ static void or_default_contour(const or_medium *md, double rho_max, or_contour *
 
 /* 3x3 G(x, x') (row-major complex128 out[9]); quad_scale > 1 refines the
  * contour (more ellipse panels, shorter tail panels) for convergence checks. */
-int lm_oracle_pair(int n_layers, const double *d, const double *k, const double *x,
+int lm_oracle_pair(int n_layers, const double *d, const double *k, const double *mu, const double *x,
                    const double *xp, double quad_scale, double *out) {
   or_medium md;
-  int rc = or_setup(&md, n_layers, d, k);
+  int rc = or_setup(&md, n_layers, d, k, mu);
   if (rc) return rc;
   or_contour ct;
   double rho = hypot(x[0] - xp[0], x[1] - xp[1]);
@@ -430,10 +443,10 @@ int lm_oracle_pair(int n_layers, const double *d, const double *k, const double 
 }
 
 /* reaction part only (no free-space term) */
-int lm_oracle_reaction_pair(int n_layers, const double *d, const double *k, const double *x,
+int lm_oracle_reaction_pair(int n_layers, const double *d, const double *k, const double *mu, const double *x,
                             const double *xp, double quad_scale, double *out) {
   or_medium md;
-  int rc = or_setup(&md, n_layers, d, k);
+  int rc = or_setup(&md, n_layers, d, k, mu);
   if (rc) return rc;
   or_contour ct;
   or_default_contour(&md, hypot(x[0] - xp[0], x[1] - xp[1]), &ct);
@@ -457,7 +470,7 @@ int lm_oracle_free_check(double k, const double *x, const double *xp, double *ou
                          double *out_closed) {
   or_medium md;
   double kk[1] = {k};
-  or_setup(&md, 1, NULL, kk);
+  or_setup(&md, 1, NULL, kk, NULL);
   or_contour ct;
   or_default_contour(&md, hypot(x[0] - xp[0], x[1] - xp[1]), &ct);
   cplx G[3][3], Gf[3][3];
@@ -476,10 +489,10 @@ int lm_oracle_free_check(double k, const double *x, const double *xp, double *ou
 /* spectral reaction scalars for pinning the 1-D solve:
  * out = complex128[2][4]: (TE, TM) x (R, dzR, dz'R, dzdz'R) at real or
  * complex kr = (kr_re, kr_im).                                           */
-int lm_oracle_spectral(int n_layers, const double *d, const double *k, double kr_re,
+int lm_oracle_spectral(int n_layers, const double *d, const double *k, const double *mu, double kr_re,
                        double kr_im, double z, double zp, double *out) {
   or_medium md;
-  int rc = or_setup(&md, n_layers, d, k);
+  int rc = or_setup(&md, n_layers, d, k, mu);
   if (rc) return rc;
   cplx kr = kr_re + I * kr_im;
   int t = or_layer_of(&md, z), s = or_layer_of(&md, zp);
@@ -510,11 +523,11 @@ void lm_oracle_bessel012(double zr, double zi, double *out) {
  * The free-space term is skipped for coincident points; sources with an
  * all-zero current in every right-hand side are skipped (they contribute
  * exactly zero).  OpenMP over targets, fixed order over sources.        */
-int lm_oracle_direct(int n_layers, const double *d, const double *k, int64_t n_src,
+int lm_oracle_direct(int n_layers, const double *d, const double *k, const double *mu, int64_t n_src,
                      const double *src_xyz, int n_rhs, const double *J, int64_t n_tgt,
                      const double *tgt_xyz, double *A, int n_threads) {
   or_medium md;
-  int rc = or_setup(&md, n_layers, d, k);
+  int rc = or_setup(&md, n_layers, d, k, mu);
   if (rc) return rc;
   or_init_gl();
   double rho_max = 0.0;
@@ -571,11 +584,11 @@ int lm_oracle_direct(int n_layers, const double *d, const double *k, int64_t n_s
 
 /* free-space part only (closed form, same-layer, x_i != x_j): used for the
  * cheap full-size check of the free-space FMM.                           */
-int lm_oracle_direct_free(int n_layers, const double *d, const double *k, int64_t n_src,
+int lm_oracle_direct_free(int n_layers, const double *d, const double *k, const double *mu, int64_t n_src,
                           const double *src_xyz, const double *J, int64_t n_tgt,
                           const double *tgt_xyz, double *A, int n_threads) {
   or_medium md;
-  int rc = or_setup(&md, n_layers, d, k);
+  int rc = or_setup(&md, n_layers, d, k, mu);
   if (rc) return rc;
   if (n_threads <= 0) n_threads = 1;
 #pragma omp parallel for schedule(static) num_threads(n_threads)

@@ -347,3 +347,86 @@ def test_solve_two_dipoles_closed_form(oracle):
         ref[0] += x1 * v
         ref[1] += x2 * v
     assert np.abs(X - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------- permeabilities
+MU3 = [1.0, 1.8, 0.7]
+
+
+@pytest.mark.parametrize("kr", [0.3, 1.3, 4.0, 0.8 - 0.3j])
+def test_two_layer_fresnel_with_mu(oracle, kr):
+    """Layers of different permeability: the 1-D solutions against the
+    textbook Fresnel coefficients r_TE = (mu1 k0z - mu0 k1z)/(mu1 k0z + mu0 k1z)
+    and r_TM = (eps1 k0z - eps0 k1z)/(eps1 k0z + eps0 k1z), eps = k^2 / mu."""
+    d, k, mu = [0.0], [1.0, 1.5], [1.3, 0.6]
+    z, zp = 0.7, 0.4
+    k0z, k1z = _kz(k[0], kr), _kz(k[1], kr)
+    e0, e1 = k[0] ** 2 / mu[0], k[1] ** 2 / mu[1]
+    r = [(mu[1] * k0z - mu[0] * k1z) / (mu[1] * k0z + mu[0] * k1z),
+         (e1 * k0z - e0 * k1z) / (e1 * k0z + e0 * k1z)]
+    c = 1j / (2 * k0z)
+    got = oracle.spectral(d, k, kr, z, zp, mu=mu)
+    gt = oracle.spectral(d, k, kr, -0.5, zp, mu=mu)
+    for pol in range(2):
+        u = c * r[pol] * np.exp(1j * k0z * (z + zp))
+        assert abs(got[pol, 0] - u) <= 1e-13 * abs(u)
+        ut = c * (1 + r[pol]) * np.exp(1j * k0z * zp) * np.exp(1j * k1z * 0.5)
+        assert abs(gt[pol, 0] - ut) <= 1e-13 * abs(ut)
+
+
+def test_reciprocity_with_mu(oracle):
+    """With permeabilities the reciprocal relation carries the layers' mu:
+    G(x, y) mu(y) = G(y, x)^T mu(x).  (The Maxwell operator curl (1/mu) curl
+    - omega^2 eps is symmetric under these interface conditions, and G, the
+    field with the free dyadic of the source layer, solves it with the source
+    delta / mu(y); so G(x, y) mu(y) is the symmetric Green's function.)"""
+    rng = np.random.default_rng(31)
+    lay = lambda z: 0 if z > D3[0] else (1 if z > D3[1] else 2)
+    for x in _pts_in_layers(rng):
+        for y in _pts_in_layers(rng):
+            a = oracle.pair(D3, K3, x, y, mu=MU3) * MU3[lay(y[2])]
+            b = oracle.pair(D3, K3, y, x, mu=MU3).T * MU3[lay(x[2])]
+            assert rel(a, b) < 1e-12
+            if lay(x[2]) != lay(y[2]):  # the plain transpose does not hold across layers
+                assert rel(oracle.pair(D3, K3, x, y, mu=MU3), oracle.pair(D3, K3, y, x, mu=MU3).T) > 1e-3
+
+
+def test_homogeneous_stack_with_mu(oracle):
+    """Equal k and equal mu != 1 in every layer: still the free dyadic."""
+    d, k, mu = [0.0, -1.2], [1.7, 1.7, 1.7], [2.2, 2.2, 2.2]
+    for x, xp in [([0.3, 0.2, 0.5], [0, 0, -0.4]), ([1, 0, -0.5], [0, 1, -2.0])]:
+        x, xp = np.array(x, float), np.array(xp, float)
+        free = oracle.free_check(1.7, x, xp)[1]
+        assert rel(oracle.pair(d, k, x, xp, mu=mu), free) < 1e-12
+
+
+@pytest.mark.parametrize("src_layer", [0, 1, 2])
+def test_maxwell_interface_conditions_with_mu(oracle, src_layer):
+    """Across every interface, with permeabilities: tangential E and normal
+    eps E continuous (eps = k^2 / mu), tangential H ~ (1/mu) curl E and
+    normal B ~ (curl E)_z continuous (finite differences of the oracle)."""
+    rng = np.random.default_rng(40 + src_layer)
+    xp = _pts_in_layers(rng)[src_layer]
+    mu = np.array(MU3)
+    eps = np.array(K3) ** 2 / mu
+    e, h = 1e-10, 4e-5
+    G = lambda q: oracle.pair(D3, K3, q, xp, mu=MU3)
+    for li, dz in enumerate(D3):
+        xy = xp[:2] + rng.uniform(-0.7, 0.7, 2)
+        up = np.array([xy[0], xy[1], dz + e])
+        dn = np.array([xy[0], xy[1], dz - e])
+        Gu, Gd = G(up), G(dn)
+        scale = np.abs(Gu).max()
+        assert np.abs(Gu[:2] - Gd[:2]).max() < 1e-8 * scale
+        assert np.abs(eps[li] * Gu[2] - eps[li + 1] * Gd[2]).max() < 1e-8 * scale * eps.max()
+
+        def curl(pt, side):
+            ex, ey, ez = np.array([h, 0, 0]), np.array([0, h, 0]), np.array([0, 0, h]) * side
+            dGx = (G(pt + ex) - G(pt - ex)) / (2 * h)
+            dGy = (G(pt + ey) - G(pt - ey)) / (2 * h)
+            dGz = (-3 * G(pt) + 4 * G(pt + ez) - G(pt + 2 * ez)) / (2 * h) * side
+            return np.array([dGy[2] - dGz[1], dGz[0] - dGx[2], dGx[1] - dGy[0]])
+        cu, cd = curl(up, +1), curl(dn, -1)
+        tang = np.abs(cu[:2] / mu[li] - cd[:2] / mu[li + 1]).max()
+        assert tang < 1e-5 * np.abs(cu[:2] / mu[li]).max()
+        assert np.abs(cu[2] - cd[2]).max() < 1e-5 * np.abs(cu).max()
