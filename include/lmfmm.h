@@ -20,8 +20,9 @@
  * (Sec. 2).
  *
  * Medium: layers 0..n-1 from top to bottom, interfaces z = d[0] > d[1] > ...
- * (n-1 values), real wavenumbers k[l] > 0, mu = 1 and eps proportional to
- * k^2 (the reading used for the paper's two interface problems of Sec. 3.1).
+ * (n-1 values), real wavenumbers k[l] > 0, relative permeabilities mu[l] > 0
+ * (default 1) and eps proportional to k^2 / mu (only ratios enter the
+ * interface conditions of the paper's two 1-D problems, Sec. 3.1).
  * A point with d[l] < z < d[l-1] lies in layer l.  Time convention: outgoing
  * e^{+ikR}, Im k_z >= 0.
  *
@@ -108,8 +109,10 @@ const char* lm_last_error(const lm_ctx* ctx);
 
 /* Sets the layered medium (Sec. 3.1).  d_host: n_layers-1 interfaces,
  * strictly decreasing; k_host: n_layers wavenumbers, finite and > 0; mu_host:
- * NULL or all 1.0 (other permeabilities: LM_EDOMAIN).  Host arrays, copied.
- * Invalidates a previous lm_build. */
+ * NULL (all 1) or n_layers relative permeabilities, finite and > 0 (they
+ * enter the TE and TM interface conditions and scale the TM part of the
+ * reaction field by mu_target / mu_source).  Host arrays, copied.  LM_EDOMAIN
+ * for an invalid value.  Invalidates a previous lm_build. */
 int lm_set_layers(lm_ctx* ctx, int n_layers, const double* d_host, const double* k_host,
                   const double* mu_host);
 
@@ -152,9 +155,9 @@ int lm_evaluate(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream);
  *     gJ_j = sum_i G(x_i, x_j)^H gA_i      (x_i targets, x_j sources),
  * for n_rhs vectors.  gA: DEVICE complex128 [n_rhs][n_tgt][3]; gJ: DEVICE
  * complex128 [n_rhs][n_src][3], overwritten.  Computed through the
- * reciprocity of the layered Green's function, G(x, y) = G(y, x)^T (Sec. 3.3,
- * mu = 1): gJ = conj(G~ conj(gA)) with G~ the forward sum with sources and
- * targets exchanged.  When the source and target arrays given to lm_build
+ * reciprocity of the layered Green's function, G(x, y) mu(y) = G(y, x)^T mu(x)
+ * (Sec. 3.3; mu(x) the permeability of x's layer): gJ_j = conj(G~ conj(mu gA))_j
+ * / mu_j with G~ the forward sum with sources and targets exchanged.  When the source and target arrays given to lm_build
  * are the same point set this is the built FMM itself; otherwise a second
  * FMM with the roles exchanged is built on the first call (which then
  * synchronises `stream` once and allocates; later calls reuse it).  The
@@ -171,11 +174,11 @@ int lm_evaluate_adjoint(lm_ctx* ctx, int n_rhs, const void* gA, void* gJ, void* 
  * [n_rhs][n_src][3] (the currents of the forward evaluation); gA: DEVICE
  * complex128 [n_rhs][n_tgt][3]; gX: DEVICE fp64 [n_src][3], overwritten.
  * Uses the same reciprocity as lm_evaluate_adjoint: the field of the
- * currents conj(gA) placed at the targets is differentiated at the source
+ * currents mu conj(gA) placed at the targets is differentiated at the source
  * points (ladder relations of the regular wave functions on the local
  * expansions, closed-form derivative of the free-space dyadic in the near
- * field) and contracted with J.  Build, stream and error behaviour as
- * lm_evaluate_adjoint. */
+ * field), contracted with J and divided by mu of the source's layer.  Build,
+ * stream and error behaviour as lm_evaluate_adjoint. */
 int lm_grad_src_xyz(lm_ctx* ctx, int n_rhs, const void* J, const void* gA, double* gX, void* stream);
 
 /* Phase timing.  lm_set_timing(ctx, 1) (re)starts recording HIP events on

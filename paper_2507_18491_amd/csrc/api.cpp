@@ -248,8 +248,11 @@ int lm_set_layers(lm_ctx* ctx, int n_layers, const double* d_host, const double*
   m.kmax = 0;
   for (int l = 0; l < n_layers; l++) {
     if (!(k_host[l] > 0) || !std::isfinite(k_host[l])) return fail(ctx, LM_EDOMAIN, "wavenumbers must be finite and > 0");
-    if (mu_host && mu_host[l] != 1.0) return fail(ctx, LM_EDOMAIN, "only mu = 1 is supported");
+    const double mu = mu_host ? mu_host[l] : 1.0;
+    if (!(mu > 0) || !std::isfinite(mu)) return fail(ctx, LM_EDOMAIN, "permeabilities must be finite and > 0");
     m.k[l] = k_host[l];
+    m.mu[l] = mu;
+    m.mu_one = m.mu_one && mu == 1.0;
     m.kmax = std::max(m.kmax, k_host[l]);
   }
   for (int l = 0; l < n_layers - 1; l++) {
@@ -531,7 +534,10 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
   MediumDev md;
   memset(&md, 0, sizeof(md));
   md.n = med.n;
-  for (int l = 0; l < med.n; l++) md.k[l] = med.k[l];
+  for (int l = 0; l < med.n; l++) {
+    md.k[l] = med.k[l];
+    md.mu[l] = med.mu[l];
+  }
   for (int l = 0; l < med.n - 1; l++) md.d[l] = med.d[l];
   ctx->md = md;
   ctx->contour_a = ctx->prm.contour_a > 0 ? ctx->prm.contour_a : 1.5 * med.kmax;
@@ -884,10 +890,16 @@ int lm_evaluate_adjoint(lm_ctx* ctx, int n_rhs, const void* gA, void* gJ, void* 
     int nr = std::min(LM_RHS_CHUNK, n_rhs - r0);
     const cd* g = (const cd*)gA + (long long)r0 * pl.n_tgt * 3;
     cd* o = (cd*)gJ + (long long)r0 * pl.n_src * 3;
-    launch_conj(ctx->Jc, g, (long long)nr * pl.n_tgt * 3, s);
+    if (ctx->med.mu_one)
+      launch_conj(ctx->Jc, g, (long long)nr * pl.n_tgt * 3, s);
+    else  // reciprocity with permeabilities: G(x, y)^H = conj(G(y, x)) mu(x) / mu(y)
+      launch_conj_mu(ctx->Jc, g, pl.n_tgt, nr, ctx->d_tgt, ctx->md, 1, s);
     rc = evaluate_chunk(T, nr, ctx->Jc, o, stream);
     if (rc) return T == ctx ? rc : fail(ctx, rc, "swapped-role evaluation: " + T->err);
-    launch_conj(o, o, (long long)nr * pl.n_src * 3, s);
+    if (ctx->med.mu_one)
+      launch_conj(o, o, (long long)nr * pl.n_src * 3, s);
+    else
+      launch_conj_mu(o, o, pl.n_src, nr, ctx->d_src, ctx->md, -1, s);
   }
   HIPC(hipGetLastError());
   return LM_OK;
@@ -917,10 +929,14 @@ int lm_grad_src_xyz(lm_ctx* ctx, int n_rhs, const void* J, const void* gA, doubl
     int nr = std::min(LM_RHS_CHUNK, n_rhs - r0);
     const cd* g = (const cd*)gA + (long long)r0 * pl.n_tgt * 3;
     const cd* w = (const cd*)J + (long long)r0 * pl.n_src * 3;
-    launch_conj(ctx->Jc, g, (long long)nr * pl.n_tgt * 3, s);
+    if (ctx->med.mu_one)
+      launch_conj(ctx->Jc, g, (long long)nr * pl.n_tgt * 3, s);
+    else
+      launch_conj_mu(ctx->Jc, g, pl.n_tgt, nr, ctx->d_tgt, ctx->md, 1, s);
     rc = evaluate_chunk(T, nr, ctx->Jc, nullptr, stream, w, gX);
     if (rc) return T == ctx ? rc : fail(ctx, rc, "swapped-role evaluation: " + T->err);
   }
+  if (!ctx->med.mu_one) launch_scale_mu_d(gX, pl.n_src, ctx->d_src, ctx->md, -1, s);
   HIPC(hipGetLastError());
   return LM_OK;
 }
@@ -1124,7 +1140,10 @@ int lm_host_components(int n_layers, const double* d, const double* k, int* out,
   if (n_layers < 1 || n_layers > LM_MAXL || !k || (n_layers > 1 && !d)) return LM_EINVAL;
   Medium m;
   m.n = n_layers;
-  for (int l = 0; l < n_layers; l++) m.k[l] = k[l];
+  for (int l = 0; l < n_layers; l++) {
+    m.k[l] = k[l];
+    m.mu[l] = 1.0;
+  }
   for (int l = 0; l < n_layers - 1; l++) m.d[l] = d[l];
   std::vector<InstParams> v;
   int n = lm_enumerate_components(m, v);

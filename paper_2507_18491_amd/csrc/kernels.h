@@ -7,6 +7,7 @@ struct MediumDev {
   int n;
   double d[LM_MAXL];
   double k[LM_MAXL];
+  double mu[LM_MAXL];  // relative permeabilities
 };
 
 // device-side view of a built plan
@@ -71,6 +72,11 @@ void launch_l2p(const DevPlan& d, const int* leaves, int n, int kind, const doub
 void launch_p2p(const DevPlan& d, const int* tboxes, int n, const double* sxyz, const cd* J, long long n_src,
                 const double* txyz, long long n_tgt, int n_rhs, cd* A, bool red, hipStream_t s);
 void launch_conj(cd* out, const cd* in, long long n, hipStream_t s);
+// out[r][i][c] = conj(in[r][i][c]) mu(layer of point i)^pw, pw = +1 or -1 (n points, n_rhs vectors)
+void launch_conj_mu(cd* out, const cd* in, long long n, int n_rhs, const double* xyz, MediumDev md, int pw,
+                    hipStream_t s);
+// g[i][c] *= mu(layer of point i)^pw
+void launch_scale_mu_d(double* g, long long n, const double* xyz, MediumDev md, int pw, hipStream_t s);
 void launch_s2t(const DevPlan& d, MediumDev md, const int* items, int n, const double* sxyz, const cd* J,
                 long long n_src, const double* txyz, long long n_tgt, int n_rhs, double a, bool smallz, cd* A,
                 hipStream_t s);

@@ -1083,6 +1083,40 @@ __global__ void k_conj(cd* out, const cd* in, long long n) {
   long long st = (long long)gridDim.x * blockDim.x;
   for (; i < n; i += st) out[i] = cconj(in[i]);
 }
+__device__ inline double mu_pow(const MediumDev& md, double z, int pw) {
+  int l = 0;
+  while (l < md.n - 1 && z < md.d[l]) l++;
+  return pw > 0 ? md.mu[l] : 1.0 / md.mu[l];
+}
+__global__ void k_conj_mu(cd* out, const cd* in, long long n, long long total, const double* xyz, MediumDev md,
+                          int pw) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; e < total; e += st) {
+    const long long i = (e / 3) % n;
+    out[e] = cconj(in[e]) * mu_pow(md, xyz[3 * i + 2], pw);
+  }
+}
+void launch_conj_mu(cd* out, const cd* in, long long n, int n_rhs, const double* xyz, MediumDev md, int pw,
+                    hipStream_t s) {
+  const long long total = 3 * n * n_rhs;
+  if (total <= 0) return;
+  long long nb = std::min<long long>((total + NT - 1) / NT, 65536);
+  hipLaunchKernelGGL(k_conj_mu, dim3((unsigned)nb), dim3(NT), 0, s, out, in, n, total, xyz, md, pw);
+}
+__global__ void k_scale_mu_d(double* g, long long n, const double* xyz, MediumDev md, int pw) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += st) {
+    const double f = mu_pow(md, xyz[3 * i + 2], pw);
+    for (int c = 0; c < 3; c++) g[3 * i + c] *= f;
+  }
+}
+void launch_scale_mu_d(double* g, long long n, const double* xyz, MediumDev md, int pw, hipStream_t s) {
+  if (n <= 0) return;
+  long long nb = std::min<long long>((n + NT - 1) / NT, 65536);
+  hipLaunchKernelGGL(k_scale_mu_d, dim3((unsigned)nb), dim3(NT), 0, s, g, n, xyz, md, pw);
+}
 __global__ void k_fill_d(double* p, long long n) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   long long st = (long long)gridDim.x * blockDim.x;
@@ -1669,7 +1703,8 @@ __device__ cd react_coef(const MediumDev& md, cd kr, int lt, int ls, int up_t, i
   double beta[LM_MAXL];
   for (int m = 0; m < n; m++) {
     kz[m] = kz_of(md.k[m], kr);
-    beta[m] = pol ? md.k[m] * md.k[m] : 1.0;
+    // interface conditions of Sec. 3.1: [[u'/mu]] = 0 (TE), [[u'/eps]] = 0 (TM), eps ~ k^2 / mu
+    beta[m] = pol ? md.k[m] * md.k[m] / md.mu[m] : md.mu[m];
     E[m] = (m >= 1 && m <= L - 1) ? cexpd(cd{0, 1} * kz[m] * (md.d[m - 1] - md.d[m])) : cd{0, 0};
     Rd[m] = Ru[m] = cd{0, 0};
   }
@@ -1747,7 +1782,9 @@ __global__ void k_nodes(DevPlan d, MediumDev md, int n_nodes, const int* node_in
   q.kzt = kz_of(ip.kt, kr);
   q.kzs = kz_of(ip.ks, kr);
   cd cte = react_coef(md, kr, ip.lt, ip.ls, ip.up_t, ip.up_s, 0);
-  cd ctm = react_coef(md, kr, ip.lt, ip.ls, ip.up_t, ip.up_s, 1);
+  // the TM terms carry mu of the target layer over mu of the source layer
+  // (the TM coefficient's mu_l and its 1-D source's 1/mu_l', Sec. 3.1)
+  cd ctm = (md.mu[ip.lt] / md.mu[ip.ls]) * react_coef(md, kr, ip.lt, ip.ls, ip.up_t, ip.up_s, 1);
   double e = ip.up_t ? 1.0 : -1.0, h = ip.up_s ? -1.0 : 1.0;
   double k2 = ip.kt * ip.kt;
   cd kk = q.kzt * q.kzs;

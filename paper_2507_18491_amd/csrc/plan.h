@@ -12,6 +12,8 @@ struct Medium {
   int n = 0;                 // number of layers
   double d[LM_MAXL] = {0};   // interfaces d[0] > d[1] > ... (n-1 values)
   double k[LM_MAXL] = {0};   // wavenumbers (n values)
+  double mu[LM_MAXL] = {0};  // relative permeabilities (n values)
+  bool mu_one = true;        // every mu is 1
   double kmax = 0;
   int layer_of(double z) const {
     int l = 0;

@@ -114,11 +114,12 @@ class LMError(RuntimeError):
 class LayeredDyadicFMM:
     """A = G J for the layered electric dyadic Green's function on one GPU.
 
-    d: interfaces (top to bottom), k: layer wavenumbers (top to bottom).
+    d: interfaces (top to bottom), k: layer wavenumbers (top to bottom),
+    mu: relative permeabilities (top to bottom; None = all 1).
     Keyword parameters are those of lm_params (p, p_free, free_depth, ...).
     """
 
-    def __init__(self, d, k, device=0, **params):
+    def __init__(self, d, k, device=0, mu=None, **params):
         self.lib = load_library()
         self.ctx = ctypes.c_void_p()
         rc = self.lib.lm_create(ctypes.byref(self.ctx), int(device))
@@ -126,7 +127,13 @@ class LayeredDyadicFMM:
             raise LMError("lm_create failed (%d)" % rc)
         self.device = int(device)
         self.d, self.k = _medium(d, k)
-        self._check(self.lib.lm_set_layers(self.ctx, self.k.size, _dp(self.d), _dp(self.k), None))
+        self.mu = None
+        if mu is not None:
+            self.mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).reshape(-1))
+            if self.mu.size != self.k.size:
+                raise LMError("mu needs one value per layer")
+        self._check(self.lib.lm_set_layers(self.ctx, self.k.size, _dp(self.d), _dp(self.k),
+                                           None if self.mu is None else _dp(self.mu)))
         self.params = make_params(**params)
         self._check(self.lib.lm_set_params(self.ctx, ctypes.byref(self.params)))
         self.n_src = self.n_tgt = None
