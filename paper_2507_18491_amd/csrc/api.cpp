@@ -760,7 +760,9 @@ int lm_evaluate(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream) {
 // writing A the leaf passes add, at every target point, Re sum_b W^b grad B_b
 // (B the field of J) into gX [n_tgt][3]; A is not touched.
 // The context that evaluates the transposed operator: by reciprocity
-// (G(x, y) = G(y, x)^T), sum_i G(x_i, x_j)^T v_i is the forward sum with the
+// (G(x, y) = G(y, x)^T when every mu is 1; with permeabilities the callers
+// weight by mu, since G(x, y) mu(y) = G(y, x)^T mu(x)),
+// sum_i G(x_i, x_j)^T v_i is the forward sum with the
 // roles of sources and targets exchanged.  That is this context when the two
 // point sets are the same array, otherwise a second context built (once, on
 // the first call) with the sets swapped.
