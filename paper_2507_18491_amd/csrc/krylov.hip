@@ -53,13 +53,20 @@ __global__ __launch_bounds__(KV_NT) void k_kv_dots(cd* const* vt, int first, int
   if (t < nk) part[((long long)(k0 + t) * R + r) * NB + blk] = sm[t][0];
 }
 
-// out[t] = sum over b in order of part[t NB + b], t < cnt
-__global__ void k_kv_sum(const cd* part, int cnt, int NB, cd* out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= cnt) return;
+// out[t] = sum of part[t NB + b] over b, one 64-lane block per t: lane l adds
+// b = l, l + 64, ... in order, then a fixed LDS tree (deterministic)
+__global__ __launch_bounds__(64) void k_kv_sum(const cd* part, int NB, cd* out) {
+  const int t = blockIdx.x, l = threadIdx.x;
   cd s{0.0, 0.0};
-  for (int b = 0; b < NB; b++) s = s + part[(long long)t * NB + b];
-  out[t] = s;
+  for (int b = l; b < NB; b += 64) s = s + part[(long long)t * NB + b];
+  __shared__ cd sm[64];
+  sm[l] = s;
+  __syncthreads();
+  for (int h = 32; h > 0; h >>= 1) {
+    if (l < h) sm[l] = sm[l] + sm[l + h];
+    __syncthreads();
+  }
+  if (l == 0) out[t] = sm[0];
 }
 
 // dst[r][i] += sum_k V_{first+k}[r][i] c[k R + r], grid (blocks, R)
@@ -131,7 +138,7 @@ void launch_kv_dots(cd* const* vt, int first, int count, int w, long long n3, in
   dim3 g((unsigned)nb, (unsigned)n_rhs, (unsigned)((count + KV_G - 1) / KV_G));
   hipLaunchKernelGGL(k_kv_dots, g, dim3(KV_NT), 0, s, vt, first, count, w, n3, n_rhs, nb, part);
   const int cnt = count * n_rhs;
-  hipLaunchKernelGGL(k_kv_sum, dim3((unsigned)((cnt + 63) / 64)), dim3(64), 0, s, part, cnt, nb, out);
+  hipLaunchKernelGGL(k_kv_sum, dim3((unsigned)cnt), dim3(64), 0, s, part, nb, out);
 }
 
 void launch_kv_combine(cd* const* vt, int first, int count, const cd* c, int dst, long long n3, int n_rhs,

@@ -20,6 +20,9 @@ benchmark configurations:
                half the points uniform (25 % per layer), half in 20 Gaussian
                blobs (sigma 0.3, 5 per layer).
 * ``clustered`` the three-layer medium with Gaussian blobs (sigma 0.3).
+* ``six_layer`` 6 layers, interfaces z=0, -0.8, -1.5, -2.4, -3.0,
+               k=(1.0, 1.6, 2.2, 1.3, 1.9, 1.1); N points uniform in
+               [-w,w]^2 x each layer's slab, equal shares.
 * ``dipole_lattice`` the three-layer medium filled with a jittered cubic
                lattice of small dielectric spheres: the coupled-dipole system
                (diag - G) X = B of the iterative solve.
@@ -32,6 +35,7 @@ MEDIA = {
     "two": dict(d=[0.0], k=[1.0, 1.5]),
     "three": dict(d=[0.0, -1.2], k=[1.2, 2.0, 1.5]),
     "four": dict(d=[0.0, -1.0, -2.5], k=[1.0, 1.8, 2.4, 1.3]),
+    "six": dict(d=[0.0, -0.8, -1.5, -2.4, -3.0], k=[1.0, 1.6, 2.2, 1.3, 1.9, 1.1]),
 }
 
 MARGIN = 0.05
@@ -231,3 +235,14 @@ def dipole_lattice(n, seed=0, n_rhs=1, eps_r=2.25, jitter=0.1, split=(0.4, 0.3, 
     xyz = np.vstack(pts)
     B = currents(rng, xyz.shape[0], n_rhs)
     return d, k, xyz, np.concatenate(diag), B
+
+
+def six_layer(n, seed=0, n_rhs=1, half_width=1.0):
+    """Six-layer uniform workload (equal shares per layer); returns (d, k, xyz, J)."""
+    rng = np.random.default_rng(seed + 8000)
+    m = MEDIA["six"]
+    counts = [n // 6] * 5
+    counts.append(n - sum(counts))
+    xyz = _uniform_layers(rng, counts, layer_slabs(m["d"]), half_width)
+    J = currents(rng, n, n_rhs)
+    return np.array(m["d"]), np.array(m["k"]), xyz, J
