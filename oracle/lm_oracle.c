@@ -299,8 +299,36 @@ static void or_accumulate(cplx G[3][3], cplx wgt, cplx kr, double k, const cplx 
   G[2][1] += w * (kr * Sp[2] * Jb[1] * s1);
 }
 
+/* Magnetic dyadic (Sec. 3.1, the J6..J9 form), normalised as
+ * G_H = (1/mu_t) curl_x G_E:
+ *   Ghat_H = (1/mu_t) [ u_TE J6 + g u_TM J7 + (d_z u_TE + g d_z' u_TM) J8 / kr^2
+ *                       - d_z u_TE J9 ]
+ * (g = mu_t/mu_s is already in the TM scalars Sp).  Angular integrals:
+ * i k_x, i k_y -> -kr J1 (cos phi, sin phi); k_x k_y, k_y^2, -k_x^2 ->
+ * kr^2 (-J2 s2, J0 + J2 c2, -(J0 - J2 c2)) / 2.                          */
+static void or_accumulate_h(cplx G[3][3], cplx wgt, cplx kr, double inv_mu, const cplx Sf[4],
+                            const cplx Sp[4], const cplx Jb[3], double c1, double s1,
+                            double c2, double s2) {
+  cplx w = wgt * kr * inv_mu;
+  cplx a6 = Sf[0], a7 = Sp[0], a8 = Sf[1] + Sp[2], a9 = -Sf[1];
+  /* J6 (row z): (-i k_y, i k_x, 0) */
+  G[2][0] += w * (a6 * kr * Jb[1] * s1);
+  G[2][1] += w * (-a6 * kr * Jb[1] * c1);
+  /* J7 (column z): (i k_y, -i k_x, 0)^T */
+  G[0][2] += w * (-a7 * kr * Jb[1] * s1);
+  G[1][2] += w * (a7 * kr * Jb[1] * c1);
+  /* J8 / kr^2: [[k_x k_y, k_y^2], [-k_x^2, -k_x k_y]] / kr^2 */
+  G[0][0] += w * (a8 * (-0.5 * Jb[2] * s2));
+  G[0][1] += w * (a8 * 0.5 * (Jb[0] + Jb[2] * c2));
+  G[1][0] += w * (a8 * (-0.5) * (Jb[0] - Jb[2] * c2));
+  G[1][1] += w * (a8 * 0.5 * Jb[2] * s2);
+  /* J9: [[0, 1], [-1, 0]] */
+  G[0][1] += w * (a9 * Jb[0]);
+  G[1][0] += w * (-a9 * Jb[0]);
+}
+
 static void or_sommerfeld_pair(const or_medium *md, const or_contour *ct, const double *x,
-                               const double *xp, int free_only, double kfree,
+                               const double *xp, int free_only, double kfree, int field,
                                cplx G[3][3]) {
   or_init_gl();
   for (int i = 0; i < 3; i++)
@@ -315,6 +343,7 @@ static void or_sommerfeld_pair(const or_medium *md, const or_contour *ct, const 
    * coefficient is scaled by the target layer's mu and its 1-D source by
    * 1 / mu of the source layer); the TE terms carry no mu                  */
   double tm_scale = free_only ? 1.0 : md->mu[t] / md->mu[s];
+  double inv_mu = free_only ? 1.0 : 1.0 / md->mu[t];
   cplx ampf[2][OR_MAXL][2], ampp[2][OR_MAXL][2];
   cplx Sf[4], Sp[4], Jb[3];
   /* ellipse: kr(th) = a/2 (1 - cos th) - i depth sin th, th in [0, pi] */
@@ -337,7 +366,10 @@ static void or_sommerfeld_pair(const or_medium *md, const or_contour *ct, const 
         for (int q = 0; q < 4; q++) Sp[q] *= tm_scale;
       }
       or_bessel012_c(kr * rho, Jb);
-      or_accumulate(G, wgt, kr, k, Sf, Sp, Jb, c1, s1, c2, s2);
+      if (field)
+        or_accumulate_h(G, wgt, kr, inv_mu, Sf, Sp, Jb, c1, s1, c2, s2);
+      else
+        or_accumulate(G, wgt, kr, k, Sf, Sp, Jb, c1, s1, c2, s2);
     }
   }
   /* real tail [a, inf) */
@@ -364,7 +396,10 @@ static void or_sommerfeld_pair(const or_medium *md, const or_contour *ct, const 
         for (int q = 0; q < 4; q++) Sp[q] *= tm_scale;
       }
       or_bessel012_r(krr * rho, Jb);
-      or_accumulate(G, wgt, kr, k, Sf, Sp, Jb, c1, s1, c2, s2);
+      if (field)
+        or_accumulate_h(G, wgt, kr, inv_mu, Sf, Sp, Jb, c1, s1, c2, s2);
+      else
+        or_accumulate(G, wgt, kr, k, Sf, Sp, Jb, c1, s1, c2, s2);
     }
   }
   for (int i = 0; i < 3; i++)
@@ -380,6 +415,18 @@ static void or_free_dyadic(double k, const double *R, cplx G[3][3]) {
   cplx b = g * (-1.0 - 3.0 * I / kr + 3.0 / (kr * kr));
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) G[i][j] = (i == j ? a : 0.0) + b * (R[i] / r) * (R[j] / r);
+}
+
+/* textbook free-space curl: (curl (g I)) q = grad g x q, i.e. the matrix
+ * [[0, -g_z, g_y], [g_z, 0, -g_x], [-g_y, g_x, 0]], grad g = g (ik - 1/r) R/r */
+static void or_free_curl(double k, const double *R, cplx G[3][3]) {
+  double r = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+  cplx g = cexp(I * k * r) / (4.0 * M_PI * r);
+  cplx gp = g * (I * k - 1.0 / r);
+  cplx gx = gp * R[0] / r, gy = gp * R[1] / r, gz = gp * R[2] / r;
+  G[0][0] = 0.0; G[0][1] = -gz; G[0][2] = gy;
+  G[1][0] = gz; G[1][1] = 0.0; G[1][2] = -gx;
+  G[2][0] = -gy; G[2][1] = gx; G[2][2] = 0.0;
 }
 
 static int or_setup(or_medium *md, int n_layers, const double *d, const double *k, const double *mu) {
@@ -412,8 +459,8 @@ static void or_default_contour(const or_medium *md, double rho_max, or_contour *
 
 /* 3x3 G(x, x') (row-major complex128 out[9]); quad_scale > 1 refines the
  * contour (more ellipse panels, shorter tail panels) for convergence checks. */
-int lm_oracle_pair(int n_layers, const double *d, const double *k, const double *mu, const double *x,
-                   const double *xp, double quad_scale, double *out) {
+static int or_pair(int field, int n_layers, const double *d, const double *k, const double *mu,
+                   const double *x, const double *xp, double quad_scale, double *out) {
   or_medium md;
   int rc = or_setup(&md, n_layers, d, k, mu);
   if (rc) return rc;
@@ -426,12 +473,18 @@ int lm_oracle_pair(int n_layers, const double *d, const double *k, const double 
     ct.decay_stop += 4.0;
   }
   cplx G[3][3];
-  or_sommerfeld_pair(&md, &ct, x, xp, 0, 0.0, G);
+  or_sommerfeld_pair(&md, &ct, x, xp, 0, 0.0, field, G);
   int t = or_layer_of(&md, x[2]), s = or_layer_of(&md, xp[2]);
   double R[3] = {x[0] - xp[0], x[1] - xp[1], x[2] - xp[2]};
   if (t == s && (R[0] != 0.0 || R[1] != 0.0 || R[2] != 0.0)) {
     cplx Gf[3][3];
-    or_free_dyadic(md.k[t], R, Gf);
+    if (field) {
+      or_free_curl(md.k[t], R, Gf);
+      for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) Gf[i][j] /= md.mu[t];
+    } else {
+      or_free_dyadic(md.k[t], R, Gf);
+    }
     for (int i = 0; i < 3; i++)
       for (int j = 0; j < 3; j++) G[i][j] += Gf[i][j];
   }
@@ -440,6 +493,17 @@ int lm_oracle_pair(int n_layers, const double *d, const double *k, const double 
     out[2 * i + 1] = cimag(G[i / 3][i % 3]);
   }
   return 0;
+}
+
+int lm_oracle_pair(int n_layers, const double *d, const double *k, const double *mu, const double *x,
+                   const double *xp, double quad_scale, double *out) {
+  return or_pair(0, n_layers, d, k, mu, x, xp, quad_scale, out);
+}
+
+/* magnetic dyadic G_H(x, x') = (1/mu_t) curl_x G(x, x') (J6..J9 form of Sec. 3.1) */
+int lm_oracle_pair_h(int n_layers, const double *d, const double *k, const double *mu, const double *x,
+                     const double *xp, double quad_scale, double *out) {
+  return or_pair(1, n_layers, d, k, mu, x, xp, quad_scale, out);
 }
 
 /* reaction part only (no free-space term) */
@@ -456,7 +520,7 @@ int lm_oracle_reaction_pair(int n_layers, const double *d, const double *k, cons
     ct.decay_stop += 4.0;
   }
   cplx G[3][3];
-  or_sommerfeld_pair(&md, &ct, x, xp, 0, 0.0, G);
+  or_sommerfeld_pair(&md, &ct, x, xp, 0, 0.0, 0, G);
   for (int i = 0; i < 9; i++) {
     out[2 * i] = creal(G[i / 3][i % 3]);
     out[2 * i + 1] = cimag(G[i / 3][i % 3]);
@@ -474,9 +538,31 @@ int lm_oracle_free_check(double k, const double *x, const double *xp, double *ou
   or_contour ct;
   or_default_contour(&md, hypot(x[0] - xp[0], x[1] - xp[1]), &ct);
   cplx G[3][3], Gf[3][3];
-  or_sommerfeld_pair(&md, &ct, x, xp, 1, k, G);
+  or_sommerfeld_pair(&md, &ct, x, xp, 1, k, 0, G);
   double R[3] = {x[0] - xp[0], x[1] - xp[1], x[2] - xp[2]};
   or_free_dyadic(k, R, Gf);
+  for (int i = 0; i < 9; i++) {
+    out_somm[2 * i] = creal(G[i / 3][i % 3]);
+    out_somm[2 * i + 1] = cimag(G[i / 3][i % 3]);
+    out_closed[2 * i] = creal(Gf[i / 3][i % 3]);
+    out_closed[2 * i + 1] = cimag(Gf[i / 3][i % 3]);
+  }
+  return 0;
+}
+
+/* free-space curl through the Sommerfeld route (J6, J7, J9 terms) and the
+ * closed form grad g x (.)                                               */
+int lm_oracle_free_check_h(double k, const double *x, const double *xp, double *out_somm,
+                           double *out_closed) {
+  or_medium md;
+  double kk[1] = {k};
+  or_setup(&md, 1, NULL, kk, NULL);
+  or_contour ct;
+  or_default_contour(&md, hypot(x[0] - xp[0], x[1] - xp[1]), &ct);
+  cplx G[3][3], Gf[3][3];
+  or_sommerfeld_pair(&md, &ct, x, xp, 1, k, 1, G);
+  double R[3] = {x[0] - xp[0], x[1] - xp[1], x[2] - xp[2]};
+  or_free_curl(k, R, Gf);
   for (int i = 0; i < 9; i++) {
     out_somm[2 * i] = creal(G[i / 3][i % 3]);
     out_somm[2 * i + 1] = cimag(G[i / 3][i % 3]);
@@ -523,8 +609,8 @@ void lm_oracle_bessel012(double zr, double zi, double *out) {
  * The free-space term is skipped for coincident points; sources with an
  * all-zero current in every right-hand side are skipped (they contribute
  * exactly zero).  OpenMP over targets, fixed order over sources.        */
-int lm_oracle_direct(int n_layers, const double *d, const double *k, const double *mu, int64_t n_src,
-                     const double *src_xyz, int n_rhs, const double *J, int64_t n_tgt,
+static int or_direct(int field, int n_layers, const double *d, const double *k, const double *mu,
+                     int64_t n_src, const double *src_xyz, int n_rhs, const double *J, int64_t n_tgt,
                      const double *tgt_xyz, double *A, int n_threads) {
   or_medium md;
   int rc = or_setup(&md, n_layers, d, k, mu);
@@ -557,12 +643,18 @@ int lm_oracle_direct(int n_layers, const double *d, const double *k, const doubl
       if (!active[j]) continue;
       const double *xp = src_xyz + 3 * j;
       cplx G[3][3];
-      or_sommerfeld_pair(&md, &ct, x, xp, 0, 0.0, G);
+      or_sommerfeld_pair(&md, &ct, x, xp, 0, 0.0, field, G);
       int s = or_layer_of(&md, xp[2]);
       double R[3] = {x[0] - xp[0], x[1] - xp[1], x[2] - xp[2]};
       if (t == s && (R[0] != 0.0 || R[1] != 0.0 || R[2] != 0.0)) {
         cplx Gf[3][3];
-        or_free_dyadic(md.k[t], R, Gf);
+        if (field) {
+          or_free_curl(md.k[t], R, Gf);
+          for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) Gf[a][b] /= md.mu[t];
+        } else {
+          or_free_dyadic(md.k[t], R, Gf);
+        }
         for (int a = 0; a < 3; a++)
           for (int b = 0; b < 3; b++) G[a][b] += Gf[a][b];
       }
@@ -580,6 +672,19 @@ int lm_oracle_direct(int n_layers, const double *d, const double *k, const doubl
   }
   free(active);
   return n_rhs > 64 ? -1 : 0;
+}
+
+int lm_oracle_direct(int n_layers, const double *d, const double *k, const double *mu, int64_t n_src,
+                     const double *src_xyz, int n_rhs, const double *J, int64_t n_tgt,
+                     const double *tgt_xyz, double *A, int n_threads) {
+  return or_direct(0, n_layers, d, k, mu, n_src, src_xyz, n_rhs, J, n_tgt, tgt_xyz, A, n_threads);
+}
+
+/* H_i = sum_j G_H(x_i, x_j) J_j, same layout and rules as lm_oracle_direct */
+int lm_oracle_direct_h(int n_layers, const double *d, const double *k, const double *mu, int64_t n_src,
+                       const double *src_xyz, int n_rhs, const double *J, int64_t n_tgt,
+                       const double *tgt_xyz, double *A, int n_threads) {
+  return or_direct(1, n_layers, d, k, mu, n_src, src_xyz, n_rhs, J, n_tgt, tgt_xyz, A, n_threads);
 }
 
 /* free-space part only (closed form, same-layer, x_i != x_j): used for the

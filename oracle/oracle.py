@@ -38,6 +38,10 @@ def _load():
         lib.lm_oracle_pair.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_double, P]
         lib.lm_oracle_reaction_pair.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_double, P]
         lib.lm_oracle_free_check.argtypes = [ctypes.c_double, P, P, P, P]
+        lib.lm_oracle_pair_h.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_double, P]
+        lib.lm_oracle_free_check_h.argtypes = [ctypes.c_double, P, P, P, P]
+        lib.lm_oracle_direct_h.argtypes = [ctypes.c_int, P, P, P, ctypes.c_int64, P, ctypes.c_int, P,
+                                           ctypes.c_int64, P, P, ctypes.c_int]
         lib.lm_oracle_spectral.argtypes = [ctypes.c_int, P, P, P, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_double, P]
         lib.lm_oracle_bessel012.argtypes = [ctypes.c_double, ctypes.c_double, P]
@@ -82,6 +86,30 @@ def pair(d, k, x, xp, quad_scale=1.0, mu=None):
     if rc:
         raise ValueError("oracle rejected the medium (rc=%d)" % rc)
     return out.view(np.complex128).reshape(3, 3)
+
+
+def pair_h(d, k, x, xp, quad_scale=1.0, mu=None):
+    """Magnetic dyadic G_H(x, x') = (1/mu_t) curl_x G(x, x'), 3x3: the J6..J9
+    form of the spectral dyadic (Sec. 3.1) plus, for the same layer and
+    distinct points, the free-space curl grad g x (.) / mu."""
+    d, k, mu = _medium(d, k, mu)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    xp = np.ascontiguousarray(xp, dtype=np.float64)
+    out = np.zeros(18)
+    rc = _load().lm_oracle_pair_h(k.size, _p(d), _p(k), _pm(mu), _p(x), _p(xp), quad_scale, _p(out))
+    if rc:
+        raise ValueError("oracle rejected the medium (rc=%d)" % rc)
+    return out.view(np.complex128).reshape(3, 3)
+
+
+def free_check_h(k, x, xp):
+    """(Sommerfeld-route free curl dyadic, closed form grad g x (.))."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    xp = np.ascontiguousarray(xp, dtype=np.float64)
+    a = np.zeros(18)
+    b = np.zeros(18)
+    _load().lm_oracle_free_check_h(float(k), _p(x), _p(xp), _p(a), _p(b))
+    return a.view(np.complex128).reshape(3, 3), b.view(np.complex128).reshape(3, 3)
 
 
 def reaction_pair(d, k, x, xp, quad_scale=1.0, mu=None):
@@ -147,6 +175,25 @@ def direct(d, k, src, J, tgt, n_threads=None, mu=None):
     if rc:
         raise ValueError("oracle failed (rc=%d)" % rc)
     return A[0] if single else A
+
+
+def direct_h(d, k, src, J, tgt, n_threads=None, mu=None):
+    """H[r, i] = sum_j G_H(tgt_i, src_j) J[r, j] (complex128 [n_rhs, n_tgt, 3])."""
+    d, k, mu = _medium(d, k, mu)
+    src = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, 3)
+    tgt = np.ascontiguousarray(tgt, dtype=np.float64).reshape(-1, 3)
+    J = np.asarray(J, dtype=np.complex128)
+    single = J.ndim == 2
+    J = np.ascontiguousarray(J.reshape(-1, src.shape[0], 3))
+    H = np.zeros((J.shape[0], tgt.shape[0], 3), dtype=np.complex128)
+    if n_threads is None:
+        n_threads = os.cpu_count() or 1
+    rc = _load().lm_oracle_direct_h(k.size, _p(d), _p(k), _pm(mu), src.shape[0], _p(src), J.shape[0],
+                                    _p(J.view(np.float64)), tgt.shape[0], _p(tgt), _p(H.view(np.float64)),
+                                    int(n_threads))
+    if rc:
+        raise ValueError("oracle failed (rc=%d)" % rc)
+    return H[0] if single else H
 
 
 def direct_free(d, k, src, J, tgt, n_threads=None):

@@ -430,3 +430,64 @@ def test_maxwell_interface_conditions_with_mu(oracle, src_layer):
         tang = np.abs(cu[:2] / mu[li] - cd[:2] / mu[li + 1]).max()
         assert tang < 1e-5 * np.abs(cu[:2] / mu[li]).max()
         assert np.abs(cu[2] - cd[2]).max() < 1e-5 * np.abs(cu).max()
+
+
+# ---------------------------------------------------------------- magnetic dyadic
+@pytest.mark.parametrize("k,x,xp", [
+    (1.3, [0.3, 0.2, 0.5], [0.0, 0.1, -0.2]),
+    (2.0, [-0.4, 0.7, 0.1], [0.2, -0.3, 0.05]),
+    (0.8, [1.5, -0.2, -0.3], [0.0, 0.0, 0.4]),
+])
+def test_free_curl_sommerfeld_identity(oracle, k, x, xp):
+    """The J6, J7, J9 terms of the magnetic spectral dyadic with the
+    free-space scalars reproduce grad g x (.) (textbook closed form)."""
+    a, b = oracle.free_check_h(k, np.array(x, float), np.array(xp, float))
+    assert rel(a, b) < 1e-12
+
+
+@pytest.mark.parametrize("mu", [None, MU3])
+def test_magnetic_dyadic_is_faraday_curl(oracle, mu):
+    """G_H(x, y) = (1/mu(x)) curl_x G(x, y) (Faraday's law) for every pair of
+    layers, by central differences of the electric oracle: pins the J6..J9
+    form, its J8 term and its mu factors against the electric dyadic."""
+    h = 2e-5
+    lay = lambda z: 0 if z > D3[0] else (1 if z > D3[1] else 2)
+    rng = np.random.default_rng(50)
+    P = _pts_in_layers(rng)
+    Q = _pts_in_layers(rng)
+    for x in P:
+        for y in Q:
+            G = lambda q: oracle.pair(D3, K3, q, y, mu=mu)
+            dG = []
+            for a in range(3):
+                e = np.zeros(3)
+                e[a] = h
+                dG.append((G(x + e) - G(x - e)) / (2 * h))
+            curl = np.array([dG[1][2] - dG[2][1], dG[2][0] - dG[0][2], dG[0][1] - dG[1][0]])
+            m = 1.0 if mu is None else mu[lay(x[2])]
+            assert rel(oracle.pair_h(D3, K3, x, y, mu=mu), curl / m) < 1e-6
+
+
+def test_magnetic_interface_conditions(oracle):
+    """Across each interface: tangential H and normal mu H continuous."""
+    rng = np.random.default_rng(60)
+    mu = np.array(MU3)
+    for src_layer in range(3):
+        xp = _pts_in_layers(rng)[src_layer]
+        for li, dz in enumerate(D3):
+            xy = xp[:2] + rng.uniform(-0.7, 0.7, 2)
+            Hu = oracle.pair_h(D3, K3, np.array([xy[0], xy[1], dz + 1e-10]), xp, mu=MU3)
+            Hd = oracle.pair_h(D3, K3, np.array([xy[0], xy[1], dz - 1e-10]), xp, mu=MU3)
+            scale = np.abs(Hu).max()
+            assert np.abs(Hu[:2] - Hd[:2]).max() < 1e-8 * scale
+            assert np.abs(mu[li] * Hu[2] - mu[li + 1] * Hd[2]).max() < 1e-8 * scale * mu.max()
+
+
+def test_direct_h_is_sum_of_pairs(oracle):
+    rng = np.random.default_rng(70)
+    src = np.vstack(_pts_in_layers(rng) + _pts_in_layers(rng))
+    tgt = np.vstack(_pts_in_layers(rng))
+    J = rng.standard_normal((src.shape[0], 3)) + 1j * rng.standard_normal((src.shape[0], 3))
+    H = oracle.direct_h(D3, K3, src, J, tgt, mu=MU3)
+    ref = np.array([sum(oracle.pair_h(D3, K3, t, s, mu=MU3) @ j for s, j in zip(src, J)) for t in tgt])
+    assert rel(H, ref) < 1e-13
