@@ -189,6 +189,7 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the 32 uneven geometries")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-vector batched evaluation")
     ap.add_argument("--no-solve", action="store_true", help="skip the iterative coupled-dipole solve")
+    ap.add_argument("--no-magnetic", action="store_true", help="skip the magnetic-field evaluation")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint and source-gradient timings (profiling runs of the forward step)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -287,6 +288,25 @@ def main():
             Js, keep = inputs.sparse_currents(J, 400, seed=0)
             As = fmm.evaluate(torch.tensor(Js, device=dev)).cpu().numpy()
             acc = float(np.linalg.norm(As[g["idx"]] - g["A"]) / np.linalg.norm(g["A"]))
+    magnetic = None
+    if not args.no_magnetic:
+        # magnetic field of the same currents (curl of the electric field); the
+        # first call builds the plan without direct reaction pairs
+        Jm = torch.tensor(J, device=dev)
+        t0 = time.time()
+        Hm = fmm.evaluate_h(Jm)
+        torch.cuda.synchronize()
+        first_s = time.time() - t0
+        t0 = time.time()
+        for _ in range(args.steps):
+            fmm.evaluate_h(Jm, out=Hm)
+        torch.cuda.synchronize()
+        mag_s = (time.time() - t0) / args.steps
+        del Hm, Jm
+        magnetic = {"targets_per_s": args.n * args.rhs / mag_s, "ms_per_step": 1e3 * mag_s,
+                    "first_call_s": first_s, "vs_forward": (wall / args.steps) / mag_s}
+        print("magnetic field: %.1f ms/step (first call %.2f s)" % (1e3 * mag_s, first_s), file=sys.stderr,
+              flush=True)
     fmm.close()
     uneven = None if args.no_uneven else uneven_geometries(args, torch, inputs, lmfmm)
     batched = None if args.no_batched else batched_rhs(args, torch, inputs, lmfmm)
@@ -328,6 +348,7 @@ def main():
         "uneven_geometries": uneven,
         "batched_rhs": batched,
         "solve": solve,
+        "magnetic": magnetic,
         "m2l_autotune": {"chosen_variant_per_launch": m2l_var,
                          "tuning_ms_per_step_by_variant": [round(float(v), 3) for v in m2l_ms.sum(axis=0)],
                          "tuning_ms_per_step_chosen": round(float(sum(m2l_ms[i, v] for i, v in enumerate(m2l_var))), 3)},

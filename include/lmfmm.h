@@ -151,6 +151,21 @@ int lm_build_batch(lm_ctx* ctx, int n_geom, const int64_t* src_off, const double
  * summation order is fixed, so repeated calls give bitwise equal results. */
 int lm_evaluate(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream);
 
+/* Magnetic field of the same currents: H = G_H J with the magnetic dyadic of
+ * Sec. 3.1 (the J6..J9 form), normalised as G_H(x, y) = (1/mu(x)) curl_x
+ * G(x, y) (Faraday's law; in free space curl (g I) q = grad g x q, the
+ * paper's free-space G_H without its constant i/(omega mu_0) factor).
+ * Evaluated as the curl of the electric field: the far field by exact
+ * derivatives of the local expansions (ladder relations of the regular wave
+ * functions), the free-space near field in closed form.  A build whose plan
+ * evaluates reaction pairs directly (the near field of components next to
+ * an interface) gets a second plan with those trees refined until none
+ * remain, built on the first call (which then synchronises `stream` once and
+ * allocates).  J: DEVICE complex128 [n_rhs][n_src][3]; H: DEVICE complex128
+ * [n_rhs][n_tgt][3], overwritten.  Asynchronous otherwise; errors as
+ * lm_evaluate. */
+int lm_evaluate_h(lm_ctx* ctx, int n_rhs, const void* J, void* H, void* stream);
+
 /* Adjoint evaluation (the conjugate transpose of lm_evaluate's operator):
  *     gJ_j = sum_i G(x_i, x_j)^H gA_i      (x_i targets, x_j sources),
  * for n_rhs vectors.  gA: DEVICE complex128 [n_rhs][n_tgt][3]; gJ: DEVICE

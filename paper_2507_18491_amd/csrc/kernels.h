@@ -75,6 +75,14 @@ void launch_conj(cd* out, const cd* in, long long n, hipStream_t s);
 // out[r][i][c] = conj(in[r][i][c]) mu(layer of point i)^pw, pw = +1 or -1 (n points, n_rhs vectors)
 void launch_conj_mu(cd* out, const cd* in, long long n, int n_rhs, const double* xyz, MediumDev md, int pw,
                     hipStream_t s);
+// v[r][i][c] *= mu(layer of point i)^pw
+void launch_scale_mu(cd* v, long long n, int n_rhs, const double* xyz, MediumDev md, int pw, hipStream_t s);
+// magnetic field (curl of the electric field): far part from the local
+// expansions, free-space near part grad g x q; both add into Hc [rhs][point][3]
+void launch_l2p_curl(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_pts,
+                     int n_rhs, const cd* LE, cd* Hc, int pi, hipStream_t s);
+void launch_p2p_curl(const DevPlan& d, const int* tboxes, int n, const double* sxyz, const cd* J, long long n_src,
+                     const double* txyz, long long n_tgt, int n_rhs, cd* Hc, bool red, hipStream_t s);
 // g[i][c] *= mu(layer of point i)^pw
 void launch_scale_mu_d(double* g, long long n, const double* xyz, MediumDev md, int pw, hipStream_t s);
 void launch_s2t(const DevPlan& d, MediumDev md, const int* items, int n, const double* sxyz, const cd* J,

@@ -1104,6 +1104,20 @@ void launch_conj_mu(cd* out, const cd* in, long long n, int n_rhs, const double*
   long long nb = std::min<long long>((total + NT - 1) / NT, 65536);
   hipLaunchKernelGGL(k_conj_mu, dim3((unsigned)nb), dim3(NT), 0, s, out, in, n, total, xyz, md, pw);
 }
+__global__ void k_scale_mu(cd* v, long long n, long long total, const double* xyz, MediumDev md, int pw) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; e < total; e += st) {
+    const long long i = (e / 3) % n;
+    v[e] = v[e] * mu_pow(md, xyz[3 * i + 2], pw);
+  }
+}
+void launch_scale_mu(cd* v, long long n, int n_rhs, const double* xyz, MediumDev md, int pw, hipStream_t s) {
+  const long long total = 3 * n * n_rhs;
+  if (total <= 0) return;
+  long long nb = std::min<long long>((total + NT - 1) / NT, 65536);
+  hipLaunchKernelGGL(k_scale_mu, dim3((unsigned)nb), dim3(NT), 0, s, v, n, total, xyz, md, pw);
+}
 __global__ void k_scale_mu_d(double* g, long long n, const double* xyz, MediumDev md, int pw) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   long long st = (long long)gridDim.x * blockDim.x;
@@ -1140,10 +1154,13 @@ void launch_conj(cd* out, const cd* in, long long n, hipStream_t s) {
 // wave functions) give 9 expansions of one order more, evaluated at every
 // point of the leaf.  For a reaction component the evaluation point is the
 // effective location zhat = at z + bt, so d/dz = at d/dzhat.
-template <int NTB>
+// CURL: instead of contracting the derivatives with W into gX, the curl of
+// the field is added to Hc [rhs][point][3] (the magnetic field's far part,
+// Faraday's law, before the 1/mu of the point's layer).
+template <int NTB, bool CURL>
 __global__ __launch_bounds__(NTB) void k_l2p_grad(DevPlan d, const int* leaves, int ch, int kind, const double* xyz,
                                                   long long n_pts, int n_rhs, const cd* LE, const cd* W,
-                                                  double* gX) {
+                                                  double* gX, cd* Hc) {
   extern __shared__ cd Ls[];
   // work item: (leaf, chunk of ch points)
   int b = leaves[2 * blockIdx.x];
@@ -1242,29 +1259,39 @@ __global__ __launch_bounds__(NTB) void k_l2p_grad(DevPlan d, const int* leaves, 
         dB[1][c] = cd{h.y, -h.x};  // (dp - dm) / (2i)
         dB[2][c] = dzv;
       }
-      const cd* w = W + ((long long)r * n_pts + id) * 3;
-      cd wx = w[0], wy = w[1], wz = w[2];
+      cd jac[3][3];  // [direction][cartesian field component]
       for (int a = 0; a < 3; a++) {
         // cartesian field components from the spin channels
-        cd bx = 0.5 * (dB[a][0] + dB[a][1]);
+        jac[a][0] = 0.5 * (dB[a][0] + dB[a][1]);
         cd h = 0.5 * (dB[a][0] - dB[a][1]);
-        cd by = cd{h.y, -h.x};
-        cd bz = dB[a][2];
-        cd v = wx * bx + wy * by + wz * bz;
-        gX[3 * id + a] += v.x;
+        jac[a][1] = cd{h.y, -h.x};
+        jac[a][2] = dB[a][2];
+      }
+      if (CURL) {
+        cd* o = Hc + ((long long)r * n_pts + id) * 3;
+        o[0] = o[0] + (jac[1][2] - jac[2][1]);
+        o[1] = o[1] + (jac[2][0] - jac[0][2]);
+        o[2] = o[2] + (jac[0][1] - jac[1][0]);
+      } else {
+        const cd* w = W + ((long long)r * n_pts + id) * 3;
+        cd wx = w[0], wy = w[1], wz = w[2];
+        for (int a = 0; a < 3; a++) {
+          cd v = wx * jac[a][0] + wy * jac[a][1] + wz * jac[a][2];
+          gX[3 * id + a] += v.x;
+        }
       }
     }
   }
 }
-template <int NTB>
+template <int NTB, bool CURL>
 static void l2p_grad_go(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_pts,
-                        int n_rhs, const cd* LE, const cd* W, double* gX, int pi, hipStream_t s) {
+                        int n_rhs, const cd* LE, const cd* W, double* gX, cd* Hc, int pi, hipStream_t s) {
   int pg = (kind == 0 ? pi + 2 : pi) + 1;
   int Pg = (pg + 1) * (pg + 1), Pd = (pi + 2) * (pi + 2);
   size_t shm = (size_t)(12 * Pg + Pd) * sizeof(cd) + (size_t)NTB * (pg + 1) * sizeof(double);
-  set_dyn_lds((const void*)k_l2p_grad<NTB>, shm);
-  hipLaunchKernelGGL(k_l2p_grad<NTB>, dim3(n), dim3(NTB), shm, s, d, leaves, LM_L2P_CHUNK(kind), kind, xyz, n_pts,
-                     n_rhs, LE, W, gX);
+  set_dyn_lds((const void*)k_l2p_grad<NTB, CURL>, shm);
+  hipLaunchKernelGGL((k_l2p_grad<NTB, CURL>), dim3(n), dim3(NTB), shm, s, d, leaves, LM_L2P_CHUNK(kind), kind, xyz,
+                     n_pts, n_rhs, LE, W, gX, Hc);
 }
 // pi: the instance's expansion order; reaction items with one-wave blocks,
 // free-space items with 128 threads (LDS of order p + 3 expansions)
@@ -1272,9 +1299,17 @@ void launch_l2p_grad(const DevPlan& d, const int* leaves, int n, int kind, const
                      int n_rhs, const cd* LE, const cd* W, double* gX, int pi, hipStream_t s) {
   if (n <= 0) return;
   if (kind == 1)
-    l2p_grad_go<64>(d, leaves, n, kind, xyz, n_pts, n_rhs, LE, W, gX, pi, s);
+    l2p_grad_go<64, false>(d, leaves, n, kind, xyz, n_pts, n_rhs, LE, W, gX, nullptr, pi, s);
   else
-    l2p_grad_go<128>(d, leaves, n, kind, xyz, n_pts, n_rhs, LE, W, gX, pi, s);
+    l2p_grad_go<128, false>(d, leaves, n, kind, xyz, n_pts, n_rhs, LE, W, gX, nullptr, pi, s);
+}
+void launch_l2p_curl(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_pts,
+                     int n_rhs, const cd* LE, cd* Hc, int pi, hipStream_t s) {
+  if (n <= 0) return;
+  if (kind == 1)
+    l2p_grad_go<64, true>(d, leaves, n, kind, xyz, n_pts, n_rhs, LE, nullptr, nullptr, Hc, pi, s);
+  else
+    l2p_grad_go<128, true>(d, leaves, n, kind, xyz, n_pts, n_rhs, LE, nullptr, nullptr, Hc, pi, s);
 }
 
 // Free-space near field: for the target point x_i (here a source point of
@@ -1375,6 +1410,77 @@ void launch_p2p_grad(const DevPlan& d, const int* tboxes, int n, const double* s
   else
     hipLaunchKernelGGL(k_p2p_grad<false>, dim3(n), dim3(NT), 0, s, d, tboxes, sxyz, Jsrc, n_src, txyz, W, n_tgt,
                        n_rhs, gX);
+}
+
+// Free-space near field of the magnetic field (Faraday's law): the curl of
+// the free dyadic's field is grad g x q (the grad grad / k^2 part has no
+// curl), with grad g = g (ik - 1/r) R / r, R = x_i - x_j; coincident points
+// are skipped as in the electric near field.  Added to Hc [rhs][point][3].
+template <bool RED>
+__global__ __launch_bounds__(NT) void k_p2p_curl(DevPlan d, const int* tboxes, const double* sxyz, const cd* J,
+                                                 long long n_src, const double* txyz, long long n_tgt, int n_rhs,
+                                                 cd* Hc) {
+  __shared__ double sp[NT][3];
+  __shared__ cd sj[NT][3];
+  int b = tboxes[2 * blockIdx.x];
+  TgtBox tb = d.tbox[b];
+  const double k = d.inst[__builtin_amdgcn_readfirstlane(tb.inst)].kt;
+  const int tid = threadIdx.x;
+  const double inv4pi = 0.079577471545947667884;
+  for (int r = 0; r < n_rhs; r++) {
+    int ti = tb.pt0 + tboxes[2 * blockIdx.x + 1] * NT + tid;
+    bool act = ti < tb.pt1;
+    int id = act ? d.tgt_perm[ti] : 0;
+    double x0 = act ? txyz[3 * id] : 0, y0 = act ? txyz[3 * id + 1] : 0, z0 = act ? txyz[3 * id + 2] : 0;
+    cd h0 = cd{0, 0}, h1 = cd{0, 0}, h2 = cd{0, 0};
+    for (int li = tb.p2p0; li < tb.p2p1; li++) {
+      SrcBox sb = d.sbox[d.p2p_list[li]];
+      for (int s0 = sb.pt0; s0 < sb.pt1; s0 += NT) {
+        int ns = min(NT, sb.pt1 - s0);
+        __syncthreads();
+        if (tid < ns) {
+          int sid = d.src_perm[s0 + tid];
+          sp[tid][0] = sxyz[3 * sid];
+          sp[tid][1] = sxyz[3 * sid + 1];
+          sp[tid][2] = sxyz[3 * sid + 2];
+          for (int c = 0; c < 3; c++) sj[tid][c] = J[((long long)r * n_src + sid) * 3 + c];
+        }
+        __syncthreads();
+        if (act) {
+          for (int j = 0; j < ns; j++) {
+            double rx = x0 - sp[j][0], ry = y0 - sp[j][1], rz = z0 - sp[j][2];
+            double r2 = rx * rx + ry * ry + rz * rz;
+            if (r2 == 0.0) continue;
+            double ir = lm_rsqrt(r2), rd = r2 * ir;
+            double sn, cs;
+            lm_sincos_nf<RED>(k * rd, &sn, &cs);
+            cd g = cd{cs * inv4pi * ir, sn * inv4pi * ir};
+            cd gr = (g * cd{-ir, k}) * ir;  // g' / r
+            cd gx = rx * gr, gy = ry * gr, gz = rz * gr;
+            cd qx = sj[j][0], qy = sj[j][1], qz = sj[j][2];
+            h0 = h0 + (gy * qz - gz * qy);
+            h1 = h1 + (gz * qx - gx * qz);
+            h2 = h2 + (gx * qy - gy * qx);
+          }
+        }
+      }
+    }
+    if (act) {
+      cd* o = Hc + ((long long)r * n_tgt + id) * 3;
+      o[0] = o[0] + h0;
+      o[1] = o[1] + h1;
+      o[2] = o[2] + h2;
+    }
+  }
+}
+void launch_p2p_curl(const DevPlan& d, const int* tboxes, int n, const double* sxyz, const cd* J, long long n_src,
+                     const double* txyz, long long n_tgt, int n_rhs, cd* Hc, bool red, hipStream_t s) {
+  if (n <= 0) return;
+  if (red)
+    hipLaunchKernelGGL(k_p2p_curl<true>, dim3(n), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src, txyz, n_tgt, n_rhs, Hc);
+  else
+    hipLaunchKernelGGL(k_p2p_curl<false>, dim3(n), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src, txyz, n_tgt, n_rhs,
+                       Hc);
 }
 
 // ------------------------------------------------------------------ S2T

@@ -67,6 +67,7 @@ def load_library():
     lib.lm_selftest_math.argtypes = [ctypes.c_int64, vp, vp, vp]
     lib.lm_build_batch.argtypes = [vp, ctypes.c_int, P(ctypes.c_int64), D, P(ctypes.c_int64), D, vp]
     lib.lm_evaluate_adjoint.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    lib.lm_evaluate_h.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     lib.lm_grad_src_xyz.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     lib.lm_stats.argtypes = [vp, D, ctypes.c_int]
     lib.lm_m2l_variants.argtypes = [vp, ctypes.c_int, P(ctypes.c_int), D, ctypes.c_int]
@@ -199,6 +200,21 @@ class LayeredDyadicFMM:
             stream = torch.cuda.current_stream(J.device).cuda_stream
         self._check(self.lib.lm_evaluate(self.ctx, n_rhs, ctypes.c_void_p(Jr.data_ptr()),
                                          ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)))
+        return out[0] if single else out
+
+    def evaluate_h(self, J, out=None, stream=None):
+        """Magnetic field H = G_H J, G_H = (1/mu) curl G (Faraday's law).
+        J: complex128 CUDA tensor [n_src, 3] or [n_rhs, n_src, 3]."""
+        import torch
+        if self.n_src is None:
+            raise LMError("build() must be called first")
+        single, n_rhs, Jr = self._rhs_view(J, self.n_src, "J")
+        if out is None:
+            out = torch.empty((n_rhs, self.n_tgt, 3), dtype=torch.complex128, device=J.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(J.device).cuda_stream
+        self._check(self.lib.lm_evaluate_h(self.ctx, n_rhs, ctypes.c_void_p(Jr.data_ptr()),
+                                           ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)))
         return out[0] if single else out
 
     def _rhs_view(self, X, n, name):
