@@ -190,6 +190,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-vector batched evaluation")
     ap.add_argument("--no-solve", action="store_true", help="skip the iterative coupled-dipole solve")
     ap.add_argument("--no-magnetic", action="store_true", help="skip the magnetic-field evaluation")
+    ap.add_argument("--no-selfconv", action="store_true", help="skip the p = 16 self-convergence check")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint and source-gradient timings (profiling runs of the forward step)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -281,6 +282,7 @@ def main():
                and abs(launches_per_step - K_M2L_TRAFFIC["launches_per_step"]) < 0.5 else None)
 
     acc = None
+    err_layers = None
     if not args.no_accuracy:
         fn = os.path.join(ROOT, "tests", "golden", "three_%d_sparse400_oracle.npz" % args.n)
         if os.path.exists(fn) and args.rhs == 1:
@@ -288,6 +290,32 @@ def main():
             Js, keep = inputs.sparse_currents(J, 400, seed=0)
             As = fmm.evaluate(torch.tensor(Js, device=dev)).cpu().numpy()
             acc = float(np.linalg.norm(As[g["idx"]] - g["A"]) / np.linalg.norm(g["A"]))
+            # per layer (the paper's Err_2 and Err_max over the sampled targets)
+            zt = x[g["idx"], 2]
+            lay = np.zeros(zt.size, dtype=int)
+            for dl in d:
+                lay += zt < dl
+            err_layers = {}
+            for l in range(len(d) + 1):
+                sel = lay == l
+                if not np.any(sel):
+                    continue
+                dA, A0 = As[g["idx"]][sel] - g["A"][sel], g["A"][sel]
+                err_layers[str(l)] = {
+                    "n_sampled": int(sel.sum()),
+                    "err2": float(np.linalg.norm(dA) / np.linalg.norm(A0)),
+                    "errmax": float(np.max(np.linalg.norm(dA, axis=1) / np.linalg.norm(A0, axis=1)))}
+    selfconv = None
+    if not args.no_accuracy and not args.no_selfconv and args.rhs == 1:
+        # p = 16 against p = 12 on every target (same currents, free part unchanged)
+        f16 = lmfmm.LayeredDyadicFMM(d, k, p=16, p_free=args.p_free, device=0).build(x)
+        A16 = f16.evaluate(Jt.reshape(args.rhs, args.n, 3))
+        A12 = fmm.evaluate(Jt.reshape(args.rhs, args.n, 3))
+        selfconv = float(torch.linalg.vector_norm(A12 - A16).item() / torch.linalg.vector_norm(A16).item())
+        f16.close()
+        del A16, A12
+        print("self-convergence: |A(p=12) - A(p=16)| / |A(p=16)| = %.2e over all %d targets" % (selfconv, args.n),
+              file=sys.stderr, flush=True)
     magnetic = None
     if not args.no_magnetic:
         # magnetic field of the same currents (curl of the electric field); the
@@ -336,6 +364,8 @@ def main():
                      "algorithmic_flops_per_launch": flops_per_launch},
         "cpu_baseline": cpu,
         "rel_err_vs_oracle": acc,
+        "rel_err_vs_oracle_per_layer": err_layers,
+        "self_convergence_p12_vs_p16": selfconv,
         "build_s": build_s,
         "cold_targets_per_s": args.n * args.rhs / (build_s + wall / args.steps),
         "phase_ms_per_step": {a: b / max(1, ncalls) for a, b in phases.items()},
