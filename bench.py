@@ -30,9 +30,10 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 fp64 FMA/clk x 2 flop x 2.4 GHz (fp
 # plain 1 GiB device copy (FETCH_SIZE reads 0.5 KiB per KiB read: factor 2.0;
 # WRITE_SIZE 1:1); see profiles/k_m2l_three_layer_1M_p12_pf20.md.  Valid only
 # for the kernel source it was measured on (digest of the M2L section of
-# kernels.hip) and the same launches per step (the plan's split of the M2L
-# work); otherwise reported as null.
-K_M2L_TRAFFIC = {"digest": "d399e554001bfd19", "launches_per_step": 8,
+# kernels.hip), the same launches per step (the plan's split of the M2L
+# work) and the same M2L work (useful complex multiply-adds of the plan);
+# otherwise reported as null.
+K_M2L_TRAFFIC = {"digest": "d399e554001bfd19", "launches_per_step": 8, "m2l_cmac_useful": 1167408236574.0,
                  "fetch_bytes": 1.7712e7 * 1024 * 2.0, "write_bytes": 5.4600e6 * 1024 * 1.0}
 
 
@@ -279,7 +280,8 @@ def main():
     default_cfg = (args.n, args.p, args.p_free, args.rhs) == (1000000, 12, 20, 1)
     traffic = (K_M2L_TRAFFIC["fetch_bytes"] + K_M2L_TRAFFIC["write_bytes"]
                if default_cfg and m2l_source_digest() == K_M2L_TRAFFIC["digest"]
-               and abs(launches_per_step - K_M2L_TRAFFIC["launches_per_step"]) < 0.5 else None)
+               and abs(launches_per_step - K_M2L_TRAFFIC["launches_per_step"]) < 0.5
+               and st["m2l_cmac_useful"] == K_M2L_TRAFFIC["m2l_cmac_useful"] else None)
 
     acc = None
     err_layers = None
