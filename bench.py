@@ -33,8 +33,8 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 fp64 FMA/clk x 2 flop x 2.4 GHz (fp
 # kernels.hip), the same launches per step (the plan's split of the M2L
 # work) and the same M2L work (useful complex multiply-adds of the plan);
 # otherwise reported as null.
-K_M2L_TRAFFIC = {"digest": "d399e554001bfd19", "launches_per_step": 8, "m2l_cmac_useful": 1167408236574.0,
-                 "fetch_bytes": 1.7712e7 * 1024 * 2.0, "write_bytes": 5.4600e6 * 1024 * 1.0}
+K_M2L_TRAFFIC = {"digest": "d399e554001bfd19", "launches_per_step": 8, "m2l_cmac_useful": 933520056030.0,
+                 "fetch_bytes": 1.4473e7 * 1024 * 2.0, "write_bytes": 4.7584e6 * 1024 * 1.0}
 
 
 def m2l_source_digest():
