@@ -33,8 +33,8 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 fp64 FMA/clk x 2 flop x 2.4 GHz (fp
 # kernels.hip), the same launches per step (the plan's split of the M2L
 # work) and the same M2L work (useful complex multiply-adds of the plan);
 # otherwise reported as null.
-K_M2L_TRAFFIC = {"digest": "d399e554001bfd19", "launches_per_step": 8, "m2l_cmac_useful": 933520056030.0,
-                 "fetch_bytes": 1.4473e7 * 1024 * 2.0, "write_bytes": 4.7584e6 * 1024 * 1.0}
+K_M2L_TRAFFIC = {"digest": "d399e554001bfd19", "launches_per_step": 8, "m2l_cmac_useful": 1167408236574.0,
+                 "fetch_bytes": 1.7731e7 * 1024 * 2.0, "write_bytes": 5.4601e6 * 1024 * 1.0}
 
 
 def m2l_source_digest():
@@ -309,17 +309,19 @@ def main():
                     "errmax": float(np.max(np.linalg.norm(dA, axis=1) / np.linalg.norm(A0, axis=1)))}
     selfconv = None
     if not args.no_accuracy and not args.no_selfconv and args.rhs == 1:
-        # p = 16 against p = 12 on every target, free part unchanged, for the
-        # 400-source sparse currents of the oracle check (far field dominates;
-        # with every source active the near field dominates every norm)
+        # the reaction expansions at p = 16 against p = 12 (free part unchanged)
+        # for the 400-source sparse currents of the oracle check, at its
+        # sampled targets (over all targets the near field of the 400
+        # sources, identical in both, dominates the norm)
         Jsp = torch.tensor(inputs.sparse_currents(J, 400, seed=0)[0], device=dev)
+        idx_s = torch.tensor(inputs.sample_targets(args.n, count=128, seed=0), device=dev)
         f16 = lmfmm.LayeredDyadicFMM(d, k, p=16, p_free=args.p_free, device=0).build(x)
-        A16 = f16.evaluate(Jsp)
-        A12 = fmm.evaluate(Jsp)
+        A16 = f16.evaluate(Jsp)[idx_s]
+        A12 = fmm.evaluate(Jsp)[idx_s]
         selfconv = float(torch.linalg.vector_norm(A12 - A16).item() / torch.linalg.vector_norm(A16).item())
         f16.close()
         del A16, A12, Jsp
-        print("self-convergence: |A(p=12) - A(p=16)| / |A(p=16)| = %.2e over all %d targets" % (selfconv, args.n),
+        print("self-convergence: |A(p=12) - A(p=16)| / |A(p=16)| = %.2e at 128 sampled targets" % selfconv,
               file=sys.stderr, flush=True)
     magnetic = None
     if not args.no_magnetic:

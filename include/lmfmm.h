@@ -73,7 +73,7 @@ typedef struct {
                       /* bound (separation ratio^(p+1)) does not exceed that of the */
                       /* instance's worst admissible pair, lowered by m2l_margin   */
                       /* decades; 0: order p everywhere                            */
-  double m2l_margin;  /* see m2l_adapt (default 2.5)                                */
+  double m2l_margin;  /* see m2l_adapt (default 3)                                  */
   int react_s2t;      /* 0: reaction trees are refined next to the gap between      */
                       /* images and effective locations until no source and        */
                       /* target leaves are adjacent (every reaction interaction   */
@@ -94,7 +94,7 @@ typedef struct {
 #define LM_M2L_VARIANTS 3
 
 /* Fills *prm with the defaults (p = 12, p_free = p, automatic depths, m2l_adapt = 1,
- * m2l_margin = 2.5, react_s2t = 1, m2l_variant = -1). */
+ * m2l_margin = 3, react_s2t = 1, m2l_variant = -1). */
 int lm_default_params(lm_params* prm);
 
 /* Creates a context bound to HIP device `hip_device`.  *out is owned by the

@@ -211,7 +211,7 @@ int lm_default_params(lm_params* prm) {
   prm->tail_digits = 60.0;
   prm->components = 3;
   prm->m2l_adapt = 1;
-  prm->m2l_margin = 2.5;
+  prm->m2l_margin = 3.0;
   prm->react_s2t = 1;
   prm->m2l_variant = -1;
   return LM_OK;
