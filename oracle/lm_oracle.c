@@ -1,6 +1,7 @@
 /*
  * lm_oracle.c -- reference (oracle) evaluation of the layered-media electric
- * dyadic Green's function sum  A(x_i) = sum_j G(x_i, x_j) J_j.
+ * dyadic Green's function sum  A(x_i) = sum_j G(x_i, x_j) J_j, and of the
+ * magnetic one H(x_i) = sum_j G_H(x_i, x_j) J_j (the J6..J9 form).
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain, fp64 CPU definition
  * that the GPU fast multipole path is checked against.  Only the test suite,

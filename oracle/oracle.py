@@ -1,9 +1,12 @@
 """Python access to the CPU oracle (test infrastructure only).
 
 The oracle is the plain fp64 definition of the layered-media electric dyadic
-Green's function sum that the GPU fast multipole path is checked against.  It
-is loaded only by the tests, by the package smoke check and by the CPU-baseline
-leg of the benchmark; the product path never imports it.
+Green's function sum that the GPU fast multipole path is checked against, of
+the magnetic dyadic sum (the J6..J9 form of Sec. 3.1), and of the solution of
+the coupled-dipole system (diag - G) X = B (dense LU of the assembled sum).
+Layers may have relative permeabilities mu (default 1).  It is loaded only by
+the tests, by the package smoke check and by the CPU-baseline leg of the
+benchmark; the product path never imports it.
 """
 import ctypes
 import os
