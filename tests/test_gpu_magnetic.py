@@ -83,3 +83,22 @@ def test_magnetic_100k_sampled():
     print("  rel err %.2e, first call %.2f s (refined plan), then %.1f ms" % (e, t1 - t0, 1e3 * (t2 - t1)),
           flush=True)
     assert e < TOL["100k"]
+
+
+def test_magnetic_batch_equals_separate_builds():
+    """Several geometries in one plan (with direct reaction pairs, so the
+    magnetic field builds the refined batch plan): each geometry's H equals
+    that of its own build."""
+    d, k, xs, Js = inputs.uneven_geometries(4, seed=1, n_min=500, n_max=6000)
+    print("case magnetic, 4 geometries, sizes %s" % [x.shape[0] for x in xs], flush=True)
+    f = lmfmm.LayeredDyadicFMM(d, k, p=8).build_batch(xs)
+    H = f.evaluate_h(cuda(np.concatenate(Js))).cpu().numpy()
+    f.close()
+    so = np.cumsum([0] + [x.shape[0] for x in xs])
+    for g in range(len(xs)):
+        fg = lmfmm.LayeredDyadicFMM(d, k, p=8).build(xs[g])
+        Hg = fg.evaluate_h(cuda(Js[g])).cpu().numpy()
+        fg.close()
+        e = rel(H[so[g]:so[g + 1]], Hg)
+        print("  geometry %d: rel diff %.3e" % (g, e), flush=True)
+        assert e < 1e-12
