@@ -270,7 +270,8 @@ int lm_stats(const lm_ctx* ctx, double* out_host, int n);
  * The build must have the same point array as sources and targets (LM_ESTATE
  * otherwise).  diag: DEVICE complex128 [n] or NULL (D = 0); B: DEVICE
  * complex128 [n_rhs][n][3]; X: DEVICE complex128 [n_rhs][n][3], the initial
- * guess on entry (zero it for the usual start), the last iterate on return.
+ * guess on entry (zero it for the usual start), the last iterate on return;
+ * X must not overlap B or diag (B and diag are only read).
  * Stopping test per column: ||B - (D - G) X|| <= tol ||B|| (2-norm), checked
  * on the true residual at the end of each restart cycle; a column with B = 0
  * returns X = 0.  restart: Krylov dimension per cycle, 1..LM_SOLVE_MAX_RESTART;

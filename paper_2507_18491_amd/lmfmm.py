@@ -276,6 +276,8 @@ class LayeredDyadicFMM:
             if not (X.is_cuda and X.dtype == torch.complex128 and X.is_contiguous()
                     and X.numel() == Bv.numel()):
                 raise LMError("X must be a contiguous complex128 CUDA tensor shaped like B")
+            if X.data_ptr() == Bv.data_ptr():
+                raise LMError("X must not share memory with B")
         if diag is not None:
             if not (diag.is_cuda and diag.dtype == torch.complex128 and diag.numel() == self.n_src):
                 raise LMError("diag must be a complex128 CUDA tensor [n]")
