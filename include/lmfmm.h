@@ -64,7 +64,9 @@ typedef struct {
   int free_depth;     /* free-space octree leaf level, 0 => chosen by a cost model   */
   int max_depth;      /* cap of the reaction-tree refinement next to interfaces      */
   int gamma1_panels;  /* Gauss-Legendre panels (16 nodes each) on the contour piece  */
-                      /* from 0 to a in the fourth quadrant (Sec. 3.4); default 3    */
+                      /* from 0 to a in the fourth quadrant (Sec. 3.4); default 4;   */
+                      /* the direct near field uses at most 3 within the series     */
+                      /* range of its Bessel functions                              */
   double contour_a;   /* end point a of that piece on the real axis, 0 => 1.5 max k  */
   double tail_digits; /* the real tail [a, kcut] of the Sommerfeld integrals ends at */
                       /* kcut = a + (3p + tail_digits) / dz_min                       */
@@ -94,7 +96,7 @@ typedef struct {
 #define LM_M2L_VARIANTS 3
 
 /* Fills *prm with the defaults (p = 12, p_free = p, automatic depths, m2l_adapt = 1,
- * m2l_margin = 3, gamma1_panels = 3, react_s2t = 1, m2l_variant = -1). */
+ * m2l_margin = 3, gamma1_panels = 4, react_s2t = 1, m2l_variant = -1). */
 int lm_default_params(lm_params* prm);
 
 /* Creates a context bound to HIP device `hip_device`.  *out is owned by the

@@ -206,7 +206,7 @@ int lm_default_params(lm_params* prm) {
   prm->p_free = 0;
   prm->free_depth = 0;
   prm->max_depth = 14;
-  prm->gamma1_panels = 3;
+  prm->gamma1_panels = 4;
   prm->contour_a = 0.0;
   prm->tail_digits = 60.0;
   prm->components = 3;
@@ -289,7 +289,7 @@ int lm_set_params(lm_ctx* ctx, const lm_params* p) {
   q.p_free = p->p_free;
   q.free_depth = p->free_depth;
   q.max_depth = p->max_depth;
-  q.gamma1_panels = p->gamma1_panels > 0 ? p->gamma1_panels : 3;
+  q.gamma1_panels = p->gamma1_panels > 0 ? p->gamma1_panels : 4;
   q.contour_a = p->contour_a;
   q.tail_digits = p->tail_digits > 0 ? p->tail_digits : 60.0;
   q.components = p->components;

@@ -27,7 +27,7 @@ struct PlanParams {
   int p_free = 0;        // 0: same as p
   int free_depth = 0;    // 0: chosen by a cost model
   int max_depth = 14;    // cap of the reaction refinement
-  int gamma1_panels = 3; // Gauss-Legendre panels on the Gamma_1 contour
+  int gamma1_panels = 4; // Gauss-Legendre panels on the Gamma_1 contour
   double contour_a = 0;  // 0: 1.5 * max k
   double tail_digits = 60;
   int components = 3;    // bit 0: free space, bit 1: reaction

@@ -44,6 +44,7 @@ def run(d, k, x, J, **kw):
 # recorded truncation errors (relative L2 over all 600 targets) x 3
 TINY_TOL = {4: 1e-4, 8: 3e-6, 12: 4e-7}
 TINY_TOL_REACT = {4: 3e-2, 8: 5e-4, 12: 1.2e-5, 16: 5e-7}
+COARSE_TOL = {8: 2.2e-4, 12: 1.4e-5}  # recorded 7.1e-5 and 4.4e-6, margin 3
 
 
 @pytest.mark.parametrize("p", [4, 8, 12])
@@ -329,3 +330,20 @@ def test_direct_near_field_many_rhs(tiny):
     for r in range(6):
         assert np.array_equal(Am[r], f.evaluate(cuda(Jm[r])).cpu().numpy()), r
     f.close()
+
+
+@pytest.mark.parametrize("p", [8, 12])
+def test_coarse_trees_subset(tiny, p):
+    """Every fifth point of the tiny workload (120 points): shallow trees, so
+    the M2L tables of the coarse levels (large horizontal offsets on the
+    contour piece Gamma_1) carry the reaction field."""
+    from oracle import oracle
+    d, k, x, J, g = tiny
+    sel = np.arange(0, 600, 5)
+    xs, Js = x[sel], J[sel]
+    print("case tiny subset n=120 p=%d" % p, flush=True)
+    A = run(d, k, xs, Js, p=p)
+    ref = oracle.direct(d, k, xs, Js, xs)
+    e = rel(A, ref)
+    print("  rel err %.2e" % e, flush=True)
+    assert e < COARSE_TOL[p]
