@@ -157,15 +157,13 @@ int lm_evaluate(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream);
  * Sec. 3.1 (the J6..J9 form), normalised as G_H(x, y) = (1/mu(x)) curl_x
  * G(x, y) (Faraday's law; in free space curl (g I) q = grad g x q, the
  * paper's free-space G_H without its constant i/(omega mu_0) factor).
- * Evaluated as the curl of the electric field: the far field by exact
- * derivatives of the local expansions (ladder relations of the regular wave
- * functions), the free-space near field in closed form.  A build whose plan
- * evaluates reaction pairs directly (the near field of components next to
- * an interface) gets a second plan with those trees refined until none
- * remain, built on the first call (which then synchronises `stream` once and
- * allocates).  J: DEVICE complex128 [n_rhs][n_src][3]; H: DEVICE complex128
- * [n_rhs][n_tgt][3], overwritten.  Asynchronous otherwise; errors as
- * lm_evaluate. */
+ * Evaluated as the curl of the electric field on the same plan: the far
+ * field by exact derivatives of the local expansions (ladder relations of
+ * the regular wave functions), the free-space near field in closed form,
+ * and the directly evaluated reaction pairs by the Sommerfeld integrals of
+ * the J6..J9 form.  J: DEVICE complex128 [n_rhs][n_src][3]; H: DEVICE
+ * complex128 [n_rhs][n_tgt][3], overwritten.  Asynchronous, errors and
+ * determinism as lm_evaluate. */
 int lm_evaluate_h(lm_ctx* ctx, int n_rhs, const void* J, void* H, void* stream);
 
 /* Adjoint evaluation (the conjugate transpose of lm_evaluate's operator):

@@ -71,7 +71,6 @@ struct lm_ctx {
   std::vector<int64_t> host_soff, host_toff;
   lm_ctx* adj = nullptr;                   // swapped-role context (built on first use)
   lm_ctx* gctx = nullptr;                  // swapped-role context without S2T, for gradients
-  lm_ctx* hctx = nullptr;                  // same roles, without S2T, for the magnetic field
   MediumDev md;                            // medium as seen by the kernels
   int* d_s2t = nullptr;                    // S2T work items (target leaf, chunk)
   struct S2TRange {
@@ -152,8 +151,6 @@ static void free_build(lm_ctx* ctx) {
   ctx->adj = nullptr;
   if (ctx->gctx) lm_destroy(ctx->gctx);
   ctx->gctx = nullptr;
-  if (ctx->hctx) lm_destroy(ctx->hctx);
-  ctx->hctx = nullptr;
   ctx->d_s2t = nullptr;
   ctx->s2t_ranges.clear();
   if (ctx->Jc) hipFree(ctx->Jc);
@@ -759,8 +756,8 @@ int lm_evaluate(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream) {
 }
 
 // One group of right-hand sides.  Normal mode (gX == nullptr, Hc == nullptr): A = G J.
-// Curl mode (Hc != nullptr, a context without direct reaction pairs): the
-// leaf passes add curl (G J) at every target into Hc; A is not touched.
+// Curl mode (Hc != nullptr): the leaf passes and the direct reaction pairs
+// add curl (G J) at every target into Hc; A is not touched.
 // Gradient mode: the upward pass and M2L run on J as usual, then instead of
 // writing A the leaf passes add, at every target point, Re sum_b W^b grad B_b
 // (B the field of J) into gX [n_tgt][3]; A is not touched.
@@ -879,39 +876,6 @@ static int ensure_jc(lm_ctx* ctx, long long n, hipStream_t s) {
   return LM_OK;
 }
 
-// The context that evaluates the magnetic field: the same roles, with
-// reaction trees refined until no direct (S2T) pairs remain, so that the
-// whole reaction field is held by local expansions that can be
-// differentiated.  This context itself when it has no direct pairs.
-static int curl_ctx(lm_ctx* ctx, hipStream_t s, lm_ctx** out) {
-  *out = nullptr;
-  if (ctx->s2t_ranges.empty()) {
-    *out = ctx;
-    return LM_OK;
-  }
-  if (!ctx->hctx) {
-    lm_ctx* a = nullptr;
-    int rc = lm_create(&a, ctx->device);
-    if (rc) return fail(ctx, rc, "cannot create the magnetic-field context");
-    a->med = ctx->med;
-    a->layers_set = true;
-    a->prm = ctx->prm;
-    a->m2l_variant = ctx->m2l_variant;
-    a->prm.react_s2t = 0;
-    int ng = (int)ctx->host_soff.size() - 1;
-    rc = build_common(a, ng, ctx->host_soff.data(), ctx->host_src.data(), ctx->host_toff.data(),
-                      ctx->host_tgt.data(), s);
-    if (rc) {
-      std::string m = a->err;
-      lm_destroy(a);
-      return fail(ctx, rc, "magnetic-field context build: " + m);
-    }
-    ctx->hctx = a;
-  }
-  *out = ctx->hctx;
-  return LM_OK;
-}
-
 int lm_evaluate_h(lm_ctx* ctx, int n_rhs, const void* J, void* H, void* stream) {
   if (!ctx) return LM_EINVAL;
   if (!ctx->built) return fail(ctx, LM_ESTATE, "lm_build must succeed before lm_evaluate_h");
@@ -921,15 +885,12 @@ int lm_evaluate_h(lm_ctx* ctx, int n_rhs, const void* J, void* H, void* stream) 
   if (((uintptr_t)J % 16) || ((uintptr_t)H % 16)) return fail(ctx, LM_EINVAL, "J and H must be 16-byte aligned");
   HIPC(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
-  lm_ctx* T = nullptr;
-  int rc = curl_ctx(ctx, s, &T);
-  if (rc) return rc;
   for (int r0 = 0; r0 < n_rhs; r0 += LM_RHS_CHUNK) {
     int nr = std::min(LM_RHS_CHUNK, n_rhs - r0);
     const cd* Jc = (const cd*)J + (long long)r0 * pl.n_src * 3;
     cd* Hc = (cd*)H + (long long)r0 * pl.n_tgt * 3;
-    rc = evaluate_chunk(T, nr, Jc, nullptr, stream, nullptr, nullptr, Hc);
-    if (rc) return T == ctx ? rc : fail(ctx, rc, "magnetic-field evaluation: " + T->err);
+    int rc = evaluate_chunk(ctx, nr, Jc, nullptr, stream, nullptr, nullptr, Hc);
+    if (rc) return rc;
   }
   // Faraday's law: H = curl E / mu of the target's layer
   if (!ctx->med.mu_one) launch_scale_mu((cd*)H, pl.n_tgt, n_rhs, ctx->d_tgt, ctx->md, -1, s);
@@ -1014,7 +975,6 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
   Plan& pl = ctx->plan;
   const bool grad = gX != nullptr, curl = Hc != nullptr;
   if ((pl.n_src > 0 && !J) || (pl.n_tgt > 0 && !grad && !curl && !A)) return fail(ctx, LM_EINVAL, "null J or A");
-  if (curl && !ctx->s2t_ranges.empty()) return fail(ctx, LM_ESTATE, "curl mode needs a plan without direct reaction pairs");
   if (((uintptr_t)J % 16) || ((uintptr_t)A % 16)) return fail(ctx, LM_EINVAL, "J and A must be 16-byte aligned");
   HIPC(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
@@ -1092,10 +1052,10 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
         launch_p2p(d, ctx->d_p2p[f], ctx->n_p2p[f], ctx->d_src, Jc, pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs, Ac,
                    ctx->p2p_red, s);
     }
-    if (!grad && !curl)
+    if (!grad)
       for (auto& r : ctx->s2t_ranges)
         launch_s2t(d, ctx->md, ctx->d_s2t + 2 * r.item0, r.n, ctx->d_src, Jc, pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs,
-                   ctx->contour_a, r.smallz, Ac, s);
+                   ctx->contour_a, r.smallz, curl ? Hc : Ac, s, curl);
     mark(7);
   } else {
     for (int i = 2; i <= 7; i++) mark(i);

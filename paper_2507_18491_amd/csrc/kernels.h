@@ -87,7 +87,7 @@ void launch_p2p_curl(const DevPlan& d, const int* tboxes, int n, const double* s
 void launch_scale_mu_d(double* g, long long n, const double* xyz, MediumDev md, int pw, hipStream_t s);
 void launch_s2t(const DevPlan& d, MediumDev md, const int* items, int n, const double* sxyz, const cd* J,
                 long long n_src, const double* txyz, long long n_tgt, int n_rhs, double a, bool smallz, cd* A,
-                hipStream_t s);
+                hipStream_t s, bool hfield = false);
 void launch_fill_d(double* p, long long n, hipStream_t s);
 void launch_selftest_math(const double* x, long long n, double* out, hipStream_t s);
 void launch_l2p_grad(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_pts,

@@ -1508,7 +1508,10 @@ void launch_p2p_curl(const DevPlan& d, const int* tboxes, int n, const double* s
 // a time and read in a wave-uniform loop.  A target adds its pairs in q order
 // (no atomics).  The integrals depend on the pair only: a block applies them
 // to RS right-hand sides (blockIdx.y: the group of RS).
-template <bool SMALLZ, int RS>
+// HF: the curl of the field instead (mu_t times the magnetic field, the
+// J6..J9 form, with the node densities FH in the same five slots):
+//   out+ as above, out- negated, out_z = W(-1,s4) u+/2 - W(1,s4) u-/2.
+template <bool SMALLZ, int RS, bool HF>
 __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md, const int* items,
                                                                      const double* sxyz, const cd* J,
                                                                      long long n_src, const double* txyz,
@@ -1583,7 +1586,7 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
           nk[tid][1] = nd.w * nd.kr;
           nk[tid][2] = nd.kzt;
           nk[tid][3] = nd.kzs;
-          for (int f = 0; f < 5; f++) nk[tid][4 + f] = nd.F[f];
+          for (int f = 0; f < 5; f++) nk[tid][4 + f] = HF ? nd.FH[f] : nd.F[f];
           nk[tid][9] = cd{nd.kr.y == 0.0 ? 1.0 / nd.kr.x : 0.0, 0.0};
         }
         __syncthreads();
@@ -1658,8 +1661,13 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
             const cd b1 = cm(W01, um), b2 = cm(W2m, up), b3 = cm(W1m2, jz);
             const cd c1 = cm(W1p4, um), c2 = cm(W1m4, up), c3 = cm(W05, jz);
             rp = cd{(0.5 * a1.x - 0.5 * a2.x) + a3.x, (0.5 * a1.y - 0.5 * a2.y) + a3.y};
-            rm = cd{(0.5 * b1.x - 0.5 * b2.x) + b3.x, (0.5 * b1.y - 0.5 * b2.y) + b3.y};
-            rz = cd{(0.5 * c1.x + 0.5 * c2.x) + c3.x, (0.5 * c1.y + 0.5 * c2.y) + c3.y};
+            if (HF) {
+              rm = cd{(0.5 * b2.x - 0.5 * b1.x) - b3.x, (0.5 * b2.y - 0.5 * b1.y) - b3.y};
+              rz = cd{0.5 * c2.x - 0.5 * c1.x, 0.5 * c2.y - 0.5 * c1.y};
+            } else {
+              rm = cd{(0.5 * b1.x - 0.5 * b2.x) + b3.x, (0.5 * b1.y - 0.5 * b2.y) + b3.y};
+              rz = cd{(0.5 * c1.x + 0.5 * c2.x) + c3.x, (0.5 * c1.y + 0.5 * c2.y) + c3.y};
+            }
           }
           res[tid][rr][0] = rp;
           res[tid][rr][1] = rm;
@@ -1703,21 +1711,33 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
 // series length comes from each block's instance)
 void launch_s2t(const DevPlan& d, MediumDev md, const int* items, int n, const double* sxyz, const cd* J,
                 long long n_src, const double* txyz, long long n_tgt, int n_rhs, double a, bool smallz, cd* A,
-                hipStream_t s) {
+                hipStream_t s, bool hfield) {
   if (n <= 0) return;
-#define LM_S2T_GO(SZ, RS)                                                                                   \
-  hipLaunchKernelGGL((k_s2t<SZ, RS>), dim3(n, (n_rhs + RS - 1) / RS), dim3(LM_S2T_CHUNK), 0, s, d, md, items, \
+#define LM_S2T_GO(SZ, RS, H)                                                                                   \
+  hipLaunchKernelGGL((k_s2t<SZ, RS, H>), dim3(n, (n_rhs + RS - 1) / RS), dim3(LM_S2T_CHUNK), 0, s, d, md, items, \
                      sxyz, J, n_src, txyz, n_tgt, n_rhs, a, A)
-  if (n_rhs == 1) {
+  if (hfield) {
+    if (n_rhs == 1) {
+      if (smallz)
+        LM_S2T_GO(true, 1, true);
+      else
+        LM_S2T_GO(false, 1, true);
+    } else {
+      if (smallz)
+        LM_S2T_GO(true, 4, true);
+      else
+        LM_S2T_GO(false, 4, true);
+    }
+  } else if (n_rhs == 1) {
     if (smallz)
-      LM_S2T_GO(true, 1);
+      LM_S2T_GO(true, 1, false);
     else
-      LM_S2T_GO(false, 1);
+      LM_S2T_GO(false, 1, false);
   } else {
     if (smallz)
-      LM_S2T_GO(true, 4);
+      LM_S2T_GO(true, 4, false);
     else
-      LM_S2T_GO(false, 4);
+      LM_S2T_GO(false, 4, false);
   }
 #undef LM_S2T_GO
 }
@@ -1902,6 +1922,19 @@ __global__ void k_nodes(DevPlan d, MediumDev md, int n_nodes, const int* node_in
   S[4] = kr * kr * ctm;
   cd pre = cd{0.0, -2.0 / k2};
   for (int j = 0; j < 5; j++) q.F[j] = pre * S[j];
+  // curl of the field (mu_t G_H, the J6..J9 form of Sec. 3.1) in the same
+  // slots: d/dz brings i e kz_t, d/dz' i h kz_s; the xy block's kappa = 0
+  // and kappa = 2 parts (J9 and half of J8) go to slots 1 and 3, the z
+  // column (J7) to slot 2, the z row (J6) to slot 4, nothing to slot 5; the
+  // near-field kernel combines them with the signs of the curl
+  cd etc = (e * cte) * q.kzt, hsc = (h * ctm) * q.kzs;
+  cd SH[5];
+  SH[0] = hsc - etc;
+  SH[1] = kr * ctm;
+  SH[2] = -(etc + hsc);
+  SH[3] = kr * cte;
+  SH[4] = cd{0.0, 0.0};
+  for (int j = 0; j < 5; j++) q.FH[j] = cd{0.0, -2.0} * SH[j];
   q.tau_t[0] = cd{1, 0};
   q.tau_t[1] = cd{ip.kt, 0} / q.kzt;
   q.tau_t[2] = (1.0 / ip.kt) * kr;

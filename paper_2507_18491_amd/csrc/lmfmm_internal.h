@@ -105,6 +105,7 @@ struct QNode {
   cd kr, w;           // node and weight (includes d kr / dt)
   cd kzt, kzs;        // vertical wavenumbers of target and source layer
   cd F[5];            // densities F_sigma = -(2i/k^2) S_sigma (no centre exponential)
+  cd FH[5];           // the same slots for the curl of the field (magnetic field times mu_t)
   cd tau_t[4];        // 1, sec b, sin b, tan b for the target side
   cd tau_s[4];        // same for the source side
   cd x0;              // cos 2 b0 (base side = smaller wavenumber)

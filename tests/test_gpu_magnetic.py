@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 MU3 = [1.0, 1.8, 0.7]
 # recorded relative L2 errors against the oracle (p = 12 unless noted, free part
 # p = 20), margin 3
-TOL = {"tiny12": 9.1e-7, "tiny16": 1.3e-7, "mu_same": 9e-6, "mu_distinct": 1.9e-6, "100k": 1.1e-5}
+TOL = {"tiny12": 9.1e-7, "tiny16": 1.3e-7, "mu_same": 9e-6, "mu_distinct": 1.9e-6, "100k": 1.1e-5,
+       "tiny_direct": 4.7e-7, "mu_direct": 8e-7}
 
 
 def rel(a, b):
@@ -59,9 +60,41 @@ def test_magnetic_with_mu():
         assert e < TOL[name]
 
 
+def test_magnetic_tiny_direct_near_field():
+    """Every adjacent reaction pair evaluated directly (the J6..J9 Sommerfeld
+    integrals of the near-field kernel), two layers, p = 12."""
+    from oracle import oracle
+    d, k, x, J = inputs.tiny(seed=0)
+    sel = np.arange(0, 600, 3)
+    x, J = x[sel], J[sel]
+    print("case magnetic tiny n=%d p=12 p_free=20, direct reaction near field" % x.shape[0], flush=True)
+    f = lmfmm.LayeredDyadicFMM(d, k, p=12, p_free=20, react_s2t=2).build(x)
+    assert f.stats()["s2t_pairs"] > 0
+    H = f.evaluate_h(cuda(J)).cpu().numpy()
+    f.close()
+    ref = oracle.direct_h(d, k, x, J, x)
+    e = rel(H, ref)
+    print("  rel err %.2e" % e, flush=True)
+    assert e < TOL["tiny_direct"]
+
+
+def test_magnetic_mu_direct_near_field():
+    from oracle import oracle
+    d, k, src, J = inputs.three_layer(160, seed=7, half_width=1.0)
+    print("case magnetic three-layer with mu, direct reaction near field", flush=True)
+    f = lmfmm.LayeredDyadicFMM(d, k, mu=MU3, p=12, p_free=20, react_s2t=2).build(src)
+    assert f.stats()["s2t_pairs"] > 0
+    H = f.evaluate_h(cuda(J)).cpu().numpy()
+    f.close()
+    ref = oracle.direct_h(d, k, src, J, src, mu=MU3)
+    e = rel(H, ref)
+    print("  rel err %.2e" % e, flush=True)
+    assert e < TOL["mu_direct"]
+
+
 def test_magnetic_100k_sampled():
-    """The scale configuration (its plan evaluates reaction pairs next to the
-    interfaces directly, so the magnetic field builds its refined plan)."""
+    """The scale configuration (its plan evaluates the reaction pairs next to
+    the interfaces directly)."""
     from oracle import oracle
     d, k, x, J = inputs.three_layer(100000, seed=0)
     Js, keep = inputs.sparse_currents(J, 400, seed=0)
@@ -80,15 +113,13 @@ def test_magnetic_100k_sampled():
     f.close()
     ref = oracle.direct_h(d, k, x[keep], Js[keep], x[idx])
     e = rel(H[idx], ref)
-    print("  rel err %.2e, first call %.2f s (refined plan), then %.1f ms" % (e, t1 - t0, 1e3 * (t2 - t1)),
-          flush=True)
+    print("  rel err %.2e, first call %.2f s, then %.1f ms" % (e, t1 - t0, 1e3 * (t2 - t1)), flush=True)
     assert e < TOL["100k"]
 
 
 def test_magnetic_batch_equals_separate_builds():
-    """Several geometries in one plan (with direct reaction pairs, so the
-    magnetic field builds the refined batch plan): each geometry's H equals
-    that of its own build."""
+    """Several geometries in one plan (with direct reaction pairs): each
+    geometry's H equals that of its own build."""
     d, k, xs, Js = inputs.uneven_geometries(4, seed=1, n_min=500, n_max=6000)
     print("case magnetic, 4 geometries, sizes %s" % [x.shape[0] for x in xs], flush=True)
     f = lmfmm.LayeredDyadicFMM(d, k, p=8).build_batch(xs)
