@@ -1,5 +1,6 @@
-"""GPU tests of media with more layers (six layers, 100 reaction components):
-the HIP path through the C ABI against the oracle evaluated live."""
+"""GPU tests of media with more layers (six layers, 100 reaction components)
+and of higher frequencies: the HIP path through the C ABI against the
+oracle evaluated live."""
 import time
 
 import numpy as np
@@ -58,3 +59,24 @@ def test_six_layers_50k_sampled():
     print("  rel err %.2e, build %.2f s, evaluation %.1f ms, %d components, %d table cases" % (
         e, tb, 1e3 * te, st["n_react_inst"], st["n_cases"]), flush=True)
     assert e < TOL_50K
+
+
+@pytest.mark.parametrize("scale,half_width,p,tol", [(3.0, 2.0, 12, 1.5e-6), (4.0, 1.5, 16, 1.9e-7)])
+def test_higher_frequency_sampled(scale, half_width, p, tol):
+    """The three-layer medium at 3x and 4x the wavenumbers (k_max 6 over a
+    4-wide domain, k_max 8 over a 3-wide one: up to about four wavelengths
+    across), 2e4 points, 200-source sparse currents, 48 sampled targets.
+    Tolerances: recorded 4.8e-7 and 6.4e-8, margin 3."""
+    from oracle import oracle
+    d, k, x, J = inputs.three_layer(20000, seed=5, half_width=half_width)
+    k = k * scale
+    Js, keep = inputs.sparse_currents(J, 200, seed=5)
+    idx = inputs.sample_targets(x.shape[0], count=48, seed=5)
+    print("case higher frequency k x%.0f, n=20000, p=%d, p_free=20" % (scale, p), flush=True)
+    f = lmfmm.LayeredDyadicFMM(d, k, p=p, p_free=20).build(x)
+    A = f.evaluate(torch.tensor(Js, device="cuda")).cpu().numpy()
+    f.close()
+    ref = oracle.direct(d, k, x[keep], Js[keep], x[idx])
+    e = rel(A[idx], ref)
+    print("  rel err %.2e" % e, flush=True)
+    assert e < tol
