@@ -15,7 +15,7 @@
 #define LM_P2M_CHUNK 512   // source points per P2M work item (larger leaves: partials, summed)
 #define LM_L2P_CHUNK(kind) ((kind) == 0 ? 256 : 64)   // points per L2P work item (free / reaction)
 #define LM_S2T_CHUNK 64    // targets per reaction near-field work item (= threads per block)
-#define LM_S2T_DIGITS 36.0 // the S2T tail stops where e^{-k (t + u)} < e^{-36}
+#define LM_S2T_DIGITS 28.0 // the S2T tail stops where e^{-k (t + u)} < e^{-28}
 #define LM_S2T_SEG 32      // near boxes per source segment of one S2T work item
 
 // One FMM instance: the free-space part of one layer, or one reaction
