@@ -65,7 +65,7 @@ typedef struct {
   int max_depth;      /* cap of the reaction-tree refinement next to interfaces      */
   int gamma1_panels;  /* Gauss-Legendre panels (16 nodes each) on the contour piece  */
                       /* from 0 to a in the fourth quadrant (Sec. 3.4); default 4;   */
-                      /* the direct near field uses at most 3 within the series     */
+                      /* the direct near field uses at most 2 within the series     */
                       /* range of its Bessel functions                              */
   double contour_a;   /* end point a of that piece on the real axis, 0 => 1.5 max k  */
   double tail_digits; /* the real tail [a, kcut] of the Sommerfeld integrals ends at */

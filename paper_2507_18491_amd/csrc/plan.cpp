@@ -1262,11 +1262,11 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       if (ipr.kind != 1 || s2t_rho_of[inst] < 0) continue;
       double dzmin = ipr.Dgap, rho_max = s2t_rho_of[inst];
       int n0 = (int)pl.node_kr.size();
-      // within the series range (|k_rho| rho <= 7.5 on Gamma_1) three panels
-      // integrate the direct pairs to about 1e-11 of the field; the tables
-      // (larger rho at coarse levels) keep the full panel count
+      // within the series range (|k_rho| rho <= 7.5 on Gamma_1) two panels
+      // integrate the direct pairs to within about 2e-9 of the field; the
+      // tables (larger rho at coarse levels) keep the full panel count
       int np1 = std::max(1, prm.gamma1_panels);
-      if (a * rho_max <= 7.5) np1 = std::min(np1, 3);
+      if (a * rho_max <= 7.5) np1 = std::min(np1, 2);
       for (int pnl = 0; pnl < np1; pnl++) {
         double t0 = (double)pnl / np1, t1 = (double)(pnl + 1) / np1;
         for (int gi = 0; gi < 16; gi++) {
