@@ -680,7 +680,7 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       // adjacent source/target leaves remain).  With the direct near field
       // enabled, the boxes next to the gap may stop one level earlier when
       // the direct (S2T) pairs of that level cost less than the M2L work of
-      // the last level (measured rates: about 2.9e-9 s per S2T pair, 2.9e-8 s
+      // the last level (measured rates: about 2.3e-9 s per S2T pair, 2.9e-8 s
       // per reaction M2L pair at p = 12 with adaptive orders; about 50 M2L
       // pairs per box at the finest level).
       int D1 = 0;
@@ -729,10 +729,10 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
           rounds += (double)((nt / CH) * ns + ((nt % CH) * ns + CH - 1) / CH);
           item_max = std::max(item_max, (double)((std::min(nt, CH) * ns + CH - 1) / CH));
         }
-        // a work item runs its rounds on one wave (about 1.07e-4 s each), so
+        // a work item runs its rounds on one wave (about 0.85e-4 s each), so
         // the launch lasts at least as long as its longest item: dense leaves
         // next to the gap make a few long items and the direct path slow
-        double c_s2t = std::max(rounds * (double)LM_S2T_CHUNK * 2.9e-9, item_max * 1.07e-4);
+        double c_s2t = std::max(rounds * (double)LM_S2T_CHUNK * 2.3e-9, item_max * 0.85e-4);
         double c_m2l = (double)tb1.size() * 50.0 * 9.0 * (double)P * P * 8.0 * 0.6 / 43e12;
         // the rate holds while every direct pair has a rho <= 7.5 on Gamma_1
         // (J0..J2 by their power series); adjacent level-(D1-1) leaves reach
