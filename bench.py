@@ -34,7 +34,7 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 fp64 FMA/clk x 2 flop x 2.4 GHz (fp
 # work) and the same M2L work (useful complex multiply-adds of the plan);
 # otherwise reported as null.
 K_M2L_TRAFFIC = {"digest": "d399e554001bfd19", "launches_per_step": 8, "m2l_cmac_useful": 1167408236574.0,
-                 "fetch_bytes": 1.7714e7 * 1024 * 2.0, "write_bytes": 5.4599e6 * 1024 * 1.0}
+                 "fetch_bytes": 1.7701e7 * 1024 * 2.0, "write_bytes": 5.4599e6 * 1024 * 1.0}
 
 
 def m2l_source_digest():
