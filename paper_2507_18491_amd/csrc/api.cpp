@@ -70,7 +70,6 @@ struct lm_ctx {
   std::vector<double> host_src, host_tgt;  // kept when they differ (for the swapped build)
   std::vector<int64_t> host_soff, host_toff;
   lm_ctx* adj = nullptr;                   // swapped-role context (built on first use)
-  lm_ctx* gctx = nullptr;                  // swapped-role context without S2T, for gradients
   MediumDev md;                            // medium as seen by the kernels
   int* d_s2t = nullptr;                    // S2T work items (target leaf, chunk)
   struct S2TRange {
@@ -149,8 +148,6 @@ static void free_build(lm_ctx* ctx) {
   ctx->built = false;
   if (ctx->adj) lm_destroy(ctx->adj);
   ctx->adj = nullptr;
-  if (ctx->gctx) lm_destroy(ctx->gctx);
-  ctx->gctx = nullptr;
   ctx->d_s2t = nullptr;
   ctx->s2t_ranges.clear();
   if (ctx->Jc) hipFree(ctx->Jc);
@@ -759,7 +756,8 @@ int lm_evaluate(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream) {
 // Curl mode (Hc != nullptr): the leaf passes and the direct reaction pairs
 // add curl (G J) at every target into Hc; A is not touched.
 // Gradient mode: the upward pass and M2L run on J as usual, then instead of
-// writing A the leaf passes add, at every target point, Re sum_b W^b grad B_b
+// writing A the leaf passes and the direct reaction pairs add, at every target
+// point, Re sum_b W^b grad B_b
 // (B the field of J) into gX [n_tgt][3]; A is not touched.
 // The context that evaluates the transposed operator: by reciprocity
 // (G(x, y) = G(y, x)^T when every mu is 1; with permeabilities the callers
@@ -793,37 +791,6 @@ static int swapped_ctx(lm_ctx* ctx, hipStream_t s, lm_ctx** out) {
     ctx->adj = a;
   }
   *out = ctx->adj;
-  return LM_OK;
-}
-
-// The context that evaluates source-position gradients: the swapped-role
-// FMM, but with reaction trees refined until no direct (S2T) pairs remain
-// (the gradient passes differentiate local expansions and the free-space
-// near field only).  Built once, on the first call, when the forward plan
-// uses S2T.
-static int grad_ctx(lm_ctx* ctx, hipStream_t s, lm_ctx** out) {
-  *out = nullptr;
-  if (!ctx->prm.react_s2t) return swapped_ctx(ctx, s, out);
-  if (!ctx->gctx) {
-    lm_ctx* a = nullptr;
-    int rc = lm_create(&a, ctx->device);
-    if (rc) return fail(ctx, rc, "cannot create the gradient context");
-    a->med = ctx->med;
-    a->layers_set = true;
-    a->prm = ctx->prm;
-    a->m2l_variant = ctx->m2l_variant;
-    a->prm.react_s2t = 0;
-    int ng = (int)ctx->host_soff.size() - 1;
-    rc = build_common(a, ng, ctx->host_toff.data(), ctx->host_tgt.data(), ctx->host_soff.data(),
-                      ctx->host_src.data(), s);
-    if (rc) {
-      std::string m = a->err;
-      lm_destroy(a);
-      return fail(ctx, rc, "gradient-context build: " + m);
-    }
-    ctx->gctx = a;
-  }
-  *out = ctx->gctx;
   return LM_OK;
 }
 
@@ -942,7 +909,7 @@ int lm_grad_src_xyz(lm_ctx* ctx, int n_rhs, const void* J, const void* gA, doubl
   HIPC(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   lm_ctx* T = nullptr;
-  int rc = grad_ctx(ctx, s, &T);
+  int rc = swapped_ctx(ctx, s, &T);
   if (rc) return rc;
   launch_fill_d(gX, 3 * pl.n_src, s);
   if (pl.n_src == 0 || pl.n_tgt == 0) {
@@ -1052,10 +1019,14 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
         launch_p2p(d, ctx->d_p2p[f], ctx->n_p2p[f], ctx->d_src, Jc, pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs, Ac,
                    ctx->p2p_red, s);
     }
-    if (!grad)
-      for (auto& r : ctx->s2t_ranges)
+    for (auto& r : ctx->s2t_ranges) {
+      if (grad)
+        launch_s2t_grad(d, ctx->md, ctx->d_s2t + 2 * r.item0, r.n, ctx->d_src, Jc, pl.n_src, ctx->d_tgt, W,
+                        pl.n_tgt, n_rhs, ctx->contour_a, r.smallz, gX, s);
+      else
         launch_s2t(d, ctx->md, ctx->d_s2t + 2 * r.item0, r.n, ctx->d_src, Jc, pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs,
                    ctx->contour_a, r.smallz, curl ? Hc : Ac, s, curl);
+    }
     mark(7);
   } else {
     for (int i = 2; i <= 7; i++) mark(i);

@@ -88,6 +88,10 @@ void launch_scale_mu_d(double* g, long long n, const double* xyz, MediumDev md, 
 void launch_s2t(const DevPlan& d, MediumDev md, const int* items, int n, const double* sxyz, const cd* J,
                 long long n_src, const double* txyz, long long n_tgt, int n_rhs, double a, bool smallz, cd* A,
                 hipStream_t s, bool hfield = false);
+// source-position gradients through the direct reaction pairs (gradient path roles)
+void launch_s2t_grad(const DevPlan& d, MediumDev md, const int* items, int n, const double* sxyz, const cd* C,
+                     long long n_src, const double* txyz, const cd* W, long long n_tgt, int n_rhs, double a,
+                     bool smallz, double* gX, hipStream_t s);
 void launch_fill_d(double* p, long long n, hipStream_t s);
 void launch_selftest_math(const double* x, long long n, double* out, hipStream_t s);
 void launch_l2p_grad(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_pts,

@@ -1706,6 +1706,226 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
     }
   }
 }
+// Source-position gradients through the direct reaction pairs (the swapped
+// roles of the gradient path: the "targets" are the points x where the
+// gradient is wanted, with weights W, the "sources" carry the currents c of
+// the conjugated output gradient).  Per pair the derivatives of the pair's
+// field B at x are taken inside the Sommerfeld integrals: with
+// D+- = d/dx +- i d/dy on e^{i kappa phi} J_|kappa|(k_rho rho), the Bessel
+// ladder D+ (J_n e^{i n phi}) = -k_rho J_{n+1} e^{i (n+1) phi},
+// D- (J_n e^{i n phi}) = k_rho J_{n-1} e^{i (n-1) phi} (signed orders), and
+// d/dz brings i e k_z of the target layer.  The integrals
+//   K_s,n = sum_nodes w k_rho Z F_s k_rho J_n,   L_s,n = sum w k_rho Z F_s (i e k_z) J_n
+// give every derivative of the five W(kappa, s); the field derivatives are
+// contracted with W, and gX[x] += Re sum_b W_b d_a B_b (summed over the
+// right-hand sides), each target adding its pairs in a fixed order.
+__device__ inline void bessel3_from012(cd z, cd iz, bool small, const cd* j, cd* j3) {
+  // J3 = 4 J2 / z - J1, or its series z^3/48 (1 - z^2/16) near 0
+  if (small) {
+    cd z2 = z * z;
+    *j3 = (z2 * z) * (1.0 / 48.0) * (cd{1.0, 0.0} - z2 * (1.0 / 16.0));
+  } else {
+    *j3 = 4.0 * (j[2] * iz) - j[1];
+  }
+}
+template <bool SMALLZ>
+__global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t_grad(DevPlan d, MediumDev md, const int* items,
+                                                              const double* sxyz, const cd* C, long long n_src,
+                                                              const double* txyz, const cd* W, long long n_tgt,
+                                                              int n_rhs, double a, double* gX) {
+  __shared__ double tp[LM_S2T_CHUNK][3];
+  __shared__ int seg_pt0[LM_S2T_SEG], seg_cum[LM_S2T_SEG + 1];
+  __shared__ double res[LM_S2T_CHUNK][3];
+  __shared__ cd nk[LM_S2T_CHUNK][10];
+  const int tid = threadIdx.x;
+  const int b = __builtin_amdgcn_readfirstlane(items[2 * blockIdx.x]);
+  const int chunk = __builtin_amdgcn_readfirstlane(items[2 * blockIdx.x + 1]);
+  const TgtBox tb = d.tbox[b];
+  const InstParams ip = d.inst[__builtin_amdgcn_readfirstlane(tb.inst)];
+  const int t0 = tb.pt0 + chunk * LM_S2T_CHUNK;
+  const int nt = min(LM_S2T_CHUNK, tb.pt1 - t0);
+  const int n0 = __builtin_amdgcn_readfirstlane(ip.s2t0), nn = __builtin_amdgcn_readfirstlane(ip.s2tn);
+  const int nser = __builtin_amdgcn_readfirstlane(ip.s2t_nser);
+  const QNode* nodes = d.nodes + n0;
+  const double dls = ip.up_s ? md.d[ip.ls - 1] : md.d[ip.ls];
+  const double esg = ip.up_t ? 1.0 : -1.0;  // d t / d z at the target
+  int id = 0;
+  if (tid < nt) {
+    id = d.tgt_perm[t0 + tid];
+    double zt = txyz[3 * id + 2];
+    tp[tid][0] = txyz[3 * id];
+    tp[tid][1] = txyz[3 * id + 1];
+    tp[tid][2] = ip.up_t ? zt - md.d[ip.lt] : md.d[ip.lt - 1] - zt;
+  }
+  double gx = 0, gy = 0, gz = 0;  // thread tid < nt: totals of target tid
+  for (int l0 = tb.p2p0; l0 < tb.p2p1; l0 += LM_S2T_SEG) {
+    const int nb = min(LM_S2T_SEG, tb.p2p1 - l0);
+    __syncthreads();
+    if (tid == 0) {
+      int cum = 0;
+      for (int e = 0; e < nb; e++) {
+        const SrcBox sb = d.sbox[d.p2p_list[l0 + e]];
+        seg_pt0[e] = sb.pt0;
+        seg_cum[e] = cum;
+        cum += sb.pt1 - sb.pt0;
+      }
+      seg_cum[nb] = cum;
+    }
+    __syncthreads();
+    const int ns = seg_cum[nb];
+    const int npair = nt * ns;
+    for (int q0 = 0; q0 < npair; q0 += LM_S2T_CHUNK) {
+      const int q = q0 + tid;
+      const bool pa = q < npair;
+      const int i = pa ? q / ns : 0, j = pa ? q - (q / ns) * ns : 0;
+      int e = 0;
+      while (e + 1 < nb && seg_cum[e + 1] <= j) e++;
+      const int sid = d.src_perm[seg_pt0[e] + (j - seg_cum[e])];
+      const double* sx = sxyz + 3 * (long long)sid;
+      double dx = tp[i][0] - sx[0], dy = tp[i][1] - sx[1];
+      double tz = tp[i][2], uz = ip.up_s ? dls - sx[2] : sx[2] - dls;
+      double rho = sqrt(dx * dx + dy * dy);
+      const double irho = rho > 0 ? 1.0 / rho : 0.0;
+      double cph = rho > 0 ? dx * irho : 1.0, sph = rho > 0 ? dy * irho : 0.0;
+      double kcut = pa ? a + LM_S2T_DIGITS / (tz + uz) : -1.0;
+      cd K11 = cd{0, 0}, K51 = cd{0, 0}, K20 = cd{0, 0}, K22 = cd{0, 0}, K40 = cd{0, 0}, K42 = cd{0, 0};
+      cd K31 = cd{0, 0}, K33 = cd{0, 0};
+      cd L10 = cd{0, 0}, L21 = cd{0, 0}, L32 = cd{0, 0}, L41 = cd{0, 0}, L50 = cd{0, 0};
+      for (int c0 = 0; c0 < nn; c0 += LM_S2T_CHUNK) {
+        const int nc = min(LM_S2T_CHUNK, nn - c0);
+        __syncthreads();
+        if (tid < nc) {
+          const QNode& nd = nodes[c0 + tid];
+          nk[tid][0] = nd.kr;
+          nk[tid][1] = nd.w * nd.kr;
+          nk[tid][2] = nd.kzt;
+          nk[tid][3] = nd.kzs;
+          for (int f = 0; f < 5; f++) nk[tid][4 + f] = nd.F[f];
+          nk[tid][9] = cd{nd.kr.y == 0.0 ? 1.0 / nd.kr.x : 0.0, 0.0};
+        }
+        __syncthreads();
+        for (int m = 0; m < nc; m++) {
+          const cd kr = nk[m][0];
+          cd jb[4], base;
+          if (kr.y != 0.0) {
+            if (!pa) continue;
+            const cd ez = cd{0, 1} * (tz * nk[m][2] + uz * nk[m][3]);
+            double esn, ecs;
+            lm_sincos_red(ez.y, &esn, &ecs);
+            const double ea = exp(ez.x);
+            base = nk[m][1] * cd{ea * ecs, ea * esn};
+            const cd z = rho * kr;
+            if (SMALLZ)
+              bessel012_horner(z, nser, jb, jb + 1, jb + 2);
+            else
+              bessel_jq(2, z, jb);
+            const bool small = rho * cabsd(kr) < 1e-2;
+            bessel3_from012(z, small ? cd{0, 0} : cd{1.0, 0.0} / z, small, jb, jb + 3);
+          } else if (kr.x <= kcut) {
+            double zf = exp(-(tz * nk[m][2].y + uz * nk[m][3].y));
+            base = cd{nk[m][1].x * zf, 0.0};
+            const double x = kr.x * rho, ix = nk[m][9].x * irho;
+            double J0, J1;
+            bessel01_real(x, ix, &J0, &J1);
+            double J2 = x > 1e-3 ? 2.0 * J1 * ix - J0 : x * x * (0.125 - x * x * (1.0 / 96.0));
+            double J3 = x > 1e-2 ? 4.0 * J2 * ix - J1 : x * x * x * (1.0 / 48.0) * (1.0 - x * x * (1.0 / 16.0));
+            jb[0] = cd{J0, 0};
+            jb[1] = cd{J1, 0};
+            jb[2] = cd{J2, 0};
+            jb[3] = cd{J3, 0};
+          } else {
+            continue;
+          }
+          const cd bk = base * kr;                                 // K weight
+          const cd bl = base * (cd{0.0, esg} * nk[m][2]);          // L weight: i e k_z
+          K11 = K11 + (bk * jb[1]) * nk[m][4];
+          K51 = K51 + (bk * jb[1]) * nk[m][8];
+          K20 = K20 + (bk * jb[0]) * nk[m][5];
+          K22 = K22 + (bk * jb[2]) * nk[m][5];
+          K40 = K40 + (bk * jb[0]) * nk[m][7];
+          K42 = K42 + (bk * jb[2]) * nk[m][7];
+          K31 = K31 + (bk * jb[1]) * nk[m][6];
+          K33 = K33 + (bk * jb[3]) * nk[m][6];
+          L10 = L10 + (bl * jb[0]) * nk[m][4];
+          L21 = L21 + (bl * jb[1]) * nk[m][5];
+          L32 = L32 + (bl * jb[2]) * nk[m][6];
+          L41 = L41 + (bl * jb[1]) * nk[m][7];
+          L50 = L50 + (bl * jb[0]) * nk[m][8];
+        }
+        bool more = false;
+        if (c0 + nc < nn) {
+          const cd kn = nodes[c0 + nc].kr;
+          more = kn.y != 0.0 || kn.x <= kcut;
+        }
+        if (!__syncthreads_or(more)) break;
+      }
+      double r0v = 0, r1v = 0, r2v = 0;
+      if (pa) {
+        const cd I{0.0, 1.0};
+        const cd e1 = cd{cph, sph}, e1c = cd{cph, -sph};
+        const cd e2 = e1 * e1, e2c = cconj(e2), e3 = e2 * e1, e3c = cconj(e3);
+        // derivatives of W(kappa, s) = e^{i kappa phi} i^{1+|kappa|} I_s,|kappa|: [D+, D-, d/dz]
+        const cd W1[3] = {-(I * e1) * K11, -(I * e1c) * K11, I * L10};
+        const cd W5[3] = {-(I * e1) * K51, -(I * e1c) * K51, I * L50};
+        const cd W2p[3] = {e2 * K22, -K20, -(e1 * L21)};
+        const cd W2m[3] = {-K20, e2c * K22, -(e1c * L21)};
+        const cd W4p[3] = {e2 * K42, -K40, -(e1 * L41)};
+        const cd W4m[3] = {-K40, e2c * K42, -(e1c * L41)};
+        const cd W3p[3] = {(I * e3) * K33, -(I * e1) * K31, -(I * e2) * L32};
+        const cd W3m[3] = {-(I * e1c) * K31, (I * e3c) * K33, -(I * e2c) * L32};
+        const double f = 0.079577471545947667884;  // 1 / (4 pi)
+        for (int r = 0; r < n_rhs; r++) {
+          const cd* cp = C + ((long long)r * n_src + sid) * 3;
+          const cd cx = cp[0], cy = cp[1], czv = cp[2];
+          const cd cpl = cx + I * cy, cmi = cx - I * cy;
+          const cd* wp = W + ((long long)r * n_tgt + d.tgt_perm[t0 + i]) * 3;
+          const cd wpl = wp[0] + I * wp[1], wmi = wp[0] - I * wp[1], wz = wp[2];
+          cd Q[3];
+          for (int x = 0; x < 3; x++) {
+            const cd dop = 0.5 * (W1[x] * cpl) - 0.5 * (W3p[x] * cmi) + W2p[x] * czv;
+            const cd dom = 0.5 * (W1[x] * cmi) - 0.5 * (W3m[x] * cpl) + W2m[x] * czv;
+            const cd doz = 0.5 * (W4p[x] * cmi) + 0.5 * (W4m[x] * cpl) + W5[x] * czv;
+            Q[x] = (0.5 * f) * (wpl * dom + wmi * dop) + f * (wz * doz);
+          }
+          // d/dx = (D+ + D-)/2, d/dy = (D+ - D-)/(2i)
+          r0v += 0.5 * (Q[0].x + Q[1].x);
+          r1v += 0.5 * (Q[0].y - Q[1].y);
+          r2v += Q[2].x;
+        }
+      }
+      res[tid][0] = r0v;
+      res[tid][1] = r1v;
+      res[tid][2] = r2v;
+      __syncthreads();
+      if (tid < nt) {
+        int qa = max(q0, tid * ns), qb = min(q0 + LM_S2T_CHUNK, (tid + 1) * ns);
+        for (int qq = qa; qq < qb; qq++) {
+          gx += res[qq - q0][0];
+          gy += res[qq - q0][1];
+          gz += res[qq - q0][2];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid < nt) {
+    gX[3 * id] += gx;
+    gX[3 * id + 1] += gy;
+    gX[3 * id + 2] += gz;
+  }
+}
+void launch_s2t_grad(const DevPlan& d, MediumDev md, const int* items, int n, const double* sxyz, const cd* C,
+                     long long n_src, const double* txyz, const cd* W, long long n_tgt, int n_rhs, double a,
+                     bool smallz, double* gX, hipStream_t s) {
+  if (n <= 0) return;
+  if (smallz)
+    hipLaunchKernelGGL(k_s2t_grad<true>, dim3(n), dim3(LM_S2T_CHUNK), 0, s, d, md, items, sxyz, C, n_src, txyz, W,
+                       n_tgt, n_rhs, a, gX);
+  else
+    hipLaunchKernelGGL(k_s2t_grad<false>, dim3(n), dim3(LM_S2T_CHUNK), 0, s, d, md, items, sxyz, C, n_src, txyz,
+                       W, n_tgt, n_rhs, a, gX);
+}
+
 // items: work items of instances of one component type (never sharing a
 // target); smallz: |k_rho| rho <= 7.5 on Gamma_1 for all of their pairs (the
 // series length comes from each block's instance)

@@ -177,9 +177,9 @@ def test_adjoint_and_grad_full_size_sampled():
 
 
 def test_adjoint_and_grad_with_direct_near_field(tiny):
-    """With the direct reaction near field on, the adjoint uses it (through
-    the same evaluation); the gradient runs on a fully refined swapped-role
-    plan."""
+    """With every adjacent reaction pair direct, the adjoint uses them
+    (through the same evaluation) and the gradient differentiates their
+    Sommerfeld integrals (Bessel ladder and d/dz inside the quadrature)."""
     d, k, x, J, g = tiny
     gg = np.load(os.path.join(GOLD, "tiny_grad_oracle.npz"))
     f = lmfmm.LayeredDyadicFMM(d, k, p=12, react_s2t=2).build(x)
