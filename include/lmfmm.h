@@ -192,8 +192,10 @@ int lm_evaluate_adjoint(lm_ctx* ctx, int n_rhs, const void* gA, void* gJ, void* 
  * currents mu conj(gA) placed at the targets is differentiated at the source
  * points (ladder relations of the regular wave functions on the local
  * expansions, closed-form derivative of the free-space dyadic in the near
- * field), contracted with J and divided by mu of the source's layer.  Build,
- * stream and error behaviour as lm_evaluate_adjoint. */
+ * field, Bessel-ladder and d/dz derivatives inside the Sommerfeld integrals
+ * of the directly evaluated reaction pairs), contracted with J and divided
+ * by mu of the source's layer.  Build, stream and error behaviour as
+ * lm_evaluate_adjoint. */
 int lm_grad_src_xyz(lm_ctx* ctx, int n_rhs, const void* J, const void* gA, double* gX, void* stream);
 
 /* Phase timing.  lm_set_timing(ctx, 1) (re)starts recording HIP events on
