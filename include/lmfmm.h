@@ -328,13 +328,14 @@ int lm_host_cheb_affine(int jmax, double a, double b, double* out);
 int lm_host_legendre_cheb(int p, double* out, int* stride);
 
 /* The host logic of lm_solve (Arnoldi with Gram-Schmidt applied twice, Givens
- * least squares, restarts and stopping tests) on a dense complex system
- * A x = b of order n held in host memory: A row-major complex128 [n][n],
- * b and x complex128 [n] (x: initial guess in, solution out).  Same
- * arguments and results as lm_solve for one column; *iters receives the
- * Arnoldi steps and *relres the final true relative residual (LM_OK also
- * when max_iter ends the iteration first: compare *relres with tol). */
-int lm_host_gmres_dense(int n, const double* A, const double* b, double* x, double tol, int restart,
+ * least squares, restarts, per-column stopping tests, right-hand sides in
+ * lockstep) on a dense complex system A X = B of order n held in host
+ * memory: A row-major complex128 [n][n], B and X complex128 [n_rhs][n]
+ * (X: initial guess in, solution out).  Same arguments and results as
+ * lm_solve; *iters receives the Arnoldi steps and relres [n_rhs] the final
+ * true relative residuals (LM_OK also when max_iter ends the iteration
+ * first: compare relres with tol). */
+int lm_host_gmres_dense(int n, int n_rhs, const double* A, const double* b, double* x, double tol, int restart,
                         int max_iter, int* iters, double* relres);
 
 /* Plans a build on the host only (trees, lists, tables sizes) and returns

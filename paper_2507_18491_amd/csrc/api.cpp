@@ -1449,61 +1449,69 @@ int lm_solve(lm_ctx* ctx, int n_rhs, const void* diag, const void* B, void* X, d
   return LM_OK;
 }
 
-// The same driver on a dense host matrix (tests of the host logic).
+// The same driver on a dense host matrix (tests of the host logic), with the
+// n_rhs columns of each vector stored one after the other (as on the device).
 struct HostKrylov : KrylovSpace {
   int n = 0;
   const double* A = nullptr;          // complex128 [n][n]
-  std::vector<std::vector<cd>> v;     // vectors 0..m+3
+  std::vector<std::vector<cd>> v;     // vectors 0..m+3, each [n_rhs][n]
   int apply(int src, int dst) override {
     const cd* a = (const cd*)A;
-    for (int i = 0; i < n; i++) {
-      cd acc{0, 0};
-      for (int j = 0; j < n; j++) acc = acc + a[(size_t)i * n + j] * v[src][j];
-      v[dst][i] = acc;
-    }
+    for (int r = 0; r < n_rhs; r++)
+      for (int i = 0; i < n; i++) {
+        cd acc{0, 0};
+        for (int j = 0; j < n; j++) acc = acc + a[(size_t)i * n + j] * v[src][(size_t)r * n + j];
+        v[dst][(size_t)r * n + i] = acc;
+      }
     return 0;
   }
   int dots(int first, int count, int w, cd* h) override {
-    for (int k = 0; k < count; k++) {
-      cd acc{0, 0};
-      for (int i = 0; i < n; i++) acc = acc + cconj(v[first + k][i]) * v[w][i];
-      h[k] = acc;
-    }
+    for (int k = 0; k < count; k++)
+      for (int r = 0; r < n_rhs; r++) {
+        cd acc{0, 0};
+        for (int i = 0; i < n; i++) acc = acc + cconj(v[first + k][(size_t)r * n + i]) * v[w][(size_t)r * n + i];
+        h[(size_t)k * n_rhs + r] = acc;
+      }
     return 0;
   }
   int combine(int first, int count, const cd* c, int dst) override {
-    for (int i = 0; i < n; i++)
-      for (int k = 0; k < count; k++) v[dst][i] = v[dst][i] + v[first + k][i] * c[k];
+    for (int r = 0; r < n_rhs; r++)
+      for (int i = 0; i < n; i++)
+        for (int k = 0; k < count; k++)
+          v[dst][(size_t)r * n + i] = v[dst][(size_t)r * n + i] + v[first + k][(size_t)r * n + i] * c[(size_t)k * n_rhs + r];
     return 0;
   }
   int scale(int src, const cd* c, int dst) override {
-    for (int i = 0; i < n; i++) v[dst][i] = v[src][i] * c[0];
+    for (int r = 0; r < n_rhs; r++)
+      for (int i = 0; i < n; i++) v[dst][(size_t)r * n + i] = v[src][(size_t)r * n + i] * c[r];
     return 0;
   }
   int rsub(int b, int w) override {
-    for (int i = 0; i < n; i++) v[w][i] = v[b][i] - v[w][i];
+    for (size_t i = 0; i < v[w].size(); i++) v[w][i] = v[b][i] - v[w][i];
     return 0;
   }
 };
 
-int lm_host_gmres_dense(int n, const double* A, const double* b, double* x, double tol, int restart, int max_iter,
-                        int* iters, double* relres) {
-  if (n < 1 || !A || !b || !x || restart < 1 || restart > LM_SOLVE_MAX_RESTART || max_iter < 1 || !(tol > 0))
+int lm_host_gmres_dense(int n, int n_rhs, const double* A, const double* b, double* x, double tol, int restart,
+                        int max_iter, int* iters, double* relres) {
+  if (n < 1 || n_rhs < 1 || n_rhs > 4096 || !A || !b || !x || restart < 1 || restart > LM_SOLVE_MAX_RESTART ||
+      max_iter < 1 || !(tol > 0))
     return LM_EINVAL;
   HostKrylov S;
   S.n = n;
   S.m = restart;
-  S.n_rhs = 1;
+  S.n_rhs = n_rhs;
   S.A = A;
-  S.v.assign(restart + 4, std::vector<cd>(n, cd{0, 0}));
-  memcpy(S.v[S.vX()].data(), x, (size_t)n * sizeof(cd));
-  memcpy(S.v[S.vB()].data(), b, (size_t)n * sizeof(cd));
-  double rr = 0;
+  const size_t len = (size_t)n_rhs * n;
+  S.v.assign(restart + 4, std::vector<cd>(len, cd{0, 0}));
+  memcpy(S.v[S.vX()].data(), x, len * sizeof(cd));
+  memcpy(S.v[S.vB()].data(), b, len * sizeof(cd));
+  std::vector<double> rr(n_rhs, 0.0);
   GmresResult gr;
-  gmres_drive(S, tol, max_iter, &rr, &gr);
-  memcpy(x, S.v[S.vX()].data(), (size_t)n * sizeof(cd));
+  gmres_drive(S, tol, max_iter, rr.data(), &gr);
+  memcpy(x, S.v[S.vX()].data(), len * sizeof(cd));
   if (iters) *iters = gr.iters;
-  if (relres) *relres = rr;
+  if (relres) memcpy(relres, rr.data(), n_rhs * sizeof(double));
   return LM_OK;
 }
 

@@ -78,8 +78,8 @@ def load_library():
     lib.lm_host_legendre_cheb.argtypes = [ctypes.c_int, D, P(ctypes.c_int)]
     lib.lm_solve.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, D,
                              P(lm_solve_info), vp]
-    lib.lm_host_gmres_dense.argtypes = [ctypes.c_int, D, D, D, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-                                        P(ctypes.c_int), D]
+    lib.lm_host_gmres_dense.argtypes = [ctypes.c_int, ctypes.c_int, D, D, D, ctypes.c_double, ctypes.c_int,
+                                        ctypes.c_int, P(ctypes.c_int), D]
     lib.lm_host_plan_stats.argtypes = [ctypes.c_int, D, D, P(lm_params), ctypes.c_int64, D, ctypes.c_int64,
                                        D, D, ctypes.c_int, ctypes.c_char_p, ctypes.c_int]
     _lib = lib
@@ -459,19 +459,24 @@ def host_plan_stats(d, k, src, tgt=None, **params):
 
 def host_gmres_dense(A, b, x0=None, tol=1e-10, restart=30, max_iter=1000):
     """The solve's host logic on a dense complex system A x = b (host
-    arrays); returns (x, iters, relres)."""
+    arrays; b of shape [n] or [n_rhs, n]); returns (x, iters, relres) with
+    relres a float for one right-hand side, else an array [n_rhs]."""
     A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128))
     n = A.shape[0]
-    b = np.ascontiguousarray(np.asarray(b, dtype=np.complex128).reshape(n))
-    x = np.zeros(n, dtype=np.complex128) if x0 is None else np.array(x0, dtype=np.complex128).reshape(n)
+    b = np.asarray(b, dtype=np.complex128)
+    single = b.ndim == 1
+    b = np.ascontiguousarray(b.reshape(-1, n))
+    nr = b.shape[0]
+    x = np.zeros((nr, n), dtype=np.complex128) if x0 is None else np.array(x0, dtype=np.complex128).reshape(nr, n)
+    x = np.ascontiguousarray(x)
     it = ctypes.c_int()
-    rr = ctypes.c_double()
-    rc = load_library().lm_host_gmres_dense(n, _dp(A.view(np.float64)), _dp(b.view(np.float64)),
+    rr = np.zeros(nr)
+    rc = load_library().lm_host_gmres_dense(n, nr, _dp(A.view(np.float64)), _dp(b.view(np.float64)),
                                             _dp(x.view(np.float64)), float(tol), int(restart), int(max_iter),
-                                            ctypes.byref(it), ctypes.byref(rr))
+                                            ctypes.byref(it), _dp(rr))
     if rc:
         raise LMError("lm_host_gmres_dense failed (%d)" % rc)
-    return x, it.value, rr.value
+    return (x[0], it.value, float(rr[0])) if single else (x, it.value, rr)
 
 
 def selftest_math(x):

@@ -305,3 +305,42 @@ def test_gmres_rejects_bad_arguments():
     for kw in (dict(restart=0), dict(restart=65), dict(max_iter=0), dict(tol=0.0)):
         with pytest.raises(lmfmm.LMError):
             lmfmm.host_gmres_dense(A, b, **kw)
+
+
+def test_gmres_lockstep_columns_match_single_solves():
+    """Several right-hand sides in lockstep: each column converges on its own
+    step count (a zero column at once, an eigenvector column in one step, a
+    generic column later), stops updating once converged, and agrees with its
+    single-column solve."""
+    n = 30
+    A, b = _rand_system(n, 6, shift=2.5)
+    lam, V = np.linalg.eig(A)
+    cols = [b, np.zeros(n, dtype=complex), V[:, 0] * (1.5 - 0.5j), _rand_system(n, 7)[1]]
+    B = np.stack(cols)
+    tol = 1e-11
+    X, it, rr = lmfmm.host_gmres_dense(A, B, tol=tol, restart=7, max_iter=400)
+    assert rr.shape == (4,) and np.all(rr <= tol)
+    assert rr[1] == 0.0 and not np.any(X[1])
+    Ainv = np.linalg.norm(np.linalg.inv(A), 2)
+    for r in (0, 2, 3):
+        xs, its, rrs = lmfmm.host_gmres_dense(A, cols[r], tol=tol, restart=7, max_iter=400)
+        assert its <= it
+        assert np.linalg.norm(B[r] - A @ X[r]) <= 1.01 * tol * np.linalg.norm(B[r])
+        lim = 2.2 * Ainv * tol * np.linalg.norm(B[r])
+        assert np.linalg.norm(X[r] - xs) <= lim
+    # the eigenvector column: one Arnoldi step solves it exactly
+    xe, ite, _ = lmfmm.host_gmres_dense(A, cols[2], tol=tol, restart=7)
+    assert ite == 1
+    assert np.abs(X[2] - cols[2] / lam[0]).max() <= 1e-10 * np.abs(cols[2] / lam[0]).max()
+
+
+def test_gmres_lockstep_iteration_cap_per_column():
+    A, b = _rand_system(25, 8, shift=0.1)
+    B = np.stack([b, 2.0 * b])
+    X, it, rr = lmfmm.host_gmres_dense(A, B, tol=1e-14, restart=4, max_iter=6)
+    assert it == 6 and np.all(rr > 1e-14)
+    # the problem is linear: the second column is twice the first throughout
+    assert np.abs(X[1] - 2.0 * X[0]).max() <= 1e-12 * np.abs(X[1]).max()
+    assert rr[1] == pytest.approx(rr[0], rel=1e-10)
+    for r in range(2):
+        assert rr[r] == pytest.approx(np.linalg.norm(B[r] - A @ X[r]) / np.linalg.norm(B[r]), rel=1e-9)
