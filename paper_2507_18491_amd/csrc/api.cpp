@@ -1227,16 +1227,17 @@ struct DevKrylov : KrylovSpace {
     hipEvent_t a, b;
     int kind;  // 0 matvec, 1 vector kernels
   };
-  std::vector<hipEvent_t> pool;
+  std::vector<hipEvent_t> owned;   // every event created here, destroyed with the object
+  std::vector<hipEvent_t> pool;    // events free for reuse
   std::vector<Ev> pending;
+  // the copy of hcoef to dcoef last enqueued: hcoef is not rewritten before
+  // it has run (the copy reads the pinned buffer when the stream reaches it)
+  hipEvent_t coef_ev = nullptr;
+  bool coef_pending = false;
   int err = 0;
 
   ~DevKrylov() override {
-    for (auto& e : pending) {
-      pool.push_back(e.a);
-      pool.push_back(e.b);
-    }
-    for (auto e : pool) hipEventDestroy(e);
+    for (auto e : owned) hipEventDestroy(e);
   }
   hipEvent_t ev() {
     if (!pool.empty()) {
@@ -1245,7 +1246,11 @@ struct DevKrylov : KrylovSpace {
       return e;
     }
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) err = 1;
+    if (hipEventCreate(&e) != hipSuccess) {
+      err = 1;
+      return nullptr;
+    }
+    owned.push_back(e);
     return e;
   }
   int tic(Ev& e, int kind) {
@@ -1272,6 +1277,7 @@ struct DevKrylov : KrylovSpace {
       pool.push_back(p.b);
     }
     pending.clear();
+    coef_pending = false;
     return 0;
   }
   int launched() {
@@ -1279,9 +1285,15 @@ struct DevKrylov : KrylovSpace {
     return e == hipSuccess ? 0 : fail(ctx, LM_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
   }
   int put_coef(const cd* c, int count) {
+    if (!coef_ev && !(coef_ev = ev())) return fail(ctx, LM_EHIP, "hipEventCreate failed");
+    hipError_t e = coef_pending ? hipEventSynchronize(coef_ev) : hipSuccess;
+    if (e != hipSuccess) return fail(ctx, LM_EHIP, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
     memcpy(hcoef, c, (size_t)count * n_rhs * sizeof(cd));
-    hipError_t e = hipMemcpyAsync(dcoef, hcoef, (size_t)count * n_rhs * sizeof(cd), hipMemcpyHostToDevice, s);
-    return e == hipSuccess ? 0 : fail(ctx, LM_EHIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+    e = hipMemcpyAsync(dcoef, hcoef, (size_t)count * n_rhs * sizeof(cd), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(coef_ev, s);
+    if (e != hipSuccess) return fail(ctx, LM_EHIP, std::string("coefficient copy: ") + hipGetErrorString(e));
+    coef_pending = true;
+    return 0;
   }
   double vec_bytes() const { return (double)n_rhs * n3 * sizeof(cd); }
 
@@ -1425,16 +1437,12 @@ int lm_solve(lm_ctx* ctx, int n_rhs, const void* diag, const void* B, void* X, d
   int rc = gmres_drive(S, tol, max_iter, rr.data(), &gr);
   if (rc) {
     hipStreamSynchronize(s);
-    S.pool.push_back(e0);
-    S.pool.push_back(e1);
     return rc;
   }
   HIPC(hipEventRecord(e1, s));
   if ((rc = S.sync())) return rc;
   float total = 0;
   hipEventElapsedTime(&total, e0, e1);
-  S.pool.push_back(e0);
-  S.pool.push_back(e1);
   if (relres_host) memcpy(relres_host, rr.data(), n_rhs * sizeof(double));
   if (info) {
     info->iters = gr.iters;
