@@ -334,7 +334,9 @@ int lm_host_legendre_cheb(int p, double* out, int* stride);
  * (X: initial guess in, solution out).  Same arguments and results as
  * lm_solve; *iters receives the Arnoldi steps and relres [n_rhs] the final
  * true relative residuals (LM_OK also when max_iter ends the iteration
- * first: compare relres with tol). */
+ * first: compare relres with tol).  LM_EINVAL, with nothing written, for
+ * n < 1, n_rhs outside 1..4096, a null A, b or x, restart outside
+ * 1..LM_SOLVE_MAX_RESTART, max_iter < 1, or tol not finite and > 0. */
 int lm_host_gmres_dense(int n, int n_rhs, const double* A, const double* b, double* x, double tol, int restart,
                         int max_iter, int* iters, double* relres);
 

@@ -1503,7 +1503,7 @@ struct HostKrylov : KrylovSpace {
 int lm_host_gmres_dense(int n, int n_rhs, const double* A, const double* b, double* x, double tol, int restart,
                         int max_iter, int* iters, double* relres) {
   if (n < 1 || n_rhs < 1 || n_rhs > 4096 || !A || !b || !x || restart < 1 || restart > LM_SOLVE_MAX_RESTART ||
-      max_iter < 1 || !(tol > 0))
+      max_iter < 1 || !(tol > 0) || !std::isfinite(tol))
     return LM_EINVAL;
   HostKrylov S;
   S.n = n;

@@ -302,7 +302,8 @@ def test_gmres_zero_rhs_and_iteration_cap():
 
 def test_gmres_rejects_bad_arguments():
     A, b = _rand_system(5, 5)
-    for kw in (dict(restart=0), dict(restart=65), dict(max_iter=0), dict(tol=0.0)):
+    for kw in (dict(restart=0), dict(restart=65), dict(max_iter=0), dict(tol=0.0), dict(tol=float("inf")),
+               dict(tol=float("nan"))):
         with pytest.raises(lmfmm.LMError):
             lmfmm.host_gmres_dense(A, b, **kw)
 
