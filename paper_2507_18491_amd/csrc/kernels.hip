@@ -1373,7 +1373,7 @@ __global__ __launch_bounds__(NT) void k_p2p_grad(DevPlan d, const int* tboxes, c
               cd fa = cd{1.0 - ikr2, ikr}, fb = cd{-1.0 + 3.0 * ikr2, -3.0 * ikr};
               cd dfa = k * cd{2.0 * ikr3, -ikr2};              // d fa / dr
               cd dfb = k * cd{-6.0 * ikr3, 3.0 * ikr2};        // d fb / dr
-              cd a = g * fa, bq = g * fb;
+              cd bq = g * fb;
               cd ap = gp * fa + g * dfa, bp = gp * fb + g * dfb;
               double ux = rx * ir, uy = ry * ir, uz = rz * ir;
               cd sx = sj[j][0], sy = sj[j][1], sz = sj[j][2];
