@@ -228,7 +228,7 @@ static void or_solve_1d(const or_medium *md, cplx kr, int s, int pol,
 
 /* Reaction scalars at (kr, z in layer t, z' in layer s) for one polarisation:
  * out[0] = R, out[1] = d_z R, out[2] = d_z' R, out[3] = d_z d_z' R.      */
-static void or_reaction_scalars(const or_medium *md, cplx kr, int t, int s, int pol,
+static void or_reaction_scalars(const or_medium *md, cplx kr, int t, int s,
                                 const cplx amp[2][OR_MAXL][2], double z, double zp,
                                 cplx out[4]) {
   int L = md->n - 1;
@@ -362,8 +362,8 @@ static void or_sommerfeld_pair(const or_medium *md, const or_contour *ct, const 
       } else {
         or_solve_1d(md, kr, s, 0, ampf);
         or_solve_1d(md, kr, s, 1, ampp);
-        or_reaction_scalars(md, kr, t, s, 0, ampf, z, zp, Sf);
-        or_reaction_scalars(md, kr, t, s, 1, ampp, z, zp, Sp);
+        or_reaction_scalars(md, kr, t, s, ampf, z, zp, Sf);
+        or_reaction_scalars(md, kr, t, s, ampp, z, zp, Sp);
         for (int q = 0; q < 4; q++) Sp[q] *= tm_scale;
       }
       or_bessel012_c(kr * rho, Jb);
@@ -392,8 +392,8 @@ static void or_sommerfeld_pair(const or_medium *md, const or_contour *ct, const 
       } else {
         or_solve_1d(md, kr, s, 0, ampf);
         or_solve_1d(md, kr, s, 1, ampp);
-        or_reaction_scalars(md, kr, t, s, 0, ampf, z, zp, Sf);
-        or_reaction_scalars(md, kr, t, s, 1, ampp, z, zp, Sp);
+        or_reaction_scalars(md, kr, t, s, ampf, z, zp, Sf);
+        or_reaction_scalars(md, kr, t, s, ampp, z, zp, Sp);
         for (int q = 0; q < 4; q++) Sp[q] *= tm_scale;
       }
       or_bessel012_r(krr * rho, Jb);
@@ -586,7 +586,7 @@ int lm_oracle_spectral(int n_layers, const double *d, const double *k, const dou
   cplx amp[2][OR_MAXL][2], S[4];
   for (int pol = 0; pol < 2; pol++) {
     or_solve_1d(&md, kr, s, pol, amp);
-    or_reaction_scalars(&md, kr, t, s, pol, amp, z, zp, S);
+    or_reaction_scalars(&md, kr, t, s, amp, z, zp, S);
     for (int q = 0; q < 4; q++) {
       out[2 * (4 * pol + q)] = creal(S[q]);
       out[2 * (4 * pol + q) + 1] = cimag(S[q]);
