@@ -112,6 +112,18 @@ def test_solve_error_paths(small):
     g.close()
 
 
+def _direct_by_source_chunks(oracle, d, k, src, X, tgt, chunks=16):
+    """The oracle's direct sum at a few targets with the sources split into
+    chunks evaluated concurrently (the oracle's own threads split over
+    targets only; the sum is linear in the sources), added in chunk order."""
+    from concurrent.futures import ThreadPoolExecutor
+    oracle.direct(d, k, src[:1], X[:, :1], tgt[:1], n_threads=1)  # one-time set-up, serially
+    parts = np.array_split(np.arange(src.shape[0]), chunks)
+    with ThreadPoolExecutor(chunks) as ex:
+        res = list(ex.map(lambda q: oracle.direct(d, k, src[q], X[:, q], tgt, n_threads=1), parts))
+    return sum(res)
+
+
 def test_solve_three_layer_20k_sampled_rows():
     """20k-point lattice in the three-layer medium (p = 12, free part p = 20):
     the solve converges, and at sampled points the residual of the exact
@@ -128,7 +140,7 @@ def test_solve_three_layer_20k_sampled_rows():
     X = X.cpu().numpy()
     f.close()
     idx = inputs.sample_targets(n, count=3, seed=2)
-    GX = oracle.direct(d, k, x, X, x[idx])
+    GX = _direct_by_source_chunks(oracle, d, k, x, X, x[idx])
     res = dg[idx][None, :, None] * X[:, idx] - GX - B[:, idx]
     e = np.linalg.norm(res) / np.linalg.norm(B[:, idx])
     print("  sampled exact-system residual %.2e" % e, flush=True)
