@@ -208,8 +208,8 @@ def main():
                           "copy_calibration_bytes_written_per_copy": src.numel() * 8}), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (got --gpus %d); the path shards by "
-              "independent FMM instances but no multi-GPU run is provided." % args.gpus, flush=True)
+        print("bench.py: the benchmark runs on one GPU only (got --gpus %d); the evaluation would shard "
+              "by independent FMM instances, but no multi-GPU run is provided." % args.gpus, flush=True)
         sys.exit(2)
     import torch
     from paper_2507_18491_amd import inputs, lmfmm
