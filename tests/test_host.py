@@ -3,7 +3,9 @@
 Covers: the shared library loads and exports every function declared in
 include/lmfmm.h; the reaction-component enumeration (paper Sec. 3.1); the
 Chebyshev identities of Appendices A and B; the planner (trees, lists,
-refinement next to interfaces) and its error paths.
+refinement next to interfaces) and its error paths; the iterative solve's
+host logic on dense host systems; loud failure without the built library or
+without a device.
 """
 import math
 import os
@@ -345,3 +347,24 @@ def test_gmres_lockstep_iteration_cap_per_column():
     assert rr[1] == pytest.approx(rr[0], rel=1e-10)
     for r in range(2):
         assert rr[r] == pytest.approx(np.linalg.norm(B[r] - A @ X[r]) / np.linalg.norm(B[r]), rel=1e-9)
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built library every entry point raises: there is no
+    fallback path."""
+    monkeypatch.setattr(lmfmm, "_lib", None)
+    monkeypatch.setattr(lmfmm, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "liblmfmm.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        lmfmm.load_library()
+    with pytest.raises(RuntimeError, match="not built"):
+        lmfmm.LayeredDyadicFMM([0.0], [1.0, 1.5])
+
+
+def test_no_device_fails_loudly():
+    """On a machine without a GPU, creating a context raises (the library
+    computes nothing on the host)."""
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    with pytest.raises(lmfmm.LMError, match="lm_create"):
+        lmfmm.LayeredDyadicFMM([0.0], [1.0, 1.5])
