@@ -189,18 +189,13 @@ class LayeredDyadicFMM:
         import torch
         if self.n_src is None:
             raise LMError("build() must be called first")
-        if not (J.is_cuda and J.dtype == torch.complex128):
-            raise LMError("J must be a complex128 CUDA tensor")
-        single = J.dim() == 2
-        n_rhs = 1 if single else J.shape[0]
-        Jr = J.reshape(n_rhs, self.n_src, 3).contiguous()
-        if out is None:
-            out = torch.empty((n_rhs, self.n_tgt, 3), dtype=torch.complex128, device=J.device)
+        single, n_rhs, Jr = self._rhs_view(J, self.n_src, "J")
+        out = self._out(out, (n_rhs, self.n_tgt, 3), torch.complex128, J)
         if stream is None:
             stream = torch.cuda.current_stream(J.device).cuda_stream
         self._check(self.lib.lm_evaluate(self.ctx, n_rhs, ctypes.c_void_p(Jr.data_ptr()),
                                          ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)))
-        return out[0] if single else out
+        return out.view(self.n_tgt, 3) if single else out.view(n_rhs, self.n_tgt, 3)
 
     def evaluate_h(self, J, out=None, stream=None):
         """Magnetic field H = G_H J, G_H = (1/mu) curl G (Faraday's law).
@@ -209,21 +204,44 @@ class LayeredDyadicFMM:
         if self.n_src is None:
             raise LMError("build() must be called first")
         single, n_rhs, Jr = self._rhs_view(J, self.n_src, "J")
-        if out is None:
-            out = torch.empty((n_rhs, self.n_tgt, 3), dtype=torch.complex128, device=J.device)
+        out = self._out(out, (n_rhs, self.n_tgt, 3), torch.complex128, J)
         if stream is None:
             stream = torch.cuda.current_stream(J.device).cuda_stream
         self._check(self.lib.lm_evaluate_h(self.ctx, n_rhs, ctypes.c_void_p(Jr.data_ptr()),
                                            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)))
-        return out[0] if single else out
+        return out.view(self.n_tgt, 3) if single else out.view(n_rhs, self.n_tgt, 3)
 
     def _rhs_view(self, X, n, name):
         import torch
         if not (X.is_cuda and X.dtype == torch.complex128):
             raise LMError("%s must be a complex128 CUDA tensor" % name)
+        if X.device.index != self.device:
+            raise LMError("%s must be on cuda:%d (the device of the build)" % (name, self.device))
         single = X.dim() == 2
         n_rhs = 1 if single else X.shape[0]
+        if X.dim() not in (2, 3) or X.numel() != n_rhs * n * 3:
+            raise LMError("%s must have shape [%d, 3] or [n_rhs, %d, 3], got %s" % (name, n, n, tuple(X.shape)))
         return single, n_rhs, X.reshape(n_rhs, n, 3).contiguous()
+
+    def _out(self, out, shape, dtype, like, name="out"):
+        """A new output tensor, or the caller's after checking everything the
+        library relies on (the C ABI itself checks only pointer alignment):
+        dtype, device, contiguity and size."""
+        import torch
+        if out is None:
+            return torch.empty(shape, dtype=dtype, device=like.device)
+        if not (out.is_cuda and out.dtype == dtype):
+            raise LMError("%s must be a %s CUDA tensor" % (name, str(dtype).replace("torch.", "")))
+        if out.device != like.device:
+            raise LMError("%s must be on %s (the input's device)" % (name, like.device))
+        if not out.is_contiguous():
+            raise LMError("%s must be contiguous" % name)
+        n = 1
+        for v in shape:
+            n *= v
+        if out.numel() != n:
+            raise LMError("%s must hold %d elements (shape %s), got %d" % (name, n, tuple(shape), out.numel()))
+        return out
 
     def evaluate_adjoint(self, gA, out=None, stream=None):
         """gJ = G^H gA.  gA: complex128 CUDA tensor [n_tgt, 3] or [n_rhs, n_tgt, 3]."""
@@ -231,13 +249,12 @@ class LayeredDyadicFMM:
         if self.n_src is None:
             raise LMError("build() must be called first")
         single, n_rhs, g = self._rhs_view(gA, self.n_tgt, "gA")
-        if out is None:
-            out = torch.empty((n_rhs, self.n_src, 3), dtype=torch.complex128, device=gA.device)
+        out = self._out(out, (n_rhs, self.n_src, 3), torch.complex128, gA)
         if stream is None:
             stream = torch.cuda.current_stream(gA.device).cuda_stream
         self._check(self.lib.lm_evaluate_adjoint(self.ctx, n_rhs, ctypes.c_void_p(g.data_ptr()),
                                                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)))
-        return out[0] if single else out
+        return out.view(self.n_src, 3) if single else out.view(n_rhs, self.n_src, 3)
 
     def grad_src_xyz(self, J, gA, out=None, stream=None):
         """Gradient [n_src, 3] (fp64) of a real loss with dL/dA = gA with respect to
@@ -249,8 +266,9 @@ class LayeredDyadicFMM:
         _, n_rhs2, g = self._rhs_view(gA, self.n_tgt, "gA")
         if n_rhs2 != n_rhs:
             raise LMError("J and gA have different numbers of right-hand sides")
-        if out is None:
-            out = torch.empty((self.n_src, 3), dtype=torch.float64, device=J.device)
+        if gA.device != J.device:
+            raise LMError("J and gA must be on the same device")
+        out = self._out(out, (self.n_src, 3), torch.float64, J)
         if stream is None:
             stream = torch.cuda.current_stream(J.device).cuda_stream
         self._check(self.lib.lm_grad_src_xyz(self.ctx, n_rhs, ctypes.c_void_p(Jr.data_ptr()),

@@ -264,6 +264,43 @@ def test_direct_sum_is_sum_of_pairs(oracle):
         assert rel(A[r], ref) < 1e-13
 
 
+def test_direct_free_is_same_layer_sum_of_closed_form_blocks(oracle):
+    """The free-space part alone (the free sum of the layered problem
+    statement of Sec. 3.3: same-layer sources only, the coincident point
+    skipped) equals the explicit sum of closed-form free dyadic blocks, each
+    with the wavenumber of the common layer, over exactly those sources; and
+    the full direct sum minus it equals the sum of the reaction blocks over
+    every source.  Three layers, targets that coincide with sources and
+    targets that do not."""
+    d, k = D3, K3
+    rng = np.random.default_rng(11)
+    zs = np.concatenate([rng.uniform(0.05, 1.0, 7), rng.uniform(-1.15, -0.05, 6), rng.uniform(-2.2, -1.25, 7)])
+    src = np.column_stack([rng.uniform(-1, 1, zs.size), rng.uniform(-1, 1, zs.size), zs])
+    J = rng.uniform(-1, 1, (zs.size, 3)) + 1j * rng.uniform(-1, 1, (zs.size, 3))
+    extra = np.array([[0.3, -0.2, 0.6], [-0.4, 0.1, -0.7], [0.2, 0.5, -1.9]])
+    tgt = np.concatenate([src[[0, 8, 15]], extra])
+
+    def layer(z):
+        return 0 if z > d[0] else (1 if z > d[1] else 2)
+
+    A = oracle.direct_free(d, k, src, J, tgt, n_threads=2)
+    for i, x in enumerate(tgt):
+        ref = np.zeros(3, dtype=np.complex128)
+        n_used = 0
+        for j, xp in enumerate(src):
+            if layer(xp[2]) != layer(x[2]) or np.array_equal(x, xp):
+                continue
+            ref += oracle.free_check(k[layer(x[2])], x, xp)[1] @ J[j]
+            n_used += 1
+        assert n_used >= 5
+        assert rel(A[i], ref) < 1e-14
+    # the rest of the direct sum is the reaction field of every source
+    full = oracle.direct(d, k, src, J, tgt, n_threads=2)
+    for i, x in enumerate(tgt):
+        react = sum(oracle.reaction_pair(d, k, x, xp) @ q for xp, q in zip(src, J))
+        assert rel(full[i] - A[i], react) < 1e-12
+
+
 def test_sparse_currents_are_skipped_exactly(oracle):
     d, k, x, J = inputs.tiny()
     Js, keep = inputs.sparse_currents(J, 25)
