@@ -1,0 +1,1304 @@
+// cpufmm.cpp -- a CPU run of the layered-media dyadic FMM (test infrastructure).
+//
+// The same algorithm as the HIP library, pass by pass, on the host in plain
+// loops: P2M, M2M, M2L, L2L and L2P of the free-space part of every layer
+// (paper Sec. 2) and of every reaction component (Sec. 3.3), the free-space
+// near field and the direct reaction pairs.  It takes from the library's
+// planner only the plan: trees, interaction lists, per-offset M2L orders and
+// the quadrature node sets (the shared tree builder; any tree gives the
+// method's result within truncation, and a rounding-level comparison needs
+// the same one).  Every number is computed here, by routes of its own:
+//
+//  * densities of the reaction components: the two 1-D interface problems
+//    of Sec. 3.1 (TE and TM jump conditions) solved as one dense linear
+//    system per node with local reference planes, read off as the amplitude
+//    of the wave arriving at the target for a unit wave leaving the source;
+//  * reaction M2L tables: the single Sommerfeld integral of the product of
+//    the two associated Legendre functions (Sec. 3.4, the reduction of the
+//    double integral to one k_rho integral), summed directly over the nodes
+//    -- no Chebyshev expansion, so the library's Appendix A/B route is
+//    checked against its definition;
+//  * free-space translations: the addition theorem of the wave functions
+//    with Gaunt coefficients by Gauss-Legendre quadrature;
+//  * special functions in long double: orthonormal Legendre functions,
+//    spherical Bessel functions by Miller's recurrence, Bessel J_q of
+//    complex argument by Miller's recurrence normalised by the trapezoid
+//    rule on Bessel's integral.
+//
+// It is not part of the product: only the tests use it.
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <complex>
+#include <map>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../include/lmfmm.h"
+#include "../paper_2507_18491_amd/csrc/plan.h"
+
+namespace {
+
+typedef std::complex<double> cx;
+typedef long double ld;
+typedef std::complex<long double> lcx;
+
+const ld PI_L = 3.14159265358979323846264338327950288L;
+
+// ------------------------------------------------------------------ threads
+template <class F>
+void pfor(long long n, int nth, F&& f) {
+  if (nth <= 1 || n <= 1) {
+    for (long long i = 0; i < n; i++) f(i);
+    return;
+  }
+  std::atomic<long long> next{0};
+  std::vector<std::thread> th;
+  const int nt = (int)std::min<long long>(nth, n);
+  for (int t = 0; t < nt; t++)
+    th.emplace_back([&]() {
+      long long i;
+      while ((i = next.fetch_add(1)) < n) f(i);
+    });
+  for (auto& x : th) x.join();
+}
+
+// ------------------------------------------------------------------ small helpers
+inline int tri(int n, int m) { return n * (n + 1) / 2 + m; }
+inline int nmi(int n, int m) { return n * n + n + m; }
+inline lcx ipow_l(int e) {
+  switch (((e % 4) + 4) % 4) {
+    case 0: return lcx(1, 0);
+    case 1: return lcx(0, 1);
+    case 2: return lcx(-1, 0);
+    default: return lcx(0, -1);
+  }
+}
+inline cx tocx(const cd& v) { return cx(v.x, v.y); }
+// vertical wavenumber sqrt(k^2 - kr^2), branch Im >= 0 (outgoing / decaying)
+inline lcx kz_branch(ld k, lcx kr) {
+  lcx s = std::sqrt(lcx(k * k, 0) - kr * kr);
+  if (s.imag() < 0) s = -s;
+  return s;
+}
+
+// Orthonormal associated Legendre functions with the Condon-Shortley phase,
+// P^m_n(cos b) for 0 <= m <= n <= nmax, from (cos b, sin b) given separately
+// (so a complex angle needs no square root); out[tri(n, m)].
+template <class T>
+void legendre(int nmax, T c, T s, T* out) {
+  out[0] = T(1.0L / std::sqrt(4.0L * PI_L));
+  for (int m = 1; m <= nmax; m++) out[tri(m, m)] = T(-std::sqrt((2.0L * m + 1) / (2.0L * m))) * s * out[tri(m - 1, m - 1)];
+  for (int m = 0; m < nmax; m++) {
+    out[tri(m + 1, m)] = T(std::sqrt(2.0L * m + 3)) * c * out[tri(m, m)];
+    for (int n = m + 2; n <= nmax; n++) {
+      const ld a = std::sqrt((4.0L * n * n - 1) / ((ld)n * n - (ld)m * m));
+      const ld b = std::sqrt(((ld)(n - 1) * (n - 1) - (ld)m * m) / (4.0L * (n - 1) * (n - 1) - 1));
+      out[tri(n, m)] = T(a) * (c * out[tri(n - 1, m)] - T(b) * out[tri(n - 2, m)]);
+    }
+  }
+}
+
+// spherical Bessel j_n(x), n = 0..nmax, x >= 0: upward recurrence where it is
+// stable (x > nmax), else Miller's downward recurrence normalised by j_0 or
+// j_1 (the larger)
+void sph_j(int nmax, ld x, ld* out) {
+  if (x == 0) {
+    out[0] = 1;
+    for (int n = 1; n <= nmax; n++) out[n] = 0;
+    return;
+  }
+  const ld sx = std::sin(x), cxv = std::cos(x);
+  const ld j0 = sx / x;
+  ld j1;
+  if (x < 0.25L) {
+    // series x/3 - x^3/30 + x^5/840 - x^7/45360 + x^9/3991680
+    const ld x2 = x * x;
+    j1 = x * (1.0L / 3 - x2 * (1.0L / 30 - x2 * (1.0L / 840 - x2 * (1.0L / 45360 - x2 / 3991680.0L))));
+  } else {
+    j1 = (sx / x - cxv) / x;
+  }
+  if (x > (ld)nmax) {
+    out[0] = j0;
+    if (nmax >= 1) out[1] = j1;
+    for (int n = 1; n < nmax; n++) out[n + 1] = (2 * n + 1) / x * out[n] - out[n - 1];
+    return;
+  }
+  const int N = nmax + 24 + (int)x;
+  std::vector<ld> f(N + 2, 0.0L);
+  f[N + 1] = 0;
+  f[N] = 1e-300L;
+  for (int n = N; n >= 1; n--) {
+    f[n - 1] = (2 * n + 1) / x * f[n] - f[n + 1];
+    if (std::fabs(f[n - 1]) > 1e300L) {
+      for (int q = n - 1; q <= N; q++) f[q] *= 1e-300L;
+    }
+  }
+  const ld sc = (std::fabs(j0) >= std::fabs(j1) || nmax < 1) ? j0 / f[0] : j1 / f[1];
+  for (int n = 0; n <= nmax; n++) out[n] = f[n] * sc;
+}
+
+// spherical Bessel y_n(x), x > 0, by the upward recurrence (stable for y)
+void sph_y(int nmax, ld x, ld* out) {
+  const ld sx = std::sin(x), cxv = std::cos(x);
+  out[0] = -cxv / x;
+  if (nmax >= 1) out[1] = -cxv / (x * x) - sx / x;
+  for (int n = 1; n < nmax; n++) out[n + 1] = (2 * n + 1) / x * out[n] - out[n - 1];
+}
+
+// J_0(z), J_1(z) by the trapezoid rule on Bessel's integral
+// J_n(z) = (1/pi) int_0^pi cos(n t - z sin t) dt (periodic integrand, so the
+// rule converges geometrically)
+void bessel01_trap(lcx z, lcx* j0, lcx* j1) {
+  const int M = 40 + 2 * (int)std::abs(z);
+  lcx s0 = 0, s1 = 0;
+  for (int i = 0; i <= M; i++) {
+    const ld t = PI_L * i / M, w = (i == 0 || i == M) ? 0.5L : 1.0L;
+    const lcx a = z * std::sin(t);
+    s0 += w * std::cos(a);
+    s1 += w * std::cos(lcx(t, 0) - a);
+  }
+  *j0 = s0 / (ld)M;
+  *j1 = s1 / (ld)M;
+}
+
+// Bessel J_q(z), q = 0..Q, complex z: Miller's downward recurrence
+// J_{n-1} = (2n/z) J_n - J_{n+1}, normalised by J_0 or J_1 from the
+// trapezoid rule (whichever is larger in modulus)
+void bessel_J(int Q, lcx z, lcx* out) {
+  const ld az = std::abs(z);
+  if (az == 0) {
+    out[0] = 1;
+    for (int q = 1; q <= Q; q++) out[q] = 0;
+    return;
+  }
+  const int N = Q + 30 + (int)(2 * az);
+  std::vector<lcx> f(N + 2, lcx(0, 0));
+  f[N] = lcx(1e-300L, 0);
+  const lcx iz = lcx(1, 0) / z;
+  for (int n = N; n >= 1; n--) {
+    f[n - 1] = (ld)(2 * n) * iz * f[n] - f[n + 1];
+    if (std::abs(f[n - 1].real()) + std::abs(f[n - 1].imag()) > 1e300L)
+      for (int q = n - 1; q <= N; q++) f[q] *= 1e-300L;
+  }
+  lcx j0, j1;
+  bessel01_trap(z, &j0, &j1);
+  const lcx sc = (std::abs(j0) >= std::abs(j1) || Q < 1) ? j0 / f[0] : j1 / f[1];
+  for (int q = 0; q <= Q; q++) out[q] = f[q] * sc;
+}
+
+// J_q(x), q = 0..Q, real x >= 0: Miller's recurrence normalised by the C
+// library's J_0 or J_1
+void bessel_J_real(int Q, ld x, ld* out) {
+  if (x == 0) {
+    out[0] = 1;
+    for (int q = 1; q <= Q; q++) out[q] = 0;
+    return;
+  }
+  const int N = Q + 30 + (int)(2 * x);
+  std::vector<ld> f(N + 2, 0.0L);
+  f[N] = 1e-300L;
+  for (int n = N; n >= 1; n--) {
+    f[n - 1] = (2 * n) / x * f[n] - f[n + 1];
+    if (std::fabs(f[n - 1]) > 1e300L)
+      for (int q = n - 1; q <= N; q++) f[q] *= 1e-300L;
+  }
+  const ld a0 = ::j0((double)x), a1 = ::j1((double)x);
+  const ld sc = (std::fabs(a0) >= std::fabs(a1) || Q < 1) ? a0 / f[0] : a1 / f[1];
+  for (int q = 0; q <= Q; q++) out[q] = f[q] * sc;
+}
+
+// Gauss-Legendre rule on [-1, 1] (Newton on P_n)
+void gauss_leg(int n, std::vector<ld>& x, std::vector<ld>& w) {
+  x.assign(n, 0);
+  w.assign(n, 0);
+  for (int i = 0; i < n; i++) {
+    ld z = std::cos(PI_L * (i + 0.75L) / (n + 0.5L)), dp = 0;
+    for (int it = 0; it < 60; it++) {
+      ld p0 = 1, p1 = z;
+      for (int j = 2; j <= n; j++) {
+        const ld p2 = ((2 * j - 1) * z * p1 - (j - 1) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) p0 = 1;
+      dp = n * (z * p1 - p0) / (z * z - 1);
+      const ld dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-19L) break;
+    }
+    x[i] = z;
+    w[i] = 2 / ((1 - z * z) * dp * dp);
+  }
+}
+
+// Gaunt coefficients  G(n,m; nu,mu; q) = int Y^m_n conj(Y^mu_nu) conj(Y^{m-mu}_q) dOmega
+// for n, nu <= p, q <= 2p (the phi integral fixes the third order; the
+// theta integrand is a polynomial of degree <= n + nu + q in cos theta, so
+// Gauss-Legendre with 2p + 2 nodes is exact).
+struct Gaunt {
+  int p = -1;
+  std::vector<double> G;  // [nmi(n,m)][nmi(nu,mu)][q]
+  double at(int n, int m, int nu, int mu, int q) const {
+    const long long P = (long long)(p + 1) * (p + 1);
+    return G[((long long)nmi(n, m) * P + nmi(nu, mu)) * (2 * p + 1) + q];
+  }
+  void build(int pp) {
+    p = pp;
+    const int Q = 2 * p, ng = 2 * p + 2;
+    std::vector<ld> xg, wg;
+    gauss_leg(ng, xg, wg);
+    const int nt = (Q + 1) * (Q + 2) / 2;
+    std::vector<ld> Pl((size_t)ng * nt);
+    for (int g = 0; g < ng; g++) legendre<ld>(Q, xg[g], std::sqrt(1 - xg[g] * xg[g]), &Pl[(size_t)g * nt]);
+    auto Ps = [&](int g, int n, int m) {  // P^m_n with the (-1)^m of negative orders
+      ld v = Pl[(size_t)g * nt + tri(n, std::abs(m))];
+      return (m < 0 && (std::abs(m) & 1)) ? -v : v;
+    };
+    const long long P = (long long)(p + 1) * (p + 1);
+    G.assign((size_t)(P * P * (2 * p + 1)), 0.0);
+    for (int n = 0; n <= p; n++)
+      for (int m = -n; m <= n; m++)
+        for (int nu = 0; nu <= p; nu++)
+          for (int mu = -nu; mu <= nu; mu++) {
+            const int s = m - mu;
+            for (int q = std::abs(s); q <= n + nu; q++) {
+              if ((n + nu + q) & 1) continue;
+              if (q < std::abs(n - nu)) continue;
+              ld acc = 0;
+              for (int g = 0; g < ng; g++) acc += wg[g] * Ps(g, n, m) * Ps(g, nu, mu) * Ps(g, q, s);
+              G[((long long)nmi(n, m) * P + nmi(nu, mu)) * (2 * p + 1) + q] = (double)(2 * PI_L * acc);
+            }
+          }
+  }
+};
+
+// Y^s_q(b) for q <= Q (all s), b != 0
+void sph_harm_all(int Q, const double* b, std::vector<lcx>& Y) {
+  const ld bn = std::sqrt((ld)b[0] * b[0] + (ld)b[1] * b[1] + (ld)b[2] * b[2]);
+  const ld bxy = std::sqrt((ld)b[0] * b[0] + (ld)b[1] * b[1]);
+  const ld ct = b[2] / bn, st = bxy / bn;
+  const ld phi = bxy > 0 ? std::atan2((ld)b[1], (ld)b[0]) : 0.0L;
+  std::vector<ld> Pl((Q + 1) * (Q + 2) / 2);
+  legendre<ld>(Q, ct, st, Pl.data());
+  Y.assign((size_t)(Q + 1) * (Q + 1), lcx(0, 0));
+  for (int q = 0; q <= Q; q++)
+    for (int s = -q; s <= q; s++) {
+      ld v = Pl[tri(q, std::abs(s))];
+      if (s < 0 && (std::abs(s) & 1)) v = -v;
+      Y[nmi(q, s)] = v * std::exp(lcx(0, s * phi));
+    }
+}
+
+// Regular-to-regular coefficient of the addition theorem:
+//   R_nm(r + b) = sum_{nu mu} RR(n,m; nu,mu) R_{nu mu}(r),  R_nm = j_n(k|.|) Y^m_n,
+//   RR = 4 pi sum_q i^{nu + q - n} j_q(k|b|) Y^{m-mu}_q(b) G(n,m; nu,mu; q)
+// (from the plane-wave expansion of e^{i k.(r+b)}); with f = h_q instead of
+// j_q the outgoing-to-regular coefficient of h_n Y^m_n (|r| < |b|).
+// Matrix [n m][nu mu] for orders <= p.
+void addition_matrix(const Gaunt& G, int p, double k, const double* b, bool outgoing, std::vector<lcx>& M) {
+  const int Q = 2 * p, P = (p + 1) * (p + 1);
+  const ld bn = std::sqrt((ld)b[0] * b[0] + (ld)b[1] * b[1] + (ld)b[2] * b[2]);
+  std::vector<ld> jq(Q + 1), yq(Q + 1);
+  sph_j(Q, k * bn, jq.data());
+  if (outgoing) sph_y(Q, k * bn, yq.data());
+  std::vector<lcx> Y;
+  sph_harm_all(Q, b, Y);
+  M.assign((size_t)P * P, lcx(0, 0));
+  for (int n = 0; n <= p; n++)
+    for (int m = -n; m <= n; m++)
+      for (int nu = 0; nu <= p; nu++)
+        for (int mu = -nu; mu <= nu; mu++) {
+          const int s = m - mu;
+          lcx v = 0;
+          for (int q = std::abs(n - nu); q <= n + nu; q += 2) {
+            if (std::abs(s) > q) continue;
+            const lcx f = outgoing ? lcx(jq[q], yq[q]) : lcx(jq[q], 0);
+            v += (4 * PI_L * (ld)G.at(n, m, nu, mu, q)) * ipow_l(nu + q - n) * f * Y[nmi(q, s)];
+          }
+          M[(size_t)nmi(n, m) * P + nmi(nu, mu)] = v;
+        }
+}
+
+// ------------------------------------------------------------------ ladders
+// Derivatives of a regular expansion sum c_nm R_nm (order o) as expansions
+// of order o + 1, scaled by 1/k: dir 0: (d/dx + i d/dy), 1: (d/dx - i d/dy),
+// 2: d/dz.  From the ladder relations of the regular wave functions
+// (Condon-Shortley phase):
+//   d/dz R^m_n / k      = a(n-1,m) R^m_{n-1} - a(n,m) R^m_{n+1}
+//   (dx + i dy) R^m_n / k = b(n,m) R^{m+1}_{n+1} + b'(n,m) R^{m+1}_{n-1}
+//   (dx - i dy) R^m_n / k = -(c(n,m) R^{m-1}_{n+1} + c'(n,m) R^{m-1}_{n-1})
+ld lad_a(int n, int m) {
+  if (n < 0 || std::abs(m) > n) return 0;
+  return std::sqrt((ld)(n + 1 - m) * (n + 1 + m) / ((2.0L * n + 1) * (2.0L * n + 3)));
+}
+void ladder(int o, int dir, const cx* c, cx* out) {
+  const int Po = (o + 2) * (o + 2);
+  for (int i = 0; i < Po; i++) out[i] = 0;
+  auto put = [&](int n, int m, cx v) {
+    if (n >= 0 && n <= o + 1 && std::abs(m) <= n) out[nmi(n, m)] += v;
+  };
+  for (int n = 0; n <= o; n++)
+    for (int m = -n; m <= n; m++) {
+      const cx v = c[nmi(n, m)];
+      if (v == cx(0, 0)) continue;
+      if (dir == 2) {
+        put(n - 1, m, (double)lad_a(n - 1, m) * v);
+        put(n + 1, m, -(double)lad_a(n, m) * v);
+      } else if (dir == 0) {
+        const ld up = std::sqrt((ld)(n + m + 1) * (n + m + 2) / ((2.0L * n + 1) * (2.0L * n + 3)));
+        const ld dn2 = (ld)(n - m) * (n - m - 1);
+        const ld dn = (n >= 1 && dn2 > 0) ? std::sqrt(dn2 / ((2.0L * n - 1) * (2.0L * n + 1))) : 0.0L;
+        put(n + 1, m + 1, (double)up * v);
+        if (dn != 0) put(n - 1, m + 1, (double)dn * v);
+      } else {
+        const ld up = std::sqrt((ld)(n - m + 1) * (n - m + 2) / ((2.0L * n + 1) * (2.0L * n + 3)));
+        const ld dn2 = (ld)(n + m) * (n + m - 1);
+        const ld dn = (n >= 1 && dn2 > 0) ? std::sqrt(dn2 / ((2.0L * n - 1) * (2.0L * n + 1))) : 0.0L;
+        put(n + 1, m - 1, -(double)up * v);
+        if (dn != 0) put(n - 1, m - 1, -(double)dn * v);
+      }
+    }
+}
+
+// sum_nm c_nm j_n(k r) Y^m_n(d) for several coefficient vectors of order o at
+// offset d (vectors nv, stride P)
+void eval_regular(int o, double k, const double* dvec, int nv, const cx* const* cs, cx* res) {
+  const ld x = dvec[0], y = dvec[1], z = dvec[2];
+  const ld rxy = std::sqrt(x * x + y * y), r = std::sqrt(x * x + y * y + z * z);
+  const ld ct = r > 0 ? z / r : 1, st = r > 0 ? rxy / r : 0;
+  const lcx e1 = rxy > 0 ? lcx(x / rxy, y / rxy) : lcx(1, 0);
+  std::vector<ld> jn(o + 1), Pl((o + 1) * (o + 2) / 2);
+  sph_j(o, (ld)k * r, jn.data());
+  legendre<ld>(o, ct, st, Pl.data());
+  std::vector<lcx> acc(nv, lcx(0, 0));
+  lcx em = 1;
+  for (int m = 0; m <= o; m++) {
+    if (m > 0) em *= e1;
+    for (int n = m; n <= o; n++) {
+      const ld rad = jn[n] * Pl[tri(n, m)];
+      const lcx bp = rad * em;
+      const lcx bm = ((m & 1) ? -rad : rad) * std::conj(em);
+      for (int v = 0; v < nv; v++) {
+        const cx a = cs[v][nmi(n, m)];
+        acc[v] += lcx(a.real(), a.imag()) * bp;
+        if (m > 0) {
+          const cx b = cs[v][nmi(n, -m)];
+          acc[v] += lcx(b.real(), b.imag()) * bm;
+        }
+      }
+    }
+  }
+  for (int v = 0; v < nv; v++) res[v] = cx((double)acc[v].real(), (double)acc[v].imag());
+}
+
+// ------------------------------------------------------------------ densities
+// Reaction amplitude of one component at node kr, polarisation pol (0 TE,
+// 1 TM): the 1-D problem u'' + kz^2 u = -delta of Sec. 3.1 with the jumps
+// [[u]] = 0 and [[u' / beta]] = 0 (beta = mu for TE, eps ~ k^2 / mu for TM).
+// The reaction field in layer m is A_m e^{i kz (z - d_m)} (up-going,
+// referenced at the bottom interface) + B_m e^{-i kz (z - d_{m-1})}
+// (down-going, referenced at the top interface); no up-going wave in the
+// bottom half-space, no down-going one in the top half-space: 2L unknowns
+// for the 2L conditions.  The source contributes only the wave leaving it
+// in the component's direction, i/(2 kz') at the interface it meets.
+// Returns A (arriving up) or B (arriving down) of the target layer.
+lcx react_amp(const Medium& md, lcx kr, int lt, int ls, int up_t, int up_s, int pol) {
+  const int n = md.n, L = n - 1, N = 2 * L;
+  std::vector<lcx> kz(n), E(n, lcx(0, 0));
+  std::vector<ld> beta(n);
+  for (int m = 0; m < n; m++) {
+    kz[m] = kz_branch(md.k[m], kr);
+    beta[m] = pol ? (ld)md.k[m] * md.k[m] / md.mu[m] : (ld)md.mu[m];
+    if (m >= 1 && m <= L - 1) E[m] = std::exp(lcx(0, 1) * kz[m] * (ld)(md.d[m - 1] - md.d[m]));
+  }
+  auto iA = [&](int m) { return m <= L - 1 ? m : -1; };       // A_0..A_{L-1}
+  auto iB = [&](int m) { return m >= 1 ? L + m - 1 : -1; };   // B_1..B_L
+  std::vector<lcx> M((size_t)N * N, lcx(0, 0)), v(N, lcx(0, 0));
+  const lcx c = lcx(0, 1) / (2.0L * kz[ls]);
+  for (int j = 0; j < L; j++) {
+    const int up = j, lo = j + 1;
+    const int r0 = 2 * j, r1 = 2 * j + 1;
+    // upper layer at z = d_j
+    if (iA(up) >= 0) {
+      M[(size_t)r0 * N + iA(up)] += 1;
+      M[(size_t)r1 * N + iA(up)] += lcx(0, 1) * kz[up] / beta[up];
+    }
+    if (iB(up) >= 0) {
+      M[(size_t)r0 * N + iB(up)] += E[up];
+      M[(size_t)r1 * N + iB(up)] += -lcx(0, 1) * kz[up] * E[up] / beta[up];
+    }
+    // lower layer at z = d_j (subtracted)
+    if (iA(lo) >= 0) {
+      M[(size_t)r0 * N + iA(lo)] -= E[lo];
+      M[(size_t)r1 * N + iA(lo)] -= lcx(0, 1) * kz[lo] * E[lo] / beta[lo];
+    }
+    if (iB(lo) >= 0) {
+      M[(size_t)r0 * N + iB(lo)] -= 1;
+      M[(size_t)r1 * N + iB(lo)] -= -lcx(0, 1) * kz[lo] / beta[lo];
+    }
+    // the source's departing wave: value c and slope +-i kz' c at its interface
+    if (up_s && j == ls - 1) {  // leaves upward, meets d_j from below
+      v[r0] += c;
+      v[r1] += lcx(0, 1) * kz[ls] * c / beta[ls];
+    }
+    if (!up_s && j == ls) {  // leaves downward, meets d_j from above
+      v[r0] -= c;
+      v[r1] -= -lcx(0, 1) * kz[ls] * c / beta[ls];
+    }
+  }
+  // Gaussian elimination with partial pivoting
+  for (int col = 0; col < N; col++) {
+    int piv = col;
+    for (int r = col + 1; r < N; r++)
+      if (std::abs(M[(size_t)r * N + col]) > std::abs(M[(size_t)piv * N + col])) piv = r;
+    if (piv != col) {
+      for (int q = 0; q < N; q++) std::swap(M[(size_t)col * N + q], M[(size_t)piv * N + q]);
+      std::swap(v[col], v[piv]);
+    }
+    const lcx dg = M[(size_t)col * N + col];
+    for (int r = col + 1; r < N; r++) {
+      const lcx f = M[(size_t)r * N + col] / dg;
+      if (f == lcx(0, 0)) continue;
+      for (int q = col; q < N; q++) M[(size_t)r * N + q] -= f * M[(size_t)col * N + q];
+      v[r] -= f * v[col];
+    }
+  }
+  std::vector<lcx> x(N);
+  for (int r = N - 1; r >= 0; r--) {
+    lcx s = v[r];
+    for (int q = r + 1; q < N; q++) s -= M[(size_t)r * N + q] * x[q];
+    x[r] = s / M[(size_t)r * N + r];
+  }
+  return up_t ? x[iA(lt)] : x[iB(lt)];
+}
+
+// quantities of one quadrature node of one reaction component
+struct NodeV {
+  lcx kr, w, kzt, kzs;
+  lcx F[5];   // densities of the eight-term decomposition (slots sigma_1..sigma_5)
+  lcx FH[5];  // the same slots for the curl of the field (J6..J9 form)
+};
+
+// sigma_1..sigma_5 (Sec. 3.1, sigma_3 = 2 phi / k'_z - sigma_1) of a
+// component written with the TE and TM amplitudes, times -2i / k_t^2; and
+// the J6..J9 densities of the curl in the same slots.
+NodeV node_values(const Medium& md, const InstParams& ip, cd kr_, cd w_) {
+  NodeV q;
+  q.kr = lcx(kr_.x, kr_.y);
+  q.w = lcx(w_.x, w_.y);
+  q.kzt = kz_branch(ip.kt, q.kr);
+  q.kzs = kz_branch(ip.ks, q.kr);
+  const lcx cte = react_amp(md, q.kr, ip.lt, ip.ls, ip.up_t, ip.up_s, 0);
+  const lcx ctm = (ld)(md.mu[ip.lt] / md.mu[ip.ls]) * react_amp(md, q.kr, ip.lt, ip.ls, ip.up_t, ip.up_s, 1);
+  const ld e = ip.up_t ? 1 : -1, h = ip.up_s ? -1 : 1;
+  const ld k2 = (ld)ip.kt * ip.kt;
+  const lcx kk = q.kzt * q.kzs, kr = q.kr;
+  lcx S[5];
+  S[0] = k2 * cte - (e * h) * kk * ctm;
+  S[1] = -e * q.kzt * kr * ctm;
+  S[2] = k2 * cte + (e * h) * kk * ctm;
+  S[3] = h * q.kzs * kr * ctm;
+  S[4] = kr * kr * ctm;
+  for (int j = 0; j < 5; j++) q.F[j] = lcx(0, -2.0L / k2) * S[j];
+  const lcx et = e * cte * q.kzt, hs = h * ctm * q.kzs;
+  lcx SH[5] = {hs - et, kr * ctm, -(et + hs), kr * cte, lcx(0, 0)};
+  for (int j = 0; j < 5; j++) q.FH[j] = lcx(0, -2) * SH[j];
+  return q;
+}
+
+// ------------------------------------------------------------------ the run
+struct Run {
+  Plan pl;
+  Medium med;
+  double a = 0;     // end of the first contour piece
+  int nth = 1;
+  int n_rhs = 1;
+  int mode = 0;     // 0: A = G J; 1: curl of the field (H times mu_t); 2: gradient contraction
+  const cx* J = nullptr;
+  const cx* W = nullptr;  // mode 2: weights at the evaluation points
+  const double* src = nullptr;
+  const double* tgt = nullptr;
+  std::vector<cx> ME, LE;
+  std::vector<NodeV> nodes;
+  Gaunt gaunt;
+  cx* out = nullptr;       // modes 0, 1: [rhs][n_tgt][3]
+  double* gX = nullptr;    // mode 2: [n_tgt][3]
+  std::string err;
+
+  const InstParams& inst_of_s(int b) const { return pl.inst[pl.sbox[b].inst]; }
+  const InstParams& inst_of_t(int b) const { return pl.inst[pl.tbox[b].inst]; }
+  cx* me(int b) { return ME.data() + pl.sbox[b].me_off * n_rhs; }
+  cx* le(int b) { return LE.data() + pl.tbox[b].le_off * n_rhs; }
+
+  // ---------------- P2M: M[ch][nm] = sum_j q_j^ch j_n(k_s |d|) conj(Y^m_n(d)),
+  // d = image of the source - centre, channels (x + iy, x - iy, z)
+  void p2m() {
+    const std::vector<int>& lv = pl.p2m_leaves;
+    pfor((long long)lv.size(), nth, [&](long long i) {
+      const int b = lv[i];
+      const SrcBox& sb = pl.sbox[b];
+      const InstParams& ip = pl.inst[sb.inst];
+      const int p = ip.p, P = ip.P;
+      cx* M = me(b);
+      std::fill(M, M + (size_t)n_rhs * 3 * P, cx(0, 0));
+      std::vector<ld> jn(p + 1), Pl((p + 1) * (p + 2) / 2);
+      for (int t = sb.pt0; t < sb.pt1; t++) {
+        const int id = pl.src_perm[t];
+        const ld dx = src[3 * id] - sb.c[0], dy = src[3 * id + 1] - sb.c[1];
+        const ld dz = (ld)(ip.as * src[3 * id + 2] + ip.bs) - sb.c[2];
+        const ld rxy = std::sqrt(dx * dx + dy * dy), r = std::sqrt(rxy * rxy + dz * dz);
+        const ld ct = r > 0 ? dz / r : 1, st = r > 0 ? rxy / r : 0;
+        const lcx em1 = rxy > 0 ? lcx(dx / rxy, -dy / rxy) : lcx(1, 0);  // e^{-i phi}
+        sph_j(p, (ld)ip.ks * r, jn.data());
+        legendre<ld>(p, ct, st, Pl.data());
+        std::vector<lcx> basis(P);
+        lcx em = 1;
+        for (int m = 0; m <= p; m++) {
+          if (m > 0) em *= em1;
+          for (int n = m; n <= p; n++) {
+            const ld rad = jn[n] * Pl[tri(n, m)];
+            basis[nmi(n, m)] = rad * em;                                        // conj Y^m_n
+            if (m > 0) basis[nmi(n, -m)] = ((m & 1) ? -rad : rad) * std::conj(em);  // conj Y^{-m}_n
+          }
+        }
+        for (int r_ = 0; r_ < n_rhs; r_++) {
+          const cx* q = J + ((size_t)r_ * pl.n_src + id) * 3;
+          const cx ch[3] = {q[0] + cx(0, 1) * q[1], q[0] - cx(0, 1) * q[1], q[2]};
+          for (int c = 0; c < 3; c++)
+            for (int e = 0; e < P; e++) {
+              const cx bv((double)basis[e].real(), (double)basis[e].imag());
+              M[((size_t)r_ * 3 + c) * P + e] += ch[c] * bv;
+            }
+        }
+      }
+    });
+  }
+
+  // translation matrices of the M2M and L2L shifts, one per distinct
+  // (wavenumber, order, box size, octant): keyed by the planner's matrix slot
+  std::map<long long, std::vector<cx>> shifts;
+  void shift_matrices() {
+    std::map<long long, std::pair<int, int>> need;  // slot -> (box, kind 1 M2M / 2 L2L)
+    for (size_t b = 0; b < pl.sbox.size(); b++)
+      if (pl.sbox_m2m[b] >= 0) need.emplace(pl.sbox_m2m[b], std::make_pair((int)b, 1));
+    for (size_t b = 0; b < pl.tbox.size(); b++)
+      if (pl.tbox_l2l[b] >= 0) need.emplace(pl.tbox_l2l[b], std::make_pair((int)b, 2));
+    std::vector<std::pair<long long, std::pair<int, int>>> v(need.begin(), need.end());
+    std::vector<std::vector<cx>> mats(v.size());
+    pfor((long long)v.size(), nth, [&](long long i) {
+      const int b = v[i].second.first, kind = v[i].second.second;
+      double bvec[3];
+      double kk;
+      int p;
+      if (kind == 1) {
+        const SrcBox& c = pl.sbox[b];
+        const SrcBox& par = pl.sbox[c.parent];
+        for (int d = 0; d < 3; d++) bvec[d] = c.c[d] - par.c[d];
+        kk = pl.inst[c.inst].ks;
+        p = pl.inst[c.inst].p;
+      } else {
+        const TgtBox& c = pl.tbox[b];
+        const TgtBox& par = pl.tbox[c.parent];
+        for (int d = 0; d < 3; d++) bvec[d] = c.c[d] - par.c[d];
+        kk = pl.inst[c.inst].kt;
+        p = pl.inst[c.inst].p;
+      }
+      std::vector<lcx> RR;
+      addition_matrix(gaunt, p, kk, bvec, false, RR);
+      const int P = (p + 1) * (p + 1);
+      std::vector<cx>& M = mats[i];
+      M.assign((size_t)P * P, cx(0, 0));
+      // M2M: ME_parent[nm] = sum conj(RR(nm; nu mu)) ME_child[nu mu]  (M[nm][nu mu])
+      // L2L: LE_child[nm] += sum RR(nu mu; nm) LE_parent[nu mu]       (M[nm][nu mu])
+      for (int a1 = 0; a1 < P; a1++)
+        for (int a2 = 0; a2 < P; a2++) {
+          const lcx v2 = kind == 1 ? std::conj(RR[(size_t)a1 * P + a2]) : RR[(size_t)a2 * P + a1];
+          M[(size_t)a1 * P + a2] = cx((double)v2.real(), (double)v2.imag());
+        }
+    });
+    for (size_t i = 0; i < v.size(); i++) shifts[v[i].first] = std::move(mats[i]);
+  }
+
+  void matvec_add(const std::vector<cx>& M, int P, const cx* x, cx* y) {
+    for (int a1 = 0; a1 < P; a1++) {
+      cx s = 0;
+      const cx* row = M.data() + (size_t)a1 * P;
+      for (int a2 = 0; a2 < P; a2++) s += row[a2] * x[a2];
+      y[a1] += s;
+    }
+  }
+
+  void m2m() {
+    for (int l = (int)pl.m2m_parents.size() - 1; l >= 0; l--) {
+      const std::vector<int>& par = pl.m2m_parents[l];
+      pfor((long long)par.size(), nth, [&](long long i) {
+        const int b = par[i];
+        const SrcBox& sb = pl.sbox[b];
+        const int P = pl.inst[sb.inst].P;
+        cx* Mp = me(b);
+        std::fill(Mp, Mp + (size_t)n_rhs * 3 * P, cx(0, 0));
+        for (int c = sb.child0; c < sb.child0 + sb.nchild; c++) {
+          const std::vector<cx>& T = shifts.at(pl.sbox_m2m[c]);
+          const cx* Mc = me(c);
+          for (int v = 0; v < n_rhs * 3; v++) matvec_add(T, P, Mc + (size_t)v * P, Mp + (size_t)v * P);
+        }
+      });
+    }
+  }
+
+  void l2l() {
+    for (size_t l = 1; l < pl.l2l_children.size(); l++) {
+      const std::vector<int>& ch = pl.l2l_children[l];
+      pfor((long long)ch.size(), nth, [&](long long i) {
+        const int b = ch[i];
+        const TgtBox& tb = pl.tbox[b];
+        const int P = pl.inst[tb.inst].P;
+        const std::vector<cx>& T = shifts.at(pl.tbox_l2l[b]);
+        const cx* Lp = le(tb.parent);
+        cx* Lc = le(b);
+        for (int v = 0; v < n_rhs * 3; v++) matvec_add(T, P, Lp + (size_t)v * P, Lc + (size_t)v * P);
+      });
+    }
+  }
+
+  // ---------------- M2L
+  struct PairRec {
+    int t, s, off, cls;
+  };
+  std::vector<PairRec> pairs;  // every M2L pair of the plan
+  void collect_pairs() {
+    pairs.assign(pl.pair_src.size(), PairRec{-1, -1, -1, -1});
+    for (size_t bt = 0; bt + 1 < pl.bt_ptr.size(); bt++)
+      for (int qi = pl.bt_ptr[bt]; qi < pl.bt_ptr[bt + 1]; qi++) pairs[pl.bt_pairs[qi]].t = pl.bt_tbox[bt];
+    for (const M2LBlock& B : pl.blocks) {
+      const M2LClass& C = pl.cls[B.cls];
+      for (int o = 0; o < C.n_off; o++)
+        for (int q = pl.offr[B.offr0 + o]; q < pl.offr[B.offr0 + o + 1]; q++) {
+          pairs[q].s = pl.pair_src[q];
+          pairs[q].off = C.off0 + o;
+          pairs[q].cls = B.cls;
+        }
+    }
+  }
+
+  // reaction M2L tensor of one table case: for the eight (sigma, kappa)
+  // terms, V[term][nm][nu mu] = 4 pi s^{n+m+nu+mu} i^{1+n+|q|} (-i)^nu Ihat,
+  //   Ihat = sum_nodes w kr Z F_sigma P^m_n(b) P^mu_nu(b') J_|q|(kr rho),
+  // q = kappa - m + mu, cos b = kz/k, sin b = kr/k on the target side and
+  // likewise on the source side; the phase (e^{i phi})^q of the pair is
+  // applied by the caller
+  static constexpr int NTERM = 8;
+  static int term_sigma(int t) { static const int s[NTERM] = {0, 2, 2, 1, 1, 3, 3, 4}; return s[t]; }
+  static int term_kappa(int t) { static const int k[NTERM] = {0, 2, -2, 1, -1, 1, -1, 0}; return k[t]; }
+  void reaction_table(const TabCase& tc, std::vector<cx>& V) {
+    const InstParams& ip = pl.inst[tc.inst];
+    const int p = ip.p, P = ip.P, Q = 2 * p + 2, nt = (p + 1) * (p + 2) / 2;
+    // accumulators [term][nm][nu mu] as separate real and imaginary planes
+    std::vector<double> ar((size_t)NTERM * P * P, 0.0), ai((size_t)NTERM * P * P, 0.0);
+    const ld tz = ip.up_t ? (ld)tc.zt_orig - med.d[ip.lt] : (ld)med.d[ip.lt - 1] - tc.zt_orig;
+    const ld uz = ip.up_s ? (ld)med.d[ip.ls - 1] - tc.zs_orig : (ld)tc.zs_orig - med.d[ip.ls];
+    std::vector<lcx> Pt(nt), Ps(nt), Jq(Q + 1);
+    std::vector<ld> Jr(Q + 1);
+    std::vector<double> are(P), aim(P), bre(P), bim(P), cre(P), cim(P);
+    for (int i = tc.node0; i < tc.node0 + tc.nnode; i++) {
+      const NodeV& nd = nodes[i];
+      const lcx g = nd.w * nd.kr * std::exp(lcx(0, 1) * (tz * nd.kzt + uz * nd.kzs));
+      legendre<lcx>(p, nd.kzt / (ld)ip.kt, nd.kr / (ld)ip.kt, Pt.data());
+      legendre<lcx>(p, nd.kzs / (ld)ip.ks, nd.kr / (ld)ip.ks, Ps.data());
+      if (nd.kr.imag() == 0) {
+        bessel_J_real(Q, nd.kr.real() * (ld)tc.rho, Jr.data());
+        for (int q = 0; q <= Q; q++) Jq[q] = Jr[q];
+      } else {
+        bessel_J(Q, nd.kr * (ld)tc.rho, Jq.data());
+      }
+      // P^m_n with the (-1)^m of negative orders, target and source side
+      for (int n = 0; n <= p; n++)
+        for (int m = -n; m <= n; m++) {
+          const ld sg = (m < 0 && (std::abs(m) & 1)) ? -1 : 1;
+          const lcx v = sg * Pt[tri(n, std::abs(m))], w = sg * Ps[tri(n, std::abs(m))];
+          are[nmi(n, m)] = (double)v.real();
+          aim[nmi(n, m)] = (double)v.imag();
+          bre[nmi(n, m)] = (double)w.real();
+          bim[nmi(n, m)] = (double)w.imag();
+        }
+      for (int t = 0; t < NTERM; t++) {
+        const lcx gf = g * nd.F[term_sigma(t)];
+        const int kap = term_kappa(t);
+        for (int m = -p; m <= p; m++) {
+          // c[nu mu] = P^mu_nu(b') J_|kappa - m + mu|
+          for (int nu = 0; nu <= p; nu++)
+            for (int mu = -nu; mu <= nu; mu++) {
+              const lcx jv = Jq[std::abs(kap - m + mu)];
+              const double jr = (double)jv.real(), ji = (double)jv.imag();
+              const int e = nmi(nu, mu);
+              cre[e] = bre[e] * jr - bim[e] * ji;
+              cim[e] = bre[e] * ji + bim[e] * jr;
+            }
+          for (int n = std::abs(m); n <= p; n++) {
+            const lcx ga = gf * lcx(are[nmi(n, m)], aim[nmi(n, m)]);
+            const double gr = (double)ga.real(), gi = (double)ga.imag();
+            double* rr = ar.data() + ((size_t)t * P + nmi(n, m)) * P;
+            double* ri = ai.data() + ((size_t)t * P + nmi(n, m)) * P;
+            for (int e = 0; e < P; e++) {
+              rr[e] += gr * cre[e] - gi * cim[e];
+              ri[e] += gr * cim[e] + gi * cre[e];
+            }
+          }
+        }
+      }
+    }
+    V.assign((size_t)NTERM * P * P, cx(0, 0));
+    for (int t = 0; t < NTERM; t++) {
+      const int kap = term_kappa(t);
+      for (int n = 0; n <= p; n++)
+        for (int m = -n; m <= n; m++)
+          for (int nu = 0; nu <= p; nu++)
+            for (int mu = -nu; mu <= nu; mu++) {
+              const int q = kap - m + mu;
+              const ld sg = ((n + m + nu + mu) & 1) ? (ld)ip.sgn : 1.0L;
+              const lcx f = (4 * PI_L * sg) * ipow_l(1 + n + std::abs(q)) * ipow_l(-nu);
+              const size_t e = ((size_t)t * P + nmi(n, m)) * P + nmi(nu, mu);
+              const lcx v = f * lcx(ar[e], ai[e]);
+              V[e] = cx((double)v.real(), (double)v.imag());
+            }
+    }
+  }
+
+  // the spin-basis M2L: output channel (+, -, z), its three terms (term,
+  // input channel, weight) -- the eight-term tensor of Sec. 3.3 acting on
+  // (m_x + i m_y, m_x - i m_y, m_z)
+  struct Slot {
+    int term, ch;
+    double wgt;
+  };
+  static const Slot* slots(int ot) {
+    static const Slot S[3][3] = {{{0, 0, 0.5}, {1, 1, -0.5}, {3, 2, 1.0}},
+                                 {{0, 1, 0.5}, {2, 0, -0.5}, {4, 2, 1.0}},
+                                 {{5, 1, 0.5}, {6, 0, 0.5}, {7, 2, 1.0}}};
+    return S[ot];
+  }
+
+  void m2l() {
+    collect_pairs();
+    const size_t npair = pairs.size();
+    if (npair == 0) return;
+    // output of every pair, then summed per target
+    std::vector<cx> Y;
+    std::vector<long long> ybase(npair + 1, 0);
+    for (size_t q = 0; q < npair; q++) ybase[q + 1] = ybase[q] + (long long)n_rhs * 3 * pl.cls[pairs[q].cls].P;
+    Y.assign((size_t)ybase[npair], cx(0, 0));
+    // group the pairs: reaction pairs by table case, free pairs by matrix slot
+    std::map<long long, int> case_of_mat;
+    for (size_t c = 0; c < pl.cases.size(); c++) case_of_mat[pl.cases[c].mat] = (int)c;
+    std::map<long long, std::vector<int>> groups;  // key: reaction case id, or -(slot+1) for free
+    for (size_t q = 0; q < npair; q++) {
+      const M2LClass& C = pl.cls[pairs[q].cls];
+      const M2LOffset& O = pl.offs[pairs[q].off];
+      if (C.nblk == 3) {
+        auto it = case_of_mat.find(O.mat[0]);
+        if (it == case_of_mat.end()) {
+          err = "internal: reaction offset without a table case";
+          return;
+        }
+        groups[it->second].push_back((int)q);
+      } else {
+        groups[-(O.mat[0] + 1)].push_back((int)q);
+      }
+    }
+    std::vector<std::pair<long long, std::vector<int>>> gv(groups.begin(), groups.end());
+    std::atomic<int> bad{0};
+    pfor((long long)gv.size(), nth, [&](long long gi) {
+      const std::vector<int>& qs = gv[gi].second;
+      const PairRec& r0 = pairs[qs[0]];
+      const M2LClass& C = pl.cls[r0.cls];
+      const InstParams& ip = pl.inst[C.inst];
+      const int p = ip.p, P = ip.P;
+      if (gv[gi].first >= 0) {
+        const TabCase& tc = pl.cases[gv[gi].first];
+        std::vector<cx> V;
+        reaction_table(tc, V);
+        std::vector<cx> eph(4 * p + 9);
+        for (int q : qs) {
+          const PairRec& pr = pairs[q];
+          const TgtBox& tb = pl.tbox[pr.t];
+          const SrcBox& sb = pl.sbox[pr.s];
+          const double dx = tb.c[0] - sb.c[0], dy = tb.c[1] - sb.c[1];
+          const double rho = std::sqrt(dx * dx + dy * dy);
+          // the case's geometry is that of the pair (box centres mapped back
+          // to physical coordinates)
+          const double zt = ip.at * (tb.c[2] - ip.bt), zs = ip.as * (sb.c[2] - ip.bs);
+          const double sc = 1e-9 * std::max(1.0, rho);
+          if (std::fabs(rho - tc.rho) > sc || std::fabs(zt - tc.zt_orig) > 1e-9 || std::fabs(zs - tc.zs_orig) > 1e-9)
+            bad = 1;
+          const double phi = std::atan2(dy, dx);
+          for (int e = 0; e < (int)eph.size(); e++) eph[e] = std::exp(cx(0, (e - (2 * p + 4)) * phi));
+          const int po = pl.offs[pr.off].pord;
+          const cx* X = me(pr.s);
+          cx* y = Y.data() + ybase[q];
+          // e^{i q phi} = e^{-i m phi} e^{i (kappa + mu) phi}: the source vectors
+          // are multiplied by e^{i (kappa + mu) phi} once per term
+          std::vector<double> xr((size_t)9 * P), xi((size_t)9 * P);  // per (output, slot)
+          for (int r_ = 0; r_ < n_rhs; r_++) {
+            for (int ot = 0; ot < 3; ot++)
+              for (int z = 0; z < 3; z++) {
+                const Slot& sl = slots(ot)[z];
+                const int kap = term_kappa(sl.term);
+                const cx* xv = X + ((size_t)r_ * 3 + sl.ch) * P;
+                for (int nu = 0; nu <= po; nu++)
+                  for (int mu = -nu; mu <= nu; mu++) {
+                    const cx v = sl.wgt * eph[kap + mu + 2 * p + 4] * xv[nmi(nu, mu)];
+                    xr[(size_t)(3 * ot + z) * P + nmi(nu, mu)] = v.real();
+                    xi[(size_t)(3 * ot + z) * P + nmi(nu, mu)] = v.imag();
+                  }
+              }
+            const int Po = (po + 1) * (po + 1);
+            for (int ot = 0; ot < 3; ot++)
+              for (int n = 0; n <= po; n++)
+                for (int m = -n; m <= n; m++) {
+                  double sr = 0, si = 0;
+                  for (int z = 0; z < 3; z++) {
+                    const int t = slots(ot)[z].term;
+                    const cx* row = V.data() + ((size_t)t * P + nmi(n, m)) * P;
+                    const double* pr_ = xr.data() + (size_t)(3 * ot + z) * P;
+                    const double* pi_ = xi.data() + (size_t)(3 * ot + z) * P;
+                    for (int e = 0; e < Po; e++) {
+                      sr += row[e].real() * pr_[e] - row[e].imag() * pi_[e];
+                      si += row[e].real() * pi_[e] + row[e].imag() * pr_[e];
+                    }
+                  }
+                  y[((size_t)r_ * 3 + ot) * P + nmi(n, m)] = eph[-m + 2 * p + 4] * cx(sr, si);
+                }
+          }
+        }
+      } else {
+        // free space: L = i k (S|R)(c_t - c_s) M per channel
+        const PairRec& pr = pairs[qs[0]];
+        double bvec[3];
+        for (int d = 0; d < 3; d++) bvec[d] = pl.tbox[pr.t].c[d] - pl.sbox[pr.s].c[d];
+        std::vector<lcx> SR;
+        addition_matrix(gaunt, p, ip.kt, bvec, true, SR);
+        std::vector<cx> T((size_t)P * P);
+        const lcx ik(0, ip.kt);
+        // T[nm][nu mu] = i k SR(nu mu; nm)
+        for (int a1 = 0; a1 < P; a1++)
+          for (int a2 = 0; a2 < P; a2++) {
+            const lcx v = ik * SR[(size_t)a2 * P + a1];
+            T[(size_t)a1 * P + a2] = cx((double)v.real(), (double)v.imag());
+          }
+        for (int q : qs) {
+          const PairRec& pq = pairs[q];
+          for (int d = 0; d < 3; d++)
+            if (std::fabs(pl.tbox[pq.t].c[d] - pl.sbox[pq.s].c[d] - bvec[d]) > 1e-9 * std::max(1.0, std::fabs(bvec[d])))
+              bad = 1;
+          const int po = pl.offs[pq.off].pord, Po = (po + 1) * (po + 1);
+          const cx* X = me(pq.s);
+          cx* y = Y.data() + ybase[q];
+          for (int v = 0; v < n_rhs * 3; v++)
+            for (int a1 = 0; a1 < Po; a1++) {
+              cx s = 0;
+              for (int a2 = 0; a2 < Po; a2++) s += T[(size_t)a1 * P + a2] * X[(size_t)v * P + a2];
+              y[(size_t)v * P + a1] = s;
+            }
+        }
+      }
+    });
+    if (bad) {
+      err = "internal: an M2L pair's geometry differs from its group's";
+      return;
+    }
+    // per target: its pairs, in plan order
+    std::vector<std::vector<int>> by_t(pl.tbox.size());
+    for (size_t q = 0; q < npair; q++) by_t[pairs[q].t].push_back((int)q);
+    pfor((long long)by_t.size(), nth, [&](long long t) {
+      if (by_t[t].empty()) return;
+      const int P = pl.inst[pl.tbox[t].inst].P;
+      cx* L = le((int)t);
+      for (int q : by_t[t]) {
+        const cx* y = Y.data() + ybase[q];
+        for (int e = 0; e < n_rhs * 3 * P; e++) L[e] += y[e];
+      }
+    });
+  }
+
+  // ---------------- L2P
+  // field expansion of a target box for one rhs: the LE itself (reaction) or
+  // U + grad div U / k^2 of order p + 2 (free space, the dyadic operator of
+  // Sec. 2 applied to the local expansion); returns its order
+  int field_expansion(int b, int r_, std::vector<cx> ch[3]) {
+    const TgtBox& tb = pl.tbox[b];
+    const InstParams& ip = pl.inst[tb.inst];
+    const int p = ip.p, P = ip.P;
+    const cx* L = le(b) + (size_t)r_ * 3 * P;
+    if (ip.kind == 1) {
+      for (int c = 0; c < 3; c++) ch[c].assign(L + (size_t)c * P, L + (size_t)(c + 1) * P);
+      return p;
+    }
+    const int Pe = (p + 3) * (p + 3);
+    std::vector<cx> U[3];
+    for (int c = 0; c < 3; c++) {
+      U[c].assign((size_t)Pe, cx(0, 0));
+      std::copy(L + (size_t)c * P, L + (size_t)(c + 1) * P, U[c].begin());
+    }
+    // div U (order p + 1): (D+ U_- + D- U_+) / 2 + Dz U_z, times k
+    std::vector<cx> t1(Pe), t2(Pe), t3(Pe), dv(Pe, cx(0, 0));
+    ladder(p, 0, U[1].data(), t1.data());
+    ladder(p, 1, U[0].data(), t2.data());
+    ladder(p, 2, U[2].data(), t3.data());
+    const int P1 = (p + 2) * (p + 2);
+    for (int e = 0; e < P1; e++) dv[e] = ip.kt * (0.5 * (t1[e] + t2[e]) + t3[e]);
+    for (int c = 0; c < 3; c++) {
+      std::vector<cx> g(Pe);
+      ladder(p + 1, c, dv.data(), g.data());
+      ch[c].assign((size_t)Pe, cx(0, 0));
+      for (int e = 0; e < Pe; e++) ch[c][e] = U[c][e] + (1.0 / ip.kt) * g[e];
+    }
+    return p + 2;
+  }
+
+  void l2p() {
+    for (size_t ii = 0; ii < pl.l2p_leaves.size(); ii++) {
+      const std::vector<int>& lv = pl.l2p_leaves[ii];
+      pfor((long long)lv.size(), nth, [&](long long i) {
+        const int b = lv[i];
+        const TgtBox& tb = pl.tbox[b];
+        const InstParams& ip = pl.inst[tb.inst];
+        for (int r_ = 0; r_ < n_rhs; r_++) {
+          std::vector<cx> ch[3];
+          const int o = field_expansion(b, r_, ch);
+          std::vector<cx> dch[9];
+          if (mode != 0)
+            for (int c = 0; c < 3; c++)
+              for (int dir = 0; dir < 3; dir++) {
+                dch[3 * c + dir].assign((size_t)(o + 2) * (o + 2), cx(0, 0));
+                ladder(o, dir, ch[c].data(), dch[3 * c + dir].data());
+              }
+          for (int t = tb.pt0; t < tb.pt1; t++) {
+            const int id = pl.tgt_perm[t];
+            double dvec[3] = {tgt[3 * id] - tb.c[0], tgt[3 * id + 1] - tb.c[1],
+                              ip.at * tgt[3 * id + 2] + ip.bt - tb.c[2]};
+            if (mode == 0) {
+              const cx* cs[3] = {ch[0].data(), ch[1].data(), ch[2].data()};
+              cx v[3];
+              eval_regular(o, ip.kt, dvec, 3, cs, v);
+              cx* A = out + ((size_t)r_ * pl.n_tgt + id) * 3;
+              A[0] += 0.5 * (v[0] + v[1]);
+              A[1] += (v[0] - v[1]) / cx(0, 2);
+              A[2] += v[2];
+              continue;
+            }
+            const cx* cs[9];
+            for (int q = 0; q < 9; q++) cs[q] = dch[q].data();
+            cx v[9];
+            eval_regular(o + 1, ip.kt, dvec, 9, cs, v);
+            // derivatives of the spin channels: D+ and D- times k, d/dz of the
+            // physical coordinate (d zhat / dz = a_t)
+            cx dB[3][3];  // [direction x, y, z][spin channel]
+            for (int c = 0; c < 3; c++) {
+              const cx dp = ip.kt * v[3 * c], dm = ip.kt * v[3 * c + 1], dzv = ip.kt * ip.at * v[3 * c + 2];
+              dB[0][c] = 0.5 * (dp + dm);
+              dB[1][c] = (dp - dm) / cx(0, 2);
+              dB[2][c] = dzv;
+            }
+            cx jac[3][3];  // [direction][cartesian component]
+            for (int a = 0; a < 3; a++) {
+              jac[a][0] = 0.5 * (dB[a][0] + dB[a][1]);
+              jac[a][1] = (dB[a][0] - dB[a][1]) / cx(0, 2);
+              jac[a][2] = dB[a][2];
+            }
+            if (mode == 1) {
+              cx* H = out + ((size_t)r_ * pl.n_tgt + id) * 3;
+              H[0] += jac[1][2] - jac[2][1];
+              H[1] += jac[2][0] - jac[0][2];
+              H[2] += jac[0][1] - jac[1][0];
+            } else {
+              const cx* w = W + ((size_t)r_ * pl.n_tgt + id) * 3;
+              for (int a = 0; a < 3; a++) gX[3 * id + a] += (w[0] * jac[a][0] + w[1] * jac[a][1] + w[2] * jac[a][2]).real();
+            }
+          }
+        }
+      });
+    }
+  }
+
+  // ---------------- free-space near field
+  void p2p() {
+    for (const std::vector<int>& items : pl.p2p_tboxes) {
+      std::vector<int> leaves;
+      for (size_t i = 0; i < items.size(); i += 2)
+        if (items[i + 1] == 0) leaves.push_back(items[i]);
+      pfor((long long)leaves.size(), nth, [&](long long i) {
+        const int b = leaves[i];
+        const TgtBox& tb = pl.tbox[b];
+        const ld k = pl.inst[tb.inst].kt;
+        for (int t = tb.pt0; t < tb.pt1; t++) {
+          const int id = pl.tgt_perm[t];
+          for (int li = tb.p2p0; li < tb.p2p1; li++) {
+            const SrcBox& sb = pl.sbox[pl.p2p_list[li]];
+            for (int s = sb.pt0; s < sb.pt1; s++) {
+              const int sid = pl.src_perm[s];
+              const ld R[3] = {(ld)tgt[3 * id] - src[3 * sid], (ld)tgt[3 * id + 1] - src[3 * sid + 1],
+                               (ld)tgt[3 * id + 2] - src[3 * sid + 2]};
+              const ld r = std::sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+              if (r == 0) continue;
+              const ld u[3] = {R[0] / r, R[1] / r, R[2] / r};
+              const lcx g = std::exp(lcx(0, k * r)) / (4 * PI_L * r);
+              const ld x = 1 / (k * r);
+              // G = g [(1 + i x - x^2) I + (-1 - 3 i x + 3 x^2) u u^T]
+              const lcx fa = g * lcx(1 - x * x, x), fb = g * lcx(-1 + 3 * x * x, -3 * x);
+              const lcx gp = g * lcx(-1 / r, k);  // dg/dr
+              for (int r_ = 0; r_ < n_rhs; r_++) {
+                const cx* q = J + ((size_t)r_ * pl.n_src + sid) * 3;
+                const lcx qv[3] = {lcx(q[0].real(), q[0].imag()), lcx(q[1].real(), q[1].imag()),
+                                   lcx(q[2].real(), q[2].imag())};
+                if (mode == 0) {
+                  const lcx uq = u[0] * qv[0] + u[1] * qv[1] + u[2] * qv[2];
+                  cx* A = out + ((size_t)r_ * pl.n_tgt + id) * 3;
+                  for (int c = 0; c < 3; c++) {
+                    const lcx v = fa * qv[c] + fb * u[c] * uq;
+                    A[c] += cx((double)v.real(), (double)v.imag());
+                  }
+                } else if (mode == 1) {
+                  // curl of g q: grad g x q
+                  const lcx gr[3] = {gp * u[0], gp * u[1], gp * u[2]};
+                  const lcx h[3] = {gr[1] * qv[2] - gr[2] * qv[1], gr[2] * qv[0] - gr[0] * qv[2],
+                                    gr[0] * qv[1] - gr[1] * qv[0]};
+                  cx* H = out + ((size_t)r_ * pl.n_tgt + id) * 3;
+                  for (int c = 0; c < 3; c++) H[c] += cx((double)h[c].real(), (double)h[c].imag());
+                } else {
+                  // d/dx_alpha of w^T G q at the evaluation point, G = fa I + fb u u^T
+                  const cx* wv = W + ((size_t)r_ * pl.n_tgt + id) * 3;
+                  const lcx w[3] = {lcx(wv[0].real(), wv[0].imag()), lcx(wv[1].real(), wv[1].imag()),
+                                    lcx(wv[2].real(), wv[2].imag())};
+                  const lcx dfa = gp * lcx(1 - x * x, x) + g * (lcx(2 * x * x, -x) / r);
+                  const lcx dfb = gp * lcx(-1 + 3 * x * x, -3 * x) + g * (lcx(-6 * x * x, 3 * x) / r);
+                  const lcx ws = w[0] * qv[0] + w[1] * qv[1] + w[2] * qv[2];
+                  const lcx wu = w[0] * u[0] + w[1] * u[1] + w[2] * u[2];
+                  const lcx us = u[0] * qv[0] + u[1] * qv[1] + u[2] * qv[2];
+                  for (int al = 0; al < 3; al++) {
+                    // d u_c / d x_al = (delta - u_al u_c) / r
+                    const lcx v = u[al] * (dfa * ws + dfb * wu * us) +
+                                  fb / r * ((w[al] - u[al] * wu) * us + wu * (qv[al] - u[al] * us));
+                    gX[3 * id + al] += (double)v.real();
+                  }
+                }
+              }
+            }
+          }
+        }
+      });
+    }
+  }
+
+  // ---------------- direct reaction pairs (S2T): the component's Sommerfeld
+  // integrals at the pair itself, combined like the M2L tensor (order 0)
+  void s2t() {
+    // target leaves with direct pairs, per instance
+    std::map<int, std::vector<int>> by_inst;
+    for (size_t i = 0; i < pl.s2t_items.size(); i += 2)
+      if (pl.s2t_items[i + 1] == 0) by_inst[pl.tbox[pl.s2t_items[i]].inst].push_back(pl.s2t_items[i]);
+    for (auto& kv : by_inst) {
+      const InstParams& ip = pl.inst[kv.first];
+      const std::vector<int>& leaves = kv.second;
+      const double dls = ip.up_s ? med.d[ip.ls - 1] : med.d[ip.ls];
+      pfor((long long)leaves.size(), nth, [&](long long i) {
+        const int b = leaves[i];
+        const TgtBox& tb = pl.tbox[b];
+        for (int t = tb.pt0; t < tb.pt1; t++) {
+          const int id = pl.tgt_perm[t];
+          const double zt = tgt[3 * id + 2];
+          const double tzv = ip.up_t ? zt - med.d[ip.lt] : med.d[ip.lt - 1] - zt;
+          std::vector<lcx> accp(n_rhs, 0), accm(n_rhs, 0), accz(n_rhs, 0);
+          for (int li = tb.p2p0; li < tb.p2p1; li++) {
+            const SrcBox& sb = pl.sbox[pl.p2p_list[li]];
+            for (int s = sb.pt0; s < sb.pt1; s++) {
+              const int sid = pl.src_perm[s];
+              const double dx = tgt[3 * id] - src[3 * sid], dy = tgt[3 * id + 1] - src[3 * sid + 1];
+              const double uzv = ip.up_s ? dls - src[3 * sid + 2] : src[3 * sid + 2] - dls;
+              const double rho = std::sqrt(dx * dx + dy * dy);
+              const double kcut = a + LM_S2T_DIGITS / (tzv + uzv);
+              const ld cph = rho > 0 ? dx / (ld)rho : 1, sph = rho > 0 ? dy / (ld)rho : 0;
+              // I[sigma][n] = sum_nodes w kr Z F_sigma J_n(kr rho), n = 0..2
+              lcx I[5][3];
+              for (int s5 = 0; s5 < 5; s5++)
+                for (int n = 0; n < 3; n++) I[s5][n] = 0;
+              for (int ni = ip.s2t0; ni < ip.s2t0 + ip.s2tn; ni++) {
+                const NodeV& nd = nodes[ni];
+                if (nd.kr.imag() == 0 && nd.kr.real() > kcut) continue;
+                lcx jb[3];
+                if (nd.kr.imag() == 0) {
+                  ld jr[3];
+                  bessel_J_real(2, nd.kr.real() * (ld)rho, jr);
+                  for (int n = 0; n < 3; n++) jb[n] = jr[n];
+                } else {
+                  bessel_J(2, nd.kr * (ld)rho, jb);
+                }
+                const lcx base = nd.w * nd.kr * std::exp(lcx(0, 1) * ((ld)tzv * nd.kzt + (ld)uzv * nd.kzs));
+                const lcx* F = mode == 1 ? nd.FH : nd.F;
+                for (int s5 = 0; s5 < 5; s5++)
+                  for (int n = 0; n < 3; n++) I[s5][n] += base * F[s5] * jb[n];
+              }
+              // W(kappa, sigma) = e^{i kappa phi} i^{1+|kappa|} I_sigma,|kappa|
+              const lcx eph(cph, sph);
+              auto Wf = [&](int kap, int sg) {
+                const int ak = std::abs(kap);
+                lcx ph = 1;
+                for (int j = 0; j < ak; j++) ph *= kap > 0 ? eph : std::conj(eph);
+                return ph * ipow_l(1 + ak) * I[sg][ak];
+              };
+              {
+                for (int r_ = 0; r_ < n_rhs; r_++) {
+                  const cx* q = J + ((size_t)r_ * pl.n_src + sid) * 3;
+                  const lcx jx(q[0].real(), q[0].imag()), jy(q[1].real(), q[1].imag()), jz(q[2].real(), q[2].imag());
+                  const lcx up = jx + lcx(0, 1) * jy, um = jx - lcx(0, 1) * jy;
+                  if (mode == 0) {
+                    accp[r_] += 0.5L * Wf(0, 0) * up - 0.5L * Wf(2, 2) * um + Wf(1, 1) * jz;
+                    accm[r_] += 0.5L * Wf(0, 0) * um - 0.5L * Wf(-2, 2) * up + Wf(-1, 1) * jz;
+                    accz[r_] += 0.5L * Wf(1, 3) * um + 0.5L * Wf(-1, 3) * up + Wf(0, 4) * jz;
+                  } else {
+                    accp[r_] += 0.5L * Wf(0, 0) * up - 0.5L * Wf(2, 2) * um + Wf(1, 1) * jz;
+                    accm[r_] -= 0.5L * Wf(0, 0) * um - 0.5L * Wf(-2, 2) * up + Wf(-1, 1) * jz;
+                    accz[r_] += 0.5L * Wf(-1, 3) * up - 0.5L * Wf(1, 3) * um;
+                  }
+                }
+              }
+            }
+          }
+          {
+            const ld f = 1 / (4 * PI_L);
+            for (int r_ = 0; r_ < n_rhs; r_++) {
+              cx* A = out + ((size_t)r_ * pl.n_tgt + id) * 3;
+              const lcx ax = f * 0.5L * (accp[r_] + accm[r_]);
+              const lcx ay = f * (accp[r_] - accm[r_]) / lcx(0, 2);
+              const lcx az = f * accz[r_];
+              A[0] += cx((double)ax.real(), (double)ax.imag());
+              A[1] += cx((double)ay.real(), (double)ay.imag());
+              A[2] += cx((double)az.real(), (double)az.imag());
+            }
+          }
+        }
+      });
+    }
+  }
+
+  int run() {
+    const int pmax = std::max(pl.p, pl.pf);
+    // node densities
+    nodes.resize(pl.node_kr.size());
+    pfor((long long)nodes.size(), nth, [&](long long i) {
+      nodes[i] = node_values(med, pl.inst[pl.node_inst[i]], pl.node_kr[i], pl.node_w[i]);
+    });
+    gaunt.build(pmax);
+    ME.assign((size_t)std::max(1LL, pl.me_size * n_rhs), cx(0, 0));
+    LE.assign((size_t)std::max(1LL, pl.le_size * n_rhs), cx(0, 0));
+    if (pl.n_src == 0 || pl.n_tgt == 0) return 0;
+    shift_matrices();
+    p2m();
+    m2m();
+    m2l();
+    if (!err.empty()) return LM_EHIP;
+    l2l();
+    l2p();
+    p2p();
+    s2t();
+    return err.empty() ? 0 : LM_EHIP;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+// Runs the FMM on the host for the given medium, parameters and points
+// (same arguments and plan as lm_build_batch + lm_evaluate / lm_evaluate_h).
+// J: complex128 [n_rhs][n_src][3] (interleaved re, im); mode 0: out = A,
+// complex128 [n_rhs][n_tgt][3]; mode 1: out = H (magnetic field, Faraday's
+// law, the 1/mu of the target's layer applied).  n_threads host threads.
+// Returns 0 or a negative LM_* code with a message in err.
+int lmc_run(int n_layers, const double* d, const double* k, const double* mu, const lm_params* prm, int n_geom,
+            const int64_t* src_off, const double* src, const int64_t* tgt_off, const double* tgt, int n_rhs,
+            const double* J, int mode, double* out, int n_threads, char* err, int errlen) {
+  auto fail = [&](int code, const std::string& m) {
+    if (err && errlen > 0) snprintf(err, errlen, "%s", m.c_str());
+    return code;
+  };
+  if (n_layers < 1 || n_layers > LM_MAXL || !k || !prm || n_geom < 1 || n_rhs < 1 || !src_off || !tgt_off ||
+      (mode != 0 && mode != 1))
+    return fail(LM_EINVAL, "invalid arguments");
+  Run R;
+  Medium& m = R.med;
+  m.n = n_layers;
+  for (int l = 0; l < n_layers; l++) {
+    m.k[l] = k[l];
+    m.mu[l] = mu ? mu[l] : 1.0;
+    m.mu_one = m.mu_one && m.mu[l] == 1.0;
+    m.kmax = std::max(m.kmax, k[l]);
+  }
+  for (int l = 0; l < n_layers - 1; l++) m.d[l] = d[l];
+  PlanParams q;
+  q.p = prm->p;
+  q.p_free = prm->p_free;
+  q.free_depth = prm->free_depth;
+  q.max_depth = prm->max_depth;
+  q.gamma1_panels = prm->gamma1_panels > 0 ? prm->gamma1_panels : 4;
+  q.contour_a = prm->contour_a;
+  q.tail_digits = prm->tail_digits > 0 ? prm->tail_digits : 60.0;
+  q.components = prm->components;
+  q.m2l_adapt = prm->m2l_adapt;
+  q.m2l_margin = prm->m2l_margin;
+  q.react_s2t = prm->react_s2t;
+  const int64_t ns = src_off[n_geom], nt = tgt_off[n_geom];
+  for (int pass = 0; pass < 2; pass++) {
+    const double* x = pass ? tgt : src;
+    const int64_t n = pass ? nt : ns;
+    for (int64_t i = 0; i < n; i++)
+      for (int l = 0; l < n_layers - 1; l++)
+        if (std::fabs(x[3 * i + 2] - m.d[l]) <= 1e-12 * std::max(1.0, std::fabs(m.d[l])))
+          return fail(LM_EDOMAIN, "a point lies on an interface");
+  }
+  std::string msg = lm_make_plan_multi(R.pl, m, q, n_geom, src_off, src, tgt_off, tgt);
+  if (!msg.empty()) return fail(LM_EDOMAIN, msg);
+  R.a = q.contour_a > 0 ? q.contour_a : 1.5 * m.kmax;
+  R.nth = std::max(1, n_threads);
+  R.n_rhs = n_rhs;
+  R.mode = mode;
+  R.J = (const cx*)J;
+  R.src = src;
+  R.tgt = tgt;
+  std::vector<cx> o((size_t)n_rhs * nt * 3, cx(0, 0));
+  R.out = o.data();
+  int rc = R.run();
+  if (rc) return fail(rc, R.err);
+  if (mode == 1 && !m.mu_one)
+    for (int r_ = 0; r_ < n_rhs; r_++)
+      for (int64_t i = 0; i < nt; i++) {
+        const double f = 1.0 / m.mu[m.layer_of(tgt[3 * i + 2])];
+        for (int c = 0; c < 3; c++) o[((size_t)r_ * nt + i) * 3 + c] *= f;
+      }
+  memcpy(out, o.data(), o.size() * sizeof(cx));
+  return 0;
+}
+
+// Ladder operators of regular expansions (for tests): c_in, order o,
+// complex128 [(o+1)^2]; out complex128 [(o+2)^2]; dir 0: (d/dx + i d/dy)/k,
+// 1: (d/dx - i d/dy)/k, 2: (d/dz)/k.
+int lmc_ladder(int o, int dir, const double* c_in, double* out) {
+  if (o < 0 || o > 40 || dir < 0 || dir > 2 || !c_in || !out) return LM_EINVAL;
+  ladder(o, dir, (const cx*)c_in, (cx*)out);
+  return 0;
+}
+
+// sum_nm c_nm j_n(k |d|) Y^m_n(d) (for tests): c complex128 [(o+1)^2], d[3]
+int lmc_eval_regular(int o, double k, const double* c, const double* dvec, double* out) {
+  if (o < 0 || o > 40 || !c || !dvec || !out) return LM_EINVAL;
+  const cx* cs[1] = {(const cx*)c};
+  eval_regular(o, k, dvec, 1, cs, (cx*)out);
+  return 0;
+}
+
+}  // extern "C"
