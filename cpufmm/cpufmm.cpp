@@ -151,10 +151,26 @@ void sph_y(int nmax, ld x, ld* out) {
   for (int n = 1; n < nmax; n++) out[n + 1] = (2 * n + 1) / x * out[n] - out[n - 1];
 }
 
-// J_0(z), J_1(z) by the trapezoid rule on Bessel's integral
+// J_0(z), J_1(z): for |z| <= 8 by their power series (in long double the
+// cancellation between terms, at most about e^{|z|}, leaves 16 digits);
+// beyond, by the trapezoid rule on Bessel's integral
 // J_n(z) = (1/pi) int_0^pi cos(n t - z sin t) dt (periodic integrand, so the
 // rule converges geometrically)
-void bessel01_trap(lcx z, lcx* j0, lcx* j1) {
+void bessel01(lcx z, lcx* j0, lcx* j1) {
+  if (std::abs(z) <= 8) {
+    const lcx w = -0.25L * z * z;
+    lcx t0 = 1, t1 = 0.5L * z, s0 = t0, s1 = t1;
+    for (int kk = 1; kk < 60; kk++) {
+      t0 *= w / (ld)((ld)kk * kk);
+      t1 *= w / (ld)((ld)kk * (kk + 1));
+      s0 += t0;
+      s1 += t1;
+      if (std::abs(t0) + std::abs(t1) < 1e-22L * (std::abs(s0) + std::abs(s1))) break;
+    }
+    *j0 = s0;
+    *j1 = s1;
+    return;
+  }
   const int M = 40 + 2 * (int)std::abs(z);
   lcx s0 = 0, s1 = 0;
   for (int i = 0; i <= M; i++) {
@@ -168,8 +184,8 @@ void bessel01_trap(lcx z, lcx* j0, lcx* j1) {
 }
 
 // Bessel J_q(z), q = 0..Q, complex z: Miller's downward recurrence
-// J_{n-1} = (2n/z) J_n - J_{n+1}, normalised by J_0 or J_1 from the
-// trapezoid rule (whichever is larger in modulus)
+// J_{n-1} = (2n/z) J_n - J_{n+1}, normalised by J_0 or J_1 (whichever is
+// larger in modulus)
 void bessel_J(int Q, lcx z, lcx* out) {
   const ld az = std::abs(z);
   if (az == 0) {
@@ -178,7 +194,8 @@ void bessel_J(int Q, lcx z, lcx* out) {
     return;
   }
   const int N = Q + 30 + (int)(2 * az);
-  std::vector<lcx> f(N + 2, lcx(0, 0));
+  thread_local std::vector<lcx> f;
+  f.assign(N + 2, lcx(0, 0));
   f[N] = lcx(1e-300L, 0);
   const lcx iz = lcx(1, 0) / z;
   for (int n = N; n >= 1; n--) {
@@ -187,7 +204,7 @@ void bessel_J(int Q, lcx z, lcx* out) {
       for (int q = n - 1; q <= N; q++) f[q] *= 1e-300L;
   }
   lcx j0, j1;
-  bessel01_trap(z, &j0, &j1);
+  bessel01(z, &j0, &j1);
   const lcx sc = (std::abs(j0) >= std::abs(j1) || Q < 1) ? j0 / f[0] : j1 / f[1];
   for (int q = 0; q <= Q; q++) out[q] = f[q] * sc;
 }
@@ -201,7 +218,8 @@ void bessel_J_real(int Q, ld x, ld* out) {
     return;
   }
   const int N = Q + 30 + (int)(2 * x);
-  std::vector<ld> f(N + 2, 0.0L);
+  thread_local std::vector<ld> f;
+  f.assign(N + 2, 0.0L);
   f[N] = 1e-300L;
   for (int n = N; n >= 1; n--) {
     f[n - 1] = (2 * n) / x * f[n] - f[n + 1];
@@ -1095,6 +1113,94 @@ struct Run {
     }
   }
 
+  // J_0..J_nmax (nmax <= 3) at kr rho for one node: the C library's j0, j1
+  // and jn on the real tail, Miller's recurrence on the complex piece
+  static void node_bessel(const NodeV& nd, double rho, int nmax, cx* jb) {
+    if (nd.kr.imag() == 0) {
+      const double x = (double)nd.kr.real() * rho;
+      jb[0] = ::j0(x);
+      if (nmax >= 1) jb[1] = ::j1(x);
+      for (int n = 2; n <= nmax; n++) jb[n] = ::jn(n, x);
+      return;
+    }
+    lcx t[4];
+    bessel_J(nmax, nd.kr * (ld)rho, t);
+    for (int n = 0; n <= nmax; n++) jb[n] = cx((double)t[n].real(), (double)t[n].imag());
+  }
+  static cx dc(lcx v) { return cx((double)v.real(), (double)v.imag()); }
+
+  // Gradient at the evaluation point x of one direct pair's field, contracted
+  // with the weights W there: W(kappa, s) = i^{1 + kappa} sum w kr Z F_s
+  // e^{i kappa phi} J_kappa(kr rho) with signed orders (J_{-n} = (-1)^n J_n),
+  // so D+- = d/dx +- i d/dy act by the Bessel ladder
+  //   D+ (e^{i n phi} J_n) = -kr e^{i (n+1) phi} J_{n+1},
+  //   D- (e^{i n phi} J_n) =  kr e^{i (n-1) phi} J_{n-1},
+  // and d/dz brings i e kz_t (e = +1 for a wave arriving up: dt/dz = e).
+  void s2t_grad_pair(const InstParams& ip, const std::vector<NodeV>& nds, double rho, lcx eph, double tzv,
+                     double uzv, double kcut, int id, int sid, ld* g3) {
+    // In[s][n + 3], Kn[s][n + 3] (extra factor kr), Ln[s][n + 3] (extra i e kz_t), n = -3..3
+    cx In[5][7], Kn[5][7], Ln[5][7];
+    for (int s5 = 0; s5 < 5; s5++)
+      for (int n = 0; n < 7; n++) In[s5][n] = Kn[s5][n] = Ln[s5][n] = 0;
+    const double e = ip.up_t ? 1 : -1;
+    cx ph[7];
+    ph[3] = 1;
+    for (int n = 1; n <= 3; n++) {
+      ph[3 + n] = ph[3 + n - 1] * dc(eph);
+      ph[3 - n] = std::conj(ph[3 + n]);
+    }
+    for (int ni = ip.s2t0; ni < ip.s2t0 + ip.s2tn; ni++) {
+      const NodeV& nd = nds[ni];
+      if (nd.kr.imag() == 0 && nd.kr.real() > kcut) continue;
+      cx jb[4];
+      node_bessel(nd, rho, 3, jb);
+      cx js[7];  // signed orders times e^{i n phi}
+      for (int n = -3; n <= 3; n++) js[n + 3] = ((n < 0 && (-n & 1)) ? -1.0 : 1.0) * jb[std::abs(n)] * ph[n + 3];
+      const cx base = dc(nd.w * nd.kr * std::exp(lcx(0, 1) * ((ld)tzv * nd.kzt + (ld)uzv * nd.kzs)));
+      const cx dz = cx(0, e) * dc(nd.kzt), kr = dc(nd.kr);
+      for (int s5 = 0; s5 < 5; s5++) {
+        const cx bf = base * dc(nd.F[s5]);
+        for (int n = 0; n < 7; n++) {
+          const cx v = bf * js[n];
+          In[s5][n] += v;
+          Kn[s5][n] += kr * v;
+          Ln[s5][n] += dz * v;
+        }
+      }
+    }
+    // derivative dir (0: D+, 1: D-, 2: d/dz) of W(kappa, s)
+    auto dW = [&](int dir, int kap, int s5) -> lcx {
+      const lcx c = ipow_l(1 + kap);
+      const cx v = dir == 0 ? -Kn[s5][kap + 1 + 3] : (dir == 1 ? Kn[s5][kap - 1 + 3] : Ln[s5][kap + 3]);
+      return c * lcx(v.real(), v.imag());
+    };
+    (void)In;
+    const ld f = 1 / (4 * PI_L);
+    for (int r_ = 0; r_ < n_rhs; r_++) {
+      const cx* q = J + ((size_t)r_ * pl.n_src + sid) * 3;
+      const lcx jx(q[0].real(), q[0].imag()), jy(q[1].real(), q[1].imag()), jz(q[2].real(), q[2].imag());
+      const lcx up = jx + lcx(0, 1) * jy, um = jx - lcx(0, 1) * jy;
+      const cx* wv = W + ((size_t)r_ * pl.n_tgt + id) * 3;
+      const lcx w[3] = {lcx(wv[0].real(), wv[0].imag()), lcx(wv[1].real(), wv[1].imag()),
+                        lcx(wv[2].real(), wv[2].imag())};
+      lcx d3[3][3];  // [D+, D-, d/dz][cartesian component of the field]
+      for (int dir = 0; dir < 3; dir++) {
+        const lcx op = 0.5L * dW(dir, 0, 0) * up - 0.5L * dW(dir, 2, 2) * um + dW(dir, 1, 1) * jz;
+        const lcx om = 0.5L * dW(dir, 0, 0) * um - 0.5L * dW(dir, -2, 2) * up + dW(dir, -1, 1) * jz;
+        const lcx oz = 0.5L * dW(dir, 1, 3) * um + 0.5L * dW(dir, -1, 3) * up + dW(dir, 0, 4) * jz;
+        d3[dir][0] = f * 0.5L * (op + om);
+        d3[dir][1] = f * (op - om) / lcx(0, 2);
+        d3[dir][2] = f * oz;
+      }
+      for (int c = 0; c < 3; c++) {
+        const lcx dx = 0.5L * (d3[0][c] + d3[1][c]), dy = (d3[0][c] - d3[1][c]) / lcx(0, 2), dzv = d3[2][c];
+        g3[0] += (w[c] * dx).real();
+        g3[1] += (w[c] * dy).real();
+        g3[2] += (w[c] * dzv).real();
+      }
+    }
+  }
+
   // ---------------- direct reaction pairs (S2T): the component's Sommerfeld
   // integrals at the pair itself, combined like the M2L tensor (order 0)
   void s2t() {
@@ -1114,6 +1220,7 @@ struct Run {
           const double zt = tgt[3 * id + 2];
           const double tzv = ip.up_t ? zt - med.d[ip.lt] : med.d[ip.lt - 1] - zt;
           std::vector<lcx> accp(n_rhs, 0), accm(n_rhs, 0), accz(n_rhs, 0);
+          ld g3[3] = {0, 0, 0};
           for (int li = tb.p2p0; li < tb.p2p1; li++) {
             const SrcBox& sb = pl.sbox[pl.p2p_list[li]];
             for (int s = sb.pt0; s < sb.pt1; s++) {
@@ -1123,28 +1230,31 @@ struct Run {
               const double rho = std::sqrt(dx * dx + dy * dy);
               const double kcut = a + LM_S2T_DIGITS / (tzv + uzv);
               const ld cph = rho > 0 ? dx / (ld)rho : 1, sph = rho > 0 ? dy / (ld)rho : 0;
+              const lcx eph(cph, sph);
+              if (mode == 2) {
+                s2t_grad_pair(ip, nodes, rho, eph, tzv, uzv, kcut, id, sid, g3);
+                continue;
+              }
               // I[sigma][n] = sum_nodes w kr Z F_sigma J_n(kr rho), n = 0..2
-              lcx I[5][3];
+              cx Id[5][3];
               for (int s5 = 0; s5 < 5; s5++)
-                for (int n = 0; n < 3; n++) I[s5][n] = 0;
+                for (int n = 0; n < 3; n++) Id[s5][n] = 0;
               for (int ni = ip.s2t0; ni < ip.s2t0 + ip.s2tn; ni++) {
                 const NodeV& nd = nodes[ni];
                 if (nd.kr.imag() == 0 && nd.kr.real() > kcut) continue;
-                lcx jb[3];
-                if (nd.kr.imag() == 0) {
-                  ld jr[3];
-                  bessel_J_real(2, nd.kr.real() * (ld)rho, jr);
-                  for (int n = 0; n < 3; n++) jb[n] = jr[n];
-                } else {
-                  bessel_J(2, nd.kr * (ld)rho, jb);
-                }
-                const lcx base = nd.w * nd.kr * std::exp(lcx(0, 1) * ((ld)tzv * nd.kzt + (ld)uzv * nd.kzs));
+                cx jb[3];
+                node_bessel(nd, rho, 2, jb);
+                const cx base = dc(nd.w * nd.kr * std::exp(lcx(0, 1) * ((ld)tzv * nd.kzt + (ld)uzv * nd.kzs)));
                 const lcx* F = mode == 1 ? nd.FH : nd.F;
-                for (int s5 = 0; s5 < 5; s5++)
-                  for (int n = 0; n < 3; n++) I[s5][n] += base * F[s5] * jb[n];
+                for (int s5 = 0; s5 < 5; s5++) {
+                  const cx bf = base * dc(F[s5]);
+                  for (int n = 0; n < 3; n++) Id[s5][n] += bf * jb[n];
+                }
               }
+              lcx I[5][3];
+              for (int s5 = 0; s5 < 5; s5++)
+                for (int n = 0; n < 3; n++) I[s5][n] = lcx(Id[s5][n].real(), Id[s5][n].imag());
               // W(kappa, sigma) = e^{i kappa phi} i^{1+|kappa|} I_sigma,|kappa|
-              const lcx eph(cph, sph);
               auto Wf = [&](int kap, int sg) {
                 const int ak = std::abs(kap);
                 lcx ph = 1;
@@ -1169,7 +1279,9 @@ struct Run {
               }
             }
           }
-          {
+          if (mode == 2) {
+            for (int c = 0; c < 3; c++) gX[3 * id + c] += (double)g3[c];
+          } else {
             const ld f = 1 / (4 * PI_L);
             for (int r_ = 0; r_ < n_rhs; r_++) {
               cx* A = out + ((size_t)r_ * pl.n_tgt + id) * 3;
@@ -1218,17 +1330,21 @@ extern "C" {
 // (same arguments and plan as lm_build_batch + lm_evaluate / lm_evaluate_h).
 // J: complex128 [n_rhs][n_src][3] (interleaved re, im); mode 0: out = A,
 // complex128 [n_rhs][n_tgt][3]; mode 1: out = H (magnetic field, Faraday's
-// law, the 1/mu of the target's layer applied).  n_threads host threads.
+// law, the 1/mu of the target's layer applied); mode 2: out = g, real
+// [n_tgt][3], g_i = sum_r Re sum_b W_{r,i,b} grad_i A_{r,i,b} (the gradient
+// at the targets of the field contracted with W, complex128
+// [n_rhs][n_tgt][3]; with the roles of the two point sets exchanged this is
+// the source-position gradient of lm_grad_src_xyz).  n_threads host threads.
 // Returns 0 or a negative LM_* code with a message in err.
 int lmc_run(int n_layers, const double* d, const double* k, const double* mu, const lm_params* prm, int n_geom,
             const int64_t* src_off, const double* src, const int64_t* tgt_off, const double* tgt, int n_rhs,
-            const double* J, int mode, double* out, int n_threads, char* err, int errlen) {
+            const double* J, const double* W, int mode, double* out, int n_threads, char* err, int errlen) {
   auto fail = [&](int code, const std::string& m) {
     if (err && errlen > 0) snprintf(err, errlen, "%s", m.c_str());
     return code;
   };
   if (n_layers < 1 || n_layers > LM_MAXL || !k || !prm || n_geom < 1 || n_rhs < 1 || !src_off || !tgt_off ||
-      (mode != 0 && mode != 1))
+      mode < 0 || mode > 2 || (mode == 2 && !W))
     return fail(LM_EINVAL, "invalid arguments");
   Run R;
   Medium& m = R.med;
@@ -1268,12 +1384,19 @@ int lmc_run(int n_layers, const double* d, const double* k, const double* mu, co
   R.n_rhs = n_rhs;
   R.mode = mode;
   R.J = (const cx*)J;
+  R.W = (const cx*)W;
   R.src = src;
   R.tgt = tgt;
   std::vector<cx> o((size_t)n_rhs * nt * 3, cx(0, 0));
+  std::vector<double> g((size_t)nt * 3, 0.0);
   R.out = o.data();
+  R.gX = g.data();
   int rc = R.run();
   if (rc) return fail(rc, R.err);
+  if (mode == 2) {
+    memcpy(out, g.data(), g.size() * sizeof(double));
+    return 0;
+  }
   if (mode == 1 && !m.mu_one)
     for (int r_ = 0; r_ < n_rhs; r_++)
       for (int64_t i = 0; i < nt; i++) {

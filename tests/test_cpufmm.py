@@ -133,3 +133,21 @@ def test_cpufmm_columns_and_linearity(cf, tiny):
     assert np.array_equal(A2[0], A0)
     A3 = cf.run(d, k, x, (2 - 1j) * J, p=6, n_threads=NTH)
     assert rel(A3, (2 - 1j) * A0) < 1e-14
+
+
+def test_cpufmm_adjoint_and_gradient_against_oracle(cf, tiny):
+    """The adjoint (reciprocity, roles exchanged) and the source-position
+    gradients (derivatives of the local expansions, of the free dyadic and
+    of the direct pairs' Sommerfeld integrals) against the oracle's
+    references (stored by tests/golden/make_golden.py), targets equal to and
+    distinct from the sources, with and without direct reaction pairs."""
+    d, k, x, J, _ = tiny
+    g = np.load(os.path.join(GOLD, "tiny_adjoint_oracle.npz"))
+    gg = np.load(os.path.join(GOLD, "tiny_grad_oracle.npz"))
+    assert rel(cf.adjoint(d, k, x, g["gA"], p=8, n_threads=NTH), g["gJ"]) < 1e-7
+    assert rel(cf.adjoint(d, k, x, g["gA2"], tgt=g["y"], p=8, n_threads=NTH), g["gJ2"]) < 4e-7
+    for s2t in (0, 2):
+        gX = cf.grad_src_xyz(d, k, x, J, g["gA"], p=8, react_s2t=s2t, n_threads=NTH)
+        assert rel(gX[gg["js"]], gg["gX"]) < 1e-6
+    gX2 = cf.grad_src_xyz(d, k, x, J, g["gA2"], tgt=g["y"], p=8, n_threads=NTH)
+    assert rel(gX2[gg["js"]], gg["gX2"]) < 1.2e-6

@@ -159,3 +159,37 @@ def test_six_layers_equals_cpu_run(cf):
     e = rel(A, ref)
     print("  GPU vs CPU run: rel L2 %.2e" % e, flush=True)
     assert e < TOL
+
+
+@pytest.mark.parametrize("direct", [0, 2])
+def test_gradient_equals_cpu_run(cf, direct):
+    """Source-position gradients (the far field's derivative expansions, the
+    free dyadic's derivative, the direct pairs' Bessel-ladder derivatives) on
+    distinct point sets with permeabilities and two right-hand sides."""
+    d, k, src, J = inputs.three_layer(300, seed=11, half_width=1.0, n_rhs=2)
+    _, _, tgt, _ = inputs.three_layer(200, seed=12, half_width=1.0)
+    gA = inputs.cotangent(200, n_rhs=2, seed=13)
+    mu = [1.0, 1.8, 0.7]
+    print("case gradient 300 sources, 200 targets, 2 rhs, mu, p=8, react_s2t=%d" % direct, flush=True)
+    f = lmfmm.LayeredDyadicFMM(d, k, mu=mu, p=8, react_s2t=direct).build(src, tgt)
+    gX = f.grad_src_xyz(cuda(J), cuda(gA)).cpu().numpy()
+    st = f.stats()
+    f.close()
+    ref = cf.grad_src_xyz(d, k, src, J, gA, tgt=tgt, mu=mu, p=8, react_s2t=direct, n_threads=NTH)
+    e = rel(gX, ref)
+    print("  GPU vs CPU run: rel L2 %.2e (direct reaction pairs of the forward plan: %d)"
+          % (e, st["s2t_pairs"]), flush=True)
+    assert e < TOL
+
+
+def test_gradient_same_points_equals_cpu_run(cf):
+    d, k, x, J = inputs.tiny(seed=0)
+    gA = inputs.cotangent(600, seed=14)
+    print("case gradient tiny, targets = sources, p=12, direct reaction pairs", flush=True)
+    f = lmfmm.LayeredDyadicFMM(d, k, p=12, react_s2t=2).build(x)
+    gX = f.grad_src_xyz(cuda(J), cuda(gA)).cpu().numpy()
+    f.close()
+    ref = cf.grad_src_xyz(d, k, x, J, gA, p=12, react_s2t=2, n_threads=NTH)
+    e = rel(gX, ref)
+    print("  GPU vs CPU run: rel L2 %.2e" % e, flush=True)
+    assert e < TOL
