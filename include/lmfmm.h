@@ -153,6 +153,29 @@ int lm_build_batch(lm_ctx* ctx, int n_geom, const int64_t* src_off, const double
  * summation order is fixed, so repeated calls give bitwise equal results. */
 int lm_evaluate(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as lm_evaluate, A = G J, with every work buffer of the
+ * evaluation (multipole and local expansions, P2M partials, M2L outputs) in
+ * a static device array of the library, LM_NOALLOC_SCRATCH_BYTES per GPU,
+ * held from the library's load until the process ends.  The call allocates
+ * nothing (no hipMalloc, hipFree, events or library allocations); the plan
+ * and its tables are allocated by lm_build as for lm_evaluate, which also
+ * prepares this call's single-right-hand-side M2L schedule.  Right-hand
+ * sides are evaluated one after the other, each bitwise equal to
+ * lm_evaluate's column.  M2L tile shapes are not autotuned here (the
+ * m2l_variant parameter if fixed, else variant 0; all give the same bits).
+ * J: DEVICE complex128 [n_rhs][n_src][3]; A: DEVICE complex128
+ * [n_rhs][n_tgt][3], overwritten; asynchronous on `stream`.  All calls on
+ * one GPU share its array: calls that overlap in time on one GPU (from
+ * several host threads or streams) race and give wrong results.  LM_ENOMEM,
+ * with nothing written, when the build's work buffers for one right-hand
+ * side exceed the array (lm_last_error gives the bytes needed); LM_EHIP if
+ * the array's device address could not be obtained (lm_create looks it up
+ * once per device); otherwise errors as lm_evaluate. */
+#define LM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int lm_evaluate_noalloc(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream);
+
 /* Magnetic field of the same currents: H = G_H J with the magnetic dyadic of
  * Sec. 3.1 (the J6..J9 form), normalised as G_H(x, y) = (1/mu(x)) curl_x
  * G(x, y) (Faraday's law; in free space curl (g I) q = grad g x q, the

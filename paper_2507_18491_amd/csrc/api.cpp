@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -58,6 +59,14 @@ struct lm_ctx {
     long long y_need = 0;     // scratch elements
   };
   std::map<int, TileSet> tilesets;
+  // lm_evaluate_noalloc: a single-right-hand-side M2L schedule whose work
+  // buffers fit the static scratch (made with the build), their offsets in
+  // the scratch (complex numbers: ME, LE, P2M partials, M2L outputs), and the
+  // scratch bytes the build needs
+  TileSet na_ts;
+  bool na_ok = false;
+  long long na_off[4] = {0, 0, 0, 0};
+  long long na_need = 0;
   cd* Y = nullptr;           // M2L scratch
   long long y_cap = 0;
   double t_plan_ms = 0, t_upload_ms = 0, t_tables_ms = 0;
@@ -122,6 +131,11 @@ static void free_build(lm_ctx* ctx) {
     if (kv.second.d_ybase) hipFree(kv.second.d_ybase);
   }
   ctx->tilesets.clear();
+  if (ctx->na_ts.d_tiles) hipFree(ctx->na_ts.d_tiles);
+  if (ctx->na_ts.d_ybase) hipFree(ctx->na_ts.d_ybase);
+  ctx->na_ts = lm_ctx::TileSet();
+  ctx->na_ok = false;
+  ctx->na_need = 0;
   if (ctx->Y) hipFree(ctx->Y);
   ctx->Y = nullptr;
   ctx->y_cap = 0;
@@ -191,6 +205,45 @@ static int dalloc(lm_ctx* ctx, void** out, size_t bytes) {
   return 0;
 }
 
+// ---------------------------------------------------------------- static scratch
+// Work buffers of lm_evaluate_noalloc, for callers that cannot allocate
+// device memory: one array per GPU, held from the library's load until the
+// process ends.  In host code `scratch` only names the array; its device
+// address on each GPU comes from hipGetSymbolAddress (lm_create, once per
+// device), and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[LM_NOALLOC_SCRATCH_BYTES];
+
+#define LM_MAX_DEVICES 64
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[LM_MAX_DEVICES];   // device address of scratch per device
+static int g_scratch_state[LM_MAX_DEVICES];   // 0: not looked up, 1: ok, -1: failed
+static std::string g_scratch_err[LM_MAX_DEVICES];
+
+// looks up the device address of `scratch` on device dev (with dev current);
+// the caller's current device is restored
+static void scratch_setup(int dev) {
+  if (dev < 0 || dev >= LM_MAX_DEVICES) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_state[dev] != 0) return;
+  int prev = 0;
+  hipError_t e = hipGetDevice(&prev);
+  if (e == hipSuccess) e = hipSetDevice(dev);
+  void* ptr = nullptr;
+  if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && !ptr) e = hipErrorInvalidSymbol;
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess) {
+    g_scratch_state[dev] = -1;
+    g_scratch_err[dev] = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    return;
+  }
+  g_scratch_ptr[dev] = ptr;
+  g_scratch_state[dev] = 1;
+}
+
+static int make_schedule(lm_ctx* ctx, int n_rhs, long long budget, lm_ctx::TileSet& ts, long long* block_max);
+static long long p2m_part_size(const lm_ctx* ctx, int n_rhs);
+
 extern "C" {
 
 int lm_default_params(lm_params* prm) {
@@ -222,6 +275,7 @@ int lm_create(lm_ctx** out, int hip_device) {
     delete ctx;
     return LM_EHIP;
   }
+  scratch_setup(hip_device);
   *out = ctx;
   return LM_OK;
 }
@@ -623,115 +677,164 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
     ctx->host_soff.assign(soff, soff + n_geom + 1);
     ctx->host_toff.assign(toff, toff + n_geom + 1);
   }
+  {
+    // lm_evaluate_noalloc: work buffers of one right-hand side laid out in
+    // the static scratch (256-byte aligned pieces), the M2L outputs chunked
+    // to the room that is left
+    auto up = [](long long n) { return (n + 15) / 16 * 16; };  // complex numbers, 256-byte multiples
+    const long long cap = (long long)(LM_NOALLOC_SCRATCH_BYTES / sizeof(cd));
+    ctx->na_off[0] = 0;
+    ctx->na_off[1] = ctx->na_off[0] + up(pl.me_size);
+    ctx->na_off[2] = ctx->na_off[1] + up(pl.le_size);
+    ctx->na_off[3] = ctx->na_off[2] + up(p2m_part_size(ctx, 1));
+    long long bmax = 0;
+    int rc2 = make_schedule(ctx, 1, std::max(0LL, cap - ctx->na_off[3]) * (long long)sizeof(cd), ctx->na_ts, &bmax);
+    if (rc2) return rc2;
+    ctx->na_need = (ctx->na_off[3] + std::max(up(ctx->na_ts.y_need), up(bmax / (long long)sizeof(cd)))) *
+                   (long long)sizeof(cd);
+    ctx->na_ok = ctx->na_need <= (long long)LM_NOALLOC_SCRATCH_BYTES;
+  }
   ctx->built = true;
   return LM_OK;
 }
 
+// The M2L schedule for n_rhs right-hand sides: chunks of whole blocks whose
+// M2L outputs fit `budget` bytes of scratch (each block gets its own scratch
+// base, blocks differ in P), and the GEMM tiles of every chunk.  Host lists,
+// uploaded into ts.  *block_max receives the scratch bytes of the largest
+// block (a chunk holds at least one block, whatever the budget).
+static int make_schedule(lm_ctx* ctx, int n_rhs, long long budget, lm_ctx::TileSet& ts, long long* block_max) {
+  Plan& pl = ctx->plan;
+  std::vector<M2LTile> tiles;
+  std::vector<long long> ybase(std::max<size_t>(1, pl.blocks.size()), 0);
+  long long need_max = 0;
+  *block_max = 0;
+  size_t bi = 0;
+  while (bi < pl.blocks.size()) {
+    lm_ctx::Chunk ch;
+    ch.tile0 = (int)tiles.size();
+    ch.bt0 = pl.blocks[bi].bt0;
+    ch.nbt = 0;
+    long long bytes = 0;
+    while (bi < pl.blocks.size()) {
+      const M2LBlock& B = pl.blocks[bi];
+      const M2LClass& C = pl.cls[B.cls];
+      long long bb = (long long)B.nq * 3 * n_rhs * C.P * (long long)sizeof(cd);
+      *block_max = std::max(*block_max, bb);
+      if (ch.nbt > 0 && bytes + bb > budget) break;
+      ybase[bi] = bytes / (long long)sizeof(cd);
+      bytes += bb;
+      for (int o = 0; o < C.n_off; o++) {
+        int np = pl.offr[B.offr0 + o + 1] - pl.offr[B.offr0 + o];
+        int ncol = np * n_rhs;
+        int po = pl.offs[C.off0 + o].pord, Po = (po + 1) * (po + 1);
+        for (int ot = 0; ot < 3; ot++)
+          for (int r0 = 0; r0 < Po; r0 += TM_ROWS)
+            for (int c0 = 0; c0 < ncol; c0 += TN_COLS) {
+              M2LTile t;
+              t.blk = (int)bi;
+              t.off = o;
+              t.out_type = ot;
+              t.row0 = r0;
+              t.col0 = c0;
+              t.ncol = std::min(TN_COLS, ncol - c0);
+              tiles.push_back(t);
+            }
+      }
+      ch.nbt += B.nt;
+      bi++;
+    }
+    ch.ntile = (int)tiles.size() - ch.tile0;
+    need_max = std::max(need_max, bytes);
+    ts.chunks.push_back(ch);
+  }
+  if (!tiles.empty()) {
+    HIPC(hipMalloc((void**)&ts.d_tiles, tiles.size() * sizeof(M2LTile)));
+    HIPC(hipMemcpy(ts.d_tiles, tiles.data(), tiles.size() * sizeof(M2LTile), hipMemcpyHostToDevice));
+  }
+  HIPC(hipMalloc((void**)&ts.d_ybase, ybase.size() * sizeof(long long)));
+  HIPC(hipMemcpy(ts.d_ybase, ybase.data(), ybase.size() * sizeof(long long), hipMemcpyHostToDevice));
+  ts.n_tiles = (int)tiles.size();
+  ts.y_need = need_max / (long long)sizeof(cd);
+  return LM_OK;
+}
+
+// complex numbers of the P2M partial expansions for n_rhs right-hand sides
+static long long p2m_part_size(const lm_ctx* ctx, int n_rhs) {
+  long long part = 0;
+  for (int g = 0; g < 2; g++) part += ctx->p2m_slots[g] * n_rhs * 3LL * (ctx->p2m_p[g] + 1) * (ctx->p2m_p[g] + 1);
+  return part;
+}
+
+// Work buffers and M2L schedule of one evaluation of n_rhs right-hand sides.
+struct Work {
+  cd* ME = nullptr;
+  cd* LE = nullptr;
+  cd* part = nullptr;
+  cd* Y = nullptr;
+  lm_ctx::TileSet* ts = nullptr;
+  bool tune = true;   // autotune untuned M2L launches (events, synchronisation)
+  bool timed = true;  // record phase events when timing is on
+};
+
 // Work buffers and the M2L schedule for n_rhs right-hand sides.  Anything
 // that must be (re)allocated is done after the stream has drained, so no
 // buffer used by queued kernels is freed or overwritten.
-static int ensure_rhs(lm_ctx* ctx, int n_rhs, hipStream_t s) {
+static int ensure_rhs(lm_ctx* ctx, int n_rhs, hipStream_t s, Work* w) {
   Plan& pl = ctx->plan;
   long long me = pl.me_size * n_rhs, le = pl.le_size * n_rhs;
-  long long part = 0;  // P2M partials of both groups
-  for (int g = 0; g < 2; g++) part += ctx->p2m_slots[g] * n_rhs * 3LL * (ctx->p2m_p[g] + 1) * (ctx->p2m_p[g] + 1);
+  long long part = p2m_part_size(ctx, n_rhs);
   bool have = ctx->tilesets.count(n_rhs) > 0;
-  if (me <= ctx->me_cap && le <= ctx->le_cap && part <= ctx->p2m_part_cap && have &&
-      ctx->tilesets[n_rhs].y_need <= ctx->y_cap) {
-    lm_ctx::TileSet& ts = ctx->tilesets[n_rhs];
-    ctx->d.tiles = ts.d_tiles;
-    ctx->d.blk_ybase = ts.d_ybase;
-    return LM_OK;
-  }
-  HIPC(hipStreamSynchronize(s));
-  if (me > ctx->me_cap) {
-    if (ctx->ME) hipFree(ctx->ME);
-    ctx->ME = nullptr;
-    HIPC(hipMalloc((void**)&ctx->ME, (size_t)std::max(1LL, me) * sizeof(cd)));
-    ctx->me_cap = me;
-  }
-  if (le > ctx->le_cap) {
-    if (ctx->LE) hipFree(ctx->LE);
-    ctx->LE = nullptr;
-    HIPC(hipMalloc((void**)&ctx->LE, (size_t)std::max(1LL, le) * sizeof(cd)));
-    ctx->le_cap = le;
-  }
-  if (part > ctx->p2m_part_cap) {
-    if (ctx->p2m_part) hipFree(ctx->p2m_part);
-    ctx->p2m_part = nullptr;
-    HIPC(hipMalloc((void**)&ctx->p2m_part, (size_t)part * sizeof(cd)));
-    ctx->p2m_part_cap = part;
-  }
-  if (!have) {
-    // chunks of whole blocks whose M2L outputs fit the scratch budget;
-    // each block gets its own scratch base (blocks differ in P)
-    const long long budget = 6LL << 30;  // bytes
-    lm_ctx::TileSet ts;
-    std::vector<M2LTile> tiles;
-    std::vector<long long> ybase(std::max<size_t>(1, pl.blocks.size()), 0);
-    long long need_max = 0;
-    size_t bi = 0;
-    while (bi < pl.blocks.size()) {
-      lm_ctx::Chunk ch;
-      ch.tile0 = (int)tiles.size();
-      ch.bt0 = pl.blocks[bi].bt0;
-      ch.nbt = 0;
-      long long bytes = 0;
-      while (bi < pl.blocks.size()) {
-        const M2LBlock& B = pl.blocks[bi];
-        const M2LClass& C = pl.cls[B.cls];
-        long long bb = (long long)B.nq * 3 * n_rhs * C.P * (long long)sizeof(cd);
-        if (ch.nbt > 0 && bytes + bb > budget) break;
-        ybase[bi] = bytes / (long long)sizeof(cd);
-        bytes += bb;
-        for (int o = 0; o < C.n_off; o++) {
-          int np = pl.offr[B.offr0 + o + 1] - pl.offr[B.offr0 + o];
-          int ncol = np * n_rhs;
-          int po = pl.offs[C.off0 + o].pord, Po = (po + 1) * (po + 1);
-          for (int ot = 0; ot < 3; ot++)
-            for (int r0 = 0; r0 < Po; r0 += TM_ROWS)
-              for (int c0 = 0; c0 < ncol; c0 += TN_COLS) {
-                M2LTile t;
-                t.blk = (int)bi;
-                t.off = o;
-                t.out_type = ot;
-                t.row0 = r0;
-                t.col0 = c0;
-                t.ncol = std::min(TN_COLS, ncol - c0);
-                tiles.push_back(t);
-              }
-        }
-        ch.nbt += B.nt;
-        bi++;
+  if (!(me <= ctx->me_cap && le <= ctx->le_cap && part <= ctx->p2m_part_cap && have &&
+        ctx->tilesets[n_rhs].y_need <= ctx->y_cap)) {
+    HIPC(hipStreamSynchronize(s));
+    if (me > ctx->me_cap) {
+      if (ctx->ME) hipFree(ctx->ME);
+      ctx->ME = nullptr;
+      HIPC(hipMalloc((void**)&ctx->ME, (size_t)std::max(1LL, me) * sizeof(cd)));
+      ctx->me_cap = me;
+    }
+    if (le > ctx->le_cap) {
+      if (ctx->LE) hipFree(ctx->LE);
+      ctx->LE = nullptr;
+      HIPC(hipMalloc((void**)&ctx->LE, (size_t)std::max(1LL, le) * sizeof(cd)));
+      ctx->le_cap = le;
+    }
+    if (part > ctx->p2m_part_cap) {
+      if (ctx->p2m_part) hipFree(ctx->p2m_part);
+      ctx->p2m_part = nullptr;
+      HIPC(hipMalloc((void**)&ctx->p2m_part, (size_t)part * sizeof(cd)));
+      ctx->p2m_part_cap = part;
+    }
+    if (!have) {
+      lm_ctx::TileSet ts;
+      long long bmax = 0;
+      int rc = make_schedule(ctx, n_rhs, 6LL << 30, ts, &bmax);
+      if (rc) {
+        if (ts.d_tiles) hipFree(ts.d_tiles);
+        if (ts.d_ybase) hipFree(ts.d_ybase);
+        return rc;
       }
-      ch.ntile = (int)tiles.size() - ch.tile0;
-      need_max = std::max(need_max, bytes);
-      ts.chunks.push_back(ch);
+      ctx->tilesets[n_rhs] = ts;
     }
-    if (!tiles.empty()) {
-      HIPC(hipMalloc((void**)&ts.d_tiles, tiles.size() * sizeof(M2LTile)));
-      HIPC(hipMemcpy(ts.d_tiles, tiles.data(), tiles.size() * sizeof(M2LTile), hipMemcpyHostToDevice));
+    lm_ctx::TileSet& ts = ctx->tilesets[n_rhs];
+    if (ts.y_need > ctx->y_cap) {
+      if (ctx->Y) hipFree(ctx->Y);
+      ctx->Y = nullptr;
+      HIPC(hipMalloc((void**)&ctx->Y, (size_t)std::max(1LL, ts.y_need) * sizeof(cd)));
+      ctx->y_cap = ts.y_need;
     }
-    HIPC(hipMalloc((void**)&ts.d_ybase, ybase.size() * sizeof(long long)));
-    HIPC(hipMemcpy(ts.d_ybase, ybase.data(), ybase.size() * sizeof(long long), hipMemcpyHostToDevice));
-    ts.n_tiles = (int)tiles.size();
-    ts.y_need = need_max / (long long)sizeof(cd);
-    ctx->tilesets[n_rhs] = ts;
   }
-  lm_ctx::TileSet& ts = ctx->tilesets[n_rhs];
-  if (ts.y_need > ctx->y_cap) {
-    if (ctx->Y) hipFree(ctx->Y);
-    ctx->Y = nullptr;
-    HIPC(hipMalloc((void**)&ctx->Y, (size_t)std::max(1LL, ts.y_need) * sizeof(cd)));
-    ctx->y_cap = ts.y_need;
-  }
-  ctx->d.tiles = ts.d_tiles;
-  ctx->d.blk_ybase = ts.d_ybase;
+  w->ME = ctx->ME;
+  w->LE = ctx->LE;
+  w->part = ctx->p2m_part;
+  w->Y = ctx->Y;
+  w->ts = &ctx->tilesets[n_rhs];
   return LM_OK;
 }
 
 static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream, const cd* W = nullptr,
-                          double* gX = nullptr, cd* Hc = nullptr);
+                          double* gX = nullptr, cd* Hc = nullptr, Work* wk = nullptr);
 
 #define LM_RHS_CHUNK 16
 
@@ -747,6 +850,41 @@ int lm_evaluate(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream) {
     const cd* Jc = J ? (const cd*)J + (long long)r0 * pl.n_src * 3 : nullptr;
     cd* Ac = A ? (cd*)A + (long long)r0 * pl.n_tgt * 3 : nullptr;
     int rc = evaluate_chunk(ctx, nr, Jc, Ac, stream);
+    if (rc) return rc;
+  }
+  return LM_OK;
+}
+
+int lm_evaluate_noalloc(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream) {
+  if (!ctx) return LM_EINVAL;
+  if (!ctx->built) return fail(ctx, LM_ESTATE, "lm_build must succeed before lm_evaluate_noalloc");
+  if (n_rhs < 1 || n_rhs > 4096) return fail(ctx, LM_EINVAL, "n_rhs out of range (1..4096)");
+  Plan& pl = ctx->plan;
+  if ((pl.n_src > 0 && !J) || (pl.n_tgt > 0 && !A)) return fail(ctx, LM_EINVAL, "null J or A");
+  if (((uintptr_t)J % 16) || ((uintptr_t)A % 16)) return fail(ctx, LM_EINVAL, "J and A must be 16-byte aligned");
+  const int dev = ctx->device;
+  if (dev < 0 || dev >= LM_MAX_DEVICES || g_scratch_state[dev] != 1)
+    return fail(ctx, LM_EHIP, dev >= 0 && dev < LM_MAX_DEVICES && g_scratch_state[dev] < 0
+                                  ? g_scratch_err[dev]
+                                  : std::string("no static scratch on this device"));
+  if (!ctx->na_ok)
+    return fail(ctx, LM_ENOMEM,
+                lm_fmt("lm_evaluate_noalloc: this build needs %lld bytes of scratch, the static scratch holds %lld",
+                       ctx->na_need, (long long)LM_NOALLOC_SCRATCH_BYTES));
+  cd* base = (cd*)g_scratch_ptr[dev];
+  Work w;
+  w.ME = base + ctx->na_off[0];
+  w.LE = base + ctx->na_off[1];
+  w.part = base + ctx->na_off[2];
+  w.Y = base + ctx->na_off[3];
+  w.ts = &ctx->na_ts;
+  w.tune = false;
+  w.timed = false;
+  // one right-hand side at a time (the work buffers hold one)
+  for (int r = 0; r < n_rhs; r++) {
+    const cd* Jr = J ? (const cd*)J + (long long)r * pl.n_src * 3 : nullptr;
+    cd* Ar = A ? (cd*)A + (long long)r * pl.n_tgt * 3 : nullptr;
+    int rc = evaluate_chunk(ctx, 1, Jr, Ar, stream, nullptr, nullptr, nullptr, &w);
     if (rc) return rc;
   }
   return LM_OK;
@@ -801,7 +939,7 @@ static int swapped_ctx(lm_ctx* ctx, hipStream_t s, lm_ctx** out) {
 // code loading); the fastest is kept for that launch.  Every run writes the
 // same scratch vectors, so the evaluation continues with valid data.  Under
 // capture nothing is timed and variant 0 is used until a later eager call.
-static int tune_m2l(lm_ctx* ctx, lm_ctx::Chunk& ch, int n_rhs, hipStream_t s) {
+static int tune_m2l(lm_ctx* ctx, const DevPlan& d, const Work& w, lm_ctx::Chunk& ch, int n_rhs, hipStream_t s) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIPC(hipStreamIsCapturing(s, &cs));
   if (cs != hipStreamCaptureStatusNone) return LM_OK;
@@ -817,7 +955,7 @@ static int tune_m2l(lm_ctx* ctx, lm_ctx::Chunk& ch, int n_rhs, hipStream_t s) {
     float ms = 0;
     for (int rep = 0; rep < 2 && rc == LM_OK; rep++) {
       if (hipEventRecord(e0, s) != hipSuccess) rc = LM_EHIP;
-      launch_m2l(ctx->d, ctx->d.tiles + ch.tile0, ch.ntile, n_rhs, ctx->ME, ctx->Y, ctx->pmax, v, s);
+      launch_m2l(d, d.tiles + ch.tile0, ch.ntile, n_rhs, w.ME, w.Y, ctx->pmax, v, s);
       if (rc == LM_OK && (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
                           hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
         rc = LM_EHIP;
@@ -935,7 +1073,7 @@ int lm_grad_src_xyz(lm_ctx* ctx, int n_rhs, const void* J, const void* gA, doubl
 }
 
 static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* stream, const cd* W, double* gX,
-                          cd* Hc) {
+                          cd* Hc, Work* wk) {
   if (!ctx) return LM_EINVAL;
   if (!ctx->built) return fail(ctx, LM_ESTATE, "lm_build must succeed before lm_evaluate");
   if (n_rhs < 1 || n_rhs > 4096) return fail(ctx, LM_EINVAL, "n_rhs out of range (1..4096)");
@@ -945,14 +1083,21 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
   if (((uintptr_t)J % 16) || ((uintptr_t)A % 16)) return fail(ctx, LM_EINVAL, "J and A must be 16-byte aligned");
   HIPC(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
-  int rc = ensure_rhs(ctx, n_rhs, s);
-  if (rc) return rc;
+  Work wl;
+  int rc = LM_OK;
+  if (!wk) {
+    if ((rc = ensure_rhs(ctx, n_rhs, s, &wl))) return rc;
+    wk = &wl;
+  }
+  const Work& w = *wk;
   const cd* Jc = (const cd*)J;
   cd* Ac = (cd*)A;
-  DevPlan& d = ctx->d;
+  DevPlan d = ctx->d;  // this evaluation's schedule
+  d.tiles = w.ts->d_tiles;
+  d.blk_ybase = w.ts->d_ybase;
   std::vector<hipEvent_t> ev;
-  const int nch = (int)ctx->tilesets[n_rhs].chunks.size();
-  if (ctx->timing && ctx->evsets.size() < 4096) {
+  const int nch = (int)w.ts->chunks.size();
+  if (w.timed && ctx->timing && ctx->evsets.size() < 4096) {
     // phase boundaries, then a start/stop pair around every M2L GEMM launch
     ev.resize(LM_PHASES + 1 + 2 * nch);
     for (auto& e : ev) HIPC(hipEventCreate(&e));
@@ -965,47 +1110,54 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
     launch_fill(Hc, (long long)n_rhs * pl.n_tgt * 3, s);
   else if (!grad)
     launch_fill(Ac, (long long)n_rhs * pl.n_tgt * 3, s);
-  if (pl.n_src > 0 && pl.n_tgt > 0) launch_fill(ctx->LE, pl.le_size * n_rhs, s);
+  if (pl.n_src > 0 && pl.n_tgt > 0) {
+    // local expansions accumulate; multipole vectors of source boxes that
+    // hold no sources (free-space leaves holding only targets) are read by
+    // M2M but written by no pass, so they must hold zeros
+    launch_fill(w.LE, pl.le_size * n_rhs, s);
+    launch_fill(w.ME, pl.me_size * n_rhs, s);
+  }
   mark(1);
   if (pl.n_src > 0 && pl.n_tgt > 0) {
-    cd* part = ctx->p2m_part;
+    cd* part = w.part;
     for (int g = 0; g < 2; g++) {
       const int pg = ctx->p2m_p[g], Pg = (pg + 1) * (pg + 1);
-      launch_p2m(d, ctx->d_p2m[g], ctx->n_p2m[g], ctx->d_src, Jc, pl.n_src, n_rhs, ctx->ME, part, pg, s);
-      launch_p2m_sum(d, ctx->d_p2m_sum[g], ctx->n_p2m_sum[g], n_rhs, part, Pg, ctx->ME, s);
+      launch_p2m(d, ctx->d_p2m[g], ctx->n_p2m[g], ctx->d_src, Jc, pl.n_src, n_rhs, w.ME, part, pg, s);
+      launch_p2m_sum(d, ctx->d_p2m_sum[g], ctx->n_p2m_sum[g], n_rhs, part, Pg, w.ME, s);
       part += ctx->p2m_slots[g] * n_rhs * 3 * Pg;
     }
     mark(2);
     for (int l = (int)ctx->d_m2m.size() - 1; l >= 0; l--)
-      launch_m2m(d, ctx->d_m2m[l], ctx->n_m2m[l], n_rhs, ctx->ME, ctx->pmax, s);
+      launch_m2m(d, ctx->d_m2m[l], ctx->n_m2m[l], n_rhs, w.ME, ctx->pmax, s);
     mark(3);
     for (int c = 0; c < nch; c++) {
-      lm_ctx::Chunk& ch = ctx->tilesets[n_rhs].chunks[c];
+      lm_ctx::Chunk& ch = w.ts->chunks[c];
       int v = ctx->m2l_variant >= 0 ? ctx->m2l_variant : ch.variant;
-      if (v < 0) {
-        if ((rc = tune_m2l(ctx, ch, n_rhs, s))) return rc;
-        v = ch.variant >= 0 ? ch.variant : 0;
+      if (v < 0 && w.tune) {
+        if ((rc = tune_m2l(ctx, d, w, ch, n_rhs, s))) return rc;
+        v = ch.variant;
       }
+      if (v < 0) v = 0;
       mark(LM_PHASES + 1 + 2 * c);
-      launch_m2l(d, d.tiles + ch.tile0, ch.ntile, n_rhs, ctx->ME, ctx->Y, ctx->pmax, v, s);
+      launch_m2l(d, d.tiles + ch.tile0, ch.ntile, n_rhs, w.ME, w.Y, ctx->pmax, v, s);
       mark(LM_PHASES + 2 + 2 * c);
-      launch_m2l_reduce(d, ch.bt0, ch.nbt, n_rhs, ctx->Y, ctx->LE, ctx->pmax, s);
+      launch_m2l_reduce(d, ch.bt0, ch.nbt, n_rhs, w.Y, w.LE, ctx->pmax, s);
     }
     mark(4);
     for (int l = 1; l < (int)ctx->d_l2l.size(); l++)
-      launch_l2l(d, ctx->d_l2l[l], ctx->n_l2l[l], n_rhs, ctx->LE, ctx->pmax, s);
+      launch_l2l(d, ctx->d_l2l[l], ctx->n_l2l[l], n_rhs, w.LE, ctx->pmax, s);
     mark(5);
     for (size_t g = 0; g < ctx->d_l2p.size(); g++) {
       const int i = ctx->l2p_inst[g];
       int kind = pl.inst[i].kind == 0 ? 0 : 1;
       if (grad)
-        launch_l2p_grad(d, ctx->d_l2p[g], ctx->n_l2p[g], kind, ctx->d_tgt, pl.n_tgt, n_rhs, ctx->LE, W, gX,
+        launch_l2p_grad(d, ctx->d_l2p[g], ctx->n_l2p[g], kind, ctx->d_tgt, pl.n_tgt, n_rhs, w.LE, W, gX,
                         pl.inst[i].p, s);
       else if (curl)
-        launch_l2p_curl(d, ctx->d_l2p[g], ctx->n_l2p[g], kind, ctx->d_tgt, pl.n_tgt, n_rhs, ctx->LE, Hc,
+        launch_l2p_curl(d, ctx->d_l2p[g], ctx->n_l2p[g], kind, ctx->d_tgt, pl.n_tgt, n_rhs, w.LE, Hc,
                         pl.inst[i].p, s);
       else
-        launch_l2p(d, ctx->d_l2p[g], ctx->n_l2p[g], kind, ctx->d_tgt, pl.n_tgt, n_rhs, ctx->LE, Ac, pl.inst[i].p, s);
+        launch_l2p(d, ctx->d_l2p[g], ctx->n_l2p[g], kind, ctx->d_tgt, pl.n_tgt, n_rhs, w.LE, Ac, pl.inst[i].p, s);
     }
     mark(6);
     for (size_t f = 0; f < ctx->d_p2p.size(); f++) {

@@ -32,6 +32,7 @@ class lm_params(ctypes.Structure):
                 ("m2l_variant", ctypes.c_int)]
 
 M2L_VARIANTS = 3
+NOALLOC_SCRATCH_BYTES = 256 << 20
 SOLVE_MAX_RESTART = 64
 
 
@@ -64,6 +65,7 @@ def load_library():
     lib.lm_set_params.argtypes = [vp, P(lm_params)]
     lib.lm_build.argtypes = [vp, ctypes.c_int64, D, ctypes.c_int64, D, vp]
     lib.lm_evaluate.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    lib.lm_evaluate_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     lib.lm_selftest_math.argtypes = [ctypes.c_int64, vp, vp, vp]
     lib.lm_build_batch.argtypes = [vp, ctypes.c_int, P(ctypes.c_int64), D, P(ctypes.c_int64), D, vp]
     lib.lm_evaluate_adjoint.argtypes = [vp, ctypes.c_int, vp, vp, vp]
@@ -195,6 +197,22 @@ class LayeredDyadicFMM:
             stream = torch.cuda.current_stream(J.device).cuda_stream
         self._check(self.lib.lm_evaluate(self.ctx, n_rhs, ctypes.c_void_p(Jr.data_ptr()),
                                          ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)))
+        return out.view(self.n_tgt, 3) if single else out.view(n_rhs, self.n_tgt, 3)
+
+    def evaluate_noalloc(self, J, out, stream=None):
+        """A = G J by lm_evaluate_noalloc: the library allocates nothing (its
+        work buffers live in a static device array of
+        NOALLOC_SCRATCH_BYTES per GPU); `out` must be given.  Calls that
+        overlap in time on one GPU race."""
+        import torch
+        if self.n_src is None:
+            raise LMError("build() must be called first")
+        single, n_rhs, Jr = self._rhs_view(J, self.n_src, "J")
+        out = self._out(out, (n_rhs, self.n_tgt, 3), torch.complex128, J)
+        if stream is None:
+            stream = torch.cuda.current_stream(J.device).cuda_stream
+        self._check(self.lib.lm_evaluate_noalloc(self.ctx, n_rhs, ctypes.c_void_p(Jr.data_ptr()),
+                                                 ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)))
         return out.view(self.n_tgt, 3) if single else out.view(n_rhs, self.n_tgt, 3)
 
     def evaluate_h(self, J, out=None, stream=None):
