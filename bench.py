@@ -24,6 +24,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "targets/s, 3-layer dyadic FMM N=1M p=12 at rel err≤1e-6; batched/adjoint vs plain"
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 fp64 FMA/clk x 2 flop x 2.4 GHz (fp64 MFMA: same)
+HBM_PEAK_GBS = 8000.0
+# algorithmic work of the near-field kernels (see the kernel table of the design notes):
+# free-space pair: distance, 1/r, e^{ikr} (one sincos), the a q + b R (R.q) dyadic form
+P2P_FLOPS_PER_PAIR = 100
+# direct reaction pair, per quadrature node: Z = exp(i (k_z t + k'_z u)), J0..J2 of
+# k_rho rho, and the five complex multiply-adds of the node's contribution
+S2T_FLOPS_PER_NODE = 100
 
 # HBM traffic of one k_m2l launch at the default workload (N=1e6, p=12,
 # p_free=20), from rocprofv3 FETCH_SIZE / WRITE_SIZE per dispatch scaled by a
@@ -45,18 +52,39 @@ def m2l_source_digest():
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
-def cpu_baseline(d, k, x, J, n_total, budget_s=15.0, threads=16):
+def host_cores():
+    """Host threads for the CPU baseline: the CPUs this process may run on,
+    at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(d, k, x, J, n_total, budget_s=15.0, budget_1core_s=8.0):
     """The oracle (direct Sommerfeld sum) timed on the host cores on a
-    bounded sample: nt sampled targets against ns sampled sources; the rate
-    is scaled to targets/s of the full N-source sum."""
+    bounded sample: 16 sampled targets against ns sampled sources, on every
+    core of the host share and on one core; the rates are scaled to
+    targets/s of the full N-source sum."""
     from oracle import oracle
+    threads = host_cores()
     rng = np.random.default_rng(11)
     ti = rng.choice(x.shape[0], 16, replace=False)
     si = rng.choice(x.shape[0], 200, replace=False)
     t = time.time()
     oracle.direct(d, k, x[si], J[si], x[ti], n_threads=threads)
     dt = time.time() - t
-    pairs = 16 * 200
     scale = max(1.0, min(50.0, budget_s / max(dt, 1e-3)))
     nt = 16
     ns = int(200 * scale)
@@ -66,9 +94,19 @@ def cpu_baseline(d, k, x, J, n_total, budget_s=15.0, threads=16):
     dt = time.time() - t
     pairs = nt * ns
     rate = pairs / dt
+    # one core: 4 targets against a source sample sized from the multi-core rate
+    ns1 = max(20, int(budget_1core_s * rate / threads / 4))
+    si1 = rng.choice(x.shape[0], ns1, replace=False)
+    t = time.time()
+    oracle.direct(d, k, x[si1], J[si1], x[ti[:4]], n_threads=1)
+    dt1 = time.time() - t
+    rate1 = 4 * ns1 / dt1
     return {"value": rate / n_total, "unit": "targets/s", "cores": threads, "kind": "oracle",
-            "sample": "%d sampled targets x %d sampled sources (%d pairs) in %.1f s; rate scaled to "
-                      "the full %d-source sum" % (nt, ns, pairs, dt, n_total)}
+            "cpu_model": cpu_model(),
+            "value_1core": rate1 / n_total,
+            "sample": "%d sampled targets x %d sampled sources (%d pairs) in %.1f s on %d threads; one core: "
+                      "4 targets x %d sources in %.1f s; rates scaled to the full %d-source sum" % (
+                          nt, ns, pairs, dt, threads, ns1, dt1, n_total)}
 
 
 def uneven_geometries(args, torch, inputs, lmfmm):
@@ -176,6 +214,53 @@ def coupled_dipole_solve(args, torch, inputs, lmfmm, n=1000000, n_rhs=1, tol=1e-
                                 "bytes": info["krylov_bytes"]}}
 
 
+def largest_config(args, torch, inputs, lmfmm, n=2000000, n_rhs=16):
+    """The largest configuration: four layers (interfaces 0, -1, -2.5; k =
+    1.0, 1.8, 2.4, 1.3), N = 2e6 points (half uniform, half in 20 Gaussian
+    clusters), p = 16 (free part p = 20), 16 current vectors in one call and
+    their adjoint; one warm-up, then one timed call each, with the M2L GEMM
+    roofline of the timed forward call."""
+    d, k, x, J = inputs.four_layer(n, seed=0, n_rhs=n_rhs)
+    t0 = time.time()
+    f = lmfmm.LayeredDyadicFMM(d, k, p=16, p_free=20, m2l_variant=0).build(x)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    st = f.stats()
+    Jt = torch.tensor(J, device="cuda:0")
+    del J
+    A = torch.empty_like(Jt)
+    f.evaluate(Jt, out=A)
+    torch.cuda.synchronize()
+    f.set_timing(True)
+    t0 = time.time()
+    f.evaluate(Jt, out=A)
+    torch.cuda.synchronize()
+    fwd_s = time.time() - t0
+    kt = f.kernel_timings()
+    f.set_timing(False)
+    gA = torch.tensor(inputs.cotangent(n, n_rhs=n_rhs, seed=0), device="cuda:0")
+    gJ = torch.empty_like(gA)
+    f.evaluate_adjoint(gA, out=gJ)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    f.evaluate_adjoint(gA, out=gJ)
+    torch.cuda.synchronize()
+    adj_s = time.time() - t0
+    f.close()
+    gms, gl = kt["m2l_gemm"]
+    ach = st["m2l_cmac_useful"] * 8.0 * n_rhs / (gms * 1e-3) / 1e12 if gms > 0 else None
+    print("largest: 2e6 points, 4 layers, p=16, %d rhs: forward %.2f s, adjoint %.2f s, build %.1f s" % (
+        n_rhs, fwd_s, adj_s, build_s), file=sys.stderr, flush=True)
+    return {"workload": "four-layer dyadic FMM, N=2e6 (half uniform, half in 20 Gaussian clusters), p=16 "
+                        "(free part 20), 16 complex128 current vectors and their adjoint",
+            "n": n, "n_rhs": n_rhs, "build_s": build_s,
+            "forward_s": fwd_s, "targets_rhs_per_s": n * n_rhs / fwd_s,
+            "adjoint_s": adj_s, "adjoint_targets_rhs_per_s": n * n_rhs / adj_s,
+            "roofline": {"bound": "mfma", "kernel": "k_m2l", "achieved": ach, "peak": FP64_VALU_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": None if ach is None else ach / FP64_VALU_PEAK_TFLOPS,
+                         "launches": gl, "gemm_ms": gms}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +277,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the iterative coupled-dipole solve")
     ap.add_argument("--no-magnetic", action="store_true", help="skip the magnetic-field evaluation")
     ap.add_argument("--no-selfconv", action="store_true", help="skip the p = 16 self-convergence check")
+    ap.add_argument("--no-largest", action="store_true",
+                    help="skip the four-layer 2e6-point p = 16 16-vector configuration")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint and source-gradient timings (profiling runs of the forward step)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -237,6 +324,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.time() - t0
     phases, ncalls = fmm.timings()
+    ktim = fmm.kernel_timings()
     gemm_ms_total, gemm_launches = fmm.m2l_gemm_timing()
     m2l_var, m2l_ms = fmm.m2l_variants(args.rhs)
     fmm.set_timing(False)
@@ -250,6 +338,47 @@ def main():
     m2l_flops = st["m2l_cmac_useful"] * 8.0 * args.rhs
     flops_per_launch = m2l_flops / max(1e-30, launches_per_step)
     achieved = flops_per_launch / (launch_ms * 1e-3) / 1e12
+    # executed MFMA work (three real products per complex step, padded 16 x 16
+    # tiles and k chunks): the matrix cores' own rate
+    exec_per_launch = st["m2l_flop_exec"] * args.rhs / max(1e-30, launches_per_step)
+    achieved_exec = exec_per_launch / (launch_ms * 1e-3) / 1e12
+
+    def kroof(name, bound, work_per_step, unit):
+        ms, launches = ktim[name]
+        if launches == 0 or ms <= 0:
+            return None
+        per_launch = work_per_step * ncalls / launches
+        sec = ms * 1e-3 / launches
+        if unit == "GB/s":
+            a = per_launch / sec / 1e9
+            pk = HBM_PEAK_GBS
+        else:
+            a = per_launch / sec / 1e12
+            pk = FP64_VALU_PEAK_TFLOPS
+        return {"bound": bound, "achieved": a, "peak": pk, "unit": unit, "frac": a / pk,
+                "launch_ms": ms / launches, "launches_per_step": launches / max(1, ncalls),
+                "work_per_launch": per_launch}
+
+    kernels = {
+        "k_m2l_reduce": kroof("m2l_reduce", "hbm", st["reduce_bytes"] * args.rhs, "GB/s"),
+        "k_p2p": kroof("p2p", "alu", st["p2p_pairs"] * P2P_FLOPS_PER_PAIR * args.rhs, "TFLOP/s"),
+        # the direct pairs' integrals are formed once per group of up to 4 vectors
+        "k_s2t": kroof("s2t", "alu", st["s2t_node_evals"] * S2T_FLOPS_PER_NODE * ((args.rhs + 3) // 4), "TFLOP/s"),
+    }
+    # whole path: the sum of each kernel's ideal time at its own peak over the
+    # measured time of the step
+    t_ideal = (m2l_flops + st["p2p_pairs"] * P2P_FLOPS_PER_PAIR * args.rhs
+               + st["s2t_node_evals"] * S2T_FLOPS_PER_NODE * ((args.rhs + 3) // 4)
+               + (st["p2m_flops"] + st["m2m_flops"] + st["l2l_flops"] + st["l2p_flops"]) * args.rhs
+               ) / (FP64_VALU_PEAK_TFLOPS * 1e12)
+    t_ideal += (st["reduce_bytes"] * args.rhs
+                + (st["me_bytes_per_rhs"] + 2 * st["le_bytes_per_rhs"]) * args.rhs
+                + 2 * 48.0 * args.n * args.rhs) / (HBM_PEAK_GBS * 1e9)
+    path = {"t_ideal_ms": 1e3 * t_ideal, "t_measured_ms": ms_per_step, "frac": 1e3 * t_ideal / ms_per_step,
+            "rule": "sum over kernels of algorithmic flops / 78.6 TFLOP/s (M2L, near field at %d flops per "
+                    "pair, direct reaction pairs at %d flops per quadrature node, P2M/M2M/L2L/L2P at 8 flops "
+                    "per complex multiply-add) plus bytes / 8 TB/s (M2L reduction, expansion clears, "
+                    "reading J and writing A)" % (P2P_FLOPS_PER_PAIR, S2T_FLOPS_PER_NODE)}
     print("timed: %.1f ms/step, phases (ms/step): %s" % (
         ms_per_step, {a: round(b / max(1, ncalls), 2) for a, b in phases.items()}), file=sys.stderr, flush=True)
 
@@ -309,20 +438,32 @@ def main():
                     "errmax": float(np.max(np.linalg.norm(dA, axis=1) / np.linalg.norm(A0, axis=1)))}
     selfconv = None
     if not args.no_accuracy and not args.no_selfconv and args.rhs == 1:
-        # the reaction expansions at p = 16 against p = 12 (free part unchanged)
-        # for the 400-source sparse currents of the oracle check, at its
-        # sampled targets (over all targets the near field of the 400
-        # sources, identical in both, dominates the norm)
-        Jsp = torch.tensor(inputs.sparse_currents(J, 400, seed=0)[0], device=dev)
-        idx_s = torch.tensor(inputs.sample_targets(args.n, count=128, seed=0), device=dev)
-        f16 = lmfmm.LayeredDyadicFMM(d, k, p=16, p_free=args.p_free, device=0).build(x)
-        A16 = f16.evaluate(Jsp)[idx_s]
-        A12 = fmm.evaluate(Jsp)[idx_s]
-        selfconv = float(torch.linalg.vector_norm(A12 - A16).item() / torch.linalg.vector_norm(A16).item())
+        # the benchmark's dense currents at every target: the evaluation at
+        # the benchmark's orders against one with both orders raised
+        # (reaction 12 -> 16, free part 20 -> 24)
+        A12 = A[0]
+        f16 = lmfmm.LayeredDyadicFMM(d, k, p=args.p + 4, p_free=args.p_free + 4, device=0).build(x)
+        A16 = f16.evaluate(Jt.reshape(args.n, 3))
         f16.close()
-        del A16, A12, Jsp
-        print("self-convergence: |A(p=12) - A(p=16)| / |A(p=16)| = %.2e at 128 sampled targets" % selfconv,
-              file=sys.stderr, flush=True)
+        diff = torch.linalg.vector_norm(A12 - A16, dim=1)
+        ref = torch.linalg.vector_norm(A16, dim=1)
+        selfconv = {"orders": [args.p, args.p_free, args.p + 4, args.p_free + 4],
+                    "rel_l2_all_targets": float(torch.linalg.vector_norm(diff).item()
+                                                / torch.linalg.vector_norm(ref).item()),
+                    "per_layer": {}}
+        zt = torch.tensor(x[:, 2], device=dev)
+        lay = torch.zeros_like(zt, dtype=torch.int64)
+        for dl in d:
+            lay += (zt < dl).to(torch.int64)
+        for l in range(len(d) + 1):
+            sel = lay == l
+            selfconv["per_layer"][str(l)] = {
+                "err2": float(torch.linalg.vector_norm(diff[sel]).item() / torch.linalg.vector_norm(ref[sel]).item()),
+                "errmax": float(torch.max(diff[sel] / ref[sel]).item())}
+        del A16, diff, ref
+        print("self-convergence (dense currents, all targets): |A(p=%d,%d) - A(p=%d,%d)| / |A| = %.2e" % (
+            args.p, args.p_free, args.p + 4, args.p_free + 4, selfconv["rel_l2_all_targets"]),
+            file=sys.stderr, flush=True)
     magnetic = None
     if not args.no_magnetic:
         # magnetic field of the same currents (curl of the electric field); the
@@ -346,6 +487,7 @@ def main():
     uneven = None if args.no_uneven else uneven_geometries(args, torch, inputs, lmfmm)
     batched = None if args.no_batched else batched_rhs(args, torch, inputs, lmfmm)
     solve = None if args.no_solve else coupled_dipole_solve(args, torch, inputs, lmfmm)
+    largest = None if args.no_largest else largest_config(args, torch, inputs, lmfmm)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(d, k, x, J if args.rhs == 1 else J[0], args.n)
@@ -368,11 +510,16 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "k_m2l", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": traffic,
                      "launch_ms": launch_ms, "launches_per_step": launches_per_step,
-                     "algorithmic_flops_per_launch": flops_per_launch},
+                     "algorithmic_flops_per_launch": flops_per_launch,
+                     "executed_flops_per_launch": exec_per_launch,
+                     "achieved_executed": achieved_exec,
+                     "frac_executed": achieved_exec / FP64_VALU_PEAK_TFLOPS},
+        "roofline_kernels": kernels,
+        "roofline_path": path,
         "cpu_baseline": cpu,
         "rel_err_vs_oracle": acc,
         "rel_err_vs_oracle_per_layer": err_layers,
-        "self_convergence_p12_vs_p16": selfconv,
+        "self_convergence_dense": selfconv,
         "build_s": build_s,
         "cold_targets_per_s": args.n * args.rhs / (build_s + wall / args.steps),
         "phase_ms_per_step": {a: b / max(1, ncalls) for a, b in phases.items()},
@@ -385,6 +532,7 @@ def main():
         "uneven_geometries": uneven,
         "batched_rhs": batched,
         "solve": solve,
+        "largest": largest,
         "magnetic": magnetic,
         "m2l_autotune": {"chosen_variant_per_launch": m2l_var,
                          "tuning_ms_per_step_by_variant": [round(float(v), 3) for v in m2l_ms.sum(axis=0)],

@@ -81,10 +81,11 @@ typedef struct {
                       /* target leaves are adjacent (every reaction interaction   */
                       /* is an M2L).  1 (default): a tree stops one level earlier */
                       /* where a cost model finds the direct near field cheaper   */
-                      /* than that level's M2L work; 2: always one level earlier. */
+                      /* than that level's M2L work; 2: always one level earlier; */
+                      /* 3: every reaction pair direct (single-box reaction trees:*/
+                      /* the decomposition of Sec. 3.1 without expansions).       */
                       /* Leaves that stay adjacent interact directly through the  */
                       /* component's Sommerfeld integral (S2T, Sec. 3.3/3.4).     */
-                      /* Source-position gradients use a second plan with 0.      */
   int m2l_variant;    /* tile shape of the M2L GEMM kernel: -1 (default) tunes each */
                       /* launch of the schedule on its first eager evaluation and  */
                       /* keeps the fastest; 0..LM_M2L_VARIANTS-1 fixes one (0: 16  */
@@ -223,13 +224,14 @@ int lm_grad_src_xyz(lm_ctx* ctx, int n_rhs, const void* J, const void* gA, doubl
 
 /* Phase timing.  lm_set_timing(ctx, 1) (re)starts recording HIP events on
  * the evaluation stream between the phases of every following lm_evaluate
- * and around every launch of the M2L GEMM kernel; lm_timings() waits for the
- * recorded events and writes up to n values, summed over the timed
- * evaluations: the milliseconds of each phase (indices LM_PHASE_*), the
- * number of timed evaluations (index LM_PHASES), the milliseconds spent in
- * the M2L GEMM kernel alone (LM_TIMING_M2L_GEMM_MS, part of LM_PHASE_M2L,
- * which also holds the per-target reduction) and the number of its launches
- * (LM_TIMING_M2L_GEMM_LAUNCHES). */
+ * and around every launch of the M2L GEMM kernel, the M2L reduction and the
+ * near-field kernels; lm_timings() waits for the recorded events and writes
+ * up to n values, summed over the timed evaluations: the milliseconds of
+ * each phase (indices LM_PHASE_*), the number of timed evaluations (index
+ * LM_PHASES), and for each of those kernels the milliseconds spent in it and
+ * the number of its launches (LM_TIMING_*_MS, LM_TIMING_*_LAUNCHES; the M2L
+ * GEMM and reduction are parts of LM_PHASE_M2L, the near-field kernels of
+ * LM_PHASE_P2P). */
 int lm_set_timing(lm_ctx* ctx, int enable);
 int lm_timings(lm_ctx* ctx, double* out_host, int n);
 
@@ -243,7 +245,13 @@ int lm_timings(lm_ctx* ctx, double* out_host, int n);
 #define LM_PHASES 7
 #define LM_TIMING_M2L_GEMM_MS (LM_PHASES + 1)
 #define LM_TIMING_M2L_GEMM_LAUNCHES (LM_PHASES + 2)
-#define LM_TIMINGS_COUNT (LM_PHASES + 3)
+#define LM_TIMING_M2L_REDUCE_MS (LM_PHASES + 3)      /* per-target sums of the M2L outputs  */
+#define LM_TIMING_M2L_REDUCE_LAUNCHES (LM_PHASES + 4)
+#define LM_TIMING_P2P_MS (LM_PHASES + 5)             /* free-space near field                */
+#define LM_TIMING_P2P_LAUNCHES (LM_PHASES + 6)
+#define LM_TIMING_S2T_MS (LM_PHASES + 7)             /* direct reaction pairs               */
+#define LM_TIMING_S2T_LAUNCHES (LM_PHASES + 8)
+#define LM_TIMINGS_COUNT (LM_PHASES + 9)
 
 /* The M2L GEMM variant of each launch of the evaluation schedule for n_rhs
  * right-hand sides (one launch per chunk, in evaluation order).  HOST arrays:
@@ -278,7 +286,17 @@ int lm_stats(const lm_ctx* ctx, double* out_host, int n);
 #define LM_STAT_N_LEAVES_P2M 19
 #define LM_STAT_FREE_DEPTH 20
 #define LM_STAT_S2T_PAIRS 21         /* reaction near-field (S2T) point pairs        */
-#define LM_STATS_COUNT 22
+#define LM_STAT_M2L_FLOP_EXEC 22     /* MFMA flops the M2L GEMM executes per rhs (16x16 */
+                                     /* tiles inside the orders and pair counts, k padded */
+                                     /* to 16, three real MFMAs per complex step)        */
+#define LM_STAT_P2M_FLOPS 23         /* algorithmic flops per rhs: 8 per complex          */
+#define LM_STAT_M2M_FLOPS 24         /* multiply-add of the expansion sums (P2M, L2P)     */
+#define LM_STAT_L2L_FLOPS 25         /* and the dense translations (M2M, L2L)             */
+#define LM_STAT_L2P_FLOPS 26
+#define LM_STAT_REDUCE_BYTES 27      /* bytes the M2L reduction must move per rhs         */
+#define LM_STAT_S2T_NODE_EVALS 28    /* quadrature nodes summed over the direct reaction  */
+                                     /* pairs (each pair stops at its own cut)            */
+#define LM_STATS_COUNT 29
 
 /* ---- iterative solve over the evaluation ---- */
 

@@ -72,7 +72,12 @@ struct lm_ctx {
   double t_plan_ms = 0, t_upload_ms = 0, t_tables_ms = 0;
   int pmax = 0;
   bool timing = false;
-  std::vector<std::vector<hipEvent_t>> evsets;  // per timed evaluation: LM_PHASES+1 events
+  struct EvSet {
+    std::vector<hipEvent_t> ph;  // phase boundaries (LM_PHASES + 1)
+    std::vector<int> kind;       // per timed launch: 0 M2L GEMM, 1 M2L reduction, 2 P2P, 3 S2T
+    std::vector<hipEvent_t> sp;  // per timed launch: start and stop
+  };
+  std::vector<EvSet> evsets;  // per timed evaluation
   // adjoint and gradients
   bool p2p_red = false;                   // near-field arguments k r bounded: reduced-range sincos
   bool same_sets = false;                 // sources and targets are the same point array
@@ -104,8 +109,10 @@ struct lm_ctx {
 extern "C" int lm_destroy(lm_ctx* ctx);
 
 static void clear_events(lm_ctx* ctx) {
-  for (auto& v : ctx->evsets)
-    for (auto e : v) hipEventDestroy(e);
+  for (auto& v : ctx->evsets) {
+    for (auto e : v.ph) hipEventDestroy(e);
+    for (auto e : v.sp) hipEventDestroy(e);
+  }
   ctx->evsets.clear();
 }
 
@@ -329,7 +336,7 @@ int lm_set_params(lm_ctx* ctx, const lm_params* p) {
   if (p->m2l_adapt != 0 && p->m2l_adapt != 1) return fail(ctx, LM_EINVAL, "m2l_adapt must be 0 or 1");
   if (p->m2l_adapt && !(p->m2l_margin >= 0 && p->m2l_margin <= 30))
     return fail(ctx, LM_EINVAL, "m2l_margin out of range (0..30 decades)");
-  if (p->react_s2t < 0 || p->react_s2t > 2) return fail(ctx, LM_EINVAL, "react_s2t must be 0, 1 or 2");
+  if (p->react_s2t < 0 || p->react_s2t > 3) return fail(ctx, LM_EINVAL, "react_s2t must be 0, 1, 2 or 3");
   if (p->m2l_variant < -1 || p->m2l_variant >= LM_M2L_VARIANTS)
     return fail(ctx, LM_EINVAL, "m2l_variant must be -1 (autotune) or 0.." + std::to_string(LM_M2L_VARIANTS - 1));
   PlanParams q;
@@ -1095,15 +1102,25 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
   DevPlan d = ctx->d;  // this evaluation's schedule
   d.tiles = w.ts->d_tiles;
   d.blk_ybase = w.ts->d_ybase;
-  std::vector<hipEvent_t> ev;
   const int nch = (int)w.ts->chunks.size();
-  if (w.timed && ctx->timing && ctx->evsets.size() < 4096) {
-    // phase boundaries, then a start/stop pair around every M2L GEMM launch
-    ev.resize(LM_PHASES + 1 + 2 * nch);
-    for (auto& e : ev) HIPC(hipEventCreate(&e));
+  lm_ctx::EvSet ev;
+  const bool timed = w.timed && ctx->timing && ctx->evsets.size() < 4096;
+  if (timed) {
+    // phase boundaries, then a start/stop pair around every launch of the
+    // M2L GEMM, the M2L reduction and the near-field kernels
+    ev.ph.resize(LM_PHASES + 1);
+    for (auto& e : ev.ph) HIPC(hipEventCreate(&e));
   }
   auto mark = [&](int i) {
-    if (!ev.empty()) (void)hipEventRecord(ev[i], s);
+    if (timed) (void)hipEventRecord(ev.ph[i], s);
+  };
+  auto span = [&](int kind, bool start) {
+    if (!timed) return;
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    if (start) ev.kind.push_back(kind);
+    ev.sp.push_back(e);
+    (void)hipEventRecord(e, s);
   };
   mark(0);
   if (curl)
@@ -1138,10 +1155,12 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
         v = ch.variant;
       }
       if (v < 0) v = 0;
-      mark(LM_PHASES + 1 + 2 * c);
+      span(0, true);
       launch_m2l(d, d.tiles + ch.tile0, ch.ntile, n_rhs, w.ME, w.Y, ctx->pmax, v, s);
-      mark(LM_PHASES + 2 + 2 * c);
+      span(0, false);
+      span(1, true);
       launch_m2l_reduce(d, ch.bt0, ch.nbt, n_rhs, w.Y, w.LE, ctx->pmax, s);
+      span(1, false);
     }
     mark(4);
     for (int l = 1; l < (int)ctx->d_l2l.size(); l++)
@@ -1161,6 +1180,7 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
     }
     mark(6);
     for (size_t f = 0; f < ctx->d_p2p.size(); f++) {
+      span(2, true);
       if (grad)
         launch_p2p_grad(d, ctx->d_p2p[f], ctx->n_p2p[f], ctx->d_src, Jc, pl.n_src, ctx->d_tgt, W, pl.n_tgt, n_rhs,
                         gX, ctx->p2p_red, s);
@@ -1170,21 +1190,23 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
       else
         launch_p2p(d, ctx->d_p2p[f], ctx->n_p2p[f], ctx->d_src, Jc, pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs, Ac,
                    ctx->p2p_red, s);
+      span(2, false);
     }
     for (auto& r : ctx->s2t_ranges) {
+      span(3, true);
       if (grad)
         launch_s2t_grad(d, ctx->md, ctx->d_s2t + 2 * r.item0, r.n, ctx->d_src, Jc, pl.n_src, ctx->d_tgt, W,
                         pl.n_tgt, n_rhs, ctx->contour_a, r.smallz, gX, s);
       else
         launch_s2t(d, ctx->md, ctx->d_s2t + 2 * r.item0, r.n, ctx->d_src, Jc, pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs,
                    ctx->contour_a, r.smallz, curl ? Hc : Ac, s, curl);
+      span(3, false);
     }
     mark(7);
   } else {
     for (int i = 2; i <= 7; i++) mark(i);
-    for (int c = 0; c < 2 * nch; c++) mark(LM_PHASES + 1 + c);
   }
-  if (!ev.empty()) ctx->evsets.push_back(ev);
+  if (timed) ctx->evsets.push_back(ev);
   HIPC(hipGetLastError());
   return LM_OK;
 }
@@ -1202,17 +1224,18 @@ int lm_timings(lm_ctx* ctx, double* out, int n) {
   HIPC(hipSetDevice(ctx->device));
   double acc[LM_TIMINGS_COUNT] = {0};
   for (auto& v : ctx->evsets) {
-    HIPC(hipEventSynchronize(v[LM_PHASES]));
+    HIPC(hipEventSynchronize(v.ph[LM_PHASES]));
     for (int i = 0; i < LM_PHASES; i++) {
       float ms = 0;
-      HIPC(hipEventElapsedTime(&ms, v[i], v[i + 1]));
+      HIPC(hipEventElapsedTime(&ms, v.ph[i], v.ph[i + 1]));
       acc[i] += ms;
     }
-    for (size_t j = LM_PHASES + 1; j + 1 < v.size(); j += 2) {
+    for (size_t j = 0; j < v.kind.size() && 2 * j + 1 < v.sp.size(); j++) {
       float ms = 0;
-      HIPC(hipEventElapsedTime(&ms, v[j], v[j + 1]));
-      acc[LM_TIMING_M2L_GEMM_MS] += ms;
-      acc[LM_TIMING_M2L_GEMM_LAUNCHES] += 1;
+      HIPC(hipEventElapsedTime(&ms, v.sp[2 * j], v.sp[2 * j + 1]));
+      const int slot = LM_TIMING_M2L_GEMM_MS + 2 * v.kind[j];
+      acc[slot] += ms;
+      acc[slot + 1] += 1;
     }
   }
   acc[LM_PHASES] = (double)ctx->evsets.size();
@@ -1277,6 +1300,87 @@ int lm_stats(const lm_ctx* ctx, double* out, int n) {
     }
     v[LM_STAT_M2L_CMAC_USEFUL] = cm;
     v[LM_STAT_M2L_CMAC_EXEC] = ce;
+  }
+  {
+    // executed MFMA flops of the M2L GEMM per rhs (variant 0: 16 values of k
+    // per chunk): a wave computes the 16 x 16 tiles that hold a row below
+    // the offset's (pord+1)^2 and a column below the tile's pair count, over
+    // k padded to whole chunks, with three real MFMAs per complex step
+    double fe = 0;
+    for (const M2LBlock& B : pl.blocks) {
+      const M2LClass& C = pl.cls[B.cls];
+      for (int o = 0; o < C.n_off; o++) {
+        const long long np = pl.offr[B.offr0 + o + 1] - pl.offr[B.offr0 + o];
+        if (np == 0) continue;
+        const int po = pl.offs[C.off0 + o].pord, Po = (po + 1) * (po + 1);
+        const double rows = (double)((Po + 15) / 16) * 16, cols = (double)((np + 15) / 16) * 16;
+        const double kp = (double)((C.nblk * Po + 15) / 16) * 16;
+        fe += 3.0 * rows * cols * kp * 3.0 * 2.0;
+      }
+    }
+    v[LM_STAT_M2L_FLOP_EXEC] = fe;
+  }
+  {
+    // algorithmic work of the other passes per rhs: 8 flops per complex
+    // multiply-add of the expansion sums and translations; the M2L
+    // reduction's bytes (outputs read once, local expansions read and
+    // written once)
+    double f_p2m = 0, f_m2m = 0, f_l2l = 0, f_l2p = 0, b_red = 0;
+    for (int b : pl.p2m_leaves) {
+      const SrcBox& sb = pl.sbox[b];
+      f_p2m += (double)(sb.pt1 - sb.pt0) * 3.0 * pl.inst[sb.inst].P * 8.0;
+    }
+    for (size_t b = 0; b < pl.sbox.size(); b++)
+      if (pl.sbox_m2m[b] >= 0) f_m2m += 3.0 * (double)pl.inst[pl.sbox[b].inst].P * pl.inst[pl.sbox[b].inst].P * 8.0;
+    for (size_t b = 0; b < pl.tbox.size(); b++)
+      if (pl.tbox_l2l[b] >= 0) f_l2l += 3.0 * (double)pl.inst[pl.tbox[b].inst].P * pl.inst[pl.tbox[b].inst].P * 8.0;
+    for (size_t i = 0; i < pl.l2p_leaves.size(); i++) {
+      const int p = pl.inst[i].p, pe = pl.inst[i].kind == 0 ? p + 2 : p;
+      for (int b : pl.l2p_leaves[i])
+        f_l2p += (double)(pl.tbox[b].pt1 - pl.tbox[b].pt0) * 3.0 * (pe + 1) * (pe + 1) * 8.0;
+    }
+    for (size_t q = 0; q < pl.pair_P.size(); q++) b_red += 3.0 * pl.pair_P[q] * 16.0;
+    for (size_t bt = 0; bt < pl.bt_tbox.size(); bt++) b_red += 2.0 * 3.0 * pl.inst[pl.tbox[pl.bt_tbox[bt]].inst].P * 16.0;
+    v[LM_STAT_P2M_FLOPS] = f_p2m;
+    v[LM_STAT_M2M_FLOPS] = f_m2m;
+    v[LM_STAT_L2L_FLOPS] = f_l2l;
+    v[LM_STAT_L2P_FLOPS] = f_l2p;
+    v[LM_STAT_REDUCE_BYTES] = b_red;
+  }
+  {
+    // quadrature nodes summed over the direct reaction pairs: each pair runs
+    // the first contour piece and the real tail up to its own cut
+    // a + LM_S2T_DIGITS / (t + u) (needs the host copies of the points)
+    double ne = 0;
+    const bool have = !ctx->host_src.empty() && !ctx->host_tgt.empty();
+    for (size_t it = 0; have && it < pl.s2t_items.size(); it += 2) {
+      if (pl.s2t_items[it + 1] != 0) continue;  // one entry per leaf
+      const TgtBox& tb = pl.tbox[pl.s2t_items[it]];
+      const InstParams& ip = pl.inst[tb.inst];
+      const cd* kr = pl.node_kr.data() + ip.s2t0;
+      int n1 = 0;
+      while (n1 < ip.s2tn && kr[n1].y != 0.0) n1++;  // first piece (complex nodes)
+      const double dls = ip.up_s ? ctx->med.d[ip.ls - 1] : ctx->med.d[ip.ls];
+      for (int t = tb.pt0; t < tb.pt1; t++) {
+        const double zt = ctx->host_tgt[3 * pl.tgt_perm[t] + 2];
+        const double tz = ip.up_t ? zt - ctx->med.d[ip.lt] : ctx->med.d[ip.lt - 1] - zt;
+        for (int li = tb.p2p0; li < tb.p2p1; li++) {
+          const SrcBox& sb = pl.sbox[pl.p2p_list[li]];
+          for (int sp = sb.pt0; sp < sb.pt1; sp++) {
+            const double zs = ctx->host_src[3 * pl.src_perm[sp] + 2];
+            const double uz = ip.up_s ? dls - zs : zs - dls;
+            const double kcut = ctx->contour_a + LM_S2T_DIGITS / (tz + uz);
+            int lo = n1, hi = ip.s2tn;  // tail nodes <= kcut (increasing)
+            while (lo < hi) {
+              const int mid = (lo + hi) / 2;
+              if (kr[mid].x <= kcut) lo = mid + 1; else hi = mid;
+            }
+            ne += (double)lo;
+          }
+        }
+      }
+    }
+    v[LM_STAT_S2T_NODE_EVALS] = ne;
   }
   v[LM_STAT_N_LEAVES_P2M] = (double)pl.p2m_leaves.size();
   double fd = 0;

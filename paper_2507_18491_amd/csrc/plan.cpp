@@ -742,6 +742,10 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
         const bool series_range = a_c * 2.0 * M_SQRT2 * sb <= 7.5;
         if (prm.react_s2t == 2 || (series_range && c_s2t < c_m2l)) Dmax = D1 - 1;
       }
+      // every reaction pair direct: single-box trees, whose one source and
+      // one target box are adjacent (the component's Sommerfeld integral for
+      // every pair, no expansion and no truncation of the method)
+      if (prm.react_s2t == 3) Dmax = 0;
       depth_used = Dmax;
       auto rule = [&](int l, int n, int j, double) { return n > 0 && l < Dmax && j == 0; };
       build_tree(S, g.spos, g.sid, std::vector<int>(g.sid.size(), 0), rule);

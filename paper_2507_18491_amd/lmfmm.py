@@ -17,7 +17,8 @@ STAT_NAMES = ["n_free_inst", "n_react_inst", "m2l_pairs_free", "m2l_pairs_react"
               "n_cases", "n_nodes", "mat_bytes", "me_bytes_per_rhs", "le_bytes_per_rhs",
               "t_plan_ms", "t_upload_ms", "t_tables_ms", "n_src_boxes", "n_tgt_boxes",
               "n_m2l_classes", "n_m2l_tiles_1rhs", "m2l_cmac_useful", "m2l_cmac_exec",
-              "n_leaves_p2m", "free_depth", "s2t_pairs"]
+              "n_leaves_p2m", "free_depth", "s2t_pairs", "m2l_flop_exec", "p2m_flops", "m2m_flops",
+              "l2l_flops", "l2p_flops", "reduce_bytes", "s2t_node_evals"]
 
 
 PHASE_NAMES = ["clear", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p"]
@@ -394,6 +395,19 @@ class LayeredDyadicFMM:
         self._check(self.lib.lm_timings(self.ctx, _dp(buf), buf.size))
         n = len(PHASE_NAMES)
         return dict(zip(PHASE_NAMES, buf[:n].tolist())), int(buf[n])
+
+    KERNEL_TIMING_NAMES = ["m2l_gemm", "m2l_reduce", "p2p", "s2t"]
+
+    def kernel_timings(self):
+        """{kernel: (milliseconds, launches)} summed over the timed
+        evaluations, from HIP events around each launch of the M2L GEMM, the
+        M2L reduction, the free-space near field and the direct reaction
+        pairs on the evaluation stream."""
+        n = len(PHASE_NAMES)
+        buf = np.zeros(n + 1 + 2 * len(self.KERNEL_TIMING_NAMES))
+        self._check(self.lib.lm_timings(self.ctx, _dp(buf), buf.size))
+        return {nm: (float(buf[n + 1 + 2 * i]), int(buf[n + 2 + 2 * i]))
+                for i, nm in enumerate(self.KERNEL_TIMING_NAMES)}
 
     def m2l_gemm_timing(self):
         """Milliseconds spent in the M2L GEMM kernel alone (HIP events around

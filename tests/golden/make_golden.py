@@ -28,7 +28,7 @@ def tiny():
     np.savez_compressed(os.path.join(OUT, "tiny_oracle.npz"), A=A, A_free=Af, seed=0)
 
 
-def scale_sparse(n=100000, n_active=400, n_tgt=128):
+def scale_sparse(n=100000, n_active=400, n_tgt=256):
     """Three-layer workload at n points with only n_active nonzero currents;
     oracle on n_tgt sampled targets (sampled outputs at full size)."""
     d, k, x, J = inputs.three_layer(n, seed=0)
@@ -124,7 +124,7 @@ def largest_sparse(n=2000000, n_rhs=16, n_active=400, n_tgt=128):
                         idx=idx, keep=keep, gJ=gJ, idx_s=idx_s, keep_a=keep_a, seed=0)
 
 
-def batched_sparse(n=200000, n_rhs=64, n_active=400, n_tgt=64):
+def batched_sparse(n=200000, n_rhs=64, n_active=400, n_tgt=256):
     """Three-layer workload at n points with n_rhs current vectors sharing
     n_active nonzero sources; the oracle at n_tgt sampled targets."""
     d, k, x, J = inputs.three_layer(n, seed=0, n_rhs=n_rhs)
@@ -133,6 +133,31 @@ def batched_sparse(n=200000, n_rhs=64, n_active=400, n_tgt=64):
     A = oracle.direct(d, k, x[keep], J[:, keep], x[idx])
     np.savez_compressed(os.path.join(OUT, "three_%d_rhs%d_sparse%d_oracle.npz" % (n, n_rhs, n_active)), A=A,
                         idx=idx, keep=keep, seed=0)
+
+
+def scale_dense(n=100000, n_tgt=8):
+    """Three-layer workload at n points with every current nonzero (the
+    benchmark's dense currents); the oracle at n_tgt sampled targets (each
+    target sums all n sources: about 6 minutes per target on 8 cores)."""
+    d, k, x, J = inputs.three_layer(n, seed=0)
+    idx = inputs.sample_targets(n, n_tgt, seed=0)
+    A = oracle.direct(d, k, x, J, x[idx])
+    np.savez_compressed(os.path.join(OUT, "three_%d_dense_oracle.npz" % n), A=A, idx=idx, seed=0)
+
+
+def uneven_sparse(n_geom=32, n_active=200, n_tgt=8):
+    """The 32 uneven clustered three-layer geometries (5e3..2e5 points each):
+    per geometry, n_active nonzero currents and the oracle at n_tgt sampled
+    targets of that geometry (only same-geometry pairs interact)."""
+    d, k, xs, Js = inputs.uneven_geometries(n_geom, seed=0)
+    out = {}
+    for g, (x, J) in enumerate(zip(xs, Js)):
+        Jg, keep = inputs.sparse_currents(J, n_active, seed=g)
+        idx = inputs.sample_targets(x.shape[0], n_tgt, seed=g)
+        out["A%d" % g] = oracle.direct(d, k, x[keep], J[keep], x[idx])
+        out["idx%d" % g] = idx
+        out["keep%d" % g] = keep
+    np.savez_compressed(os.path.join(OUT, "uneven_%d_sparse%d_oracle.npz" % (n_geom, n_active)), seed=0, **out)
 
 
 if __name__ == "__main__":
@@ -152,6 +177,11 @@ if __name__ == "__main__":
             largest_sparse()
         elif nm == "batched":
             batched_sparse()
+        elif nm == "uneven":
+            uneven_sparse()
+        elif nm.startswith("dense"):
+            parts = nm.split(":")
+            scale_dense(n=int(parts[1]) if len(parts) > 1 else 100000)
         elif nm.startswith("scale"):
             parts = nm.split(":")
             n = int(parts[1]) if len(parts) > 1 else 100000

@@ -369,3 +369,41 @@ def test_coarse_trees_subset(tiny, p):
     e = rel(A, ref)
     print("  rel err %.2e" % e, flush=True)
     assert e < COARSE_TOL[p]
+
+
+def test_all_reaction_pairs_direct_equals_oracle(tiny):
+    """Every reaction pair through its component's Sommerfeld integral
+    (react_s2t = 3: single-box reaction trees, no expansions): the paper's
+    decomposition of the reaction field into components at images and
+    effective locations (sigma_1..sigma_5 with the sigma_3 reading, the Z
+    functions and signs) equals the oracle's undecomposed reaction field to
+    the quadrature's accuracy, with no truncation of the method in between
+    (recorded 8.2e-11 over all 600 targets)."""
+    d, k, x, J, g = tiny
+    print("case tiny, reaction part, every pair direct", flush=True)
+    f = lmfmm.LayeredDyadicFMM(d, k, p=8, components=2, react_s2t=3).build(x)
+    st = f.stats()
+    assert st["m2l_pairs_react"] == 0 and st["s2t_pairs"] == 600 * 600
+    A = f.evaluate(torch.tensor(J, device="cuda")).cpu().numpy()
+    f.close()
+    e = rel(A, g["A"] - g["A_free"])
+    print("  rel L2 = %.3e" % e, flush=True)
+    assert e < 2e-10
+
+
+def test_all_reaction_pairs_direct_with_mu_equals_oracle():
+    """The same on three layers with permeabilities, targets distinct from
+    the sources (oracle computed live)."""
+    from oracle import oracle
+    d, k, src, J = inputs.three_layer(90, seed=21, half_width=1.0)
+    _, _, tgt, _ = inputs.three_layer(60, seed=22, half_width=1.0)
+    mu = [1.0, 1.8, 0.7]
+    print("case three layers with mu, every reaction pair direct, 90 x 60", flush=True)
+    f = lmfmm.LayeredDyadicFMM(d, k, mu=mu, p=8, components=2, react_s2t=3).build(src, tgt)
+    A = f.evaluate(torch.tensor(J, device="cuda")).cpu().numpy()
+    f.close()
+    full = oracle.direct(d, k, src, J, tgt, mu=mu)
+    free = oracle.direct_free(d, k, src, J, tgt)
+    e = rel(A, full - free)
+    print("  rel L2 = %.3e" % e, flush=True)
+    assert e < 2e-10
