@@ -132,3 +132,36 @@ def test_uneven_geometries_full_size():
         worst = max(worst, rel(A[so[g]:so[g + 1]], one))
     print("  worst per-geometry rel diff %.3e" % worst, flush=True)
     assert worst < 1e-12
+
+
+def test_uneven_geometries_against_oracle():
+    """The 32 uneven clustered geometries (5e3 .. 2e5 points each, 1.34e6
+    in all) in one plan, as the benchmark replays them: per geometry 200
+    nonzero currents and 8 sampled targets against the oracle (stored), at
+    p = 12 (free part 20); every geometry within the metric's 1e-6."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                             "uneven_32_sparse200_oracle.npz"))
+    d, k, xs, Js = inputs.uneven_geometries(32, seed=0)
+    Jsp = []
+    for gi, J in enumerate(Js):
+        Jg, keep = inputs.sparse_currents(J, 200, seed=gi)
+        assert np.array_equal(keep, g["keep%d" % gi])
+        Jsp.append(Jg)
+    print("case 32 uneven geometries against the oracle, p=12 p_free=20", flush=True)
+    f = lmfmm.LayeredDyadicFMM(d, k, p=12, p_free=20).build_batch(xs)
+    A = f.evaluate(cuda(np.concatenate(Jsp))).cpu().numpy()
+    so = f.src_off
+    f.close()
+    num = den = 0.0
+    worst = 0.0
+    for gi in range(32):
+        Ag = A[so[gi]:so[gi + 1]][g["idx%d" % gi]]
+        ref = g["A%d" % gi]
+        eg = rel(Ag, ref)
+        worst = max(worst, eg)
+        num += np.linalg.norm(Ag - ref) ** 2
+        den += np.linalg.norm(ref) ** 2
+    e = np.sqrt(num / den)
+    print("  rel L2 over the 256 targets %.3e, worst geometry %.3e" % (e, worst), flush=True)
+    assert e < 1e-6 and worst < 1e-6

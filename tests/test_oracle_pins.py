@@ -559,3 +559,20 @@ def test_stored_values_are_the_oracles(oracle, name):
         got = oracle.direct(d, k, x[keep], J[keep], x[ti])
         ref = g["A"][rows]
     assert rel(got, ref) < 1e-12
+
+
+def test_stored_uneven_geometry_values_are_the_oracles(oracle):
+    """The stored oracle outputs of the 32 uneven geometries: two sampled
+    targets of the smallest and of one mid-size geometry recomputed from the
+    seeded inputs.  (The dense-current files, whose every target sums all
+    sources, take minutes per row and are left to the script.)"""
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    g = np.load(os.path.join(here, "uneven_32_sparse200_oracle.npz"))
+    d, k, xs, Js = inputs.uneven_geometries(32, seed=0)
+    sizes = [x.shape[0] for x in xs]
+    for gi in (int(np.argmin(sizes)), 7):
+        _, keep = inputs.sparse_currents(Js[gi], 200, seed=gi)
+        assert np.array_equal(keep, g["keep%d" % gi])
+        ti = g["idx%d" % gi][[0, 5]]
+        got = oracle.direct(d, k, xs[gi][keep], Js[gi][keep], xs[gi][ti])
+        assert rel(got, g["A%d" % gi][[0, 5]]) < 1e-12
