@@ -65,7 +65,7 @@ struct lm_ctx {
   // scratch bytes the build needs
   TileSet na_ts;
   bool na_ok = false;
-  long long na_off[4] = {0, 0, 0, 0};
+  long long na_off[5] = {0, 0, 0, 0, 0};  // ME, LE, P2M partials, M2L outputs, direct-pair slots
   long long na_need = 0;
   cd* Y = nullptr;           // M2L scratch
   long long y_cap = 0;
@@ -90,7 +90,19 @@ struct lm_ctx {
     int item0, n;  // work items of one launch (one component type)
     bool smallz;   // |k_rho| rho <= 7.5 on Gamma_1: J0..J2 by their power series
   };
-  std::vector<S2TRange> s2t_ranges;        // per reaction component with direct pairs
+  std::vector<S2TRange> s2t_ranges;        // per reaction component with direct pairs (gradient path)
+  // forward and curl paths: every component's work items in one launch per
+  // Bessel variant, longest first, each target's totals in its own output
+  // slot, then one gather that adds a point's slots in component order
+  int* d_s2t_items = nullptr;              // (target leaf, chunk, first slot)
+  int s2t_launch[2][2] = {{0, 0}, {0, 0}}; // per variant (general, series): first item, count
+  int* d_s2t_gpt = nullptr;                // points with slots
+  int* d_s2t_gptr = nullptr;               // their slot ranges
+  int* d_s2t_gslot = nullptr;              // slots in the points' fixed order
+  int s2t_npts = 0;
+  long long s2t_slots = 0;
+  cd* S2TY = nullptr;                      // slot outputs [slot][rhs][3]
+  long long s2ty_cap = 0;
   double contour_a = 0;
   cd* Jc = nullptr;                        // conjugated-input scratch
   long long jc_cap = 0;
@@ -171,6 +183,13 @@ static void free_build(lm_ctx* ctx) {
   ctx->adj = nullptr;
   ctx->d_s2t = nullptr;
   ctx->s2t_ranges.clear();
+  ctx->d_s2t_items = ctx->d_s2t_gpt = ctx->d_s2t_gptr = ctx->d_s2t_gslot = nullptr;
+  memset(ctx->s2t_launch, 0, sizeof(ctx->s2t_launch));
+  ctx->s2t_npts = 0;
+  ctx->s2t_slots = 0;
+  if (ctx->S2TY) hipFree(ctx->S2TY);
+  ctx->S2TY = nullptr;
+  ctx->s2ty_cap = 0;
   if (ctx->Jc) hipFree(ctx->Jc);
   ctx->Jc = nullptr;
   ctx->jc_cap = 0;
@@ -581,6 +600,72 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
       ctx->s2t_ranges.push_back(r);
     }
     if ((rc = upload(ctx, &ctx->d_s2t, all))) return rc;
+    // one launch per Bessel variant: slots are numbered in the fixed order
+    // (component, leaf, chunk) of `all`; the launch order puts the longest
+    // items first (rounds of 64 pairs times the component's node count), so
+    // that the short ones fill the tail
+    std::vector<int> slot0(n_items + 1, 0);
+    long long slots = 0;
+    for (int it = 0; it < (int)all.size() / 2; it++) {
+      const TgtBox& tb = pl.tbox[all[2 * it]];
+      const int t0 = tb.pt0 + all[2 * it + 1] * LM_S2T_CHUNK;
+      slot0[it] = (int)slots;
+      slots += std::min(LM_S2T_CHUNK, tb.pt1 - t0);
+    }
+    if (slots > 2000000000LL) return fail(ctx, LM_EINVAL, "too many direct reaction pair targets");
+    ctx->s2t_slots = slots;
+    std::vector<std::pair<double, int>> order[2];
+    for (size_t r = 0; r < ctx->s2t_ranges.size(); r++) {
+      const lm_ctx::S2TRange& R = ctx->s2t_ranges[r];
+      for (int it = R.item0; it < R.item0 + R.n; it++) {
+        const TgtBox& tb = pl.tbox[all[2 * it]];
+        const int t0 = tb.pt0 + all[2 * it + 1] * LM_S2T_CHUNK;
+        const long long nt = std::min(LM_S2T_CHUNK, tb.pt1 - t0);
+        long long ns = 0;
+        for (int li = tb.p2p0; li < tb.p2p1; li++) ns += pl.sbox[pl.p2p_list[li]].pt1 - pl.sbox[pl.p2p_list[li]].pt0;
+        const double cost = (double)((nt * ns + LM_S2T_CHUNK - 1) / LM_S2T_CHUNK) * pl.inst[tb.inst].s2tn;
+        order[R.smallz ? 1 : 0].push_back(std::make_pair(-cost, it));
+      }
+    }
+    std::vector<int> items3;
+    for (int v = 0; v < 2; v++) {
+      std::stable_sort(order[v].begin(), order[v].end(),
+                       [](const std::pair<double, int>& x, const std::pair<double, int>& y) { return x.first < y.first; });
+      ctx->s2t_launch[v][0] = (int)items3.size() / 3;
+      ctx->s2t_launch[v][1] = (int)order[v].size();
+      for (auto& o : order[v]) items3.insert(items3.end(), {all[2 * o.second], all[2 * o.second + 1], slot0[o.second]});
+    }
+    if ((rc = upload(ctx, &ctx->d_s2t_items, items3))) return rc;
+    // gather lists: for each point with slots, its slots in `all` order
+    std::vector<int> cnt(pl.n_tgt + 1, 0);
+    for (int it = 0; it < (int)all.size() / 2; it++) {
+      const TgtBox& tb = pl.tbox[all[2 * it]];
+      const int t0 = tb.pt0 + all[2 * it + 1] * LM_S2T_CHUNK, t1 = std::min(tb.pt1, t0 + LM_S2T_CHUNK);
+      for (int t = t0; t < t1; t++) cnt[pl.tgt_perm[t] + 1]++;
+    }
+    std::vector<int> gpt, gptr, start(pl.n_tgt, -1);
+    int acc = 0;
+    for (int64_t i = 0; i < pl.n_tgt; i++)
+      if (cnt[i + 1] > 0) {
+        start[i] = acc;
+        gpt.push_back((int)i);
+        gptr.push_back(acc);
+        acc += cnt[i + 1];
+      }
+    gptr.push_back(acc);
+    std::vector<int> gslot(acc), fill(pl.n_tgt, 0);
+    for (int it = 0; it < (int)all.size() / 2; it++) {
+      const TgtBox& tb = pl.tbox[all[2 * it]];
+      const int t0 = tb.pt0 + all[2 * it + 1] * LM_S2T_CHUNK, t1 = std::min(tb.pt1, t0 + LM_S2T_CHUNK);
+      for (int t = t0; t < t1; t++) {
+        const int id = pl.tgt_perm[t];
+        gslot[start[id] + fill[id]++] = slot0[it] + (t - t0);
+      }
+    }
+    ctx->s2t_npts = (int)gpt.size();
+    if ((rc = upload(ctx, &ctx->d_s2t_gpt, gpt))) return rc;
+    if ((rc = upload(ctx, &ctx->d_s2t_gptr, gptr))) return rc;
+    if ((rc = upload(ctx, &ctx->d_s2t_gslot, gslot))) return rc;
   }
   // matrices and table scratch
   void* vp = nullptr;
@@ -693,7 +778,8 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
     ctx->na_off[0] = 0;
     ctx->na_off[1] = ctx->na_off[0] + up(pl.me_size);
     ctx->na_off[2] = ctx->na_off[1] + up(pl.le_size);
-    ctx->na_off[3] = ctx->na_off[2] + up(p2m_part_size(ctx, 1));
+    ctx->na_off[4] = ctx->na_off[2] + up(p2m_part_size(ctx, 1));
+    ctx->na_off[3] = ctx->na_off[4] + up(ctx->s2t_slots * 3);
     long long bmax = 0;
     int rc2 = make_schedule(ctx, 1, std::max(0LL, cap - ctx->na_off[3]) * (long long)sizeof(cd), ctx->na_ts, &bmax);
     if (rc2) return rc2;
@@ -779,6 +865,7 @@ struct Work {
   cd* LE = nullptr;
   cd* part = nullptr;
   cd* Y = nullptr;
+  cd* S2TY = nullptr;  // direct-pair output slots
   lm_ctx::TileSet* ts = nullptr;
   bool tune = true;   // autotune untuned M2L launches (events, synchronisation)
   bool timed = true;  // record phase events when timing is on
@@ -832,10 +919,20 @@ static int ensure_rhs(lm_ctx* ctx, int n_rhs, hipStream_t s, Work* w) {
       ctx->y_cap = ts.y_need;
     }
   }
+  const long long sy = ctx->s2t_slots * n_rhs * 3;
+  if (sy > ctx->s2ty_cap) {
+    HIPC(hipStreamSynchronize(s));
+    if (ctx->S2TY) hipFree(ctx->S2TY);
+    ctx->S2TY = nullptr;
+    ctx->s2ty_cap = 0;
+    HIPC(hipMalloc((void**)&ctx->S2TY, (size_t)sy * sizeof(cd)));
+    ctx->s2ty_cap = sy;
+  }
   w->ME = ctx->ME;
   w->LE = ctx->LE;
   w->part = ctx->p2m_part;
   w->Y = ctx->Y;
+  w->S2TY = ctx->S2TY;
   w->ts = &ctx->tilesets[n_rhs];
   return LM_OK;
 }
@@ -884,6 +981,7 @@ int lm_evaluate_noalloc(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* st
   w.LE = base + ctx->na_off[1];
   w.part = base + ctx->na_off[2];
   w.Y = base + ctx->na_off[3];
+  w.S2TY = base + ctx->na_off[4];
   w.ts = &ctx->na_ts;
   w.tune = false;
   w.timed = false;
@@ -1192,14 +1290,20 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
                    ctx->p2p_red, s);
       span(2, false);
     }
-    for (auto& r : ctx->s2t_ranges) {
-      span(3, true);
-      if (grad)
+    if (grad) {
+      for (auto& r : ctx->s2t_ranges) {
+        span(3, true);
         launch_s2t_grad(d, ctx->md, ctx->d_s2t + 2 * r.item0, r.n, ctx->d_src, Jc, pl.n_src, ctx->d_tgt, W,
                         pl.n_tgt, n_rhs, ctx->contour_a, r.smallz, gX, s);
-      else
-        launch_s2t(d, ctx->md, ctx->d_s2t + 2 * r.item0, r.n, ctx->d_src, Jc, pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs,
-                   ctx->contour_a, r.smallz, curl ? Hc : Ac, s, curl);
+        span(3, false);
+      }
+    } else if (ctx->s2t_slots > 0) {
+      span(3, true);
+      for (int v = 0; v < 2; v++)
+        launch_s2t(d, ctx->md, ctx->d_s2t_items + 3 * ctx->s2t_launch[v][0], ctx->s2t_launch[v][1], ctx->d_src, Jc,
+                   pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs, ctx->contour_a, v == 1, w.S2TY, s, curl);
+      launch_s2t_gather(ctx->d_s2t_gpt, ctx->d_s2t_gptr, ctx->d_s2t_gslot, ctx->s2t_npts, n_rhs, w.S2TY, pl.n_tgt,
+                        curl ? Hc : Ac, s);
       span(3, false);
     }
     mark(7);

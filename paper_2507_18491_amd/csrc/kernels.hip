@@ -1516,15 +1516,16 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
                                                                      const double* sxyz, const cd* J,
                                                                      long long n_src, const double* txyz,
                                                                      long long n_tgt, int n_rhs, double a,
-                                                                     cd* A) {
+                                                                     cd* Ys) {
   __shared__ double tp[LM_S2T_CHUNK][3];  // targets: x, y, t
   __shared__ int seg_pt0[LM_S2T_SEG], seg_cum[LM_S2T_SEG + 1];
   __shared__ cd res[LM_S2T_CHUNK][RS][3];  // per pair of the round and rhs: out+, out-, out_z
   __shared__ cd nk[LM_S2T_CHUNK][10];     // node chunk: kr, w, kz_t, kz_s, F_1..F_5, 1 / kr (tail)
   const int tid = threadIdx.x;
   // work item, component and node range are uniform over the block
-  const int b = __builtin_amdgcn_readfirstlane(items[2 * blockIdx.x]);
-  const int chunk = __builtin_amdgcn_readfirstlane(items[2 * blockIdx.x + 1]);
+  const int b = __builtin_amdgcn_readfirstlane(items[3 * blockIdx.x]);
+  const int chunk = __builtin_amdgcn_readfirstlane(items[3 * blockIdx.x + 1]);
+  const long long slot0 = __builtin_amdgcn_readfirstlane(items[3 * blockIdx.x + 2]);
   const TgtBox tb = d.tbox[b];
   const InstParams ip = d.inst[__builtin_amdgcn_readfirstlane(tb.inst)];
   const int r0 = blockIdx.y * RS, nr = min(RS, n_rhs - r0);
@@ -1691,6 +1692,8 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
     }
   }
   if (tid < nt) {
+    // this target's totals go to its slot; k_s2t_gather adds the slots of a
+    // point in a fixed order
 #pragma clang fp contract(off)
     const double f = 0.079577471545947667884;  // 1 / (4 pi)
 #pragma unroll
@@ -1698,13 +1701,43 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
       if (rr >= nr) break;
       const double hx = 0.5 * f * (op[rr].x + om[rr].x), hy = 0.5 * f * (op[rr].y + om[rr].y);
       const double dx = 0.5 * f * (op[rr].x - om[rr].x), dy = 0.5 * f * (op[rr].y - om[rr].y);
-      cd* Ap = A + ((long long)(r0 + rr) * n_tgt + id) * 3;
-      const cd a0 = Ap[0], a1 = Ap[1], a2 = Ap[2];
-      Ap[0] = cd{a0.x + hx, a0.y + hy};
-      Ap[1] = cd{a1.x + dy, a1.y - dx};
-      Ap[2] = cd{a2.x + f * oz[rr].x, a2.y + f * oz[rr].y};
+      cd* Yp = Ys + ((slot0 + tid) * n_rhs + r0 + rr) * 3;
+      Yp[0] = cd{hx, hy};
+      Yp[1] = cd{dy, -dx};
+      Yp[2] = cd{f * oz[rr].x, f * oz[rr].y};
     }
   }
+  (void)id;
+}
+
+// A[r][pt][c] += the point's direct-pair slots in their fixed order (the
+// order of the reaction components, then of the leaves and chunks), for
+// every point that has slots: gpt[i] the point, its slots gslot[gptr[i] ..
+// gptr[i+1]-1].  One thread per (point, rhs).
+__global__ void k_s2t_gather(const int* gpt, const int* gptr, const int* gslot, int n_pts, int n_rhs, const cd* Ys,
+                             long long n_tgt, cd* A) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)n_pts * n_rhs) return;
+  const int i = (int)(e / n_rhs), r = (int)(e - (long long)i * n_rhs);
+  const int id = gpt[i];
+  cd* Ap = A + ((long long)r * n_tgt + id) * 3;
+  cd a0 = Ap[0], a1 = Ap[1], a2 = Ap[2];
+  for (int q = gptr[i]; q < gptr[i + 1]; q++) {
+    const cd* Yp = Ys + ((long long)gslot[q] * n_rhs + r) * 3;
+    a0 = a0 + Yp[0];
+    a1 = a1 + Yp[1];
+    a2 = a2 + Yp[2];
+  }
+  Ap[0] = a0;
+  Ap[1] = a1;
+  Ap[2] = a2;
+}
+void launch_s2t_gather(const int* gpt, const int* gptr, const int* gslot, int n_pts, int n_rhs, const cd* Ys,
+                       long long n_tgt, cd* A, hipStream_t s) {
+  const long long n = (long long)n_pts * n_rhs;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_s2t_gather, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, gpt, gptr, gslot, n_pts,
+                     n_rhs, Ys, n_tgt, A);
 }
 // Source-position gradients through the direct reaction pairs (the swapped
 // roles of the gradient path: the "targets" are the points x where the
@@ -1926,16 +1959,17 @@ void launch_s2t_grad(const DevPlan& d, MediumDev md, const int* items, int n, co
                        W, n_tgt, n_rhs, a, gX);
 }
 
-// items: work items of instances of one component type (never sharing a
-// target); smallz: |k_rho| rho <= 7.5 on Gamma_1 for all of their pairs (the
-// series length comes from each block's instance)
+// items: n work items (target leaf, chunk, first output slot) of any
+// reaction components, each block writing its targets' totals to its own
+// slots of Ys [slot][rhs][3]; smallz: |k_rho| rho <= 7.5 on Gamma_1 for all
+// of their pairs (the series length comes from each block's instance)
 void launch_s2t(const DevPlan& d, MediumDev md, const int* items, int n, const double* sxyz, const cd* J,
-                long long n_src, const double* txyz, long long n_tgt, int n_rhs, double a, bool smallz, cd* A,
+                long long n_src, const double* txyz, long long n_tgt, int n_rhs, double a, bool smallz, cd* Ys,
                 hipStream_t s, bool hfield) {
   if (n <= 0) return;
 #define LM_S2T_GO(SZ, RS, H)                                                                                   \
   hipLaunchKernelGGL((k_s2t<SZ, RS, H>), dim3(n, (n_rhs + RS - 1) / RS), dim3(LM_S2T_CHUNK), 0, s, d, md, items, \
-                     sxyz, J, n_src, txyz, n_tgt, n_rhs, a, A)
+                     sxyz, J, n_src, txyz, n_tgt, n_rhs, a, Ys)
   if (hfield) {
     if (n_rhs == 1) {
       if (smallz)
