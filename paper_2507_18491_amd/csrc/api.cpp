@@ -94,7 +94,9 @@ struct lm_ctx {
   // forward and curl paths: every component's work items in one launch per
   // Bessel variant, longest first, each target's totals in its own output
   // slot, then one gather that adds a point's slots in component order
-  int* d_s2t_items = nullptr;              // (target leaf, chunk, first slot)
+  int* d_s2t_items = nullptr;              // (target leaf, chunk, first slot, target order, source list, count)
+  int* d_s2t_tlist = nullptr;              // per item: chunk positions of its targets in increasing t
+  int* d_s2t_slist = nullptr;              // per item: its near source points in increasing u
   int s2t_launch[2][2] = {{0, 0}, {0, 0}}; // per variant (general, series): first item, count
   int* d_s2t_gpt = nullptr;                // points with slots
   int* d_s2t_gptr = nullptr;               // their slot ranges
@@ -184,6 +186,7 @@ static void free_build(lm_ctx* ctx) {
   ctx->d_s2t = nullptr;
   ctx->s2t_ranges.clear();
   ctx->d_s2t_items = ctx->d_s2t_gpt = ctx->d_s2t_gptr = ctx->d_s2t_gslot = nullptr;
+  ctx->d_s2t_tlist = ctx->d_s2t_slist = nullptr;
   memset(ctx->s2t_launch, 0, sizeof(ctx->s2t_launch));
   ctx->s2t_npts = 0;
   ctx->s2t_slots = 0;
@@ -627,15 +630,48 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
         order[R.smallz ? 1 : 0].push_back(std::make_pair(-cost, it));
       }
     }
-    std::vector<int> items3;
+    // per item: its targets ordered by t (distance of the effective location
+    // from its interface plane) and its near sources by u (that of the
+    // image), so that the pairs of one round of 64 have similar tail cuts
+    std::vector<int> items6, tlist, slist;
     for (int v = 0; v < 2; v++) {
       std::stable_sort(order[v].begin(), order[v].end(),
                        [](const std::pair<double, int>& x, const std::pair<double, int>& y) { return x.first < y.first; });
-      ctx->s2t_launch[v][0] = (int)items3.size() / 3;
+      ctx->s2t_launch[v][0] = (int)items6.size() / 6;
       ctx->s2t_launch[v][1] = (int)order[v].size();
-      for (auto& o : order[v]) items3.insert(items3.end(), {all[2 * o.second], all[2 * o.second + 1], slot0[o.second]});
+      for (auto& o : order[v]) {
+        const int it = o.second;
+        const TgtBox& tb = pl.tbox[all[2 * it]];
+        const InstParams& ip = pl.inst[tb.inst];
+        const int t0 = tb.pt0 + all[2 * it + 1] * LM_S2T_CHUNK, nt = std::min(LM_S2T_CHUNK, tb.pt1 - t0);
+        const double dls = ip.up_s ? med.d[ip.ls - 1] : med.d[ip.ls];
+        std::vector<std::pair<double, int>> tv, sv;
+        for (int q = 0; q < nt; q++) {
+          const double z = tgt_xyz[3 * pl.tgt_perm[t0 + q] + 2];
+          tv.push_back(std::make_pair(ip.up_t ? z - med.d[ip.lt] : med.d[ip.lt - 1] - z, q));
+        }
+        for (int li = tb.p2p0; li < tb.p2p1; li++) {
+          const SrcBox& sb = pl.sbox[pl.p2p_list[li]];
+          for (int sp = sb.pt0; sp < sb.pt1; sp++) {
+            const int sid = pl.src_perm[sp];
+            const double z = src_xyz[3 * sid + 2];
+            sv.push_back(std::make_pair(ip.up_s ? dls - z : z - dls, sid));
+          }
+        }
+        std::stable_sort(tv.begin(), tv.end(),
+                         [](const std::pair<double, int>& x, const std::pair<double, int>& y) { return x.first < y.first; });
+        std::stable_sort(sv.begin(), sv.end(),
+                         [](const std::pair<double, int>& x, const std::pair<double, int>& y) { return x.first < y.first; });
+        if (slist.size() + sv.size() > 2000000000ULL) return fail(ctx, LM_EINVAL, "too many direct reaction pairs");
+        items6.insert(items6.end(), {all[2 * it], all[2 * it + 1], slot0[it], (int)tlist.size(), (int)slist.size(),
+                                     (int)sv.size()});
+        for (auto& x : tv) tlist.push_back(x.second);
+        for (auto& x : sv) slist.push_back(x.second);
+      }
     }
-    if ((rc = upload(ctx, &ctx->d_s2t_items, items3))) return rc;
+    if ((rc = upload(ctx, &ctx->d_s2t_items, items6))) return rc;
+    if ((rc = upload(ctx, &ctx->d_s2t_tlist, tlist))) return rc;
+    if ((rc = upload(ctx, &ctx->d_s2t_slist, slist))) return rc;
     // gather lists: for each point with slots, its slots in `all` order
     std::vector<int> cnt(pl.n_tgt + 1, 0);
     for (int it = 0; it < (int)all.size() / 2; it++) {
@@ -1300,8 +1336,9 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
     } else if (ctx->s2t_slots > 0) {
       span(3, true);
       for (int v = 0; v < 2; v++)
-        launch_s2t(d, ctx->md, ctx->d_s2t_items + 3 * ctx->s2t_launch[v][0], ctx->s2t_launch[v][1], ctx->d_src, Jc,
-                   pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs, ctx->contour_a, v == 1, w.S2TY, s, curl);
+        launch_s2t(d, ctx->md, ctx->d_s2t_items + 6 * ctx->s2t_launch[v][0], ctx->d_s2t_tlist, ctx->d_s2t_slist,
+                   ctx->s2t_launch[v][1], ctx->d_src, Jc, pl.n_src, ctx->d_tgt, pl.n_tgt, n_rhs, ctx->contour_a, v == 1,
+                   w.S2TY, s, curl);
       launch_s2t_gather(ctx->d_s2t_gpt, ctx->d_s2t_gptr, ctx->d_s2t_gslot, ctx->s2t_npts, n_rhs, w.S2TY, pl.n_tgt,
                         curl ? Hc : Ac, s);
       span(3, false);

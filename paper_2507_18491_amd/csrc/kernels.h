@@ -85,9 +85,9 @@ void launch_p2p_curl(const DevPlan& d, const int* tboxes, int n, const double* s
                      const double* txyz, long long n_tgt, int n_rhs, cd* Hc, bool red, hipStream_t s);
 // g[i][c] *= mu(layer of point i)^pw
 void launch_scale_mu_d(double* g, long long n, const double* xyz, MediumDev md, int pw, hipStream_t s);
-void launch_s2t(const DevPlan& d, MediumDev md, const int* items, int n, const double* sxyz, const cd* J,
-                long long n_src, const double* txyz, long long n_tgt, int n_rhs, double a, bool smallz, cd* Ys,
-                hipStream_t s, bool hfield = false);
+void launch_s2t(const DevPlan& d, MediumDev md, const int* items, const int* tlist, const int* slist, int n,
+                const double* sxyz, const cd* J, long long n_src, const double* txyz, long long n_tgt, int n_rhs,
+                double a, bool smallz, cd* Ys, hipStream_t s, bool hfield = false);
 void launch_s2t_gather(const int* gpt, const int* gptr, const int* gslot, int n_pts, int n_rhs, const cd* Ys,
                        long long n_tgt, cd* A, hipStream_t s);
 // source-position gradients through the direct reaction pairs (gradient path roles)

@@ -911,11 +911,14 @@ __global__ __launch_bounds__(NT) void k_p2p(DevPlan d, const int* tboxes, const 
         }
         __syncthreads();
         if (act) {
+          // the coincident point (r = 0) is skipped without a branch: 1/r is
+          // set to 0, so that g and every term vanish; the loop body then
+          // has no data-dependent control flow and is unrolled
+#pragma unroll 4
           for (int j = 0; j < ns; j++) {
             double rx = x0 - sp[j][0], ry = y0 - sp[j][1], rz = z0 - sp[j][2];
             double r2 = rx * rx + ry * ry + rz * rz;
-            if (r2 == 0.0) continue;
-            double ir = lm_rsqrt(r2), r = r2 * ir;
+            double ir = r2 > 0.0 ? lm_rsqrt(r2) : 0.0, r = r2 * ir;
             double kr = k * r, ikr = invk * ir, ikr2 = ikr * ikr;
             double sn, cs;
             lm_sincos_nf<RED>(kr, &sn, &cs);
@@ -1513,19 +1516,23 @@ void launch_p2p_curl(const DevPlan& d, const int* tboxes, int n, const double* s
 //   out+ as above, out- negated, out_z = W(-1,s4) u+/2 - W(1,s4) u-/2.
 template <bool SMALLZ, int RS, bool HF>
 __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md, const int* items,
+                                                                     const int* tlist, const int* slist,
                                                                      const double* sxyz, const cd* J,
                                                                      long long n_src, const double* txyz,
                                                                      long long n_tgt, int n_rhs, double a,
                                                                      cd* Ys) {
   __shared__ double tp[LM_S2T_CHUNK][3];  // targets: x, y, t
-  __shared__ int seg_pt0[LM_S2T_SEG], seg_cum[LM_S2T_SEG + 1];
   __shared__ cd res[LM_S2T_CHUNK][RS][3];  // per pair of the round and rhs: out+, out-, out_z
   __shared__ cd nk[LM_S2T_CHUNK][10];     // node chunk: kr, w, kz_t, kz_s, F_1..F_5, 1 / kr (tail)
   const int tid = threadIdx.x;
   // work item, component and node range are uniform over the block
-  const int b = __builtin_amdgcn_readfirstlane(items[3 * blockIdx.x]);
-  const int chunk = __builtin_amdgcn_readfirstlane(items[3 * blockIdx.x + 1]);
-  const long long slot0 = __builtin_amdgcn_readfirstlane(items[3 * blockIdx.x + 2]);
+  const int* it6 = items + 6 * blockIdx.x;
+  const int b = __builtin_amdgcn_readfirstlane(it6[0]);
+  const int chunk = __builtin_amdgcn_readfirstlane(it6[1]);
+  const long long slot0 = __builtin_amdgcn_readfirstlane(it6[2]);
+  const int* tl = tlist + __builtin_amdgcn_readfirstlane(it6[3]);  // chunk positions, sorted by t
+  const int* sl = slist + __builtin_amdgcn_readfirstlane(it6[4]);  // near source points, sorted by u
+  const int ns = __builtin_amdgcn_readfirstlane(it6[5]);
   const TgtBox tb = d.tbox[b];
   const InstParams ip = d.inst[__builtin_amdgcn_readfirstlane(tb.inst)];
   const int r0 = blockIdx.y * RS, nr = min(RS, n_rhs - r0);
@@ -1535,40 +1542,28 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
   const int nser = __builtin_amdgcn_readfirstlane(ip.s2t_nser);
   const QNode* nodes = d.nodes + n0;
   const double dls = ip.up_s ? md.d[ip.ls - 1] : md.d[ip.ls];
-  int id = 0;
+  // lane tid owns the target at chunk position pos (targets in increasing
+  // t, sources in increasing u: neighbouring pairs of a round then have
+  // similar cuts, so that few lanes idle on the real tail)
+  int pos = 0;
   if (tid < nt) {
-    id = d.tgt_perm[t0 + tid];
+    pos = tl[tid];
+    const int id = d.tgt_perm[t0 + pos];
     double zt = txyz[3 * id + 2];
     tp[tid][0] = txyz[3 * id];
     tp[tid][1] = txyz[3 * id + 1];
     tp[tid][2] = ip.up_t ? zt - md.d[ip.lt] : md.d[ip.lt - 1] - zt;
   }
+  __syncthreads();
   cd op[RS], om[RS], oz[RS];  // thread tid < nt: totals of target tid
   for (int rr = 0; rr < RS; rr++) op[rr] = om[rr] = oz[rr] = cd{0, 0};
-  for (int l0 = tb.p2p0; l0 < tb.p2p1; l0 += LM_S2T_SEG) {
-    const int nb = min(LM_S2T_SEG, tb.p2p1 - l0);
-    __syncthreads();
-    if (tid == 0) {
-      int cum = 0;
-      for (int e = 0; e < nb; e++) {
-        const SrcBox sb = d.sbox[d.p2p_list[l0 + e]];
-        seg_pt0[e] = sb.pt0;
-        seg_cum[e] = cum;
-        cum += sb.pt1 - sb.pt0;
-      }
-      seg_cum[nb] = cum;
-    }
-    __syncthreads();
-    const int ns = seg_cum[nb];
+  {
     const int npair = nt * ns;
     for (int q0 = 0; q0 < npair; q0 += LM_S2T_CHUNK) {
       const int q = q0 + tid;
       const bool pa = q < npair;
       const int i = pa ? q / ns : 0, j = pa ? q - (q / ns) * ns : 0;
-      // this lane's source: box of the segment holding source j
-      int e = 0;
-      while (e + 1 < nb && seg_cum[e + 1] <= j) e++;
-      const int sid = d.src_perm[seg_pt0[e] + (j - seg_cum[e])];
+      const int sid = sl[j];
       const double* sx = sxyz + 3 * (long long)sid;
       double dx = tp[i][0] - sx[0], dy = tp[i][1] - sx[1];
       double tz = tp[i][2], uz = ip.up_s ? dls - sx[2] : sx[2] - dls;
@@ -1701,13 +1696,12 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
       if (rr >= nr) break;
       const double hx = 0.5 * f * (op[rr].x + om[rr].x), hy = 0.5 * f * (op[rr].y + om[rr].y);
       const double dx = 0.5 * f * (op[rr].x - om[rr].x), dy = 0.5 * f * (op[rr].y - om[rr].y);
-      cd* Yp = Ys + ((slot0 + tid) * n_rhs + r0 + rr) * 3;
+      cd* Yp = Ys + ((slot0 + pos) * n_rhs + r0 + rr) * 3;
       Yp[0] = cd{hx, hy};
       Yp[1] = cd{dy, -dx};
       Yp[2] = cd{f * oz[rr].x, f * oz[rr].y};
     }
   }
-  (void)id;
 }
 
 // A[r][pt][c] += the point's direct-pair slots in their fixed order (the
@@ -1959,17 +1953,18 @@ void launch_s2t_grad(const DevPlan& d, MediumDev md, const int* items, int n, co
                        W, n_tgt, n_rhs, a, gX);
 }
 
-// items: n work items (target leaf, chunk, first output slot) of any
-// reaction components, each block writing its targets' totals to its own
-// slots of Ys [slot][rhs][3]; smallz: |k_rho| rho <= 7.5 on Gamma_1 for all
+// items: n work items (target leaf, chunk, first output slot, offset of its
+// target order in tlist, offset of its source list in slist, source count)
+// of any reaction components, each block writing its targets' totals to its
+// own slots of Ys [slot][rhs][3]; smallz: |k_rho| rho <= 7.5 on Gamma_1 for all
 // of their pairs (the series length comes from each block's instance)
-void launch_s2t(const DevPlan& d, MediumDev md, const int* items, int n, const double* sxyz, const cd* J,
-                long long n_src, const double* txyz, long long n_tgt, int n_rhs, double a, bool smallz, cd* Ys,
-                hipStream_t s, bool hfield) {
+void launch_s2t(const DevPlan& d, MediumDev md, const int* items, const int* tlist, const int* slist, int n,
+                const double* sxyz, const cd* J, long long n_src, const double* txyz, long long n_tgt, int n_rhs,
+                double a, bool smallz, cd* Ys, hipStream_t s, bool hfield) {
   if (n <= 0) return;
 #define LM_S2T_GO(SZ, RS, H)                                                                                   \
   hipLaunchKernelGGL((k_s2t<SZ, RS, H>), dim3(n, (n_rhs + RS - 1) / RS), dim3(LM_S2T_CHUNK), 0, s, d, md, items, \
-                     sxyz, J, n_src, txyz, n_tgt, n_rhs, a, Ys)
+                     tlist, slist, sxyz, J, n_src, txyz, n_tgt, n_rhs, a, Ys)
   if (hfield) {
     if (n_rhs == 1) {
       if (smallz)
