@@ -1368,6 +1368,7 @@ int lmc_run(int n_layers, const double* d, const double* k, const double* mu, co
   q.m2l_adapt = prm->m2l_adapt;
   q.m2l_margin = prm->m2l_margin;
   q.react_s2t = prm->react_s2t;
+  q.tol = prm->tol;
   const int64_t ns = src_off[n_geom], nt = tgt_off[n_geom];
   for (int pass = 0; pass < 2; pass++) {
     const double* x = pass ? tgt : src;

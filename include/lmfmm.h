@@ -53,6 +53,8 @@ extern "C" {
 #define LM_ESTATE (-3)   /* wrong call order                                        */
 #define LM_ENOMEM (-4)   /* device allocation failed                                */
 #define LM_EHIP (-5)     /* HIP runtime error (message carries hipGetErrorString)   */
+#define LM_EACCURACY (-6) /* a quadrature rule of the build cannot reach the         */
+                          /* accuracy requested in lm_params.tol                     */
 
 #define LM_PMAX_ORDER 20
 
@@ -92,12 +94,23 @@ typedef struct {
                       /* values of k per LDS chunk, 3 blocks per CU; 1: 32 values,  */
                       /* 2 blocks; 2: 16 values double-buffered, 2 blocks).  All   */
                       /* variants give bitwise equal results.                      */
+  double tol;         /* requested relative accuracy, 0 (default): no check.  With  */
+                      /* tol > 0, lm_build returns LM_EACCURACY when a quadrature   */
+                      /* rule of the plan is coarser than tol: the real tail of the*/
+                      /* M2L tables' Sommerfeld integrals (cut where the integrand */
+                      /* has decayed by e^-tail_digits beyond the growth of the     */
+                      /* Legendre products), the direct reaction pairs (tail cut at*/
+                      /* 28 e-folds and two panels on the first contour piece,     */
+                      /* about 2.5e-9 of a pair's field), or fewer than three      */
+                      /* panels on that piece (about 2e-9).  The expansions'       */
+                      /* truncation error is not bounded a priori: it is set by p  */
+                      /* (recorded errors per order: see the tests).                */
 } lm_params;
 
 #define LM_M2L_VARIANTS 3
 
 /* Fills *prm with the defaults (p = 12, p_free = p, automatic depths, m2l_adapt = 1,
- * m2l_margin = 3, gamma1_panels = 4, react_s2t = 1, m2l_variant = -1). */
+ * m2l_margin = 3, gamma1_panels = 4, react_s2t = 1, m2l_variant = -1, tol = 0). */
 int lm_default_params(lm_params* prm);
 
 /* Creates a context bound to HIP device `hip_device`.  *out is owned by the
@@ -128,7 +141,8 @@ int lm_set_params(lm_ctx* ctx, const lm_params* prm);
  * `stream` (a hipStream_t, NULL = default stream) and synchronises it once
  * before returning.  LM_EDOMAIN if a point lies on an interface
  * (|z - d| <= 1e-12 max(1,|d|)) or closer to one than the refinement cap
- * allows; LM_ESTATE if no medium was set. */
+ * allows; LM_ESTATE if no medium was set; LM_EACCURACY if lm_params.tol is
+ * set and a quadrature rule of the plan cannot reach it. */
 int lm_build(lm_ctx* ctx, int64_t n_src, const double* src_xyz, int64_t n_tgt,
              const double* tgt_xyz, void* stream);
 

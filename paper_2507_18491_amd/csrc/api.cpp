@@ -290,6 +290,7 @@ int lm_default_params(lm_params* prm) {
   prm->m2l_margin = 3.0;
   prm->react_s2t = 1;
   prm->m2l_variant = -1;
+  prm->tol = 0.0;
   return LM_OK;
 }
 
@@ -359,6 +360,7 @@ int lm_set_params(lm_ctx* ctx, const lm_params* p) {
   if (p->m2l_adapt && !(p->m2l_margin >= 0 && p->m2l_margin <= 30))
     return fail(ctx, LM_EINVAL, "m2l_margin out of range (0..30 decades)");
   if (p->react_s2t < 0 || p->react_s2t > 3) return fail(ctx, LM_EINVAL, "react_s2t must be 0, 1, 2 or 3");
+  if (!(p->tol >= 0) || !std::isfinite(p->tol)) return fail(ctx, LM_EINVAL, "tol must be finite and >= 0");
   if (p->m2l_variant < -1 || p->m2l_variant >= LM_M2L_VARIANTS)
     return fail(ctx, LM_EINVAL, "m2l_variant must be -1 (autotune) or 0.." + std::to_string(LM_M2L_VARIANTS - 1));
   PlanParams q;
@@ -373,6 +375,7 @@ int lm_set_params(lm_ctx* ctx, const lm_params* p) {
   q.m2l_adapt = p->m2l_adapt;
   q.m2l_margin = p->m2l_margin;
   q.react_s2t = p->react_s2t;
+  q.tol = p->tol;
   ctx->prm = q;
   ctx->m2l_variant = p->m2l_variant;
   if (ctx->built) {
@@ -435,7 +438,10 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
   if (lm_upload_leg_tables()) return fail(ctx, LM_EHIP, "cannot upload the Legendre coefficient tables");
   auto t0 = std::chrono::steady_clock::now();
   std::string msg = lm_make_plan_multi(ctx->plan, med, ctx->prm, n_geom, soff, src_xyz, toff, tgt_xyz);
-  if (!msg.empty()) return fail(ctx, LM_EDOMAIN, msg);
+  if (!msg.empty())
+    return fail(ctx, msg.compare(0, strlen(LM_PLAN_ACCURACY_PREFIX), LM_PLAN_ACCURACY_PREFIX) == 0 ? LM_EACCURACY
+                                                                                               : LM_EDOMAIN,
+                msg);
   auto t1 = std::chrono::steady_clock::now();
   Plan& pl = ctx->plan;
   ctx->pmax = std::max(pl.p, pl.pf);
@@ -1597,7 +1603,7 @@ int lm_host_plan_stats(int n_layers, const double* d, const double* k, const lm_
   std::string msg = lm_make_plan(tmp.plan, tmp.med, tmp.prm, n_src, src_xyz, n_tgt, tgt_xyz);
   if (!msg.empty()) {
     if (errbuf && errlen > 0) snprintf(errbuf, errlen, "%s", msg.c_str());
-    return LM_EDOMAIN;
+    return msg.compare(0, strlen(LM_PLAN_ACCURACY_PREFIX), LM_PLAN_ACCURACY_PREFIX) == 0 ? LM_EACCURACY : LM_EDOMAIN;
   }
   return lm_stats(&tmp, out, n);
 }

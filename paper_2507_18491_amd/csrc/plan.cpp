@@ -1312,6 +1312,23 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
     }
   }
 
+  // ---- the requested accuracy against the quadrature rules of the plan
+  if (prm.tol > 0) {
+    if (!pl.cases.empty() && std::exp(-prm.tail_digits) > prm.tol)
+      return lm_fmt(LM_PLAN_ACCURACY_PREFIX "the real tail of the M2L tables' Sommerfeld integrals is cut at "
+                    "e^-%.1f (tail_digits) beyond the Legendre products' growth, coarser than tol = %.1e",
+                    prm.tail_digits, prm.tol);
+    if (!pl.cases.empty() && prm.gamma1_panels < 3 && prm.tol < 1e-8)
+      return lm_fmt(LM_PLAN_ACCURACY_PREFIX "%d Gauss-Legendre panels on the first contour piece give about "
+                    "2e-9 of the M2L tables, coarser than tol = %.1e (use 3 or more)",
+                    prm.gamma1_panels, prm.tol);
+    if (pl.n_s2t_pairs > 0 && prm.tol < 2.5e-9)
+      return lm_fmt(LM_PLAN_ACCURACY_PREFIX "the direct reaction pairs' integrals are cut at %.0f e-folds on "
+                    "the real tail with two panels on the first contour piece (about 2.5e-9 of a pair's field), "
+                    "coarser than tol = %.1e (react_s2t = 0 refines the trees instead)",
+                    (double)LM_S2T_DIGITS, prm.tol);
+  }
+
   // ---- coefficient tables
   lm_legendre_cheb(pmax, pl.Bcoef);
   for (auto& ip : pl.inst) {

@@ -35,8 +35,13 @@ struct PlanParams {
   double m2l_margin = 3.0;  // decades below the worst pair's truncation bound
   int react_s2t = 1;         // 0: refine reaction trees until no adjacent leaves remain;
                              // 1: stop one level early next to the gap where direct (S2T)
-                             // pairs are estimated cheaper; 2: always stop one level early
+                             // pairs are estimated cheaper; 2: always stop one level early;
+                             // 3: every reaction pair direct
+  double tol = 0;            // requested accuracy: plans whose quadrature rules are coarser fail
 };
+
+// prefix of the planner's messages for a requested accuracy out of reach
+#define LM_PLAN_ACCURACY_PREFIX "accuracy: "
 
 struct Plan {
   Medium med;

@@ -13,6 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblmfmm.so")
 
 LM_OK = 0
+LM_EACCURACY = -6
 STAT_NAMES = ["n_free_inst", "n_react_inst", "m2l_pairs_free", "m2l_pairs_react", "p2p_pairs",
               "n_cases", "n_nodes", "mat_bytes", "me_bytes_per_rhs", "le_bytes_per_rhs",
               "t_plan_ms", "t_upload_ms", "t_tables_ms", "n_src_boxes", "n_tgt_boxes",
@@ -30,7 +31,7 @@ class lm_params(ctypes.Structure):
                 ("contour_a", ctypes.c_double), ("tail_digits", ctypes.c_double),
                 ("components", ctypes.c_int), ("m2l_adapt", ctypes.c_int),
                 ("m2l_margin", ctypes.c_double), ("react_s2t", ctypes.c_int),
-                ("m2l_variant", ctypes.c_int)]
+                ("m2l_variant", ctypes.c_int), ("tol", ctypes.c_double)]
 
 M2L_VARIANTS = 3
 NOALLOC_SCRATCH_BYTES = 256 << 20
@@ -145,7 +146,9 @@ class LayeredDyadicFMM:
     def _check(self, rc):
         if rc != LM_OK:
             msg = self.lib.lm_last_error(self.ctx)
-            raise LMError("lmfmm error %d: %s" % (rc, msg.decode() if msg else ""))
+            e = LMError("lmfmm error %d: %s" % (rc, msg.decode() if msg else ""))
+            e.code = rc
+            raise e
 
     def build(self, src, tgt=None, stream=None):
         import torch
@@ -503,7 +506,9 @@ def host_plan_stats(d, k, src, tgt=None, **params):
     rc = lib.lm_host_plan_stats(k.size, _dp(d), _dp(k), ctypes.byref(prm), src.shape[0], _dp(src),
                                 tgt.shape[0], _dp(tgt), _dp(out), out.size, err, 1024)
     if rc:
-        raise LMError("planning failed (%d): %s" % (rc, err.value.decode()))
+        e = LMError("planning failed (%d): %s" % (rc, err.value.decode()))
+        e.code = rc
+        raise e
     return dict(zip(STAT_NAMES, out.tolist()))
 
 

@@ -368,3 +368,26 @@ def test_no_device_fails_loudly():
         pytest.skip("a GPU is visible")
     with pytest.raises(lmfmm.LMError, match="lm_create"):
         lmfmm.LayeredDyadicFMM([0.0], [1.0, 1.5])
+
+
+def test_requested_accuracy_out_of_reach_is_lm_eaccuracy():
+    """lm_params.tol checks the plan's quadrature rules: a tolerance the
+    direct reaction pairs' integrals cannot reach (their tail cut at 28
+    e-folds) or a table tail cut coarser than tol fails with LM_EACCURACY;
+    tolerances within reach, or no tolerance, plan normally."""
+    d, k, x, J = inputs.tiny()
+    # every reaction pair direct: their integrals reach about 2.5e-9
+    lmfmm.host_plan_stats(d, k, x, p=8, react_s2t=3, tol=1e-6)
+    with pytest.raises(lmfmm.LMError) as e:
+        lmfmm.host_plan_stats(d, k, x, p=8, react_s2t=3, tol=1e-10)
+    assert e.value.code == lmfmm.LM_EACCURACY and "direct reaction pairs" in str(e.value)
+    # no direct pairs: the same tolerance is within reach of the tables
+    lmfmm.host_plan_stats(d, k, x, p=8, react_s2t=0, tol=1e-10)
+    with pytest.raises(lmfmm.LMError) as e:
+        lmfmm.host_plan_stats(d, k, x, p=8, react_s2t=0, tail_digits=10.0, tol=1e-6)
+    assert e.value.code == lmfmm.LM_EACCURACY and "tail" in str(e.value)
+    with pytest.raises(lmfmm.LMError) as e:
+        lmfmm.host_plan_stats(d, k, x, p=8, react_s2t=0, gamma1_panels=2, tol=1e-10)
+    assert e.value.code == lmfmm.LM_EACCURACY
+    with pytest.raises(lmfmm.LMError):
+        lmfmm.host_plan_stats(d, k, x, p=8, tol=-1.0)
