@@ -85,15 +85,14 @@ struct lm_ctx {
   std::vector<int64_t> host_soff, host_toff;
   lm_ctx* adj = nullptr;                   // swapped-role context (built on first use)
   MediumDev md;                            // medium as seen by the kernels
-  int* d_s2t = nullptr;                    // S2T work items (target leaf, chunk)
   struct S2TRange {
-    int item0, n;  // work items of one launch (one component type)
+    int item0, n;  // work items of one component type (host grouping)
     bool smallz;   // |k_rho| rho <= 7.5 on Gamma_1: J0..J2 by their power series
   };
-  std::vector<S2TRange> s2t_ranges;        // per reaction component with direct pairs (gradient path)
-  // forward and curl paths: every component's work items in one launch per
-  // Bessel variant, longest first, each target's totals in its own output
-  // slot, then one gather that adds a point's slots in component order
+  std::vector<S2TRange> s2t_ranges;        // per reaction component with direct pairs
+  // every component's work items in one launch per Bessel variant, longest
+  // first, each target's totals in its own output slot, then one gather
+  // that adds a point's slots in component order (forward, curl, gradient)
   int* d_s2t_items = nullptr;              // (target leaf, chunk, first slot, target order, source list, count)
   int* d_s2t_tlist = nullptr;              // per item: chunk positions of its targets in increasing t
   int* d_s2t_slist = nullptr;              // per item: its near source points in increasing u
@@ -183,7 +182,6 @@ static void free_build(lm_ctx* ctx) {
   ctx->built = false;
   if (ctx->adj) lm_destroy(ctx->adj);
   ctx->adj = nullptr;
-  ctx->d_s2t = nullptr;
   ctx->s2t_ranges.clear();
   ctx->d_s2t_items = ctx->d_s2t_gpt = ctx->d_s2t_gptr = ctx->d_s2t_gslot = nullptr;
   ctx->d_s2t_tlist = ctx->d_s2t_slist = nullptr;
@@ -608,7 +606,6 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
       all.insert(all.end(), kv.second.begin(), kv.second.end());
       ctx->s2t_ranges.push_back(r);
     }
-    if ((rc = upload(ctx, &ctx->d_s2t, all))) return rc;
     // one launch per Bessel variant: slots are numbered in the fixed order
     // (component, leaf, chunk) of `all`; the launch order puts the longest
     // items first (rounds of 64 pairs times the component's node count), so
@@ -1333,10 +1330,16 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
       span(2, false);
     }
     if (grad) {
-      for (auto& r : ctx->s2t_ranges) {
+      if (ctx->s2t_slots > 0) {
+        // the slot buffer holds n_rhs complex triples per slot, at least the
+        // one real triple per slot of the gradient
+        double* Gs = (double*)w.S2TY;
         span(3, true);
-        launch_s2t_grad(d, ctx->md, ctx->d_s2t + 2 * r.item0, r.n, ctx->d_src, Jc, pl.n_src, ctx->d_tgt, W,
-                        pl.n_tgt, n_rhs, ctx->contour_a, r.smallz, gX, s);
+        for (int v = 0; v < 2; v++)
+          launch_s2t_grad(d, ctx->md, ctx->d_s2t_items + 6 * ctx->s2t_launch[v][0], ctx->d_s2t_tlist,
+                          ctx->d_s2t_slist, ctx->s2t_launch[v][1], ctx->d_src, Jc, pl.n_src, ctx->d_tgt, W, pl.n_tgt,
+                          n_rhs, ctx->contour_a, v == 1, Gs, s);
+        launch_s2t_gather_grad(ctx->d_s2t_gpt, ctx->d_s2t_gptr, ctx->d_s2t_gslot, ctx->s2t_npts, Gs, gX, s);
         span(3, false);
       }
     } else if (ctx->s2t_slots > 0) {

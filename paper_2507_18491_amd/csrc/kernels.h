@@ -91,9 +91,11 @@ void launch_s2t(const DevPlan& d, MediumDev md, const int* items, const int* tli
 void launch_s2t_gather(const int* gpt, const int* gptr, const int* gslot, int n_pts, int n_rhs, const cd* Ys,
                        long long n_tgt, cd* A, hipStream_t s);
 // source-position gradients through the direct reaction pairs (gradient path roles)
-void launch_s2t_grad(const DevPlan& d, MediumDev md, const int* items, int n, const double* sxyz, const cd* C,
-                     long long n_src, const double* txyz, const cd* W, long long n_tgt, int n_rhs, double a,
-                     bool smallz, double* gX, hipStream_t s);
+void launch_s2t_grad(const DevPlan& d, MediumDev md, const int* items, const int* tlist, const int* slist, int n,
+                     const double* sxyz, const cd* C, long long n_src, const double* txyz, const cd* W,
+                     long long n_tgt, int n_rhs, double a, bool smallz, double* Gs, hipStream_t s);
+void launch_s2t_gather_grad(const int* gpt, const int* gptr, const int* gslot, int n_pts, const double* Gs,
+                            double* gX, hipStream_t s);
 void launch_fill_d(double* p, long long n, hipStream_t s);
 void launch_selftest_math(const double* x, long long n, double* out, hipStream_t s);
 void launch_l2p_grad(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_pts,

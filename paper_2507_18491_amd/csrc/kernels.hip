@@ -1757,16 +1757,24 @@ __device__ inline void bessel3_from012(cd z, cd iz, bool small, const cd* j, cd*
 }
 template <bool SMALLZ>
 __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t_grad(DevPlan d, MediumDev md, const int* items,
+                                                              const int* tlist, const int* slist,
                                                               const double* sxyz, const cd* C, long long n_src,
                                                               const double* txyz, const cd* W, long long n_tgt,
-                                                              int n_rhs, double a, double* gX) {
+                                                              int n_rhs, double a, double* Gs) {
   __shared__ double tp[LM_S2T_CHUNK][3];
-  __shared__ int seg_pt0[LM_S2T_SEG], seg_cum[LM_S2T_SEG + 1];
   __shared__ double res[LM_S2T_CHUNK][3];
   __shared__ cd nk[LM_S2T_CHUNK][10];
+  __shared__ int tpid[LM_S2T_CHUNK];  // point of each target lane
   const int tid = threadIdx.x;
-  const int b = __builtin_amdgcn_readfirstlane(items[2 * blockIdx.x]);
-  const int chunk = __builtin_amdgcn_readfirstlane(items[2 * blockIdx.x + 1]);
+  // work item as in k_s2t (targets and sources ordered by their distances
+  // to the interface planes); each target's gradient goes to its slot of Gs
+  const int* it6 = items + 6 * blockIdx.x;
+  const int b = __builtin_amdgcn_readfirstlane(it6[0]);
+  const int chunk = __builtin_amdgcn_readfirstlane(it6[1]);
+  const long long slot0 = __builtin_amdgcn_readfirstlane(it6[2]);
+  const int* tl = tlist + __builtin_amdgcn_readfirstlane(it6[3]);
+  const int* sl = slist + __builtin_amdgcn_readfirstlane(it6[4]);
+  const int ns = __builtin_amdgcn_readfirstlane(it6[5]);
   const TgtBox tb = d.tbox[b];
   const InstParams ip = d.inst[__builtin_amdgcn_readfirstlane(tb.inst)];
   const int t0 = tb.pt0 + chunk * LM_S2T_CHUNK;
@@ -1776,38 +1784,25 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t_grad(DevPlan d, MediumD
   const QNode* nodes = d.nodes + n0;
   const double dls = ip.up_s ? md.d[ip.ls - 1] : md.d[ip.ls];
   const double esg = ip.up_t ? 1.0 : -1.0;  // d t / d z at the target
-  int id = 0;
+  int pos = 0;
   if (tid < nt) {
-    id = d.tgt_perm[t0 + tid];
+    pos = tl[tid];
+    const int id = d.tgt_perm[t0 + pos];
     double zt = txyz[3 * id + 2];
     tp[tid][0] = txyz[3 * id];
     tp[tid][1] = txyz[3 * id + 1];
     tp[tid][2] = ip.up_t ? zt - md.d[ip.lt] : md.d[ip.lt - 1] - zt;
+    tpid[tid] = id;
   }
+  __syncthreads();
   double gx = 0, gy = 0, gz = 0;  // thread tid < nt: totals of target tid
-  for (int l0 = tb.p2p0; l0 < tb.p2p1; l0 += LM_S2T_SEG) {
-    const int nb = min(LM_S2T_SEG, tb.p2p1 - l0);
-    __syncthreads();
-    if (tid == 0) {
-      int cum = 0;
-      for (int e = 0; e < nb; e++) {
-        const SrcBox sb = d.sbox[d.p2p_list[l0 + e]];
-        seg_pt0[e] = sb.pt0;
-        seg_cum[e] = cum;
-        cum += sb.pt1 - sb.pt0;
-      }
-      seg_cum[nb] = cum;
-    }
-    __syncthreads();
-    const int ns = seg_cum[nb];
+  {
     const int npair = nt * ns;
     for (int q0 = 0; q0 < npair; q0 += LM_S2T_CHUNK) {
       const int q = q0 + tid;
       const bool pa = q < npair;
       const int i = pa ? q / ns : 0, j = pa ? q - (q / ns) * ns : 0;
-      int e = 0;
-      while (e + 1 < nb && seg_cum[e + 1] <= j) e++;
-      const int sid = d.src_perm[seg_pt0[e] + (j - seg_cum[e])];
+      const int sid = sl[j];
       const double* sx = sxyz + 3 * (long long)sid;
       double dx = tp[i][0] - sx[0], dy = tp[i][1] - sx[1];
       double tz = tp[i][2], uz = ip.up_s ? dls - sx[2] : sx[2] - dls;
@@ -1905,7 +1900,7 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t_grad(DevPlan d, MediumD
           const cd* cp = C + ((long long)r * n_src + sid) * 3;
           const cd cx = cp[0], cy = cp[1], czv = cp[2];
           const cd cpl = cx + I * cy, cmi = cx - I * cy;
-          const cd* wp = W + ((long long)r * n_tgt + d.tgt_perm[t0 + i]) * 3;
+          const cd* wp = W + ((long long)r * n_tgt + tpid[i]) * 3;
           const cd wpl = wp[0] + I * wp[1], wmi = wp[0] - I * wp[1], wz = wp[2];
           cd Q[3];
           for (int x = 0; x < 3; x++) {
@@ -1936,21 +1931,44 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t_grad(DevPlan d, MediumD
     }
   }
   if (tid < nt) {
-    gX[3 * id] += gx;
-    gX[3 * id + 1] += gy;
-    gX[3 * id + 2] += gz;
+    double* g = Gs + (slot0 + pos) * 3;
+    g[0] = gx;
+    g[1] = gy;
+    g[2] = gz;
   }
 }
-void launch_s2t_grad(const DevPlan& d, MediumDev md, const int* items, int n, const double* sxyz, const cd* C,
-                     long long n_src, const double* txyz, const cd* W, long long n_tgt, int n_rhs, double a,
-                     bool smallz, double* gX, hipStream_t s) {
+void launch_s2t_grad(const DevPlan& d, MediumDev md, const int* items, const int* tlist, const int* slist, int n,
+                     const double* sxyz, const cd* C, long long n_src, const double* txyz, const cd* W,
+                     long long n_tgt, int n_rhs, double a, bool smallz, double* Gs, hipStream_t s) {
   if (n <= 0) return;
   if (smallz)
-    hipLaunchKernelGGL(k_s2t_grad<true>, dim3(n), dim3(LM_S2T_CHUNK), 0, s, d, md, items, sxyz, C, n_src, txyz, W,
-                       n_tgt, n_rhs, a, gX);
+    hipLaunchKernelGGL(k_s2t_grad<true>, dim3(n), dim3(LM_S2T_CHUNK), 0, s, d, md, items, tlist, slist, sxyz, C,
+                       n_src, txyz, W, n_tgt, n_rhs, a, Gs);
   else
-    hipLaunchKernelGGL(k_s2t_grad<false>, dim3(n), dim3(LM_S2T_CHUNK), 0, s, d, md, items, sxyz, C, n_src, txyz,
-                       W, n_tgt, n_rhs, a, gX);
+    hipLaunchKernelGGL(k_s2t_grad<false>, dim3(n), dim3(LM_S2T_CHUNK), 0, s, d, md, items, tlist, slist, sxyz, C,
+                       n_src, txyz, W, n_tgt, n_rhs, a, Gs);
+}
+// gradient slots (three reals each) added into gX, per point in slot order
+__global__ void k_s2t_gather_grad(const int* gpt, const int* gptr, const int* gslot, int n_pts, const double* Gs,
+                                  double* gX) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pts) return;
+  double* g = gX + 3 * (long long)gpt[i];
+  double g0 = g[0], g1 = g[1], g2 = g[2];
+  for (int q = gptr[i]; q < gptr[i + 1]; q++) {
+    const double* Gp = Gs + 3 * (long long)gslot[q];
+    g0 += Gp[0];
+    g1 += Gp[1];
+    g2 += Gp[2];
+  }
+  g[0] = g0;
+  g[1] = g1;
+  g[2] = g2;
+}
+void launch_s2t_gather_grad(const int* gpt, const int* gptr, const int* gslot, int n_pts, const double* Gs,
+                            double* gX, hipStream_t s) {
+  if (n_pts <= 0) return;
+  hipLaunchKernelGGL(k_s2t_gather_grad, dim3((n_pts + NT - 1) / NT), dim3(NT), 0, s, gpt, gptr, gslot, n_pts, Gs, gX);
 }
 
 // items: n work items (target leaf, chunk, first output slot, offset of its
