@@ -333,13 +333,18 @@ def main():
     ms_per_step = 1000.0 * wall / args.steps
     value = args.n * args.rhs / (wall / args.steps)
     # roofline of the M2L GEMM kernel: algorithmic flops (8 real flops per
-    # complex multiply-add actually needed, absent-source columns excluded)
-    # per launch over the kernel's average launch duration
+    # complex multiply-add actually needed, absent-source columns excluded;
+    # reaction pairs as the even and odd blocks of the mirror-adapted tensor)
+    # per launch over the kernel's average launch duration.  The same M2L in
+    # the dense spin-basis form (three P x 3P products per reaction pair)
+    # needs about twice the work: reported beside it as the dense-equivalent
+    # rate.
     launches_per_step = gemm_launches / max(1, ncalls)
     launch_ms = gemm_ms_total / max(1, gemm_launches)
     m2l_flops = st["m2l_cmac_useful"] * 8.0 * args.rhs
     flops_per_launch = m2l_flops / max(1e-30, launches_per_step)
     achieved = flops_per_launch / (launch_ms * 1e-3) / 1e12
+    dense_per_launch = st["m2l_cmac_dense"] * 8.0 * args.rhs / max(1e-30, launches_per_step)
     # executed MFMA work (three real products per complex step, padded 16 x 16
     # tiles and k chunks): the matrix cores' own rate
     exec_per_launch = st["m2l_flop_exec"] * args.rhs / max(1e-30, launches_per_step)
@@ -523,6 +528,8 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": traffic,
                      "launch_ms": launch_ms, "launches_per_step": launches_per_step,
                      "algorithmic_flops_per_launch": flops_per_launch,
+                     "dense_form_flops_per_launch": dense_per_launch,
+                     "achieved_dense_equivalent": dense_per_launch / (launch_ms * 1e-3) / 1e12,
                      "executed_flops_per_launch": exec_per_launch,
                      "achieved_executed": achieved_exec,
                      "frac_executed": achieved_exec / FP64_VALU_PEAK_TFLOPS},

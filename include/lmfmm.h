@@ -296,7 +296,9 @@ int lm_stats(const lm_ctx* ctx, double* out_host, int n);
 #define LM_STAT_N_M2L_CLASSES 15
 #define LM_STAT_N_M2L_TILES_1RHS 16
 #define LM_STAT_M2L_CMAC_USEFUL 17   /* complex multiply-adds of the M2L per rhs   */
-#define LM_STAT_M2L_CMAC_EXEC 18     /* same, including absent-source columns      */
+                                     /* (reaction: the even and odd blocks of the  */
+                                     /* mirror-adapted tensor)                     */
+#define LM_STAT_M2L_CMAC_EXEC 18     /* same, rows padded to 64-row GEMM tiles     */
 #define LM_STAT_N_LEAVES_P2M 19
 #define LM_STAT_FREE_DEPTH 20
 #define LM_STAT_S2T_PAIRS 21         /* reaction near-field (S2T) point pairs        */
@@ -310,7 +312,10 @@ int lm_stats(const lm_ctx* ctx, double* out_host, int n);
 #define LM_STAT_REDUCE_BYTES 27      /* bytes the M2L reduction must move per rhs         */
 #define LM_STAT_S2T_NODE_EVALS 28    /* quadrature nodes summed over the direct reaction  */
                                      /* pairs (each pair stops at its own cut)            */
-#define LM_STATS_COUNT 29
+#define LM_STAT_M2L_CMAC_DENSE 29    /* complex multiply-adds of the same M2L per rhs in  */
+                                     /* the dense spin-basis form (three P x 3P products  */
+                                     /* per reaction pair, Sec. 3.3)                      */
+#define LM_STATS_COUNT 30
 
 /* ---- iterative solve over the evaluation ---- */
 

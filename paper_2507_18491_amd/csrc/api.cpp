@@ -487,6 +487,7 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
   if ((rc = upload(ctx, &d.offr, pl.offr))) return rc;
   if ((rc = upload(ctx, &d.bt_blk, pl.bt_blk))) return rc;
   if ((rc = upload(ctx, &d.pair_P, pl.pair_P))) return rc;
+  if ((rc = upload(ctx, &d.pair_phi, pl.pair_phi))) return rc;
   if ((rc = upload(ctx, &d.gaunt, pl.gaunt))) return rc;
   d.gaunt_p = pl.gaunt_p;
   if ((rc = upload(ctx, &d.Bcoef, pl.Bcoef))) return rc;
@@ -767,8 +768,21 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
       launch_tab_integrals(d, md, c0, nc, pl.p, (cd*)psc, maxnode, s);
       HIPC(hipGetLastError());
     }
-    launch_tab_assemble(d, 0, (int)pl.cases.size(), pl.p, pl.kmaxcheb, (ctx->pmax + 1) / 2 + 2, s);
-    HIPC(hipGetLastError());
+    hipFree(psc);
+    psc = nullptr;
+    // the + and z output rows of a batch of cases into bounded scratch, then
+    // the even and odd blocks of the mirror-adapted tensor into the tables
+    long long stride = 0;
+    for (auto& tc : pl.cases) stride = std::max(stride, 6LL * pl.inst[tc.inst].P * pl.inst[tc.inst].P);
+    const int ncs = (int)pl.cases.size();
+    const int bat = (int)std::max(1LL, std::min((long long)ncs, (512LL << 20) / (stride * 16)));
+    HIPC(hipMalloc(&psc, (size_t)bat * stride * sizeof(cd)));
+    for (int c0 = 0; c0 < ncs; c0 += bat) {
+      const int nc = std::min(bat, ncs - c0);
+      launch_tab_assemble(d, c0, nc, pl.p, pl.kmaxcheb, (ctx->pmax + 1) / 2 + 2, (cd*)psc, stride, s);
+      launch_tab_sym(d, c0, nc, (cd*)psc, stride, s);
+      HIPC(hipGetLastError());
+    }
     HIPC(hipStreamSynchronize(s));
     hipFree(psc);
     hipFree(pib);
@@ -859,9 +873,12 @@ static int make_schedule(lm_ctx* ctx, int n_rhs, long long budget, lm_ctx::TileS
       for (int o = 0; o < C.n_off; o++) {
         int np = pl.offr[B.offr0 + o + 1] - pl.offr[B.offr0 + o];
         int ncol = np * n_rhs;
-        int po = pl.offs[C.off0 + o].pord, Po = (po + 1) * (po + 1);
-        for (int ot = 0; ot < 3; ot++)
-          for (int r0 = 0; r0 < Po; r0 += TM_ROWS)
+        // free space: three output types of Po rows; reaction: the even and
+        // the odd block of the mirror-adapted tensor
+        const int po = pl.offs[C.off0 + o].pord, Po = (po + 1) * (po + 1);
+        const bool sym = C.nblk == 3;
+        for (int ot = 0; ot < (sym ? 2 : 3); ot++)
+          for (int r0 = 0; r0 < (sym ? lm_sym_dim(po, ot) : Po); r0 += TM_ROWS)
             for (int c0 = 0; c0 < ncol; c0 += TN_COLS) {
               M2LTile t;
               t.blk = (int)bi;
@@ -1429,32 +1446,53 @@ int lm_stats(const lm_ctx* ctx, double* out, int n) {
   v[LM_STAT_N_M2L_TILES_1RHS] = 0;
   {
     long long t = 0;
-    for (auto& C : pl.cls) t += 3LL * ((C.P + TM_ROWS - 1) / TM_ROWS) * ((C.n_tgt + TN_COLS - 1) / TN_COLS);
+    for (auto& C : pl.cls) {
+      const int p = pl.inst[C.inst].p;
+      const long long rt = C.nblk == 3 ? (lm_sym_dim(p, 0) + TM_ROWS - 1) / TM_ROWS + (lm_sym_dim(p, 1) + TM_ROWS - 1) / TM_ROWS
+                                       : 3LL * ((C.P + TM_ROWS - 1) / TM_ROWS);
+      t += rt * ((C.n_tgt + TN_COLS - 1) / TN_COLS);
+    }
     v[LM_STAT_N_M2L_TILES_1RHS] = (double)t;
   }
   {
-    // M2L work (complex multiply-adds) per right-hand side: useful (one
-    // P x nblk*P product per pair and output type) and as executed by the
-    // 64 x 64 GEMM tiles (padding of partial tiles included)
+    // M2L work (complex multiply-adds) per right-hand side: useful (free
+    // space: a Po x Po product per pair and output type; reaction: the even
+    // and the odd square block of the mirror-adapted tensor per pair) and as
+    // executed by the 64 x 64 GEMM tiles (padding of partial tiles included)
     double cm = 0, ce = 0;
     for (const M2LBlock& B : pl.blocks) {
       const M2LClass& C = pl.cls[B.cls];
       for (int o = 0; o < C.n_off; o++) {
-        int np = pl.offr[B.offr0 + o + 1] - pl.offr[B.offr0 + o];
-        int po = pl.offs[C.off0 + o].pord, Po = (po + 1) * (po + 1);
-        double K = (double)C.nblk * Po;
-        double rows = (double)((Po + TM_ROWS - 1) / TM_ROWS) * TM_ROWS;
-        cm += 3.0 * Po * K * np;
-        ce += 3.0 * rows * K * (double)((np + TN_COLS - 1) / TN_COLS) * TN_COLS;
+        const int np = pl.offr[B.offr0 + o + 1] - pl.offr[B.offr0 + o];
+        const int po = pl.offs[C.off0 + o].pord, Po = (po + 1) * (po + 1);
+        const double cols = (double)((np + TN_COLS - 1) / TN_COLS) * TN_COLS;
+        for (int ot = 0; ot < 3; ot++) {
+          if (C.nblk == 3 && ot == 2) break;
+          const double R = C.nblk == 3 ? lm_sym_dim(po, ot) : Po;
+          const double rows = (double)(((int)R + TM_ROWS - 1) / TM_ROWS) * TM_ROWS;
+          cm += R * R * np;
+          ce += rows * R * cols;
+        }
       }
     }
     v[LM_STAT_M2L_CMAC_USEFUL] = cm;
     v[LM_STAT_M2L_CMAC_EXEC] = ce;
+    double cd_ = 0;
+    for (const M2LBlock& B : pl.blocks) {
+      const M2LClass& C = pl.cls[B.cls];
+      for (int o = 0; o < C.n_off; o++) {
+        const int np = pl.offr[B.offr0 + o + 1] - pl.offr[B.offr0 + o];
+        const int po = pl.offs[C.off0 + o].pord;
+        const double Po = (po + 1) * (po + 1);
+        cd_ += 3.0 * Po * C.nblk * Po * np;
+      }
+    }
+    v[LM_STAT_M2L_CMAC_DENSE] = cd_;
   }
   {
     // executed MFMA flops of the M2L GEMM per rhs (variant 0: 16 values of k
     // per chunk): a wave computes the 16 x 16 tiles that hold a row below
-    // the offset's (pord+1)^2 and a column below the tile's pair count, over
+    // the offset's used rows and a column below the tile's pair count, over
     // k padded to whole chunks, with three real MFMAs per complex step
     double fe = 0;
     for (const M2LBlock& B : pl.blocks) {
@@ -1463,9 +1501,13 @@ int lm_stats(const lm_ctx* ctx, double* out, int n) {
         const long long np = pl.offr[B.offr0 + o + 1] - pl.offr[B.offr0 + o];
         if (np == 0) continue;
         const int po = pl.offs[C.off0 + o].pord, Po = (po + 1) * (po + 1);
-        const double rows = (double)((Po + 15) / 16) * 16, cols = (double)((np + 15) / 16) * 16;
-        const double kp = (double)((C.nblk * Po + 15) / 16) * 16;
-        fe += 3.0 * rows * cols * kp * 3.0 * 2.0;
+        const double cols = (double)((np + 15) / 16) * 16;
+        for (int ot = 0; ot < 3; ot++) {
+          if (C.nblk == 3 && ot == 2) break;
+          const int R = C.nblk == 3 ? lm_sym_dim(po, ot) : Po;
+          const double rows = (double)((R + 15) / 16) * 16, kp = (double)((R + 15) / 16) * 16;
+          fe += rows * cols * kp * 3.0 * 2.0;
+        }
       }
     }
     v[LM_STAT_M2L_FLOP_EXEC] = fe;

@@ -34,6 +34,7 @@ struct DevPlan {
   int* offr;
   int* bt_blk;          // block of each block-target
   int* pair_P;          // per pair: number of rows/columns used ((pord+1)^2)
+  double* pair_phi;     // per pair: azimuth of its offset (reaction output phases)
   long long* blk_ybase; // per block: first scratch element (depends on the rhs count)
   cd* mats;        // all translation / M2L matrices
   double* gaunt;
@@ -55,7 +56,9 @@ void launch_nodes(const DevPlan& d, MediumDev med, int n_nodes, const int* node_
                   const cd* w, hipStream_t s);
 void launch_tab_integrals(const DevPlan& d, MediumDev med, int case0, int ncase, int p, cd* scratch,
                           long long scratch_stride, hipStream_t s);
-void launch_tab_assemble(const DevPlan& d, int case0, int ncase, int p, int kmaxcheb, int bstride, hipStream_t s);
+void launch_tab_assemble(const DevPlan& d, int case0, int ncase, int p, int KB, int BS, cd* out, long long stride,
+                         hipStream_t s);
+void launch_tab_sym(const DevPlan& d, int case0, int ncase, const cd* src, long long stride, hipStream_t s);
 void launch_p2m(const DevPlan& d, const int* items, int n, const double* xyz, const cd* J, long long n_src,
                 int n_rhs, cd* ME, cd* part, int pl, hipStream_t s);
 void launch_p2m_sum(const DevPlan& d, const int* items, int n, int n_rhs, const cd* part, int Pg, cd* ME,

@@ -350,26 +350,64 @@ void launch_l2l(const DevPlan& d, const int* children, int n, int n_rhs, cd* LE,
 }
 
 // ------------------------------------------------------------------ M2L
-// Tiled complex GEMM, one tile per (block, offset o, output type, row tile,
-// 64 (pair, rhs) columns):  Y_q[out] = e^{-i m phi_o} A_o[out] X_q,  where
-// X_q stacks the source box's channel vectors multiplied by
-// e^{i (kappa + mu) phi_o} (reaction: the three-block spin-basis form of the
-// M2L tensor, Sec. 3.3; free space: one block, phi = 0).  Only pairs whose
-// source box exists are columns.  Y is a scratch buffer; a second kernel
-// adds, per target, its pairs in a fixed order (no atomics).
+// Tiled complex GEMM, one tile per (block, offset o, output part, row tile,
+// 64 (pair, rhs) columns).  Free space (one channel per output type, phi =
+// 0): Y_q[ot] = A_o X_q[ot].
+// Reaction: the spin-basis M2L tensor of Sec. 3.3 maps the channels (u+,
+// u-, z) of the source box to the outputs (+, -, z) through blocks
+// V(sigma, kappa) with the azimuthal phase e^{i q phi}, q = kappa - m + mu.
+// Every block has kappa = a_o - b_c (a = 1, -1, 0 for the outputs +, -, z;
+// b = 1, -1, 0 for the channels u+, u-, z), so the tensor is
+// e^{i (a_o - m) phi} V e^{i (mu - b_c) phi} with a phase-free core V, and V
+// commutes with the mirror S: (S x)_{+,nm} = e_m x_{-,n,-m},
+// (S x)_{-,nm} = e_m x_{+,n,-m}, (S x)_{z,nm} = e_m x_{z,n,-m}, e_m =
+// (-1)^m, because P^{-m}_n = e_m P^m_n, J_|q| depends on |q| only, and the
+// blocks of the - output are the kappa -> -kappa images of those of the +
+// output with the same densities (the z output's blocks pair among
+// themselves).  V therefore maps the even part (x + S x)/2 and the odd part
+// (x - S x)/2 of the phased input x~_c = e^{i (mu - b_c) phi} X_c
+// separately: two square GEMMs of dimension lm_sym_dim(q, 0) and
+// lm_sym_dim(q, 1) (about 1.5 (q+1)^2 each) in place of the 3 (q+1)^2
+// square one, half the multiply-adds.  The even (odd) coordinates are
+//   + part:  x~_{u+,nm} + (-) e_m x~_{u-,n,-m}   (every nm),
+//   z part:  x~_{z,nm} + (-) e_m x~_{z,n,-m}     (m >= 1; m = 0: x~_{z,n0}, even only),
+// and k_tab_sym stores V in these coordinates.  Tiles write the phase-free
+// even and odd outputs; k_m2l_reduce recombines them per pair and applies
+// e^{i (a_o - m) phi}.  Only pairs whose source box exists are columns.  Y
+// is a scratch buffer; the reduction adds, per target, its pairs in a fixed
+// order (no atomics).
 #define TM 64
 #define TN 64
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // Shared state of one M2L tile (read by all waves of the block).
 struct M2LTileCtx {
-  const cd* A;        // the offset's P x Kf matrix of this output type
+  const cd* A;        // free: the offset's P x P matrix; reaction: its even or odd block
   const cd* ME;
   cd* Y;
   long long ybase;    // scratch base of the tile's block
-  int P, Po, K, Kf, p, ot, row0, ncol, col0, qo, q0b, n_rhs;
-  bool phased;
+  int P;              // (p+1)^2 of the class
+  int R;              // rows = columns used by this offset's order
+  int Pb;             // (pord+1)^2: the leading R entries are Pb of the first part, then the second part
+  int Kf;             // row pitch of the stored matrix (its full dimension)
+  int p, ot, row0, ncol, col0, qo, q0b, n_rhs;
+  bool sym;           // reaction: ot 0 = even block, 1 = odd block
 };
+
+// stored row / column of the offset's r-th used row / column: the first Pb
+// entries, then the second part from position P on
+__device__ __forceinline__ int m2l_sidx(const M2LTileCtx& c, int r) { return r < c.Pb ? r : c.P + (r - c.Pb); }
+
+// (n, m) of entry j of the z part of the even (m >= 0) or odd (m >= 1)
+// coordinates, as the index n^2 + n + m
+__device__ inline int sym_znm(int j, int par) {
+  int n = par, base = 0;  // base: first entry of order n
+  while (j >= base + n + 1 - par) {
+    base += n + 1 - par;
+    n++;
+  }
+  return n * n + n + (j - base) + par;
+}
 
 // Operand planes are row-major, [row or column][k], pitch KCV + 1 doubles
 // (KCV values of k per chunk, NB chunk buffers): the threads that store one
@@ -382,23 +420,11 @@ struct M2LLds {
   long long sbase[TN];
   cd eph[2 * LM_PMAX + 8];
   short mu_of[(LM_PMAX + 1) * (LM_PMAX + 1)];
+  short zmap[(LM_PMAX + 1) * (LM_PMAX + 2) / 2];  // z part: entry -> n^2 + n + m
 };
 
-// input channel and kappa of column block bl (reaction, spin basis):
-//   out +: (u+, 0), (u-, 2), (z, 1);  out -: (u-, 0), (u+, -2), (z, -1);
-//   out z: (u-, 1), (u+, -1), (z, 0).  Packed as 2 bits (channel) and
-//   3 bits (kappa + 2) per (ot, bl) entry.
-__device__ inline int m2l_rch(bool phased, int ot, int bl) {
-  const unsigned CH = 0u | 1u << 2 | 2u << 4 | 1u << 6 | 0u << 8 | 2u << 10 | 1u << 12 | 0u << 14 | 2u << 16;
-  return phased ? (int)((CH >> (2 * (3 * ot + bl))) & 3u) : ot;
-}
-__device__ inline int m2l_rkap(bool phased, int ot, int bl) {
-  const unsigned KP = 2u | 4u << 3 | 3u << 6 | 2u << 9 | 0u << 12 | 1u << 15 | 3u << 18 | 1u << 21 | 2u << 24;
-  return phased ? (int)((KP >> (3 * (3 * ot + bl))) & 7u) - 2 : 0;
-}
-
 // K loop and epilogue of one wave whose 32 x 32 wave tile has NI x NJ active
-// 16 x 16 MFMA tiles (NI, NJ in 0..2; rows beyond Po and columns beyond the
+// 16 x 16 MFMA tiles (NI, NJ in 0..2; rows beyond R and columns beyond the
 // pair count are never computed).  Every wave of the block runs the same
 // number of barriers whatever its NI, NJ.
 // MFMA operand layout (v_mfma_f64_16x16x4f64, one fp64 per lane and
@@ -413,7 +439,7 @@ __device__ inline int m2l_rkap(bool phased, int ot, int bl) {
 // multiplies and waits again; NB = 2 loads the next chunk into registers
 // while the current one is multiplied and stores it into the other buffer
 // (one barrier per chunk).
-template <int KCV, int NB, int NI, int NJ>
+template <int KCV, int NB, int NI, int NJ, bool SYM>
 __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds<KCV, NB>& L, int tid, int wr, int wc) {
   constexpr int NIx = NI > 0 ? NI : 1, NJx = NJ > 0 ? NJ : 1;
   v4d p1[NIx][NJx], p2[NIx][NJx], p3[NIx][NJx];
@@ -433,60 +459,84 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds<KCV, NB>& L
   // columns r16 + RPI it; indices outside the tile are clamped to a valid
   // entry and the value zeroed
   const int kk = tid & (KCV - 1), r16 = tid / KCV;
-  long long aoff[NA], boff[NB_];
-  bool aok[NA], bok[NB_];
+  int aoff[NA];  // below 2^31: the largest matrix has lm_sym_dim(LM_PMAX, 0)^2 entries
+  bool aok[NA];
 #pragma unroll
   for (int it = 0; it < NA; it++) {
     int row = c.row0 + r16 + RPI * it;
-    aok[it] = row < c.Po;
-    aoff[it] = (long long)(aok[it] ? row : c.Po - 1) * c.Kf;
+    aok[it] = row < c.R;
+    aoff[it] = m2l_sidx(c, aok[it] ? row : c.R - 1) * c.Kf;
   }
-#pragma unroll
-  for (int it = 0; it < NB_; it++) {
-    long long sb = L.sbase[r16 + RPI * it];
-    bok[it] = sb >= 0;
-    boff[it] = sb >= 0 ? sb : L.sbase[0];
-  }
-  cd ra[NA], rb[NB_];
+  cd ra[NA], rb[NB_], rm[SYM ? NB_ : 1];
+  // source coordinate of this thread's k (reaction): channel entries i1 and
+  // i2 (its mirror) with phases e^{i e1 phi} and e^{-i e1 phi}, the mirror
+  // term with sign s2 (-1, 0 or 1)
+  int e1 = 0, s2 = 0;
   auto load = [&](int k0) {
     const int k = k0 + kk;
-    const bool kok = k < c.K;
-    const int kc = kok ? k : c.K - 1;
-    const int bl = kc >= c.Po ? (kc >= 2 * c.Po ? 2 : 1) : 0;
-    const int num = kc - bl * c.Po;
-    const long long colA = (long long)bl * c.P + num;
-    const long long colB = (long long)m2l_rch(c.phased, c.ot, bl) * c.P + num;
+    const bool kok = k < c.R;
+    const int kc = kok ? k : c.R - 1;
+    const int colA = m2l_sidx(c, kc);
+    // source columns: base offsets re-read from LDS (fewer live registers);
+    // columns without a pair read column 0 and are zeroed
+    long long boff[NB_];
+    bool bok[NB_];
+#pragma unroll
+    for (int it = 0; it < NB_; it++) {
+      const long long sb = L.sbase[r16 + RPI * it];
+      bok[it] = sb >= 0;
+      boff[it] = sb >= 0 ? sb : L.sbase[0];
+    }
 #pragma unroll
     for (int it = 0; it < NA; it++) {
       cd v = c.A[aoff[it] + colA];
       ra[it] = (aok[it] && kok) ? v : cd{0, 0};
     }
+    if (SYM) {
+      const bool zp = kc >= c.Pb;
+      const int nm = zp ? L.zmap[kc - c.Pb] : kc;
+      const int mu = L.mu_of[nm];
+      const int i1 = (zp ? 2 * c.P : 0) + nm;          // u+ or z
+      const int i2 = (zp ? 2 * c.P : c.P) + nm - 2 * mu;  // u- or z, order -mu
+      e1 = zp ? mu : mu - 1;
+      s2 = (zp && mu == 0) ? 0 : ((c.ot ? -1 : 1) * ((mu & 1) ? -1 : 1));
 #pragma unroll
-    for (int it = 0; it < NB_; it++) {
-      cd v = c.ME[boff[it] + colB];
-      rb[it] = (bok[it] && kok) ? v : cd{0, 0};
+      for (int it = 0; it < NB_; it++) {
+        cd v = c.ME[boff[it] + i1], w = c.ME[boff[it] + i2];
+        rb[it] = (bok[it] && kok) ? v : cd{0, 0};
+        rm[it] = (bok[it] && kok) ? w : cd{0, 0};
+      }
+    } else {
+      const long long colB = (long long)c.ot * c.P + kc;
+#pragma unroll
+      for (int it = 0; it < NB_; it++) {
+        cd v = c.ME[boff[it] + colB];
+        rb[it] = (bok[it] && kok) ? v : cd{0, 0};
+      }
     }
   };
-  // registers -> LDS planes of buffer bf; source values times the offset's
-  // phase e^{i (kappa + mu) phi}, which depends on k only
-  auto store = [&](int k0, int bf) {
-    cd ph = cd{1, 0};
-    if (c.phased) {
-      const int k = k0 + kk;
-      const int kc = k < c.K ? k : c.K - 1;
-      const int bl = kc >= c.Po ? (kc >= 2 * c.Po ? 2 : 1) : 0;
-      ph = L.eph[m2l_rkap(true, c.ot, bl) + L.mu_of[kc - bl * c.Po] + c.p + 2];
-    }
+  // registers -> LDS planes of buffer bf (reaction: the even or odd
+  // coordinate of the phased source vector)
+  auto store = [&](int bf) {
 #pragma unroll
     for (int it = 0; it < NA; it++) {
       L.Ar[bf][r16 + RPI * it][kk] = ra[it].x;
       L.Ai[bf][r16 + RPI * it][kk] = ra[it].y;
     }
+    if (SYM) {
+      const cd ph1 = L.eph[e1 + c.p + 2], ph2 = (double)s2 * cconj(ph1);
 #pragma unroll
-    for (int it = 0; it < NB_; it++) {
-      cd v = c.phased ? rb[it] * ph : rb[it];
-      L.Br[bf][r16 + RPI * it][kk] = v.x;
-      L.Bi[bf][r16 + RPI * it][kk] = v.y;
+      for (int it = 0; it < NB_; it++) {
+        cd v = ph1 * rb[it] + ph2 * rm[it];
+        L.Br[bf][r16 + RPI * it][kk] = v.x;
+        L.Bi[bf][r16 + RPI * it][kk] = v.y;
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < NB_; it++) {
+        L.Br[bf][r16 + RPI * it][kk] = rb[it].x;
+        L.Bi[bf][r16 + RPI * it][kk] = rb[it].y;
+      }
     }
   };
   auto mma = [&](int bf) {
@@ -523,9 +573,9 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds<KCV, NB>& L
     }
   };
   if (NB == 1) {
-    for (int k0 = 0; k0 < c.K; k0 += KCV) {
+    for (int k0 = 0; k0 < c.R; k0 += KCV) {
       load(k0);
-      store(k0, 0);
+      store(0);
       __syncthreads();
       mma(0);
       __syncthreads();
@@ -535,21 +585,23 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds<KCV, NB>& L
     // in flight during this chunk's MFMAs, and its stores go to the buffer
     // that every wave finished reading before the previous barrier
     load(0);
-    store(0, 0);
+    store(0);
     __syncthreads();
-    for (int k0 = 0; k0 < c.K; k0 += KCV) {
+    for (int k0 = 0; k0 < c.R; k0 += KCV) {
       const int bf = (k0 / KCV) & 1;
-      const bool more = k0 + KCV < c.K;
+      const bool more = k0 + KCV < c.R;
       if (more) load(k0 + KCV);
       mma(bf);
-      if (more) store(k0 + KCV, bf ^ 1);
+      if (more) store(bf ^ 1);
       __syncthreads();
     }
   }
   if (NI == 0 || NJ == 0) return;
   // epilogue: lane holds rows 4 r + lane / 16 of each 16 x 16 tile, column
   // lane % 16; column j of the tile is (pair, rhs) = (qo + (col0 + j) / n_rhs,
-  // (col0 + j) % n_rhs) and goes to that pair's scratch vector
+  // (col0 + j) % n_rhs) and goes to that pair's scratch vector: free space
+  // [pair][ot][rhs][P], reaction [pair][even: rhs][lm_sym_dim(p, 0)] then
+  // [odd: rhs][lm_sym_dim(p, 1)] (3 n_rhs P per pair either way)
   const int li = lane & 15, rq = lane >> 4;
 #pragma unroll
   for (int i = 0; i < NIx; i++)
@@ -560,28 +612,28 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds<KCV, NB>& L
       v4d vr = p1[i][j] - p2[i][j], vi = p3[i][j] - p1[i][j] - p2[i][j];
       const int jj = c.col0 + col;
       const int q = c.qo + jj / c.n_rhs, r = jj % c.n_rhs;
-      cd* Yq = c.Y + c.ybase + ((long long)((q - c.q0b) * 3 + c.ot) * c.n_rhs + r) * c.P;
+      cd* Yq = SYM ? c.Y + c.ybase + (long long)(q - c.q0b) * 3 * c.n_rhs * c.P +
+                           (c.ot ? (long long)c.n_rhs * lm_sym_dim(c.p, 0) : 0) + (long long)r * c.Kf
+                     : c.Y + c.ybase + ((long long)((q - c.q0b) * 3 + c.ot) * c.n_rhs + r) * c.P;
 #pragma unroll
       for (int rr = 0; rr < 4; rr++) {
         const int row = c.row0 + wr * 32 + i * 16 + 4 * rr + rq;
-        if (row >= c.Po) continue;
-        cd v = cd{vr[rr], vi[rr]};
-        if (c.phased) v = cconj(L.eph[L.mu_of[row] + c.p + 2]) * v;
-        Yq[row] = v;
+        if (row >= c.R) continue;
+        Yq[m2l_sidx(c, row)] = cd{vr[rr], vi[rr]};
       }
     }
 }
 
 // One 64 x 64 output tile per block, complex fp64 on the matrix cores.  The
 // four waves form a 2 x 2 grid of 32 x 32 wave tiles; a wave computes only
-// those of its four 16 x 16 MFMA tiles that hold rows below the offset's
-// (pord+1)^2 and columns below the tile's pair count, so partial tiles cost
-// little; the choice is made once per tile from a wave-uniform value.
-// Operands are staged through LDS as separate real / imaginary planes, KCV
-// values of k at a time (variants above); resident blocks overlap one
-// block's global loads with the others' MFMAs.  Consecutive tiles are sent
-// to one XCD (blocks are dealt round-robin over the 8 XCDs), so the tiles
-// sharing one offset's matrix and source vectors run against one L2.
+// those of its four 16 x 16 MFMA tiles that hold rows below the offset's R
+// and columns below the tile's pair count, so partial tiles cost little;
+// the choice is made once per tile from a wave-uniform value.  Operands are
+// staged through LDS as separate real / imaginary planes, KCV values of k at
+// a time (variants above); resident blocks overlap one block's global loads
+// with the others' MFMAs.  Consecutive tiles are sent to one XCD (blocks are
+// dealt round-robin over the 8 XCDs), so the tiles sharing one offset's
+// matrix and source vectors run against one L2.
 template <int KCV, int NB, int OCC>
 __global__ __launch_bounds__(NT, OCC) void k_m2l(DevPlan d, const M2LTile* tiles, int n_tiles, int n_rhs,
                                                  const cd* ME, cd* Y) {
@@ -598,12 +650,13 @@ __global__ __launch_bounds__(NT, OCC) void k_m2l(DevPlan d, const M2LTile* tiles
   c.P = C.P;
   c.p = d.inst[C.inst].p;
   c.ot = tl.out_type;
-  c.phased = (C.nblk == 3);
-  // order used for this offset: the leading Po rows and, in every column
-  // block, the leading Po columns of the P x nblk*P matrix
-  c.Po = (offp->pord + 1) * (offp->pord + 1);
-  c.Kf = C.nblk * C.P;
-  c.K = C.nblk * c.Po;
+  c.sym = (C.nblk == 3);
+  // order used for this offset: free space, the leading Pb rows and columns
+  // of the P x P matrix; reaction, the leading entries of both parts
+  const int po = offp->pord;
+  c.Pb = (po + 1) * (po + 1);
+  c.R = c.sym ? lm_sym_dim(po, c.ot) : c.Pb;
+  c.Kf = c.sym ? lm_sym_dim(c.p, c.ot) : c.P;
   c.row0 = tl.row0;
   c.ncol = tl.ncol;
   c.col0 = tl.col0;
@@ -611,13 +664,20 @@ __global__ __launch_bounds__(NT, OCC) void k_m2l(DevPlan d, const M2LTile* tiles
   c.q0b = B.q0;
   c.n_rhs = n_rhs;
   c.ybase = d.blk_ybase[tl.blk];    // per-block scratch base (blocks differ in P)
-  c.A = d.mats + offp->mat[c.ot];
+  c.A = d.mats + offp->mat[c.sym ? c.ot : 0];
   c.ME = ME;
   c.Y = Y;
-  const double phi = offp->phi;
-  for (int e = tid; e < c.P; e += NT) {
-    int n = n_of(e);
-    L.mu_of[e] = (short)(e - n * n - n);
+  if (c.sym) {
+    const double phi = offp->phi;
+    for (int e = tid; e < c.P; e += NT) {
+      int n = n_of(e);
+      L.mu_of[e] = (short)(e - n * n - n);
+    }
+    for (int e = tid; e < lm_sym_dim(c.p, c.ot) - c.P; e += NT) L.zmap[e] = (short)sym_znm(e, c.ot);
+    if (tid < 2 * c.p + 5) {
+      double a = (tid - (c.p + 2)) * phi;
+      L.eph[tid] = cd{cos(a), sin(a)};
+    }
   }
   if (tid < TN) {
     long long v = -1;
@@ -628,23 +688,29 @@ __global__ __launch_bounds__(NT, OCC) void k_m2l(DevPlan d, const M2LTile* tiles
     }
     L.sbase[tid] = v;
   }
-  if (tid < 2 * c.p + 5) {
-    double a = (tid - (c.p + 2)) * phi;
-    L.eph[tid] = cd{cos(a), sin(a)};
-  }
   __syncthreads();
   // this wave's active MFMA tiles (uniform over the wave, kept in an SGPR)
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
-  const int ni = (c.row0 + wr * 32 < c.Po) + (c.row0 + wr * 32 + 16 < c.Po);
+  const int ni = (c.row0 + wr * 32 < c.R) + (c.row0 + wr * 32 + 16 < c.R);
   const int nj = (wc * 32 < c.ncol) + (wc * 32 + 16 < c.ncol);
   const int pat = __builtin_amdgcn_readfirstlane(ni * 3 + nj);
-  switch (pat) {
-    case 4: m2l_wave<KCV, NB, 1, 1>(c, L, tid, wr, wc); break;
-    case 5: m2l_wave<KCV, NB, 1, 2>(c, L, tid, wr, wc); break;
-    case 7: m2l_wave<KCV, NB, 2, 1>(c, L, tid, wr, wc); break;
-    case 8: m2l_wave<KCV, NB, 2, 2>(c, L, tid, wr, wc); break;
-    default: m2l_wave<KCV, NB, 0, 0>(c, L, tid, wr, wc); break;
+  if (c.sym) {
+    switch (pat) {
+      case 4: m2l_wave<KCV, NB, 1, 1, true>(c, L, tid, wr, wc); break;
+      case 5: m2l_wave<KCV, NB, 1, 2, true>(c, L, tid, wr, wc); break;
+      case 7: m2l_wave<KCV, NB, 2, 1, true>(c, L, tid, wr, wc); break;
+      case 8: m2l_wave<KCV, NB, 2, 2, true>(c, L, tid, wr, wc); break;
+      default: m2l_wave<KCV, NB, 0, 0, true>(c, L, tid, wr, wc); break;
+    }
+  } else {
+    switch (pat) {
+      case 4: m2l_wave<KCV, NB, 1, 1, false>(c, L, tid, wr, wc); break;
+      case 5: m2l_wave<KCV, NB, 1, 2, false>(c, L, tid, wr, wc); break;
+      case 7: m2l_wave<KCV, NB, 2, 1, false>(c, L, tid, wr, wc); break;
+      case 8: m2l_wave<KCV, NB, 2, 2, false>(c, L, tid, wr, wc); break;
+      default: m2l_wave<KCV, NB, 0, 0, false>(c, L, tid, wr, wc); break;
+    }
   }
 }
 // variant: 0 = 16 values of k per chunk, one buffer, three blocks per CU;
@@ -661,26 +727,96 @@ void launch_m2l(const DevPlan& d, const M2LTile* tiles, int n_tiles, int n_rhs, 
   }
 }
 
-// LE_t[out][rhs] += sum over the target's pairs (fixed offset order) of Y
+// LE_t[out][rhs] += sum over the target's pairs (fixed offset order) of the
+// pair's output.  Free space: Y as written.  Reaction: the pair's even (E)
+// and odd (O) outputs recombined and phased (k_m2l), with e_m = (-1)^m and
+// the z part indexed by (n, |m|):
+//   (+, nm):  e^{i (1 - m) phi} (E_{+,nm} + O_{+,nm})
+//   (-, nm):  e^{i (-1 - m) phi} e_m (E_{+,n,-m} - O_{+,n,-m})
+//   (z, nm):  e^{-i m phi} (E_{z,n|m|} + O_{z,n|m|}) for m >= 0 (no O at m = 0),
+//             e^{-i m phi} e_m (E_{z,n|m|} - O_{z,n|m|}) for m < 0;
+// the phases of LM_RED_PAIRS pairs at a time are tabulated in LDS, and each
+// such group is added into LE in turn.  (At m = 0 of the z part, O is absent
+// and the second output coincides with the first: only the first is kept.)
+#define LM_RED_PAIRS 32
 __global__ __launch_bounds__(NT) void k_m2l_reduce(DevPlan d, int bt0, int n_rhs, const cd* Y, cd* LE) {
+  __shared__ cd ph[LM_RED_PAIRS][2 * LM_PMAX + 5];
   int bt = bt0 + blockIdx.x;
   TgtBox tb = d.tbox[d.bt_tbox[bt]];
-  int P = d.inst[tb.inst].P;
+  const int P = d.inst[tb.inst].P, p = d.inst[tb.inst].p;
   int blk = d.bt_blk[bt];
   long long ybase = d.blk_ybase[blk];
   int qb = d.blocks[blk].q0;
   int q0 = d.bt_ptr[bt], q1 = d.bt_ptr[bt + 1];
   int nel = 3 * n_rhs * P;
-  for (int e = threadIdx.x; e < nel; e += NT) {
-    int tr_ = e / P, row = e - tr_ * P;   // tr_ = ot * n_rhs + r
-    int ot = tr_ / n_rhs, r = tr_ - ot * n_rhs;
-    cd s = cd{0, 0};
-    for (int qi = q0; qi < q1; qi++) {
-      int q = d.bt_pairs[qi];
-      if (row < d.pair_P[q]) s = s + Y[ybase + ((long long)(q - qb) * 3 * n_rhs + tr_) * P + row];
+  if (d.cls[d.blocks[blk].cls].nblk != 3) {
+    for (int e = threadIdx.x; e < nel; e += NT) {
+      int tr_ = e / P, row = e - tr_ * P;   // tr_ = ot * n_rhs + r
+      int ot = tr_ / n_rhs, r = tr_ - ot * n_rhs;
+      cd s = cd{0, 0};
+      for (int qi = q0; qi < q1; qi++) {
+        int q = d.bt_pairs[qi];
+        if (row < d.pair_P[q]) s = s + Y[ybase + ((long long)(q - qb) * 3 * n_rhs + tr_) * P + row];
+      }
+      long long idx = tb.le_off * n_rhs + ((long long)r * 3 + ot) * P + row;
+      LE[idx] = LE[idx] + s;
     }
-    long long idx = tb.le_off * n_rhs + ((long long)r * 3 + ot) * P + row;
-    LE[idx] = LE[idx] + s;
+    return;
+  }
+  const int Re = lm_sym_dim(p, 0), Ro = lm_sym_dim(p, 1), NJ = 2 * p + 5;
+  // one thread per (rhs, entry of the even part): the + part entries nm give
+  // (+, nm) and (-, n, -m), the z part entries (n, m >= 0) give (z, n, m) and
+  // (z, n, -m); both outputs of an entry read the same E and O entries, with
+  // conjugate phases
+  for (int c0 = q0; c0 < q1; c0 += LM_RED_PAIRS) {
+    const int nc = min(LM_RED_PAIRS, q1 - c0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nc * NJ; e += NT) {
+      const int i = e / NJ, j = e - i * NJ;
+      const double a = (j - (p + 2)) * d.pair_phi[d.bt_pairs[c0 + i]];
+      ph[i][j] = cd{cos(a), sin(a)};
+    }
+    __syncthreads();
+    for (int u = threadIdx.x; u < n_rhs * Re; u += NT) {
+      const int r = u / Re, w = u - r * Re;  // w: entry of the even part
+      const bool zp = w >= P;
+      int n, m, io, jph;
+      if (!zp) {
+        n = n_of(w);
+        m = w - n * n - n;
+        io = w;
+        jph = 1 - m;   // e^{i (1 - m) phi} on (+, nm), its conjugate on (-, n, -m)
+      } else {
+        const int t = w - P;  // (n, m >= 0) in the z part
+        n = 0;
+        while ((n + 1) * (n + 2) / 2 <= t) n++;
+        m = t - n * (n + 1) / 2;
+        io = w - n - 1;       // (n, m) in the z part of O (m >= 1)
+        jph = -m;             // e^{-i m phi} on (z, nm), its conjugate on (z, n, -m)
+      }
+      const int nm = n * n + n + m;
+      const bool has_o = !zp || m > 0;
+      cd s1 = cd{0, 0}, s2 = cd{0, 0};
+      for (int i = 0; i < nc; i++) {
+        const int q = d.bt_pairs[c0 + i];
+        if (nm >= d.pair_P[q]) continue;
+        const cd* Yp = Y + ybase + (long long)(q - qb) * 3 * n_rhs * P;
+        const cd E = Yp[(long long)r * Re + w];
+        const cd O = has_o ? Yp[(long long)n_rhs * Re + (long long)r * Ro + io] : cd{0, 0};
+        const cd f = ph[i][jph + p + 2];
+        s1 = s1 + f * (E + O);
+        s2 = s2 + cconj(f) * (E - O);
+      }
+      const double em = (m & 1) ? -1.0 : 1.0;
+      cd* L0 = LE + tb.le_off * n_rhs + (long long)r * 3 * P;
+      if (!zp) {
+        L0[nm] = L0[nm] + s1;
+        L0[P + nm - 2 * m] = L0[P + nm - 2 * m] + em * s2;
+      } else {
+        L0[2 * P + nm] = L0[2 * P + nm] + s1;
+        if (m > 0) L0[2 * P + nm - 2 * m] = L0[2 * P + nm - 2 * m] + em * s2;
+      }
+    }
   }
 }
 void launch_m2l_reduce(const DevPlan& d, int bt0, int nbt, int n_rhs, const cd* Y, cd* LE, int pmax,
@@ -2312,7 +2448,12 @@ void launch_tab_integrals(const DevPlan& d, MediumDev med, int case0, int ncase,
 //   A_ij = sum_s C_js (I_{i+s} + I_{|i-s|})   (roles of i, j swapped if k > k')
 // and V = 4 pi i^{1+n+|q|} (-i)^nu s^{n+m+nu+mu} Ihat with q = kappa - m + mu.
 // The matrices for the three spin outputs are stored as P x 3P blocks.
-__global__ __launch_bounds__(NT) void k_tab_assemble(DevPlan d, int case0, int p, int KB, int BS) {
+// Writes, per case, the + and z output rows of the spin-basis tensor (the -
+// rows are their mirror images): out[ci * stride + (slot * P + a) * 3P + blk * P
+// + b], slot 0 for +, 1 for z, with the column blocks of each output type in the order of its
+// input channels (+: u+, u-, z; z: u-, u+, z).
+__global__ __launch_bounds__(NT) void k_tab_assemble(DevPlan d, int case0, int p, int KB, int BS, cd* out,
+                                                     long long stride) {
   extern __shared__ cd Aij[];  // [(KB+1)^2][NQ]
   int ci = blockIdx.x, sg = blockIdx.y;
   TabCase tc = d.cases[case0 + ci];
@@ -2333,7 +2474,7 @@ __global__ __launch_bounds__(NT) void k_tab_assemble(DevPlan d, int case0, int p
   if (sg == 3) { nk = 2; kap[0] = 1; kap[1] = -1; nslot[0] = nslot[1] = 1; slot_t[0][0] = 2; slot_b[0][0] = 0; coef[0][0] = 0.5; slot_t[1][0] = 2; slot_b[1][0] = 1; coef[1][0] = 0.5; }
   if (sg == 4) { nk = 1; kap[0] = 0; nslot[0] = 1; slot_t[0][0] = 2; slot_b[0][0] = 2; coef[0][0] = 1.0; }
   const cd* Ib = d.ibuf + tc.ibuf;
-  cd* Mbase = d.mats + tc.mat;
+  cd* Mbase = out + (long long)ci * stride;
   const double fourpi = 12.566370614359172954;
   for (int tt = 0; tt < 4; tt++)
     for (int ts = 0; ts < 4; ts++) {
@@ -2381,16 +2522,59 @@ __global__ __launch_bounds__(NT) void k_tab_assemble(DevPlan d, int case0, int p
           cd V = (fourpi * sgn_s) * (ipow(1 + n + aq) * ipow(-nu) * ih);  // i^{1+n+|q|} (-i)^nu
           for (int sl = 0; sl < nslot[kk]; sl++) {
             int t = slot_t[kk][sl], blk = slot_b[kk][sl];
-            Mbase[(long long)t * 3 * P * P + (long long)a * 3 * P + (long long)blk * P + bb] = coef[kk][sl] * V;
+            if (t == 1) continue;  // the - rows: mirror images of the + rows
+            Mbase[(long long)(t >> 1) * 3 * P * P + (long long)a * 3 * P + (long long)blk * P + bb] = coef[kk][sl] * V;
           }
         }
       }
     }
 }
-void launch_tab_assemble(const DevPlan& d, int case0, int ncase, int p, int KB, int BS, hipStream_t s) {
+void launch_tab_assemble(const DevPlan& d, int case0, int ncase, int p, int KB, int BS, cd* out, long long stride,
+                         hipStream_t s) {
   if (ncase <= 0) return;
   int NQ = 2 * p + 3;
   size_t shm = (size_t)(KB + 1) * (KB + 1) * NQ * sizeof(cd);
   set_dyn_lds((const void*)k_tab_assemble, shm);
-  hipLaunchKernelGGL(k_tab_assemble, dim3(ncase, 5), dim3(NT), shm, s, d, case0, p, KB, BS);
+  hipLaunchKernelGGL(k_tab_assemble, dim3(ncase, 5), dim3(NT), shm, s, d, case0, p, KB, BS, out, stride);
+}
+
+// Even (par 0) and odd (par 1) blocks of each case's reaction M2L tensor
+// from the + and z output rows written by k_tab_assemble (src[ci]): with
+// e_m = (-1)^m, sign s = +1 (even) or -1 (odd), and the input blocks
+// (u+, u-) in the order of the row's output type,
+//   column (+, nu mu):  (A[row][u+][nu mu] + s e_mu A[row][u-][nu, -mu]) / 2
+//   column (z, nu mu):  (A[row][z][nu mu] + s e_mu A[row][z][nu, -mu]) / 2,
+//                       A[row][z][nu 0] for mu = 0 (even only),
+// over the rows (+, nm) (every nm) and (z, nm) (m >= 0 even, m >= 1 odd),
+// stored row-major [lm_sym_dim(p, par)]^2, the even block first.
+__global__ __launch_bounds__(NT) void k_tab_sym(DevPlan d, int case0, const cd* src, long long stride) {
+  const int ci = blockIdx.x, par = blockIdx.z;
+  const TabCase tc = d.cases[case0 + ci];
+  const int p = d.inst[tc.inst].p, P = (p + 1) * (p + 1), R = lm_sym_dim(p, par);
+  const cd* A = src + (long long)ci * stride;
+  cd* M = d.mats + tc.mat + (par ? (long long)lm_sym_dim(p, 0) * lm_sym_dim(p, 0) : 0);
+  const double sg = par ? -1.0 : 1.0;
+  const long long n_el = (long long)R * R;
+  for (long long e = (long long)blockIdx.y * NT + threadIdx.x; e < n_el; e += (long long)gridDim.y * NT) {
+    const int r = (int)(e / R), c = (int)(e - (long long)r * R);
+    const bool zrow = r >= P;
+    const int a = zrow ? sym_znm(r - P, par) : r;
+    const cd* Ar = A + (zrow ? 3LL * P * P : 0) + (long long)a * 3 * P;
+    cd v;
+    if (c < P) {
+      const int nu = n_of(c), mu = c - nu * nu - nu;
+      const int bp = zrow ? 1 : 0, bm = zrow ? 0 : 1;  // blocks of u+ and u- in this row's output type
+      const double f = sg * ((mu & 1) ? -1.0 : 1.0);
+      v = 0.5 * (Ar[(long long)bp * P + c] + f * Ar[(long long)bm * P + c - 2 * mu]);
+    } else {
+      const int b = sym_znm(c - P, par), nu = n_of(b), mu = b - nu * nu - nu;
+      const double f = sg * ((mu & 1) ? -1.0 : 1.0);
+      v = mu == 0 ? Ar[2LL * P + b] : 0.5 * (Ar[2LL * P + b] + f * Ar[2LL * P + b - 2 * mu]);
+    }
+    M[e] = v;
+  }
+}
+void launch_tab_sym(const DevPlan& d, int case0, int ncase, const cd* src, long long stride, hipStream_t s) {
+  if (ncase <= 0) return;
+  hipLaunchKernelGGL(k_tab_sym, dim3(ncase, 16, 2), dim3(NT), 0, s, d, case0, src, stride);
 }

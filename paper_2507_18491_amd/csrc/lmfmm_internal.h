@@ -18,6 +18,16 @@
 #define LM_S2T_DIGITS 28.0 // the S2T tail stops where e^{-k (t + u)} < e^{-28}
 #define LM_S2T_SEG 32      // near boxes per source segment of one S2T work item
 
+// Reaction M2L in the mirror-adapted basis: the reaction M2L tensor
+// commutes with the mirror that swaps the +/- channels and takes m to -m
+// (with the sign (-1)^m), so it acts on the even and the odd part of a
+// vector separately.  Dimension of the even (par 0) or odd (par 1) part at
+// order q: the (q+1)^2 entries of the + channel, then the z-channel entries
+// with m >= 0 (even) or m >= 1 (odd), both n-major.
+__host__ __device__ inline int lm_sym_dim(int q, int par) {
+  return (q + 1) * (q + 1) + (par == 0 ? (q + 1) * (q + 2) / 2 : q * (q + 1) / 2);
+}
+
 // One FMM instance: the free-space part of one layer, or one reaction
 // component (target layer lt, source layer ls, arrival direction at the
 // target, departure direction at the source).

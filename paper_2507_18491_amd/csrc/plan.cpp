@@ -1107,17 +1107,19 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
             tc.zs_orig = ip.as * (zs_img - ip.bs);
             tc.node0 = l;  // temporarily the level
             tc.nnode = 0;
+            // the even and the odd block of the mirror-adapted M2L tensor
             tc.mat = pl.mat_size;
-            pl.mat_size += 9LL * P * P;
+            pl.mat_size += (long long)lm_sym_dim(ip.p, 0) * lm_sym_dim(ip.p, 0) +
+                           (long long)lm_sym_dim(ip.p, 1) * lm_sym_dim(ip.p, 1);
             pl.cases.push_back(tc);
           } else
             cid = it->second;
           long long base = pl.cases[cid].mat;
           double R = sqrt((double)(dx * dx + dy * dy) * Sl * Sl + (zt_img - zs_img) * (zt_img - zs_img));
           off_ratio.push_back(sqrt(3.0) * Sl / R);
-          mo.mat[0] = base;
-          mo.mat[1] = base + 3LL * P * P;
-          mo.mat[2] = base + 6LL * P * P;
+          mo.mat[0] = base;                                                  // even block
+          mo.mat[1] = base + (long long)lm_sym_dim(ip.p, 0) * lm_sym_dim(ip.p, 0);  // odd block
+          mo.mat[2] = base;                                                  // (unused)
           mo.phi = atan2(-(double)dy, -(double)dx);
         }
         mo.pord = ip.p;
@@ -1179,6 +1181,7 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
             pl.pair_src.push_back(sb);
             int po = pl.offs[C.off0 + o].pord;
             pl.pair_P.push_back((po + 1) * (po + 1));
+            pl.pair_phi.push_back(pl.offs[C.off0 + o].phi);
           }
         }
         pl.offr.push_back((int)pl.pair_src.size());

@@ -74,6 +74,7 @@ struct Plan {
   std::vector<int> offr;                      // per block: n_off+1 pair-range starts
   std::vector<int> bt_blk;                    // per block-target: its block
   std::vector<int> pair_P;                    // per pair: (pord+1)^2 of its offset
+  std::vector<double> pair_phi;               // per pair: azimuth of its offset (reaction phases)
   std::vector<int> s2t_items;                 // reaction near field: (target leaf, chunk) pairs
   // tables
   std::vector<TransJob> trans;
