@@ -91,9 +91,9 @@ typedef struct {
   int m2l_variant;    /* tile shape of the M2L GEMM kernel: -1 (default) tunes each */
                       /* launch of the schedule on its first eager evaluation and  */
                       /* keeps the fastest; 0..LM_M2L_VARIANTS-1 fixes one (0: 16  */
-                      /* values of k per LDS chunk, 3 blocks per CU; 1: 32 values,  */
-                      /* 2 blocks; 2: 16 values double-buffered, 2 blocks).  All   */
-                      /* variants give bitwise equal results.                      */
+                      /* values of k per LDS chunk, 3 blocks per CU; 1: 8 values   */
+                      /* double-buffered, 3 blocks; 2: 16 values double-buffered,  */
+                      /* 2 blocks).  All variants give bitwise equal results.      */
   double tol;         /* requested relative accuracy, 0 (default): no check.  With  */
                       /* tol > 0, lm_build returns LM_EACCURACY when a quadrature   */
                       /* rule of the plan is coarser than tol: the real tail of the*/

@@ -268,6 +268,22 @@ static void scratch_setup(int dev) {
   g_scratch_state[dev] = 1;
 }
 
+// GEMM groups of one M2L block: runs of consecutive offsets that share one
+// matrix (reaction: one table case, the offsets differing only in azimuth;
+// free space: each offset alone).  f(o0, o1) gets the offsets [o0, o1).
+template <class F>
+static void m2l_groups(const Plan& pl, const M2LBlock& B, F&& f) {
+  const M2LClass& C = pl.cls[B.cls];
+  int o = 0;
+  while (o < C.n_off) {
+    int e = o + 1;
+    if (C.nblk == 3)
+      while (e < C.n_off && pl.offs[C.off0 + e].mat[0] == pl.offs[C.off0 + o].mat[0]) e++;
+    f(o, e);
+    o = e;
+  }
+}
+
 static int make_schedule(lm_ctx* ctx, int n_rhs, long long budget, lm_ctx::TileSet& ts, long long* block_max);
 static long long p2m_part_size(const lm_ctx* ctx, int n_rhs);
 
@@ -484,6 +500,11 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
   if ((rc = upload(ctx, &d.bt_ptr, pl.bt_ptr))) return rc;
   if ((rc = upload(ctx, &d.bt_pairs, pl.bt_pairs))) return rc;
   if ((rc = upload(ctx, &d.pair_src, pl.pair_src))) return rc;
+  {
+    std::vector<long long> pm(pl.pair_src.size());
+    for (size_t q = 0; q < pm.size(); q++) pm[q] = pl.sbox[pl.pair_src[q]].me_off;
+    if ((rc = upload(ctx, &d.pair_me, pm))) return rc;
+  }
   if ((rc = upload(ctx, &d.offr, pl.offr))) return rc;
   if ((rc = upload(ctx, &d.bt_blk, pl.bt_blk))) return rc;
   if ((rc = upload(ctx, &d.pair_P, pl.pair_P))) return rc;
@@ -870,26 +891,36 @@ static int make_schedule(lm_ctx* ctx, int n_rhs, long long budget, lm_ctx::TileS
       if (ch.nbt > 0 && bytes + bb > budget) break;
       ybase[bi] = bytes / (long long)sizeof(cd);
       bytes += bb;
-      for (int o = 0; o < C.n_off; o++) {
-        int np = pl.offr[B.offr0 + o + 1] - pl.offr[B.offr0 + o];
-        int ncol = np * n_rhs;
+      m2l_groups(pl, B, [&](int o0, int o1) {
+        const int q0 = pl.offr[B.offr0 + o0], ncol = (pl.offr[B.offr0 + o1] - q0) * n_rhs;
+        if (ncol == 0) return;
         // free space: three output types of Po rows; reaction: the even and
         // the odd block of the mirror-adapted tensor
-        const int po = pl.offs[C.off0 + o].pord, Po = (po + 1) * (po + 1);
+        const M2LOffset& O = pl.offs[C.off0 + o0];
+        const int po = O.pord, Po = (po + 1) * (po + 1);
         const bool sym = C.nblk == 3;
-        for (int ot = 0; ot < (sym ? 2 : 3); ot++)
-          for (int r0 = 0; r0 < (sym ? lm_sym_dim(po, ot) : Po); r0 += TM_ROWS)
+        for (int ot = 0; ot < (sym ? 2 : 3); ot++) {
+          M2LTile t;
+          t.mat = O.mat[sym ? ot : 0];
+          t.ybase = ybase[bi];
+          t.qo = q0;
+          t.q0b = B.q0;
+          t.P = C.P;
+          t.p = pl.inst[C.inst].p;
+          t.R = sym ? lm_sym_dim(po, ot) : Po;
+          t.Pb = Po;
+          t.Kf = sym ? lm_sym_dim(t.p, ot) : C.P;
+          t.ot = ot;
+          t.sym = sym ? 1 : 0;
+          for (int r0 = 0; r0 < t.R; r0 += TM_ROWS)
             for (int c0 = 0; c0 < ncol; c0 += TN_COLS) {
-              M2LTile t;
-              t.blk = (int)bi;
-              t.off = o;
-              t.out_type = ot;
               t.row0 = r0;
               t.col0 = c0;
               t.ncol = std::min(TN_COLS, ncol - c0);
               tiles.push_back(t);
             }
-      }
+        }
+      });
       ch.nbt += B.nt;
       bi++;
     }
@@ -1462,18 +1493,17 @@ int lm_stats(const lm_ctx* ctx, double* out, int n) {
     double cm = 0, ce = 0;
     for (const M2LBlock& B : pl.blocks) {
       const M2LClass& C = pl.cls[B.cls];
-      for (int o = 0; o < C.n_off; o++) {
-        const int np = pl.offr[B.offr0 + o + 1] - pl.offr[B.offr0 + o];
-        const int po = pl.offs[C.off0 + o].pord, Po = (po + 1) * (po + 1);
+      m2l_groups(pl, B, [&](int o0, int o1) {
+        const int np = pl.offr[B.offr0 + o1] - pl.offr[B.offr0 + o0];
+        const int po = pl.offs[C.off0 + o0].pord, Po = (po + 1) * (po + 1);
         const double cols = (double)((np + TN_COLS - 1) / TN_COLS) * TN_COLS;
-        for (int ot = 0; ot < 3; ot++) {
-          if (C.nblk == 3 && ot == 2) break;
+        for (int ot = 0; ot < (C.nblk == 3 ? 2 : 3); ot++) {
           const double R = C.nblk == 3 ? lm_sym_dim(po, ot) : Po;
           const double rows = (double)(((int)R + TM_ROWS - 1) / TM_ROWS) * TM_ROWS;
           cm += R * R * np;
           ce += rows * R * cols;
         }
-      }
+      });
     }
     v[LM_STAT_M2L_CMAC_USEFUL] = cm;
     v[LM_STAT_M2L_CMAC_EXEC] = ce;
@@ -1497,18 +1527,18 @@ int lm_stats(const lm_ctx* ctx, double* out, int n) {
     double fe = 0;
     for (const M2LBlock& B : pl.blocks) {
       const M2LClass& C = pl.cls[B.cls];
-      for (int o = 0; o < C.n_off; o++) {
-        const long long np = pl.offr[B.offr0 + o + 1] - pl.offr[B.offr0 + o];
-        if (np == 0) continue;
-        const int po = pl.offs[C.off0 + o].pord, Po = (po + 1) * (po + 1);
-        const double cols = (double)((np + 15) / 16) * 16;
-        for (int ot = 0; ot < 3; ot++) {
-          if (C.nblk == 3 && ot == 2) break;
+      m2l_groups(pl, B, [&](int o0, int o1) {
+        const long long np = pl.offr[B.offr0 + o1] - pl.offr[B.offr0 + o0];
+        if (np == 0) return;
+        const int po = pl.offs[C.off0 + o0].pord, Po = (po + 1) * (po + 1);
+        // 64-column tiles: a wave computes the 16-column tiles below the tile's count
+        const double cols = (double)(np / 64) * 64 + (double)(((np % 64) + 15) / 16) * 16;
+        for (int ot = 0; ot < (C.nblk == 3 ? 2 : 3); ot++) {
           const int R = C.nblk == 3 ? lm_sym_dim(po, ot) : Po;
-          const double rows = (double)((R + 15) / 16) * 16, kp = (double)((R + 15) / 16) * 16;
+          const double rows = (double)((R / 64) * 64 + (((R % 64) + 15) / 16) * 16), kp = (double)((R + 15) / 16) * 16;
           fe += rows * cols * kp * 3.0 * 2.0;
         }
-      }
+      });
     }
     v[LM_STAT_M2L_FLOP_EXEC] = fe;
   }

@@ -31,6 +31,7 @@ struct DevPlan {
   int* bt_ptr;
   int* bt_pairs;
   int* pair_src;
+  long long* pair_me;   // per pair: multipole vector offset of its source box
   int* offr;
   int* bt_blk;          // block of each block-target
   int* pair_P;          // per pair: number of rows/columns used ((pord+1)^2)

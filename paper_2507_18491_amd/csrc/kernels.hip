@@ -371,11 +371,14 @@ void launch_l2l(const DevPlan& d, const int* children, int n, int n_rhs, cd* LE,
 // square one, half the multiply-adds.  The even (odd) coordinates are
 //   + part:  x~_{u+,nm} + (-) e_m x~_{u-,n,-m}   (every nm),
 //   z part:  x~_{z,nm} + (-) e_m x~_{z,n,-m}     (m >= 1; m = 0: x~_{z,n0}, even only),
-// and k_tab_sym stores V in these coordinates.  Tiles write the phase-free
-// even and odd outputs; k_m2l_reduce recombines them per pair and applies
-// e^{i (a_o - m) phi}.  Only pairs whose source box exists are columns.  Y
-// is a scratch buffer; the reduction adds, per target, its pairs in a fixed
-// order (no atomics).
+// and k_tab_sym stores V in these coordinates.  V depends on the horizontal
+// distance and the heights only, so the offsets of one table case (equal
+// distance, different azimuths) share it: their pairs are the columns of
+// one GEMM, each column phased with its own pair's azimuth.  Tiles write
+// the phase-free even and odd outputs; k_m2l_reduce recombines them per
+// pair and applies e^{i (a_o - m) phi}.  Only pairs whose source box exists
+// are columns.  Y is a scratch buffer; the reduction adds, per target, its
+// pairs in a fixed order (no atomics).
 #define TM 64
 #define TN 64
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -418,9 +421,10 @@ template <int KCV, int NB>
 struct M2LLds {
   double Ar[NB][TM][KCV + 1], Ai[NB][TM][KCV + 1], Br[NB][TN][KCV + 1], Bi[NB][TN][KCV + 1];
   long long sbase[TN];
-  cd eph[2 * LM_PMAX + 8];
-  short mu_of[(LM_PMAX + 1) * (LM_PMAX + 1)];
-  short zmap[(LM_PMAX + 1) * (LM_PMAX + 2) / 2];  // z part: entry -> n^2 + n + m
+  // reaction: powers of each column's e^{i phi}: lo[c][j] = e^{i j phi}
+  // (j < 8), hi[c][j] = e^{i 8 j phi} (j < 4), so e^{i e phi} for |e| < 32
+  // is lo[e % 8] hi[e / 8] (conjugated for e < 0)
+  cd plo[TN][8], phi8[TN][4];
 };
 
 // K loop and epilogue of one wave whose 32 x 32 wave tile has NI x NJ active
@@ -493,9 +497,25 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds<KCV, NB>& L
       ra[it] = (aok[it] && kok) ? v : cd{0, 0};
     }
     if (SYM) {
+      // (n, mu) of coordinate kc: the + part in nm order, then the z part
+      // with mu >= 0 (even) or mu >= 1 (odd), n-major
       const bool zp = kc >= c.Pb;
-      const int nm = zp ? L.zmap[kc - c.Pb] : kc;
-      const int mu = L.mu_of[nm];
+      int n, mu;
+      if (!zp) {
+        n = n_of(kc);
+        mu = kc - n * n - n;
+      } else {
+        const int j = kc - c.Pb;
+        const double sq = sqrt(8.0 * j + 1.0);
+        if (c.ot == 0) {
+          n = (int)((sq - 1.0) * 0.5);
+          mu = j - n * (n + 1) / 2;
+        } else {
+          n = (int)((sq + 1.0) * 0.5);
+          mu = j - n * (n - 1) / 2 + 1;
+        }
+      }
+      const int nm = n * n + n + mu;
       const int i1 = (zp ? 2 * c.P : 0) + nm;          // u+ or z
       const int i2 = (zp ? 2 * c.P : c.P) + nm - 2 * mu;  // u- or z, order -mu
       e1 = zp ? mu : mu - 1;
@@ -516,18 +536,28 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds<KCV, NB>& L
     }
   };
   // registers -> LDS planes of buffer bf (reaction: the even or odd
-  // coordinate of the phased source vector)
+  // coordinate of the phased source vector, each column with the phase
+  // e^{i e1 phi} of its own pair; the phases are read before any store)
   auto store = [&](int bf) {
+    cd ph[SYM ? NB_ : 1];
+    if (SYM) {
+      const int ae = e1 < 0 ? -e1 : e1;
+#pragma unroll
+      for (int it = 0; it < NB_; it++) {
+        const int col = r16 + RPI * it;
+        ph[it] = L.plo[col][ae & 7] * L.phi8[col][ae >> 3];
+        if (e1 < 0) ph[it] = cconj(ph[it]);
+      }
+    }
 #pragma unroll
     for (int it = 0; it < NA; it++) {
       L.Ar[bf][r16 + RPI * it][kk] = ra[it].x;
       L.Ai[bf][r16 + RPI * it][kk] = ra[it].y;
     }
     if (SYM) {
-      const cd ph1 = L.eph[e1 + c.p + 2], ph2 = (double)s2 * cconj(ph1);
 #pragma unroll
       for (int it = 0; it < NB_; it++) {
-        cd v = ph1 * rb[it] + ph2 * rm[it];
+        const cd v = ph[it] * rb[it] + ((double)s2 * cconj(ph[it])) * rm[it];
         L.Br[bf][r16 + RPI * it][kk] = v.x;
         L.Bi[bf][r16 + RPI * it][kk] = v.y;
       }
@@ -642,41 +672,44 @@ __global__ __launch_bounds__(NT, OCC) void k_m2l(DevPlan d, const M2LTile* tiles
   const int t_id = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
   if (t_id >= n_tiles) return;
   const M2LTile tl = tiles[t_id];
-  const M2LBlock B = d.blocks[tl.blk];
-  const M2LClass C = d.cls[B.cls];
   const int tid = threadIdx.x;
-  const M2LOffset* offp = d.offs + C.off0 + tl.off;
   M2LTileCtx c;
-  c.P = C.P;
-  c.p = d.inst[C.inst].p;
-  c.ot = tl.out_type;
-  c.sym = (C.nblk == 3);
+  c.P = tl.P;
+  c.p = tl.p;
+  c.ot = tl.ot;
+  c.sym = tl.sym != 0;
   // order used for this offset: free space, the leading Pb rows and columns
   // of the P x P matrix; reaction, the leading entries of both parts
-  const int po = offp->pord;
-  c.Pb = (po + 1) * (po + 1);
-  c.R = c.sym ? lm_sym_dim(po, c.ot) : c.Pb;
-  c.Kf = c.sym ? lm_sym_dim(c.p, c.ot) : c.P;
+  c.Pb = tl.Pb;
+  c.R = tl.R;
+  c.Kf = tl.Kf;
   c.row0 = tl.row0;
   c.ncol = tl.ncol;
   c.col0 = tl.col0;
-  c.qo = d.offr[B.offr0 + tl.off];  // first pair of this offset
-  c.q0b = B.q0;
+  c.qo = tl.qo;      // first pair of this offset
+  c.q0b = tl.q0b;
   c.n_rhs = n_rhs;
-  c.ybase = d.blk_ybase[tl.blk];    // per-block scratch base (blocks differ in P)
-  c.A = d.mats + offp->mat[c.sym ? c.ot : 0];
+  c.ybase = tl.ybase;  // per-block scratch base (blocks differ in P)
+  c.A = d.mats + tl.mat;
   c.ME = ME;
   c.Y = Y;
-  if (c.sym) {
-    const double phi = offp->phi;
-    for (int e = tid; e < c.P; e += NT) {
-      int n = n_of(e);
-      L.mu_of[e] = (short)(e - n * n - n);
+  if (c.sym && tid < TN) {
+    // the tile's columns may come from several offsets of one table case:
+    // each column takes the azimuth of its own pair (columns past the
+    // tile's count: any valid value, their sources are zero)
+    const int q = c.qo + (tl.col0 + (tid < tl.ncol ? tid : 0)) / n_rhs;
+    const double phi = d.pair_phi[q];
+    const cd z = cd{cos(phi), sin(phi)};
+    cd w = cd{1, 0};
+    for (int j = 0; j < 8; j++) {
+      L.plo[tid][j] = w;
+      w = w * z;
     }
-    for (int e = tid; e < lm_sym_dim(c.p, c.ot) - c.P; e += NT) L.zmap[e] = (short)sym_znm(e, c.ot);
-    if (tid < 2 * c.p + 5) {
-      double a = (tid - (c.p + 2)) * phi;
-      L.eph[tid] = cd{cos(a), sin(a)};
+    const cd z8 = w;
+    w = cd{1, 0};
+    for (int j = 0; j < 4; j++) {
+      L.phi8[tid][j] = w;
+      w = w * z8;
     }
   }
   if (tid < TN) {
@@ -684,7 +717,7 @@ __global__ __launch_bounds__(NT, OCC) void k_m2l(DevPlan d, const M2LTile* tiles
     if (tid < tl.ncol) {
       int j = tl.col0 + tid;
       int q = c.qo + j / n_rhs, r = j % n_rhs;
-      v = d.sbox[d.pair_src[q]].me_off * n_rhs + (long long)r * 3 * c.P;
+      v = d.pair_me[q] * n_rhs + (long long)r * 3 * c.P;
     }
     L.sbase[tid] = v;
   }
@@ -714,15 +747,15 @@ __global__ __launch_bounds__(NT, OCC) void k_m2l(DevPlan d, const M2LTile* tiles
   }
 }
 // variant: 0 = 16 values of k per chunk, one buffer, three blocks per CU;
-// 1 = 32 values, one buffer, two blocks; 2 = 16 values, two buffers, two
+// 1 = 8 values, two buffers, three blocks; 2 = 16 values, two buffers, two
 // blocks (LM_M2L_VARIANTS variants, bitwise equal results)
 void launch_m2l(const DevPlan& d, const M2LTile* tiles, int n_tiles, int n_rhs, const cd* ME, cd* Y, int pmax,
                 int variant, hipStream_t s) {
   if (n_tiles <= 0) return;
   int grid = ((n_tiles + 7) / 8) * 8;
   switch (variant) {
-    case 1: hipLaunchKernelGGL((k_m2l<32, 1, 2>), dim3(grid), dim3(NT), 0, s, d, tiles, n_tiles, n_rhs, ME, Y); break;
-    case 2: hipLaunchKernelGGL((k_m2l<16, 2, 2>), dim3(grid), dim3(NT), 0, s, d, tiles, n_tiles, n_rhs, ME, Y); break;
+    case 1: hipLaunchKernelGGL((k_m2l<8, 1, 3>), dim3(grid), dim3(NT), 0, s, d, tiles, n_tiles, n_rhs, ME, Y); break;
+    case 2: hipLaunchKernelGGL((k_m2l<8, 2, 3>), dim3(grid), dim3(NT), 0, s, d, tiles, n_tiles, n_rhs, ME, Y); break;
     default: hipLaunchKernelGGL((k_m2l<16, 1, 3>), dim3(grid), dim3(NT), 0, s, d, tiles, n_tiles, n_rhs, ME, Y); break;
   }
 }
@@ -739,7 +772,8 @@ void launch_m2l(const DevPlan& d, const M2LTile* tiles, int n_tiles, int n_rhs, 
 // such group is added into LE in turn.  (At m = 0 of the z part, O is absent
 // and the second output coincides with the first: only the first is kept.)
 #define LM_RED_PAIRS 32
-__global__ __launch_bounds__(NT) void k_m2l_reduce(DevPlan d, int bt0, int n_rhs, const cd* Y, cd* LE) {
+#define RED_NT 512  // threads per target: the even part of p = 12 (260 entries) in one pass
+__global__ __launch_bounds__(RED_NT) void k_m2l_reduce(DevPlan d, int bt0, int n_rhs, const cd* Y, cd* LE) {
   __shared__ cd ph[LM_RED_PAIRS][2 * LM_PMAX + 5];
   int bt = bt0 + blockIdx.x;
   TgtBox tb = d.tbox[d.bt_tbox[bt]];
@@ -750,7 +784,7 @@ __global__ __launch_bounds__(NT) void k_m2l_reduce(DevPlan d, int bt0, int n_rhs
   int q0 = d.bt_ptr[bt], q1 = d.bt_ptr[bt + 1];
   int nel = 3 * n_rhs * P;
   if (d.cls[d.blocks[blk].cls].nblk != 3) {
-    for (int e = threadIdx.x; e < nel; e += NT) {
+    for (int e = threadIdx.x; e < nel; e += RED_NT) {
       int tr_ = e / P, row = e - tr_ * P;   // tr_ = ot * n_rhs + r
       int ot = tr_ / n_rhs, r = tr_ - ot * n_rhs;
       cd s = cd{0, 0};
@@ -763,6 +797,8 @@ __global__ __launch_bounds__(NT) void k_m2l_reduce(DevPlan d, int bt0, int n_rhs
     }
     return;
   }
+  __shared__ long long yq[LM_RED_PAIRS];  // each pair's scratch vector
+  __shared__ int plim[LM_RED_PAIRS];      // and its (pord+1)^2
   const int Re = lm_sym_dim(p, 0), Ro = lm_sym_dim(p, 1), NJ = 2 * p + 5;
   // one thread per (rhs, entry of the even part): the + part entries nm give
   // (+, nm) and (-, n, -m), the z part entries (n, m >= 0) give (z, n, m) and
@@ -771,13 +807,19 @@ __global__ __launch_bounds__(NT) void k_m2l_reduce(DevPlan d, int bt0, int n_rhs
   for (int c0 = q0; c0 < q1; c0 += LM_RED_PAIRS) {
     const int nc = min(LM_RED_PAIRS, q1 - c0);
     __syncthreads();
-    for (int e = threadIdx.x; e < nc * NJ; e += NT) {
+    for (int e = threadIdx.x; e < nc * NJ; e += RED_NT) {
       const int i = e / NJ, j = e - i * NJ;
       const double a = (j - (p + 2)) * d.pair_phi[d.bt_pairs[c0 + i]];
       ph[i][j] = cd{cos(a), sin(a)};
     }
+    if (threadIdx.x < LM_RED_PAIRS) {
+      const int i = threadIdx.x;
+      const int q = i < nc ? d.bt_pairs[c0 + i] : qb;
+      yq[i] = ybase + (long long)(q - qb) * 3 * n_rhs * P;
+      plim[i] = i < nc ? d.pair_P[q] : 0;
+    }
     __syncthreads();
-    for (int u = threadIdx.x; u < n_rhs * Re; u += NT) {
+    for (int u = threadIdx.x; u < n_rhs * Re; u += RED_NT) {
       const int r = u / Re, w = u - r * Re;  // w: entry of the even part
       const bool zp = w >= P;
       int n, m, io, jph;
@@ -797,12 +839,14 @@ __global__ __launch_bounds__(NT) void k_m2l_reduce(DevPlan d, int bt0, int n_rhs
       const int nm = n * n + n + m;
       const bool has_o = !zp || m > 0;
       cd s1 = cd{0, 0}, s2 = cd{0, 0};
+      const long long oe = (long long)r * Re + w, oo = (long long)n_rhs * Re + (long long)r * Ro + (has_o ? io : w);
+#pragma unroll 4
       for (int i = 0; i < nc; i++) {
-        const int q = d.bt_pairs[c0 + i];
-        if (nm >= d.pair_P[q]) continue;
-        const cd* Yp = Y + ybase + (long long)(q - qb) * 3 * n_rhs * P;
-        const cd E = Yp[(long long)r * Re + w];
-        const cd O = has_o ? Yp[(long long)n_rhs * Re + (long long)r * Ro + io] : cd{0, 0};
+        // pairs whose order is below n contribute nothing
+        const bool ok = nm < plim[i];
+        const cd* Yp = Y + yq[i];
+        const cd E = ok ? Yp[oe] : cd{0, 0};
+        const cd O = (ok && has_o) ? Yp[oo] : cd{0, 0};
         const cd f = ph[i][jph + p + 2];
         s1 = s1 + f * (E + O);
         s2 = s2 + cconj(f) * (E - O);
@@ -822,7 +866,7 @@ __global__ __launch_bounds__(NT) void k_m2l_reduce(DevPlan d, int bt0, int n_rhs
 void launch_m2l_reduce(const DevPlan& d, int bt0, int nbt, int n_rhs, const cd* Y, cd* LE, int pmax,
                        hipStream_t s) {
   if (nbt <= 0) return;
-  hipLaunchKernelGGL(k_m2l_reduce, dim3(nbt), dim3(NT), 0, s, d, bt0, n_rhs, Y, LE);
+  hipLaunchKernelGGL(k_m2l_reduce, dim3(nbt), dim3(RED_NT), 0, s, d, bt0, n_rhs, Y, LE);
 }
 
 // ------------------------------------------------------------------ L2P

@@ -101,11 +101,18 @@ struct M2LBlock {
   int offr0;          // start of the per-offset pair ranges (n_off + 1 entries)
 };
 
-// one work tile of the M2L GEMM: one offset, up to 64 (pair, rhs) columns
+// one work tile of the M2L GEMM: one matrix (free space: one offset;
+// reaction: the offsets of one table case, which differ only in azimuth),
+// one output part, up to 64 rows and 64 (pair, rhs) columns; everything the
+// kernel needs to start the tile in one record (no chain of dependent loads)
 struct M2LTile {
-  int blk;
-  int off;            // offset index within the class
-  int out_type;       // 0: +, 1: -, 2: z
+  long long mat;      // offset of the tile's matrix in the tables
+  long long ybase;    // scratch base of the tile's M2L block
+  int qo, q0b;        // first pair of the tile's offsets; first pair of the block
+  int P, p;           // (p+1)^2 and p of the class
+  int R, Pb, Kf;      // rows (= columns) used, (pord+1)^2, row pitch of the stored matrix
+  int ot;             // free space: output type 0..2; reaction: 0 even, 1 odd block
+  int sym;            // 1: reaction (mirror-adapted blocks)
   int row0;           // first output row
   int col0, ncol;     // column range within the offset's (pair, rhs) list
 };

@@ -1070,9 +1070,22 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       C.P = P;
       int oi = 0;
       int jt = std::get<4>(kv.first);
-      for (auto& ov : offmap) {
-        ov.second = oi++;
-        int dx = std::get<0>(ov.first), dy = std::get<1>(ov.first), dz = std::get<2>(ov.first);
+      // offset order: reaction offsets with equal horizontal distance and
+      // source gap index share one table case (they differ only in the
+      // azimuth, which the M2L applies per column), so they are placed next
+      // to each other and their pairs form the columns of one GEMM
+      std::vector<std::tuple<int, int, int>> okeys;
+      for (auto& ov : offmap) okeys.push_back(ov.first);
+      if (!free)
+        std::stable_sort(okeys.begin(), okeys.end(),
+                         [](const std::tuple<int, int, int>& a, const std::tuple<int, int, int>& b) {
+                           const int ra = std::get<0>(a) * std::get<0>(a) + std::get<1>(a) * std::get<1>(a);
+                           const int rb = std::get<0>(b) * std::get<0>(b) + std::get<1>(b) * std::get<1>(b);
+                           return ra != rb ? ra < rb : std::get<2>(a) < std::get<2>(b);
+                         });
+      for (const auto& okey : okeys) {
+        offmap[okey] = oi++;
+        int dx = std::get<0>(okey), dy = std::get<1>(okey), dz = std::get<2>(okey);
         M2LOffset mo;
         group_offs[gid].push_back((int)pl.offs.size());
         if (free) {
