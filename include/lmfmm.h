@@ -90,10 +90,10 @@ typedef struct {
                       /* component's Sommerfeld integral (S2T, Sec. 3.3/3.4).     */
   int m2l_variant;    /* tile shape of the M2L GEMM kernel: -1 (default) tunes each */
                       /* launch of the schedule on its first eager evaluation and  */
-                      /* keeps the fastest; 0..LM_M2L_VARIANTS-1 fixes one (0: 16  */
-                      /* values of k per LDS chunk, 3 blocks per CU; 1: 8 values   */
-                      /* double-buffered, 3 blocks; 2: 16 values double-buffered,  */
-                      /* 2 blocks).  All variants give bitwise equal results.      */
+                      /* keeps the fastest; 0..LM_M2L_VARIANTS-1 fixes one (64-row  */
+                      /* tiles; 0: 8 values of k per LDS chunk; 1: 4 values,       */
+                      /* double-buffered; 2: 8 values, double-buffered).  All      */
+                      /* variants give bitwise equal results.                      */
   double tol;         /* requested relative accuracy, 0 (default): no check.  With  */
                       /* tol > 0, lm_build returns LM_EACCURACY when a quadrature   */
                       /* rule of the plan is coarser than tol: the real tail of the*/

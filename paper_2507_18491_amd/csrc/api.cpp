@@ -15,7 +15,7 @@
 #include "kernels.h"
 #include "plan.h"
 
-#define TM_ROWS 64
+#define TM_ROWS 64  // rows per M2L GEMM tile (32 per wave row, 2 wave rows)
 #define TN_COLS 64
 
 struct lm_ctx {

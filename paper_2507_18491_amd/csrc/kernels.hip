@@ -379,8 +379,7 @@ void launch_l2l(const DevPlan& d, const int* children, int n, int n_rhs, cd* LE,
 // pair and applies e^{i (a_o - m) phi}.  Only pairs whose source box exists
 // are columns.  Y is a scratch buffer; the reduction adds, per target, its
 // pairs in a fixed order (no atomics).
-#define TM 64
-#define TN 64
+#define TN 64   // columns per tile (the rows are 32 per wave row: 32 * WR)
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // Shared state of one M2L tile (read by all waves of the block).
@@ -396,6 +395,13 @@ struct M2LTileCtx {
   int p, ot, row0, ncol, col0, qo, q0b, n_rhs;
   bool sym;           // reaction: ot 0 = even block, 1 = odd block
 };
+
+// complex product with a fixed fused multiply-add order: every tile-shape
+// variant must round the phases and source coordinates alike, and the
+// compiler's own contraction could differ between instantiations
+__device__ __forceinline__ cd cmul_fx(cd a, cd b) {
+  return cd{__builtin_fma(a.x, b.x, -(a.y * b.y)), __builtin_fma(a.x, b.y, a.y * b.x)};
+}
 
 // stored row / column of the offset's r-th used row / column: the first Pb
 // entries, then the second part from position P on
@@ -417,9 +423,9 @@ __device__ inline int sym_znm(int j, int par) {
 // row's KCV values write consecutive words, and the MFMA operand reads (16
 // lanes on 16 rows, 4 groups of lanes on 4 consecutive k) fall on distinct
 // banks (the pitch is odd in doubles).
-template <int KCV, int NB>
+template <int KCV, int NB, int WR>
 struct M2LLds {
-  double Ar[NB][TM][KCV + 1], Ai[NB][TM][KCV + 1], Br[NB][TN][KCV + 1], Bi[NB][TN][KCV + 1];
+  double Ar[NB][32 * WR][KCV + 1], Ai[NB][32 * WR][KCV + 1], Br[NB][TN][KCV + 1], Bi[NB][TN][KCV + 1];
   long long sbase[TN];
   // reaction: powers of each column's e^{i phi}: lo[c][j] = e^{i j phi}
   // (j < 8), hi[c][j] = e^{i 8 j phi} (j < 4), so e^{i e phi} for |e| < 32
@@ -443,8 +449,8 @@ struct M2LLds {
 // multiplies and waits again; NB = 2 loads the next chunk into registers
 // while the current one is multiplied and stores it into the other buffer
 // (one barrier per chunk).
-template <int KCV, int NB, int NI, int NJ, bool SYM>
-__device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds<KCV, NB>& L, int tid, int wr, int wc) {
+template <int KCV, int NB, int WR, int NI, int NJ, bool SYM>
+__device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds<KCV, NB, WR>& L, int tid, int wr, int wc) {
   constexpr int NIx = NI > 0 ? NI : 1, NJx = NJ > 0 ? NJ : 1;
   v4d p1[NIx][NJx], p2[NIx][NJx], p3[NIx][NJx];
 #pragma unroll
@@ -456,12 +462,15 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds<KCV, NB>& L
       p3[i][j] = p1[i][j];
     }
   const int lane = tid & 63;
-  // rows (matrix) / columns (source vectors) staged per pass of the block
-  constexpr int RPI = NT / KCV;
-  constexpr int NA = TM / RPI, NB_ = TN / RPI;
-  // fixed roles of this thread in the chunk loads: k offset kk, and rows /
-  // columns r16 + RPI it; indices outside the tile are clamped to a valid
-  // entry and the value zeroed
+  // rows (matrix) / columns (source vectors) staged per pass: all 128 WR
+  // threads stage the 32 WR matrix rows (RPI rows per pass), the first 256
+  // the 64 source columns (RPB columns per pass); KCV / 4 of each per thread
+  constexpr int NTB = 128 * WR, RPI = NTB / KCV, RPB = 256 / KCV;
+  constexpr int NA = 32 * WR / RPI, NB_ = TN / RPB;
+  const bool bst = tid < 256;
+  // fixed roles of this thread in the chunk loads: k offset kk, and rows
+  // r16 + RPI it, columns r16 + RPB it; indices outside the tile are
+  // clamped to a valid entry and the value zeroed
   const int kk = tid & (KCV - 1), r16 = tid / KCV;
   int aoff[NA];  // below 2^31: the largest matrix has lm_sym_dim(LM_PMAX, 0)^2 entries
   bool aok[NA];
@@ -481,20 +490,21 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds<KCV, NB>& L
     const bool kok = k < c.R;
     const int kc = kok ? k : c.R - 1;
     const int colA = m2l_sidx(c, kc);
+#pragma unroll
+    for (int it = 0; it < NA; it++) {
+      cd v = c.A[aoff[it] + colA];
+      ra[it] = (aok[it] && kok) ? v : cd{0, 0};
+    }
+    if (!bst) return;
     // source columns: base offsets re-read from LDS (fewer live registers);
     // columns without a pair read column 0 and are zeroed
     long long boff[NB_];
     bool bok[NB_];
 #pragma unroll
     for (int it = 0; it < NB_; it++) {
-      const long long sb = L.sbase[r16 + RPI * it];
+      const long long sb = L.sbase[r16 + RPB * it];
       bok[it] = sb >= 0;
       boff[it] = sb >= 0 ? sb : L.sbase[0];
-    }
-#pragma unroll
-    for (int it = 0; it < NA; it++) {
-      cd v = c.A[aoff[it] + colA];
-      ra[it] = (aok[it] && kok) ? v : cd{0, 0};
     }
     if (SYM) {
       // (n, mu) of coordinate kc: the + part in nm order, then the z part
@@ -540,12 +550,12 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds<KCV, NB>& L
   // e^{i e1 phi} of its own pair; the phases are read before any store)
   auto store = [&](int bf) {
     cd ph[SYM ? NB_ : 1];
-    if (SYM) {
+    if (SYM && bst) {
       const int ae = e1 < 0 ? -e1 : e1;
 #pragma unroll
       for (int it = 0; it < NB_; it++) {
-        const int col = r16 + RPI * it;
-        ph[it] = L.plo[col][ae & 7] * L.phi8[col][ae >> 3];
+        const int col = r16 + RPB * it;
+        ph[it] = cmul_fx(L.plo[col][ae & 7], L.phi8[col][ae >> 3]);
         if (e1 < 0) ph[it] = cconj(ph[it]);
       }
     }
@@ -554,18 +564,20 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds<KCV, NB>& L
       L.Ar[bf][r16 + RPI * it][kk] = ra[it].x;
       L.Ai[bf][r16 + RPI * it][kk] = ra[it].y;
     }
+    if (!bst) return;
     if (SYM) {
 #pragma unroll
       for (int it = 0; it < NB_; it++) {
-        const cd v = ph[it] * rb[it] + ((double)s2 * cconj(ph[it])) * rm[it];
-        L.Br[bf][r16 + RPI * it][kk] = v.x;
-        L.Bi[bf][r16 + RPI * it][kk] = v.y;
+        const cd u = cmul_fx(ph[it], rb[it]), w = cmul_fx((double)s2 * cconj(ph[it]), rm[it]);
+        const cd v = cd{u.x + w.x, u.y + w.y};
+        L.Br[bf][r16 + RPB * it][kk] = v.x;
+        L.Bi[bf][r16 + RPB * it][kk] = v.y;
       }
     } else {
 #pragma unroll
       for (int it = 0; it < NB_; it++) {
-        L.Br[bf][r16 + RPI * it][kk] = rb[it].x;
-        L.Bi[bf][r16 + RPI * it][kk] = rb[it].y;
+        L.Br[bf][r16 + RPB * it][kk] = rb[it].x;
+        L.Bi[bf][r16 + RPB * it][kk] = rb[it].y;
       }
     }
   };
@@ -654,20 +666,20 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds<KCV, NB>& L
     }
 }
 
-// One 64 x 64 output tile per block, complex fp64 on the matrix cores.  The
-// four waves form a 2 x 2 grid of 32 x 32 wave tiles; a wave computes only
-// those of its four 16 x 16 MFMA tiles that hold rows below the offset's R
-// and columns below the tile's pair count, so partial tiles cost little;
-// the choice is made once per tile from a wave-uniform value.  Operands are
+// One (32 WR) x 64 output tile per block, complex fp64 on the matrix cores.
+// The 2 WR waves form a WR x 2 grid of 32 x 32 wave tiles; a wave computes
+// only those of its four 16 x 16 MFMA tiles that hold rows below the
+// offset's R and columns below the tile's pair count, so partial tiles cost
+// little; the choice is made once per tile from a wave-uniform value.  Operands are
 // staged through LDS as separate real / imaginary planes, KCV values of k at
 // a time (variants above); resident blocks overlap one block's global loads
 // with the others' MFMAs.  Consecutive tiles are sent to one XCD (blocks are
 // dealt round-robin over the 8 XCDs), so the tiles sharing one offset's
 // matrix and source vectors run against one L2.
-template <int KCV, int NB, int OCC>
-__global__ __launch_bounds__(NT, OCC) void k_m2l(DevPlan d, const M2LTile* tiles, int n_tiles, int n_rhs,
-                                                 const cd* ME, cd* Y) {
-  __shared__ M2LLds<KCV, NB> L;
+template <int KCV, int NB, int OCC, int WR>
+__global__ __launch_bounds__(128 * WR, OCC) void k_m2l(DevPlan d, const M2LTile* tiles, int n_tiles, int n_rhs,
+                                                       const cd* ME, cd* Y) {
+  __shared__ M2LLds<KCV, NB, WR> L;
   const int per_xcd = (n_tiles + 7) >> 3;
   const int t_id = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
   if (t_id >= n_tiles) return;
@@ -703,13 +715,13 @@ __global__ __launch_bounds__(NT, OCC) void k_m2l(DevPlan d, const M2LTile* tiles
     cd w = cd{1, 0};
     for (int j = 0; j < 8; j++) {
       L.plo[tid][j] = w;
-      w = w * z;
+      w = cmul_fx(w, z);
     }
     const cd z8 = w;
     w = cd{1, 0};
     for (int j = 0; j < 4; j++) {
       L.phi8[tid][j] = w;
-      w = w * z8;
+      w = cmul_fx(w, z8);
     }
   }
   if (tid < TN) {
@@ -730,33 +742,34 @@ __global__ __launch_bounds__(NT, OCC) void k_m2l(DevPlan d, const M2LTile* tiles
   const int pat = __builtin_amdgcn_readfirstlane(ni * 3 + nj);
   if (c.sym) {
     switch (pat) {
-      case 4: m2l_wave<KCV, NB, 1, 1, true>(c, L, tid, wr, wc); break;
-      case 5: m2l_wave<KCV, NB, 1, 2, true>(c, L, tid, wr, wc); break;
-      case 7: m2l_wave<KCV, NB, 2, 1, true>(c, L, tid, wr, wc); break;
-      case 8: m2l_wave<KCV, NB, 2, 2, true>(c, L, tid, wr, wc); break;
-      default: m2l_wave<KCV, NB, 0, 0, true>(c, L, tid, wr, wc); break;
+      case 4: m2l_wave<KCV, NB, WR, 1, 1, true>(c, L, tid, wr, wc); break;
+      case 5: m2l_wave<KCV, NB, WR, 1, 2, true>(c, L, tid, wr, wc); break;
+      case 7: m2l_wave<KCV, NB, WR, 2, 1, true>(c, L, tid, wr, wc); break;
+      case 8: m2l_wave<KCV, NB, WR, 2, 2, true>(c, L, tid, wr, wc); break;
+      default: m2l_wave<KCV, NB, WR, 0, 0, true>(c, L, tid, wr, wc); break;
     }
   } else {
     switch (pat) {
-      case 4: m2l_wave<KCV, NB, 1, 1, false>(c, L, tid, wr, wc); break;
-      case 5: m2l_wave<KCV, NB, 1, 2, false>(c, L, tid, wr, wc); break;
-      case 7: m2l_wave<KCV, NB, 2, 1, false>(c, L, tid, wr, wc); break;
-      case 8: m2l_wave<KCV, NB, 2, 2, false>(c, L, tid, wr, wc); break;
-      default: m2l_wave<KCV, NB, 0, 0, false>(c, L, tid, wr, wc); break;
+      case 4: m2l_wave<KCV, NB, WR, 1, 1, false>(c, L, tid, wr, wc); break;
+      case 5: m2l_wave<KCV, NB, WR, 1, 2, false>(c, L, tid, wr, wc); break;
+      case 7: m2l_wave<KCV, NB, WR, 2, 1, false>(c, L, tid, wr, wc); break;
+      case 8: m2l_wave<KCV, NB, WR, 2, 2, false>(c, L, tid, wr, wc); break;
+      default: m2l_wave<KCV, NB, WR, 0, 0, false>(c, L, tid, wr, wc); break;
     }
   }
 }
-// variant: 0 = 16 values of k per chunk, one buffer, three blocks per CU;
-// 1 = 8 values, two buffers, three blocks; 2 = 16 values, two buffers, two
-// blocks (LM_M2L_VARIANTS variants, bitwise equal results)
+// variant (tiles of 64 rows, 4 waves; 3 waves per SIMD): 0 = 8 values of k
+// per chunk, one buffer; 1 = 4 values, two buffers; 2 = 8 values, two
+// buffers (LM_M2L_VARIANTS variants, bitwise equal results).  Tiles of 96
+// rows (WR = 3, two blocks of 6 waves per CU) measured 40% slower.
 void launch_m2l(const DevPlan& d, const M2LTile* tiles, int n_tiles, int n_rhs, const cd* ME, cd* Y, int pmax,
                 int variant, hipStream_t s) {
   if (n_tiles <= 0) return;
   int grid = ((n_tiles + 7) / 8) * 8;
   switch (variant) {
-    case 1: hipLaunchKernelGGL((k_m2l<8, 1, 3>), dim3(grid), dim3(NT), 0, s, d, tiles, n_tiles, n_rhs, ME, Y); break;
-    case 2: hipLaunchKernelGGL((k_m2l<8, 2, 3>), dim3(grid), dim3(NT), 0, s, d, tiles, n_tiles, n_rhs, ME, Y); break;
-    default: hipLaunchKernelGGL((k_m2l<16, 1, 3>), dim3(grid), dim3(NT), 0, s, d, tiles, n_tiles, n_rhs, ME, Y); break;
+    case 1: hipLaunchKernelGGL((k_m2l<4, 2, 3, 2>), dim3(grid), dim3(256), 0, s, d, tiles, n_tiles, n_rhs, ME, Y); break;
+    case 2: hipLaunchKernelGGL((k_m2l<8, 2, 3, 2>), dim3(grid), dim3(256), 0, s, d, tiles, n_tiles, n_rhs, ME, Y); break;
+    default: hipLaunchKernelGGL((k_m2l<8, 1, 3, 2>), dim3(grid), dim3(256), 0, s, d, tiles, n_tiles, n_rhs, ME, Y); break;
   }
 }
 
