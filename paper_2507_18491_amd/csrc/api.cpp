@@ -990,7 +990,9 @@ static int ensure_rhs(lm_ctx* ctx, int n_rhs, hipStream_t s, Work* w) {
     if (!have) {
       lm_ctx::TileSet ts;
       long long bmax = 0;
-      int rc = make_schedule(ctx, n_rhs, 6LL << 30, ts, &bmax);
+      // M2L scratch budget: fewer, larger launches for many right-hand
+      // sides (each launch ends with a partial wave of tiles)
+      int rc = make_schedule(ctx, n_rhs, 24LL << 30, ts, &bmax);
       if (rc) {
         if (ts.d_tiles) hipFree(ts.d_tiles);
         if (ts.d_ybase) hipFree(ts.d_ybase);

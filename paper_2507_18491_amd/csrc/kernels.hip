@@ -335,18 +335,15 @@ __global__ __launch_bounds__(NT) void k_l2l(DevPlan d, const int* children, int 
       }
   }
 }
+// one block per (child, right-hand side): blocks that each served four
+// right-hand sides held 4x the LDS and ran at a quarter of the occupancy,
+// 1.7x slower per right-hand side than one at a time
 void launch_l2l(const DevPlan& d, const int* children, int n, int n_rhs, cd* LE, int pmax, hipStream_t s) {
   if (n <= 0) return;
   int P = (pmax + 1) * (pmax + 1);
-  int rc = n_rhs == 1 ? 1 : 4;
-  size_t shm = (size_t)rc * 3 * P * sizeof(cd);
-  if (rc == 1) {
-    set_dyn_lds((const void*)k_l2l<1>, shm);
-    hipLaunchKernelGGL(k_l2l<1>, dim3(n, n_rhs), dim3(NT), shm, s, d, children, n_rhs, LE);
-  } else {
-    set_dyn_lds((const void*)k_l2l<4>, shm);
-    hipLaunchKernelGGL(k_l2l<4>, dim3(n, (n_rhs + 3) / 4), dim3(NT), shm, s, d, children, n_rhs, LE);
-  }
+  size_t shm = (size_t)3 * P * sizeof(cd);
+  set_dyn_lds((const void*)k_l2l<1>, shm);
+  hipLaunchKernelGGL(k_l2l<1>, dim3(n, n_rhs), dim3(NT), shm, s, d, children, n_rhs, LE);
 }
 
 // ------------------------------------------------------------------ M2L
@@ -1045,19 +1042,13 @@ static void l2p_go(const DevPlan& d, const int* leaves, int n, int ch, int kind,
 void launch_l2p(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_tgt,
                 int n_rhs, const cd* LE, cd* A, int pi, hipStream_t s) {
   if (n <= 0) return;
-  bool rc1 = n_rhs == 1;
+  // one right-hand side per block (four per block measured 1.7x slower per
+  // right-hand side: 4x the LDS, a quarter of the occupancy)
   int ch = LM_L2P_CHUNK(kind);
-  if (kind == 1) {
-    if (rc1)
-      l2p_go<1, 64>(d, leaves, n, ch, kind, xyz, n_tgt, n_rhs, LE, A, pi, s);
-    else
-      l2p_go<4, 64>(d, leaves, n, ch, kind, xyz, n_tgt, n_rhs, LE, A, pi, s);
-  } else {
-    if (rc1)
-      l2p_go<1, NT>(d, leaves, n, ch, kind, xyz, n_tgt, n_rhs, LE, A, pi, s);
-    else  // 4 right-hand sides at p = 20: 128 threads keep LDS under 160 KB
-      l2p_go<4, 128>(d, leaves, n, ch, kind, xyz, n_tgt, n_rhs, LE, A, pi, s);
-  }
+  if (kind == 1)
+    l2p_go<1, 64>(d, leaves, n, ch, kind, xyz, n_tgt, n_rhs, LE, A, pi, s);
+  else
+    l2p_go<1, NT>(d, leaves, n, ch, kind, xyz, n_tgt, n_rhs, LE, A, pi, s);
 }
 
 // ------------------------------------------------------------------ P2P
