@@ -35,21 +35,26 @@ S2T_FLOPS_PER_NODE = 100
 # HBM traffic of one k_m2l launch at the default workload (N=1e6, p=12,
 # p_free=20), from rocprofv3 FETCH_SIZE / WRITE_SIZE per dispatch scaled by a
 # plain 1 GiB device copy (FETCH_SIZE reads 0.5 KiB per KiB read: factor 2.0;
-# WRITE_SIZE 1:1); see profiles/k_m2l_three_layer_1M_p12_pf20.md.  Valid only
-# for the kernel source it was measured on (digest of the M2L section of
-# kernels.hip), the same launches per step (the plan's split of the M2L
-# work) and the same M2L work (useful complex multiply-adds of the plan);
-# otherwise reported as null.
-K_M2L_TRAFFIC = {"digest": "d399e554001bfd19", "launches_per_step": 8, "m2l_cmac_useful": 1167408236574.0,
-                 "fetch_bytes": 1.7701e7 * 1024 * 2.0, "write_bytes": 5.4599e6 * 1024 * 1.0}
+# WRITE_SIZE 1:1), averaged over the evaluation's two launches; see
+# profiles/k_m2l_three_layer_1M_p12_pf20.md.  Valid only for the kernel and
+# tile-order source it was measured on (digest below), the same launches per
+# step and the same M2L work; otherwise reported as null.
+K_M2L_TRAFFIC = {"digest": "b76d06a24d27691b", "launches_per_step": 2, "m2l_cmac_useful": 619120501668.0,
+                 "fetch_bytes": 0.5 * (3.5280e7 + 2.0719e7) * 1024 * 2.0,
+                 "write_bytes": 0.5 * (2.3324e7 + 2.1005e7) * 1024 * 1.0}
 
 
 def m2l_source_digest():
+    """Digest of the M2L GEMM kernel's source and of the host code that
+    orders its tiles (both decide its memory traffic)."""
     import hashlib
     src = open(os.path.join(ROOT, "paper_2507_18491_amd", "csrc", "kernels.hip")).read()
     a = src.index("// ------------------------------------------------------------------ M2L")
     b = src.index("// LE_t[out][rhs] += sum")
-    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+    api = open(os.path.join(ROOT, "paper_2507_18491_amd", "csrc", "api.cpp")).read()
+    c = api.index("static int make_schedule(lm_ctx* ctx, int n_rhs, long long budget, lm_ctx::TileSet& ts, long long* block_max) {")
+    e = api.index("// complex numbers of the P2M partial expansions")
+    return hashlib.sha256((src[a:b] + api[c:e]).encode()).hexdigest()[:16]
 
 
 def host_cores():

@@ -899,27 +899,32 @@ static int make_schedule(lm_ctx* ctx, int n_rhs, long long budget, lm_ctx::TileS
         const M2LOffset& O = pl.offs[C.off0 + o0];
         const int po = O.pord, Po = (po + 1) * (po + 1);
         const bool sym = C.nblk == 3;
-        for (int ot = 0; ot < (sym ? 2 : 3); ot++) {
-          M2LTile t;
-          t.mat = O.mat[sym ? ot : 0];
-          t.ybase = ybase[bi];
-          t.qo = q0;
-          t.q0b = B.q0;
-          t.P = C.P;
-          t.p = pl.inst[C.inst].p;
-          t.R = sym ? lm_sym_dim(po, ot) : Po;
-          t.Pb = Po;
-          t.Kf = sym ? lm_sym_dim(t.p, ot) : C.P;
-          t.ot = ot;
-          t.sym = sym ? 1 : 0;
-          for (int r0 = 0; r0 < t.R; r0 += TM_ROWS)
-            for (int c0 = 0; c0 < ncol; c0 += TN_COLS) {
+        // column tile outermost: the row tiles of both parts (or of the
+        // three output types) of one column tile are consecutive, so they
+        // run together on one XCD and read the tile's source vectors from
+        // its L2 (with the row tile outermost, the source vectors of a
+        // large group were read from HBM once per row tile)
+        for (int c0 = 0; c0 < ncol; c0 += TN_COLS)
+          for (int ot = 0; ot < (sym ? 2 : 3); ot++) {
+            M2LTile t;
+            t.mat = O.mat[sym ? ot : 0];
+            t.ybase = ybase[bi];
+            t.qo = q0;
+            t.q0b = B.q0;
+            t.P = C.P;
+            t.p = pl.inst[C.inst].p;
+            t.R = sym ? lm_sym_dim(po, ot) : Po;
+            t.Pb = Po;
+            t.Kf = sym ? lm_sym_dim(t.p, ot) : C.P;
+            t.ot = ot;
+            t.sym = sym ? 1 : 0;
+            t.col0 = c0;
+            t.ncol = std::min(TN_COLS, ncol - c0);
+            for (int r0 = 0; r0 < t.R; r0 += TM_ROWS) {
               t.row0 = r0;
-              t.col0 = c0;
-              t.ncol = std::min(TN_COLS, ncol - c0);
               tiles.push_back(t);
             }
-        }
+          }
       });
       ch.nbt += B.nt;
       bi++;
