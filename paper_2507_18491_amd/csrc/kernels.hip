@@ -436,7 +436,10 @@ struct M2LLds {
 // number of barriers whatever its NI, NJ.
 // MFMA operand layout (v_mfma_f64_16x16x4f64, one fp64 per lane and
 // operand): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; the four
-// result registers of lane l hold C[4 r + l / 16][l % 16], r = 0..3.
+// result registers of lane l hold C[4 r + l / 16][l % 16], r = 0..3.  The
+// kernel passes the source values (lane l: column l % 16, k = l / 16) as
+// the first operand and the matrix (lane l: row l % 16, k = l / 16) as the
+// second, so it accumulates the transposed tile.
 // Complex product with three real MFMAs per step (Gauss): P1 = sum A_re
 // B_re, P2 = sum A_im B_im, P3 = sum (A_re + A_im)(B_re + B_im); then C_re =
 // P1 - P2 and C_im = P3 - P1 - P2.  The accumulator chains are interleaved
@@ -599,15 +602,15 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds<KCV, NB, WR
 #pragma unroll
         for (int i = 0; i < NIx; i++)
 #pragma unroll
-          for (int j = 0; j < NJx; j++) p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[i], b_r[j], p1[i][j], 0, 0, 0);
+          for (int j = 0; j < NJx; j++) p1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b_r[j], a_r[i], p1[i][j], 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < NIx; i++)
 #pragma unroll
-          for (int j = 0; j < NJx; j++) p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[i], b_i[j], p2[i][j], 0, 0, 0);
+          for (int j = 0; j < NJx; j++) p2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b_i[j], a_i[i], p2[i][j], 0, 0, 0);
 #pragma unroll
         for (int i = 0; i < NIx; i++)
 #pragma unroll
-          for (int j = 0; j < NJx; j++) p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_s[i], b_s[j], p3[i][j], 0, 0, 0);
+          for (int j = 0; j < NJx; j++) p3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b_s[j], a_s[i], p3[i][j], 0, 0, 0);
       }
     }
   };
@@ -636,8 +639,12 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds<KCV, NB, WR
     }
   }
   if (NI == 0 || NJ == 0) return;
-  // epilogue: lane holds rows 4 r + lane / 16 of each 16 x 16 tile, column
-  // lane % 16; column j of the tile is (pair, rhs) = (qo + (col0 + j) / n_rhs,
+  // epilogue.  The MFMAs take the source values as their first operand and
+  // the matrix as their second, so each 16 x 16 accumulator holds the
+  // transposed tile: register r of lane l is row lane % 16 of column
+  // 4 r + lane / 16, and the 16 lanes of one column write 16 consecutive
+  // rows (one contiguous 256-byte run instead of 16 scattered 16-byte
+  // stores).  Column j of the tile is (pair, rhs) = (qo + (col0 + j) / n_rhs,
   // (col0 + j) % n_rhs) and goes to that pair's scratch vector: free space
   // [pair][ot][rhs][P], reaction [pair][even: rhs][lm_sym_dim(p, 0)] then
   // [odd: rhs][lm_sym_dim(p, 1)] (3 n_rhs P per pair either way)
@@ -646,18 +653,17 @@ __device__ __forceinline__ void m2l_wave(const M2LTileCtx& c, M2LLds<KCV, NB, WR
   for (int i = 0; i < NIx; i++)
 #pragma unroll
     for (int j = 0; j < NJx; j++) {
-      const int col = wc * 32 + j * 16 + li;
-      if (col >= c.ncol) continue;
-      v4d vr = p1[i][j] - p2[i][j], vi = p3[i][j] - p1[i][j] - p2[i][j];
-      const int jj = c.col0 + col;
-      const int q = c.qo + jj / c.n_rhs, r = jj % c.n_rhs;
-      cd* Yq = SYM ? c.Y + c.ybase + (long long)(q - c.q0b) * 3 * c.n_rhs * c.P +
-                           (c.ot ? (long long)c.n_rhs * lm_sym_dim(c.p, 0) : 0) + (long long)r * c.Kf
-                     : c.Y + c.ybase + ((long long)((q - c.q0b) * 3 + c.ot) * c.n_rhs + r) * c.P;
+      const int row = c.row0 + wr * 32 + i * 16 + li;
+      const v4d vr = p1[i][j] - p2[i][j], vi = p3[i][j] - p1[i][j] - p2[i][j];
 #pragma unroll
       for (int rr = 0; rr < 4; rr++) {
-        const int row = c.row0 + wr * 32 + i * 16 + 4 * rr + rq;
-        if (row >= c.R) continue;
+        const int col = wc * 32 + j * 16 + 4 * rr + rq;
+        if (col >= c.ncol || row >= c.R) continue;
+        const int jj = c.col0 + col;
+        const int q = c.qo + jj / c.n_rhs, r = jj % c.n_rhs;
+        cd* Yq = SYM ? c.Y + c.ybase + (long long)(q - c.q0b) * 3 * c.n_rhs * c.P +
+                             (c.ot ? (long long)c.n_rhs * lm_sym_dim(c.p, 0) : 0) + (long long)r * c.Kf
+                       : c.Y + c.ybase + ((long long)((q - c.q0b) * 3 + c.ot) * c.n_rhs + r) * c.P;
         Yq[m2l_sidx(c, row)] = cd{vr[rr], vi[rr]};
       }
     }
