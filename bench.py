@@ -26,8 +26,12 @@ METRIC = "targets/s, 3-layer dyadic FMM N=1M p=12 at rel err≤1e-6; batched/adj
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 fp64 FMA/clk x 2 flop x 2.4 GHz (fp64 MFMA: same)
 HBM_PEAK_GBS = 8000.0
 # algorithmic work of the near-field kernels (see the kernel table of the design notes):
-# free-space pair: distance, 1/r, e^{ikr} (one sincos), the a q + b R (R.q) dyadic form
-P2P_FLOPS_PER_PAIR = 100
+# free-space pair: distance, 1/r, e^{ikr} (one sincos) and the two coefficients per kernel
+# evaluation (60), the a q + b R (R.q) dyadic form per ordered pair (40); when the targets
+# are the sources one evaluation serves both orders of a pair of different leaves
+P2P_FLOPS_PER_EVAL = 60
+P2P_FLOPS_PER_APPLY = 40
+P2P_FLOPS_PER_PAIR = P2P_FLOPS_PER_EVAL + P2P_FLOPS_PER_APPLY
 # direct reaction pair, per quadrature node: Z = exp(i (k_z t + k'_z u)), J0..J2 of
 # k_rho rho, and the five complex multiply-adds of the node's contribution
 S2T_FLOPS_PER_NODE = 100
@@ -373,13 +377,14 @@ def main():
 
     kernels = {
         "k_m2l_reduce": kroof("m2l_reduce", "hbm", st["reduce_bytes"] * args.rhs, "GB/s"),
-        "k_p2p": kroof("p2p", "alu", st["p2p_pairs"] * P2P_FLOPS_PER_PAIR * args.rhs, "TFLOP/s"),
+        "k_p2p": kroof("p2p", "alu", (st["p2p_kernel_evals"] * P2P_FLOPS_PER_EVAL
+                                      + st["p2p_pairs"] * P2P_FLOPS_PER_APPLY) * args.rhs, "TFLOP/s"),
         # the direct pairs' integrals are formed once per group of up to 4 vectors
         "k_s2t": kroof("s2t", "alu", st["s2t_node_evals"] * S2T_FLOPS_PER_NODE * ((args.rhs + 3) // 4), "TFLOP/s"),
     }
     # whole path: the sum of each kernel's ideal time at its own peak over the
     # measured time of the step
-    t_ideal = (m2l_flops + st["p2p_pairs"] * P2P_FLOPS_PER_PAIR * args.rhs
+    t_ideal = (m2l_flops + (st["p2p_kernel_evals"] * P2P_FLOPS_PER_EVAL + st["p2p_pairs"] * P2P_FLOPS_PER_APPLY) * args.rhs
                + st["s2t_node_evals"] * S2T_FLOPS_PER_NODE * ((args.rhs + 3) // 4)
                + (st["p2m_flops"] + st["m2m_flops"] + st["l2l_flops"] + st["l2p_flops"]) * args.rhs
                ) / (FP64_VALU_PEAK_TFLOPS * 1e12)
@@ -388,7 +393,7 @@ def main():
                 + 2 * 48.0 * args.n * args.rhs) / (HBM_PEAK_GBS * 1e9)
     path = {"t_ideal_ms": 1e3 * t_ideal, "t_measured_ms": ms_per_step, "frac": 1e3 * t_ideal / ms_per_step,
             "rule": "sum over kernels of algorithmic flops / 78.6 TFLOP/s (M2L, near field at %d flops per "
-                    "pair, direct reaction pairs at %d flops per quadrature node, P2M/M2M/L2L/L2P at 8 flops "
+                    "pair, the kernel's 60 counted once per evaluation, direct reaction pairs at %d flops per quadrature node, P2M/M2M/L2L/L2P at 8 flops "
                     "per complex multiply-add) plus bytes / 8 TB/s (M2L reduction, expansion clears, "
                     "reading J and writing A)" % (P2P_FLOPS_PER_PAIR, S2T_FLOPS_PER_NODE)}
     print("timed: %.1f ms/step, phases (ms/step): %s" % (

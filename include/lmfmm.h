@@ -315,7 +315,11 @@ int lm_stats(const lm_ctx* ctx, double* out_host, int n);
 #define LM_STAT_M2L_CMAC_DENSE 29    /* complex multiply-adds of the same M2L per rhs in  */
                                      /* the dense spin-basis form (three P x 3P products  */
                                      /* per reaction pair, Sec. 3.3)                      */
-#define LM_STATS_COUNT 30
+#define LM_STAT_P2P_KERNEL_EVALS 30  /* free-space near field: evaluations of the pair    */
+                                     /* kernel (when the targets are the sources, one per */
+                                     /* unordered pair of different leaves, and every     */
+                                     /* ordered pair inside a leaf; else P2P_PAIRS)       */
+#define LM_STATS_COUNT 31
 
 /* ---- iterative solve over the evaluation ---- */
 

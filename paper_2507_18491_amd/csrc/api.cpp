@@ -102,8 +102,21 @@ struct lm_ctx {
   int* d_s2t_gslot = nullptr;              // slots in the points' fixed order
   int s2t_npts = 0;
   long long s2t_slots = 0;
-  cd* S2TY = nullptr;                      // slot outputs [slot][rhs][3]
-  long long s2ty_cap = 0;
+  cd* S2TY = nullptr;                      // slot outputs [slot][rhs][3] (direct pairs, then the
+  long long s2ty_cap = 0;                  // symmetric near field's partner sums: used one after the other)
+  // symmetric free-space near field (targets are the sources): work items
+  // (target leaf, chunk, first slot, partner range, own source box), the
+  // partners (adjacent leaves of higher source-box id), and per point its
+  // partner-sum slots in item order
+  int* d_p2ps_items = nullptr;
+  int p2ps_n = 0;
+  int* d_p2ps_part = nullptr;
+  int* d_p2ps_gpt = nullptr;
+  int* d_p2ps_gptr = nullptr;
+  int* d_p2ps_gslot = nullptr;
+  int p2ps_npts = 0;
+  long long p2ps_slots = 0;
+  double p2ps_evals = 0;                   // kernel evaluations: own-leaf ordered pairs + partner pairs
   double contour_a = 0;
   cd* Jc = nullptr;                        // conjugated-input scratch
   long long jc_cap = 0;
@@ -188,6 +201,10 @@ static void free_build(lm_ctx* ctx) {
   memset(ctx->s2t_launch, 0, sizeof(ctx->s2t_launch));
   ctx->s2t_npts = 0;
   ctx->s2t_slots = 0;
+  ctx->d_p2ps_items = ctx->d_p2ps_part = ctx->d_p2ps_gpt = ctx->d_p2ps_gptr = ctx->d_p2ps_gslot = nullptr;
+  ctx->p2ps_n = ctx->p2ps_npts = 0;
+  ctx->p2ps_slots = 0;
+  ctx->p2ps_evals = 0;
   if (ctx->S2TY) hipFree(ctx->S2TY);
   ctx->S2TY = nullptr;
   ctx->s2ty_cap = 0;
@@ -728,6 +745,87 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
     if ((rc = upload(ctx, &ctx->d_s2t_gptr, gptr))) return rc;
     if ((rc = upload(ctx, &ctx->d_s2t_gslot, gslot))) return rc;
   }
+  {
+    // symmetric free-space near field, when the targets are the sources (the
+    // same point of a free-space leaf is then a source and a target with the
+    // same id): each unordered pair of adjacent leaves is evaluated once, in
+    // the work items of the leaf with the lower source-box id
+    const bool same = n_src == n_tgt && memcmp(soff, toff, (size_t)(n_geom + 1) * sizeof(int64_t)) == 0 &&
+                      (src_xyz == tgt_xyz || n_src == 0 ||
+                       memcmp(src_xyz, tgt_xyz, (size_t)n_src * 3 * sizeof(double)) == 0);
+    std::vector<int> items6, part;
+    long long slots = 0;
+    double evals = 0;
+    bool ok = same;
+    for (size_t f = 0; ok && f < pl.p2p_tboxes.size(); f++)
+      for (size_t i = 0; ok && i < pl.p2p_tboxes[f].size(); i += 2) {
+        const int b = pl.p2p_tboxes[f][i], c = pl.p2p_tboxes[f][i + 1];
+        const TgtBox& tb = pl.tbox[b];
+        int self = -1;  // the source box of the same leaf
+        for (int li = tb.p2p0; li < tb.p2p1; li++) {
+          const SrcBox& sb = pl.sbox[pl.p2p_list[li]];
+          if (sb.c[0] == tb.c[0] && sb.c[1] == tb.c[1] && sb.c[2] == tb.c[2] && sb.inst == tb.inst &&
+              sb.pt1 - sb.pt0 == tb.pt1 - tb.pt0)
+            self = pl.p2p_list[li];
+        }
+        if (self < 0) {
+          ok = false;
+          break;
+        }
+        const int p0 = (int)part.size();
+        long long ns = 0;
+        for (int li = tb.p2p0; li < tb.p2p1; li++)
+          if (pl.p2p_list[li] > self) {
+            part.push_back(pl.p2p_list[li]);
+            ns += pl.sbox[pl.p2p_list[li]].pt1 - pl.sbox[pl.p2p_list[li]].pt0;
+          }
+        items6.insert(items6.end(), {b, c, (int)slots, p0, (int)part.size(), self});
+        const int nt = std::min(LM_P2P_CHUNK, tb.pt1 - (tb.pt0 + c * LM_P2P_CHUNK));
+        evals += (double)nt * ((pl.sbox[self].pt1 - pl.sbox[self].pt0) + ns);
+        slots += ns;
+        if (slots > 2000000000LL) ok = false;
+      }
+    if (ok && !items6.empty()) {
+      // per point: its slots in item order
+      std::vector<int> cnt(pl.n_tgt + 1, 0);
+      for (size_t it = 0; it < items6.size(); it += 6)
+        for (int pi = items6[it + 3]; pi < items6[it + 4]; pi++) {
+          const SrcBox& sb = pl.sbox[part[pi]];
+          for (int pt = sb.pt0; pt < sb.pt1; pt++) cnt[pl.src_perm[pt] + 1]++;
+        }
+      std::vector<int> gpt, gptr, start(pl.n_tgt, -1);
+      int acc = 0;
+      for (int64_t i = 0; i < pl.n_tgt; i++)
+        if (cnt[i + 1] > 0) {
+          start[i] = acc;
+          gpt.push_back((int)i);
+          gptr.push_back(acc);
+          acc += cnt[i + 1];
+        }
+      gptr.push_back(acc);
+      std::vector<int> gslot(acc), fill(pl.n_tgt, 0);
+      for (size_t it = 0; it < items6.size(); it += 6) {
+        long long so = items6[it + 2];
+        for (int pi = items6[it + 3]; pi < items6[it + 4]; pi++) {
+          const SrcBox& sb = pl.sbox[part[pi]];
+          for (int pt = sb.pt0; pt < sb.pt1; pt++) {
+            const int id = pl.src_perm[pt];
+            gslot[start[id] + fill[id]++] = (int)(so + (pt - sb.pt0));
+          }
+          so += sb.pt1 - sb.pt0;
+        }
+      }
+      if ((rc = upload(ctx, &ctx->d_p2ps_items, items6))) return rc;
+      if ((rc = upload(ctx, &ctx->d_p2ps_part, part))) return rc;
+      if ((rc = upload(ctx, &ctx->d_p2ps_gpt, gpt))) return rc;
+      if ((rc = upload(ctx, &ctx->d_p2ps_gptr, gptr))) return rc;
+      if ((rc = upload(ctx, &ctx->d_p2ps_gslot, gslot))) return rc;
+      ctx->p2ps_n = (int)(items6.size() / 6);
+      ctx->p2ps_npts = (int)gpt.size();
+      ctx->p2ps_slots = slots;
+      ctx->p2ps_evals = evals;
+    }
+  }
   // matrices and table scratch
   void* vp = nullptr;
   if ((rc = dalloc(ctx, &vp, (size_t)pl.mat_size * sizeof(cd)))) return rc;
@@ -853,7 +951,7 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
     ctx->na_off[1] = ctx->na_off[0] + up(pl.me_size);
     ctx->na_off[2] = ctx->na_off[1] + up(pl.le_size);
     ctx->na_off[4] = ctx->na_off[2] + up(p2m_part_size(ctx, 1));
-    ctx->na_off[3] = ctx->na_off[4] + up(ctx->s2t_slots * 3);
+    ctx->na_off[3] = ctx->na_off[4] + up(std::max(ctx->s2t_slots, ctx->p2ps_slots) * 3);
     long long bmax = 0;
     int rc2 = make_schedule(ctx, 1, std::max(0LL, cap - ctx->na_off[3]) * (long long)sizeof(cd), ctx->na_ts, &bmax);
     if (rc2) return rc2;
@@ -1013,7 +1111,7 @@ static int ensure_rhs(lm_ctx* ctx, int n_rhs, hipStream_t s, Work* w) {
       ctx->y_cap = ts.y_need;
     }
   }
-  const long long sy = ctx->s2t_slots * n_rhs * 3;
+  const long long sy = std::max(ctx->s2t_slots, ctx->p2ps_slots) * n_rhs * 3;
   if (sy > ctx->s2ty_cap) {
     HIPC(hipStreamSynchronize(s));
     if (ctx->S2TY) hipFree(ctx->S2TY);
@@ -1371,7 +1469,17 @@ static int evaluate_chunk(lm_ctx* ctx, int n_rhs, const void* J, void* A, void* 
         launch_l2p(d, ctx->d_l2p[g], ctx->n_l2p[g], kind, ctx->d_tgt, pl.n_tgt, n_rhs, w.LE, Ac, pl.inst[i].p, s);
     }
     mark(6);
-    for (size_t f = 0; f < ctx->d_p2p.size(); f++) {
+    if (!grad && !curl && ctx->p2ps_n > 0) {
+      // targets are the sources: one kernel evaluation per unordered pair
+      // (the partner sums through the slots, added in item order)
+      span(2, true);
+      launch_p2p_sym(d, ctx->d_p2ps_items, ctx->p2ps_n, ctx->d_p2ps_part, ctx->d_src, Jc, pl.n_src, n_rhs, Ac,
+                     w.S2TY, ctx->p2p_red, s);
+      launch_s2t_gather(ctx->d_p2ps_gpt, ctx->d_p2ps_gptr, ctx->d_p2ps_gslot, ctx->p2ps_npts, n_rhs, w.S2TY,
+                        pl.n_tgt, Ac, s);
+      span(2, false);
+    }
+    for (size_t f = 0; f < ctx->d_p2p.size() && (grad || curl || ctx->p2ps_n == 0); f++) {
       span(2, true);
       if (grad)
         launch_p2p_grad(d, ctx->d_p2p[f], ctx->n_p2p[f], ctx->d_src, Jc, pl.n_src, ctx->d_tgt, W, pl.n_tgt, n_rhs,
@@ -1525,6 +1633,7 @@ int lm_stats(const lm_ctx* ctx, double* out, int n) {
       }
     }
     v[LM_STAT_M2L_CMAC_DENSE] = cd_;
+    v[LM_STAT_P2P_KERNEL_EVALS] = ctx->p2ps_n > 0 ? ctx->p2ps_evals : (double)pl.n_p2p_pairs;
   }
   {
     // executed MFMA flops of the M2L GEMM per rhs (variant 0: 16 values of k

@@ -73,6 +73,8 @@ void launch_m2l_reduce(const DevPlan& d, int bt0, int nbt, int n_rhs, const cd* 
 void launch_l2l(const DevPlan& d, const int* children, int n, int n_rhs, cd* LE, int pmax, hipStream_t s);
 void launch_l2p(const DevPlan& d, const int* leaves, int n, int kind, const double* xyz, long long n_tgt,
                 int n_rhs, const cd* LE, cd* A, int pi, hipStream_t s);
+void launch_p2p_sym(const DevPlan& d, const int* items, int n, const int* part, const double* xyz, const cd* J,
+                    long long n_pts, int n_rhs, cd* A, cd* Ys, bool red, hipStream_t s);
 void launch_p2p(const DevPlan& d, const int* tboxes, int n, const double* sxyz, const cd* J, long long n_src,
                 const double* txyz, long long n_tgt, int n_rhs, cd* A, bool red, hipStream_t s);
 void launch_conj(cd* out, const cd* in, long long n, hipStream_t s);

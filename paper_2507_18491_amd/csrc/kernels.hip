@@ -1155,6 +1155,160 @@ void launch_p2p(const DevPlan& d, const int* tboxes, int n, const double* sxyz, 
   }
 }
 
+// Symmetric free-space near field, for builds whose targets are the
+// sources: G^f(x_i - x_j) = G^f(x_j - x_i) (a symmetric dyadic of r), so one
+// evaluation of the kernel per unordered pair serves both ends.  A work
+// item is (leaf, chunk of NT points): its points interact with their own
+// leaf as in k_p2p (every ordered pair, the coincident one skipped) and
+// with the adjacent leaves of higher source-box id (the partners), whose
+// points receive G J_i back.  Per partner, 64 points at a time: each wave
+// holds 64 of the item's points (one per lane) and runs a systolic cycle of
+// 64 steps: at step s lane l pairs its point with partner point
+// (l - s) mod 64, adds G J_j to its own sum and G J_i to that partner
+// point's sum for the wave (in LDS; the 64 lanes of a step touch 64
+// different points).  The four waves' sums are added in wave order and written to the item's output slot
+// for that point; k_s2t_gather adds each point's slots in item order after
+// the item's own sums went into A.  Deterministic, no atomics; one
+// right-hand side per block (blockIdx.y).
+template <bool RED>
+__global__ __launch_bounds__(NT) void k_p2p_sym(DevPlan d, const int* items, const int* part, const double* xyz,
+                                                const cd* J, long long n_pts, int n_rhs, cd* A, cd* Ys) {
+  __shared__ double sp[NT][3];
+  __shared__ cd sj[NT][3];
+  __shared__ double qx[64], qy[64], qz[64], qj[6][64];  // one block of 64 partner points
+  __shared__ cd tw[NT / 64][64][3];                    // per wave: sums for the partner points
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // item: (target leaf, chunk, first output slot, partner range, own source box)
+  const int* it = items + 6 * blockIdx.x;
+  const int b = __builtin_amdgcn_readfirstlane(it[0]);
+  const int chunk = __builtin_amdgcn_readfirstlane(it[1]);
+  const long long slot0 = __builtin_amdgcn_readfirstlane(it[2]);
+  const int p0 = __builtin_amdgcn_readfirstlane(it[3]), p1 = __builtin_amdgcn_readfirstlane(it[4]);
+  const int self = __builtin_amdgcn_readfirstlane(it[5]);
+  const TgtBox tb = d.tbox[b];
+  const double k = d.inst[__builtin_amdgcn_readfirstlane(tb.inst)].kt;
+  const int r = blockIdx.y;
+  const cd* Jr = J + (long long)r * n_pts * 3;
+  const double inv4pi = 0.079577471545947667884;
+  const double invk = 1.0 / k;
+  const int ti = tb.pt0 + chunk * NT + tid;
+  const bool act = ti < tb.pt1;
+  // lanes past the chunk take the leaf's first point with no current: every
+  // lane runs the systolic cycle, their terms vanish
+  const int id = d.tgt_perm[act ? ti : tb.pt0];
+  const double x0 = xyz[3 * id], y0 = xyz[3 * id + 1], z0 = xyz[3 * id + 2];
+  cd ji[3];
+  for (int c = 0; c < 3; c++) ji[c] = act ? Jr[(long long)id * 3 + c] : cd{0, 0};
+  cd acc[3] = {cd{0, 0}, cd{0, 0}, cd{0, 0}};
+  // pair kernel: a = g (1 - 1/(kr)^2 + i/(kr)), b = g (-1 + 3/(kr)^2 - 3i/(kr)),
+  // g = e^{ikr} / (4 pi r), unit vector u; r = 0 gives 1/r = 0 and no term
+  auto kern = [&](double rx, double ry, double rz, cd& a, cd& bq, double& ux, double& uy, double& uz) {
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    const double ir = r2 > 0.0 ? lm_rsqrt(r2) : 0.0, rr = r2 * ir;
+    const double kr = k * rr, ikr = invk * ir, ikr2 = ikr * ikr;
+    double sn, cs;
+    lm_sincos_nf<RED>(kr, &sn, &cs);
+    const cd g = cd{cs * inv4pi * ir, sn * inv4pi * ir};
+    a = g * cd{1.0 - ikr2, ikr};
+    bq = g * cd{-1.0 + 3.0 * ikr2, -3.0 * ikr};
+    ux = rx * ir;
+    uy = ry * ir;
+    uz = rz * ir;
+  };
+  {
+    // own leaf: every ordered pair
+    const SrcBox sb = d.sbox[self];
+    for (int s0 = sb.pt0; s0 < sb.pt1; s0 += NT) {
+      const int ns = min(NT, sb.pt1 - s0);
+      __syncthreads();
+      if (tid < ns) {
+        const int sid = d.src_perm[s0 + tid];
+        sp[tid][0] = xyz[3 * sid];
+        sp[tid][1] = xyz[3 * sid + 1];
+        sp[tid][2] = xyz[3 * sid + 2];
+        for (int c = 0; c < 3; c++) sj[tid][c] = Jr[(long long)sid * 3 + c];
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll 4
+        for (int j = 0; j < ns; j++) {
+          cd a, bq;
+          double ux, uy, uz;
+          kern(x0 - sp[j][0], y0 - sp[j][1], z0 - sp[j][2], a, bq, ux, uy, uz);
+          const cd jx = sj[j][0], jy = sj[j][1], jz = sj[j][2];
+          const cd brj = bq * (ux * jx + uy * jy + uz * jz);
+          acc[0] = acc[0] + a * jx + ux * brj;
+          acc[1] = acc[1] + a * jy + uy * brj;
+          acc[2] = acc[2] + a * jz + uz * brj;
+        }
+      }
+    }
+  }
+  long long so = slot0;
+  for (int pi = p0; pi < p1; pi++) {
+    const SrcBox sb = d.sbox[part[pi]];
+    for (int s0 = sb.pt0; s0 < sb.pt1; s0 += 64) {
+      const int nb = min(64, sb.pt1 - s0);
+      __syncthreads();
+      if (tid < 64) {
+        const bool ok = tid < nb;
+        const int sid = d.src_perm[ok ? s0 + tid : sb.pt0];
+        qx[tid] = xyz[3 * sid];
+        qy[tid] = xyz[3 * sid + 1];
+        qz[tid] = xyz[3 * sid + 2];
+        for (int c = 0; c < 3; c++) {
+          const cd v = ok ? Jr[(long long)sid * 3 + c] : cd{0, 0};
+          qj[2 * c][tid] = v.x;
+          qj[2 * c + 1][tid] = v.y;
+        }
+      }
+      __syncthreads();
+      // partner sums of this wave in LDS: at step s lane l adds to point
+      // (l - s) mod 64, so the 64 lanes touch 64 different points and each
+      // point receives its terms in step order (the wave's LDS operations
+      // complete in issue order, so step s + 1 reads what step s wrote)
+      for (int c = 0; c < 3; c++) tw[wave][lane][c] = cd{0, 0};
+      for (int st = 0; st < 64; st++) {
+        const int j = (lane - st) & 63;
+        cd a, bq;
+        double ux, uy, uz;
+        kern(x0 - qx[j], y0 - qy[j], z0 - qz[j], a, bq, ux, uy, uz);
+        const cd jx = cd{qj[0][j], qj[1][j]}, jy = cd{qj[2][j], qj[3][j]}, jz = cd{qj[4][j], qj[5][j]};
+        const cd brj = bq * (ux * jx + uy * jy + uz * jz);
+        acc[0] = acc[0] + a * jx + ux * brj;
+        acc[1] = acc[1] + a * jy + uy * brj;
+        acc[2] = acc[2] + a * jz + uz * brj;
+        // the same kernel at the partner point: G(x_j - x_i) = G(x_i - x_j)
+        const cd bri = bq * (ux * ji[0] + uy * ji[1] + uz * ji[2]);
+        tw[wave][j][0] = tw[wave][j][0] + (a * ji[0] + ux * bri);
+        tw[wave][j][1] = tw[wave][j][1] + (a * ji[1] + uy * bri);
+        tw[wave][j][2] = tw[wave][j][2] + (a * ji[2] + uz * bri);
+      }
+      __syncthreads();
+      if (tid < nb) {
+        cd u[3] = {tw[0][tid][0], tw[0][tid][1], tw[0][tid][2]};
+        for (int w = 1; w < NT / 64; w++)
+          for (int c = 0; c < 3; c++) u[c] = u[c] + tw[w][tid][c];
+        cd* Yp = Ys + ((so + (s0 - sb.pt0) + tid) * n_rhs + r) * 3;
+        for (int c = 0; c < 3; c++) Yp[c] = u[c];
+      }
+    }
+    so += sb.pt1 - sb.pt0;
+  }
+  if (act) {
+    cd* Ap = A + ((long long)r * n_pts + id) * 3;
+    for (int c = 0; c < 3; c++) Ap[c] = Ap[c] + acc[c];
+  }
+}
+void launch_p2p_sym(const DevPlan& d, const int* items, int n, const int* part, const double* xyz, const cd* J,
+                    long long n_pts, int n_rhs, cd* A, cd* Ys, bool red, hipStream_t s) {
+  if (n <= 0) return;
+  if (red)
+    hipLaunchKernelGGL(k_p2p_sym<true>, dim3(n, n_rhs), dim3(NT), 0, s, d, items, part, xyz, J, n_pts, n_rhs, A, Ys);
+  else
+    hipLaunchKernelGGL(k_p2p_sym<false>, dim3(n, n_rhs), dim3(NT), 0, s, d, items, part, xyz, J, n_pts, n_rhs, A, Ys);
+}
+
 // ------------------------------------------------------------------ self-test
 // out[4 i .. 4 i + 3] = (sin, cos) by the near-field routine (library beyond
 // its range), then

@@ -19,7 +19,8 @@ STAT_NAMES = ["n_free_inst", "n_react_inst", "m2l_pairs_free", "m2l_pairs_react"
               "t_plan_ms", "t_upload_ms", "t_tables_ms", "n_src_boxes", "n_tgt_boxes",
               "n_m2l_classes", "n_m2l_tiles_1rhs", "m2l_cmac_useful", "m2l_cmac_exec",
               "n_leaves_p2m", "free_depth", "s2t_pairs", "m2l_flop_exec", "p2m_flops", "m2m_flops",
-              "l2l_flops", "l2p_flops", "reduce_bytes", "s2t_node_evals", "m2l_cmac_dense"]
+              "l2l_flops", "l2p_flops", "reduce_bytes", "s2t_node_evals", "m2l_cmac_dense",
+              "p2p_kernel_evals"]
 
 
 PHASE_NAMES = ["clear", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p"]
