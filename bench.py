@@ -43,9 +43,9 @@ S2T_FLOPS_PER_NODE = 100
 # profiles/k_m2l_three_layer_1M_p12_pf20.md.  Valid only for the kernel and
 # tile-order source it was measured on (digest below), the same launches per
 # step and the same M2L work; otherwise reported as null.
-K_M2L_TRAFFIC = {"digest": "b76d06a24d27691b", "launches_per_step": 2, "m2l_cmac_useful": 619120501668.0,
-                 "fetch_bytes": 0.5 * (3.5280e7 + 2.0719e7) * 1024 * 2.0,
-                 "write_bytes": 0.5 * (2.3324e7 + 2.1005e7) * 1024 * 1.0}
+K_M2L_TRAFFIC = {"digest": "ce9a57772387ed21", "launches_per_step": 2, "m2l_cmac_useful": 619120501668.0,
+                 "fetch_bytes": 0.5 * (3.5078e7 + 2.0243e7) * 1024 * 2.0,
+                 "write_bytes": 0.5 * (2.3779e7 + 2.1319e7) * 1024 * 1.0}
 
 
 def m2l_source_digest():

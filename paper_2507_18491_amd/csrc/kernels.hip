@@ -1244,6 +1244,10 @@ __global__ __launch_bounds__(NT) void k_p2p_sym(DevPlan d, const int* items, con
       }
     }
   }
+  // waves with points of the chunk (the others skip the partner cycles)
+  const int nchunk = min(NT, tb.pt1 - (tb.pt0 + chunk * NT));
+  const int nwav = (nchunk + 63) >> 6;
+  const bool wact = wave < nwav;
   long long so = slot0;
   for (int pi = p0; pi < p1; pi++) {
     const SrcBox sb = d.sbox[part[pi]];
@@ -1267,6 +1271,8 @@ __global__ __launch_bounds__(NT) void k_p2p_sym(DevPlan d, const int* items, con
       // (l - s) mod 64, so the 64 lanes touch 64 different points and each
       // point receives its terms in step order (the wave's LDS operations
       // complete in issue order, so step s + 1 reads what step s wrote)
+      // waves holding none of the chunk's points (short leaves) add nothing
+      if (wact) {
       for (int c = 0; c < 3; c++) tw[wave][lane][c] = cd{0, 0};
       for (int st = 0; st < 64; st++) {
         const int j = (lane - st) & 63;
@@ -1284,10 +1290,11 @@ __global__ __launch_bounds__(NT) void k_p2p_sym(DevPlan d, const int* items, con
         tw[wave][j][1] = tw[wave][j][1] + (a * ji[1] + uy * bri);
         tw[wave][j][2] = tw[wave][j][2] + (a * ji[2] + uz * bri);
       }
+      }
       __syncthreads();
       if (tid < nb) {
         cd u[3] = {tw[0][tid][0], tw[0][tid][1], tw[0][tid][2]};
-        for (int w = 1; w < NT / 64; w++)
+        for (int w = 1; w < nwav; w++)
           for (int c = 0; c < 3; c++) u[c] = u[c] + tw[w][tid][c];
         cd* Yp = Ys + ((so + (s0 - sb.pt0) + tid) * n_rhs + r) * 3;
         for (int c = 0; c < 3; c++) Yp[c] = u[c];
