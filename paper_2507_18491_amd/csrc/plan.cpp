@@ -28,7 +28,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <atomic>
 #include <mutex>
+#include <thread>
 #include <unordered_map>
 
 std::string lm_fmt(const char* fmt, ...) {
@@ -571,14 +573,26 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
   std::vector<double> inst_S0;    // root size of each instance's lattice
 
   std::vector<double> s2t_rho_of;  // per instance: largest horizontal S2T pair distance, -1 if none
-  for (auto& g : geo) {
+  // every instance's trees first, on host threads: its sort, its depth
+  // (cost models) and its boxes depend on its own points alone; the
+  // records, lists and tables below are then built in instance order
+  struct Prep {
+    HTree S, T;
+    double Dgap = 0;
+    int depth_used = 0;
+    std::string err;
+  };
+  std::vector<Prep> preps(geo.size());
+  auto prepare = [&](size_t gi) {
+    const IGeom& g = geo[gi];
+    Prep& pr = preps[gi];
     const double S0 = g.S0, eps = g.eps, X0 = g.X0, Y0 = g.Y0;
     InstParams ip = g.ip;
-    int inst = (int)pl.inst.size();
     ip.p = ip.kind == 0 ? pl.pf : pl.p;
     ip.P = (ip.p + 1) * (ip.p + 1);
     int P = ip.P;
-    HTree S, T;
+    HTree& S = pr.S;
+    HTree& T = pr.T;
     S.x0 = T.x0 = X0;
     S.y0 = T.y0 = Y0;
     S.S0 = T.S0 = S0;
@@ -652,7 +666,7 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       }
       depth_used = D;
       build_tree(S, pos, ids, tags, [&](int l, int n, int, double) { return n > 0 && l < D; });
-      pl.free_depth_used.push_back(D);
+
     } else {
       // anchors on the two sides of the gap, moved outward to multiples of a
       // power-of-two fraction delta of S0 (at most S0 / 1024 and an eighth of
@@ -686,9 +700,12 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       int D1 = 0;
       while (S0 / (double)(1 << D1) > Dgap) D1++;
       if (D1 > prm.max_depth)
-        return lm_fmt("reaction component (%d,%d): points are too close to an interface "
-                      "(gap %.3e needs %d tree levels, limit %d)",
-                      ip.lt, ip.ls, Dgap, D1, prm.max_depth);
+      {
+        pr.err = lm_fmt("reaction component (%d,%d): points are too close to an interface "
+                        "(gap %.3e needs %d tree levels, limit %d)",
+                        ip.lt, ip.ls, Dgap, D1, prm.max_depth);
+        return;
+      }
       int Dmax = D1;
       if (prm.react_s2t && D1 >= 2) {
         // distance of each point from the gap plane of its tree
@@ -751,6 +768,37 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       build_tree(S, g.spos, g.sid, std::vector<int>(g.sid.size(), 0), rule);
       build_tree(T, g.tpos, g.tid, std::vector<int>(g.tid.size(), 1), rule);
     }
+    pr.Dgap = Dgap;
+    pr.depth_used = depth_used;
+  };
+  {
+    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::atomic<size_t> next_gi{0};
+    auto work = [&]() {
+      for (size_t gi = next_gi++; gi < geo.size(); gi = next_gi++) prepare(gi);
+    };
+    std::vector<std::thread> pool;
+    for (unsigned t = 1; t < nth && t < geo.size(); t++) pool.emplace_back(work);
+    work();
+    for (auto& th : pool) th.join();
+  }
+  for (size_t gi = 0; gi < geo.size(); gi++) {
+    const IGeom& g = geo[gi];
+    Prep& pr = preps[gi];
+    if (!pr.err.empty()) return pr.err;
+    const double S0 = g.S0;
+    (void)S0;
+    InstParams ip = g.ip;
+    int inst = (int)pl.inst.size();
+    ip.p = ip.kind == 0 ? pl.pf : pl.p;
+    ip.P = (ip.p + 1) * (ip.p + 1);
+    int P = ip.P;
+    HTree& S = pr.S;
+    HTree& T = pr.T;
+    bool free = ip.kind == 0;
+    double Dgap = pr.Dgap;
+    int depth_used = pr.depth_used;
+    if (free) pl.free_depth_used.push_back(depth_used);
     ip.Dgap = Dgap;
     (void)depth_used;
     HTree& TT = free ? S : T;  // target tree
