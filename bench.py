@@ -225,6 +225,29 @@ def coupled_dipole_solve(args, torch, inputs, lmfmm, n=1000000, n_rhs=1, tol=1e-
                                 "bytes": info["krylov_bytes"]}}
 
 
+def trees_roofline(st):
+    """The octrees' records keyed and radix-sorted on the device at build
+    time (HBM-bound): algorithmic bytes per record -- the key kernel reads
+    the position and the id and writes key, payload and tree (44 B); each of
+    the eight key passes reads the key for the histogram and moves the
+    16-byte record once (40 B), each tree pass the same plus the tree index
+    (44 B) -- over the device time of those kernels."""
+    recs, ms = st["tree_records"], st["tree_sort_ms"]
+    if recs <= 0 or ms <= 0:
+        return None
+    n_trees = st["n_free_inst"] + 2 * st["n_react_inst"]
+    tree_passes = 0
+    t = int(n_trees) - 1
+    while t > 0:
+        tree_passes += 1
+        t >>= 8
+    per_rec = 44.0 + 8 * 40.0 + tree_passes * 44.0
+    a = recs * per_rec / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "records": recs, "trees": n_trees, "device_ms": ms, "bytes_per_record": per_rec,
+            "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a / HBM_PEAK_GBS,
+            "plan_ms": st["t_plan_ms"]}
+
+
 def largest_config(args, torch, inputs, lmfmm, n=2000000, n_rhs=16):
     """The largest configuration: four layers (interfaces 0, -1, -2.5; k =
     1.0, 1.8, 2.4, 1.3), N = 2e6 points (half uniform, half in 20 Gaussian
@@ -319,9 +342,10 @@ def main():
     torch.cuda.synchronize()
     build_s = time.time() - t0
     st = fmm.stats()
-    print("built: %.2f s (plan %.0f ms, tables %.0f ms), m2l pairs free %d react %d, cases %d" % (
-        build_s, st["t_plan_ms"], st["t_tables_ms"], st["m2l_pairs_free"], st["m2l_pairs_react"],
-        st["n_cases"]), file=sys.stderr, flush=True)
+    print("built: %.2f s (plan %.0f ms with the octree sort %.1f ms on the device for %d records, tables %.0f ms), "
+          "m2l pairs free %d react %d, cases %d" % (
+              build_s, st["t_plan_ms"], st["tree_sort_ms"], st["tree_records"], st["t_tables_ms"],
+              st["m2l_pairs_free"], st["m2l_pairs_react"], st["n_cases"]), file=sys.stderr, flush=True)
     Jt = torch.tensor(J, device=dev)
     A = torch.empty((args.rhs, args.n, 3), dtype=torch.complex128, device=dev)
     for _ in range(args.warmup):
@@ -551,6 +575,7 @@ def main():
         "self_convergence_dense": selfconv,
         "build_s": build_s,
         "cold_targets_per_s": args.n * args.rhs / (build_s + wall / args.steps),
+        "trees": trees_roofline(st),
         "phase_ms_per_step": {a: b / max(1, ncalls) for a, b in phases.items()},
         "adjoint": None if adj_s is None else {
             "targets_per_s": args.n * args.rhs / adj_s, "ms_per_step": 1e3 * adj_s,

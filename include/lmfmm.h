@@ -30,7 +30,10 @@
  * negative code; lm_last_error() describes the last failure on a context.
  * On LM_EINVAL, LM_EDOMAIN and LM_ESTATE no output is touched.  Nothing
  * throws across the ABI.  One context must not be used from two host
- * threads at once; distinct contexts are independent.
+ * threads at once; distinct contexts are independent.  The evaluations of
+ * one context share its work buffers and the work-queue counters of its
+ * persistent launches, so they must not overlap on the device either: issue
+ * them on one stream, or order their streams.
  *
  * Ownership: the caller owns every array it passes.  Positions are host
  * arrays, copied by lm_build.  Currents and outputs are device arrays of
@@ -105,12 +108,17 @@ typedef struct {
                       /* panels on that piece (about 2e-9).  The expansions'       */
                       /* truncation error is not bounded a priori: it is set by p  */
                       /* (recorded errors per order: see the tests).                */
+  int host_trees;     /* 0 (default): lm_build keys and sorts the records of every */
+                      /* octree on the device (Morton keys, radix sort); 1: on the */
+                      /* host.  Both give the same plan (the boxes, lists and     */
+                      /* tables are built on the host from the sorted records).   */
 } lm_params;
 
 #define LM_M2L_VARIANTS 3
 
 /* Fills *prm with the defaults (p = 12, p_free = p, automatic depths, m2l_adapt = 1,
- * m2l_margin = 3, gamma1_panels = 4, react_s2t = 1, m2l_variant = -1, tol = 0). */
+ * m2l_margin = 3, gamma1_panels = 4, react_s2t = 1, m2l_variant = -1, tol = 0,
+ * host_trees = 0). */
 int lm_default_params(lm_params* prm);
 
 /* Creates a context bound to HIP device `hip_device`.  *out is owned by the
@@ -319,7 +327,13 @@ int lm_stats(const lm_ctx* ctx, double* out_host, int n);
                                      /* kernel (when the targets are the sources, one per */
                                      /* unordered pair of different leaves, and every     */
                                      /* ordered pair inside a leaf; else P2P_PAIRS)       */
-#define LM_STATS_COUNT 31
+#define LM_STAT_TREE_RECORDS 31      /* records of every octree (points of each tree) */
+#define LM_STAT_TREE_SORT_MS 32      /* device time of their keys and sort (0 when    */
+                                     /* sorted on the host)                           */
+#define LM_STAT_PLAN_DIGEST_HI 33    /* 64-bit hash of the plan (trees, lists, M2L    */
+#define LM_STAT_PLAN_DIGEST_LO 34    /* schedule, table cases, nodes), its two halves:*/
+                                     /* equal plans give equal values                 */
+#define LM_STATS_COUNT 35
 
 /* ---- iterative solve over the evaluation ---- */
 

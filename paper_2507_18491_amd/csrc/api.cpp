@@ -25,6 +25,9 @@ struct lm_ctx {
   bool layers_set = false;
   PlanParams prm;
   int m2l_variant = -1;       // M2L GEMM variant: -1 autotune per launch, else fixed
+  int host_trees = 0;         // 1: octree records sorted on the host
+  double tree_records = 0;    // records of every octree of the build
+  float tree_sort_ms = 0;     // device time of their keys and sort
   Plan plan;
   bool built = false;
   DevPlan d;
@@ -322,6 +325,7 @@ int lm_default_params(lm_params* prm) {
   prm->react_s2t = 1;
   prm->m2l_variant = -1;
   prm->tol = 0.0;
+  prm->host_trees = 0;
   return LM_OK;
 }
 
@@ -394,6 +398,7 @@ int lm_set_params(lm_ctx* ctx, const lm_params* p) {
   if (!(p->tol >= 0) || !std::isfinite(p->tol)) return fail(ctx, LM_EINVAL, "tol must be finite and >= 0");
   if (p->m2l_variant < -1 || p->m2l_variant >= LM_M2L_VARIANTS)
     return fail(ctx, LM_EINVAL, "m2l_variant must be -1 (autotune) or 0.." + std::to_string(LM_M2L_VARIANTS - 1));
+  if (p->host_trees != 0 && p->host_trees != 1) return fail(ctx, LM_EINVAL, "host_trees must be 0 or 1");
   PlanParams q;
   q.p = p->p;
   q.p_free = p->p_free;
@@ -409,6 +414,7 @@ int lm_set_params(lm_ctx* ctx, const lm_params* p) {
   q.tol = p->tol;
   ctx->prm = q;
   ctx->m2l_variant = p->m2l_variant;
+  ctx->host_trees = p->host_trees;
   if (ctx->built) {
     hipSetDevice(ctx->device);
     free_build(ctx);
@@ -468,16 +474,36 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
   free_build(ctx);
   if (lm_upload_leg_tables()) return fail(ctx, LM_EHIP, "cannot upload the Legendre coefficient tables");
   auto t0 = std::chrono::steady_clock::now();
-  std::string msg = lm_make_plan_multi(ctx->plan, med, ctx->prm, n_geom, soff, src_xyz, toff, tgt_xyz);
-  if (!msg.empty())
-    return fail(ctx, msg.compare(0, strlen(LM_PLAN_ACCURACY_PREFIX), LM_PLAN_ACCURACY_PREFIX) == 0 ? LM_EACCURACY
-                                                                                               : LM_EDOMAIN,
-                msg);
+  // the points on the device first: the octrees' records are keyed and
+  // sorted there
+  int rc;
+  {
+    std::vector<double> sx(src_xyz, src_xyz + 3 * n_src), tx(tgt_xyz, tgt_xyz + 3 * n_tgt);
+    if ((rc = upload(ctx, &ctx->d_src, sx))) return rc;
+    if ((rc = upload(ctx, &ctx->d_tgt, tx))) return rc;
+  }
+  ctx->tree_records = 0;
+  ctx->tree_sort_ms = 0;
+  TreeSorter dev_sort = [&](const std::vector<TreeJob>& jobs, const std::vector<TreeSeg>& segs,
+                            std::vector<uint64_t>& keys, std::vector<uint32_t>& pay) -> std::string {
+    std::string e = lm_device_tree_sort(jobs, segs, ctx->d_src, ctx->d_tgt, keys, pay, &ctx->tree_sort_ms, s);
+    ctx->tree_records = (double)keys.size();
+    return e;
+  };
+  std::string msg = lm_make_plan_multi(ctx->plan, med, ctx->prm, n_geom, soff, src_xyz, toff, tgt_xyz,
+                                       ctx->host_trees || n_src == 0 || n_tgt == 0 ? nullptr : &dev_sort);
+  if (!msg.empty()) {
+    int code = LM_EDOMAIN;
+    if (msg.compare(0, strlen(LM_PLAN_ACCURACY_PREFIX), LM_PLAN_ACCURACY_PREFIX) == 0)
+      code = LM_EACCURACY;
+    else if (msg.compare(0, 10, "tree sort:") == 0)
+      code = msg.find("allocation") != std::string::npos ? LM_ENOMEM : LM_EHIP;
+    return fail(ctx, code, msg);
+  }
   auto t1 = std::chrono::steady_clock::now();
   Plan& pl = ctx->plan;
   ctx->pmax = std::max(pl.p, pl.pf);
   DevPlan& d = ctx->d;
-  int rc;
   {
     // direct reaction near field: J0..J2 on Gamma_1 by their power series
     // where |k_rho| rho <= 7.5 for every pair of the component; the series
@@ -533,9 +559,7 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
   if ((rc = upload(ctx, &d.Ccoef0, pl.Ccoef0))) return rc;
   if ((rc = upload(ctx, &d.cases, pl.cases))) return rc;
   if ((rc = upload(ctx, &d.trans, pl.trans))) return rc;
-  std::vector<double> sx(src_xyz, src_xyz + 3 * n_src), tx(tgt_xyz, tgt_xyz + 3 * n_tgt);
-  if ((rc = upload(ctx, &ctx->d_src, sx))) return rc;
-  if ((rc = upload(ctx, &ctx->d_tgt, tx))) return rc;
+  if ((rc = upload(ctx, &d.wq, std::vector<int>(LM_WQ_COUNT, 0)))) return rc;
   {
     // leaves of low-order instances (reaction components, typically few points
     // each) and of high-order ones are launched separately, each with LDS
@@ -786,6 +810,8 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
         if (slots > 2000000000LL) ok = false;
       }
     if (ok && !items6.empty()) {
+      // the items stay in box order (neighbouring items share partner
+      // leaves in the cache; longest first measured no faster)
       // per point: its slots in item order
       std::vector<int> cnt(pl.n_tgt + 1, 0);
       for (size_t it = 0; it < items6.size(); it += 6)
@@ -1725,6 +1751,35 @@ int lm_stats(const lm_ctx* ctx, double* out, int n) {
   for (int x : pl.free_depth_used) fd = std::max(fd, (double)x);
   v[LM_STAT_FREE_DEPTH] = fd;
   v[LM_STAT_S2T_PAIRS] = (double)pl.n_s2t_pairs;
+  v[LM_STAT_TREE_RECORDS] = ctx->tree_records;
+  v[LM_STAT_TREE_SORT_MS] = ctx->tree_sort_ms;
+  if (n > LM_STAT_PLAN_DIGEST_HI) {
+    // FNV-style hash over 8-byte words of every array of the plan
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t bytes) {
+      const unsigned char* c = (const unsigned char*)p;
+      h = (h ^ (uint64_t)bytes) * 1099511628211ull;
+      size_t i = 0;
+      for (; i + 8 <= bytes; i += 8) {
+        uint64_t w;
+        memcpy(&w, c + i, 8);
+        h = (h ^ w) * 1099511628211ull;
+      }
+      for (; i < bytes; i++) h = (h ^ c[i]) * 1099511628211ull;
+    };
+    auto vec = [&](const auto& x) { mix(x.data(), x.size() * sizeof(x[0])); };
+    auto vecs = [&](const auto& xs) {
+      for (const auto& x : xs) vec(x);
+    };
+    vec(pl.inst), vec(pl.src_perm), vec(pl.tgt_perm), vec(pl.sbox), vec(pl.tbox), vec(pl.sbox_m2m), vec(pl.tbox_l2l);
+    vecs(pl.m2m_parents), vecs(pl.l2l_children), vec(pl.p2m_leaves), vecs(pl.l2p_leaves), vecs(pl.p2p_tboxes);
+    vec(pl.p2p_list), vec(pl.cls), vec(pl.offs), vec(pl.cls_tgt), vec(pl.cls_srcof), vec(pl.cls_srcof0);
+    vec(pl.blocks), vec(pl.bt_tbox), vec(pl.bt_ptr), vec(pl.bt_pairs), vec(pl.pair_src), vec(pl.offr), vec(pl.bt_blk);
+    vec(pl.pair_P), vec(pl.pair_phi), vec(pl.s2t_items), vec(pl.trans), vec(pl.cases), vec(pl.node_kr);
+    vec(pl.node_w), vec(pl.node_inst), vec(pl.Bcoef), vec(pl.Ccoef), vec(pl.Ccoef0), vec(pl.free_depth_used);
+    v[LM_STAT_PLAN_DIGEST_HI] = (double)(h >> 32);
+    v[LM_STAT_PLAN_DIGEST_LO] = (double)(h & 0xffffffffull);
+  }
   int m = n < LM_STATS_COUNT ? n : LM_STATS_COUNT;
   memcpy(out, v, m * sizeof(double));
   return LM_OK;

@@ -11,7 +11,9 @@
 // channels in the spin basis (x + i y, x - i y, z).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "bessel_pq.h"
@@ -103,6 +105,68 @@ void launch_fill(cd* p, long long n, hipStream_t s) {
   long long nb = (n + NT - 1) / NT;
   if (nb > 65536) nb = 65536;
   hipLaunchKernelGGL(k_fill, dim3((unsigned)nb), dim3(NT), 0, s, p, n);
+}
+
+// ------------------------------------------------------------------ work queues
+// Persistent launches of the passes whose work items differ widely in cost
+// (near field, direct reaction pairs): as many blocks as the device keeps
+// resident, each taking the next item index from a counter in device memory
+// until the items run out (items are stored longest first, so the queue
+// hands out the long ones first, across every geometry and component of the
+// plan).  q[0] hands out indices, q[1] counts the blocks that have left; the
+// last block to leave sets both back to zero for the next launch on the
+// stream.  The counters start at zero (cleared when the plan is built).
+// Launches that share a queue must not overlap in time (they run in stream
+// order).  Every item writes outputs of its own, so the order in which the
+// blocks take them does not change any result.
+struct WorkQueue {
+  int* q;  // the counter pair
+  int* s;  // an LDS slot of the block
+  // the block's next index, once every thread is done with the previous
+  // item (taking it ahead, while an item runs, measured slower)
+  __device__ int next() {
+    __syncthreads();
+    if (threadIdx.x == 0) *s = atomicAdd(q, 1);
+    __syncthreads();
+    return *s;
+  }
+  __device__ void leave() {
+    if (threadIdx.x == 0 && atomicAdd(q + 1, 1) == (int)(gridDim.x * gridDim.y * gridDim.z) - 1) {
+      atomicExch(q, 0);
+      atomicExch(q + 1, 0);
+    }
+  }
+};
+// Blocks of a persistent launch: the kernel's resident blocks per compute
+// unit times the compute units, at most `work`.  Cached per (device,
+// kernel) in a fixed table (nothing allocated).
+static int persistent_grid(const void* f, int nthreads, size_t shm, long long work) {
+  struct Ent {
+    int dev;
+    const void* f;
+    int nthreads;
+    int blocks;
+  };
+  static Ent cache[64];
+  static int n_cache = 0;
+  static std::mutex mu;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  int blocks = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (int i = 0; i < n_cache; i++)
+      if (cache[i].dev == dev && cache[i].f == f && cache[i].nthreads == nthreads) blocks = cache[i].blocks;
+  }
+  if (blocks <= 0) {
+    int ncu = 0, per = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0) ncu = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, nthreads, shm) != hipSuccess || per <= 0) per = 1;
+    blocks = ncu * per;
+    std::lock_guard<std::mutex> lk(mu);
+    if (n_cache < 64) cache[n_cache++] = Ent{dev, f, nthreads, blocks};
+  }
+  return (int)std::min<long long>(blocks, work);
 }
 
 // ------------------------------------------------------------------ P2M
@@ -1062,22 +1126,27 @@ void launch_l2p(const DevPlan& d, const int* leaves, int n, int kind, const doub
 // sources in adjacent leaves, coincident points skipped (paper Sec. 2 and the
 // layered sums of Sec. 3.3)
 template <int RC, bool RED>
-__global__ __launch_bounds__(NT) void k_p2p(DevPlan d, const int* tboxes, const double* sxyz, const cd* J,
-                                            long long n_src, const double* txyz, long long n_tgt, int n_rhs,
-                                            cd* A) {
+__global__ __launch_bounds__(NT) void k_p2p(DevPlan d, const int* tboxes, int n_items, const double* sxyz,
+                                            const cd* J, long long n_src, const double* txyz, long long n_tgt,
+                                            int n_rhs, cd* A) {
   __shared__ double sp[NT][3];
   __shared__ cd sj[NT][RC][3];
+  const int ny = (n_rhs + RC - 1) / RC, total = n_items * ny;
+  __shared__ int wq_s;
+  WorkQueue wq{d.wq + LM_WQ_P2P, &wq_s};
+  for (int wi = wq.next(); wi < total; wi = wq.next()) {
+  const int bx = wi / ny, by = wi - bx * ny;
   // work item: (target leaf, chunk of NT targets); the wavenumber is that of
   // the leaf's instance (its layer)
-  int b = tboxes[2 * blockIdx.x];
+  int b = tboxes[2 * bx];
   TgtBox tb = d.tbox[b];
   const double k = d.inst[__builtin_amdgcn_readfirstlane(tb.inst)].kt;
-  int r0 = blockIdx.y * RC, nr = min(RC, n_rhs - r0);
+  int r0 = by * RC, nr = min(RC, n_rhs - r0);
   int tid = threadIdx.x;
   const double inv4pi = 0.079577471545947667884;
   const double invk = 1.0 / k;
   {
-    int t0 = tb.pt0 + tboxes[2 * blockIdx.x + 1] * NT;
+    int t0 = tb.pt0 + tboxes[2 * bx + 1] * NT;
     int ti = t0 + tid;
     bool act = ti < tb.pt1;
     int id = act ? d.tgt_perm[ti] : 0;
@@ -1134,25 +1203,31 @@ __global__ __launch_bounds__(NT) void k_p2p(DevPlan d, const int* tboxes, const 
         for (int c = 0; c < 3; c++) Ap[c] = Ap[c] + acc[rr][c];
       }
   }
+  }
+  wq.leave();
 }
 void launch_p2p(const DevPlan& d, const int* tboxes, int n, const double* sxyz, const cd* J, long long n_src,
                 const double* txyz, long long n_tgt, int n_rhs, cd* A, bool red, hipStream_t s) {
   if (n <= 0) return;
+#define LM_P2P_GO(RC, RED)                                                                                     \
+  do {                                                                                                         \
+    const void* f = (const void*)k_p2p<RC, RED>;                                                               \
+    const int g = persistent_grid(f, NT, 0, (long long)n * ((n_rhs + RC - 1) / RC));                           \
+    hipLaunchKernelGGL((k_p2p<RC, RED>), dim3(g), dim3(NT), 0, s, d, tboxes, n, sxyz, J, n_src, txyz, n_tgt,   \
+                       n_rhs, A);                                                                              \
+  } while (0)
   if (n_rhs == 1) {
     if (red)
-      hipLaunchKernelGGL((k_p2p<1, true>), dim3(n, n_rhs), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src, txyz, n_tgt,
-                         n_rhs, A);
+      LM_P2P_GO(1, true);
     else
-      hipLaunchKernelGGL((k_p2p<1, false>), dim3(n, n_rhs), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src, txyz, n_tgt,
-                         n_rhs, A);
+      LM_P2P_GO(1, false);
   } else {
     if (red)
-      hipLaunchKernelGGL((k_p2p<4, true>), dim3(n, (n_rhs + 3) / 4), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src, txyz,
-                         n_tgt, n_rhs, A);
+      LM_P2P_GO(4, true);
     else
-      hipLaunchKernelGGL((k_p2p<4, false>), dim3(n, (n_rhs + 3) / 4), dim3(NT), 0, s, d, tboxes, sxyz, J, n_src,
-                         txyz, n_tgt, n_rhs, A);
+      LM_P2P_GO(4, false);
   }
+#undef LM_P2P_GO
 }
 
 // Symmetric free-space near field, for builds whose targets are the
@@ -1171,15 +1246,21 @@ void launch_p2p(const DevPlan& d, const int* tboxes, int n, const double* sxyz, 
 // the item's own sums went into A.  Deterministic, no atomics; one
 // right-hand side per block (blockIdx.y).
 template <bool RED>
-__global__ __launch_bounds__(NT) void k_p2p_sym(DevPlan d, const int* items, const int* part, const double* xyz,
-                                                const cd* J, long long n_pts, int n_rhs, cd* A, cd* Ys) {
+__global__ __launch_bounds__(NT, RED ? 3 : 2) void k_p2p_sym(DevPlan d, const int* items, int n_items, const int* part,
+                                                const double* xyz, const cd* J, long long n_pts, int n_rhs, cd* A,
+                                                cd* Ys) {
   __shared__ double sp[NT][3];
   __shared__ cd sj[NT][3];
   __shared__ double qx[64], qy[64], qz[64], qj[6][64];  // one block of 64 partner points
   __shared__ cd tw[NT / 64][64][3];                    // per wave: sums for the partner points
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int total = n_items * n_rhs;
+  __shared__ int wq_s;
+  WorkQueue wq{d.wq + LM_WQ_P2PS, &wq_s};
+  for (int wi = wq.next(); wi < total; wi = wq.next()) {
+  const int bx = wi / n_rhs;
   // item: (target leaf, chunk, first output slot, partner range, own source box)
-  const int* it = items + 6 * blockIdx.x;
+  const int* it = items + 6 * bx;
   const int b = __builtin_amdgcn_readfirstlane(it[0]);
   const int chunk = __builtin_amdgcn_readfirstlane(it[1]);
   const long long slot0 = __builtin_amdgcn_readfirstlane(it[2]);
@@ -1187,7 +1268,7 @@ __global__ __launch_bounds__(NT) void k_p2p_sym(DevPlan d, const int* items, con
   const int self = __builtin_amdgcn_readfirstlane(it[5]);
   const TgtBox tb = d.tbox[b];
   const double k = d.inst[__builtin_amdgcn_readfirstlane(tb.inst)].kt;
-  const int r = blockIdx.y;
+  const int r = wi - bx * n_rhs;
   const cd* Jr = J + (long long)r * n_pts * 3;
   const double inv4pi = 0.079577471545947667884;
   const double invk = 1.0 / k;
@@ -1306,14 +1387,297 @@ __global__ __launch_bounds__(NT) void k_p2p_sym(DevPlan d, const int* items, con
     cd* Ap = A + ((long long)r * n_pts + id) * 3;
     for (int c = 0; c < 3; c++) Ap[c] = Ap[c] + acc[c];
   }
+  }
+  wq.leave();
 }
 void launch_p2p_sym(const DevPlan& d, const int* items, int n, const int* part, const double* xyz, const cd* J,
                     long long n_pts, int n_rhs, cd* A, cd* Ys, bool red, hipStream_t s) {
   if (n <= 0) return;
+  const void* f = red ? (const void*)k_p2p_sym<true> : (const void*)k_p2p_sym<false>;
+  const int g = persistent_grid(f, NT, 0, (long long)n * n_rhs);
   if (red)
-    hipLaunchKernelGGL(k_p2p_sym<true>, dim3(n, n_rhs), dim3(NT), 0, s, d, items, part, xyz, J, n_pts, n_rhs, A, Ys);
+    hipLaunchKernelGGL(k_p2p_sym<true>, dim3(g), dim3(NT), 0, s, d, items, n, part, xyz, J, n_pts, n_rhs, A, Ys);
   else
-    hipLaunchKernelGGL(k_p2p_sym<false>, dim3(n, n_rhs), dim3(NT), 0, s, d, items, part, xyz, J, n_pts, n_rhs, A, Ys);
+    hipLaunchKernelGGL(k_p2p_sym<false>, dim3(g), dim3(NT), 0, s, d, items, n, part, xyz, J, n_pts, n_rhs, A, Ys);
+}
+
+// ------------------------------------------------------------------ octrees
+// The records of every octree of a plan (paper Sec. 3.3: one tree per
+// layer's free-space part and per reaction component, over images and
+// effective locations), keyed and sorted on the device in one batch: a
+// record is (Morton key of its lattice cell, point id | tag << 31, tree);
+// an LSD radix sort with 8-bit digits orders them by key (eight passes)
+// and then by tree (one pass per byte of the tree count), every pass stable,
+// so that each tree's records end up contiguous, in key order, equal keys
+// in input order -- the order of the host planner's own sort.
+
+// Morton code of a lattice cell: bits of ux, uy, uz interleaved from the
+// lowest (x at bit 3b, y at 3b + 1, z at 3b + 2).
+__device__ __forceinline__ uint64_t tree_spread3(uint64_t v) {
+  v &= 0xFFFFF;
+  v = (v | (v << 32)) & 0x1F00000000FFFFull;
+  v = (v | (v << 16)) & 0x1F0000FF0000FFull;
+  v = (v | (v << 8)) & 0x100F00F00F00F00Full;
+  v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+struct TreeSegDev {
+  long long r0;   // first record of the segment
+  long long ids;  // first id of the segment in the uploaded id lists
+  int n, tgt, tag, tree;
+  double za, zb;
+};
+struct TreeLatDev {
+  double x0, y0, z0, inv;  // inv = 2^DK / S0
+};
+__global__ void k_tree_keys(const TreeSegDev* segs, int nseg, const TreeLatDev* lat, const int* ids,
+                            const double* sxyz, const double* txyz, long long n, uint64_t* key, uint32_t* pay,
+                            int* tree) {
+  const long long st = (long long)gridDim.x * blockDim.x;
+  for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += st) {
+    // the segment holding record r (segments in record order)
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (segs[mid].r0 <= r)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const TreeSegDev sg = segs[lo];
+    const TreeLatDev L = lat[sg.tree];
+    const int id = ids[sg.ids + (r - sg.r0)];
+    const double* x = (sg.tgt ? txyz : sxyz) + 3 * (long long)id;
+    // the same operations, in the same order and rounding, as the host's
+    // (a product and a sum, not fused)
+    const double z = __dadd_rn(__dmul_rn(sg.za, x[2]), sg.zb);
+    const long long mx = (1LL << LM_TREE_DK) - 1;
+    long long u[3] = {(long long)floor((x[0] - L.x0) * L.inv), (long long)floor((x[1] - L.y0) * L.inv),
+                      (long long)floor((z - L.z0) * L.inv)};
+    for (int a = 0; a < 3; a++) u[a] = u[a] < 0 ? 0 : (u[a] > mx ? mx : u[a]);
+    key[r] = tree_spread3((uint64_t)u[0]) | (tree_spread3((uint64_t)u[1]) << 1) | (tree_spread3((uint64_t)u[2]) << 2);
+    pay[r] = (uint32_t)id | ((uint32_t)sg.tag << 31);
+    tree[r] = sg.tree;
+  }
+}
+
+#define RS_NT 256                 // threads per radix block
+#define RS_ITEMS 8                // records per thread
+#define RS_TILE (RS_NT * RS_ITEMS)  // records per block
+__device__ __forceinline__ int rs_digit(int pass, uint64_t key, int tree) {
+  return pass < 8 ? (int)((key >> (8 * pass)) & 255) : ((tree >> (8 * (pass - 8))) & 255);
+}
+// per block: how many of its records hold each digit, at cnt[d * nblk + b]
+__global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t* key, const int* tree, long long n, int pass,
+                                                   int* cnt, int nblk) {
+  __shared__ int h[256];
+  const int tid = threadIdx.x;
+  h[tid] = 0;
+  __syncthreads();
+  const long long t0 = (long long)blockIdx.x * RS_TILE;
+  for (int k = 0; k < RS_ITEMS; k++) {
+    const long long r = t0 + k * RS_NT + tid;
+    if (r < n) atomicAdd(&h[rs_digit(pass, key[r], tree[r])], 1);
+  }
+  __syncthreads();
+  cnt[(long long)tid * nblk + blockIdx.x] = h[tid];
+}
+// stable scatter: a record goes to the start of its digit in its block
+// (exclusive scan of cnt) plus the number of earlier records of the block
+// with the same digit.  Records are taken in RS_ITEMS rounds of RS_NT in
+// index order; in a round, the lanes of a wave with equal digits find each
+// other by eight ballots (one per digit bit), the waves' counts per digit
+// are added in wave order, and a running count per digit carries over the
+// rounds.
+__global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* key, const uint32_t* pay, const int* tree,
+                                                      uint64_t* key2, uint32_t* pay2, int* tree2, long long n,
+                                                      int pass, const int* off, int nblk) {
+  __shared__ int base[256], run[256], wc[RS_NT / 64][256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  base[tid] = off[(long long)tid * nblk + blockIdx.x];
+  run[tid] = 0;
+  const long long t0 = (long long)blockIdx.x * RS_TILE;
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  for (int k = 0; k < RS_ITEMS; k++) {
+    for (int w = 0; w < RS_NT / 64; w++) wc[w][tid] = 0;
+    __syncthreads();
+    const long long r = t0 + k * RS_NT + tid;
+    const bool ok = r < n;
+    uint64_t kv = 0;
+    uint32_t pv = 0;
+    int tv = 0, d = 0;
+    if (ok) {
+      kv = key[r];
+      pv = pay[r];
+      tv = tree[r];
+      d = rs_digit(pass, kv, tv);
+    }
+    uint64_t peers = __ballot(ok);
+    for (int b = 0; b < 8; b++) {
+      const bool bit = (d >> b) & 1;
+      const uint64_t m = __ballot(ok && bit);
+      peers &= bit ? m : ~m;
+    }
+    const int rank = __popcll(peers & below);
+    if (ok && rank == 0) wc[wave][d] = __popcll(peers);
+    __syncthreads();
+    if (ok) {
+      int pos = base[d] + run[d] + rank;
+      for (int w = 0; w < wave; w++) pos += wc[w][d];
+      key2[pos] = kv;
+      pay2[pos] = pv;
+      tree2[pos] = tv;
+    }
+    __syncthreads();
+    int add = 0;
+    for (int w = 0; w < RS_NT / 64; w++) add += wc[w][tid];
+    run[tid] += add;
+  }
+}
+// exclusive scan of a[0..m) in tiles of RS_TILE (each tile's total to sums)
+__global__ __launch_bounds__(RS_NT) void k_scan_tiles(int* a, long long m, int* sums) {
+  __shared__ int sh[RS_NT];
+  const int tid = threadIdx.x;
+  const long long e0 = (long long)blockIdx.x * RS_TILE + (long long)tid * RS_ITEMS;
+  int v[RS_ITEMS], tot = 0;
+  for (int k = 0; k < RS_ITEMS; k++) {
+    v[k] = e0 + k < m ? a[e0 + k] : 0;
+    tot += v[k];
+  }
+  sh[tid] = tot;
+  __syncthreads();
+  for (int o = 1; o < RS_NT; o <<= 1) {
+    const int x = tid >= o ? sh[tid - o] : 0;
+    __syncthreads();
+    sh[tid] += x;
+    __syncthreads();
+  }
+  int acc = sh[tid] - tot;  // exclusive prefix of this thread's items
+  for (int k = 0; k < RS_ITEMS; k++) {
+    if (e0 + k < m) a[e0 + k] = acc;
+    acc += v[k];
+  }
+  if (tid == RS_NT - 1) sums[blockIdx.x] = sh[tid];
+}
+__global__ void k_scan_add(int* a, long long m, const int* sums) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < m) a[e] += sums[e / RS_TILE];
+}
+// exclusive scan of a[0..m) on the device; scratch holds the tile sums of
+// every level (at least m / RS_TILE + 2 entries per level, levels in turn)
+static void scan_excl(int* a, long long m, int* scratch, hipStream_t s) {
+  const long long nt = (m + RS_TILE - 1) / RS_TILE;
+  if (nt <= 0) return;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(RS_NT), 0, s, a, m, scratch);
+  if (nt > 1) {
+    scan_excl(scratch, nt, scratch + nt, s);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a, m, (const int*)scratch);
+  }
+}
+
+std::string lm_device_tree_sort(const std::vector<TreeJob>& jobs, const std::vector<TreeSeg>& segs,
+                                const double* d_src, const double* d_tgt, std::vector<uint64_t>& keys,
+                                std::vector<uint32_t>& pay, float* ms, hipStream_t s) {
+  // segments in record order; each distinct host id list uploaded once
+  std::vector<TreeSegDev> sd;
+  std::vector<TreeLatDev> ld;
+  std::vector<int> ids;
+  std::vector<std::pair<const int*, long long>> seen;  // (list, its offset in ids)
+  long long n = 0;
+  for (size_t t = 0; t < jobs.size(); t++) {
+    const TreeJob& J = jobs[t];
+    ld.push_back(TreeLatDev{J.x0, J.y0, J.z0, (double)(1 << LM_TREE_DK) / J.S0});
+    for (int q = 0; q < J.nseg; q++) {
+      const TreeSeg& g = segs[J.seg0 + q];
+      if (g.n <= 0) continue;
+      long long io = -1;
+      for (auto& e : seen)
+        if (e.first == g.ids) io = e.second;
+      if (io < 0) {
+        io = (long long)ids.size();
+        seen.push_back({g.ids, io});
+        ids.insert(ids.end(), g.ids, g.ids + g.n);
+      }
+      sd.push_back(TreeSegDev{n, io, g.n, g.tgt, g.tag, (int)t, g.za, g.zb});
+      n += g.n;
+    }
+  }
+  keys.assign((size_t)n, 0);
+  pay.assign((size_t)n, 0);
+  if (ms) *ms = 0;
+  if (n == 0) return "";
+  if (n > 0x7fffffffLL) return "tree sort: too many records";
+  const int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
+  const long long m = 256LL * nblk;
+  long long nscr = 0;
+  for (long long mm = m; mm > 1; mm = (mm + RS_TILE - 1) / RS_TILE) nscr += (mm + RS_TILE - 1) / RS_TILE + 2;
+  std::vector<void*> bufs;
+  bool alloc_ok = true;
+  auto dmal = [&](size_t bytes) -> void* {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+      alloc_ok = false;
+      return nullptr;
+    }
+    bufs.push_back(p);
+    return p;
+  };
+  auto done = [&](const std::string& e) {
+    for (void* p : bufs) (void)hipFree(p);
+    return e;
+  };
+  TreeSegDev* d_sd = (TreeSegDev*)dmal(sd.size() * sizeof(TreeSegDev));
+  TreeLatDev* d_ld = (TreeLatDev*)dmal(ld.size() * sizeof(TreeLatDev));
+  int* d_ids = (int*)dmal(ids.size() * sizeof(int));
+  uint64_t* k0 = (uint64_t*)dmal((size_t)n * 8);
+  uint64_t* k1 = (uint64_t*)dmal((size_t)n * 8);
+  uint32_t* p0 = (uint32_t*)dmal((size_t)n * 4);
+  uint32_t* p1 = (uint32_t*)dmal((size_t)n * 4);
+  int* t0 = (int*)dmal((size_t)n * 4);
+  int* t1 = (int*)dmal((size_t)n * 4);
+  int* cnt = (int*)dmal((size_t)m * 4);
+  int* scr = (int*)dmal((size_t)(nscr + 2) * 4);
+  if (!alloc_ok) return done("tree sort: device allocation failed");
+  if (hipMemcpy(d_sd, sd.data(), sd.size() * sizeof(TreeSegDev), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(d_ld, ld.data(), ld.size() * sizeof(TreeLatDev), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(d_ids, ids.data(), ids.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    return done("tree sort: upload failed");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ms) {
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    (void)hipEventRecord(e0, s);
+  }
+  const long long gk = std::min<long long>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_tree_keys, dim3((unsigned)gk), dim3(256), 0, s, (const TreeSegDev*)d_sd, (int)sd.size(),
+                     (const TreeLatDev*)d_ld, (const int*)d_ids, d_src, d_tgt, n, k0, p0, t0);
+  int npass = 8;
+  for (size_t nt = jobs.size() - 1; nt > 0; nt >>= 8) npass++;
+  for (int pass = 0; pass < npass; pass++) {
+    hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(RS_NT), 0, s, (const uint64_t*)k0, (const int*)t0, n, pass, cnt,
+                       nblk);
+    scan_excl(cnt, m, scr, s);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(RS_NT), 0, s, (const uint64_t*)k0, (const uint32_t*)p0,
+                       (const int*)t0, k1, p1, t1, n, pass, (const int*)cnt, nblk);
+    std::swap(k0, k1);
+    std::swap(p0, p1);
+    std::swap(t0, t1);
+  }
+  if (ms) {
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    (void)hipEventElapsedTime(ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return done(std::string("tree sort: ") + hipGetErrorString(err));
+  if (hipMemcpyAsync(keys.data(), k0, (size_t)n * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(pay.data(), p0, (size_t)n * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return done("tree sort: download failed");
+  return done("");
 }
 
 // ------------------------------------------------------------------ self-test
@@ -1866,7 +2230,7 @@ void launch_p2p_curl(const DevPlan& d, const int* tboxes, int n, const double* s
 // J6..J9 form, with the node densities FH in the same five slots):
 //   out+ as above, out- negated, out_z = W(-1,s4) u+/2 - W(1,s4) u-/2.
 template <bool SMALLZ, int RS, bool HF>
-__global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md, const int* items,
+__global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md, const int* items, int n_items,
                                                                      const int* tlist, const int* slist,
                                                                      const double* sxyz, const cd* J,
                                                                      long long n_src, const double* txyz,
@@ -1876,8 +2240,13 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
   __shared__ cd res[LM_S2T_CHUNK][RS][3];  // per pair of the round and rhs: out+, out-, out_z
   __shared__ cd nk[LM_S2T_CHUNK][10];     // node chunk: kr, w, kz_t, kz_s, F_1..F_5, 1 / kr (tail)
   const int tid = threadIdx.x;
+  const int ny = (n_rhs + RS - 1) / RS, total = n_items * ny;
+  __shared__ int wq_s;
+  WorkQueue wq{d.wq + LM_WQ_S2T, &wq_s};
+  for (int wi = wq.next(); wi < total; wi = wq.next()) {
+  const int bx = wi / ny, by = wi - bx * ny;
   // work item, component and node range are uniform over the block
-  const int* it6 = items + 6 * blockIdx.x;
+  const int* it6 = items + 6 * bx;
   const int b = __builtin_amdgcn_readfirstlane(it6[0]);
   const int chunk = __builtin_amdgcn_readfirstlane(it6[1]);
   const long long slot0 = __builtin_amdgcn_readfirstlane(it6[2]);
@@ -1886,7 +2255,7 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
   const int ns = __builtin_amdgcn_readfirstlane(it6[5]);
   const TgtBox tb = d.tbox[b];
   const InstParams ip = d.inst[__builtin_amdgcn_readfirstlane(tb.inst)];
-  const int r0 = blockIdx.y * RS, nr = min(RS, n_rhs - r0);
+  const int r0 = by * RS, nr = min(RS, n_rhs - r0);
   const int t0 = tb.pt0 + chunk * LM_S2T_CHUNK;
   const int nt = min(LM_S2T_CHUNK, tb.pt1 - t0);
   const int n0 = __builtin_amdgcn_readfirstlane(ip.s2t0), nn = __builtin_amdgcn_readfirstlane(ip.s2tn);
@@ -2053,6 +2422,8 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
       Yp[2] = cd{f * oz[rr].x, f * oz[rr].y};
     }
   }
+  }
+  wq.leave();
 }
 
 // A[r][pt][c] += the point's direct-pair slots in their fixed order (the
@@ -2331,9 +2702,13 @@ void launch_s2t(const DevPlan& d, MediumDev md, const int* items, const int* tli
                 const double* sxyz, const cd* J, long long n_src, const double* txyz, long long n_tgt, int n_rhs,
                 double a, bool smallz, cd* Ys, hipStream_t s, bool hfield) {
   if (n <= 0) return;
-#define LM_S2T_GO(SZ, RS, H)                                                                                   \
-  hipLaunchKernelGGL((k_s2t<SZ, RS, H>), dim3(n, (n_rhs + RS - 1) / RS), dim3(LM_S2T_CHUNK), 0, s, d, md, items, \
-                     tlist, slist, sxyz, J, n_src, txyz, n_tgt, n_rhs, a, Ys)
+#define LM_S2T_GO(SZ, RS, H)                                                                                 \
+  do {                                                                                                       \
+    const int g = persistent_grid((const void*)k_s2t<SZ, RS, H>, LM_S2T_CHUNK, 0,                            \
+                                  (long long)n * ((n_rhs + RS - 1) / RS));                                   \
+    hipLaunchKernelGGL((k_s2t<SZ, RS, H>), dim3(g), dim3(LM_S2T_CHUNK), 0, s, d, md, items, n, tlist, slist, \
+                       sxyz, J, n_src, txyz, n_tgt, n_rhs, a, Ys);                                           \
+  } while (0)
   if (hfield) {
     if (n_rhs == 1) {
       if (smallz)

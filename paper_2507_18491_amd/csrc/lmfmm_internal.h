@@ -18,6 +18,29 @@
 #define LM_S2T_DIGITS 28.0 // the S2T tail stops where e^{-k (t + u)} < e^{-28}
 #define LM_S2T_SEG 32      // near boxes per source segment of one S2T work item
 
+// Octree records sorted outside the host planner (lm_build sorts them on
+// the device).  Tree t holds the points of its segments in segment order:
+// a segment lists the ids of source (tgt = 0) or target (tgt = 1) points,
+// with tag `tag`, whose positions in the tree's frame are (x, y, za z + zb).
+// A record's key is the Morton code of its cell in the depth-LM_TREE_DK
+// lattice of cells of size S0 / 2^LM_TREE_DK from (x0, y0, z0) (the cell
+// index floor((x - x0) 2^LM_TREE_DK / S0), clamped to the lattice, per axis;
+// bits interleaved x, y, z from the lowest).  The sorted output holds every
+// tree's records in tree order, each tree's by key with equal keys in input
+// order: the key and id | tag << 31.
+#define LM_TREE_DK 20
+struct TreeSeg {
+  const int* ids;  // host array of point ids
+  int n;
+  int tgt;         // 0: source points, 1: target points
+  int tag;         // 0 or 1
+  double za, zb;   // z in the tree's frame: za z + zb
+};
+struct TreeJob {
+  double x0, y0, z0, S0;
+  int seg0, nseg;  // segments of the tree
+};
+
 // Reaction M2L in the mirror-adapted basis: the reaction M2L tensor
 // commutes with the mirror that swaps the +/- channels and takes m to -m
 // (with the sign (-1)^m), so it acts on the even and the odd part of a

@@ -26,9 +26,11 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <atomic>
+#include <functional>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -241,7 +243,7 @@ int lm_enumerate_components(const Medium& med, std::vector<InstParams>& out) {
 
 // ------------------------------------------------------------------ trees
 
-static const int DK = 20;  // key depth
+static const int DK = LM_TREE_DK;  // key depth
 
 static inline uint64_t spread3(uint64_t v) {
   v &= 0xFFFFF;
@@ -294,11 +296,12 @@ struct HTree {
   }
 };
 
-// Build an octree over tagged points (positions pos[3*i]).  split(level, n,
-// j, S) decides whether a box is refined.
-template <class Split>
-static void build_tree(HTree& T, const std::vector<double>& pos, const std::vector<int>& ids,
-                       const std::vector<int>& tags, Split split) {
+// An octree over tagged points (positions pos[3*i]): first the records
+// sorted by Morton key (tree_sort, or a sorter outside the planner), then the
+// boxes (tree_boxes), where split(level, n, j, S) decides whether a box is
+// refined.
+static void tree_sort(HTree& T, const std::vector<double>& pos, const std::vector<int>& ids,
+                      const std::vector<int>& tags) {
   size_t n = ids.size();
   T.recs.resize(n);
   double inv = (double)(1 << DK) / T.S0;
@@ -316,6 +319,10 @@ static void build_tree(HTree& T, const std::vector<double>& pos, const std::vect
     T.recs[i].tag = tags[i];
   }
   radix_sort(T.recs);
+}
+template <class Split>
+static void tree_boxes(HTree& T, Split split) {
+  size_t n = T.recs.size();
   std::vector<int> cntA(n + 1, 0);
   for (size_t i = 0; i < n; i++) cntA[i + 1] = cntA[i] + (T.recs[i].tag == 0);
   T.permA.clear();
@@ -420,7 +427,7 @@ std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int
 
 std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& prm, int n_geom,
                                const int64_t* src_off, const double* src, const int64_t* tgt_off,
-                               const double* tgt) {
+                               const double* tgt, const TreeSorter* sorter) {
   pl = Plan();
   pl.med = med;
   pl.prm = prm;
@@ -442,81 +449,126 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
     double S0, eps, X0, Y0;         // lattice of the geometry: x-y origin and root size
   };
   std::vector<IGeom> geo;
+  // per geometry: its first instance, layer lists, x-y bounds
+  struct GeoRange {
+    size_t geo0, geo1;
+    double xmin, ymin, ext;
+  };
+  std::vector<GeoRange> granges;
+  std::vector<std::vector<std::vector<int>>> src_in_g, tgt_in_g;
+  std::vector<int> geo_of;  // geometry of each instance
   for (int gi = 0; gi < n_geom; gi++) {
-  const int64_t s_lo = src_off[gi], s_hi = src_off[gi + 1], t_lo = tgt_off[gi], t_hi = tgt_off[gi + 1];
-  if (s_hi == s_lo && t_hi == t_lo) continue;
-  size_t geo0 = geo.size();
-
-  // layer membership
-  std::vector<std::vector<int>> src_in(med.n), tgt_in(med.n);
-  for (int64_t i = s_lo; i < s_hi; i++) src_in[med.layer_of(src[3 * i + 2])].push_back((int)i);
-  for (int64_t i = t_lo; i < t_hi; i++) tgt_in[med.layer_of(tgt[3 * i + 2])].push_back((int)i);
-
-  // lattice of this geometry: common x-y origin and root size for every tree
-  double xmin = 1e300, ymin = 1e300, xmax = -1e300, ymax = -1e300;
-  for (int64_t i = s_lo; i < s_hi; i++) {
-    xmin = std::min(xmin, src[3 * i]);
-    xmax = std::max(xmax, src[3 * i]);
-    ymin = std::min(ymin, src[3 * i + 1]);
-    ymax = std::max(ymax, src[3 * i + 1]);
-  }
-  for (int64_t i = t_lo; i < t_hi; i++) {
-    xmin = std::min(xmin, tgt[3 * i]);
-    xmax = std::max(xmax, tgt[3 * i]);
-    ymin = std::min(ymin, tgt[3 * i + 1]);
-    ymax = std::max(ymax, tgt[3 * i + 1]);
-  }
-  double ext = std::max(xmax - xmin, ymax - ymin);
-  if (prm.components & 1) {
-    for (int l = 0; l <= L; l++) {
-      if (src_in[l].empty() || tgt_in[l].empty()) continue;
-      IGeom g;
-      memset(&g.ip, 0, sizeof(g.ip));
-      g.ip.kind = 0;
-      g.ip.lt = g.ip.ls = l;
-      g.ip.kt = g.ip.ks = med.k[l];
-      g.ip.at = g.ip.as = 1;
-      g.ip.sgn = 1;
-      g.sid = src_in[l];
-      g.tid = tgt_in[l];
-      g.zs0 = 1e300;
-      g.zs1 = -1e300;
-      for (int i : g.sid) {
-        g.spos.insert(g.spos.end(), {src[3 * i], src[3 * i + 1], src[3 * i + 2]});
-        g.zs0 = std::min(g.zs0, src[3 * i + 2]);
-        g.zs1 = std::max(g.zs1, src[3 * i + 2]);
-      }
-      for (int i : g.tid) {
-        g.tpos.insert(g.tpos.end(), {tgt[3 * i], tgt[3 * i + 1], tgt[3 * i + 2]});
-        g.zs0 = std::min(g.zs0, tgt[3 * i + 2]);
-        g.zs1 = std::max(g.zs1, tgt[3 * i + 2]);
-      }
-      g.zt0 = g.zs0;
-      g.zt1 = g.zs1;
-      ext = std::max(ext, g.zs1 - g.zs0);
-      geo.push_back(g);
+    const int64_t s_lo = src_off[gi], s_hi = src_off[gi + 1], t_lo = tgt_off[gi], t_hi = tgt_off[gi + 1];
+    if (s_hi == s_lo && t_hi == t_lo) continue;
+    const int gx = (int)granges.size();
+    GeoRange gr;
+    gr.geo0 = geo.size();
+    // layer membership
+    src_in_g.emplace_back(med.n);
+    tgt_in_g.emplace_back(med.n);
+    std::vector<std::vector<int>>& src_in = src_in_g.back();
+    std::vector<std::vector<int>>& tgt_in = tgt_in_g.back();
+    for (int64_t i = s_lo; i < s_hi; i++) src_in[med.layer_of(src[3 * i + 2])].push_back((int)i);
+    for (int64_t i = t_lo; i < t_hi; i++) tgt_in[med.layer_of(tgt[3 * i + 2])].push_back((int)i);
+    // lattice of this geometry: common x-y origin and root size for every tree
+    double xmin = 1e300, ymin = 1e300, xmax = -1e300, ymax = -1e300;
+    for (int64_t i = s_lo; i < s_hi; i++) {
+      xmin = std::min(xmin, src[3 * i]);
+      xmax = std::max(xmax, src[3 * i]);
+      ymin = std::min(ymin, src[3 * i + 1]);
+      ymax = std::max(ymax, src[3 * i + 1]);
     }
-  }
-  if (prm.components & 2) {
-    for (auto& c : comps) {
-      if (src_in[c.ls].empty() || tgt_in[c.lt].empty()) continue;
-      IGeom g;
-      g.ip = c;
-      g.sid = src_in[c.ls];
-      g.tid = tgt_in[c.lt];
-      g.zs0 = g.zt0 = 1e300;
-      g.zs1 = g.zt1 = -1e300;
-      for (int i : g.sid) {
-        double z = c.as * src[3 * i + 2] + c.bs;
-        g.spos.insert(g.spos.end(), {src[3 * i], src[3 * i + 1], z});
-        g.zs0 = std::min(g.zs0, z);
-        g.zs1 = std::max(g.zs1, z);
+    for (int64_t i = t_lo; i < t_hi; i++) {
+      xmin = std::min(xmin, tgt[3 * i]);
+      xmax = std::max(xmax, tgt[3 * i]);
+      ymin = std::min(ymin, tgt[3 * i + 1]);
+      ymax = std::max(ymax, tgt[3 * i + 1]);
+    }
+    gr.xmin = xmin;
+    gr.ymin = ymin;
+    gr.ext = std::max(xmax - xmin, ymax - ymin);
+    if (prm.components & 1) {
+      for (int l = 0; l <= L; l++) {
+        if (src_in[l].empty() || tgt_in[l].empty()) continue;
+        IGeom g;
+        memset(&g.ip, 0, sizeof(g.ip));
+        g.ip.kind = 0;
+        g.ip.lt = g.ip.ls = l;
+        g.ip.kt = g.ip.ks = med.k[l];
+        g.ip.at = g.ip.as = 1;
+        g.ip.sgn = 1;
+        geo.push_back(g);
+        geo_of.push_back(gx);
       }
-      for (int i : g.tid) {
-        double z = c.at * tgt[3 * i + 2] + c.bt;
-        g.tpos.insert(g.tpos.end(), {tgt[3 * i], tgt[3 * i + 1], z});
-        g.zt0 = std::min(g.zt0, z);
-        g.zt1 = std::max(g.zt1, z);
+    }
+    if (prm.components & 2) {
+      for (auto& c : comps) {
+        if (src_in[c.ls].empty() || tgt_in[c.lt].empty()) continue;
+        IGeom g;
+        g.ip = c;
+        geo.push_back(g);
+        geo_of.push_back(gx);
+      }
+    }
+    gr.geo1 = geo.size();
+    granges.push_back(gr);
+  }
+  if (geo.empty()) return "";
+  // every instance's points in its own coordinates (images and effective
+  // locations of a reaction component), on host threads
+  auto fill = [&](size_t q) {
+    IGeom& g = geo[q];
+    const InstParams& c = g.ip;
+    g.sid = src_in_g[geo_of[q]][c.ls];
+    g.tid = tgt_in_g[geo_of[q]][c.lt];
+    g.spos.resize(3 * g.sid.size());
+    g.tpos.resize(3 * g.tid.size());
+    g.zs0 = g.zt0 = 1e300;
+    g.zs1 = g.zt1 = -1e300;
+    for (size_t u = 0; u < g.sid.size(); u++) {
+      const int i = g.sid[u];
+      const double z = c.kind == 0 ? src[3 * i + 2] : c.as * src[3 * i + 2] + c.bs;
+      g.spos[3 * u] = src[3 * i];
+      g.spos[3 * u + 1] = src[3 * i + 1];
+      g.spos[3 * u + 2] = z;
+      g.zs0 = std::min(g.zs0, z);
+      g.zs1 = std::max(g.zs1, z);
+    }
+    for (size_t u = 0; u < g.tid.size(); u++) {
+      const int i = g.tid[u];
+      const double z = c.kind == 0 ? tgt[3 * i + 2] : c.at * tgt[3 * i + 2] + c.bt;
+      g.tpos[3 * u] = tgt[3 * i];
+      g.tpos[3 * u + 1] = tgt[3 * i + 1];
+      g.tpos[3 * u + 2] = z;
+      g.zt0 = std::min(g.zt0, z);
+      g.zt1 = std::max(g.zt1, z);
+    }
+    if (c.kind == 0) {
+      // one tree over the layer's sources and targets: one z range
+      g.zs0 = g.zt0 = std::min(g.zs0, g.zt0);
+      g.zs1 = g.zt1 = std::max(g.zs1, g.zt1);
+    }
+  };
+  auto run_threads = [&](size_t n, const std::function<void(size_t)>& fn) {
+    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::atomic<size_t> next_i{0};
+    auto work = [&]() {
+      for (size_t i = next_i++; i < n; i = next_i++) fn(i);
+    };
+    std::vector<std::thread> pool;
+    for (unsigned t = 1; t < nth && t < n; t++) pool.emplace_back(work);
+    work();
+    for (auto& th : pool) th.join();
+  };
+  run_threads(geo.size(), fill);
+  for (const GeoRange& gr : granges) {
+    double ext = gr.ext;
+    for (size_t q = gr.geo0; q < gr.geo1; q++) {
+      const IGeom& g = geo[q];
+      const InstParams& c = g.ip;
+      if (c.kind == 0) {
+        ext = std::max(ext, g.zs1 - g.zs0);
+        continue;
       }
       // images and effective locations must lie on the two sides of a gap
       double gap = c.sgn > 0 ? g.zt0 - g.zs1 : g.zs0 - g.zt1;
@@ -525,27 +577,24 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
                       "separated (a point lies on an interface?)",
                       c.lt, c.ls, c.up_t ? "up" : "down", c.up_s ? "up" : "down");
       ext = std::max(ext, std::max(g.zs1 - g.zs0, g.zt1 - g.zt0));
-      geo.push_back(g);
+    }
+    // root size: the power of two at or above the extent (with room for the
+    // anchor snapping of the reaction trees below), a function of this
+    // geometry alone, so that geometries of like size share box sizes level by
+    // level (and translation tables) whether built together or apart
+    const double need = ext * (1.0 + 1.0 / 256) + 1e-300;
+    double S0 = 1.0;
+    while (S0 < need) S0 *= 2.0;
+    while (S0 * 0.5 >= need) S0 *= 0.5;
+    double eps = 1e-9 * S0;
+    double X0 = gr.xmin - eps, Y0 = gr.ymin - eps;
+    for (size_t q = gr.geo0; q < gr.geo1; q++) {
+      geo[q].S0 = S0;
+      geo[q].eps = eps;
+      geo[q].X0 = X0;
+      geo[q].Y0 = Y0;
     }
   }
-  // root size: the power of two at or above the extent (with room for the
-  // anchor snapping of the reaction trees below), a function of this
-  // geometry alone, so that geometries of like size share box sizes level by
-  // level (and translation tables) whether built together or apart
-  const double need = ext * (1.0 + 1.0 / 256) + 1e-300;
-  double S0 = 1.0;
-  while (S0 < need) S0 *= 2.0;
-  while (S0 * 0.5 >= need) S0 *= 0.5;
-  double eps = 1e-9 * S0;
-  double X0 = xmin - eps, Y0 = ymin - eps;
-  for (size_t q = geo0; q < geo.size(); q++) {
-    geo[q].S0 = S0;
-    geo[q].eps = eps;
-    geo[q].X0 = X0;
-    geo[q].Y0 = Y0;
-  }
-  }  // geometries
-  if (geo.empty()) return "";
 
   auto kquant = [](double k) { return (long long)llround(k * 1e12); };
   std::map<MatKey, long long> matmap;
@@ -568,6 +617,7 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
   std::map<std::tuple<int, int, long long, long long, long long>, int> casemap;
   std::vector<double> off_ratio;  // per M2L offset: (r_s + r_t) / |c_t - c_s|
   std::vector<M2LRec> recs;       // M2L pairs of every instance
+  std::vector<std::vector<M2LRec>> irecs(geo.size());  // the same, per instance
   std::map<LatKey, int> latmap;
   std::vector<LatGroup> lat;
   std::vector<double> inst_S0;    // root size of each instance's lattice
@@ -665,7 +715,7 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
         }
       }
       depth_used = D;
-      build_tree(S, pos, ids, tags, [&](int l, int n, int, double) { return n > 0 && l < D; });
+      if (!sorter) tree_sort(S, pos, ids, tags);
 
     } else {
       // anchors on the two sides of the gap, moved outward to multiples of a
@@ -764,24 +814,81 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       // every pair, no expansion and no truncation of the method)
       if (prm.react_s2t == 3) Dmax = 0;
       depth_used = Dmax;
-      auto rule = [&](int l, int n, int j, double) { return n > 0 && l < Dmax && j == 0; };
-      build_tree(S, g.spos, g.sid, std::vector<int>(g.sid.size(), 0), rule);
-      build_tree(T, g.tpos, g.tid, std::vector<int>(g.tid.size(), 1), rule);
+      if (!sorter) {
+        tree_sort(S, g.spos, g.sid, std::vector<int>(g.sid.size(), 0));
+        tree_sort(T, g.tpos, g.tid, std::vector<int>(g.tid.size(), 1));
+      }
     }
     pr.Dgap = Dgap;
     pr.depth_used = depth_used;
   };
-  {
-    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    std::atomic<size_t> next_gi{0};
-    auto work = [&]() {
-      for (size_t gi = next_gi++; gi < geo.size(); gi = next_gi++) prepare(gi);
-    };
-    std::vector<std::thread> pool;
-    for (unsigned t = 1; t < nth && t < geo.size(); t++) pool.emplace_back(work);
-    work();
-    for (auto& th : pool) th.join();
+  run_threads(geo.size(), prepare);
+  // (an instance whose depth failed gets no trees; the loop below returns
+  // the first error in instance order)
+  if (sorter) {
+    // every tree's records keyed and sorted in one call: per instance the
+    // source tree (the free-space tree holds the layer's sources, then its
+    // targets), then the target tree of a reaction component
+    std::vector<TreeJob> jobs;
+    std::vector<TreeSeg> segs;
+    std::vector<HTree*> trees;
+    for (size_t gi = 0; gi < geo.size(); gi++) {
+      if (!preps[gi].err.empty()) continue;
+      const IGeom& g = geo[gi];
+      const InstParams& c = g.ip;
+      const auto& sl = src_in_g[geo_of[gi]][c.ls];
+      const auto& tl = tgt_in_g[geo_of[gi]][c.lt];
+      HTree& S = preps[gi].S;
+      HTree& T = preps[gi].T;
+      if (c.kind == 0) {
+        jobs.push_back(TreeJob{S.x0, S.y0, S.z0, S.S0, (int)segs.size(), 2});
+        segs.push_back(TreeSeg{sl.data(), (int)sl.size(), 0, 0, 1.0, 0.0});
+        segs.push_back(TreeSeg{tl.data(), (int)tl.size(), 1, 1, 1.0, 0.0});
+        trees.push_back(&S);
+      } else {
+        jobs.push_back(TreeJob{S.x0, S.y0, S.z0, S.S0, (int)segs.size(), 1});
+        segs.push_back(TreeSeg{sl.data(), (int)sl.size(), 0, 0, c.as, c.bs});
+        trees.push_back(&S);
+        jobs.push_back(TreeJob{T.x0, T.y0, T.z0, T.S0, (int)segs.size(), 1});
+        segs.push_back(TreeSeg{tl.data(), (int)tl.size(), 1, 1, c.at, c.bt});
+        trees.push_back(&T);
+      }
+    }
+    std::vector<uint64_t> keys;
+    std::vector<uint32_t> pay;
+    std::string e = (*sorter)(jobs, segs, keys, pay);
+    if (!e.empty()) return e;
+    std::vector<size_t> r0(jobs.size() + 1, 0);
+    for (size_t t = 0; t < jobs.size(); t++) {
+      size_t nt = 0;
+      for (int q = 0; q < jobs[t].nseg; q++) nt += (size_t)segs[jobs[t].seg0 + q].n;
+      r0[t + 1] = r0[t] + nt;
+    }
+    if (keys.size() != r0.back() || pay.size() != r0.back()) return "tree sorter: wrong record count";
+    run_threads(jobs.size(), [&](size_t t) {
+      HTree& T = *trees[t];
+      T.recs.resize(r0[t + 1] - r0[t]);
+      for (size_t i = 0; i < T.recs.size(); i++) {
+        const uint32_t v = pay[r0[t] + i];
+        T.recs[i].key = keys[r0[t] + i];
+        T.recs[i].id = (int)(v & 0x7fffffffu);
+        T.recs[i].tag = (int)(v >> 31);
+      }
+    });
   }
+  // the boxes of every tree
+  run_threads(geo.size(), [&](size_t gi) {
+    Prep& pr = preps[gi];
+    if (!pr.err.empty()) return;
+    const int D = pr.depth_used;
+    if (geo[gi].ip.kind == 0) {
+      tree_boxes(pr.S, [&](int l, int n, int, double) { return n > 0 && l < D; });
+    } else {
+      auto rule = [&](int l, int n, int j, double) { return n > 0 && l < D && j == 0; };
+      tree_boxes(pr.S, rule);
+      tree_boxes(pr.T, rule);
+    }
+  });
   for (size_t gi = 0; gi < geo.size(); gi++) {
     const IGeom& g = geo[gi];
     Prep& pr = preps[gi];
@@ -1016,6 +1123,8 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
     // classes (and tables) when their lattices agree: same kind and
     // component, order, root size, anchors and worst ratio.
     double rref = 0;
+    std::vector<M2LRec>& ir = irecs[gi];
+    ir.reserve(m2l.size());
     for (auto& pr : m2l) {
       int t = pr.t;
       int l = TT.lvl[t];
@@ -1041,7 +1150,7 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
         r = sqrt(3.0) * Sl / R;
       }
       rref = std::max(rref, r);
-      recs.push_back(rec);
+      ir.push_back(rec);
     }
     {
       LatKey key;
@@ -1072,10 +1181,19 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       } else {
         gid = it->second;
       }
-      for (size_t q = recs.size() - m2l.size(); q < recs.size(); q++) recs[q].gid = gid;
+      for (M2LRec& rec : ir) rec.gid = gid;
     }
     inst_S0.push_back(S0);
     pl.inst.push_back(ip);
+  }
+  {
+    size_t total = 0;
+    for (const auto& ir : irecs) total += ir.size();
+    recs.reserve(total);
+    for (auto& ir : irecs) {
+      recs.insert(recs.end(), ir.begin(), ir.end());
+      std::vector<M2LRec>().swap(ir);
+    }
   }
 
   // ---- M2L classes, across instances of one lattice group: key (group,
@@ -1084,46 +1202,92 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
   // instance alone, so a geometry in a batch computes exactly what its own
   // build computes; the batch only puts more pairs into each GEMM.
   {
-    std::map<std::tuple<int, int, int, int, int>, std::vector<const M2LRec*>> byclass;
-    for (const M2LRec& r : recs) byclass[std::make_tuple(r.gid, r.l, r.px, r.py, r.c3)].push_back(&r);
+    // pairs grouped by class key (group, level, px, py, c3) in key order,
+    // each class's pairs in record order
+    std::vector<std::tuple<int, int, int, int, int>> ckeys;
+    std::vector<int> rec_cls(recs.size());
+    {
+      std::unordered_map<uint64_t, int> kidx;
+      auto pack = [](const M2LRec& r) {
+        return ((uint64_t)(uint32_t)r.gid << 40) ^ ((uint64_t)(uint32_t)r.l << 32) ^
+               ((uint64_t)(uint32_t)r.px << 31) ^ ((uint64_t)(uint32_t)r.py << 30) ^ (uint64_t)(uint32_t)r.c3;
+      };
+      for (size_t q = 0; q < recs.size(); q++) {
+        const M2LRec& r = recs[q];
+        auto ins = kidx.emplace(pack(r), (int)ckeys.size());
+        if (ins.second) ckeys.push_back(std::make_tuple(r.gid, r.l, r.px, r.py, r.c3));
+        rec_cls[q] = ins.first->second;
+      }
+    }
+    std::vector<int> corder(ckeys.size()), crank(ckeys.size());
+    for (size_t c = 0; c < corder.size(); c++) corder[c] = (int)c;
+    std::sort(corder.begin(), corder.end(), [&](int a, int b) { return ckeys[a] < ckeys[b]; });
+    for (size_t c = 0; c < corder.size(); c++) crank[corder[c]] = (int)c;
+    std::vector<int> cptr(ckeys.size() + 1, 0), cpairs(recs.size());
+    for (size_t q = 0; q < recs.size(); q++) cptr[crank[rec_cls[q]] + 1]++;
+    for (size_t c = 0; c < ckeys.size(); c++) cptr[c + 1] += cptr[c];
+    {
+      std::vector<int> fillp(cptr.begin(), cptr.end() - 1);
+      for (size_t q = 0; q < recs.size(); q++) cpairs[fillp[crank[rec_cls[q]]]++] = (int)q;
+    }
+    std::vector<int> tslot_of(pl.tbox.size(), -1);  // target box -> slot in the current class
     std::vector<std::vector<int>> group_offs(lat.size());
-    for (auto& kv : byclass) {
-      const int gid = std::get<0>(kv.first);
+    for (size_t ci = 0; ci < ckeys.size(); ci++) {
+      const auto& ckey = ckeys[corder[ci]];
+      const int gid = std::get<0>(ckey);
       const LatGroup& lg = lat[gid];
       const InstParams& ip = pl.inst[lg.inst];
       const bool free = lg.free;
       const int inst = lg.inst;
       const int P = ip.P;
       const double S0 = lg.S0;
-      int l = std::get<1>(kv.first);
+      int l = std::get<1>(ckey);
       double Sl = S0 / (double)(1 << l);
-      auto& prs = kv.second;
-      std::map<std::tuple<int, int, int>, int> offmap;
-      std::map<int, int> tslot;
-      std::vector<int> tlist;
-      for (const M2LRec* pr : prs) {
-        offmap.emplace(std::make_tuple(pr->dx, pr->dy, pr->dz), 0);
-        if (!tslot.count(pr->t)) {
-          tslot[pr->t] = (int)tlist.size();
-          tlist.push_back(pr->t);
+      const int* prs = cpairs.data() + cptr[ci];
+      const int nprs = cptr[ci + 1] - cptr[ci];
+      // the class's offsets on a dense grid over their range, read in
+      // (dx, dy, dz) order; targets in order of first appearance
+      int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+      for (int u = 0; u < nprs; u++) {
+        const M2LRec& r = recs[prs[u]];
+        const int v[3] = {r.dx, r.dy, r.dz};
+        for (int a = 0; a < 3; a++) {
+          lo[a] = std::min(lo[a], v[a]);
+          hi[a] = std::max(hi[a], v[a]);
         }
       }
+      const long long ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+      auto cell = [&](const M2LRec& r) { return ((r.dx - lo[0]) * ey + (r.dy - lo[1])) * ez + (r.dz - lo[2]); };
+      std::vector<int> offgrid((size_t)(ex * ey * ez), -1);
+      std::vector<int> tlist;
+      for (int u = 0; u < nprs; u++) {
+        const M2LRec& r = recs[prs[u]];
+        offgrid[cell(r)] = 0;
+        if (tslot_of[r.t] < 0) {
+          tslot_of[r.t] = (int)tlist.size();
+          tlist.push_back(r.t);
+        }
+      }
+      std::vector<std::tuple<int, int, int>> okeys;
+      for (long long x = 0; x < ex; x++)
+        for (long long y = 0; y < ey; y++)
+          for (long long z = 0; z < ez; z++)
+            if (offgrid[(x * ey + y) * ez + z] == 0)
+              okeys.push_back(std::make_tuple((int)x + lo[0], (int)y + lo[1], (int)z + lo[2]));
       M2LClass C;
       C.inst = inst;
-      C.n_off = (int)offmap.size();
+      C.n_off = (int)okeys.size();
       C.off0 = (int)pl.offs.size();
       C.n_tgt = (int)tlist.size();
       C.tgt0 = (int)pl.cls_tgt.size();
       C.nblk = free ? 1 : 3;
       C.P = P;
       int oi = 0;
-      int jt = std::get<4>(kv.first);
+      int jt = std::get<4>(ckey);
       // offset order: reaction offsets with equal horizontal distance and
       // source gap index share one table case (they differ only in the
       // azimuth, which the M2L applies per column), so they are placed next
       // to each other and their pairs form the columns of one GEMM
-      std::vector<std::tuple<int, int, int>> okeys;
-      for (auto& ov : offmap) okeys.push_back(ov.first);
       if (!free)
         std::stable_sort(okeys.begin(), okeys.end(),
                          [](const std::tuple<int, int, int>& a, const std::tuple<int, int, int>& b) {
@@ -1132,8 +1296,8 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
                            return ra != rb ? ra < rb : std::get<2>(a) < std::get<2>(b);
                          });
       for (const auto& okey : okeys) {
-        offmap[okey] = oi++;
         int dx = std::get<0>(okey), dy = std::get<1>(okey), dz = std::get<2>(okey);
+        offgrid[((long long)(dx - lo[0]) * ey + (dy - lo[1])) * ez + (dz - lo[2])] = oi++;
         M2LOffset mo;
         group_offs[gid].push_back((int)pl.offs.size());
         if (free) {
@@ -1190,11 +1354,14 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       pl.cls_srcof0.push_back((long long)pl.cls_srcof.size());
       size_t base = pl.cls_srcof.size();
       pl.cls_srcof.resize(base + (size_t)C.n_tgt * C.n_off, -1);
-      for (const M2LRec* pr : prs) {
-        int o = offmap[std::make_tuple(pr->dx, pr->dy, pr->dz)];
-        pl.cls_srcof[base + (size_t)tslot[pr->t] * C.n_off + o] = pr->s;
+      for (int u = 0; u < nprs; u++) {
+        const M2LRec& r = recs[prs[u]];
+        pl.cls_srcof[base + (size_t)tslot_of[r.t] * C.n_off + offgrid[cell(r)]] = r.s;
       }
-      for (int t : tlist) pl.cls_tgt.push_back(t);
+      for (int t : tlist) {
+        pl.cls_tgt.push_back(t);
+        tslot_of[t] = -1;
+      }
       pl.cls.push_back(C);
     }
     // per-offset orders: the truncation error of an M2L pair behaves like

@@ -2,6 +2,7 @@
 // reaction components, trees, interaction lists, M2L classes and table
 // cases, coefficient tables.
 #pragma once
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -101,10 +102,14 @@ std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int
 // several independent geometries in one plan: geometry g owns sources
 // src_off[g] .. src_off[g+1]-1 and targets tgt_off[g] .. tgt_off[g+1]-1 (global
 // indices into src / tgt); each gets its own lattice and FMM instances, and
-// only same-geometry pairs interact
+// only same-geometry pairs interact.  With `sorter`, the records of every
+// octree are keyed and sorted by it, all trees in one call (lm_build does it
+// on the device), instead of on the host; the plan is the same.
+using TreeSorter = std::function<std::string(const std::vector<TreeJob>& jobs, const std::vector<TreeSeg>& segs,
+                                             std::vector<uint64_t>& keys, std::vector<uint32_t>& pay)>;
 std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& prm, int n_geom,
                                const int64_t* src_off, const double* src, const int64_t* tgt_off,
-                               const double* tgt);
+                               const double* tgt, const TreeSorter* sorter = nullptr);
 
 // small helpers exported for host-only tests
 void lm_cheb_affine(int jmax, double a, double b, std::vector<double>& C);

@@ -20,7 +20,7 @@ STAT_NAMES = ["n_free_inst", "n_react_inst", "m2l_pairs_free", "m2l_pairs_react"
               "n_m2l_classes", "n_m2l_tiles_1rhs", "m2l_cmac_useful", "m2l_cmac_exec",
               "n_leaves_p2m", "free_depth", "s2t_pairs", "m2l_flop_exec", "p2m_flops", "m2m_flops",
               "l2l_flops", "l2p_flops", "reduce_bytes", "s2t_node_evals", "m2l_cmac_dense",
-              "p2p_kernel_evals"]
+              "p2p_kernel_evals", "tree_records", "tree_sort_ms", "plan_digest_hi", "plan_digest_lo"]
 
 
 PHASE_NAMES = ["clear", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p"]
@@ -32,7 +32,7 @@ class lm_params(ctypes.Structure):
                 ("contour_a", ctypes.c_double), ("tail_digits", ctypes.c_double),
                 ("components", ctypes.c_int), ("m2l_adapt", ctypes.c_int),
                 ("m2l_margin", ctypes.c_double), ("react_s2t", ctypes.c_int),
-                ("m2l_variant", ctypes.c_int), ("tol", ctypes.c_double)]
+                ("m2l_variant", ctypes.c_int), ("tol", ctypes.c_double), ("host_trees", ctypes.c_int)]
 
 M2L_VARIANTS = 3
 NOALLOC_SCRATCH_BYTES = 256 << 20
