@@ -424,6 +424,18 @@ int lm_host_plan_stats(int n_layers, const double* d, const double* k, const lm_
                        int64_t n_src, const double* src_xyz, int64_t n_tgt, const double* tgt_xyz,
                        double* out, int n, char* errbuf, int errlen);
 
+/* For tests of the planner's external-sort route (the one lm_build takes
+ * with the octree sort on the device), on the host only: plans the
+ * geometries (offsets as lm_build_batch) with the octree records keyed and
+ * sorted outside the planner by a plain host implementation of that
+ * route's contract (Morton keys of the lattice cells, a stable sort per
+ * tree), and with the planner's own sort, and writes both plans' 64-bit
+ * digests (as lm_stats PLAN_DIGEST) to digest[0] and digest[1].  Errors as
+ * lm_host_plan_stats. */
+int lm_host_plan_digests(int n_layers, const double* d, const double* k, const lm_params* prm, int n_geom,
+                         const int64_t* src_off, const double* src_xyz, const int64_t* tgt_off,
+                         const double* tgt_xyz, uint64_t* digest, char* errbuf, int errlen);
+
 #ifdef __cplusplus
 }
 #endif

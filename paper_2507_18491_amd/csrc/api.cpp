@@ -1595,6 +1595,8 @@ int lm_m2l_variants(const lm_ctx* ctx, int n_rhs, int* variant_host, double* ms_
   return (int)ch.size();
 }
 
+static uint64_t plan_digest(const Plan& pl);
+
 int lm_stats(const lm_ctx* ctx, double* out, int n) {
   if (!ctx || !out || n < 1) return LM_EINVAL;
   const Plan& pl = ctx->plan;
@@ -1754,7 +1756,19 @@ int lm_stats(const lm_ctx* ctx, double* out, int n) {
   v[LM_STAT_TREE_RECORDS] = ctx->tree_records;
   v[LM_STAT_TREE_SORT_MS] = ctx->tree_sort_ms;
   if (n > LM_STAT_PLAN_DIGEST_HI) {
-    // FNV-style hash over 8-byte words of every array of the plan
+    const uint64_t h = plan_digest(pl);
+    v[LM_STAT_PLAN_DIGEST_HI] = (double)(h >> 32);
+    v[LM_STAT_PLAN_DIGEST_LO] = (double)(h & 0xffffffffull);
+  }
+  int m = n < LM_STATS_COUNT ? n : LM_STATS_COUNT;
+  memcpy(out, v, m * sizeof(double));
+  return LM_OK;
+}
+
+// FNV-style hash over 8-byte words of every array of a plan (trees, lists,
+// M2L schedule, table cases, nodes, coefficient tables)
+static uint64_t plan_digest(const Plan& pl) {
+  {
     uint64_t h = 1469598103934665603ull;
     auto mix = [&](const void* p, size_t bytes) {
       const unsigned char* c = (const unsigned char*)p;
@@ -1777,12 +1791,8 @@ int lm_stats(const lm_ctx* ctx, double* out, int n) {
     vec(pl.blocks), vec(pl.bt_tbox), vec(pl.bt_ptr), vec(pl.bt_pairs), vec(pl.pair_src), vec(pl.offr), vec(pl.bt_blk);
     vec(pl.pair_P), vec(pl.pair_phi), vec(pl.s2t_items), vec(pl.trans), vec(pl.cases), vec(pl.node_kr);
     vec(pl.node_w), vec(pl.node_inst), vec(pl.Bcoef), vec(pl.Ccoef), vec(pl.Ccoef0), vec(pl.free_depth_used);
-    v[LM_STAT_PLAN_DIGEST_HI] = (double)(h >> 32);
-    v[LM_STAT_PLAN_DIGEST_LO] = (double)(h & 0xffffffffull);
+    return h;
   }
-  int m = n < LM_STATS_COUNT ? n : LM_STATS_COUNT;
-  memcpy(out, v, m * sizeof(double));
-  return LM_OK;
 }
 
 int lm_selftest_math(int64_t n, const double* x_dev, double* out_dev, void* stream) {
@@ -1852,6 +1862,69 @@ int lm_host_plan_stats(int n_layers, const double* d, const double* k, const lm_
     return msg.compare(0, strlen(LM_PLAN_ACCURACY_PREFIX), LM_PLAN_ACCURACY_PREFIX) == 0 ? LM_EACCURACY : LM_EDOMAIN;
   }
   return lm_stats(&tmp, out, n);
+}
+
+int lm_host_plan_digests(int n_layers, const double* d, const double* k, const lm_params* prm, int n_geom,
+                         const int64_t* src_off, const double* src_xyz, const int64_t* tgt_off,
+                         const double* tgt_xyz, uint64_t* digest, char* errbuf, int errlen) {
+  if (n_geom < 1 || !src_off || !tgt_off || !digest || src_off[0] != 0 || tgt_off[0] != 0) return LM_EINVAL;
+  for (int g = 0; g < n_geom; g++)
+    if (src_off[g + 1] < src_off[g] || tgt_off[g + 1] < tgt_off[g]) return LM_EINVAL;
+  if ((src_off[n_geom] > 0 && !src_xyz) || (tgt_off[n_geom] > 0 && !tgt_xyz)) return LM_EINVAL;
+  lm_ctx tmp;
+  int rc = lm_set_layers(&tmp, n_layers, d, k, nullptr);
+  if (!rc && prm) rc = lm_set_params(&tmp, prm);
+  if (rc) {
+    if (errbuf && errlen > 0) snprintf(errbuf, errlen, "%s", tmp.err.c_str());
+    return rc;
+  }
+  // the external route's contract, by plain loops: per tree, every
+  // segment's records keyed by the bits of the three cell indices
+  // interleaved one at a time, then a stable sort by key
+  TreeSorter plain = [&](const std::vector<TreeJob>& jobs, const std::vector<TreeSeg>& segs,
+                         std::vector<uint64_t>& keys, std::vector<uint32_t>& pay) -> std::string {
+    keys.clear();
+    pay.clear();
+    for (const TreeJob& J : jobs) {
+      std::vector<std::pair<uint64_t, uint32_t>> r;
+      const double inv = (double)(1 << LM_TREE_DK) / J.S0;
+      for (int q = 0; q < J.nseg; q++) {
+        const TreeSeg& g = segs[J.seg0 + q];
+        const double* xyz = g.tgt ? tgt_xyz : src_xyz;
+        for (int i = 0; i < g.n; i++) {
+          const double* x = xyz + 3 * (size_t)g.ids[i];
+          const double z = g.za * x[2] + g.zb;
+          const double c[3] = {x[0] - J.x0, x[1] - J.y0, z - J.z0};
+          uint64_t key = 0;
+          for (int a = 0; a < 3; a++) {
+            long long u = (long long)floor(c[a] * inv);
+            u = std::min(std::max(u, 0LL), (1LL << LM_TREE_DK) - 1);
+            for (int b = 0; b < LM_TREE_DK; b++) key |= (uint64_t)((u >> b) & 1) << (3 * b + a);
+          }
+          r.push_back({key, (uint32_t)g.ids[i] | ((uint32_t)g.tag << 31)});
+        }
+      }
+      std::stable_sort(r.begin(), r.end(), [](const std::pair<uint64_t, uint32_t>& a,
+                                              const std::pair<uint64_t, uint32_t>& b) { return a.first < b.first; });
+      for (const auto& e : r) {
+        keys.push_back(e.first);
+        pay.push_back(e.second);
+      }
+    }
+    return "";
+  };
+  for (int route = 0; route < 2; route++) {
+    Plan pl;
+    std::string msg = lm_make_plan_multi(pl, tmp.med, tmp.prm, n_geom, src_off, src_xyz, tgt_off, tgt_xyz,
+                                         route == 0 ? &plain : nullptr);
+    if (!msg.empty()) {
+      if (errbuf && errlen > 0) snprintf(errbuf, errlen, "%s", msg.c_str());
+      return msg.compare(0, strlen(LM_PLAN_ACCURACY_PREFIX), LM_PLAN_ACCURACY_PREFIX) == 0 ? LM_EACCURACY
+                                                                                           : LM_EDOMAIN;
+    }
+    digest[route] = plan_digest(pl);
+  }
+  return LM_OK;
 }
 
 

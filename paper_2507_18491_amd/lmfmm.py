@@ -87,6 +87,9 @@ def load_library():
                                         ctypes.c_int, P(ctypes.c_int), D]
     lib.lm_host_plan_stats.argtypes = [ctypes.c_int, D, D, P(lm_params), ctypes.c_int64, D, ctypes.c_int64,
                                        D, D, ctypes.c_int, ctypes.c_char_p, ctypes.c_int]
+    I64 = P(ctypes.c_int64)
+    lib.lm_host_plan_digests.argtypes = [ctypes.c_int, D, D, P(lm_params), ctypes.c_int, I64, D, I64, D,
+                                         P(ctypes.c_uint64), ctypes.c_char_p, ctypes.c_int]
     _lib = lib
     return lib
 
@@ -494,6 +497,32 @@ def host_legendre_cheb(p):
     if rc:
         raise LMError("lm_host_legendre_cheb failed")
     return out.reshape(-1, stride.value)
+
+
+def host_plan_digests(d, k, srcs, tgts=None, **params):
+    """Digests of the host-planned geometries (lists of [n_g, 3] arrays) with
+    the octree records sorted by the external route's contract in plain host
+    code, and by the planner's own sort (lm_host_plan_digests)."""
+    lib = load_library()
+    d, k = _medium(d, k)
+    srcs = [np.asarray(a, dtype=np.float64).reshape(-1, 3) for a in srcs]
+    tgts = srcs if tgts is None else [np.asarray(a, dtype=np.float64).reshape(-1, 3) for a in tgts]
+    soff = np.ascontiguousarray(np.cumsum([0] + [a.shape[0] for a in srcs]), dtype=np.int64)
+    toff = np.ascontiguousarray(np.cumsum([0] + [a.shape[0] for a in tgts]), dtype=np.int64)
+    src = np.ascontiguousarray(np.concatenate(srcs) if srcs else np.zeros((0, 3)))
+    tgt = np.ascontiguousarray(np.concatenate(tgts) if tgts else np.zeros((0, 3)))
+    prm = make_params(**params)
+    out = (ctypes.c_uint64 * 2)()
+    err = ctypes.create_string_buffer(1024)
+    I64 = ctypes.POINTER(ctypes.c_int64)
+    rc = lib.lm_host_plan_digests(k.size, _dp(d), _dp(k), ctypes.byref(prm), len(srcs),
+                                  soff.ctypes.data_as(I64), _dp(src), toff.ctypes.data_as(I64), _dp(tgt),
+                                  out, err, 1024)
+    if rc:
+        e = LMError("planning failed (%d): %s" % (rc, err.value.decode()))
+        e.code = rc
+        raise e
+    return int(out[0]), int(out[1])
 
 
 def host_plan_stats(d, k, src, tgt=None, **params):

@@ -142,6 +142,36 @@ def test_plan_three_layer_small():
     assert s["m2l_pairs_react"] > 0
 
 
+def test_plan_external_tree_sort_route_gives_the_same_plan():
+    """The route lm_build takes (octree records keyed and sorted outside the
+    planner, all trees in one call; on the device there) gives the plan of
+    the planner's own sort: a plain host implementation of that route's
+    contract (bit-by-bit Morton keys, a stable sort per tree) against the
+    planner's radix sort, by 64-bit plan digests, on one and on several
+    geometries, with targets distinct from the sources, and with every
+    reaction pair direct (single-box reaction trees)."""
+    d, k, x, _ = inputs.tiny()
+    a, b = lmfmm.host_plan_digests(d, k, [x], p=8)
+    assert a == b
+    d, k, x, _ = inputs.three_layer(20000, seed=1)
+    a, b = lmfmm.host_plan_digests(d, k, [x], p=12)
+    assert a == b
+    d, k, xs, _ = inputs.uneven_geometries(5, seed=2, n_min=100, n_max=3000)
+    ys = [xx[::2] + np.array([0.011, -0.017, 0.0]) for xx in xs]
+    for y in ys:
+        y[:, 2] = np.where(np.abs(y[:, 2]) < 0.06, np.sign(y[:, 2]) * 0.08, y[:, 2])
+        y[:, 2] = np.where(np.abs(y[:, 2] + 1.2) < 0.06, -1.2 + np.sign(y[:, 2] + 1.2) * 0.08, y[:, 2])
+    a, b = lmfmm.host_plan_digests(d, k, xs, ys, p=8)
+    assert a == b
+    a2, b2 = lmfmm.host_plan_digests(d, k, xs, ys, p=8, react_s2t=3)
+    assert a2 == b2 and a2 != a
+    # the digest sees a change of one tree: a point moved by one lattice cell
+    xs2 = [xx.copy() for xx in xs]
+    xs2[0][0, 0] += 0.37
+    a3, b3 = lmfmm.host_plan_digests(d, k, xs2, ys, p=8)
+    assert a3 == b3 and a3 != a
+
+
 def test_plan_rejects_point_on_interface():
     d, k, x, _ = inputs.tiny()
     x = x.copy()
