@@ -1761,6 +1761,33 @@ __device__ inline void bessel012_horner(cd z, int n, cd* j0, cd* j1, cd* j2) {
   *j2 = 2.0 * (w * d2);
 }
 
+// J0 and J1 alone: the same pass without the second derivative (the direct
+// pairs take J2 from the recurrence).  Every complex product is written out
+// with explicit multiply-adds, so that each instantiation of the caller
+// rounds alike (a batch column equals its single-vector run bitwise).
+__device__ inline cd cmul_exact(cd a, cd b) {
+  return cd{fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x)};
+}
+// acc + a b
+__device__ inline cd cmac_exact(cd acc, cd a, cd b) {
+  return cd{fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y))};
+}
+__device__ inline void bessel01_horner(cd z, int n, cd* j0, cd* j1) {
+  const cd zz = cmul_exact(z, z);
+  const cd w = cd{0.25 * zz.x, 0.25 * zz.y};
+  int zo = 0;
+  asm volatile("" : "+s"(zo));
+  const double* c = c_bpq + zo;
+  cd v = cd{c[n - 1], 0.0}, d1 = cd{0, 0};
+  for (int k = n - 2; k >= 0; k--) {
+    d1 = cd{fma(d1.x, w.x, fma(-d1.y, w.y, v.x)), fma(d1.x, w.y, fma(d1.y, w.x, v.y))};
+    v = cd{fma(v.x, w.x, fma_s(-v.y, w.y, c[k])), fma(v.x, w.y, v.y * w.x)};
+  }
+  *j0 = v;
+  const cd zd = cmul_exact(z, d1);
+  *j1 = cd{-0.5 * zd.x, -0.5 * zd.y};
+}
+
 __global__ void k_selftest_math(const double* x, long long n, double* out) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -2303,33 +2330,50 @@ __global__ __launch_bounds__(LM_S2T_CHUNK, 2) void k_s2t(DevPlan d, MediumDev md
           nk[tid][2] = nd.kzt;
           nk[tid][3] = nd.kzs;
           for (int f = 0; f < 5; f++) nk[tid][4 + f] = HF ? nd.FH[f] : nd.F[f];
-          nk[tid][9] = cd{nd.kr.y == 0.0 ? 1.0 / nd.kr.x : 0.0, 0.0};
+          // 1 / k_rho (real on the tail)
+          const double ik2 = 1.0 / (nd.kr.x * nd.kr.x + nd.kr.y * nd.kr.y);
+          nk[tid][9] = nd.kr.y == 0.0 ? cd{1.0 / nd.kr.x, 0.0} : cd{nd.kr.x * ik2, -nd.kr.y * ik2};
         }
         __syncthreads();
         for (int m = 0; m < nc; m++) {
           const cd kr = nk[m][0];
           if (kr.y != 0.0) {  // Gamma_1 (complex k_rho): every active pair
             if (!pa) continue;
-            // w k_rho exp(i (t k_z + u k_z')); the phase is small (|k_z| (t + u))
-            const cd ez = cd{0, 1} * (tz * nk[m][2] + uz * nk[m][3]);
+            // w k_rho exp(i (t k_z + u k_z')); the phase is small (|k_z| (t + u)).
+            // Products written out with explicit multiply-adds here and below:
+            // every instantiation (right-hand sides per block) rounds alike
+            const cd kzt = nk[m][2], kzs = nk[m][3];
+            const double ez_re = -fma(tz, kzt.y, uz * kzs.y), ez_im = fma(tz, kzt.x, uz * kzs.x);
             double esn, ecs;
-            lm_sincos_red(ez.y, &esn, &ecs);
-            const double ea = exp(ez.x);
-            const cd base = nk[m][1] * cd{ea * ecs, ea * esn};
+            lm_sincos_red(ez_im, &esn, &ecs);
+            const double ea = exp(ez_re);
+            const cd base = cmul_exact(nk[m][1], cd{ea * ecs, ea * esn});
             cd jb[3];
-            if (SMALLZ)
-              bessel012_horner(rho * kr, nser, jb, jb + 1, jb + 2);
-            else
+            if (SMALLZ) {
+              // J0, J1 by the series; J2 = 2 J1 / z - J0 (1/z = (1/k_rho)(1/rho)),
+              // or its series z^2/8 (1 - z^2/12) near 0 (explicit multiply-adds)
+              const cd z = cd{rho * kr.x, rho * kr.y};
+              bessel01_horner(z, nser, jb, jb + 1);
+              if (fma(z.x, z.x, z.y * z.y) > 1e-6) {
+                const cd t = cmul_exact(jb[1], cd{irho * nk[m][9].x, irho * nk[m][9].y});
+                jb[2] = cd{fma(2.0, t.x, -jb[0].x), fma(2.0, t.y, -jb[0].y)};
+              } else {
+                const cd z2 = cmul_exact(z, z);
+                const cd q = cmul_exact(z2, cd{fma(z2.x, -1.0 / 12.0, 1.0), z2.y * (-1.0 / 12.0)});
+                jb[2] = cd{0.125 * q.x, 0.125 * q.y};
+              }
+            } else {
               bessel_jq(2, rho * kr, jb);
-            cd b0 = base * jb[0], b1 = base * jb[1], b2 = base * jb[2];
-            I1 = I1 + b0 * nk[m][4];
-            I2 = I2 + b1 * nk[m][5];
-            I3 = I3 + b2 * nk[m][6];
-            I4 = I4 + b1 * nk[m][7];
-            I5 = I5 + b0 * nk[m][8];
+            }
+            const cd b0 = cmul_exact(base, jb[0]), b1 = cmul_exact(base, jb[1]), b2 = cmul_exact(base, jb[2]);
+            I1 = cmac_exact(I1, b0, nk[m][4]);
+            I2 = cmac_exact(I2, b1, nk[m][5]);
+            I3 = cmac_exact(I3, b2, nk[m][6]);
+            I4 = cmac_exact(I4, b1, nk[m][7]);
+            I5 = cmac_exact(I5, b0, nk[m][8]);
           } else if (kr.x <= kcut) {
             // real tail: k_z = i |k_z|, Z = exp(-t |k_z| - u |k_z'|)
-            double z = exp(-(tz * nk[m][2].y + uz * nk[m][3].y));
+            double z = exp(-fma(tz, nk[m][2].y, uz * nk[m][3].y));
             double base = nk[m][1].x * z;
             const double x = kr.x * rho, ix = nk[m][9].x * irho;
             double J0, J1;

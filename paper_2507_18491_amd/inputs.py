@@ -23,6 +23,10 @@ benchmark configurations:
 * ``six_layer`` 6 layers, interfaces z=0, -0.8, -1.5, -2.4, -3.0,
                k=(1.0, 1.6, 2.2, 1.3, 1.9, 1.1); N points uniform in
                [-w,w]^2 x each layer's slab, equal shares.
+* ``near_interface`` the three-layer medium with a third of the points in
+               thin sheets between m and 2m from each interface, both
+               sides (m = 0.02 and 0.005 in the tests: the slow-decay regime
+               of the Sommerfeld tail).
 * ``dipole_lattice`` the three-layer medium filled with a jittered cubic
                lattice of small dielectric spheres: the coupled-dipole system
                (diag - G) X = B of the iterative solve.
@@ -124,6 +128,34 @@ def clustered_three_layer(n, seed=0, n_blobs=8, sigma=0.3, n_rhs=1):
     xyz = _blobs(rng, n, slabs, per, sigma, 4.0, [0.4, 0.3, 0.3])
     J = currents(rng, n, n_rhs)
     return np.array(m["d"]), np.array(m["k"]), xyz, J
+
+
+def near_interface(n, margin, seed=0, n_rhs=1, half_width=1.0):
+    """Three-layer points crowding the interfaces: two thirds uniform in the
+    layer slabs kept `margin` from the interfaces, one third in thin sheets
+    between `margin` and 2 `margin` on both sides of each interface (so the
+    images and effective locations of the reaction components come within
+    2 `margin` of each other).  Returns (d, k, xyz[n,3], J)."""
+    rng = np.random.default_rng(seed + 9000)
+    m = MEDIA["three"]
+    d = m["d"]
+    n_sheet = n // 3
+    per = [n_sheet // (2 * len(d))] * (2 * len(d))
+    per[-1] += n_sheet - sum(per)
+    n_uni = n - n_sheet
+    counts = [int(round(n_uni * s)) for s in (0.4, 0.3)]
+    counts.append(n_uni - sum(counts))
+    pts = [_uniform_layers(rng, counts, layer_slabs(d, margin=margin), half_width)]
+    q = 0
+    for di in d:
+        for sgn in (1.0, -1.0):
+            xy = rng.uniform(-half_width, half_width, (per[q], 2))
+            z = di + sgn * rng.uniform(margin, 2.0 * margin, (per[q], 1))
+            pts.append(np.hstack([xy, z]))
+            q += 1
+    xyz = np.vstack(pts)
+    J = currents(rng, n, n_rhs)
+    return np.array(d), np.array(m["k"]), xyz, J
 
 
 def four_layer(n, seed=0, n_rhs=1):

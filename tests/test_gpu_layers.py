@@ -80,3 +80,35 @@ def test_higher_frequency_sampled(scale, half_width, p, tol):
     e = rel(A[idx], ref)
     print("  rel err %.2e" % e, flush=True)
     assert e < tol
+
+
+@pytest.mark.parametrize("margin", [0.02, 0.005])
+def test_points_crowding_the_interfaces(margin):
+    """Points between margin and 2 margin from both sides of each interface
+    (images and effective locations down to 2 margin apart): the real-axis
+    tail of the Sommerfeld integrals grows like 1 / dz_min there (paper
+    Sec. 3.4, the slow-decay regime of the contour discussion).  Against the
+    oracle's adaptive quadrature at 40 sampled targets: every reaction pair
+    direct (the component integrals on the plan's contour and tail, no
+    expansion) within 1e-9, and the FMM at p = 16 within the 1e-6 gate.
+    (At p = 12 the truncation error grows as the points crowd the
+    interfaces: 3.1e-6 and 2.4e-5 here, the same in the CPU run of the FMM,
+    while changes of the tail or the first contour piece do not move it.)"""
+    from oracle import oracle
+    d, k, x, J = inputs.near_interface(300, margin, seed=0)
+    idx = inputs.sample_targets(x.shape[0], count=40, seed=1)
+    ref = oracle.direct(d, k, x, J, x[idx])
+    for kw, tol in ((dict(p=12, p_free=20, react_s2t=3), 1e-9), (dict(p=16, p_free=20), 1e-6),
+                    (dict(p=12, p_free=20), None)):
+        print("case near-interface sheets margin=%g n=300 %s" % (margin, kw), flush=True)
+        t0 = time.time()
+        f = lmfmm.LayeredDyadicFMM(d, k, **kw).build(x)
+        tb = time.time() - t0
+        A = f.evaluate(torch.tensor(J, device="cuda")).cpu().numpy()
+        st = f.stats()
+        f.close()
+        e = rel(A[idx], ref)
+        print("  rel err %.2e, build %.2f s, %d nodes, %d direct reaction pairs" % (
+            e, tb, st["n_nodes"], st["s2t_pairs"]), flush=True)
+        if tol is not None:
+            assert e < tol
