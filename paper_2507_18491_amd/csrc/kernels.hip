@@ -1121,6 +1121,22 @@ void launch_l2p(const DevPlan& d, const int* leaves, int n, int kind, const doub
     l2p_go<1, NT>(d, leaves, n, ch, kind, xyz, n_tgt, n_rhs, LE, A, pi, s);
 }
 
+// One pair's dyadic contribution, acc_c += a q_c + u_c b (u . q): the dot
+// product and b (u . q) formed once, every product folded into a
+// multiply-add chain.
+__device__ __forceinline__ void p2p_apply(cd* acc, cd a, cd bq, double ux, double uy, double uz, cd qx, cd qy,
+                                          cd qz) {
+  const double dre = fma(ux, qx.x, fma(uy, qy.x, uz * qz.x));
+  const double dim = fma(ux, qx.y, fma(uy, qy.y, uz * qz.y));
+  const double bre = fma(bq.x, dre, -(bq.y * dim)), bim = fma(bq.x, dim, bq.y * dre);
+  acc[0] = cd{fma(a.x, qx.x, fma(-a.y, qx.y, fma(ux, bre, acc[0].x))),
+              fma(a.x, qx.y, fma(a.y, qx.x, fma(ux, bim, acc[0].y)))};
+  acc[1] = cd{fma(a.x, qy.x, fma(-a.y, qy.y, fma(uy, bre, acc[1].x))),
+              fma(a.x, qy.y, fma(a.y, qy.x, fma(uy, bim, acc[1].y)))};
+  acc[2] = cd{fma(a.x, qz.x, fma(-a.y, qz.y, fma(uz, bre, acc[2].x))),
+              fma(a.x, qz.y, fma(a.y, qz.x, fma(uz, bim, acc[2].y)))};
+}
+
 // ------------------------------------------------------------------ P2P
 // free-space near field: A_i += sum_j G^f(x_i - x_j) J_j over same-layer
 // sources in adjacent leaves, coincident points skipped (paper Sec. 2 and the
@@ -1185,14 +1201,7 @@ __global__ __launch_bounds__(NT) void k_p2p(DevPlan d, const int* tboxes, int n_
             cd a = g * cd{1.0 - ikr2, ikr};
             cd bq = g * cd{-1.0 + 3.0 * ikr2, -3.0 * ikr};
             double ux = rx * ir, uy = ry * ir, uz = rz * ir;
-            for (int rr = 0; rr < RC; rr++) {
-              cd jx = sj[j][rr][0], jy = sj[j][rr][1], jz = sj[j][rr][2];
-              cd rj = ux * jx + uy * jy + uz * jz;
-              cd brj = bq * rj;
-              acc[rr][0] = acc[rr][0] + a * jx + ux * brj;
-              acc[rr][1] = acc[rr][1] + a * jy + uy * brj;
-              acc[rr][2] = acc[rr][2] + a * jz + uz * brj;
-            }
+            for (int rr = 0; rr < RC; rr++) p2p_apply(acc[rr], a, bq, ux, uy, uz, sj[j][rr][0], sj[j][rr][1], sj[j][rr][2]);
           }
         }
       }
@@ -1316,11 +1325,7 @@ __global__ __launch_bounds__(NT, RED ? 3 : 2) void k_p2p_sym(DevPlan d, const in
           cd a, bq;
           double ux, uy, uz;
           kern(x0 - sp[j][0], y0 - sp[j][1], z0 - sp[j][2], a, bq, ux, uy, uz);
-          const cd jx = sj[j][0], jy = sj[j][1], jz = sj[j][2];
-          const cd brj = bq * (ux * jx + uy * jy + uz * jz);
-          acc[0] = acc[0] + a * jx + ux * brj;
-          acc[1] = acc[1] + a * jy + uy * brj;
-          acc[2] = acc[2] + a * jz + uz * brj;
+          p2p_apply(acc, a, bq, ux, uy, uz, sj[j][0], sj[j][1], sj[j][2]);
         }
       }
     }
@@ -1360,16 +1365,13 @@ __global__ __launch_bounds__(NT, RED ? 3 : 2) void k_p2p_sym(DevPlan d, const in
         cd a, bq;
         double ux, uy, uz;
         kern(x0 - qx[j], y0 - qy[j], z0 - qz[j], a, bq, ux, uy, uz);
-        const cd jx = cd{qj[0][j], qj[1][j]}, jy = cd{qj[2][j], qj[3][j]}, jz = cd{qj[4][j], qj[5][j]};
-        const cd brj = bq * (ux * jx + uy * jy + uz * jz);
-        acc[0] = acc[0] + a * jx + ux * brj;
-        acc[1] = acc[1] + a * jy + uy * brj;
-        acc[2] = acc[2] + a * jz + uz * brj;
+        p2p_apply(acc, a, bq, ux, uy, uz, cd{qj[0][j], qj[1][j]}, cd{qj[2][j], qj[3][j]}, cd{qj[4][j], qj[5][j]});
         // the same kernel at the partner point: G(x_j - x_i) = G(x_i - x_j)
-        const cd bri = bq * (ux * ji[0] + uy * ji[1] + uz * ji[2]);
-        tw[wave][j][0] = tw[wave][j][0] + (a * ji[0] + ux * bri);
-        tw[wave][j][1] = tw[wave][j][1] + (a * ji[1] + uy * bri);
-        tw[wave][j][2] = tw[wave][j][2] + (a * ji[2] + uz * bri);
+        cd t[3] = {tw[wave][j][0], tw[wave][j][1], tw[wave][j][2]};
+        p2p_apply(t, a, bq, ux, uy, uz, ji[0], ji[1], ji[2]);
+        tw[wave][j][0] = t[0];
+        tw[wave][j][1] = t[1];
+        tw[wave][j][2] = t[2];
       }
       }
       __syncthreads();
