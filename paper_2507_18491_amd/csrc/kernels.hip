@@ -94,6 +94,19 @@ __device__ inline int n_of(int nm) {
   return n;
 }
 
+// Complex products with explicit multiply-adds: the compiler would otherwise
+// keep a multiply and an add beside each fused one, and may fuse either real
+// product of a complex product -- differently in two instantiations of one
+// loop (results that must agree bitwise across the kernels' right-hand-side
+// variants use these).
+__device__ inline cd cmul_exact(cd a, cd b) {
+  return cd{fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x)};
+}
+// acc + a b
+__device__ inline cd cmac_exact(cd acc, cd a, cd b) {
+  return cd{fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y))};
+}
+
 // ------------------------------------------------------------------ fill
 __global__ void k_fill(cd* p, long long n) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -251,7 +264,8 @@ __global__ __launch_bounds__(NTB) void k_p2m(DevPlan d, const int* items, const 
         cd bas = rad * ph;
         const double* q = e + 2 * (p + 1);
         for (int rr = 0; rr < RC; rr++)
-          for (int c = 0; c < 3; c++) acc[h][rr][c] = acc[h][rr][c] + cd{q[rr * 6 + 2 * c], q[rr * 6 + 2 * c + 1]} * bas;
+          for (int c = 0; c < 3; c++)
+            acc[h][rr][c] = cmac_exact(acc[h][rr][c], cd{q[rr * 6 + 2 * c], q[rr * 6 + 2 * c + 1]}, bas);
       }
     }
   }
@@ -1076,10 +1090,10 @@ __global__ __launch_bounds__(NTB) void k_l2p(DevPlan d, const int* leaves, int c
         for (int rr = 0; rr < RC; rr++)
           for (int c = 0; c < 3; c++) {
             const cd* L = Lc + (rr * 3 + c) * Pe;
-            acc[rr][c] = acc[rr][c] + L[ip_] * bp;
+            acc[rr][c] = cmac_exact(acc[rr][c], L[ip_], bp);
             if (m > 0) {
               cd bm = ((m & 1) ? -rad : rad) * cconj(em);  // j_n Y^{-m}_n
-              acc[rr][c] = acc[rr][c] + L[im_] * bm;
+              acc[rr][c] = cmac_exact(acc[rr][c], L[im_], bm);
             }
           }
       }
@@ -1764,16 +1778,8 @@ __device__ inline void bessel012_horner(cd z, int n, cd* j0, cd* j1, cd* j2) {
 }
 
 // J0 and J1 alone: the same pass without the second derivative (the direct
-// pairs take J2 from the recurrence).  Every complex product is written out
-// with explicit multiply-adds, so that each instantiation of the caller
-// rounds alike (a batch column equals its single-vector run bitwise).
-__device__ inline cd cmul_exact(cd a, cd b) {
-  return cd{fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x)};
-}
-// acc + a b
-__device__ inline cd cmac_exact(cd acc, cd a, cd b) {
-  return cd{fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y))};
-}
+// pairs take J2 from the recurrence), every complex product written out with
+// explicit multiply-adds.
 __device__ inline void bessel01_horner(cd z, int n, cd* j0, cd* j1) {
   const cd zz = cmul_exact(z, z);
   const cd w = cd{0.25 * zz.x, 0.25 * zz.y};
