@@ -329,54 +329,83 @@ void launch_p2m(const DevPlan& d, const int* items, int n, const double* xyz, co
 
 // ------------------------------------------------------------------ M2M
 // ME_parent[nm] = sum_children sum_{nu mu} Mat_child[nu mu][nm] ME_child[nu mu]
-// (regular-to-regular shift, paper Sec. 2; identical for reaction components, Sec. 3.3)
-template <int RC>
-__global__ __launch_bounds__(NT) void k_m2m(DevPlan d, const int* parents, int n_rhs, cd* ME) {
-  extern __shared__ cd xs[];
-  int pb = parents[blockIdx.x];
-  SrcBox sp = d.sbox[pb];
-  int P = d.inst[sp.inst].P;
-  int r0 = blockIdx.y * RC, nr = min(RC, n_rhs - r0);
-  int tid = threadIdx.x;
-  cd acc[2][RC][3];
+// (regular-to-regular shift, paper Sec. 2; identical for reaction
+// components, Sec. 3.3).  One block per (parent, right-hand side), G groups
+// of NT threads: group g translates children g, g + G, ... (each staged in
+// the group's LDS), and the groups' sums are added in group order (no
+// atomics; the same order for every right-hand side).  Coarse levels hold
+// few parents, so there G = 4 spreads a parent's eight children over four
+// groups (four times the threads in flight); fine levels run G = 1 at the
+// higher occupancy of the smaller LDS.
+template <int G>
+__global__ __launch_bounds__(NT * G) void k_m2m(DevPlan d, const int* parents, int n_rhs, cd* ME) {
+  extern __shared__ cd xs[];  // G x 3P
+  const int pb = parents[blockIdx.x];
+  const SrcBox sp = d.sbox[pb];
+  const int P = d.inst[sp.inst].P;
+  const int r = blockIdx.y;
+  const int g = threadIdx.x / NT, tid = threadIdx.x - g * NT;
+  cd* xg = xs + (long long)g * 3 * P;
+  cd acc[2][3];
   for (int h = 0; h < 2; h++)
-    for (int r = 0; r < RC; r++)
-      for (int c = 0; c < 3; c++) acc[h][r][c] = cd{0, 0};
-  for (int ci = 0; ci < sp.nchild; ci++) {
-    int cb = sp.child0 + ci;
-    long long base = d.sbox[cb].me_off * n_rhs + (long long)r0 * 3 * P;
-    const cd* M = d.mats + d.sbox_m2m[cb];
+    for (int c = 0; c < 3; c++) acc[h][c] = cd{0, 0};
+  for (int c0 = 0; c0 < sp.nchild; c0 += G) {
+    const int ci = c0 + g;
+    const bool has = ci < sp.nchild;
+    const int cb = sp.child0 + ci;
     __syncthreads();
-    for (int e = tid; e < RC * 3 * P; e += NT) xs[e] = (e < nr * 3 * P) ? ME[base + e] : cd{0, 0};
+    if (has) {
+      const long long base = d.sbox[cb].me_off * n_rhs + (long long)r * 3 * P;
+      for (int e = tid; e < 3 * P; e += NT) xg[e] = ME[base + e];
+    }
     __syncthreads();
-    for (int h = 0; h < 2; h++) {
-      int nm = tid + NT * h;
-      if (nm >= P) continue;
-      for (int k = 0; k < P; k++) {
-        cd a = M[(long long)k * P + nm];
-        for (int rr = 0; rr < RC; rr++)
-          for (int c = 0; c < 3; c++) acc[h][rr][c] = acc[h][rr][c] + a * xs[(rr * 3 + c) * P + k];
+    if (has) {
+      const cd* M = d.mats + d.sbox_m2m[cb];
+      for (int h = 0; h < 2; h++) {
+        const int nm = tid + NT * h;
+        if (nm >= P) continue;
+        for (int k = 0; k < P; k++) {
+          const cd a = M[(long long)k * P + nm];
+          for (int c = 0; c < 3; c++) acc[h][c] = cmac_exact(acc[h][c], a, xg[c * P + k]);
+        }
       }
     }
   }
+  cd* out = ME + sp.me_off * n_rhs + (long long)r * 3 * P;
+  if (G == 1) {
+    for (int h = 0; h < 2; h++) {
+      const int nm = tid + NT * h;
+      if (nm >= P) continue;
+      for (int c = 0; c < 3; c++) out[c * P + nm] = acc[h][c];
+    }
+    return;
+  }
+  __syncthreads();
   for (int h = 0; h < 2; h++) {
-    int nm = tid + NT * h;
+    const int nm = tid + NT * h;
     if (nm >= P) continue;
-    for (int rr = 0; rr < nr; rr++)
-      for (int c = 0; c < 3; c++) ME[sp.me_off * n_rhs + ((long long)(r0 + rr) * 3 + c) * P + nm] = acc[h][rr][c];
+    for (int c = 0; c < 3; c++) xg[c * P + nm] = acc[h][c];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 3 * P; e += NT * G) {
+    cd v = xs[e];
+    for (int q = 1; q < G; q++) v = v + xs[(long long)q * 3 * P + e];
+    out[e] = v;
   }
 }
+// one launch per level; G = 4 where the level has fewer parents than eight
+// per compute unit
 void launch_m2m(const DevPlan& d, const int* parents, int n, int n_rhs, cd* ME, int pmax, hipStream_t s) {
   if (n <= 0) return;
-  int P = (pmax + 1) * (pmax + 1);
-  int rc = n_rhs == 1 ? 1 : 4;
-  size_t shm = (size_t)rc * 3 * P * sizeof(cd);
-  if (rc == 1) {
+  const int P = (pmax + 1) * (pmax + 1);
+  if (n < 2048) {
+    const size_t shm = (size_t)4 * 3 * P * sizeof(cd);
+    set_dyn_lds((const void*)k_m2m<4>, shm);
+    hipLaunchKernelGGL(k_m2m<4>, dim3(n, n_rhs), dim3(NT * 4), shm, s, d, parents, n_rhs, ME);
+  } else {
+    const size_t shm = (size_t)3 * P * sizeof(cd);
     set_dyn_lds((const void*)k_m2m<1>, shm);
     hipLaunchKernelGGL(k_m2m<1>, dim3(n, n_rhs), dim3(NT), shm, s, d, parents, n_rhs, ME);
-  } else {
-    set_dyn_lds((const void*)k_m2m<4>, shm);
-    hipLaunchKernelGGL(k_m2m<4>, dim3(n, (n_rhs + 3) / 4), dim3(NT), shm, s, d, parents, n_rhs, ME);
   }
 }
 
