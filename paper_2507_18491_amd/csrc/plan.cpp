@@ -889,6 +889,144 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       tree_boxes(pr.T, rule);
     }
   });
+  // every instance's interaction lists and M2L pair records (local box
+  // ids), on host threads: they depend on the instance's own trees alone
+  struct ILists {
+    std::vector<int> near_t, near_ptr, near_q;  // free space: leaves with targets, their near source boxes
+    long long near_pairs = 0;
+    std::vector<std::pair<int, std::vector<int>>> s2t_near;  // reaction: target leaf, near source boxes
+    std::vector<M2LRec> recs;                                 // M2L pairs (local s, t; gid unset)
+    double rref = 0;                                          // worst separation ratio of the pairs
+    std::string err;
+  };
+  std::vector<ILists> ilists(geo.size());
+  run_threads(geo.size(), [&](size_t gi) {
+    const Prep& pr = preps[gi];
+    if (!pr.err.empty()) return;
+    ILists& li = ilists[gi];
+    const IGeom& g = geo[gi];
+    const InstParams& ip = g.ip;
+    const double S0 = g.S0;
+    const HTree& S = pr.S;
+    const HTree& T = pr.T;
+    const bool free = ip.kind == 0;
+    const HTree& TT = free ? S : T;
+    struct Pair {
+      int s, t;  // local box ids
+    };
+    std::vector<Pair> m2l;
+    std::vector<std::unordered_map<uint64_t, int>> smap(DK + 2);
+    for (int b = 0; b < S.nbox(); b++) smap[S.lvl[b]][ckey(S.ix[b], S.iy[b], S.iz[b])] = b;
+    if (free) {
+      int D = S.lvl[S.nbox() - 1];
+      li.near_ptr.push_back(0);
+      for (int t = 0; t < S.nbox(); t++) {
+        if (S.b1[t] <= S.b0[t]) continue;  // no targets
+        int l = S.lvl[t];
+        if (l < 1) continue;
+        int px = S.ix[t] >> 1, py = S.iy[t] >> 1, pz = S.iz[t] >> 1;
+        for (int dx = -1; dx <= 1; dx++)
+          for (int dy = -1; dy <= 1; dy++)
+            for (int dz = -1; dz <= 1; dz++) {
+              auto it = smap[l - 1].find(ckey(px + dx, py + dy, pz + dz));
+              if (it == smap[l - 1].end()) continue;
+              int q = it->second;
+              for (int c = S.child0[q]; c >= 0 && c < S.child0[q] + S.nchild[q]; c++) {
+                if (S.a1[c] <= S.a0[c]) continue;
+                int ddx = S.ix[c] - S.ix[t], ddy = S.iy[c] - S.iy[t], ddz = S.iz[c] - S.iz[t];
+                if (std::max(std::abs(ddx), std::max(std::abs(ddy), std::abs(ddz))) >= 2)
+                  m2l.push_back({c, t});
+              }
+            }
+        if (l == D) {
+          li.near_t.push_back(t);
+          for (int dx = -1; dx <= 1; dx++)
+            for (int dy = -1; dy <= 1; dy++)
+              for (int dz = -1; dz <= 1; dz++) {
+                auto it = smap[l].find(ckey(S.ix[t] + dx, S.iy[t] + dy, S.iz[t] + dz));
+                if (it == smap[l].end()) continue;
+                int q = it->second;
+                if (S.a1[q] <= S.a0[q]) continue;
+                li.near_q.push_back(q);
+                li.near_pairs += (long long)(S.a1[q] - S.a0[q]) * (S.b1[t] - S.b0[t]);
+              }
+          li.near_ptr.push_back((int)li.near_q.size());
+        }
+      }
+    } else {
+      std::vector<std::vector<int>> nearT(T.nbox());
+      auto ws = [&](int s, int t) {
+        double cs[3], ct[3];
+        S.centre(s, cs);
+        T.centre(t, ct);
+        double sl = S.S(S.lvl[s]) * (2.0 - 1e-9);
+        return fabs(cs[0] - ct[0]) >= sl || fabs(cs[1] - ct[1]) >= sl || fabs(cs[2] - ct[2]) >= sl;
+      };
+      if (S.nbox() > 0 && T.nbox() > 0) {
+        if (ws(0, 0))
+          m2l.push_back({0, 0});
+        else
+          nearT[0].push_back(0);
+      }
+      for (int t = 0; t < T.nbox(); t++) {
+        int P0 = T.parent[t];
+        if (P0 >= 0) {
+          for (int q : nearT[P0]) {
+            if (S.nchild[q] == 0) {
+              li.err = lm_fmt("reaction component (%d,%d): adjacent source leaf at level %d "
+                              "(points too close to an interface)",
+                              ip.lt, ip.ls, S.lvl[q]);
+              return;
+            }
+            for (int c = S.child0[q]; c < S.child0[q] + S.nchild[q]; c++) {
+              if (ws(c, t))
+                m2l.push_back({c, t});
+              else
+                nearT[t].push_back(c);
+            }
+          }
+        }
+        if (T.nchild[t] == 0 && !nearT[t].empty()) {
+          if (!prm.react_s2t) {
+            li.err = lm_fmt("reaction component (%d,%d): adjacent target leaf at level %d "
+                            "(points too close to an interface)",
+                            ip.lt, ip.ls, T.lvl[t]);
+            return;
+          }
+          li.s2t_near.push_back({t, nearT[t]});
+        }
+      }
+    }
+    li.recs.reserve(m2l.size());
+    for (auto& pq : m2l) {
+      int t = pq.t;
+      int l = TT.lvl[t];
+      double Sl = S0 / (double)(1 << l);
+      M2LRec rec;
+      rec.gid = 0;
+      rec.l = l;
+      rec.px = TT.ix[t] & 1;
+      rec.py = TT.iy[t] & 1;
+      rec.c3 = free ? (TT.iz[t] & 1) : TT.j(t);
+      rec.dx = S.ix[pq.s] - TT.ix[t];
+      rec.dy = S.iy[pq.s] - TT.iy[t];
+      rec.dz = free ? S.iz[pq.s] - TT.iz[t] : S.j(pq.s);
+      rec.s = pq.s;
+      rec.t = t;
+      double r;
+      if (free) {
+        r = sqrt(3.0) / sqrt((double)(rec.dx * rec.dx + rec.dy * rec.dy + rec.dz * rec.dz));
+      } else {
+        const int jt = rec.c3, js = rec.dz;
+        double zt_img = ip.sgn > 0 ? T.z0 + (jt + 0.5) * Sl : T.z0 + S0 - (jt + 0.5) * Sl;
+        double zs_img = ip.sgn > 0 ? S.z0 + S0 - (js + 0.5) * Sl : S.z0 + (js + 0.5) * Sl;
+        double R = sqrt((double)(rec.dx * rec.dx + rec.dy * rec.dy) * Sl * Sl + (zt_img - zs_img) * (zt_img - zs_img));
+        r = sqrt(3.0) * Sl / R;
+      }
+      li.rref = std::max(li.rref, r);
+      li.recs.push_back(rec);
+    }
+  });
   for (size_t gi = 0; gi < geo.size(); gi++) {
     const IGeom& g = geo[gi];
     Prep& pr = preps[gi];
@@ -993,52 +1131,20 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
     for (int b = 0; b < TT.nbox(); b++)
       if (TT.nchild[b] == 0 && TT.b1[b] > TT.b0[b]) pl.l2p_leaves.back().push_back(tbase + b);
 
-    // ---- interaction lists
-    struct Pair {
-      int s, t;  // local box ids
-    };
-    std::vector<Pair> m2l;
-    std::vector<std::pair<int, std::vector<int>>> s2t_near;  // reaction: target leaf, near source boxes
-    std::vector<std::unordered_map<uint64_t, int>> smap(DK + 2);
-    for (int b = 0; b < S.nbox(); b++) smap[S.lvl[b]][ckey(S.ix[b], S.iy[b], S.iz[b])] = b;
+    // ---- interaction lists (built per instance on host threads above)
+    ILists& li = ilists[gi];
+    if (!li.err.empty()) return li.err;
     if (free) {
-      int D = S.lvl[S.nbox() - 1];
-      for (int t = 0; t < S.nbox(); t++) {
-        if (S.b1[t] <= S.b0[t]) continue;  // no targets
-        int l = S.lvl[t];
-        if (l < 1) continue;
-        int px = S.ix[t] >> 1, py = S.iy[t] >> 1, pz = S.iz[t] >> 1;
-        for (int dx = -1; dx <= 1; dx++)
-          for (int dy = -1; dy <= 1; dy++)
-            for (int dz = -1; dz <= 1; dz++) {
-              auto it = smap[l - 1].find(ckey(px + dx, py + dy, pz + dz));
-              if (it == smap[l - 1].end()) continue;
-              int q = it->second;
-              for (int c = S.child0[q]; c >= 0 && c < S.child0[q] + S.nchild[q]; c++) {
-                if (S.a1[c] <= S.a0[c]) continue;
-                int ddx = S.ix[c] - S.ix[t], ddy = S.iy[c] - S.iy[t], ddz = S.iz[c] - S.iz[t];
-                if (std::max(std::abs(ddx), std::max(std::abs(ddy), std::abs(ddz))) >= 2)
-                  m2l.push_back({c, t});
-              }
-            }
-        if (l == D) {
-          TgtBox& tb = pl.tbox[tbase + t];
-          tb.p2p0 = (int)pl.p2p_list.size();
-          for (int dx = -1; dx <= 1; dx++)
-            for (int dy = -1; dy <= 1; dy++)
-              for (int dz = -1; dz <= 1; dz++) {
-                auto it = smap[l].find(ckey(S.ix[t] + dx, S.iy[t] + dy, S.iz[t] + dz));
-                if (it == smap[l].end()) continue;
-                int q = it->second;
-                if (S.a1[q] <= S.a0[q]) continue;
-                pl.p2p_list.push_back(sbase + q);
-                pl.n_p2p_pairs += (long long)(S.a1[q] - S.a0[q]) * (S.b1[t] - S.b0[t]);
-              }
-          tb.p2p1 = (int)pl.p2p_list.size();
-        }
+      for (size_t u = 0; u < li.near_t.size(); u++) {
+        TgtBox& tb = pl.tbox[tbase + li.near_t[u]];
+        tb.p2p0 = (int)pl.p2p_list.size();
+        for (int v = li.near_ptr[u]; v < li.near_ptr[u + 1]; v++) pl.p2p_list.push_back(sbase + li.near_q[v]);
+        tb.p2p1 = (int)pl.p2p_list.size();
       }
+      pl.n_p2p_pairs += li.near_pairs;
       // near-field work items: (target leaf, chunk of LM_P2P_CHUNK targets),
       // so that leaves holding many points spread over many workgroups
+      const int D = S.lvl[S.nbox() - 1];
       pl.p2p_tboxes.push_back({});
       for (int t = 0; t < S.nbox(); t++)
         if (S.lvl[t] == D && S.b1[t] > S.b0[t])
@@ -1046,47 +1152,8 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
             pl.p2p_tboxes.back().push_back(tbase + t);
             pl.p2p_tboxes.back().push_back(c);
           }
-    } else {
-      std::vector<std::vector<int>> nearT(T.nbox());
-      s2t_near.clear();
-      auto ws = [&](int s, int t) {
-        double cs[3], ct[3];
-        S.centre(s, cs);
-        T.centre(t, ct);
-        double sl = S.S(S.lvl[s]) * (2.0 - 1e-9);
-        return fabs(cs[0] - ct[0]) >= sl || fabs(cs[1] - ct[1]) >= sl || fabs(cs[2] - ct[2]) >= sl;
-      };
-      if (S.nbox() > 0 && T.nbox() > 0) {
-        if (ws(0, 0))
-          m2l.push_back({0, 0});
-        else
-          nearT[0].push_back(0);
-      }
-      for (int t = 0; t < T.nbox(); t++) {
-        int P0 = T.parent[t];
-        if (P0 >= 0) {
-          for (int q : nearT[P0]) {
-            if (S.nchild[q] == 0)
-              return lm_fmt("reaction component (%d,%d): adjacent source leaf at level %d "
-                            "(points too close to an interface)",
-                            ip.lt, ip.ls, S.lvl[q]);
-            for (int c = S.child0[q]; c < S.child0[q] + S.nchild[q]; c++) {
-              if (ws(c, t))
-                m2l.push_back({c, t});
-              else
-                nearT[t].push_back(c);
-            }
-          }
-        }
-        if (T.nchild[t] == 0 && !nearT[t].empty()) {
-          if (!prm.react_s2t)
-            return lm_fmt("reaction component (%d,%d): adjacent target leaf at level %d "
-                          "(points too close to an interface)",
-                          ip.lt, ip.ls, T.lvl[t]);
-          s2t_near.push_back({t, nearT[t]});
-        }
-      }
     }
+    const auto& s2t_near = li.s2t_near;
     // ---- reaction near field (S2T): target leaves next to the gap and their
     // adjacent source boxes, evaluated by direct Sommerfeld integrals
     double s2t_rho = 0;
@@ -1113,44 +1180,23 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       }
     }
     s2t_rho_of.push_back(s2t_near.empty() ? -1.0 : s2t_rho);
-    pl.n_m2l_pairs += (long long)m2l.size();
-    (free ? pl.n_m2l_pairs_free : pl.n_m2l_pairs_react) += (long long)m2l.size();
+    const long long n_m2l = (long long)li.recs.size();
+    pl.n_m2l_pairs += n_m2l;
+    (free ? pl.n_m2l_pairs_free : pl.n_m2l_pairs_react) += n_m2l;
     (free ? pl.n_free_inst : pl.n_react_inst)++;
 
     // ---- M2L pairs of this instance, for the classes formed below across
-    // instances.  The worst separation ratio rho = (r_s + r_t) / |c_t - c_s|
-    // of the instance's pairs sets its adaptive orders; instances share
-    // classes (and tables) when their lattices agree: same kind and
-    // component, order, root size, anchors and worst ratio.
-    double rref = 0;
+    // instances (computed with the lists; here their global box ids).  The
+    // worst separation ratio of the instance's pairs sets its adaptive
+    // orders; instances share classes (and tables) when their lattices
+    // agree: same kind and component, order, root size, anchors and worst
+    // ratio.
+    const double rref = li.rref;
     std::vector<M2LRec>& ir = irecs[gi];
-    ir.reserve(m2l.size());
-    for (auto& pr : m2l) {
-      int t = pr.t;
-      int l = TT.lvl[t];
-      double Sl = S0 / (double)(1 << l);
-      M2LRec rec;
-      rec.l = l;
-      rec.px = TT.ix[t] & 1;
-      rec.py = TT.iy[t] & 1;
-      rec.c3 = free ? (TT.iz[t] & 1) : TT.j(t);
-      rec.dx = S.ix[pr.s] - TT.ix[t];
-      rec.dy = S.iy[pr.s] - TT.iy[t];
-      rec.dz = free ? S.iz[pr.s] - TT.iz[t] : S.j(pr.s);
-      rec.s = sbase + pr.s;
-      rec.t = tbase + t;
-      double r;
-      if (free) {
-        r = sqrt(3.0) / sqrt((double)(rec.dx * rec.dx + rec.dy * rec.dy + rec.dz * rec.dz));
-      } else {
-        const int jt = rec.c3, js = rec.dz;
-        double zt_img = ip.sgn > 0 ? T.z0 + (jt + 0.5) * Sl : T.z0 + S0 - (jt + 0.5) * Sl;
-        double zs_img = ip.sgn > 0 ? S.z0 + S0 - (js + 0.5) * Sl : S.z0 + (js + 0.5) * Sl;
-        double R = sqrt((double)(rec.dx * rec.dx + rec.dy * rec.dy) * Sl * Sl + (zt_img - zs_img) * (zt_img - zs_img));
-        r = sqrt(3.0) * Sl / R;
-      }
-      rref = std::max(rref, r);
-      ir.push_back(rec);
+    ir.swap(li.recs);
+    for (M2LRec& rec : ir) {
+      rec.s += sbase;
+      rec.t += tbase;
     }
     {
       LatKey key;
