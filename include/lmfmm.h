@@ -109,9 +109,10 @@ typedef struct {
                       /* truncation error is not bounded a priori: it is set by p  */
                       /* (recorded errors per order: see the tests).                */
   int host_trees;     /* 0 (default): lm_build keys and sorts the records of every */
-                      /* octree on the device (Morton keys, radix sort); 1: on the */
-                      /* host.  Both give the same plan (the boxes, lists and     */
-                      /* tables are built on the host from the sorted records).   */
+                      /* octree and forms its boxes on the device (Morton keys,    */
+                      /* radix sort, box starts per level); 1: on the host.  Both  */
+                      /* give the same plan (the interaction lists and tables are  */
+                      /* built on the host).                                       */
 } lm_params;
 
 #define LM_M2L_VARIANTS 3

@@ -485,8 +485,10 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
   ctx->tree_records = 0;
   ctx->tree_sort_ms = 0;
   TreeSorter dev_sort = [&](const std::vector<TreeJob>& jobs, const std::vector<TreeSeg>& segs,
-                            std::vector<uint64_t>& keys, std::vector<uint32_t>& pay) -> std::string {
-    std::string e = lm_device_tree_sort(jobs, segs, ctx->d_src, ctx->d_tgt, keys, pay, &ctx->tree_sort_ms, s);
+                            std::vector<uint64_t>& keys, std::vector<uint32_t>& pay,
+                            std::vector<uint64_t>& boxes) -> std::string {
+    std::string e =
+        lm_device_tree_sort(jobs, segs, ctx->d_src, ctx->d_tgt, keys, pay, boxes, &ctx->tree_sort_ms, s);
     ctx->tree_records = (double)keys.size();
     return e;
   };
@@ -1882,9 +1884,11 @@ int lm_host_plan_digests(int n_layers, const double* d, const double* k, const l
   // segment's records keyed by the bits of the three cell indices
   // interleaved one at a time, then a stable sort by key
   TreeSorter plain = [&](const std::vector<TreeJob>& jobs, const std::vector<TreeSeg>& segs,
-                         std::vector<uint64_t>& keys, std::vector<uint32_t>& pay) -> std::string {
+                         std::vector<uint64_t>& keys, std::vector<uint32_t>& pay,
+                         std::vector<uint64_t>& boxes) -> std::string {
     keys.clear();
     pay.clear();
+    boxes.clear();
     for (const TreeJob& J : jobs) {
       std::vector<std::pair<uint64_t, uint32_t>> r;
       const double inv = (double)(1 << LM_TREE_DK) / J.S0;
@@ -1906,6 +1910,30 @@ int lm_host_plan_digests(int n_layers, const double* d, const double* k, const l
       }
       std::stable_sort(r.begin(), r.end(), [](const std::pair<uint64_t, uint32_t>& a,
                                               const std::pair<uint64_t, uint32_t>& b) { return a.first < b.first; });
+      // the boxes, level by level: a level-l box starts at every record whose
+      // level-l cell differs from the previous record's, if every box above
+      // it on the record's path is split (below the depth; with gap_only,
+      // gap index 0)
+      const size_t base = keys.size();
+      for (size_t i = 0; i < r.size(); i++) {
+        const uint64_t key = r[i].first;
+        int depth = J.depth;
+        if (J.gap_only)
+          for (int l = 0; l < J.depth; l++) {
+            long long iz = 0;
+            for (int b = 0; b < l; b++) iz |= (long long)((key >> (3 * (LM_TREE_DK - l + b) + 2)) & 1) << b;
+            const long long j = J.zflip ? (1LL << l) - 1 - iz : iz;
+            if (j != 0) {
+              depth = l;
+              break;
+            }
+          }
+        for (int l = 0; l <= depth; l++) {
+          const int sh = 3 * (LM_TREE_DK - l);
+          const bool starts = i == 0 || (l > 0 && (key >> sh) != (r[i - 1].first >> sh));
+          if (starts) boxes.push_back(((uint64_t)l << 40) | (uint64_t)(base + i));
+        }
+      }
       for (const auto& e : r) {
         keys.push_back(e.first);
         pay.push_back(e.second);

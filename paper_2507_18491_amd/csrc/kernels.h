@@ -56,12 +56,13 @@ struct DevPlan {
 #define LM_WQ_COUNT 8
 
 void launch_fill(cd* p, long long n, hipStream_t s);
-// Keys and sorts the records of every octree on the device (the sorter of
-// lm_make_plan_multi): d_src / d_tgt are the point positions on the device;
+// Keys and sorts the records of every octree on the device, and forms their
+// boxes (the sorter of lm_make_plan_multi): d_src / d_tgt are the point positions on the device;
 // returns "" or a message; *ms (if given) the time of the kernels.
 std::string lm_device_tree_sort(const std::vector<TreeJob>& jobs, const std::vector<TreeSeg>& segs,
                                 const double* d_src, const double* d_tgt, std::vector<uint64_t>& keys,
-                                std::vector<uint32_t>& pay, float* ms, hipStream_t s);
+                                std::vector<uint32_t>& pay, std::vector<uint64_t>& boxes, float* ms,
+                                hipStream_t s);
 // uploads the Legendre recurrence coefficients to the current device (once)
 int lm_upload_leg_tables();
 void launch_trans(const DevPlan& d, int n_jobs, int pmax_gaunt, hipStream_t s);

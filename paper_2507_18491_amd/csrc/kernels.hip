@@ -1621,9 +1621,76 @@ static void scan_excl(int* a, long long m, int* scratch, hipStream_t s) {
   }
 }
 
+// The boxes of the sorted trees.  A record lies in a box at every level up
+// to its depth: a free-space tree's depth, or, with gap_only, the first
+// level whose box has a nonzero gap index (its boxes below that are not
+// split), capped at the depth; and it is the first record of its box at
+// level l when l is at least the first level at which its key's prefix
+// differs from the previous record's (every level for a tree's first
+// record).  k_tree_box_count counts the boxes each record starts; after a
+// scan k_tree_box_emit writes them, (level << 40) | record, in record and
+// level order.
+struct TreeRuleDev {
+  long long r0;  // first record of the tree in the sorted output
+  int depth, gap_only, zflip;
+};
+__device__ __forceinline__ int tree_z_at(uint64_t key, int l) {
+  // the z cell index at level l: bits 3b + 2 of the key's top l levels
+  int iz = 0;
+  for (int b = LM_TREE_DK - l; b < LM_TREE_DK; b++) iz |= (int)((key >> (3 * b + 2)) & 1) << (b - (LM_TREE_DK - l));
+  return iz;
+}
+__device__ __forceinline__ void tree_box_range(const uint64_t* key, const int* tree, const TreeRuleDev* rule,
+                                               long long u, int* lo, int* hi) {
+  const TreeRuleDev R = rule[tree[u]];
+  int depth = R.depth;
+  if (R.gap_only) {
+    int dd = 0;
+    while (dd < R.depth) {
+      const int iz = tree_z_at(key[u], dd);
+      const int j = R.zflip ? ((1 << dd) - 1 - iz) : iz;
+      if (j != 0) break;
+      dd++;
+    }
+    depth = dd;
+  }
+  int first = 0;
+  if (u > R.r0) {
+    const uint64_t x = key[u] ^ key[u - 1];
+    if (x == 0) {
+      first = LM_TREE_DK + 1;
+    } else {
+      const int b = 63 - __clzll((long long)x);  // highest differing bit
+      first = LM_TREE_DK - b / 3;
+    }
+  }
+  *lo = first;
+  *hi = depth;
+}
+__global__ void k_tree_box_count(const uint64_t* key, const int* tree, const TreeRuleDev* rule, long long n,
+                                 int* cnt) {
+  const long long st = (long long)gridDim.x * blockDim.x;
+  for (long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += st) {
+    int lo, hi;
+    tree_box_range(key, tree, rule, u, &lo, &hi);
+    cnt[u] = hi >= lo ? hi - lo + 1 : 0;
+    if (u == 0) cnt[n] = 0;  // the scan's total lands here
+  }
+}
+__global__ void k_tree_box_emit(const uint64_t* key, const int* tree, const TreeRuleDev* rule, long long n,
+                                const int* off, uint64_t* out) {
+  const long long st = (long long)gridDim.x * blockDim.x;
+  for (long long u = (long long)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += st) {
+    int lo, hi;
+    tree_box_range(key, tree, rule, u, &lo, &hi);
+    for (int l = lo; l <= hi; l++) out[off[u] + (l - lo)] = ((uint64_t)l << 40) | (uint64_t)u;
+  }
+}
+
 std::string lm_device_tree_sort(const std::vector<TreeJob>& jobs, const std::vector<TreeSeg>& segs,
                                 const double* d_src, const double* d_tgt, std::vector<uint64_t>& keys,
-                                std::vector<uint32_t>& pay, float* ms, hipStream_t s) {
+                                std::vector<uint32_t>& pay, std::vector<uint64_t>& boxes, float* ms,
+                                hipStream_t s) {
   // segments in record order; each distinct host id list uploaded once
   std::vector<TreeSegDev> sd;
   std::vector<TreeLatDev> ld;
@@ -1650,13 +1717,23 @@ std::string lm_device_tree_sort(const std::vector<TreeJob>& jobs, const std::vec
   }
   keys.assign((size_t)n, 0);
   pay.assign((size_t)n, 0);
+  boxes.clear();
   if (ms) *ms = 0;
   if (n == 0) return "";
+  std::vector<TreeRuleDev> rd(jobs.size());
+  {
+    long long r = 0;
+    for (size_t t = 0; t < jobs.size(); t++) {
+      rd[t] = TreeRuleDev{r, jobs[t].depth, jobs[t].gap_only, jobs[t].zflip};
+      for (int q = 0; q < jobs[t].nseg; q++) r += segs[jobs[t].seg0 + q].n > 0 ? segs[jobs[t].seg0 + q].n : 0;
+    }
+  }
   if (n > 0x7fffffffLL) return "tree sort: too many records";
   const int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
   const long long m = 256LL * nblk;
   long long nscr = 0;
-  for (long long mm = m; mm > 1; mm = (mm + RS_TILE - 1) / RS_TILE) nscr += (mm + RS_TILE - 1) / RS_TILE + 2;
+  for (long long mm = std::max<long long>(m, n + 1); mm > 1; mm = (mm + RS_TILE - 1) / RS_TILE)
+    nscr += (mm + RS_TILE - 1) / RS_TILE + 2;
   std::vector<void*> bufs;
   bool alloc_ok = true;
   auto dmal = [&](size_t bytes) -> void* {
@@ -1681,12 +1758,14 @@ std::string lm_device_tree_sort(const std::vector<TreeJob>& jobs, const std::vec
   uint32_t* p1 = (uint32_t*)dmal((size_t)n * 4);
   int* t0 = (int*)dmal((size_t)n * 4);
   int* t1 = (int*)dmal((size_t)n * 4);
-  int* cnt = (int*)dmal((size_t)m * 4);
+  int* cnt = (int*)dmal((size_t)std::max<long long>(m, n + 1) * 4);
   int* scr = (int*)dmal((size_t)(nscr + 2) * 4);
+  TreeRuleDev* d_rd = (TreeRuleDev*)dmal(rd.size() * sizeof(TreeRuleDev));
   if (!alloc_ok) return done("tree sort: device allocation failed");
   if (hipMemcpy(d_sd, sd.data(), sd.size() * sizeof(TreeSegDev), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(d_ld, ld.data(), ld.size() * sizeof(TreeLatDev), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(d_ids, ids.data(), ids.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+      hipMemcpy(d_ids, ids.data(), ids.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(d_rd, rd.data(), rd.size() * sizeof(TreeRuleDev), hipMemcpyHostToDevice) != hipSuccess)
     return done("tree sort: upload failed");
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ms) {
@@ -1709,17 +1788,42 @@ std::string lm_device_tree_sort(const std::vector<TreeJob>& jobs, const std::vec
     std::swap(p0, p1);
     std::swap(t0, t1);
   }
-  if (ms) {
-    (void)hipEventRecord(e1, s);
+  // (the time reported is that of the keys and the sort)
+  if (ms) (void)hipEventRecord(e1, s);
+  auto drop_events = [&]() {
+    if (!ms) return;
     (void)hipEventSynchronize(e1);
     (void)hipEventElapsedTime(ms, e0, e1);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+  };
+  // the boxes: per record the count of boxes it starts, their offsets (an
+  // exclusive scan over n + 1 entries gives the total last), the entries
+  const long long gb = std::min<long long>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_tree_box_count, dim3((unsigned)gb), dim3(256), 0, s, (const uint64_t*)k0, (const int*)t0,
+                     (const TreeRuleDev*)d_rd, n, cnt);
+  scan_excl(cnt, n + 1, scr, s);
+  int nbox = 0;
+  if (hipMemcpyAsync(&nbox, cnt + n, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    drop_events();
+    return done("tree sort: box count download failed");
   }
+  uint64_t* d_box = nbox > 0 ? (uint64_t*)dmal((size_t)nbox * 8) : nullptr;
+  if (!alloc_ok) {
+    drop_events();
+    return done("tree sort: device allocation failed");
+  }
+  if (nbox > 0)
+    hipLaunchKernelGGL(k_tree_box_emit, dim3((unsigned)gb), dim3(256), 0, s, (const uint64_t*)k0, (const int*)t0,
+                       (const TreeRuleDev*)d_rd, n, (const int*)cnt, d_box);
+  drop_events();
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return done(std::string("tree sort: ") + hipGetErrorString(err));
+  boxes.assign((size_t)nbox, 0);
   if (hipMemcpyAsync(keys.data(), k0, (size_t)n * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(pay.data(), p0, (size_t)n * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      (nbox > 0 && hipMemcpyAsync(boxes.data(), d_box, (size_t)nbox * 8, hipMemcpyDeviceToHost, s) != hipSuccess) ||
       hipStreamSynchronize(s) != hipSuccess)
     return done("tree sort: download failed");
   return done("");

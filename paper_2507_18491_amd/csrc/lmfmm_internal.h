@@ -27,7 +27,10 @@
 // index floor((x - x0) 2^LM_TREE_DK / S0), clamped to the lattice, per axis;
 // bits interleaved x, y, z from the lowest).  The sorted output holds every
 // tree's records in tree order, each tree's by key with equal keys in input
-// order: the key and id | tag << 31.
+// order: the key and id | tag << 31.  A sorter may also return the boxes:
+// for every box, in record order and, per record, level order, the entry
+// (level << 40) | r, r the index (in the sorted output) of the box's first
+// record.
 #define LM_TREE_DK 20
 struct TreeSeg {
   const int* ids;  // host array of point ids
@@ -39,6 +42,11 @@ struct TreeSeg {
 struct TreeJob {
   double x0, y0, z0, S0;
   int seg0, nseg;  // segments of the tree
+  // refinement rule of the boxes (for a sorter that also forms them): every
+  // non-empty box above level `depth` is split, with gap_only only those
+  // whose gap index j is 0 (the z index from the gap side: iz, or
+  // 2^l - 1 - iz with zflip)
+  int depth, gap_only, zflip;
 };
 
 // Reaction M2L in the mirror-adapted basis: the reaction M2L tensor

@@ -379,6 +379,63 @@ static void tree_boxes(HTree& T, Split split) {
   if (T.lvl_start.back() != T.nbox()) T.lvl_start.push_back(T.nbox());
 }
 
+// The boxes of a sorted tree from their first records: starts[l] lists, in
+// increasing order, the first record of every box at level l (level 0: the
+// root).  The same boxes, in the same order, as tree_boxes with the rule the
+// starts were formed by: a level's boxes are the runs of equal key prefix
+// inside the split boxes of the level above.
+static void tree_boxes_from(HTree& T, const std::vector<std::vector<int>>& starts) {
+  size_t n = T.recs.size();
+  std::vector<int> cntA(n + 1, 0);
+  for (size_t i = 0; i < n; i++) cntA[i + 1] = cntA[i] + (T.recs[i].tag == 0);
+  T.permA.clear();
+  T.permB.clear();
+  for (size_t i = 0; i < n; i++) (T.recs[i].tag == 0 ? T.permA : T.permB).push_back(T.recs[i].id);
+  auto push_box = [&](int l, int px, int py, int pz, int par, int oc, int u0, int u1) {
+    T.lvl.push_back(l);
+    T.ix.push_back(px);
+    T.iy.push_back(py);
+    T.iz.push_back(pz);
+    T.parent.push_back(par);
+    T.child0.push_back(-1);
+    T.nchild.push_back(0);
+    T.oct.push_back(oc);
+    T.u0.push_back(u0);
+    T.u1.push_back(u1);
+    T.a0.push_back(cntA[u0]);
+    T.a1.push_back(cntA[u1]);
+    T.b0.push_back(u0 - cntA[u0]);
+    T.b1.push_back(u1 - cntA[u1]);
+  };
+  T.lvl_start.clear();
+  if (n == 0) {
+    T.lvl_start.push_back(0);
+    return;
+  }
+  push_box(0, 0, 0, 0, -1, -1, 0, (int)n);
+  T.lvl_start.push_back(0);
+  for (size_t l = 1; l < starts.size() && (int)l <= DK; l++) {
+    const std::vector<int>& v = starts[l];
+    if (v.empty()) break;
+    const int b0 = T.lvl_start.back(), b1 = T.nbox();  // the parents' level
+    T.lvl_start.push_back(b1);
+    const int sh = 3 * (DK - (int)l);
+    int pb = b0;
+    for (size_t i = 0; i < v.size(); i++) {
+      const int u = v[i];
+      while (pb < b1 && u >= T.u1[pb]) pb++;
+      if (pb >= b1 || u < T.u0[pb]) break;  // (not inside a box of the level above)
+      const int u1 = (i + 1 < v.size() && v[i + 1] < T.u1[pb]) ? v[i + 1] : T.u1[pb];
+      const int dig = (int)((T.recs[u].key >> sh) & 7);
+      if (T.child0[pb] < 0) T.child0[pb] = T.nbox();
+      T.nchild[pb]++;
+      push_box((int)l, 2 * T.ix[pb] + (dig & 1), 2 * T.iy[pb] + ((dig >> 1) & 1), 2 * T.iz[pb] + ((dig >> 2) & 1),
+               pb, dig, u, u1);
+    }
+  }
+  if (T.lvl_start.back() != T.nbox()) T.lvl_start.push_back(T.nbox());
+}
+
 static inline uint64_t ckey(int x, int y, int z) {
   return (uint64_t)(uint32_t)x | ((uint64_t)(uint32_t)y << 21) | ((uint64_t)(uint32_t)z << 42);
 }
@@ -825,6 +882,7 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
   run_threads(geo.size(), prepare);
   // (an instance whose depth failed gets no trees; the loop below returns
   // the first error in instance order)
+  std::map<const HTree*, std::vector<std::vector<int>>> tree_starts;  // a sorter's boxes per tree
   if (sorter) {
     // every tree's records keyed and sorted in one call: per instance the
     // source tree (the free-space tree holds the layer's sources, then its
@@ -840,23 +898,24 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       const auto& tl = tgt_in_g[geo_of[gi]][c.lt];
       HTree& S = preps[gi].S;
       HTree& T = preps[gi].T;
+      const int D = preps[gi].depth_used;
       if (c.kind == 0) {
-        jobs.push_back(TreeJob{S.x0, S.y0, S.z0, S.S0, (int)segs.size(), 2});
+        jobs.push_back(TreeJob{S.x0, S.y0, S.z0, S.S0, (int)segs.size(), 2, D, 0, S.zflip});
         segs.push_back(TreeSeg{sl.data(), (int)sl.size(), 0, 0, 1.0, 0.0});
         segs.push_back(TreeSeg{tl.data(), (int)tl.size(), 1, 1, 1.0, 0.0});
         trees.push_back(&S);
       } else {
-        jobs.push_back(TreeJob{S.x0, S.y0, S.z0, S.S0, (int)segs.size(), 1});
+        jobs.push_back(TreeJob{S.x0, S.y0, S.z0, S.S0, (int)segs.size(), 1, D, 1, S.zflip});
         segs.push_back(TreeSeg{sl.data(), (int)sl.size(), 0, 0, c.as, c.bs});
         trees.push_back(&S);
-        jobs.push_back(TreeJob{T.x0, T.y0, T.z0, T.S0, (int)segs.size(), 1});
+        jobs.push_back(TreeJob{T.x0, T.y0, T.z0, T.S0, (int)segs.size(), 1, D, 1, T.zflip});
         segs.push_back(TreeSeg{tl.data(), (int)tl.size(), 1, 1, c.at, c.bt});
         trees.push_back(&T);
       }
     }
-    std::vector<uint64_t> keys;
+    std::vector<uint64_t> keys, boxes;
     std::vector<uint32_t> pay;
-    std::string e = (*sorter)(jobs, segs, keys, pay);
+    std::string e = (*sorter)(jobs, segs, keys, pay, boxes);
     if (!e.empty()) return e;
     std::vector<size_t> r0(jobs.size() + 1, 0);
     for (size_t t = 0; t < jobs.size(); t++) {
@@ -865,6 +924,21 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       r0[t + 1] = r0[t] + nt;
     }
     if (keys.size() != r0.back() || pay.size() != r0.back()) return "tree sorter: wrong record count";
+    // the sorter's boxes, if it formed them: per tree, the first records of
+    // its boxes level by level (entries are in record order)
+    std::vector<size_t> e0(jobs.size() + 1, boxes.size());
+    if (!boxes.empty()) {
+      size_t q = 0;
+      for (size_t t = 0; t < jobs.size(); t++) {
+        while (q < boxes.size() && (boxes[q] & 0xffffffffffull) < r0[t]) q++;
+        e0[t] = q;
+      }
+      for (size_t q2 = 1; q2 < boxes.size(); q2++)
+        if ((boxes[q2] & 0xffffffffffull) < (boxes[q2 - 1] & 0xffffffffffull) ||
+            (boxes[q2] >> 40) > (uint64_t)DK)
+          return "tree sorter: boxes out of order";
+      for (size_t t = 0; t < jobs.size(); t++) tree_starts[trees[t]].assign(DK + 2, {});  // (threads below only fill)
+    }
     run_threads(jobs.size(), [&](size_t t) {
       HTree& T = *trees[t];
       T.recs.resize(r0[t + 1] - r0[t]);
@@ -874,14 +948,22 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
         T.recs[i].id = (int)(v & 0x7fffffffu);
         T.recs[i].tag = (int)(v >> 31);
       }
+      if (!boxes.empty()) {
+        std::vector<std::vector<int>>& st = tree_starts.at(trees[t]);
+        for (size_t q = e0[t]; q < e0[t + 1]; q++) st[boxes[q] >> 40].push_back((int)((boxes[q] & 0xffffffffffull) - r0[t]));
+      }
     });
   }
-  // the boxes of every tree
+  // the boxes of every tree (from the sorter's boxes when it formed them)
   run_threads(geo.size(), [&](size_t gi) {
     Prep& pr = preps[gi];
     if (!pr.err.empty()) return;
     const int D = pr.depth_used;
-    if (geo[gi].ip.kind == 0) {
+    auto sit = tree_starts.find(&pr.S);
+    if (sit != tree_starts.end()) {
+      tree_boxes_from(pr.S, sit->second);
+      if (geo[gi].ip.kind != 0) tree_boxes_from(pr.T, tree_starts.at(&pr.T));
+    } else if (geo[gi].ip.kind == 0) {
       tree_boxes(pr.S, [&](int l, int n, int, double) { return n > 0 && l < D; });
     } else {
       auto rule = [&](int l, int n, int j, double) { return n > 0 && l < D && j == 0; };

@@ -106,7 +106,8 @@ std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int
 // octree are keyed and sorted by it, all trees in one call (lm_build does it
 // on the device), instead of on the host; the plan is the same.
 using TreeSorter = std::function<std::string(const std::vector<TreeJob>& jobs, const std::vector<TreeSeg>& segs,
-                                             std::vector<uint64_t>& keys, std::vector<uint32_t>& pay)>;
+                                             std::vector<uint64_t>& keys, std::vector<uint32_t>& pay,
+                                             std::vector<uint64_t>& boxes)>;
 std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& prm, int n_geom,
                                const int64_t* src_off, const double* src, const int64_t* tgt_off,
                                const double* tgt, const TreeSorter* sorter = nullptr);
