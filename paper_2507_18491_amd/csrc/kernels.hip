@@ -1454,7 +1454,8 @@ void launch_p2p_sym(const DevPlan& d, const int* items, int n, const int* part, 
 // an LSD radix sort with 8-bit digits orders them by key (eight passes)
 // and then by tree (one pass per byte of the tree count), every pass stable,
 // so that each tree's records end up contiguous, in key order, equal keys
-// in input order -- the order of the host planner's own sort.
+// in input order -- the order of the host planner's own sort; then the
+// trees' boxes are formed from the sorted keys (k_tree_box_count / emit).
 
 // Morton code of a lattice cell: bits of ux, uy, uz interleaved from the
 // lowest (x at bit 3b, y at 3b + 1, z at 3b + 2).
