@@ -1,12 +1,16 @@
 // api.cpp -- C ABI of the layered-media dyadic FMM library (see include/lmfmm.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "bessel_pq.h"
@@ -227,6 +231,21 @@ static void free_build(lm_ctx* ctx) {
   ctx->host_tgt.clear();
   ctx->host_soff.clear();
   ctx->host_toff.clear();
+}
+
+// Host threads for the build's list construction: fn(i) for i < n, indices
+// handed out one at a time; every fn writes only outputs of its own index,
+// so the result does not depend on the thread count.
+static unsigned host_threads() { return std::max(1u, std::min(16u, std::thread::hardware_concurrency())); }
+static void par_for(size_t n, unsigned nth, const std::function<void(size_t)>& fn) {
+  std::atomic<size_t> next_i{0};
+  auto work = [&]() {
+    for (size_t i = next_i++; i < n; i = next_i++) fn(i);
+  };
+  std::vector<std::thread> pool;
+  for (unsigned t = 1; t < nth && t < n; t++) pool.emplace_back(work);
+  work();
+  for (auto& th : pool) th.join();
 }
 
 template <class T>
@@ -701,7 +720,10 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
     // per item: its targets ordered by t (distance of the effective location
     // from its interface plane) and its near sources by u (that of the
     // image), so that the pairs of one round of 64 have similar tail cuts
-    std::vector<int> items6, tlist, slist;
+    // (the items and their list offsets in launch order here; the lists
+    // themselves item by item on host threads, each into its own range)
+    std::vector<int> items6, tlist, slist, seq;
+    long long tl_n = 0, sl_n = 0;
     for (int v = 0; v < 2; v++) {
       std::stable_sort(order[v].begin(), order[v].end(),
                        [](const std::pair<double, int>& x, const std::pair<double, int>& y) { return x.first < y.first; });
@@ -710,33 +732,46 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
       for (auto& o : order[v]) {
         const int it = o.second;
         const TgtBox& tb = pl.tbox[all[2 * it]];
-        const InstParams& ip = pl.inst[tb.inst];
         const int t0 = tb.pt0 + all[2 * it + 1] * LM_S2T_CHUNK, nt = std::min(LM_S2T_CHUNK, tb.pt1 - t0);
-        const double dls = ip.up_s ? med.d[ip.ls - 1] : med.d[ip.ls];
-        std::vector<std::pair<double, int>> tv, sv;
-        for (int q = 0; q < nt; q++) {
-          const double z = tgt_xyz[3 * pl.tgt_perm[t0 + q] + 2];
-          tv.push_back(std::make_pair(ip.up_t ? z - med.d[ip.lt] : med.d[ip.lt - 1] - z, q));
-        }
-        for (int li = tb.p2p0; li < tb.p2p1; li++) {
-          const SrcBox& sb = pl.sbox[pl.p2p_list[li]];
-          for (int sp = sb.pt0; sp < sb.pt1; sp++) {
-            const int sid = pl.src_perm[sp];
-            const double z = src_xyz[3 * sid + 2];
-            sv.push_back(std::make_pair(ip.up_s ? dls - z : z - dls, sid));
-          }
-        }
-        std::stable_sort(tv.begin(), tv.end(),
-                         [](const std::pair<double, int>& x, const std::pair<double, int>& y) { return x.first < y.first; });
-        std::stable_sort(sv.begin(), sv.end(),
-                         [](const std::pair<double, int>& x, const std::pair<double, int>& y) { return x.first < y.first; });
-        if (slist.size() + sv.size() > 2000000000ULL) return fail(ctx, LM_EINVAL, "too many direct reaction pairs");
-        items6.insert(items6.end(), {all[2 * it], all[2 * it + 1], slot0[it], (int)tlist.size(), (int)slist.size(),
-                                     (int)sv.size()});
-        for (auto& x : tv) tlist.push_back(x.second);
-        for (auto& x : sv) slist.push_back(x.second);
+        long long ns = 0;
+        for (int li = tb.p2p0; li < tb.p2p1; li++) ns += pl.sbox[pl.p2p_list[li]].pt1 - pl.sbox[pl.p2p_list[li]].pt0;
+        if (sl_n + ns > 2000000000LL) return fail(ctx, LM_EINVAL, "too many direct reaction pairs");
+        items6.insert(items6.end(), {all[2 * it], all[2 * it + 1], slot0[it], (int)tl_n, (int)sl_n, (int)ns});
+        seq.push_back(it);
+        tl_n += nt;
+        sl_n += ns;
       }
     }
+    tlist.resize(tl_n);
+    slist.resize(sl_n);
+    par_for(seq.size(), host_threads(), [&](size_t k) {
+      const int it = seq[k];
+      const int* e = items6.data() + 6 * k;
+      const TgtBox& tb = pl.tbox[all[2 * it]];
+      const InstParams& ip = pl.inst[tb.inst];
+      const int t0 = tb.pt0 + all[2 * it + 1] * LM_S2T_CHUNK, nt = std::min(LM_S2T_CHUNK, tb.pt1 - t0);
+      const double dls = ip.up_s ? med.d[ip.ls - 1] : med.d[ip.ls];
+      std::vector<std::pair<double, int>> tv, sv;
+      tv.reserve(nt);
+      sv.reserve(e[5]);
+      for (int q = 0; q < nt; q++) {
+        const double z = tgt_xyz[3 * pl.tgt_perm[t0 + q] + 2];
+        tv.push_back(std::make_pair(ip.up_t ? z - med.d[ip.lt] : med.d[ip.lt - 1] - z, q));
+      }
+      for (int li = tb.p2p0; li < tb.p2p1; li++) {
+        const SrcBox& sb = pl.sbox[pl.p2p_list[li]];
+        for (int sp = sb.pt0; sp < sb.pt1; sp++) {
+          const int sid = pl.src_perm[sp];
+          const double z = src_xyz[3 * sid + 2];
+          sv.push_back(std::make_pair(ip.up_s ? dls - z : z - dls, sid));
+        }
+      }
+      auto by_first = [](const std::pair<double, int>& x, const std::pair<double, int>& y) { return x.first < y.first; };
+      std::stable_sort(tv.begin(), tv.end(), by_first);
+      std::stable_sort(sv.begin(), sv.end(), by_first);
+      for (int q = 0; q < nt; q++) tlist[e[3] + q] = tv[q].second;
+      for (int j = 0; j < e[5]; j++) slist[e[4] + j] = sv[j].second;
+    });
     if ((rc = upload(ctx, &ctx->d_s2t_items, items6))) return rc;
     if ((rc = upload(ctx, &ctx->d_s2t_tlist, tlist))) return rc;
     if ((rc = upload(ctx, &ctx->d_s2t_slist, slist))) return rc;
@@ -814,35 +849,72 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
     if (ok && !items6.empty()) {
       // the items stay in box order (neighbouring items share partner
       // leaves in the cache; longest first measured no faster)
-      // per point: its slots in item order
-      std::vector<int> cnt(pl.n_tgt + 1, 0);
-      for (size_t it = 0; it < items6.size(); it += 6)
-        for (int pi = items6[it + 3]; pi < items6[it + 4]; pi++) {
-          const SrcBox& sb = pl.sbox[part[pi]];
-          for (int pt = sb.pt0; pt < sb.pt1; pt++) cnt[pl.src_perm[pt] + 1]++;
-        }
-      std::vector<int> gpt, gptr, start(pl.n_tgt, -1);
+      // per point: its slots in item order.  The items are cut into nr
+      // consecutive runs of about equal slot counts; each run counts its
+      // slots per point, a point's slots from run r follow those of the
+      // runs before it, and each run then fills its own positions (host
+      // threads, the same lists as one pass over the items)
+      const size_t n_it = items6.size() / 6;
+      const int64_t nt_pts = pl.n_tgt;
+      const unsigned nr = (unsigned)std::max<int64_t>(
+          1, std::min<int64_t>(host_threads(), 250000000LL / std::max<int64_t>(1, nt_pts)));
+      std::vector<size_t> run0(nr + 1, n_it);
+      run0[0] = 0;
+      for (unsigned r = 1, k = 0; r < nr; r++) {
+        const long long target = slots * (long long)r / nr;
+        while (k < n_it && items6[6 * k + 2] < target) k++;
+        run0[r] = k;
+      }
+      std::vector<std::vector<int>> rcnt(nr);
+      par_for(nr, nr, [&](size_t r) {
+        rcnt[r].assign(nt_pts, 0);
+        int* c = rcnt[r].data();
+        for (size_t k = run0[r]; k < run0[r + 1]; k++)
+          for (int pi = items6[6 * k + 3]; pi < items6[6 * k + 4]; pi++) {
+            const SrcBox& sb = pl.sbox[part[pi]];
+            for (int pt = sb.pt0; pt < sb.pt1; pt++) c[pl.src_perm[pt]]++;
+          }
+      });
+      const int64_t blk = 1 << 16;
+      const size_t nblk = (size_t)((nt_pts + blk - 1) / blk);
+      std::vector<int> cnt(nt_pts, 0);
+      par_for(nblk, host_threads(), [&](size_t bi) {
+        for (int64_t i = bi * blk; i < std::min<int64_t>(nt_pts, (bi + 1) * blk); i++)
+          for (unsigned r = 0; r < nr; r++) cnt[i] += rcnt[r][i];
+      });
+      std::vector<int> gpt, gptr, start(nt_pts, -1);
       int acc = 0;
-      for (int64_t i = 0; i < pl.n_tgt; i++)
-        if (cnt[i + 1] > 0) {
+      for (int64_t i = 0; i < nt_pts; i++)
+        if (cnt[i] > 0) {
           start[i] = acc;
           gpt.push_back((int)i);
           gptr.push_back(acc);
-          acc += cnt[i + 1];
+          acc += cnt[i];
         }
       gptr.push_back(acc);
-      std::vector<int> gslot(acc), fill(pl.n_tgt, 0);
-      for (size_t it = 0; it < items6.size(); it += 6) {
-        long long so = items6[it + 2];
-        for (int pi = items6[it + 3]; pi < items6[it + 4]; pi++) {
-          const SrcBox& sb = pl.sbox[part[pi]];
-          for (int pt = sb.pt0; pt < sb.pt1; pt++) {
-            const int id = pl.src_perm[pt];
-            gslot[start[id] + fill[id]++] = (int)(so + (pt - sb.pt0));
+      // each run's counts become its first position per point
+      par_for(nblk, host_threads(), [&](size_t bi) {
+        for (int64_t i = bi * blk; i < std::min<int64_t>(nt_pts, (bi + 1) * blk); i++) {
+          int off = start[i];
+          for (unsigned r = 0; r < nr; r++) {
+            const int c = rcnt[r][i];
+            rcnt[r][i] = off;
+            off += c;
           }
-          so += sb.pt1 - sb.pt0;
         }
-      }
+      });
+      std::vector<int> gslot(acc);
+      par_for(nr, nr, [&](size_t r) {
+        int* pos = rcnt[r].data();
+        for (size_t k = run0[r]; k < run0[r + 1]; k++) {
+          long long so = items6[6 * k + 2];
+          for (int pi = items6[6 * k + 3]; pi < items6[6 * k + 4]; pi++) {
+            const SrcBox& sb = pl.sbox[part[pi]];
+            for (int pt = sb.pt0; pt < sb.pt1; pt++) gslot[pos[pl.src_perm[pt]]++] = (int)(so + (pt - sb.pt0));
+            so += sb.pt1 - sb.pt0;
+          }
+        }
+      });
       if ((rc = upload(ctx, &ctx->d_p2ps_items, items6))) return rc;
       if ((rc = upload(ctx, &ctx->d_p2ps_part, part))) return rc;
       if ((rc = upload(ctx, &ctx->d_p2ps_gpt, gpt))) return rc;
