@@ -26,6 +26,7 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <array>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -34,6 +35,7 @@
 #include <mutex>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 
 std::string lm_fmt(const char* fmt, ...) {
   char buf[1024];
@@ -458,6 +460,7 @@ struct MatKey {
 // one M2L pair (global box ids) with its class key and offset
 struct M2LRec {
   int gid, l, px, py, c3, dx, dy, dz, s, t;
+  M2LRec() {}  // fields left unset: the concatenated list is first written by host threads
 };
 // lattice of an instance: instances with equal keys share M2L classes
 struct LatKey {
@@ -675,6 +678,7 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
   std::vector<double> off_ratio;  // per M2L offset: (r_s + r_t) / |c_t - c_s|
   std::vector<M2LRec> recs;       // M2L pairs of every instance
   std::vector<std::vector<M2LRec>> irecs(geo.size());  // the same, per instance
+  std::vector<std::array<int, 3>> irec_base(geo.size());  // per instance: source, target box base, lattice group
   std::map<LatKey, int> latmap;
   std::vector<LatGroup> lat;
   std::vector<double> inst_S0;    // root size of each instance's lattice
@@ -1135,6 +1139,9 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
     int sp0 = (int)pl.src_perm.size(), tp0 = (int)pl.tgt_perm.size();
     pl.src_perm.insert(pl.src_perm.end(), S.permA.begin(), S.permA.end());
     pl.tgt_perm.insert(pl.tgt_perm.end(), TT.permB.begin(), TT.permB.end());
+    // translation matrices depend on the level and octant alone within an
+    // instance: looked up once per (level, octant), in first-use order
+    std::vector<std::array<long long, 8>> m2m_at, l2l_at;
     for (int b = 0; b < S.nbox(); b++) {
       SrcBox sb;
       memset(&sb, 0, sizeof(sb));
@@ -1153,15 +1160,20 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       long long mm = -1;
       if (S.parent[b] >= 0) {
         int o = S.oct[b];
-        double s = S.S(S.lvl[b]);
-        TransJob j;
-        j.b[0] = ((o & 1) - 0.5) * s;
-        j.b[1] = (((o >> 1) & 1) - 0.5) * s;
-        j.b[2] = (((o >> 2) & 1) - 0.5) * s;
-        j.k = ip.ks;
-        j.p = ip.p;
-        j.kind = 1;
-        mm = alloc_mat(MatKey{1, kquant(ip.ks), ip.p, kquant(S.S(S.lvl[b])), o, 0, 0}, (long long)P * P, &j);
+        const int l = S.lvl[b];
+        if ((int)m2m_at.size() <= l) m2m_at.resize(l + 1, {-1, -1, -1, -1, -1, -1, -1, -1});
+        if (m2m_at[l][o] < 0) {
+          double s = S.S(l);
+          TransJob j;
+          j.b[0] = ((o & 1) - 0.5) * s;
+          j.b[1] = (((o >> 1) & 1) - 0.5) * s;
+          j.b[2] = (((o >> 2) & 1) - 0.5) * s;
+          j.k = ip.ks;
+          j.p = ip.p;
+          j.kind = 1;
+          m2m_at[l][o] = alloc_mat(MatKey{1, kquant(ip.ks), ip.p, kquant(S.S(l)), o, 0, 0}, (long long)P * P, &j);
+        }
+        mm = m2m_at[l][o];
       }
       pl.sbox_m2m.push_back(mm);
       if (S.nchild[b] == 0 && S.a1[b] > S.a0[b]) pl.p2m_leaves.push_back(sbase + b);
@@ -1184,15 +1196,20 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       long long mm = -1;
       if (TT.parent[b] >= 0) {
         int o = TT.oct[b];
-        double s = TT.S(TT.lvl[b]);
-        TransJob j;
-        j.b[0] = ((o & 1) - 0.5) * s;
-        j.b[1] = (((o >> 1) & 1) - 0.5) * s;
-        j.b[2] = (((o >> 2) & 1) - 0.5) * s;
-        j.k = ip.kt;
-        j.p = ip.p;
-        j.kind = 2;
-        mm = alloc_mat(MatKey{2, kquant(ip.kt), ip.p, kquant(TT.S(TT.lvl[b])), o, 0, 0}, (long long)P * P, &j);
+        const int l = TT.lvl[b];
+        if ((int)l2l_at.size() <= l) l2l_at.resize(l + 1, {-1, -1, -1, -1, -1, -1, -1, -1});
+        if (l2l_at[l][o] < 0) {
+          double s = TT.S(l);
+          TransJob j;
+          j.b[0] = ((o & 1) - 0.5) * s;
+          j.b[1] = (((o >> 1) & 1) - 0.5) * s;
+          j.b[2] = (((o >> 2) & 1) - 0.5) * s;
+          j.k = ip.kt;
+          j.p = ip.p;
+          j.kind = 2;
+          l2l_at[l][o] = alloc_mat(MatKey{2, kquant(ip.kt), ip.p, kquant(TT.S(l)), o, 0, 0}, (long long)P * P, &j);
+        }
+        mm = l2l_at[l][o];
       }
       pl.tbox_l2l.push_back(mm);
     }
@@ -1274,12 +1291,9 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
     // agree: same kind and component, order, root size, anchors and worst
     // ratio.
     const double rref = li.rref;
-    std::vector<M2LRec>& ir = irecs[gi];
-    ir.swap(li.recs);
-    for (M2LRec& rec : ir) {
-      rec.s += sbase;
-      rec.t += tbase;
-    }
+    irecs[gi].swap(li.recs);
+    irec_base[gi][0] = sbase;
+    irec_base[gi][1] = tbase;
     {
       LatKey key;
       key.free = free ? 1 : 0;
@@ -1309,19 +1323,34 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       } else {
         gid = it->second;
       }
-      for (M2LRec& rec : ir) rec.gid = gid;
+      irec_base[gi][2] = gid;
     }
     inst_S0.push_back(S0);
     pl.inst.push_back(ip);
   }
   {
-    size_t total = 0;
-    for (const auto& ir : irecs) total += ir.size();
-    recs.reserve(total);
-    for (auto& ir : irecs) {
-      recs.insert(recs.end(), ir.begin(), ir.end());
-      std::vector<M2LRec>().swap(ir);
+    // every instance's pairs in instance order, with global box ids and the
+    // lattice group (pieces of up to 2^18 pairs on host threads)
+    std::vector<size_t> r0(geo.size() + 1, 0);
+    std::vector<std::array<size_t, 2>> pieces;
+    const size_t piece = (size_t)1 << 18;
+    for (size_t gi = 0; gi < geo.size(); gi++) {
+      r0[gi + 1] = r0[gi] + irecs[gi].size();
+      for (size_t u = 0; u < irecs[gi].size(); u += piece) pieces.push_back({gi, u});
     }
+    recs.resize(r0.back());
+    run_threads(pieces.size(), [&](size_t k) {
+      const size_t gi = pieces[k][0], u0 = pieces[k][1], u1 = std::min(irecs[gi].size(), u0 + piece);
+      const int sb = irec_base[gi][0], tb = irec_base[gi][1], gid = irec_base[gi][2];
+      for (size_t u = u0; u < u1; u++) {
+        M2LRec r = irecs[gi][u];
+        r.s += sb;
+        r.t += tb;
+        r.gid = gid;
+        recs[r0[gi] + u] = r;
+      }
+    });
+    for (auto& ir : irecs) std::vector<M2LRec>().swap(ir);
   }
 
   // ---- M2L classes, across instances of one lattice group: key (group,
@@ -1332,36 +1361,58 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
   {
     // pairs grouped by class key (group, level, px, py, c3) in key order,
     // each class's pairs in record order
-    std::vector<std::tuple<int, int, int, int, int>> ckeys;
-    std::vector<int> rec_cls(recs.size());
+    // The key packs into 64 bits in the same order (group < 2^25, level <
+    // 64, parities one bit each, iz parity or gap index j < 2^30), so the
+    // distinct keys of pieces of the list (host threads) are merged by one
+    // sort, and each pair's class is its key's rank.
+    std::vector<std::tuple<int, int, int, int, int>> ckeys;  // distinct keys, increasing
+    std::vector<int> rec_cls(recs.size());                   // each pair's class
     {
-      std::unordered_map<uint64_t, int> kidx;
       auto pack = [](const M2LRec& r) {
-        return ((uint64_t)(uint32_t)r.gid << 40) ^ ((uint64_t)(uint32_t)r.l << 32) ^
-               ((uint64_t)(uint32_t)r.px << 31) ^ ((uint64_t)(uint32_t)r.py << 30) ^ (uint64_t)(uint32_t)r.c3;
+        return ((uint64_t)(uint32_t)r.gid << 38) | ((uint64_t)(uint32_t)r.l << 32) |
+               ((uint64_t)(uint32_t)r.px << 31) | ((uint64_t)(uint32_t)r.py << 30) | (uint64_t)(uint32_t)r.c3;
       };
-      for (size_t q = 0; q < recs.size(); q++) {
-        const M2LRec& r = recs[q];
-        auto ins = kidx.emplace(pack(r), (int)ckeys.size());
-        if (ins.second) ckeys.push_back(std::make_tuple(r.gid, r.l, r.px, r.py, r.c3));
-        rec_cls[q] = ins.first->second;
+      const size_t piece = (size_t)1 << 18, npc = (recs.size() + piece - 1) / piece;
+      std::vector<std::vector<uint64_t>> pkeys(npc);
+      std::atomic<bool> bad{false};
+      run_threads(npc, [&](size_t k) {
+        std::unordered_set<uint64_t> seen;
+        for (size_t q = k * piece; q < std::min(recs.size(), (k + 1) * piece); q++) {
+          const M2LRec& r = recs[q];
+          if (r.gid < 0 || r.gid >= (1 << 25) || r.l < 0 || r.l >= 64 || (r.px | r.py) & ~1 || r.c3 < 0 ||
+              r.c3 >= (1 << 30))
+            bad = true;
+          seen.insert(pack(r));
+        }
+        pkeys[k].assign(seen.begin(), seen.end());
+      });
+      if (bad) return "internal: M2L class key out of range";
+      std::vector<uint64_t> keys;
+      for (const auto& v : pkeys) keys.insert(keys.end(), v.begin(), v.end());
+      std::sort(keys.begin(), keys.end());
+      keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+      std::unordered_map<uint64_t, int> rank;
+      for (size_t c = 0; c < keys.size(); c++) {
+        const uint64_t u = keys[c];
+        rank[u] = (int)c;
+        ckeys.push_back(std::make_tuple((int)(u >> 38), (int)((u >> 32) & 63), (int)((u >> 31) & 1),
+                                        (int)((u >> 30) & 1), (int)(u & ((1u << 30) - 1))));
       }
+      run_threads(npc, [&](size_t k) {
+        for (size_t q = k * piece; q < std::min(recs.size(), (k + 1) * piece); q++) rec_cls[q] = rank.at(pack(recs[q]));
+      });
     }
-    std::vector<int> corder(ckeys.size()), crank(ckeys.size());
-    for (size_t c = 0; c < corder.size(); c++) corder[c] = (int)c;
-    std::sort(corder.begin(), corder.end(), [&](int a, int b) { return ckeys[a] < ckeys[b]; });
-    for (size_t c = 0; c < corder.size(); c++) crank[corder[c]] = (int)c;
     std::vector<int> cptr(ckeys.size() + 1, 0), cpairs(recs.size());
-    for (size_t q = 0; q < recs.size(); q++) cptr[crank[rec_cls[q]] + 1]++;
+    for (size_t q = 0; q < recs.size(); q++) cptr[rec_cls[q] + 1]++;
     for (size_t c = 0; c < ckeys.size(); c++) cptr[c + 1] += cptr[c];
     {
       std::vector<int> fillp(cptr.begin(), cptr.end() - 1);
-      for (size_t q = 0; q < recs.size(); q++) cpairs[fillp[crank[rec_cls[q]]]++] = (int)q;
+      for (size_t q = 0; q < recs.size(); q++) cpairs[fillp[rec_cls[q]]++] = (int)q;
     }
     std::vector<int> tslot_of(pl.tbox.size(), -1);  // target box -> slot in the current class
     std::vector<std::vector<int>> group_offs(lat.size());
     for (size_t ci = 0; ci < ckeys.size(); ci++) {
-      const auto& ckey = ckeys[corder[ci]];
+      const auto& ckey = ckeys[ci];
       const int gid = std::get<0>(ckey);
       const LatGroup& lg = lat[gid];
       const InstParams& ip = pl.inst[lg.inst];
