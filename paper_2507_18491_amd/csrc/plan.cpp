@@ -1409,8 +1409,76 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       std::vector<int> fillp(cptr.begin(), cptr.end() - 1);
       for (size_t q = 0; q < recs.size(); q++) cpairs[fillp[rec_cls[q]]++] = (int)q;
     }
-    std::vector<int> tslot_of(pl.tbox.size(), -1);  // target box -> slot in the current class
+    // Per class, on host threads: the offsets on a dense grid over their
+    // range (occupied cells read in (dx, dy, dz) order) and the targets in
+    // order of first appearance.  A target box lies in one class only (the
+    // key is made of its own lattice group, level, parities and z index), so
+    // the classes write disjoint entries of tslot_of.
+    std::vector<int> tslot_of(pl.tbox.size(), -1);  // target box -> slot in its class
+    struct ClsPre {
+      int lo[3];
+      long long ey, ez;
+      std::vector<int> offgrid, tlist;
+      std::vector<std::tuple<int, int, int>> okeys;
+    };
+    std::vector<ClsPre> pre(ckeys.size());
+    run_threads(ckeys.size(), [&](size_t ci) {
+      ClsPre& cp = pre[ci];
+      const bool free = lat[std::get<0>(ckeys[ci])].free;
+      const int* prs = cpairs.data() + cptr[ci];
+      const int nprs = cptr[ci + 1] - cptr[ci];
+      int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+      for (int u = 0; u < nprs; u++) {
+        const M2LRec& r = recs[prs[u]];
+        const int v[3] = {r.dx, r.dy, r.dz};
+        for (int a = 0; a < 3; a++) {
+          lo[a] = std::min(lo[a], v[a]);
+          hi[a] = std::max(hi[a], v[a]);
+        }
+      }
+      const long long ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+      for (int a = 0; a < 3; a++) cp.lo[a] = lo[a];
+      cp.ey = ey;
+      cp.ez = ez;
+      cp.offgrid.assign((size_t)(ex * ey * ez), -1);
+      for (int u = 0; u < nprs; u++) {
+        const M2LRec& r = recs[prs[u]];
+        cp.offgrid[((r.dx - lo[0]) * ey + (r.dy - lo[1])) * ez + (r.dz - lo[2])] = 0;
+        if (tslot_of[r.t] < 0) {
+          tslot_of[r.t] = (int)cp.tlist.size();
+          cp.tlist.push_back(r.t);
+        }
+      }
+      for (long long x = 0; x < ex; x++)
+        for (long long y = 0; y < ey; y++)
+          for (long long z = 0; z < ez; z++)
+            if (cp.offgrid[(x * ey + y) * ez + z] == 0)
+              cp.okeys.push_back(std::make_tuple((int)x + lo[0], (int)y + lo[1], (int)z + lo[2]));
+      // offset order: reaction offsets with equal horizontal distance and
+      // source gap index share one table case (they differ only in the
+      // azimuth, which the M2L applies per column), so they are placed next
+      // to each other and their pairs form the columns of one GEMM
+      if (!free)
+        std::stable_sort(cp.okeys.begin(), cp.okeys.end(),
+                         [](const std::tuple<int, int, int>& a, const std::tuple<int, int, int>& b) {
+                           const int ra = std::get<0>(a) * std::get<0>(a) + std::get<1>(a) * std::get<1>(a);
+                           const int rb = std::get<0>(b) * std::get<0>(b) + std::get<1>(b) * std::get<1>(b);
+                           return ra != rb ? ra < rb : std::get<2>(a) < std::get<2>(b);
+                         });
+    });
+    {
+      std::vector<int> owner(pl.tbox.size(), -1);
+      for (size_t ci = 0; ci < pre.size(); ci++)
+        for (size_t k = 0; k < pre[ci].tlist.size(); k++) {
+          const int t = pre[ci].tlist[k];
+          if (owner[t] >= 0 || tslot_of[t] != (int)k) return "internal: target box in two M2L classes";
+          owner[t] = (int)ci;
+        }
+    }
+    // offsets, table cases and matrices in class order (serial), then each
+    // class's (target, offset) -> source box table on host threads
     std::vector<std::vector<int>> group_offs(lat.size());
+    long long srcof_n = 0;
     for (size_t ci = 0; ci < ckeys.size(); ci++) {
       const auto& ckey = ckeys[ci];
       const int gid = std::get<0>(ckey);
@@ -1422,37 +1490,12 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       const double S0 = lg.S0;
       int l = std::get<1>(ckey);
       double Sl = S0 / (double)(1 << l);
-      const int* prs = cpairs.data() + cptr[ci];
-      const int nprs = cptr[ci + 1] - cptr[ci];
-      // the class's offsets on a dense grid over their range, read in
-      // (dx, dy, dz) order; targets in order of first appearance
-      int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
-      for (int u = 0; u < nprs; u++) {
-        const M2LRec& r = recs[prs[u]];
-        const int v[3] = {r.dx, r.dy, r.dz};
-        for (int a = 0; a < 3; a++) {
-          lo[a] = std::min(lo[a], v[a]);
-          hi[a] = std::max(hi[a], v[a]);
-        }
-      }
-      const long long ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
-      auto cell = [&](const M2LRec& r) { return ((r.dx - lo[0]) * ey + (r.dy - lo[1])) * ez + (r.dz - lo[2]); };
-      std::vector<int> offgrid((size_t)(ex * ey * ez), -1);
-      std::vector<int> tlist;
-      for (int u = 0; u < nprs; u++) {
-        const M2LRec& r = recs[prs[u]];
-        offgrid[cell(r)] = 0;
-        if (tslot_of[r.t] < 0) {
-          tslot_of[r.t] = (int)tlist.size();
-          tlist.push_back(r.t);
-        }
-      }
-      std::vector<std::tuple<int, int, int>> okeys;
-      for (long long x = 0; x < ex; x++)
-        for (long long y = 0; y < ey; y++)
-          for (long long z = 0; z < ez; z++)
-            if (offgrid[(x * ey + y) * ez + z] == 0)
-              okeys.push_back(std::make_tuple((int)x + lo[0], (int)y + lo[1], (int)z + lo[2]));
+      ClsPre& cp = pre[ci];
+      const int* lo = cp.lo;
+      const long long ey = cp.ey, ez = cp.ez;
+      std::vector<int>& offgrid = cp.offgrid;
+      const std::vector<int>& tlist = cp.tlist;
+      const std::vector<std::tuple<int, int, int>>& okeys = cp.okeys;
       M2LClass C;
       C.inst = inst;
       C.n_off = (int)okeys.size();
@@ -1463,17 +1506,6 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       C.P = P;
       int oi = 0;
       int jt = std::get<4>(ckey);
-      // offset order: reaction offsets with equal horizontal distance and
-      // source gap index share one table case (they differ only in the
-      // azimuth, which the M2L applies per column), so they are placed next
-      // to each other and their pairs form the columns of one GEMM
-      if (!free)
-        std::stable_sort(okeys.begin(), okeys.end(),
-                         [](const std::tuple<int, int, int>& a, const std::tuple<int, int, int>& b) {
-                           const int ra = std::get<0>(a) * std::get<0>(a) + std::get<1>(a) * std::get<1>(a);
-                           const int rb = std::get<0>(b) * std::get<0>(b) + std::get<1>(b) * std::get<1>(b);
-                           return ra != rb ? ra < rb : std::get<2>(a) < std::get<2>(b);
-                         });
       for (const auto& okey : okeys) {
         int dx = std::get<0>(okey), dy = std::get<1>(okey), dz = std::get<2>(okey);
         offgrid[((long long)(dx - lo[0]) * ey + (dy - lo[1])) * ez + (dz - lo[2])] = oi++;
@@ -1530,19 +1562,22 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
         mo.pad_ = 0;
         pl.offs.push_back(mo);
       }
-      pl.cls_srcof0.push_back((long long)pl.cls_srcof.size());
-      size_t base = pl.cls_srcof.size();
-      pl.cls_srcof.resize(base + (size_t)C.n_tgt * C.n_off, -1);
-      for (int u = 0; u < nprs; u++) {
-        const M2LRec& r = recs[prs[u]];
-        pl.cls_srcof[base + (size_t)tslot_of[r.t] * C.n_off + offgrid[cell(r)]] = r.s;
-      }
-      for (int t : tlist) {
-        pl.cls_tgt.push_back(t);
-        tslot_of[t] = -1;
-      }
+      pl.cls_srcof0.push_back(srcof_n);
+      srcof_n += (long long)C.n_tgt * C.n_off;
+      pl.cls_tgt.insert(pl.cls_tgt.end(), tlist.begin(), tlist.end());
       pl.cls.push_back(C);
     }
+    pl.cls_srcof.assign((size_t)srcof_n, -1);
+    run_threads(ckeys.size(), [&](size_t ci) {
+      const ClsPre& cp = pre[ci];
+      const int n_off = pl.cls[ci].n_off;
+      int* so = pl.cls_srcof.data() + pl.cls_srcof0[ci];
+      for (int u = cptr[ci]; u < cptr[ci + 1]; u++) {
+        const M2LRec& r = recs[cpairs[u]];
+        const int o = cp.offgrid[((r.dx - cp.lo[0]) * cp.ey + (r.dy - cp.lo[1])) * cp.ez + (r.dz - cp.lo[2])];
+        so[(size_t)tslot_of[r.t] * n_off + o] = r.s;
+      }
+    });
     // per-offset orders: the truncation error of an M2L pair behaves like
     // rho^(p+1).  Every offset gets the least order whose bound lies
     // m2l_margin decades below the bound of the group's worst admissible
@@ -1563,49 +1598,88 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
   }
 
   // ---- M2L work blocks: targets of a class in groups of at most 2048, pairs
-  // sorted by offset (GEMM columns) and per target (reduction)
+  // sorted by offset (GEMM columns) and per target (reduction).  The blocks'
+  // sizes are counted first, then every block fills its own ranges of the
+  // pair and target arrays (host threads; the arrays are those of one pass
+  // over the blocks in class order).
   {
     const int TB = 512;
-    for (int c = 0; c < (int)pl.cls.size(); c++) {
-      const M2LClass& C = pl.cls[c];
-      long long base = pl.cls_srcof0[c];
-      for (int t0 = 0; t0 < C.n_tgt; t0 += TB) {
-        int t1 = std::min(C.n_tgt, t0 + TB);
-        M2LBlock B;
-        B.cls = c;
-        B.nt = t1 - t0;
-        B.bt0 = (int)pl.bt_tbox.size();
-        B.q0 = (int)pl.pair_src.size();
-        B.offr0 = (int)pl.offr.size();
-        // pair index of (target slot, offset) inside the block
-        std::vector<int> qidx((size_t)B.nt * C.n_off, -1);
-        for (int o = 0; o < C.n_off; o++) {
-          pl.offr.push_back((int)pl.pair_src.size());
-          for (int t = t0; t < t1; t++) {
-            int sb = pl.cls_srcof[base + (long long)t * C.n_off + o];
-            if (sb < 0) continue;
-            qidx[(size_t)(t - t0) * C.n_off + o] = (int)pl.pair_src.size();
-            pl.pair_src.push_back(sb);
-            int po = pl.offs[C.off0 + o].pord;
-            pl.pair_P.push_back((po + 1) * (po + 1));
-            pl.pair_phi.push_back(pl.offs[C.off0 + o].phi);
-          }
-        }
-        pl.offr.push_back((int)pl.pair_src.size());
-        B.nq = (int)pl.pair_src.size() - B.q0;
-        for (int t = t0; t < t1; t++) {
-          pl.bt_tbox.push_back(pl.cls_tgt[C.tgt0 + t]);
-          pl.bt_blk.push_back((int)pl.blocks.size());
-          pl.bt_ptr.push_back((int)pl.bt_pairs.size());
-          for (int o = 0; o < C.n_off; o++) {
-            int q = qidx[(size_t)(t - t0) * C.n_off + o];
-            if (q >= 0) pl.bt_pairs.push_back(q);
-          }
-        }
-        pl.blocks.push_back(B);
-      }
+    struct BJob {
+      int c, t0, t1;
+      long long nq, q0, offr0, bt0;
+    };
+    std::vector<BJob> jobs;
+    for (int c = 0; c < (int)pl.cls.size(); c++)
+      for (int t0 = 0; t0 < pl.cls[c].n_tgt; t0 += TB) jobs.push_back({c, t0, std::min(pl.cls[c].n_tgt, t0 + TB), 0, 0, 0, 0});
+    run_threads(jobs.size(), [&](size_t j) {
+      BJob& b = jobs[j];
+      const M2LClass& C = pl.cls[b.c];
+      const int* so = pl.cls_srcof.data() + pl.cls_srcof0[b.c];
+      long long n = 0;
+      for (long long e = (long long)b.t0 * C.n_off; e < (long long)b.t1 * C.n_off; e++) n += so[e] >= 0;
+      b.nq = n;
+    });
+    long long nq = 0, noffr = 0, nbt = 0;
+    for (BJob& b : jobs) {
+      b.q0 = nq;
+      b.offr0 = noffr;
+      b.bt0 = nbt;
+      nq += b.nq;
+      noffr += pl.cls[b.c].n_off + 1;
+      nbt += b.t1 - b.t0;
     }
-    pl.bt_ptr.push_back((int)pl.bt_pairs.size());
+    if (nq > INT_MAX || noffr > INT_MAX || nbt > INT_MAX) return "too many M2L pairs";
+    pl.offr.resize(noffr);
+    pl.pair_src.resize(nq);
+    pl.pair_P.resize(nq);
+    pl.pair_phi.resize(nq);
+    pl.bt_pairs.resize(nq);
+    pl.bt_tbox.resize(nbt);
+    pl.bt_blk.resize(nbt);
+    pl.bt_ptr.resize(nbt + 1);
+    pl.blocks.resize(jobs.size());
+    run_threads(jobs.size(), [&](size_t j) {
+      const BJob& b = jobs[j];
+      const M2LClass& C = pl.cls[b.c];
+      const long long base = pl.cls_srcof0[b.c];
+      M2LBlock B;
+      B.cls = b.c;
+      B.nt = b.t1 - b.t0;
+      B.bt0 = (int)b.bt0;
+      B.q0 = (int)b.q0;
+      B.offr0 = (int)b.offr0;
+      B.nq = (int)b.nq;
+      // pair index of (target slot, offset) inside the block
+      std::vector<int> qidx((size_t)B.nt * C.n_off, -1);
+      int q = B.q0, r = B.offr0;
+      for (int o = 0; o < C.n_off; o++) {
+        pl.offr[r++] = q;
+        const int po = pl.offs[C.off0 + o].pord;
+        const double phi = pl.offs[C.off0 + o].phi;
+        for (int t = b.t0; t < b.t1; t++) {
+          const int sb = pl.cls_srcof[base + (long long)t * C.n_off + o];
+          if (sb < 0) continue;
+          qidx[(size_t)(t - b.t0) * C.n_off + o] = q;
+          pl.pair_src[q] = sb;
+          pl.pair_P[q] = (po + 1) * (po + 1);
+          pl.pair_phi[q] = phi;
+          q++;
+        }
+      }
+      pl.offr[r] = q;
+      int bt = B.bt0, bp = B.q0;
+      for (int t = b.t0; t < b.t1; t++, bt++) {
+        pl.bt_tbox[bt] = pl.cls_tgt[C.tgt0 + t];
+        pl.bt_blk[bt] = (int)j;
+        pl.bt_ptr[bt] = bp;
+        for (int o = 0; o < C.n_off; o++) {
+          const int qq = qidx[(size_t)(t - b.t0) * C.n_off + o];
+          if (qq >= 0) pl.bt_pairs[bp++] = qq;
+        }
+      }
+      pl.blocks[j] = B;
+    });
+    pl.bt_ptr[nbt] = (int)nq;
   }
 
   // ---- quadrature node sets: one per (reaction instance, level)
