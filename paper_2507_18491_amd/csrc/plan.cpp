@@ -1113,6 +1113,27 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
       li.recs.push_back(rec);
     }
   });
+  struct BoxFill {
+    int gi, inst, sbase, tbase, sp0, tp0, P;
+    long long me0, le0;
+    std::vector<std::array<long long, 8>> m2m_at, l2l_at;
+  };
+  std::vector<BoxFill> box_fills;
+  {
+    size_t ns = 0, nt = 0, np = 0, nq = 0;
+    for (const Prep& pr : preps) {
+      ns += pr.S.nbox();
+      nt += pr.T.nbox();  // (free instances use S: an upper bound)
+      np += pr.S.permA.size();
+      nq += pr.T.permB.size() + pr.S.permB.size();
+    }
+    pl.sbox.reserve(ns);
+    pl.sbox_m2m.reserve(ns);
+    pl.tbox.reserve(nt + ns);
+    pl.tbox_l2l.reserve(nt + ns);
+    pl.src_perm.reserve(np);
+    pl.tgt_perm.reserve(nq);
+  }
   for (size_t gi = 0; gi < geo.size(); gi++) {
     const IGeom& g = geo[gi];
     Prep& pr = preps[gi];
@@ -1134,85 +1155,63 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
     (void)depth_used;
     HTree& TT = free ? S : T;  // target tree
 
-    // ---- boxes -> global records
+    // ---- boxes -> global records: ranges, matrices and offsets here, the
+    // records themselves on host threads after the loop
     int sbase = (int)pl.sbox.size(), tbase = (int)pl.tbox.size();
     int sp0 = (int)pl.src_perm.size(), tp0 = (int)pl.tgt_perm.size();
-    pl.src_perm.insert(pl.src_perm.end(), S.permA.begin(), S.permA.end());
-    pl.tgt_perm.insert(pl.tgt_perm.end(), TT.permB.begin(), TT.permB.end());
+    pl.src_perm.resize(sp0 + S.permA.size());  // (filled with the records below)
+    pl.tgt_perm.resize(tp0 + TT.permB.size());
     // translation matrices depend on the level and octant alone within an
     // instance: looked up once per (level, octant), in first-use order
-    std::vector<std::array<long long, 8>> m2m_at, l2l_at;
-    for (int b = 0; b < S.nbox(); b++) {
-      SrcBox sb;
-      memset(&sb, 0, sizeof(sb));
-      S.centre(b, sb.c);
-      sb.pt0 = sp0 + S.a0[b];
-      sb.pt1 = sp0 + S.a1[b];
-      sb.inst = inst;
-      sb.level = S.lvl[b];
-      sb.child0 = S.child0[b] >= 0 ? sbase + S.child0[b] : -1;
-      sb.nchild = S.nchild[b];
-      sb.octant = S.oct[b];
-      sb.parent = S.parent[b] >= 0 ? sbase + S.parent[b] : -1;
-      sb.me_off = pl.me_size;
-      pl.me_size += 3LL * P;
-      pl.sbox.push_back(sb);
-      long long mm = -1;
+    BoxFill bf;
+    bf.gi = (int)gi;
+    bf.inst = inst;
+    bf.sbase = sbase;
+    bf.tbase = tbase;
+    bf.sp0 = sp0;
+    bf.tp0 = tp0;
+    bf.me0 = pl.me_size;
+    bf.le0 = pl.le_size;
+    bf.P = P;
+    for (int b = 0; b < S.nbox(); b++)
       if (S.parent[b] >= 0) {
-        int o = S.oct[b];
-        const int l = S.lvl[b];
-        if ((int)m2m_at.size() <= l) m2m_at.resize(l + 1, {-1, -1, -1, -1, -1, -1, -1, -1});
-        if (m2m_at[l][o] < 0) {
-          double s = S.S(l);
-          TransJob j;
-          j.b[0] = ((o & 1) - 0.5) * s;
-          j.b[1] = (((o >> 1) & 1) - 0.5) * s;
-          j.b[2] = (((o >> 2) & 1) - 0.5) * s;
-          j.k = ip.ks;
-          j.p = ip.p;
-          j.kind = 1;
-          m2m_at[l][o] = alloc_mat(MatKey{1, kquant(ip.ks), ip.p, kquant(S.S(l)), o, 0, 0}, (long long)P * P, &j);
-        }
-        mm = m2m_at[l][o];
+        const int o = S.oct[b], l = S.lvl[b];
+        if ((int)bf.m2m_at.size() <= l) bf.m2m_at.resize(l + 1, {-1, -1, -1, -1, -1, -1, -1, -1});
+        if (bf.m2m_at[l][o] >= 0) continue;
+        double s = S.S(l);
+        TransJob j;
+        j.b[0] = ((o & 1) - 0.5) * s;
+        j.b[1] = (((o >> 1) & 1) - 0.5) * s;
+        j.b[2] = (((o >> 2) & 1) - 0.5) * s;
+        j.k = ip.ks;
+        j.p = ip.p;
+        j.kind = 1;
+        bf.m2m_at[l][o] = alloc_mat(MatKey{1, kquant(ip.ks), ip.p, kquant(S.S(l)), o, 0, 0}, (long long)P * P, &j);
       }
-      pl.sbox_m2m.push_back(mm);
+    for (int b = 0; b < S.nbox(); b++)
       if (S.nchild[b] == 0 && S.a1[b] > S.a0[b]) pl.p2m_leaves.push_back(sbase + b);
-    }
-    for (int b = 0; b < TT.nbox(); b++) {
-      TgtBox tb;
-      memset(&tb, 0, sizeof(tb));
-      TT.centre(b, tb.c);
-      tb.pt0 = tp0 + TT.b0[b];
-      tb.pt1 = tp0 + TT.b1[b];
-      tb.inst = inst;
-      tb.level = TT.lvl[b];
-      tb.parent = TT.parent[b] >= 0 ? tbase + TT.parent[b] : -1;
-      tb.octant = TT.oct[b];
-      tb.leaf = TT.nchild[b] == 0;
-      tb.le_off = pl.le_size;
-      tb.p2p0 = tb.p2p1 = 0;
-      pl.le_size += 3LL * P;
-      pl.tbox.push_back(tb);
-      long long mm = -1;
+    for (int b = 0; b < TT.nbox(); b++)
       if (TT.parent[b] >= 0) {
-        int o = TT.oct[b];
-        const int l = TT.lvl[b];
-        if ((int)l2l_at.size() <= l) l2l_at.resize(l + 1, {-1, -1, -1, -1, -1, -1, -1, -1});
-        if (l2l_at[l][o] < 0) {
-          double s = TT.S(l);
-          TransJob j;
-          j.b[0] = ((o & 1) - 0.5) * s;
-          j.b[1] = (((o >> 1) & 1) - 0.5) * s;
-          j.b[2] = (((o >> 2) & 1) - 0.5) * s;
-          j.k = ip.kt;
-          j.p = ip.p;
-          j.kind = 2;
-          l2l_at[l][o] = alloc_mat(MatKey{2, kquant(ip.kt), ip.p, kquant(TT.S(l)), o, 0, 0}, (long long)P * P, &j);
-        }
-        mm = l2l_at[l][o];
+        const int o = TT.oct[b], l = TT.lvl[b];
+        if ((int)bf.l2l_at.size() <= l) bf.l2l_at.resize(l + 1, {-1, -1, -1, -1, -1, -1, -1, -1});
+        if (bf.l2l_at[l][o] >= 0) continue;
+        double s = TT.S(l);
+        TransJob j;
+        j.b[0] = ((o & 1) - 0.5) * s;
+        j.b[1] = (((o >> 1) & 1) - 0.5) * s;
+        j.b[2] = (((o >> 2) & 1) - 0.5) * s;
+        j.k = ip.kt;
+        j.p = ip.p;
+        j.kind = 2;
+        bf.l2l_at[l][o] = alloc_mat(MatKey{2, kquant(ip.kt), ip.p, kquant(TT.S(l)), o, 0, 0}, (long long)P * P, &j);
       }
-      pl.tbox_l2l.push_back(mm);
-    }
+    pl.me_size += 3LL * P * S.nbox();
+    pl.le_size += 3LL * P * TT.nbox();
+    pl.sbox.resize(sbase + S.nbox());
+    pl.sbox_m2m.resize(sbase + S.nbox());
+    pl.tbox.resize(tbase + TT.nbox());  // (zero near-box ranges until the lists below set them)
+    pl.tbox_l2l.resize(tbase + TT.nbox());
+    box_fills.push_back(std::move(bf));
     // M2M parents / L2L children per level
     for (int b = 0; b < S.nbox(); b++)
       if (S.nchild[b] > 0) {
@@ -1327,6 +1326,68 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
     }
     inst_S0.push_back(S0);
     pl.inst.push_back(ip);
+  }
+  {
+    // the box records of every instance (pieces of up to 2^16 boxes)
+    // and their point permutations
+    std::vector<std::array<int, 3>> pieces;  // (instance, kind: source / target boxes, source / target points; first)
+    const int piece = 1 << 16;
+    for (size_t k = 0; k < box_fills.size(); k++) {
+      const Prep& pr = preps[box_fills[k].gi];
+      const HTree& TT = pl.inst[box_fills[k].inst].kind == 0 ? pr.S : pr.T;
+      for (int b = 0; b < pr.S.nbox(); b += piece) pieces.push_back({(int)k, 0, b});
+      for (int b = 0; b < TT.nbox(); b += piece) pieces.push_back({(int)k, 1, b});
+      for (int b = 0; b < (int)pr.S.permA.size(); b += 4 * piece) pieces.push_back({(int)k, 2, b});
+      for (int b = 0; b < (int)TT.permB.size(); b += 4 * piece) pieces.push_back({(int)k, 3, b});
+    }
+    run_threads(pieces.size(), [&](size_t pi) {
+      const BoxFill& bf = box_fills[pieces[pi][0]];
+      const Prep& pr = preps[bf.gi];
+      const int kind = pieces[pi][1], first = pieces[pi][2];
+      if (kind >= 2) {
+        const std::vector<int>& v = kind == 2 ? pr.S.permA : (pl.inst[bf.inst].kind == 0 ? pr.S : pr.T).permB;
+        int* out = kind == 2 ? pl.src_perm.data() + bf.sp0 : pl.tgt_perm.data() + bf.tp0;
+        const int last = std::min((int)v.size(), first + 4 * piece);
+        for (int i = first; i < last; i++) out[i] = v[i];
+      } else if (kind == 0) {
+        const HTree& S = pr.S;
+        for (int b = pieces[pi][2]; b < std::min(S.nbox(), pieces[pi][2] + piece); b++) {
+          SrcBox sb;
+          memset(&sb, 0, sizeof(sb));
+          S.centre(b, sb.c);
+          sb.pt0 = bf.sp0 + S.a0[b];
+          sb.pt1 = bf.sp0 + S.a1[b];
+          sb.inst = bf.inst;
+          sb.level = S.lvl[b];
+          sb.child0 = S.child0[b] >= 0 ? bf.sbase + S.child0[b] : -1;
+          sb.nchild = S.nchild[b];
+          sb.octant = S.oct[b];
+          sb.parent = S.parent[b] >= 0 ? bf.sbase + S.parent[b] : -1;
+          sb.me_off = bf.me0 + 3LL * bf.P * b;
+          pl.sbox[bf.sbase + b] = sb;
+          pl.sbox_m2m[bf.sbase + b] = S.parent[b] >= 0 ? bf.m2m_at[S.lvl[b]][S.oct[b]] : -1;
+        }
+      } else {
+        const HTree& TT = pl.inst[bf.inst].kind == 0 ? pr.S : pr.T;
+        for (int b = pieces[pi][2]; b < std::min(TT.nbox(), pieces[pi][2] + piece); b++) {
+          TgtBox tb;
+          memset(&tb, 0, sizeof(tb));
+          TT.centre(b, tb.c);
+          tb.pt0 = bf.tp0 + TT.b0[b];
+          tb.pt1 = bf.tp0 + TT.b1[b];
+          tb.inst = bf.inst;
+          tb.level = TT.lvl[b];
+          tb.parent = TT.parent[b] >= 0 ? bf.tbase + TT.parent[b] : -1;
+          tb.octant = TT.oct[b];
+          tb.leaf = TT.nchild[b] == 0;
+          tb.le_off = bf.le0 + 3LL * bf.P * b;
+          tb.p2p0 = pl.tbox[bf.tbase + b].p2p0;
+          tb.p2p1 = pl.tbox[bf.tbase + b].p2p1;
+          pl.tbox[bf.tbase + b] = tb;
+          pl.tbox_l2l[bf.tbase + b] = TT.parent[b] >= 0 ? bf.l2l_at[TT.lvl[b]][TT.oct[b]] : -1;
+        }
+      }
+    });
   }
   {
     // every instance's pairs in instance order, with global box ids and the
