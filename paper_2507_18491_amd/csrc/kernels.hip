@@ -3227,7 +3227,9 @@ void launch_tab_integrals(const DevPlan& d, MediumDev med, int case0, int ncase,
 // Writes, per case, the + and z output rows of the spin-basis tensor (the -
 // rows are their mirror images): out[ci * stride + (slot * P + a) * 3P + blk * P
 // + b], slot 0 for +, 1 for z, with the column blocks of each output type in the order of its
-// input channels (+: u+, u-, z; z: u-, u+, z).
+// input channels (+: u+, u-, z; z: u-, u+, z).  One block per (case,
+// density, pair of tau types): the entries of one pair of types are
+// disjoint from those of every other pair.
 __global__ __launch_bounds__(NT) void k_tab_assemble(DevPlan d, int case0, int p, int KB, int BS, cd* out,
                                                      long long stride) {
   extern __shared__ cd Aij[];  // [(KB+1)^2][NQ]
@@ -3252,10 +3254,21 @@ __global__ __launch_bounds__(NT) void k_tab_assemble(DevPlan d, int case0, int p
   const cd* Ib = d.ibuf + tc.ibuf;
   cd* Mbase = out + (long long)ci * stride;
   const double fourpi = 12.566370614359172954;
-  for (int tt = 0; tt < 4; tt++)
-    for (int ts = 0; ts < 4; ts++) {
+  const int tt = blockIdx.z >> 2, ts = blockIdx.z & 3;
+  // the rows (n, m) of tau type tt and the columns (nu, mu) of type ts (in
+  // any order: every entry is computed and written on its own)
+  __shared__ int rows[(LM_PMAX + 1) * (LM_PMAX + 1)], cols[(LM_PMAX + 1) * (LM_PMAX + 1)];
+  __shared__ int nrow, ncol;
+  if (tid == 0) nrow = ncol = 0;
+  __syncthreads();
+  for (int a = tid; a < P; a += NT) {
+    const int n = n_of(a), am = abs(a - n * n - n);
+    const int t = (n % 2 == 0) ? ((am % 2 == 0) ? 0 : 3) : ((am % 2 == 0) ? 1 : 2);
+    if (t == tt) rows[atomicAdd(&nrow, 1)] = a;
+    if (t == ts) cols[atomicAdd(&ncol, 1)] = a;
+  }
+    {
       const cd* I = Ib + ((long long)(sg * 16 + tt * 4 + ts)) * NLQ;
-      __syncthreads();
       for (int e = tid; e < K1 * K1 * NQ; e += NT) {
         int ij = e / NQ, q = e - ij * NQ, i = ij / K1, j = ij - i * K1;
         // ib: index on the base (smaller-k) side, io: index expanded by C
@@ -3272,14 +3285,12 @@ __global__ __launch_bounds__(NT) void k_tab_assemble(DevPlan d, int case0, int p
         Aij[e] = v;
       }
       __syncthreads();
-      for (long long e = tid; e < (long long)P * P; e += NT) {
-        int a = (int)(e / P), bb = (int)(e - (long long)a * P);
+      // tau types (Appendix B): t1 = tt, t2 = ts for every entry below
+      const int nc = ncol;
+      for (int e = tid; e < nrow * nc; e += NT) {
+        const int a = rows[e / nc], bb = cols[e - (e / nc) * nc];
         int n = n_of(a), m = a - n * n - n, nu = n_of(bb), mu = bb - nu * nu - nu;
         int am = m < 0 ? -m : m, amu = mu < 0 ? -mu : mu;
-        // tau types (Appendix B)
-        int t1 = (n % 2 == 0) ? ((am % 2 == 0) ? 0 : 3) : ((am % 2 == 0) ? 1 : 2);
-        int t2 = (nu % 2 == 0) ? ((amu % 2 == 0) ? 0 : 3) : ((amu % 2 == 0) ? 1 : 2);
-        if (t1 != tt || t2 != ts) continue;
         int Kn = (n % 2 == 0) ? n / 2 : ((am % 2 == 0) ? (n + 1) / 2 : (n - 1) / 2);
         int Kv = (nu % 2 == 0) ? nu / 2 : ((amu % 2 == 0) ? (nu + 1) / 2 : (nu - 1) / 2);
         double smu = ((m < 0 && (am & 1)) ? -1.0 : 1.0) * ((mu < 0 && (amu & 1)) ? -1.0 : 1.0);
@@ -3311,7 +3322,7 @@ void launch_tab_assemble(const DevPlan& d, int case0, int ncase, int p, int KB, 
   int NQ = 2 * p + 3;
   size_t shm = (size_t)(KB + 1) * (KB + 1) * NQ * sizeof(cd);
   set_dyn_lds((const void*)k_tab_assemble, shm);
-  hipLaunchKernelGGL(k_tab_assemble, dim3(ncase, 5), dim3(NT), shm, s, d, case0, p, KB, BS, out, stride);
+  hipLaunchKernelGGL(k_tab_assemble, dim3(ncase, 5, 16), dim3(NT), shm, s, d, case0, p, KB, BS, out, stride);
 }
 
 // Even (par 0) and odd (par 1) blocks of each case's reaction M2L tensor
