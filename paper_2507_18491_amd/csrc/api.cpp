@@ -555,21 +555,15 @@ static int build_common(lm_ctx* ctx, int n_geom, const int64_t* soff, const doub
   if ((rc = upload(ctx, &d.tgt_perm, pl.tgt_perm))) return rc;
   if ((rc = upload(ctx, &d.p2p_list, pl.p2p_list))) return rc;
   if ((rc = upload(ctx, &d.cls, pl.cls))) return rc;
-  if ((rc = upload(ctx, &d.offs, pl.offs))) return rc;
-  if ((rc = upload(ctx, &d.cls_tgt, pl.cls_tgt))) return rc;
-  if ((rc = upload(ctx, &d.cls_srcof, pl.cls_srcof))) return rc;
-  if ((rc = upload(ctx, &d.cls_srcof0, pl.cls_srcof0))) return rc;
   if ((rc = upload(ctx, &d.blocks, pl.blocks))) return rc;
   if ((rc = upload(ctx, &d.bt_tbox, pl.bt_tbox))) return rc;
   if ((rc = upload(ctx, &d.bt_ptr, pl.bt_ptr))) return rc;
   if ((rc = upload(ctx, &d.bt_pairs, pl.bt_pairs))) return rc;
-  if ((rc = upload(ctx, &d.pair_src, pl.pair_src))) return rc;
   {
     std::vector<long long> pm(pl.pair_src.size());
     for (size_t q = 0; q < pm.size(); q++) pm[q] = pl.sbox[pl.pair_src[q]].me_off;
     if ((rc = upload(ctx, &d.pair_me, pm))) return rc;
   }
-  if ((rc = upload(ctx, &d.offr, pl.offr))) return rc;
   if ((rc = upload(ctx, &d.bt_blk, pl.bt_blk))) return rc;
   if ((rc = upload(ctx, &d.pair_P, pl.pair_P))) return rc;
   if ((rc = upload(ctx, &d.pair_phi, pl.pair_phi))) return rc;

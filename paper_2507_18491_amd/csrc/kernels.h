@@ -21,18 +21,12 @@ struct DevPlan {
   int* tgt_perm;
   int* p2p_list;
   M2LClass* cls;
-  M2LOffset* offs;
-  int* cls_tgt;
-  int* cls_srcof;
-  long long* cls_srcof0;
   M2LTile* tiles;
   M2LBlock* blocks;
   int* bt_tbox;
   int* bt_ptr;
   int* bt_pairs;
-  int* pair_src;
   long long* pair_me;   // per pair: multipole vector offset of its source box
-  int* offr;
   int* bt_blk;          // block of each block-target
   int* pair_P;          // per pair: number of rows/columns used ((pord+1)^2)
   double* pair_phi;     // per pair: azimuth of its offset (reaction output phases)
