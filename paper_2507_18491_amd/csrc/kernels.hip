@@ -3153,6 +3153,7 @@ __global__ void k_tab_bessel(DevPlan d, MediumDev md, int case0, int ncase, int 
 // Chebyshev-weighted Sommerfeld integrals of one case (Sec. 3.4):
 //   I[sig][tt][ts][l][q] = sum_nodes w kr Z F_sig tau_tt(b) tau_ts(b') T_l(cos 2 b0) J_q(kr rho)
 #define TAB_NC 8
+#define TAB_OUT 16  // outputs per thread (a block: NT * TAB_OUT consecutive entries of one case)
 __global__ __launch_bounds__(NT) void k_tab_integrals(DevPlan d, int case0, int p, int maxnode, const cd* scr) {
   extern __shared__ cd shm[];
   int NQ = 2 * p + 3, NL = p + 2, NLQ = NL * NQ;
@@ -3163,9 +3164,9 @@ __global__ __launch_bounds__(NT) void k_tab_integrals(DevPlan d, int case0, int 
   int ci = blockIdx.x;
   TabCase tc = d.cases[case0 + ci];
   int tid = threadIdx.x;
-  int e0 = blockIdx.y * (NT * 4);
-  cd acc[4];
-  for (int j = 0; j < 4; j++) acc[j] = cd{0, 0};
+  int e0 = blockIdx.y * (NT * TAB_OUT);
+  cd acc[TAB_OUT];
+  for (int j = 0; j < TAB_OUT; j++) acc[j] = cd{0, 0};
   const cd* sc = scr + (long long)ci * maxnode * (NQ + 1);
   for (int n0 = 0; n0 < tc.nnode; n0 += TAB_NC) {
     int nn = min(TAB_NC, tc.nnode - n0);
@@ -3187,7 +3188,8 @@ __global__ __launch_bounds__(NT) void k_tab_integrals(DevPlan d, int case0, int 
       U[e] = (t < nn) ? Tl[t * NL + l] * sc[(long long)(n0 + t) * (NQ + 1) + 1 + qq] : cd{0, 0};
     }
     __syncthreads();
-    for (int j = 0; j < 4; j++) {
+#pragma unroll
+    for (int j = 0; j < TAB_OUT; j++) {
       int e = e0 + j * NT + tid;
       if (e >= E) break;
       int a = e / NLQ, b = e - a * NLQ;
@@ -3196,7 +3198,8 @@ __global__ __launch_bounds__(NT) void k_tab_integrals(DevPlan d, int case0, int 
       acc[j] = s;
     }
   }
-  for (int j = 0; j < 4; j++) {
+#pragma unroll
+  for (int j = 0; j < TAB_OUT; j++) {
     int e = e0 + j * NT + tid;
     if (e < E) d.ibuf[tc.ibuf + e] = acc[j];
   }
@@ -3212,7 +3215,7 @@ void launch_tab_integrals(const DevPlan& d, MediumDev med, int case0, int ncase,
   int E = 80 * NL * NQ;
   size_t shm = (size_t)(TAB_NC * 80 + TAB_NC * NL * NQ + TAB_NC * NL) * sizeof(cd);
   set_dyn_lds((const void*)k_tab_integrals, shm);
-  hipLaunchKernelGGL(k_tab_integrals, dim3(ncase, (E + NT * 4 - 1) / (NT * 4)), dim3(NT), shm, s, d, case0, p,
+  hipLaunchKernelGGL(k_tab_integrals, dim3(ncase, (E + NT * TAB_OUT - 1) / (NT * TAB_OUT)), dim3(NT), shm, s, d, case0, p,
                      (int)maxnode, scr);
 }
 
