@@ -236,7 +236,7 @@ static void free_build(lm_ctx* ctx) {
 // Host threads for the build's list construction: fn(i) for i < n, indices
 // handed out one at a time; every fn writes only outputs of its own index,
 // so the result does not depend on the thread count.
-static unsigned host_threads() { return std::max(1u, std::min(16u, std::thread::hardware_concurrency())); }
+static unsigned host_threads() { return lm_host_thread_count(); }
 static void par_for(size_t n, unsigned nth, const std::function<void(size_t)>& fn) {
   std::atomic<size_t> next_i{0};
   auto work = [&]() {

@@ -485,6 +485,16 @@ std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int
   return lm_make_plan_multi(pl, med, prm, 1, so, src, to, tgt);
 }
 
+unsigned lm_host_thread_count() {
+  const char* e = getenv("LMFMM_HOST_THREADS");
+  if (e && *e) {
+    char* end = nullptr;
+    const long v = strtol(e, &end, 10);
+    if (end && *end == 0 && v >= 1 && v <= 256) return (unsigned)v;
+  }
+  return std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+}
+
 std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& prm, int n_geom,
                                const int64_t* src_off, const double* src, const int64_t* tgt_off,
                                const double* tgt, const TreeSorter* sorter) {
@@ -610,7 +620,7 @@ std::string lm_make_plan_multi(Plan& pl, const Medium& med, const PlanParams& pr
     }
   };
   auto run_threads = [&](size_t n, const std::function<void(size_t)>& fn) {
-    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const unsigned nth = lm_host_thread_count();
     std::atomic<size_t> next_i{0};
     auto work = [&]() {
       for (size_t i = next_i++; i < n; i = next_i++) fn(i);

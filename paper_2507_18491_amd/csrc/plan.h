@@ -99,6 +99,11 @@ struct Plan {
 std::string lm_make_plan(Plan& pl, const Medium& med, const PlanParams& prm, int64_t n_src,
                          const double* src, int64_t n_tgt, const double* tgt);
 
+// Host threads of the planner and of the build's list construction: the
+// LMFMM_HOST_THREADS environment variable (1..256) when set, else the
+// hardware's count up to 16.  Plans and lists do not depend on it.
+unsigned lm_host_thread_count();
+
 // several independent geometries in one plan: geometry g owns sources
 // src_off[g] .. src_off[g+1]-1 and targets tgt_off[g] .. tgt_off[g+1]-1 (global
 // indices into src / tgt); each gets its own lattice and FMM instances, and

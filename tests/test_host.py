@@ -172,6 +172,33 @@ def test_plan_external_tree_sort_route_gives_the_same_plan():
     assert a3 == b3 and a3 != a
 
 
+def test_plan_does_not_depend_on_the_host_thread_count(monkeypatch):
+    """The planner's threaded steps (instance trees and lists, box records,
+    the M2L pair list and its class keys, class tables, work blocks) write
+    ranges sized beforehand and keep every first-use numbering serial, so
+    one thread and several give the same plan: equal digests with
+    LMFMM_HOST_THREADS = 1, 3 and 8 on clustered points, uneven geometries
+    with distinct targets, and six layers."""
+    cases = []
+    d, k, x, _ = inputs.clustered_three_layer(30000, seed=7)
+    cases.append((d, k, [x], None, dict(p=12, p_free=16)))
+    d, k, xs, _ = inputs.uneven_geometries(12, seed=8, n_min=200, n_max=4000)
+    ys = [xx[::3] + np.array([0.013, -0.019, 0.0]) for xx in xs]
+    for y in ys:
+        y[:, 2] = np.where(np.abs(y[:, 2]) < 0.06, np.sign(y[:, 2]) * 0.08, y[:, 2])
+        y[:, 2] = np.where(np.abs(y[:, 2] + 1.2) < 0.06, -1.2 + np.sign(y[:, 2] + 1.2) * 0.08, y[:, 2])
+    cases.append((d, k, xs, ys, dict(p=8)))
+    d, k, x, _ = inputs.six_layer(8000, seed=9)
+    cases.append((d, k, [x], None, dict(p=10)))
+    for d, k, srcs, tgts, prm in cases:
+        got = []
+        for nth in ("1", "3", "8"):
+            monkeypatch.setenv("LMFMM_HOST_THREADS", nth)
+            got.append(lmfmm.host_plan_digests(d, k, srcs, tgts, **prm))
+        assert got[0][0] == got[0][1]
+        assert got[0] == got[1] == got[2], got
+
+
 def test_plan_rejects_point_on_interface():
     d, k, x, _ = inputs.tiny()
     x = x.copy()
