@@ -3270,54 +3270,52 @@ __global__ __launch_bounds__(NT) void k_tab_assemble(DevPlan d, int case0, int p
     if (t == tt) rows[atomicAdd(&nrow, 1)] = a;
     if (t == ts) cols[atomicAdd(&ncol, 1)] = a;
   }
-    {
-      const cd* I = Ib + ((long long)(sg * 16 + tt * 4 + ts)) * NLQ;
-      for (int e = tid; e < K1 * K1 * NQ; e += NT) {
-        int ij = e / NQ, q = e - ij * NQ, i = ij / K1, j = ij - i * K1;
-        // ib: index on the base (smaller-k) side, io: index expanded by C
-        int ib = tbase ? i : j, io = tbase ? j : i;
-        cd v = cd{0, 0};
-        for (int s = 0; s <= io; s++) {
-          double c = C[io * W + s];
-          if (c == 0.0) continue;
-          int l1 = ib + s, l2 = ib > s ? ib - s : s - ib;
-          cd t1 = l1 < NL ? I[l1 * NQ + q] : cd{0, 0};
-          cd t2 = l2 < NL ? I[l2 * NQ + q] : cd{0, 0};
-          v = v + c * (t1 + t2);
-        }
-        Aij[e] = v;
+  const cd* I = Ib + ((long long)(sg * 16 + tt * 4 + ts)) * NLQ;
+  for (int e = tid; e < K1 * K1 * NQ; e += NT) {
+    int ij = e / NQ, q = e - ij * NQ, i = ij / K1, j = ij - i * K1;
+    // ib: index on the base (smaller-k) side, io: index expanded by C
+    int ib = tbase ? i : j, io = tbase ? j : i;
+    cd v = cd{0, 0};
+    for (int s = 0; s <= io; s++) {
+      double c = C[io * W + s];
+      if (c == 0.0) continue;
+      int l1 = ib + s, l2 = ib > s ? ib - s : s - ib;
+      cd t1 = l1 < NL ? I[l1 * NQ + q] : cd{0, 0};
+      cd t2 = l2 < NL ? I[l2 * NQ + q] : cd{0, 0};
+      v = v + c * (t1 + t2);
+    }
+    Aij[e] = v;
+  }
+  __syncthreads();
+  // tau types (Appendix B): t1 = tt, t2 = ts for every entry below
+  const int nc = ncol;
+  for (int e = tid; e < nrow * nc; e += NT) {
+    const int a = rows[e / nc], bb = cols[e - (e / nc) * nc];
+    int n = n_of(a), m = a - n * n - n, nu = n_of(bb), mu = bb - nu * nu - nu;
+    int am = m < 0 ? -m : m, amu = mu < 0 ? -mu : mu;
+    int Kn = (n % 2 == 0) ? n / 2 : ((am % 2 == 0) ? (n + 1) / 2 : (n - 1) / 2);
+    int Kv = (nu % 2 == 0) ? nu / 2 : ((amu % 2 == 0) ? (nu + 1) / 2 : (nu - 1) / 2);
+    double smu = ((m < 0 && (am & 1)) ? -1.0 : 1.0) * ((mu < 0 && (amu & 1)) ? -1.0 : 1.0);
+    const double* Bn = d.Bcoef + (long long)tri_idx(n, am) * BS;
+    const double* Bv = d.Bcoef + (long long)tri_idx(nu, amu) * BS;
+    double sgn_s = ((n + m + nu + mu) & 1) ? (double)ip.sgn : 1.0;
+    for (int kk = 0; kk < nk; kk++) {
+      int q = kap[kk] - m + mu, aq = q < 0 ? -q : q;
+      cd ih = cd{0, 0};
+      for (int i = 0; i <= Kn; i++) {
+        cd row = cd{0, 0};
+        for (int j = 0; j <= Kv; j++) row = row + Bv[j] * Aij[(i * K1 + j) * NQ + aq];
+        ih = ih + Bn[i] * row;
       }
-      __syncthreads();
-      // tau types (Appendix B): t1 = tt, t2 = ts for every entry below
-      const int nc = ncol;
-      for (int e = tid; e < nrow * nc; e += NT) {
-        const int a = rows[e / nc], bb = cols[e - (e / nc) * nc];
-        int n = n_of(a), m = a - n * n - n, nu = n_of(bb), mu = bb - nu * nu - nu;
-        int am = m < 0 ? -m : m, amu = mu < 0 ? -mu : mu;
-        int Kn = (n % 2 == 0) ? n / 2 : ((am % 2 == 0) ? (n + 1) / 2 : (n - 1) / 2);
-        int Kv = (nu % 2 == 0) ? nu / 2 : ((amu % 2 == 0) ? (nu + 1) / 2 : (nu - 1) / 2);
-        double smu = ((m < 0 && (am & 1)) ? -1.0 : 1.0) * ((mu < 0 && (amu & 1)) ? -1.0 : 1.0);
-        const double* Bn = d.Bcoef + (long long)tri_idx(n, am) * BS;
-        const double* Bv = d.Bcoef + (long long)tri_idx(nu, amu) * BS;
-        double sgn_s = ((n + m + nu + mu) & 1) ? (double)ip.sgn : 1.0;
-        for (int kk = 0; kk < nk; kk++) {
-          int q = kap[kk] - m + mu, aq = q < 0 ? -q : q;
-          cd ih = cd{0, 0};
-          for (int i = 0; i <= Kn; i++) {
-            cd row = cd{0, 0};
-            for (int j = 0; j <= Kv; j++) row = row + Bv[j] * Aij[(i * K1 + j) * NQ + aq];
-            ih = ih + Bn[i] * row;
-          }
-          ih = (0.5 * smu) * ih;
-          cd V = (fourpi * sgn_s) * (ipow(1 + n + aq) * ipow(-nu) * ih);  // i^{1+n+|q|} (-i)^nu
-          for (int sl = 0; sl < nslot[kk]; sl++) {
-            int t = slot_t[kk][sl], blk = slot_b[kk][sl];
-            if (t == 1) continue;  // the - rows: mirror images of the + rows
-            Mbase[(long long)(t >> 1) * 3 * P * P + (long long)a * 3 * P + (long long)blk * P + bb] = coef[kk][sl] * V;
-          }
-        }
+      ih = (0.5 * smu) * ih;
+      cd V = (fourpi * sgn_s) * (ipow(1 + n + aq) * ipow(-nu) * ih);  // i^{1+n+|q|} (-i)^nu
+      for (int sl = 0; sl < nslot[kk]; sl++) {
+        int t = slot_t[kk][sl], blk = slot_b[kk][sl];
+        if (t == 1) continue;  // the - rows: mirror images of the + rows
+        Mbase[(long long)(t >> 1) * 3 * P * P + (long long)a * 3 * P + (long long)blk * P + bb] = coef[kk][sl] * V;
       }
     }
+  }
 }
 void launch_tab_assemble(const DevPlan& d, int case0, int ncase, int p, int KB, int BS, cd* out, long long stride,
                          hipStream_t s) {
