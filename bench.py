@@ -337,6 +337,9 @@ def main():
 
     d, k, x, J = inputs.three_layer(args.n, seed=0, n_rhs=args.rhs)
     dev = torch.device("cuda:0")
+    # the HIP runtime's one-time start in this process is not part of a build
+    torch.zeros(1, device=dev)
+    torch.cuda.synchronize()
     t0 = time.time()
     fmm = lmfmm.LayeredDyadicFMM(d, k, p=args.p, p_free=args.p_free, device=0).build(x)
     torch.cuda.synchronize()
